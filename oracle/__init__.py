@@ -1,0 +1,231 @@
+"""FP64 CPU oracle of the GSW-MTP iteration (Liu et al., arXiv:2206.12661).
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The GPU library
+(``paper_2206_12661_amd``) never imports it and shares no code with it.
+
+Two parts:
+  * the propagation operators and Algorithm 1, in plain C (``gsw_oracle.c``),
+    double precision, called through ctypes;
+  * the index work (unique focal coordinates, gather indices, aperture
+    compaction, axis choice, per-row focus lists) written out with numpy's
+    sort-based ``unique`` and ``searchsorted``: integer results that the GPU
+    must reproduce bit for bit.
+
+Pins that tie this oracle to something other than itself live in
+``tests/test_oracle_pins.py``.  One function has no external pin: the full
+multi-step GSW trajectory (the paper prints no worked example), reported as
+"parity unpinned" there and in the design notes; its single steps are pinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_forward.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, _D, _D, _D]
+    lib.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]
+    lib.oracle_stats.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double, _D]
+    lib.oracle_stats.restype = None
+    lib.oracle_weight_update.argtypes = [ctypes.c_int, _D, _D, _D, _D]
+    lib.oracle_weight_update.restype = None
+    lib.oracle_gsw.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, ctypes.c_int,
+                               ctypes.c_double, _D, _I, _D]
+    lib.oracle_phase_gradient.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
+                                          _D, _D, _D, _D, _D]
+    _lib = lib
+    return lib
+
+
+def _d(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+# ----------------------------------------------------------------------------
+# Propagation operators (Eq. 1 / Eq. 2 and its adjoint)
+# ----------------------------------------------------------------------------
+
+def forward(E, u, v, s_x, s_y, fx, fy) -> np.ndarray:
+    """Focal field Theta_n of the complex pupil field E[ny, nx] (complex128)."""
+    E = np.ascontiguousarray(np.asarray(E, dtype=np.complex128))
+    ny, nx = E.shape
+    u, v, fx, fy = _f64(u), _f64(v), _f64(fx), _f64(fy)
+    out = np.zeros(fx.shape[0], dtype=np.complex128)
+    rc = _load().oracle_forward(ny, nx, E.view(np.float64).ctypes.data_as(_D), _d(u), _d(v),
+                                float(s_x), float(s_y), fx.shape[0], _d(fx), _d(fy),
+                                out.view(np.float64).ctypes.data_as(_D))
+    if rc:
+        raise MemoryError("oracle_forward")
+    return out
+
+
+def adjoint(theta, ny, nx, u, v, s_x, s_y, fx, fy) -> np.ndarray:
+    """Adjoint field E'[ny, nx] of focal values theta[N] (zero off the foci)."""
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.complex128))
+    u, v, fx, fy = _f64(u), _f64(v), _f64(fx), _f64(fy)
+    out = np.zeros((ny, nx), dtype=np.complex128)
+    rc = _load().oracle_adjoint(ny, nx, _d(u), _d(v), float(s_x), float(s_y), fx.shape[0],
+                                _d(fx), _d(fy), theta.view(np.float64).ctypes.data_as(_D),
+                                out.view(np.float64).ctypes.data_as(_D))
+    if rc:
+        raise MemoryError("oracle_adjoint")
+    return out
+
+
+def stats(theta, target, amplitude) -> dict:
+    """xi (accuracy), eta (efficiency), U (uniformity) and sum I of one field."""
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.complex128))
+    target = _f64(target)
+    amp = np.asarray(amplitude, dtype=np.float64)
+    n_ap = float(np.count_nonzero(amp > 0))
+    sum_a2 = float(np.sum(amp * amp))
+    out = np.zeros(4)
+    _load().oracle_stats(theta.shape[0], theta.view(np.float64).ctypes.data_as(_D),
+                         _d(target), n_ap, sum_a2, _d(out))
+    return {"xi": out[0], "eta": out[1], "uniformity": out[2], "sum_I": out[3]}
+
+
+def weight_update(theta, target, w):
+    """One weight update + focal-field update; returns (w_new, theta_new)."""
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.complex128))
+    target = _f64(target)
+    w = _f64(w).copy()
+    out = np.zeros_like(theta)
+    _load().oracle_weight_update(theta.shape[0], theta.view(np.float64).ctypes.data_as(_D),
+                                 _d(target), _d(w), out.view(np.float64).ctypes.data_as(_D))
+    return w, out
+
+
+def gsw(holo, n_iter: Optional[int] = None, stop: float = 0.0, phi=None, w=None) -> dict:
+    """Run Algorithm 1 on a ``synth_ofa.Hologram`` (or any object with the same
+    fields).  Returns phi (float64 [ny, nx]), w, history [passes, 3],
+    iters_done and the field of the returned phase."""
+    n_iter = holo.n_iter if n_iter is None else n_iter
+    ny, nx = holo.ny, holo.nx
+    amp = _f64(holo.amplitude)
+    ph = _f64(holo.phi0 if phi is None else phi).copy()
+    ww = np.ones(holo.n_foci) if w is None else _f64(w).copy()
+    hist = np.zeros((max(n_iter, 1), 3))
+    done = ctypes.c_int(0)
+    th = np.zeros(holo.n_foci, dtype=np.complex128)
+    rc = _load().oracle_gsw(ny, nx, _d(amp), _d(_f64(holo.u)), _d(_f64(holo.v)),
+                            float(holo.s_x), float(holo.s_y), holo.n_foci, _d(_f64(holo.fx)),
+                            _d(_f64(holo.fy)), _d(_f64(holo.target)), _d(ph), _d(ww),
+                            int(n_iter), float(stop), _d(hist), ctypes.byref(done),
+                            th.view(np.float64).ctypes.data_as(_D))
+    if rc:
+        raise MemoryError("oracle_gsw")
+    passes = done.value + (1 if (stop > 0 and done.value < n_iter) else 0)
+    return {"phi": ph, "w": ww, "history": hist[:passes], "iters_done": done.value,
+            "theta": th}
+
+
+def phase_gradient(holo, phi, g):
+    """dL/dphi for L = sum_n g_n |Theta_n(phi)|^2; returns (grad [ny, nx], theta)."""
+    ny, nx = holo.ny, holo.nx
+    grad = np.zeros((ny, nx))
+    th = np.zeros(holo.n_foci, dtype=np.complex128)
+    rc = _load().oracle_phase_gradient(
+        ny, nx, _d(_f64(holo.amplitude)), _d(_f64(holo.u)), _d(_f64(holo.v)),
+        float(holo.s_x), float(holo.s_y), holo.n_foci, _d(_f64(holo.fx)), _d(_f64(holo.fy)),
+        _d(_f64(phi)), _d(_f64(g)), _d(grad), th.view(np.float64).ctypes.data_as(_D))
+    if rc:
+        raise MemoryError("oracle_phase_gradient")
+    return grad, th
+
+
+def pupil_field(holo, phi=None) -> np.ndarray:
+    """E = A exp(i phi) in complex128 (phi defaults to the initial phase)."""
+    ph = np.asarray(holo.phi0 if phi is None else phi, dtype=np.float64)
+    return np.asarray(holo.amplitude, dtype=np.float64) * np.exp(1j * ph)
+
+
+# ----------------------------------------------------------------------------
+# Index work: reduced focal grid, gather indices, aperture compaction
+# ----------------------------------------------------------------------------
+
+def canonical(c) -> np.ndarray:
+    """Focal coordinates with -0.0 replaced by +0.0 (equal values, one key)."""
+    c = np.asarray(c, dtype=np.float64)
+    return np.where(c == 0.0, 0.0, c)
+
+
+def unique_coords(c):
+    """Sorted unique coordinates and the gather index of every focus into them.
+    The reduced focal grid of the paper keeps one sample row (column) per
+    distinct focus y (x) coordinate: k x l grid foci give l unique x and k
+    unique y values."""
+    key = canonical(c)
+    uniq = np.unique(key)
+    idx = np.searchsorted(uniq, key).astype(np.int32)
+    return uniq, idx
+
+
+def compaction(amplitude):
+    """Pupil rows and columns holding any non-zero amplitude, ascending
+    (the zero padding the MTP does not need is never sampled)."""
+    nz = np.asarray(amplitude) != 0
+    rows = np.nonzero(nz.any(axis=1))[0].astype(np.int32)
+    cols = np.nonzero(nz.any(axis=0))[0].astype(np.int32)
+    return rows, cols
+
+
+def axis_choice(ux: int, uy: int) -> int:
+    """Which focal axis the dense product reduces: 0 (y) unless x has fewer
+    unique coordinates.  The dense cost is U_axis * Ny' * Nx' either way."""
+    return 1 if ux < uy else 0
+
+
+def has_duplicate_foci(fx, fy) -> bool:
+    pts = np.stack([canonical(fx), canonical(fy)], axis=1)
+    return np.unique(pts, axis=0).shape[0] != pts.shape[0]
+
+
+def index_plan(fx, fy, amplitude) -> dict:
+    """Every integer the GPU plan derives from the foci and the aperture."""
+    xu, ix = unique_coords(fx)
+    yu, iy = unique_coords(fy)
+    rows, cols = compaction(amplitude)
+    axis = axis_choice(xu.shape[0], yu.shape[0])
+    ir, ic = (iy, ix) if axis == 0 else (ix, iy)
+    order = np.lexsort((ic, ir)).astype(np.int32)        # sort by (ir, ic)
+    ur = (yu if axis == 0 else xu).shape[0]
+    row_ptr = np.searchsorted(ir[order], np.arange(ur + 1)).astype(np.int32)
+    return {"xu": xu, "yu": yu, "ix": ix, "iy": iy, "rows": rows, "cols": cols,
+            "axis": axis, "order": order, "row_ptr": row_ptr,
+            "duplicate": has_duplicate_foci(fx, fy)}

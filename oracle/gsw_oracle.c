@@ -1,0 +1,339 @@
+/*
+ * FP64 CPU oracle for the weighted Gerchberg-Saxton iteration whose
+ * diffraction operator is the matrix triple product (MTP) of
+ * Liu et al., "Fast generation of arbitrary optical focus array",
+ * arXiv:2206.12661.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark build, load or call this file.  The GPU
+ * library never links, includes or calls it, and this file includes nothing
+ * of the GPU library.
+ *
+ * What it computes, all in double precision:
+ *
+ *  - Forward propagation (Eq. 1 sampled on the pupil, written in the separable
+ *    form of Eq. 2): for every focus n,
+ *        Theta_n = sum_j sum_i E[j][i] exp(-2 pi i s_y v_j y_n) exp(-2 pi i s_x u_i x_n).
+ *    The sum runs over every pupil sample and every focus separately: there is
+ *    no deduplication of focal coordinates and no aperture compaction, so this
+ *    checks the GPU's reduced-grid evaluation independently.
+ *
+ *  - Inverse propagation: the paper only says the inverse operator is
+ *    formulated like the forward one.  It is read here as the adjoint
+ *    (conjugate transpose) of the forward map with zero focal field at every
+ *    point that is not a focus:
+ *        E'[j][i] = sum_n Theta'_n exp(+2 pi i s_y v_j y_n) exp(+2 pi i s_x u_i x_n).
+ *
+ *  - The iteration of Algorithm 1 ("Fast generation of arbitrary OFA"), step
+ *    by step: forward propagation, focus intensities, intensity accuracy,
+ *    termination test, weight update, focal-field update, inverse
+ *    propagation, phase-only projection.  Where the paper leaves a choice open
+ *    the reading taken is stated at the step.
+ *
+ * Parallelism: OpenMP over foci (forward) and pupil rows (adjoint).  Every
+ * output element is summed by one thread in a fixed order, so results do not
+ * depend on the thread count.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* Smallest normalised intensity used in the weight update (division guard). */
+#define ORACLE_TAU 1e-30
+
+/* exp(-2 pi i s c f) for every sample coordinate c, one focal coordinate f.
+ * The exponent follows Eq. 1 (negative sign in the forward direction). */
+static void phasor_row(int n, const double *coord, double s, double f,
+                       double *re, double *im)
+{
+    for (int p = 0; p < n; ++p) {
+        double arg = -2.0 * M_PI * s * coord[p] * f;
+        re[p] = cos(arg);
+        im[p] = sin(arg);
+    }
+}
+
+/* Per-focus phasor tables: ax[n][i] and ay[n][j]. */
+typedef struct {
+    int nf, nx, ny;
+    double *axr, *axi, *ayr, *ayi;
+} tables;
+
+static int tables_build(tables *t, int ny, int nx, const double *u, const double *v,
+                        double sx, double sy, int nf, const double *fx, const double *fy)
+{
+    t->nf = nf; t->nx = nx; t->ny = ny;
+    t->axr = malloc(sizeof(double) * (size_t)nf * nx);
+    t->axi = malloc(sizeof(double) * (size_t)nf * nx);
+    t->ayr = malloc(sizeof(double) * (size_t)nf * ny);
+    t->ayi = malloc(sizeof(double) * (size_t)nf * ny);
+    if (!t->axr || !t->axi || !t->ayr || !t->ayi) return -1;
+#pragma omp parallel for schedule(static)
+    for (int n = 0; n < nf; ++n) {
+        phasor_row(nx, u, sx, fx[n], t->axr + (size_t)n * nx, t->axi + (size_t)n * nx);
+        phasor_row(ny, v, sy, fy[n], t->ayr + (size_t)n * ny, t->ayi + (size_t)n * ny);
+    }
+    return 0;
+}
+
+static void tables_free(tables *t)
+{
+    free(t->axr); free(t->axi); free(t->ayr); free(t->ayi);
+}
+
+/* Forward propagation with prebuilt tables.  E is interleaved complex
+ * [ny][nx]; theta is interleaved complex [nf]. */
+static void forward_t(const tables *t, const double *E, double *theta)
+{
+    const int nx = t->nx, ny = t->ny;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int n = 0; n < t->nf; ++n) {
+        const double *axr = t->axr + (size_t)n * nx, *axi = t->axi + (size_t)n * nx;
+        const double *ayr = t->ayr + (size_t)n * ny, *ayi = t->ayi + (size_t)n * ny;
+        double tr = 0.0, ti = 0.0;
+        for (int j = 0; j < ny; ++j) {
+            const double *row = E + 2 * (size_t)j * nx;
+            double rr = 0.0, ri = 0.0;          /* sum_i E[j][i] ax[i] */
+            for (int i = 0; i < nx; ++i) {
+                double er = row[2 * i], ei = row[2 * i + 1];
+                rr += er * axr[i] - ei * axi[i];
+                ri += er * axi[i] + ei * axr[i];
+            }
+            tr += ayr[j] * rr - ayi[j] * ri;    /* ... times ay[j] */
+            ti += ayr[j] * ri + ayi[j] * rr;
+        }
+        theta[2 * n] = tr;
+        theta[2 * n + 1] = ti;
+    }
+}
+
+/* Adjoint with prebuilt tables: E'[j][i] = sum_n theta_n conj(ay[n][j]) conj(ax[n][i]). */
+static void adjoint_t(const tables *t, const double *theta, double *E)
+{
+    const int nx = t->nx, ny = t->ny;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int j = 0; j < ny; ++j) {
+        double *row = E + 2 * (size_t)j * nx;
+        memset(row, 0, sizeof(double) * 2 * (size_t)nx);
+        for (int n = 0; n < t->nf; ++n) {
+            double ayr = t->ayr[(size_t)n * ny + j], ayi = -t->ayi[(size_t)n * ny + j];
+            double cr = theta[2 * n] * ayr - theta[2 * n + 1] * ayi;
+            double ci = theta[2 * n] * ayi + theta[2 * n + 1] * ayr;
+            const double *axr = t->axr + (size_t)n * nx, *axi = t->axi + (size_t)n * nx;
+            for (int i = 0; i < nx; ++i) {      /* times conj(ax[n][i]) */
+                row[2 * i] += cr * axr[i] + ci * axi[i];
+                row[2 * i + 1] += ci * axr[i] - cr * axi[i];
+            }
+        }
+    }
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Forward propagation, Eq. 1 / Eq. 2, evaluated at the foci. */
+int oracle_forward(int ny, int nx, const double *E, const double *u, const double *v,
+                   double sx, double sy, int nf, const double *fx, const double *fy,
+                   double *theta)
+{
+    tables t;
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); return -1; }
+    forward_t(&t, E, theta);
+    tables_free(&t);
+    return 0;
+}
+
+/* Inverse propagation read as the adjoint of the forward map. */
+int oracle_adjoint(int ny, int nx, const double *u, const double *v, double sx, double sy,
+                   int nf, const double *fx, const double *fy, const double *theta, double *E)
+{
+    tables t;
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); return -1; }
+    adjoint_t(&t, theta, E);
+    tables_free(&t);
+    return 0;
+}
+
+/* Focus statistics of one forward field (Algorithm 1, intensity and accuracy;
+ * efficiency and uniformity as diagnostics).
+ *   I_n = |Theta_n|^2, i = I / sum I, t = target / sum target.
+ *   accuracy   xi  = 1 - ||t - i||_2 / ||i||_2.  The paper writes the norm of
+ *              (target - I) over the norm of I; both intensities are taken
+ *              normalised to unit sum so that the measure does not depend on
+ *              the arbitrary scale of the computed field.
+ *   efficiency eta = sum I / (N_ap * sum A^2): the fraction of the incident
+ *              power that reaches the foci, relative to the peak a single focus
+ *              can reach under the same pupil (equality by Cauchy-Schwarz).
+ *   uniformity  U  = 1 - (max r - min r) / (max r + min r), r_n = i_n / t_n over
+ *              foci with a positive target.
+ * out[0..2] = xi, eta, U; out[3] = sum I. */
+void oracle_stats(int nf, const double *theta, const double *target, double n_ap,
+                  double sum_a2, double *out)
+{
+    double sI = 0.0, sT = 0.0;
+    for (int n = 0; n < nf; ++n) {
+        sI += theta[2 * n] * theta[2 * n] + theta[2 * n + 1] * theta[2 * n + 1];
+        sT += target[n];
+    }
+    double d2 = 0.0, i2 = 0.0, rmax = -INFINITY, rmin = INFINITY;
+    for (int n = 0; n < nf; ++n) {
+        double I = theta[2 * n] * theta[2 * n] + theta[2 * n + 1] * theta[2 * n + 1];
+        double in = sI > 0.0 ? I / sI : 0.0;
+        double tn = target[n] / sT;
+        d2 += (tn - in) * (tn - in);
+        i2 += in * in;
+        if (tn > 0.0) {
+            double r = in / tn;
+            if (r > rmax) rmax = r;
+            if (r < rmin) rmin = r;
+        }
+    }
+    out[0] = i2 > 0.0 ? 1.0 - sqrt(d2) / sqrt(i2) : -INFINITY;
+    out[1] = sI / (n_ap * sum_a2);
+    out[2] = (rmax + rmin) > 0.0 ? 1.0 - (rmax - rmin) / (rmax + rmin) : 0.0;
+    out[3] = sI;
+}
+
+/* Weight update and focal-field update of Algorithm 1:
+ *   w_n <- w_n sqrt(t_n / max(i_n, tau))          (generalised weighting)
+ *   Theta'_n = w_n sqrt(target_n) Theta_n / |Theta_n|   (phasor 1 when Theta_n = 0)
+ * The ratio uses the unit-sum intensities t and i (the paper's raw target / I
+ * ratio would shrink every weight by the arbitrary field scale at every step);
+ * tau keeps it finite when a focus is dark. */
+void oracle_weight_update(int nf, const double *theta, const double *target, double *w,
+                          double *theta_new)
+{
+    double sI = 0.0, sT = 0.0;
+    for (int n = 0; n < nf; ++n) {
+        sI += theta[2 * n] * theta[2 * n] + theta[2 * n + 1] * theta[2 * n + 1];
+        sT += target[n];
+    }
+    for (int n = 0; n < nf; ++n) {
+        double re = theta[2 * n], im = theta[2 * n + 1];
+        double I = re * re + im * im;
+        double in = sI > 0.0 ? I / sI : 0.0;
+        double tn = target[n] / sT;
+        w[n] *= sqrt(tn / (in > ORACLE_TAU ? in : ORACLE_TAU));
+        double mag = sqrt(I);
+        double pr = 1.0, pi = 0.0;
+        if (mag > 0.0) { pr = re / mag; pi = im / mag; }
+        double a = w[n] * sqrt(target[n]);
+        theta_new[2 * n] = a * pr;
+        theta_new[2 * n + 1] = a * pi;
+    }
+}
+
+/* Phase-only projection of Algorithm 1: phi = arg E' where A > 0 (0 elsewhere
+ * and where E' = 0), range (-pi, pi]; then E = A exp(i phi). */
+static void project(int np, const double *amp, const double *Ep, double *phi, double *E)
+{
+    for (int p = 0; p < np; ++p) {
+        double ph = 0.0;
+        if (amp[p] > 0.0 && (Ep[2 * p] != 0.0 || Ep[2 * p + 1] != 0.0)) {
+            ph = atan2(Ep[2 * p + 1], Ep[2 * p]);
+            if (ph == -M_PI) ph = M_PI;
+        }
+        phi[p] = ph;
+        E[2 * p] = amp[p] * cos(ph);
+        E[2 * p + 1] = amp[p] * sin(ph);
+    }
+}
+
+/* Algorithm 1.  phi: in = initial phase, out = phase after the run.  w: in/out
+ * weights (pass ones for a fresh start).  hist (nullable): 3 doubles per pass
+ * (xi, eta, U of that pass's forward field).  The termination test (xi > stop,
+ * disabled when stop <= 0) runs before the update, so a stopping pass leaves
+ * phi unchanged and is not counted in iters_done.  theta_final (nullable)
+ * receives the field of the returned phase.  Returns 0, or -1 on allocation
+ * failure. */
+int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double *v,
+               double sx, double sy, int nf, const double *fx, const double *fy,
+               const double *target, double *phi, double *w, int n_iter, double stop,
+               double *hist, int *iters_done, double *theta_final)
+{
+    const size_t np = (size_t)ny * nx;
+    tables t;
+    double *E = malloc(sizeof(double) * 2 * np);
+    double *Ep = malloc(sizeof(double) * 2 * np);
+    double *th = malloc(sizeof(double) * 2 * (size_t)nf);
+    double *thn = malloc(sizeof(double) * 2 * (size_t)nf);
+    int rc = -1;
+    if (!E || !Ep || !th || !thn) goto done;
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); goto done; }
+
+    double n_ap = 0.0, sum_a2 = 0.0;
+    for (size_t p = 0; p < np; ++p) {
+        if (amp[p] > 0.0) n_ap += 1.0;
+        sum_a2 += amp[p] * amp[p];
+    }
+    /* Initial pupil function E0 = A exp(i phi0). */
+    for (size_t p = 0; p < np; ++p) {
+        E[2 * p] = amp[p] * cos(phi[p]);
+        E[2 * p + 1] = amp[p] * sin(phi[p]);
+    }
+    int done_passes = 0;
+    for (int it = 0; it < n_iter; ++it) {
+        forward_t(&t, E, th);                         /* forward propagation */
+        double st[4];
+        oracle_stats(nf, th, target, n_ap, sum_a2, st); /* intensity, accuracy */
+        if (hist) { hist[3 * it] = st[0]; hist[3 * it + 1] = st[1]; hist[3 * it + 2] = st[2]; }
+        if (stop > 0.0 && st[0] > stop) break;        /* termination test */
+        oracle_weight_update(nf, th, target, w, thn); /* weights, focal field */
+        adjoint_t(&t, thn, Ep);                       /* inverse propagation */
+        project((int)np, amp, Ep, phi, E);            /* phase-only constraint */
+        ++done_passes;
+    }
+    if (iters_done) *iters_done = done_passes;
+    if (theta_final) forward_t(&t, E, theta_final);
+    tables_free(&t);
+    rc = 0;
+done:
+    free(E); free(Ep); free(th); free(thn);
+    return rc;
+}
+
+/* Gradient of L(phi) = sum_n g_n I_n(phi) with I_n = |Theta_n|^2 and
+ * E = A exp(i phi):
+ *   dL/dphi_p = 2 Im( conj(E_p) * [adjoint(g * Theta)]_p ).
+ * theta (nullable) receives the forward field at phi. */
+int oracle_phase_gradient(int ny, int nx, const double *amp, const double *u, const double *v,
+                          double sx, double sy, int nf, const double *fx, const double *fy,
+                          const double *phi, const double *g, double *grad, double *theta)
+{
+    const size_t np = (size_t)ny * nx;
+    tables t;
+    double *E = malloc(sizeof(double) * 2 * np);
+    double *Ep = malloc(sizeof(double) * 2 * np);
+    double *th = malloc(sizeof(double) * 2 * (size_t)nf);
+    int rc = -1;
+    if (!E || !Ep || !th) goto done;
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); goto done; }
+    for (size_t p = 0; p < np; ++p) {
+        E[2 * p] = amp[p] * cos(phi[p]);
+        E[2 * p + 1] = amp[p] * sin(phi[p]);
+    }
+    forward_t(&t, E, th);
+    if (theta) memcpy(theta, th, sizeof(double) * 2 * (size_t)nf);
+    for (int n = 0; n < nf; ++n) { th[2 * n] *= g[n]; th[2 * n + 1] *= g[n]; }
+    adjoint_t(&t, th, Ep);
+    for (size_t p = 0; p < np; ++p)
+        grad[p] = 2.0 * (E[2 * p] * Ep[2 * p + 1] - E[2 * p + 1] * Ep[2 * p]);
+    tables_free(&t);
+    rc = 0;
+done:
+    free(E); free(Ep); free(th);
+    return rc;
+}

@@ -1,0 +1,392 @@
+"""Pins of the FP64 oracle against facts it does not compute itself.
+
+Every test here runs on the CPU.  Each one fixes the oracle to the
+mathematics the paper rests on (the DFT, its adjoint, Parseval), to closed
+forms (the single-focus grating), to invariances of Algorithm 1, to a
+hand-worked example, or to brute force, so that a dropped term, a wrong
+sign, a swapped index or a transposed operand in the oracle fails at least
+one of them.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth_ofa
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_field(rng, ny, nx):
+    return rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+
+
+def _full_grid(ny, nx):
+    """Every integer focal point (x = k, y = l), focus n = l * nx + k."""
+    yy, xx = np.meshgrid(np.arange(ny, dtype=float), np.arange(nx, dtype=float), indexing="ij")
+    return xx.reshape(-1), yy.reshape(-1)
+
+
+# --------------------------------------------------------------------------
+# Forward operator (Eq. 1 sampled, Eq. 2 separable)
+# --------------------------------------------------------------------------
+
+def test_forward_equals_fft2_on_integer_grid():
+    """With pupil samples u = 0..nx-1, v = 0..ny-1, s = 1/n and foci on every
+    integer point, the MTP is the 2-D DFT: Theta = numpy.fft.fft2(E)."""
+    rng = np.random.default_rng(1)
+    ny, nx = 7, 12
+    E = _rand_field(rng, ny, nx)
+    fx, fy = _full_grid(ny, nx)
+    th = oracle.forward(E, np.arange(nx, dtype=float), np.arange(ny, dtype=float),
+                        1.0 / nx, 1.0 / ny, fx, fy)
+    ref = np.fft.fft2(E).reshape(-1)
+    assert np.max(np.abs(th - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_forward_fractional_points_equal_zero_padded_fft():
+    """Foci on a grid P times finer than the DFT grid equal the FFT of the
+    pupil zero-padded P times: the conventional IFTA's padding (Eq. 3) that
+    the MTP avoids.  Negative coordinates wrap modulo the padded length."""
+    rng = np.random.default_rng(2)
+    ny, nx, P = 6, 10, 4
+    E = _rand_field(rng, ny, nx)
+    kx = rng.integers(-nx * P // 2, nx * P // 2, size=25)
+    ky = rng.integers(-ny * P // 2, ny * P // 2, size=25)
+    th = oracle.forward(E, np.arange(nx, dtype=float), np.arange(ny, dtype=float),
+                        1.0 / nx, 1.0 / ny, kx / P, ky / P)
+    F = np.fft.fft2(E, s=(ny * P, nx * P))
+    ref = F[ky % (ny * P), kx % (nx * P)]
+    assert np.max(np.abs(th - ref)) <= 1e-11 * np.max(np.abs(F))
+
+
+def test_forward_centred_coordinates_shift_theorem():
+    """Centred pupil coordinates u - c multiply each focal value by the
+    closed-form phase exp(+2 pi i s c x) relative to the uncentred DFT."""
+    rng = np.random.default_rng(3)
+    ny, nx = 8, 6
+    E = _rand_field(rng, ny, nx)
+    fx, fy = _full_grid(ny, nx)
+    cx, cy = (nx - 1) / 2, (ny - 1) / 2
+    th = oracle.forward(E, synth_ofa.centred(nx), synth_ofa.centred(ny), 1.0 / nx, 1.0 / ny,
+                        fx, fy)
+    ref = np.fft.fft2(E).reshape(-1) * np.exp(2j * np.pi * (cx * fx / nx + cy * fy / ny))
+    assert np.max(np.abs(th - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_forward_nonuniform_sampling_brute_force():
+    """Arbitrary, non-uniform pupil and focal samples (the decoupled sampling
+    the MTP allows): compare with a direct 2-D sum of exp terms over every
+    (pupil sample, focus) pair.  A consistency check of the separable
+    evaluation; the independent pins are the FFT ones above."""
+    rng = np.random.default_rng(4)
+    ny, nx = 5, 7
+    E = _rand_field(rng, ny, nx)
+    u = np.sort(rng.uniform(-3, 3, nx))
+    v = np.sort(rng.uniform(-2, 2, ny))
+    fx, fy = rng.uniform(-4, 4, 6), rng.uniform(-4, 4, 6)
+    sx, sy = 0.37, 0.21
+    th = oracle.forward(E, u, v, sx, sy, fx, fy)
+    ref = np.array([sum(E[j, i] * np.exp(-2j * np.pi * (sx * u[i] * fx[n] + sy * v[j] * fy[n]))
+                        for j in range(ny) for i in range(nx)) for n in range(6)])
+    assert np.max(np.abs(th - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+# --------------------------------------------------------------------------
+# Inverse operator (adjoint)
+# --------------------------------------------------------------------------
+
+def test_adjoint_dot_product_identity():
+    """<P E, T> = <E, P^H T> for random fields at arbitrary coordinates."""
+    rng = np.random.default_rng(5)
+    ny, nx, n = 9, 11, 13
+    E = _rand_field(rng, ny, nx)
+    T = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    u, v = synth_ofa.centred(nx), rng.uniform(-5, 5, ny)
+    fx, fy = rng.uniform(-4, 4, n), rng.uniform(-4, 4, n)
+    lhs = np.vdot(oracle.forward(E, u, v, 1 / nx, 1 / ny, fx, fy), T)
+    rhs = np.vdot(E, oracle.adjoint(T, ny, nx, u, v, 1 / nx, 1 / ny, fx, fy))
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+def test_adjoint_equals_scaled_ifft2_on_full_grid():
+    """On the full integer grid the adjoint is ny nx ifft2."""
+    rng = np.random.default_rng(6)
+    ny, nx = 6, 9
+    T = _rand_field(rng, ny, nx)
+    fx, fy = _full_grid(ny, nx)
+    E = oracle.adjoint(T.reshape(-1), ny, nx, np.arange(nx, dtype=float),
+                       np.arange(ny, dtype=float), 1 / nx, 1 / ny, fx, fy)
+    ref = ny * nx * np.fft.ifft2(T)
+    assert np.max(np.abs(E - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_parseval_on_full_grid():
+    """sum |Theta|^2 = ny nx sum |E|^2 over the full integer grid."""
+    rng = np.random.default_rng(7)
+    ny, nx = 8, 8
+    E = _rand_field(rng, ny, nx)
+    fx, fy = _full_grid(ny, nx)
+    th = oracle.forward(E, synth_ofa.centred(nx), synth_ofa.centred(ny), 1 / nx, 1 / ny, fx, fy)
+    assert np.sum(np.abs(th) ** 2) == pytest.approx(ny * nx * np.sum(np.abs(E) ** 2), rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1 steps
+# --------------------------------------------------------------------------
+
+def test_weight_update_hand_example():
+    """Hand-worked three-focus example (exact rationals) of the intensity,
+    accuracy, uniformity, weight update and focal-field update."""
+    g = json.load(open(os.path.join(GOLDEN, "weight_update_3foci.json")))
+    theta = np.array([complex(a, b) for a, b in g["theta"]])
+    target = np.array(g["target"], dtype=float)
+    ex = g["expected"]
+    st = oracle.stats(theta, target, np.ones((2, 2)))
+    assert st["xi"] == pytest.approx(1 - math.sqrt(float(Fraction(ex["xi_sqrt_arg"]))), abs=1e-15)
+    assert st["uniformity"] == pytest.approx(float(Fraction(ex["uniformity"])), abs=1e-15)
+    w, tn = oracle.weight_update(theta, target, np.array(g["w0"], dtype=float))
+    w_ref = np.sqrt([float(Fraction(s)) for s in ex["w_squared"]])
+    assert np.allclose(w, w_ref, rtol=1e-15, atol=0)
+    re = [math.sqrt(float(Fraction(a))) * float(Fraction(b)) for a, b in ex["theta_new_re_over_sqrt"]]
+    im = [math.sqrt(float(Fraction(a))) * float(Fraction(b)) for a, b in ex["theta_new_im_over_sqrt"]]
+    assert np.allclose(tn.real, re, rtol=1e-14, atol=1e-15)
+    assert np.allclose(tn.imag, im, rtol=1e-14, atol=1e-15)
+
+
+def test_weight_update_dark_focus_stays_finite():
+    theta = np.array([0j, 1 + 0j, 2j])
+    w, tn = oracle.weight_update(theta, np.array([1.0, 1.0, 1.0]), np.ones(3))
+    assert np.all(np.isfinite(w)) and np.all(np.isfinite(tn))
+    assert tn[0].imag == 0.0 and tn[0].real > 0.0          # phasor 1 for a zero field
+
+
+@pytest.mark.parametrize("aperture", ["rect", "disc"])
+def test_single_focus_grating_closed_form(aperture):
+    """One focus at a non-grid point, uniform amplitude: after one pass the
+    phase is the linear grating arg(c) + 2 pi (s_x u x0 + s_y v y0) and the
+    next forward field puts all the light on the focus: |Theta|^2 = (sum A)^2,
+    accuracy 1 and efficiency 1."""
+    ny, nx = 24, 20
+    amp = synth_ofa.disc(ny, nx, 10.0).astype(np.float32) if aperture == "disc" \
+        else np.ones((ny, nx), np.float32)
+    rng = np.random.default_rng(8)
+    h = synth_ofa.Hologram("grating", ny, nx, amp, synth_ofa.centred(nx), synth_ofa.centred(ny),
+                           1 / nx, 1 / ny, np.array([3.37]), np.array([-2.81]), np.array([0.7]),
+                           synth_ofa.initial_phase(rng, ny, nx), n_iter=2)
+    r = oracle.gsw(h, n_iter=1)
+    th0 = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)[0]
+    ramp = 2 * np.pi * (h.s_x * h.u[None, :] * h.fx[0] + h.s_y * h.v[:, None] * h.fy[0])
+    expect = np.angle(th0) + ramp
+    on = amp > 0
+    d = np.angle(np.exp(1j * (r["phi"] - expect)))
+    assert np.max(np.abs(d[on])) < 1e-12
+    assert np.all(r["phi"][~on] == 0.0)
+    assert abs(r["theta"][0]) ** 2 == pytest.approx(float(amp.sum()) ** 2, rel=1e-12)
+    st = oracle.stats(r["theta"], h.target, amp)
+    assert st["xi"] == pytest.approx(1.0, abs=1e-12)
+    assert st["eta"] == pytest.approx(1.0, rel=1e-12)
+
+
+def _small(seed=0, ny=16, nx=20, n=7, radius=None):
+    return synth_ofa.random_case(seed, ny, nx, n, radius=radius, amplitude="random", n_iter=4)
+
+
+def test_gsw_scale_invariance():
+    """A -> 4 A and targets -> 2 targets leave the phase trajectory unchanged
+    (the weighting uses unit-sum intensities; the projection drops scale)."""
+    h = _small(1)
+    r1 = oracle.gsw(h)
+    h.amplitude = (4 * h.amplitude).astype(np.float32)
+    h.target = 2 * h.target
+    r2 = oracle.gsw(h)
+    on = h.amplitude > 0
+    assert np.max(np.abs(np.angle(np.exp(1j * (r1["phi"] - r2["phi"])))[on])) < 1e-10
+    assert np.allclose(r1["history"][:, 0], r2["history"][:, 0], rtol=0, atol=1e-12)
+
+
+def test_gsw_translation_adds_linear_ramp():
+    """Shifting every focus by (dx, dy) while adding the matching linear phase
+    to the start phase leaves all intensities unchanged and adds the same
+    ramp to the final phase (Fourier shift theorem through every step)."""
+    h = _small(2, radius=8.0)
+    r1 = oracle.gsw(h)
+    dx, dy = 1.75, -2.5
+    ramp = 2 * np.pi * (h.s_x * h.u[None, :] * dx + h.s_y * h.v[:, None] * dy)
+    h2 = _small(2, radius=8.0)
+    h2.fx = h.fx + dx
+    h2.fy = h.fy + dy
+    r2 = oracle.gsw(h2, phi=np.asarray(h.phi0, np.float64) + ramp)
+    on = h.amplitude > 0
+    d = np.angle(np.exp(1j * (r2["phi"] - r1["phi"] - ramp)))
+    assert np.max(np.abs(d[on])) < 1e-9
+    assert np.allclose(np.abs(r1["theta"]), np.abs(r2["theta"]), rtol=1e-10)
+
+
+def test_gsw_mirror_conjugates_phase():
+    """Foci (x, y) -> (-x, -y) with phi0 -> -phi0 conjugates every field of the
+    iteration, so the final phase is negated."""
+    h = _small(3)
+    r1 = oracle.gsw(h)
+    h2 = _small(3)
+    h2.fx, h2.fy = -h.fx, -h.fy
+    r2 = oracle.gsw(h2, phi=-np.asarray(h.phi0, np.float64))
+    on = h.amplitude > 0
+    assert np.max(np.abs(np.angle(np.exp(1j * (r1["phi"] + r2["phi"])))[on])) < 1e-10
+
+
+def test_gsw_termination_before_update():
+    """The accuracy test runs before the update: the pass whose forward field
+    first exceeds the threshold leaves the phase as it was and is not counted;
+    the returned phase equals that of an unstopped run after as many passes."""
+    h = _small(4)
+    full = oracle.gsw(h, n_iter=8)
+    xi = full["history"][:, 0]
+    k = next(k for k in range(1, 8) if xi[k] > np.max(xi[:k]))
+    stop = 0.5 * (np.max(xi[:k]) + xi[k])
+    r = oracle.gsw(h, n_iter=8, stop=stop)
+    assert r["iters_done"] == k
+    assert r["history"].shape[0] == k + 1
+    ref = oracle.gsw(h, n_iter=k)
+    assert np.array_equal(r["phi"], ref["phi"])
+    # a threshold met by the start phase leaves it untouched
+    one = synth_ofa.random_case(5, 12, 12, 1, n_iter=3)
+    r1 = oracle.gsw(one, stop=0.5)
+    assert r1["iters_done"] == 0
+    assert np.array_equal(r1["phi"], one.phi0.astype(np.float64))
+
+
+def test_gsw_convergence_soft_check():
+    """Plausibility, not parity: the paper reports 99% intensity accuracy after
+    16 iterations for a 9x9 array with various intensities and efficiency
+    above 90% (Sec. 2, Fig. 2(g)-(h)); a 9x9 array on a smaller pupil reaches
+    the same regime."""
+    rng = np.random.default_rng(9)
+    ny = nx = 128
+    amp = synth_ofa.disc(ny, nx, 64.0).astype(np.float32)
+    fx, fy = synth_ofa.grid_foci(9, 9, 4.39)
+    h = synth_ofa.Hologram("9x9", ny, nx, amp, synth_ofa.centred(nx), synth_ofa.centred(ny),
+                           1 / nx, 1 / ny, fx, fy, rng.uniform(0.5, 1.0, 81),
+                           synth_ofa.initial_phase(rng, ny, nx), n_iter=30)
+    r = oracle.gsw(h)
+    xi = r["history"][:, 0]
+    assert np.max(xi[:25]) > 0.99
+    assert oracle.stats(r["theta"], h.target, amp)["eta"] > 0.85
+
+
+# --------------------------------------------------------------------------
+# Gradient (differentiable form)
+# --------------------------------------------------------------------------
+
+def test_phase_gradient_matches_central_differences():
+    h = synth_ofa.config5_gradcheck()
+    rng = np.random.default_rng(10)
+    g = rng.standard_normal(h.n_foci)
+    phi = np.asarray(h.phi0, np.float64)
+    grad, _ = oracle.phase_gradient(h, phi, g)
+
+    def loss(p):
+        th = oracle.forward(oracle.pupil_field(h, p), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+        return float(np.dot(g, np.abs(th) ** 2))
+
+    on = np.argwhere(h.amplitude > 0)
+    pick = on[rng.choice(on.shape[0], 12, replace=False)]
+    eps = 1e-5
+    for (j, i) in pick:
+        pp, pm = phi.copy(), phi.copy()
+        pp[j, i] += eps
+        pm[j, i] -= eps
+        fd = (loss(pp) - loss(pm)) / (2 * eps)
+        assert fd == pytest.approx(grad[j, i], rel=1e-6, abs=1e-6 * np.max(np.abs(grad)))
+    off = h.amplitude == 0
+    assert np.all(grad[off] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# Index work
+# --------------------------------------------------------------------------
+
+def _brute_unique(c):
+    vals = []
+    for x in c:
+        x = 0.0 if x == 0.0 else float(x)
+        if not any(x == y for y in vals):
+            vals.append(x)
+    vals.sort()
+    idx = [sum(1 for y in vals if y < (0.0 if x == 0.0 else x)) for x in c]
+    return np.array(vals), np.array(idx)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_index_oracle_against_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = 40
+    base = rng.uniform(-5, 5, 12)
+    c = base[rng.integers(0, 12, n)]
+    c[rng.integers(0, n, 3)] = -0.0
+    c[rng.integers(0, n, 3)] = 0.0
+    u, idx = oracle.unique_coords(c)
+    bu, bidx = _brute_unique(c)
+    assert np.array_equal(u, bu) and np.array_equal(idx, bidx)
+    assert not np.any(np.signbit(u[u == 0.0]))
+
+
+def test_index_grid_semantics_reduced_grid():
+    """A k x l grid of foci reduces to l unique x and k unique y coordinates
+    (the 9x9 reduced sampling grid of Sec. 2 / Fig. 2(c))."""
+    fx, fy = synth_ofa.grid_foci(9, 9, 4.39)
+    assert oracle.unique_coords(fx)[0].shape[0] == 9
+    assert oracle.unique_coords(fy)[0].shape[0] == 9
+    fx, fy = synth_ofa.grid_foci(3, 5, 2.0)
+    plan = oracle.index_plan(fx, fy, np.ones((4, 4)))
+    assert plan["xu"].shape[0] == 5 and plan["yu"].shape[0] == 3
+    assert plan["axis"] == 0          # fewer unique y than x: reduce along y
+    fx, fy = synth_ofa.grid_foci(5, 3, 2.0)
+    assert oracle.index_plan(fx, fy, np.ones((4, 4)))["axis"] == 1
+
+
+def test_index_compaction_and_csr():
+    amp = np.zeros((6, 7))
+    amp[1, 2] = 1
+    amp[4, 5] = 0.5
+    rows, cols = oracle.compaction(amp)
+    assert rows.tolist() == [1, 4] and cols.tolist() == [2, 5]
+    fx = np.array([1.0, 2.0, 1.0, 3.0])
+    fy = np.array([0.5, 0.5, -1.0, 0.5])
+    p = oracle.index_plan(fx, fy, amp)
+    assert p["yu"].tolist() == [-1.0, 0.5]
+    assert p["row_ptr"].tolist() == [0, 1, 4]
+    assert p["order"].tolist() == [2, 0, 1, 3]
+    assert not p["duplicate"]
+    assert oracle.has_duplicate_foci(np.array([0.0, -0.0]), np.array([1.0, 1.0]))
+
+
+# --------------------------------------------------------------------------
+# Units of the paper's system (Table 1, Eq. 3)
+# --------------------------------------------------------------------------
+
+def test_table1_zero_padding_and_focal_unit():
+    """Table 1: 785 nm, 1000 SLM pixels of 12.5 um, camera pitch 3.45 um,
+    f = 250 mm.  Eq. 3 gives the IFTA padding M = M0 lambda / (2 NA dd) = 4550.7
+    (the paper quotes 4551); the focal unit lambda f / (M0 p) is 15.7 um, i.e.
+    4.55 camera pixels, and 4551 / 20 leaves 227 foci per axis at a 20-pixel gap."""
+    lam, m0, p, dd, f = 785e-9, 1000, 12.5e-6, 3.45e-6, 0.25
+    na = (m0 * p / 2) / f
+    M = m0 * lam / (2 * na * dd)
+    assert M == pytest.approx(4550.7, abs=0.05)
+    assert math.ceil(M) == 4551
+    unit = lam * f / (m0 * p)
+    assert unit == pytest.approx(15.7e-6, rel=1e-9)
+    assert unit / dd == pytest.approx(M / m0, rel=1e-12)
+    assert math.ceil(M) // 20 == 227
+
+
+def test_config1_aperture_pixel_count():
+    h = synth_ofa.config1()
+    assert int(np.count_nonzero(h.amplitude)) == 3228
+    rows, cols = oracle.compaction(h.amplitude)
+    assert rows.shape[0] == 64 and cols.shape[0] == 64
