@@ -1,0 +1,242 @@
+/*
+ * gswmtp.h - C ABI of the MI355X (gfx950) GSW-MTP hologram library.
+ *
+ * The library computes phase-only holograms (CGHs) for arbitrary optical focus
+ * arrays with the weighted Gerchberg-Saxton iteration of Liu et al.,
+ * "Fast generation of arbitrary optical focus array" (arXiv:2206.12661),
+ * Algorithm 1, in which the diffraction step is the matrix triple product of
+ * Eq. 2,  Theta = Omega_y E Omega_x,  Omega_x = exp(-i 2 pi K_x^T X),
+ * Omega_y = exp(-i 2 pi Y^T K_y),  evaluated only at the foci, with all-zero
+ * pupil rows/columns and non-focus focal samples removed (Sec. 2, Fig. 1).
+ *
+ * Conventions used by every call:
+ *   - The pupil is ny x nx samples, row-major (row j <-> y / v_j, column i <->
+ *     x / u_i).  Phase arrays are float32 [ny*nx]; complex arrays are float32
+ *     interleaved (re, im).
+ *   - The kernel phase of a pupil sample (u, v) and a focus (x, y) is
+ *     -2 pi (s_x u x + s_y v y)  (sign of Eq. 1).  With u, v in pixels and
+ *     s_x = 1/nx, s_y = 1/ny, focal coordinates are in units of lambda f/(N du).
+ *   - Foci keep the caller's order in every per-focus array.
+ *   - Every call returns an int status: GSWMTP_OK (0) or a negative
+ *     GSWMTP_E_* code; gswmtp_last_error() gives a message for the last
+ *     failing call on a plan.  No C++ exception crosses this boundary.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ *   - Streams: every plan orders its GPU work after work already queued on the
+ *     caller's stream (the one given at creation or by gswmtp_set_stream; NULL
+ *     is the default stream) and makes that stream wait for it, so device
+ *     pointers passed to *_device calls may be produced and consumed on the
+ *     caller's stream without extra synchronisation.  Calls with host output
+ *     buffers return after the data is copied.
+ *   - Ownership: gswmtp_plan_create deep-copies every input array; the caller
+ *     may free or modify them afterwards.  Output buffers belong to the
+ *     caller.  The library frees only what it allocated.
+ */
+#ifndef GSWMTP_H
+#define GSWMTP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSWMTP_VERSION 100
+
+/* Status codes. */
+enum {
+    GSWMTP_OK = 0,
+    GSWMTP_E_INVAL = -1,          /* bad size, pointer, non-finite or negative input */
+    GSWMTP_E_DUPFOCUS = -2,       /* two foci with identical (x, y) */
+    GSWMTP_E_EMPTYAPERTURE = -3,  /* amplitude (after mask) is zero everywhere */
+    GSWMTP_E_NOMEM = -4,          /* host or device allocation failed */
+    GSWMTP_E_HIP = -5,            /* a HIP runtime call failed */
+    GSWMTP_E_NONFINITE = -6,      /* a focus intensity sum became non-finite */
+    GSWMTP_E_NODEV = -7,          /* no usable gfx950 device */
+    GSWMTP_E_UNSUPPORTED = -8     /* valid request this build does not implement */
+};
+
+/* Arithmetic of the two dense complex products (forward and adjoint MTP).
+ *   FP32:   float32 operands, float32 MFMA (v_mfma_f32_32x32x2_f32).
+ *   BF16X3: each operand split x = hi + lo in bfloat16; products
+ *           hi*hi + hi*lo + lo*hi on bf16 MFMA with float32 accumulation.
+ *   FP16X3: the same with float16 halves (operands pre-scaled by powers of 2).
+ *   BF16X6: three-term bfloat16 split, six products.
+ * Kernel-matrix phases are always reduced in float64; focus statistics are
+ * always reduced in float64. */
+typedef enum {
+    GSWMTP_FP32 = 0,
+    GSWMTP_BF16X3 = 1,
+    GSWMTP_FP16X3 = 2,
+    GSWMTP_BF16X6 = 3
+} gswmtp_precision;
+
+/* Focal-field update rule (Algorithm 1, weight update).
+ *   GSW:  generalised weighting w <- w sqrt(t / i) (the paper's method).
+ *   GS:   no weighting (w stays 1): the plain Gerchberg-Saxton baseline. */
+typedef enum {
+    GSWMTP_WEIGHT_GSW = 0,
+    GSWMTP_WEIGHT_GS = 1
+} gswmtp_weighting;
+
+/* Plan descriptor.  Fill with gswmtp_desc_init, then set fields.
+ * All pointers are HOST pointers and are copied by gswmtp_plan_create. */
+typedef struct gswmtp_desc {
+    int ny, nx;                   /* pupil samples, 1..16384 each */
+    const float *amplitude;       /* [ny*nx] >= 0, finite; NULL = all ones.
+                                     Zero marks samples outside the aperture. */
+    const uint8_t *mask;          /* [ny*nx]; NULL = all ones.  Effective
+                                     amplitude is mask ? amplitude : 0. */
+    const double *u;              /* [nx] pupil x coordinates; NULL = i-(nx-1)/2 */
+    const double *v;              /* [ny] pupil y coordinates; NULL = j-(ny-1)/2 */
+    double s_x, s_y;              /* kernel phase scales, finite and non-zero */
+    int n_foci;                   /* 1..262144 */
+    const double *fx, *fy;        /* [n_foci] focus coordinates, finite */
+    const double *target;         /* [n_foci] target intensities, >= 0, sum > 0 */
+    const float *phi0;            /* [ny*nx] initial phase, finite; NULL = zeros */
+    int precision;                /* gswmtp_precision */
+    int axis;                     /* -1 auto, 0 reduce along y, 1 along x */
+    int weighting;                /* gswmtp_weighting */
+} gswmtp_desc;
+
+/* Index information of a plan (the reduced focal grid and pupil compaction). */
+typedef struct gswmtp_index_info {
+    int n_foci;
+    int ux, uy;                   /* unique focus x / y coordinates */
+    int ny_kept, nx_kept;         /* pupil rows / columns with any non-zero amplitude */
+    int axis;                     /* 0: dense product over the y foci (M = uy); 1: over x */
+    int n_aperture;               /* samples with amplitude > 0 */
+    double sum_a2;                /* sum of amplitude^2 over the pupil */
+} gswmtp_index_info;
+
+typedef struct gswmtp_plan gswmtp_plan;
+typedef struct gswmtp_batch gswmtp_batch;
+
+/* Library version (GSWMTP_VERSION of the build). */
+int gswmtp_version(void);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *gswmtp_status_string(int status);
+
+/* Message of the last failed call on plan p (static "" if none or p == NULL). */
+const char *gswmtp_last_error(const gswmtp_plan *p);
+
+/* Fill d with defaults: all pointers NULL, s_x = s_y = 0 (must be set),
+ * precision FP32, axis -1, weighting GSW.  Returns GSWMTP_E_INVAL if d == NULL. */
+int gswmtp_desc_init(gswmtp_desc *d);
+
+/* Build a plan on the current HIP device (Algorithm 1 inputs: A, phi0,
+ * target intensities, w0 = 1, focus coordinates).
+ * Validates every input on the host first (GSWMTP_E_INVAL, no GPU use), then
+ * runs the plan kernels: effective amplitude and compaction, unique focal
+ * coordinates and gather indices (GSWMTP_E_DUPFOCUS on a repeated (x, y);
+ * -0.0 and +0.0 are one coordinate), axis choice (fewer unique coordinates,
+ * ties to y), kernel matrices (phase reduced in float64), E0 = A exp(i phi0).
+ * Synchronises once to size the product buffers.  stream: hipStream_t or NULL.
+ * On failure *out is NULL and nothing is leaked. */
+int gswmtp_plan_create(gswmtp_plan **out, const gswmtp_desc *d, void *stream);
+
+/* Free a plan (NULL-safe).  Waits for its queued work first. */
+int gswmtp_plan_destroy(gswmtp_plan *p);
+
+/* Change the caller stream used for ordering (NULL = default stream). */
+int gswmtp_set_stream(gswmtp_plan *p, void *stream);
+
+/* Block until all work queued by p has finished. */
+int gswmtp_sync(gswmtp_plan *p);
+
+/* Queue n_iter >= 0 passes of Algorithm 1 (forward MTP, foci intensities,
+ * accuracy xi, termination test, weight update, focal-field update, adjoint
+ * MTP, phase-only projection).  If stop_accuracy > 0, a pass whose forward
+ * field has xi > stop_accuracy ends the run before updating anything; later
+ * queued passes do nothing.  Asynchronous: returns once the work is queued.
+ * Passes are replayed from a captured HIP graph unless the environment
+ * variable GSWMTP_NO_GRAPH is set to a non-zero value. */
+int gswmtp_iterate(gswmtp_plan *p, int n_iter, double stop_accuracy);
+
+/* Total passes that updated the phase since creation or the last set_state
+ * (synchronises). */
+int gswmtp_iterations_done(gswmtp_plan *p, int *n);
+
+/* Current phase phi, (-pi, pi], 0 outside the aperture: host [ny*nx]. */
+int gswmtp_get_phase(gswmtp_plan *p, float *out);
+/* Same into device memory [ny*nx] (stream-ordered, no host sync). */
+int gswmtp_get_phase_device(gswmtp_plan *p, float *dev_out);
+
+/* Replace the current phase (host / device [ny*nx], finite): E = A exp(i phi).
+ * Weights and the iteration count are kept. */
+int gswmtp_set_phase(gswmtp_plan *p, const float *phi);
+int gswmtp_set_phase_device(gswmtp_plan *p, const float *dev_phi);
+
+/* Focal field Theta of the CURRENT phase at every focus (caller order),
+ * interleaved complex [2*n_foci] on the host.  Runs a forward pass when the
+ * phase changed since the last one. */
+int gswmtp_get_foci_field(gswmtp_plan *p, float *out);
+/* Same into device memory; dev_intensity (nullable) receives |Theta|^2 [n_foci]. */
+int gswmtp_get_foci_field_device(gswmtp_plan *p, float *dev_field, float *dev_intensity);
+
+/* Accuracy xi, efficiency eta and uniformity of the CURRENT phase's field
+ * (any output pointer may be NULL). */
+int gswmtp_get_stats(gswmtp_plan *p, double *xi, double *eta, double *uniformity);
+
+/* Weights w [n_foci] (float64, host). */
+int gswmtp_get_weights(gswmtp_plan *p, double *out);
+int gswmtp_set_weights(gswmtp_plan *p, const double *w);
+
+/* Per-pass history of (xi, eta, uniformity) of the field each pass started
+ * from, oldest first.  Copies min(cap, stored) entries (3 doubles each) of the
+ * most recent passes; *n receives the number copied.  The ring keeps the last
+ * 4096 passes. */
+int gswmtp_get_history(gswmtp_plan *p, double *buf, int cap, int *n);
+
+/* Checkpoint: phase [ny*nx], weights [n_foci], pass count.  set_state restores
+ * all three and clears the history.  Either array may be NULL to skip it. */
+int gswmtp_get_state(gswmtp_plan *p, float *phi, double *w, int *iters);
+int gswmtp_set_state(gswmtp_plan *p, const float *phi, const double *w, int iters);
+
+/* Index results (host).  info is required; each array may be NULL:
+ * ix, iy [n_foci] gather indices; xu [ux], yu [uy] sorted unique
+ * coordinates; rows [ny_kept], cols [nx_kept] kept pupil rows/columns. */
+int gswmtp_get_index(gswmtp_plan *p, gswmtp_index_info *info, int32_t *ix, int32_t *iy,
+                     double *xu, double *yu, int32_t *rows, int32_t *cols);
+
+/* Operator-level calls (do not touch the plan's phase, weights or history).
+ * forward_field: Theta = P(E) at the foci for an arbitrary complex pupil field
+ *   E (host, interleaved [2*ny*nx]); samples outside the kept rows/columns are
+ *   ignored.  Output host [2*n_foci].
+ * adjoint_field: E' = P^H(Theta) (no projection) for focal values Theta (host
+ *   [2*n_foci]); output host [2*ny*nx], zero outside the kept rows/columns. */
+int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta);
+int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E);
+
+/* Gradient of L = sum_n g_n |Theta_n|^2 with respect to the current phase:
+ *   dL/dphi = 2 Im(conj(E) * P^H(g * Theta)),
+ * with Theta the field of the current phase.  dev_g: device float [n_foci];
+ * dev_grad: device float [ny*nx] (0 outside the aperture).  Stream-ordered. */
+int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad);
+
+/* Profiling: run n_iter passes eagerly with HIP events around each stage on
+ * the plan's stream and return the mean milliseconds per launch of each stage
+ * in ms_out[GSWMTP_N_STAGES] (order: forward product, gather, focus update,
+ * scatter, adjoint product + projection).  Changes the plan state exactly as
+ * gswmtp_iterate(p, n_iter, 0) would. */
+#define GSWMTP_N_STAGES 5
+int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out);
+
+/* Kernel names of the stages, for matching profiler output (static strings). */
+const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
+
+/* Batched form: run several independent plans together, one grouped launch per
+ * stage for all of them, replayed from one captured HIP graph.  The plans must
+ * outlive the batch and use FP32 precision; their results equal those of
+ * gswmtp_iterate on each plan alone.  stream as for plans. */
+int gswmtp_batch_create(gswmtp_batch **out, gswmtp_plan *const *plans, int n_plans, void *stream);
+int gswmtp_batch_iterate(gswmtp_batch *b, int n_iter);
+int gswmtp_batch_sync(gswmtp_batch *b);
+int gswmtp_batch_destroy(gswmtp_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSWMTP_H */

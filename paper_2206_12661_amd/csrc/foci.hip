@@ -1,0 +1,265 @@
+// Focal-plane stages of a GSW-MTP pass: the focus gather that completes the
+// forward matrix triple product at the foci only, the focus statistics and
+// generalised weight update of Algorithm 1, and the scatter of the updated
+// focal field back onto the reduced focal rows (every non-focus sample of the
+// reduced focal grid is zero in the inverse propagation).
+#include "gswmtp_internal.h"
+
+namespace gswmtp {
+namespace {
+
+constexpr int kUpdThreads = 1024;
+
+// Theta_n = sum_i L[ir_n][i] Wc[ic_n][i]: one wave per focus, lanes stride
+// over the Ck kept columns, fixed-order 64-lane tree at the end.
+__global__ __launch_bounds__(256) void focus_gather(
+    const float *__restrict__ lr, const float *__restrict__ li, const float *__restrict__ wr,
+    const float *__restrict__ wi, const int *__restrict__ ir, const int *__restrict__ ic,
+    float *__restrict__ theta, int nf, int Ck, int ld, const int *done) {
+  if (done && *done) return;
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (n >= nf) return;
+  const float *a_r = lr + (size_t)ir[n] * ld, *a_i = li + (size_t)ir[n] * ld;
+  const float *b_r = wr + (size_t)ic[n] * ld, *b_i = wi + (size_t)ic[n] * ld;
+  float sr = 0.f, si = 0.f;
+  for (int i = lane; i < Ck; i += 64) {
+    const float xr = a_r[i], xi = a_i[i], yr = b_r[i], yi = b_i[i];
+    sr = fmaf(xr, yr, fmaf(-xi, yi, sr));
+    si = fmaf(xr, yi, fmaf(xi, yr, si));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off, 64);
+    si += __shfl_xor(si, off, 64);
+  }
+  if (lane == 0) {
+    theta[2 * n] = sr;
+    theta[2 * n + 1] = si;
+  }
+}
+
+// Deterministic block reductions (fixed thread-to-element map, fixed tree).
+template <typename T, typename Op>
+__device__ T block_reduce(T v, T *sh, Op op) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kUpdThreads / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = op(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  T r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+struct Sum { __device__ double operator()(double a, double b) const { return a + b; } };
+struct Max { __device__ double operator()(double a, double b) const { return a > b ? a : b; } };
+struct Min { __device__ double operator()(double a, double b) const { return a < b ? a : b; } };
+
+struct UpdateArgs {
+  float *theta;            // [2 nf] forward field (read); written as float32
+  float *theta_new;        // [2 nf] updated focal field (scaled by a power of 2)
+  float *intensity;        // [nf] |Theta|^2
+  const double *target;    // [nf] raw target intensities
+  const double *tnorm;     // [nf] target / sum(target)
+  double *w;               // [nf]
+  double *stats;           // ST_*
+  double *hist;            // [3 kHistCap]
+  int *ctrl;               // CTRL_*
+  int nf;
+  int mode;                // UPD_ITERATE or UPD_STATS
+  int weighting;           // GSWMTP_WEIGHT_*
+  double n_ap, sum_a2;
+};
+
+// Algorithm 1 between the two propagations, for all foci, in one workgroup:
+//   I_n = |Theta_n|^2; accuracy xi from unit-sum intensities; efficiency and
+//   uniformity; termination test (before any update); weight update
+//   w <- w sqrt(t / max(i, 1e-30)); new focal field w sqrt(target) Theta/|Theta|
+//   (phasor 1 at a dark focus), written scaled by 2^e so its largest
+//   magnitude is in [0.5, 1) - the phase projection discards the scale.
+// All reductions are float64 in a fixed order.
+__global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
+  __shared__ double sh[kUpdThreads];
+  __shared__ int stop_flag;
+  const int t = threadIdx.x;
+  if (a.mode == UPD_ITERATE && a.ctrl[CTRL_DONE]) return;
+
+  double sI = 0.0;
+  for (int n = t; n < a.nf; n += kUpdThreads) {
+    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
+    const double I = re * re + im * im;
+    a.intensity[n] = (float)I;
+    sI += I;
+  }
+  sI = block_reduce(sI, sh, Sum());
+
+  double d2 = 0.0, i2 = 0.0, rmax = -INFINITY, rmin = INFINITY;
+  const double inv = sI > 0.0 ? 1.0 / sI : 0.0;
+  for (int n = t; n < a.nf; n += kUpdThreads) {
+    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
+    const double in = (re * re + im * im) * inv;
+    const double tn = a.tnorm[n];
+    d2 += (tn - in) * (tn - in);
+    i2 += in * in;
+    if (tn > 0.0) {
+      const double r = in / tn;
+      rmax = r > rmax ? r : rmax;
+      rmin = r < rmin ? r : rmin;
+    }
+  }
+  d2 = block_reduce(d2, sh, Sum());
+  i2 = block_reduce(i2, sh, Sum());
+  rmax = block_reduce(rmax, sh, Max());
+  rmin = block_reduce(rmin, sh, Min());
+
+  if (t == 0) {
+    const double xi = i2 > 0.0 ? 1.0 - sqrt(d2) / sqrt(i2) : -INFINITY;
+    const double eta = sI / (a.n_ap * a.sum_a2);
+    const double U = (rmax + rmin) > 0.0 ? 1.0 - (rmax - rmin) / (rmax + rmin) : 0.0;
+    a.stats[ST_XI] = xi;
+    a.stats[ST_ETA] = eta;
+    a.stats[ST_U] = U;
+    a.stats[ST_SUMI] = sI;
+    int stop = 0;
+    if (a.mode == UPD_ITERATE) {
+      const int h = a.ctrl[CTRL_HIST];
+      double *e = a.hist + 3 * (h % kHistCap);
+      e[0] = xi;
+      e[1] = eta;
+      e[2] = U;
+      a.ctrl[CTRL_HIST] = h + 1;
+      if (!isfinite(sI)) {
+        a.ctrl[CTRL_NONFINITE] = 1;
+        stop = 1;
+      }
+      const double X = a.stats[ST_STOP];
+      if (X > 0.0 && xi > X) stop = 1;
+      if (stop) a.ctrl[CTRL_DONE] = 1;
+    }
+    stop_flag = stop;
+  }
+  __syncthreads();
+  if (a.mode != UPD_ITERATE || stop_flag) return;
+
+  // weight update and new focal field
+  double amax = 0.0;
+  for (int n = t; n < a.nf; n += kUpdThreads) {
+    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
+    const double I = re * re + im * im;
+    double w = a.w[n];
+    if (a.weighting == GSWMTP_WEIGHT_GSW) {
+      const double in = I * inv;
+      w *= sqrt(a.tnorm[n] / (in > 1e-30 ? in : 1e-30));
+      a.w[n] = w;
+    }
+    const double amag = w * sqrt(a.target[n]);
+    amax = amag > amax ? amag : amax;
+  }
+  amax = block_reduce(amax, sh, Max());
+  int e = 0;
+  if (amax > 0.0 && isfinite(amax)) e = -ilogb(amax) - 1;
+  const double scale = ldexp(1.0, e);
+  for (int n = t; n < a.nf; n += kUpdThreads) {
+    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
+    const double mag = sqrt(re * re + im * im);
+    double pr = 1.0, pi = 0.0;
+    if (mag > 0.0) {
+      pr = re / mag;
+      pi = im / mag;
+    }
+    const double amag = a.w[n] * sqrt(a.target[n]) * scale;
+    a.theta_new[2 * n] = (float)(amag * pr);
+    a.theta_new[2 * n + 1] = (float)(amag * pi);
+  }
+  if (t == 0) a.ctrl[CTRL_ITERS] += 1;
+}
+
+// Focal values for the phase gradient: g_n Theta_n.
+__global__ void grad_field(const float *__restrict__ theta, const float *__restrict__ g,
+                           float *__restrict__ out, int nf) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nf) return;
+  out[2 * n] = g[n] * theta[2 * n];
+  out[2 * n + 1] = g[n] * theta[2 * n + 1];
+}
+
+// S[a][i] = sum_{n in row a} Theta'_n conj(Wc[ic_n][i]) for all a < Urp and
+// i < Cp (rows past Ur and padded columns come out zero).  Foci of a row are
+// summed in ascending (ic, n) order.
+__global__ __launch_bounds__(256) void focus_scatter(
+    const float *__restrict__ tn, const float *__restrict__ wr, const float *__restrict__ wi,
+    const int *__restrict__ ic, const int *__restrict__ ptr, const int *__restrict__ foci,
+    float *__restrict__ sr, float *__restrict__ si, int Ur, int Cp, const int *done) {
+  if (done && *done) return;
+  const int a = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Cp) return;
+  float accr = 0.f, acci = 0.f;
+  if (a < Ur) {
+    const int p0 = ptr[a], p1 = ptr[a + 1];
+    for (int p = p0; p < p1; ++p) {
+      const int n = foci[p];
+      const float xr = tn[2 * n], xi = tn[2 * n + 1];
+      const size_t o = (size_t)ic[n] * Cp + i;
+      const float yr = wr[o], yi = -wi[o];
+      accr = fmaf(xr, yr, fmaf(-xi, yi, accr));
+      acci = fmaf(xr, yi, fmaf(xi, yr, acci));
+    }
+  }
+  sr[(size_t)a * Cp + i] = accr;
+  si[(size_t)a * Cp + i] = acci;
+}
+
+}  // namespace
+
+hipError_t launch_gather(const gswmtp_plan *p, const float *lr, const float *li, float *theta,
+                         bool honour_done, hipStream_t s) {
+  const Dims &d = p->d;
+  const int *ir = d.axis == 0 ? p->b.iy : p->b.ix;
+  const int *ic = d.axis == 0 ? p->b.ix : p->b.iy;
+  hipLaunchKernelGGL(focus_gather, dim3((d.nf + 3) / 4), dim3(256), 0, s, lr, li, p->b.wc_r,
+                     p->b.wc_i, ir, ic, theta, d.nf, d.Ck, d.Cp,
+                     honour_done ? p->b.ctrl + CTRL_DONE : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
+  UpdateArgs a{};
+  a.theta = p->b.theta;
+  a.theta_new = p->b.theta_new;
+  a.intensity = p->b.intensity;
+  a.target = p->b.target;
+  a.tnorm = p->b.tnorm;
+  a.w = p->b.w;
+  a.stats = p->b.stats;
+  a.hist = p->b.hist;
+  a.ctrl = p->b.ctrl;
+  a.nf = p->d.nf;
+  a.mode = mode;
+  a.weighting = p->weighting;
+  a.n_ap = (double)p->d.n_ap;
+  a.sum_a2 = p->d.sum_a2;
+  hipLaunchKernelGGL(focus_update, dim3(1), dim3(kUpdThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_field(const gswmtp_plan *p, const float *g, hipStream_t s) {
+  hipLaunchKernelGGL(grad_field, dim3((p->d.nf + 255) / 256), dim3(256), 0, s, p->b.theta, g,
+                     p->b.theta_new, p->d.nf);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,
+                          hipStream_t s) {
+  const Dims &d = p->d;
+  const int *ic = d.axis == 0 ? p->b.ix : p->b.iy;
+  hipLaunchKernelGGL(focus_scatter, dim3((d.Cp + 255) / 256, d.Urp), dim3(256), 0, s, theta_new,
+                     p->b.wc_r, p->b.wc_i, ic, p->b.csr_ptr, p->b.csr_foci, p->b.s_r, p->b.s_i,
+                     d.Ur, d.Cp, honour_done ? p->b.ctrl + CTRL_DONE : nullptr);
+  return hipGetLastError();
+}
+
+}  // namespace gswmtp

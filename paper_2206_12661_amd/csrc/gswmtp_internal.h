@@ -1,0 +1,120 @@
+// Internal declarations of the gfx950 GSW-MTP library (not part of the C ABI).
+//
+// Layout of a plan on the device ("internal orientation"):
+//   The dense complex product of Eq. 2 runs over one focal axis, the "r" axis
+//   (y unless x has fewer unique focus coordinates).  Internal pupil row r is
+//   the r-th kept pupil row (axis y) or kept pupil column (axis x); internal
+//   column c is the other kept pupil coordinate.  Every matrix is stored as two
+//   float32 planes (real, imaginary), row-major, zero-padded to tile multiples:
+//     P    [Rp][Cp]   pupil field E = A exp(i phi)        (Rk x Ck used)
+//     amp  [Rp][Cp]   amplitude, 0 in the padding
+//     OmT  [Rp][Urp]  Omega_r^T: OmT[j][a] = exp(-2 pi i s_r ur_j R_a)
+//     OmC  [Urp][Rp]  conj(Omega_r):  OmC[a][j] = conj(OmT[j][a])
+//     Wc   [Uc][Cp]   Omega_c^T: Wc[b][i] = exp(-2 pi i s_c uc_i C_b)
+//     L    [Urp][Cp]  L = Omega_r P              (forward product)
+//     S    [Urp][Cp]  scatter of the new focal field onto its r rows
+//   One pass:  L = OmT^T P;  Theta_n = sum_i L[ir_n][i] Wc[ic_n][i];
+//   focus update;  S[a][i] = sum_{n: ir_n = a} Theta'_n conj(Wc[ic_n][i]);
+//   P = amp * normalise(OmC^T S).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/gswmtp.h"
+
+namespace gswmtp {
+
+constexpr int kHistCap = 4096;     // history ring entries
+constexpr int kPadRows = 64;       // padding granule of M / K dimensions
+constexpr int kPadCols = 64;       // padding granule of the N dimension
+constexpr int kMaxFoci = 262144;
+constexpr int kMaxSide = 16384;
+
+// Control block (device ints): done flag, passes done, history count, non-finite flag.
+enum { CTRL_DONE = 0, CTRL_ITERS = 1, CTRL_HIST = 2, CTRL_NONFINITE = 3, CTRL_N = 8 };
+// Stats block (device doubles): xi, eta, U, sum I, stop threshold, ...
+enum { ST_XI = 0, ST_ETA = 1, ST_U = 2, ST_SUMI = 3, ST_STOP = 4, ST_N = 8 };
+
+struct Dims {
+  int ny = 0, nx = 0, nf = 0;
+  int ux = 0, uy = 0, ny_kept = 0, nx_kept = 0;
+  int axis = 0;
+  int Rk = 0, Ck = 0, Ur = 0, Uc = 0;   // internal orientation
+  int Rp = 0, Cp = 0, Urp = 0;          // padded
+  int n_ap = 0;
+  double sum_a2 = 0.0;
+};
+
+// Device buffers of one plan.
+struct Bufs {
+  // inputs and index work (sized by ny, nx, nf)
+  double *fx = nullptr, *fy = nullptr, *target = nullptr, *tnorm = nullptr;
+  double *xu = nullptr, *yu = nullptr;
+  int *ix = nullptr, *iy = nullptr, *firstx = nullptr, *firsty = nullptr;
+  int *rows = nullptr, *cols = nullptr, *row_pos = nullptr, *col_pos = nullptr;
+  int *keep_row = nullptr, *keep_col = nullptr;
+  float *aeff = nullptr;                 // [ny][nx] effective amplitude (user orientation)
+  double *ucoord = nullptr, *vcoord = nullptr;
+  int *csr_ptr = nullptr, *csr_foci = nullptr;
+  int *scalars = nullptr;                // plan-time integer results
+  double *dscalars = nullptr;            // plan-time float64 results
+  int *dup = nullptr;
+  // products and state (sized after the index work)
+  float *omt_r = nullptr, *omt_i = nullptr, *omc_r = nullptr, *omc_i = nullptr;
+  float *wc_r = nullptr, *wc_i = nullptr;
+  float *amp = nullptr, *p_r = nullptr, *p_i = nullptr;
+  float *l_r = nullptr, *l_i = nullptr, *s_r = nullptr, *s_i = nullptr;
+  float *x_r = nullptr, *x_i = nullptr;  // operator-call scratch pupil
+  float *theta = nullptr, *theta_new = nullptr;   // interleaved [2*nf]
+  float *intensity = nullptr;            // [nf]
+  double *w = nullptr, *stats = nullptr, *hist = nullptr;
+  int *ctrl = nullptr;
+  float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
+};
+
+struct GemmTile { int bm = 64, bn = 64; };
+
+}  // namespace gswmtp
+
+struct gswmtp_plan {
+  int device = 0;
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_user = nullptr, ev_int = nullptr;
+  hipEvent_t ev_t[GSWMTP_N_STAGES + 1] = {};
+  gswmtp::Dims d;
+  gswmtp::Bufs b;
+  int precision = GSWMTP_FP32;
+  int weighting = GSWMTP_WEIGHT_GSW;
+  gswmtp::GemmTile tile_fwd, tile_bwd;
+  void *pool0 = nullptr, *pool1 = nullptr;
+  size_t pool0_bytes = 0, pool1_bytes = 0;
+  hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
+  bool fwd_valid = false;                 // theta/stats match the current phase
+  bool use_graph = true;
+  std::string err;
+};
+
+namespace gswmtp {
+
+// Kernel launchers (stream-ordered, no synchronisation).
+// honour_done: the kernel returns at once when the plan's done flag is set
+// (early termination inside a queued / graph-replayed run of passes).
+hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float *br,
+                        const float *bi, float *cr, float *ci, const float *er,
+                        const float *ei, bool honour_done, hipStream_t s);
+hipError_t launch_gather(const gswmtp_plan *p, const float *lr, const float *li, float *theta,
+                         bool honour_done, hipStream_t s);
+hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s);
+hipError_t launch_grad_field(const gswmtp_plan *p, const float *g, hipStream_t s);
+hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,
+                          hipStream_t s);
+const char *cgemm_kernel_name(const gswmtp_plan *p, bool forward, int epi);
+
+enum { EPI_STORE = 0, EPI_PROJECT = 1, EPI_GRAD = 2 };
+enum { UPD_ITERATE = 0, UPD_STATS = 1, UPD_GRAD = 2 };
+
+}  // namespace gswmtp

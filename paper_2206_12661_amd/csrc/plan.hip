@@ -1,0 +1,1227 @@
+// C ABI, plan construction and the per-pass driver of the gfx950 GSW-MTP
+// library (Liu et al., arXiv:2206.12661, Algorithm 1 with the matrix triple
+// product of Eq. 2).
+//
+// Plan construction runs on the GPU: effective amplitude, compaction of the
+// pupil to its non-zero rows/columns, the reduced focal grid (sorted unique
+// focus coordinates per axis and the gather index of every focus), duplicate
+// detection, the per-row focus lists used by the scatter, the kernel matrices
+// (phase arguments reduced in float64), and E0 = A exp(i phi0).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gswmtp_internal.h"
+
+using namespace gswmtp;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Error handling
+// ---------------------------------------------------------------------------
+
+int fail(gswmtp_plan *p, int code, const char *what, hipError_t e = hipSuccess) {
+  if (p) {
+    char buf[512];
+    if (e != hipSuccess)
+      snprintf(buf, sizeof buf, "%s: %s (%s)", what, hipGetErrorString(e), hipGetErrorName(e));
+    else
+      snprintf(buf, sizeof buf, "%s", what);
+    p->err = buf;
+  }
+  return code;
+}
+
+#define HIP_TRY(p, expr)                                       \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return fail((p), GSWMTP_E_HIP, #expr, e_); \
+  } while (0)
+
+// Keeps the plan's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      changed = hipSetDevice(dev) == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+// Orders plan work after the caller's stream and the caller after plan work.
+hipError_t enter(gswmtp_plan *p) {
+  hipError_t e = hipEventRecord(p->ev_user, p->user_stream);
+  if (e != hipSuccess) return e;
+  return hipStreamWaitEvent(p->stream, p->ev_user, 0);
+}
+hipError_t leave(gswmtp_plan *p) {
+  hipError_t e = hipEventRecord(p->ev_int, p->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamWaitEvent(p->user_stream, p->ev_int, 0);
+}
+
+size_t round_up(size_t v, size_t g) { return (v + g - 1) / g * g; }
+
+// Bump allocator over one device allocation.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(size_t count) {
+    T *r = reinterpret_cast<T *>(base ? base + off : nullptr);
+    off += round_up(count * sizeof(T) + 1, 256);
+    return r;
+  }
+};
+
+bool finite_all(const double *a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+bool finite_all(const float *a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Plan-time kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double canon(double x) { return x == 0.0 ? 0.0 : x; }
+
+// Effective amplitude: mask ? amplitude : 0 (in place).
+__global__ void k_aeff(float *aeff, const unsigned char *mask, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && mask && !mask[i]) aeff[i] = 0.f;
+}
+
+__global__ void k_fill_f(float *a, float v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+__global__ void k_fill_d(double *a, double v, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// keep[r] = any(a[r * rs + c * cs] != 0 for c < len), one block per line.
+__global__ void k_keep(const float *a, int lines, int len, size_t rs, size_t cs, int *keep) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  const int r = blockIdx.x;
+  int mine = 0;
+  for (int c = threadIdx.x; c < len; c += blockDim.x)
+    if (a[(size_t)r * rs + (size_t)c * cs] != 0.f) mine = 1;
+  if (mine) atomicOr(&any, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) keep[r] = any;
+}
+
+// Stable compaction of a 0/1 flag array: list[k] = index of the k-th set flag,
+// pos[i] = k or -1; count written to *count.  One block of 1024 threads, each
+// scanning a contiguous chunk.
+__global__ __launch_bounds__(1024) void k_compact(const int *keep, int n, int *list, int *pos,
+                                                  int *count) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = t * chunk < n ? t * chunk : n;
+  const int hi = lo + chunk < n ? lo + chunk : n;
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += keep[i] ? 1 : 0;
+  part[t] = c;
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int q = 0; q < 1024; ++q) {
+      const int v = part[q];
+      part[q] = run;
+      run += v;
+    }
+    *count = run;
+  }
+  __syncthreads();
+  int k = part[t];
+  for (int i = lo; i < hi; ++i) {
+    if (keep[i]) {
+      list[k] = i;
+      pos[i] = k++;
+    } else {
+      pos[i] = -1;
+    }
+  }
+}
+
+// Aperture statistics: number of samples with A > 0 and sum of A^2 (float64,
+// fixed order).
+__global__ __launch_bounds__(1024) void k_aperture(const float *a, size_t n, int *n_ap,
+                                                   double *sum_a2) {
+  __shared__ double sd[1024];
+  __shared__ int si[1024];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  int c = 0;
+  for (size_t i = t; i < n; i += 1024) {
+    const double v = a[i];
+    s += v * v;
+    c += v > 0.0 ? 1 : 0;
+  }
+  sd[t] = s;
+  si[t] = c;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      sd[t] += sd[t + w];
+      si[t] += si[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    *sum_a2 = sd[0];
+    *n_ap = si[0];
+  }
+}
+
+// first[i] = 1 when no focus m < i has the same canonical coordinate.
+__global__ __launch_bounds__(256) void k_first(const double *c, int n, int *first) {
+  __shared__ double tile[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const double key = i < n ? canon(c[i]) : 0.0;
+  int seen = 0;
+  const int last = (blockIdx.x + 1) * 256;  // only m < i matter
+  for (int base = 0; base < n && base < last; base += 256) {
+    const int j = base + threadIdx.x;
+    tile[threadIdx.x] = j < n ? canon(c[j]) : 0.0;
+    __syncthreads();
+    const int lim = n - base < 256 ? n - base : 256;
+    for (int q = 0; q < lim; ++q)
+      if (base + q < i && tile[q] == key) seen = 1;
+    __syncthreads();
+  }
+  if (i < n) first[i] = !seen;
+}
+
+// idx[i] = number of distinct coordinates below coordinate i (its position in
+// the sorted unique list); the first occurrence writes uniq[idx[i]].
+__global__ __launch_bounds__(256) void k_rank(const double *c, const int *first, int n, int *idx,
+                                              double *uniq) {
+  __shared__ double tile[256];
+  __shared__ int tf[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const double key = i < n ? canon(c[i]) : 0.0;
+  int cnt = 0;
+  for (int base = 0; base < n; base += 256) {
+    const int j = base + threadIdx.x;
+    tile[threadIdx.x] = j < n ? canon(c[j]) : 0.0;
+    tf[threadIdx.x] = j < n ? first[j] : 0;
+    __syncthreads();
+    const int lim = n - base < 256 ? n - base : 256;
+    for (int q = 0; q < lim; ++q) cnt += (tf[q] && tile[q] < key) ? 1 : 0;
+    __syncthreads();
+  }
+  if (i < n) {
+    idx[i] = cnt;
+    if (first[i]) uniq[cnt] = key;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_count(const int *flags, int n, int *out) {
+  __shared__ int s[1024];
+  const int t = threadIdx.x;
+  int c = 0;
+  for (int i = t; i < n; i += 1024) c += flags[i];
+  s[t] = c;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) s[t] += s[t + w];
+    __syncthreads();
+  }
+  if (t == 0) *out = s[0];
+}
+
+// Any two foci with the same (ix, iy) pair.
+__global__ __launch_bounds__(256) void k_dup(const int *ix, const int *iy, int n, int *dup) {
+  __shared__ int tx[256], ty[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int kx = i < n ? ix[i] : -1, ky = i < n ? iy[i] : -1;
+  int d = 0;
+  for (int base = 0; base < n; base += 256) {
+    const int j = base + threadIdx.x;
+    tx[threadIdx.x] = j < n ? ix[j] : -2;
+    ty[threadIdx.x] = j < n ? iy[j] : -2;
+    __syncthreads();
+    const int lim = n - base < 256 ? n - base : 256;
+    for (int q = 0; q < lim; ++q)
+      if (base + q != i && tx[q] == kx && ty[q] == ky) d = 1;
+    __syncthreads();
+  }
+  if (i < n && d) atomicOr(dup, 1);
+}
+
+// Foci sorted by (ir, ic): foci[pos] = n with pos = #{m : key_m < key_n}.
+__global__ __launch_bounds__(256) void k_csr_order(const int *ir, const int *ic, int n,
+                                                   int *foci) {
+  __shared__ long long tk[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const long long key = i < n ? ((long long)ir[i] << 32) | (long long)ic[i] : 0;
+  int pos = 0;
+  for (int base = 0; base < n; base += 256) {
+    const int j = base + threadIdx.x;
+    tk[threadIdx.x] = j < n ? (((long long)ir[j] << 32) | (long long)ic[j]) : 0;
+    __syncthreads();
+    const int lim = n - base < 256 ? n - base : 256;
+    for (int q = 0; q < lim; ++q) pos += tk[q] < key ? 1 : 0;
+    __syncthreads();
+  }
+  if (i < n) foci[pos] = i;
+}
+
+// Row pointers from the sorted order: ptr[a] = first sorted position whose
+// row is >= a, ptr[ur] = n.
+__global__ void k_row_ptr(const int *ir, const int *foci, int n, int ur, int *ptr) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > n) return;
+  const int prev = p > 0 ? ir[foci[p - 1]] : -1;
+  const int cur = p < n ? ir[foci[p]] : ur;
+  for (int a = prev + 1; a <= cur; ++a) ptr[a] = p;
+}
+
+// Target intensities normalised to unit sum (float64, fixed order).
+__global__ __launch_bounds__(1024) void k_tnorm(const double *target, int n, double *tnorm) {
+  __shared__ double s[1024];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int i = t; i < n; i += 1024) acc += target[i];
+  s[t] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) s[t] += s[t + w];
+    __syncthreads();
+  }
+  const double tot = s[0];
+  for (int i = t; i < n; i += 1024) tnorm[i] = target[i] / tot;
+}
+
+// exp(-2 pi i s c f) with the argument reduced exactly in float64:
+// t = s c f, r = t - rint(t), then sincospi(-2 r).
+__device__ __forceinline__ void kernel_phasor(double s, double c, double f, float *re,
+                                              float *im) {
+  const double t = s * c * f;
+  const double r = t - rint(t);
+  double sn, cs;
+  sincospi(-2.0 * r, &sn, &cs);
+  *re = (float)cs;
+  *im = (float)sn;
+}
+
+// Omega_r in both layouts: OmT[j][a] and OmC[a][j] = conj(OmT[j][a]).
+__global__ void k_omega_r(const double *coord, const int *kept, int Rk, const double *fu,
+                          int Ur, double s, int Rp, int Urp, float *omt_r, float *omt_i,
+                          float *omc_r, float *omc_i) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Rp * Urp) return;
+  const int j = (int)(id / Urp), a = (int)(id % Urp);
+  float re = 0.f, im = 0.f;
+  if (j < Rk && a < Ur) kernel_phasor(s, coord[kept[j]], fu[a], &re, &im);
+  omt_r[(size_t)j * Urp + a] = re;
+  omt_i[(size_t)j * Urp + a] = im;
+  omc_r[(size_t)a * Rp + j] = re;
+  omc_i[(size_t)a * Rp + j] = -im;
+}
+
+// Wc[b][i] = exp(-2 pi i s_c uc_i C_b) for b < Uc, i < Cp (0 past Ck).
+__global__ void k_omega_c(const double *coord, const int *kept, int Ck, const double *fu,
+                          int Uc, double s, int Cp, float *wr, float *wi) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Uc * Cp) return;
+  const int b = (int)(id / Cp), i = (int)(id % Cp);
+  float re = 0.f, im = 0.f;
+  if (i < Ck) kernel_phasor(s, coord[kept[i]], fu[b], &re, &im);
+  wr[id] = re;
+  wi[id] = im;
+}
+
+// Map an internal (r, c) sample to the user's (y, x); false in the padding.
+struct Orient {
+  const int *rows, *cols;
+  int axis, Rk, Ck;
+  __device__ bool user(int r, int c, int *y, int *x) const {
+    if (r >= Rk || c >= Ck) return false;
+    if (axis == 0) {
+      *y = rows[r];
+      *x = cols[c];
+    } else {
+      *y = rows[c];
+      *x = cols[r];
+    }
+    return true;
+  }
+};
+
+// Internal amplitude (zero in the padding).
+__global__ void k_encode_amp(Orient o, const float *aeff, int nx, int Rp, int Cp, float *amp) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Rp * Cp) return;
+  int y, x;
+  amp[id] = o.user((int)(id / Cp), (int)(id % Cp), &y, &x) ? aeff[(size_t)y * nx + x] : 0.f;
+}
+
+// Pupil field E = A exp(i phi) from a user-layout phase (nullable = zeros).
+__global__ void k_encode_phase(Orient o, const float *phi, const float *amp, int nx, int Rp,
+                               int Cp, float *pr, float *pi) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Rp * Cp) return;
+  int y, x;
+  float re = 0.f, im = 0.f;
+  if (o.user((int)(id / Cp), (int)(id % Cp), &y, &x)) {
+    const float a = amp[id];
+    const float ph = phi ? phi[(size_t)y * nx + x] : 0.f;
+    float s, c;
+    sincosf(ph, &s, &c);
+    re = a * c;
+    im = a * s;
+  }
+  pr[id] = re;
+  pi[id] = im;
+}
+
+// User-layout complex field (interleaved) -> internal planes (zero padding).
+__global__ void k_compact_complex(Orient o, const float *in, int nx, int Rp, int Cp, float *xr,
+                                  float *xi) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Rp * Cp) return;
+  int y, x;
+  float re = 0.f, im = 0.f;
+  if (o.user((int)(id / Cp), (int)(id % Cp), &y, &x)) {
+    re = in[2 * ((size_t)y * nx + x)];
+    im = in[2 * ((size_t)y * nx + x) + 1];
+  }
+  xr[id] = re;
+  xi[id] = im;
+}
+
+// Internal (r, c) of a user (y, x), or false when the sample was compacted away.
+__device__ __forceinline__ bool internal_of(const int *row_pos, const int *col_pos, int axis,
+                                            int y, int x, int *r, int *c) {
+  const int rp = row_pos[y], cp = col_pos[x];
+  if (rp < 0 || cp < 0) return false;
+  *r = axis == 0 ? rp : cp;
+  *c = axis == 0 ? cp : rp;
+  return true;
+}
+
+// Phase of the current pupil field in the user's layout: atan2 on aperture
+// samples, (-pi, pi]; 0 outside the aperture.
+__global__ void k_phase_out(const float *pr, const float *pi, const float *amp,
+                            const int *row_pos, const int *col_pos, int axis, int ny, int nx,
+                            int Cp, float *out) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)ny * nx) return;
+  const int y = (int)(id / nx), x = (int)(id % nx);
+  int r, c;
+  float ph = 0.f;
+  if (internal_of(row_pos, col_pos, axis, y, x, &r, &c)) {
+    const size_t o = (size_t)r * Cp + c;
+    if (amp[o] > 0.f) {
+      ph = atan2f(pi[o], pr[o]);
+      if (ph == -3.14159274101257324f) ph = 3.14159274101257324f;
+    }
+  }
+  out[id] = ph;
+}
+
+// Internal planes -> user-layout interleaved complex (zero where compacted).
+__global__ void k_expand_complex(const float *xr, const float *xi, const int *row_pos,
+                                 const int *col_pos, int axis, int ny, int nx, int Cp,
+                                 float *out) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)ny * nx) return;
+  int r, c;
+  float re = 0.f, im = 0.f;
+  if (internal_of(row_pos, col_pos, axis, (int)(id / nx), (int)(id % nx), &r, &c)) {
+    re = xr[(size_t)r * Cp + c];
+    im = xi[(size_t)r * Cp + c];
+  }
+  out[2 * id] = re;
+  out[2 * id + 1] = im;
+}
+
+// Internal real plane -> user layout (zero where compacted).
+__global__ void k_expand_real(const float *xr, const int *row_pos, const int *col_pos, int axis,
+                              int ny, int nx, int Cp, float *out) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)ny * nx) return;
+  int r, c;
+  float v = 0.f;
+  if (internal_of(row_pos, col_pos, axis, (int)(id / nx), (int)(id % nx), &r, &c))
+    v = xr[(size_t)r * Cp + c];
+  out[id] = v;
+}
+
+// Run control written by a kernel (graph-safe, no memset): clear the done
+// flag and set the termination threshold.
+__global__ void k_control(int *ctrl, double *stats, double stop) {
+  ctrl[CTRL_DONE] = 0;
+  ctrl[CTRL_NONFINITE] = 0;
+  stats[ST_STOP] = stop;
+}
+
+__global__ void k_set_state(int *ctrl, int iters) {
+  ctrl[CTRL_ITERS] = iters;
+  ctrl[CTRL_HIST] = 0;
+  ctrl[CTRL_DONE] = 0;
+}
+
+inline dim3 grid1(size_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+Orient orient_of(const gswmtp_plan *p) {
+  Orient o;
+  o.rows = p->b.rows;
+  o.cols = p->b.cols;
+  o.axis = p->d.axis;
+  o.Rk = p->d.Rk;
+  o.Ck = p->d.Ck;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+
+int validate(const gswmtp_desc *d) {
+  if (!d) return GSWMTP_E_INVAL;
+  if (d->ny < 1 || d->nx < 1 || d->ny > kMaxSide || d->nx > kMaxSide) return GSWMTP_E_INVAL;
+  if (d->n_foci < 1 || d->n_foci > kMaxFoci) return GSWMTP_E_INVAL;
+  if (!d->fx || !d->fy || !d->target) return GSWMTP_E_INVAL;
+  if (!std::isfinite(d->s_x) || !std::isfinite(d->s_y) || d->s_x == 0.0 || d->s_y == 0.0)
+    return GSWMTP_E_INVAL;
+  if (d->precision < GSWMTP_FP32 || d->precision > GSWMTP_BF16X6) return GSWMTP_E_INVAL;
+  if (d->axis < -1 || d->axis > 1) return GSWMTP_E_INVAL;
+  if (d->weighting < GSWMTP_WEIGHT_GSW || d->weighting > GSWMTP_WEIGHT_GS) return GSWMTP_E_INVAL;
+  const size_t nf = (size_t)d->n_foci, np = (size_t)d->ny * d->nx;
+  if (!finite_all(d->fx, nf) || !finite_all(d->fy, nf) || !finite_all(d->target, nf))
+    return GSWMTP_E_INVAL;
+  double tsum = 0.0;
+  for (size_t i = 0; i < nf; ++i) {
+    if (d->target[i] < 0.0) return GSWMTP_E_INVAL;
+    tsum += d->target[i];
+  }
+  if (!(tsum > 0.0) || !std::isfinite(tsum)) return GSWMTP_E_INVAL;
+  if (d->u && !finite_all(d->u, d->nx)) return GSWMTP_E_INVAL;
+  if (d->v && !finite_all(d->v, d->ny)) return GSWMTP_E_INVAL;
+  if (d->amplitude) {
+    for (size_t i = 0; i < np; ++i)
+      if (!(d->amplitude[i] >= 0.f) || !std::isfinite(d->amplitude[i])) return GSWMTP_E_INVAL;
+  }
+  if (d->phi0 && !finite_all(d->phi0, np)) return GSWMTP_E_INVAL;
+  return GSWMTP_OK;
+}
+
+int check_device(gswmtp_plan *p) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(p, GSWMTP_E_NODEV, "no HIP device");
+  HIP_TRY(p, hipGetDevice(&p->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(p, hipGetDeviceProperties(&prop, p->device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(p, GSWMTP_E_NODEV, "device is not gfx950");
+  return GSWMTP_OK;
+}
+
+void free_plan(gswmtp_plan *p) {
+  if (!p) return;
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  if (p->graph1) (void)hipGraphExecDestroy(p->graph1);
+  if (p->graph8) (void)hipGraphExecDestroy(p->graph8);
+  if (p->pool0) (void)hipFree(p->pool0);
+  if (p->pool1) (void)hipFree(p->pool1);
+  for (auto &e : p->ev_t)
+    if (e) (void)hipEventDestroy(e);
+  if (p->ev_user) (void)hipEventDestroy(p->ev_user);
+  if (p->ev_int) (void)hipEventDestroy(p->ev_int);
+  if (p->stream) (void)hipStreamDestroy(p->stream);
+  delete p;
+}
+
+// GEMM tile choice per product shape (M, N): largest tile that keeps at least
+// one workgroup per CU, else the smallest.
+GemmTile choose_tile(int M, int N) {
+  static const int cand[4][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
+  const char *env = std::getenv("GSWMTP_TILE");
+  if (env) {
+    int bm = 0, bn = 0;
+    if (std::sscanf(env, "%dx%d", &bm, &bn) == 2 && M % bm == 0 && N % bn == 0 &&
+        (bm == 64 || bm == 128) && (bn == 64 || bn == 128))
+      return GemmTile{bm, bn};
+  }
+  for (auto &c : cand) {
+    if (M % c[0] || N % c[1]) continue;
+    if ((long)(M / c[0]) * (N / c[1]) >= 256) return GemmTile{c[0], c[1]};
+  }
+  return GemmTile{64, 64};
+}
+
+// One GSW pass (Algorithm 1 from forward propagation to the projected pupil).
+hipError_t enqueue_pass(gswmtp_plan *p, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r, p->b.l_i, nullptr,
+                        nullptr, true, s)) != hipSuccess)
+    return e;
+  if ((e = launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta, true, s)) != hipSuccess) return e;
+  if ((e = launch_update(p, UPD_ITERATE, s)) != hipSuccess) return e;
+  if ((e = launch_scatter(p, p->b.theta_new, true, s)) != hipSuccess) return e;
+  return launch_cgemm(p, false, EPI_PROJECT, p->b.s_r, p->b.s_i, p->b.p_r, p->b.p_i, nullptr,
+                      nullptr, true, s);
+}
+
+// Forward field and statistics of the current phase (no weight update).
+hipError_t ensure_forward(gswmtp_plan *p) {
+  if (p->fwd_valid) return hipSuccess;
+  hipError_t e;
+  if ((e = launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r, p->b.l_i, nullptr,
+                        nullptr, false, p->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta, false, p->stream)) != hipSuccess)
+    return e;
+  if ((e = launch_update(p, UPD_STATS, p->stream)) != hipSuccess) return e;
+  p->fwd_valid = true;
+  return hipSuccess;
+}
+
+hipError_t capture(gswmtp_plan *p, int passes, hipGraphExec_t *out) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < passes && le == hipSuccess; ++i) le = enqueue_pass(p, p->stream);
+  e = hipStreamEndCapture(p->stream, &g);
+  if (le != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return le;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
+  Dims &D = p->d;
+  D.ny = d->ny;
+  D.nx = d->nx;
+  D.nf = d->n_foci;
+  p->precision = d->precision;
+  p->weighting = d->weighting;
+  if (p->precision != GSWMTP_FP32)
+    return fail(p, GSWMTP_E_UNSUPPORTED, "precision mode not built in this version");
+  const char *ng = std::getenv("GSWMTP_NO_GRAPH");
+  p->use_graph = !(ng && std::atoi(ng) != 0);
+
+  const size_t nf = D.nf, ny = D.ny, nx = D.nx, np = ny * nx;
+  HIP_TRY(p, hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+  HIP_TRY(p, hipEventCreateWithFlags(&p->ev_user, hipEventDisableTiming));
+  HIP_TRY(p, hipEventCreateWithFlags(&p->ev_int, hipEventDisableTiming));
+  HIP_TRY(p, enter(p));
+  hipStream_t s = p->stream;
+
+  // ---- pool 0: inputs, index work, per-focus state ----
+  auto carve0 = [&](Carver &c) {
+    Bufs &b = p->b;
+    b.fx = c.take<double>(nf); b.fy = c.take<double>(nf);
+    b.target = c.take<double>(nf); b.tnorm = c.take<double>(nf);
+    b.xu = c.take<double>(nf); b.yu = c.take<double>(nf);
+    b.ix = c.take<int>(nf); b.iy = c.take<int>(nf);
+    b.firstx = c.take<int>(nf); b.firsty = c.take<int>(nf);
+    b.rows = c.take<int>(ny); b.row_pos = c.take<int>(ny); b.keep_row = c.take<int>(ny);
+    b.cols = c.take<int>(nx); b.col_pos = c.take<int>(nx); b.keep_col = c.take<int>(nx);
+    b.aeff = c.take<float>(np);
+    b.ucoord = c.take<double>(nx); b.vcoord = c.take<double>(ny);
+    b.csr_foci = c.take<int>(nf); b.csr_ptr = c.take<int>(nf + 1);
+    b.scalars = c.take<int>(16); b.dscalars = c.take<double>(8); b.dup = c.take<int>(1);
+    b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
+    b.intensity = c.take<float>(nf);
+    b.w = c.take<double>(nf); b.stats = c.take<double>(ST_N);
+    b.hist = c.take<double>(3 * (size_t)kHistCap); b.ctrl = c.take<int>(CTRL_N);
+    b.iobuf = c.take<float>(2 * np);
+  };
+  {
+    Carver c(nullptr);
+    carve0(c);
+    p->pool0_bytes = c.off;
+  }
+  if (hipMalloc(&p->pool0, p->pool0_bytes) != hipSuccess)
+    return fail(p, GSWMTP_E_NOMEM, "device allocation (index pool)");
+  {
+    Carver c(p->pool0);
+    carve0(c);
+  }
+  Bufs &b = p->b;
+  HIP_TRY(p, hipMemsetAsync(p->pool0, 0, p->pool0_bytes, s));
+
+  // ---- inputs ----
+  std::vector<double> uc(nx), vc(ny);
+  for (size_t i = 0; i < nx; ++i) uc[i] = d->u ? d->u[i] : (double)i - (double)(nx - 1) / 2.0;
+  for (size_t j = 0; j < ny; ++j) vc[j] = d->v ? d->v[j] : (double)j - (double)(ny - 1) / 2.0;
+  HIP_TRY(p, hipMemcpyAsync(b.fx, d->fx, nf * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(p, hipMemcpyAsync(b.fy, d->fy, nf * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(p, hipMemcpyAsync(b.target, d->target, nf * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(p, hipMemcpyAsync(b.ucoord, uc.data(), nx * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(p, hipMemcpyAsync(b.vcoord, vc.data(), ny * 8, hipMemcpyHostToDevice, s));
+  if (d->amplitude) {
+    HIP_TRY(p, hipMemcpyAsync(b.aeff, d->amplitude, np * 4, hipMemcpyHostToDevice, s));
+  } else {
+    hipLaunchKernelGGL(k_fill_f, grid1(np), dim3(256), 0, s, b.aeff, 1.f, np);
+  }
+  if (d->mask) {
+    auto *m = reinterpret_cast<unsigned char *>(b.iobuf);
+    HIP_TRY(p, hipMemcpyAsync(m, d->mask, np, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_aeff, grid1(np), dim3(256), 0, s, b.aeff, m, np);
+  }
+
+  // ---- index work ----
+  int *sc = b.scalars;  // 0 ux, 1 uy, 2 ny_kept, 3 nx_kept, 4 n_ap
+  hipLaunchKernelGGL(k_keep, dim3((unsigned)ny), dim3(256), 0, s, b.aeff, (int)ny, (int)nx,
+                     (size_t)nx, (size_t)1, b.keep_row);
+  hipLaunchKernelGGL(k_keep, dim3((unsigned)nx), dim3(256), 0, s, b.aeff, (int)nx, (int)ny,
+                     (size_t)1, (size_t)nx, b.keep_col);
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, b.keep_row, (int)ny, b.rows,
+                     b.row_pos, sc + 2);
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, b.keep_col, (int)nx, b.cols,
+                     b.col_pos, sc + 3);
+  hipLaunchKernelGGL(k_aperture, dim3(1), dim3(1024), 0, s, b.aeff, np, sc + 4, b.dscalars);
+  const dim3 gf = grid1(nf);
+  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fx, (int)nf, b.firstx);
+  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fy, (int)nf, b.firsty);
+  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fx, b.firstx, (int)nf, b.ix, b.xu);
+  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fy, b.firsty, (int)nf, b.iy, b.yu);
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firstx, (int)nf, sc + 0);
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firsty, (int)nf, sc + 1);
+  hipLaunchKernelGGL(k_dup, gf, dim3(256), 0, s, b.ix, b.iy, (int)nf, b.dup);
+  hipLaunchKernelGGL(k_tnorm, dim3(1), dim3(1024), 0, s, b.target, (int)nf, b.tnorm);
+  HIP_TRY(p, hipGetLastError());
+
+  int hs[8] = {0};
+  int hdup = 0;
+  double hsum = 0.0;
+  HIP_TRY(p, hipMemcpyAsync(hs, sc, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(&hdup, b.dup, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipMemcpyAsync(&hsum, b.dscalars, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  D.ux = hs[0];
+  D.uy = hs[1];
+  D.ny_kept = hs[2];
+  D.nx_kept = hs[3];
+  D.n_ap = hs[4];
+  D.sum_a2 = hsum;
+  if (hdup) return fail(p, GSWMTP_E_DUPFOCUS, "two foci share the same (x, y)");
+  if (D.n_ap == 0 || D.ny_kept == 0 || D.nx_kept == 0 || !(D.sum_a2 > 0.0))
+    return fail(p, GSWMTP_E_EMPTYAPERTURE, "amplitude is zero everywhere");
+
+  // ---- axis and sizes ----
+  D.axis = d->axis >= 0 ? d->axis : (D.ux < D.uy ? 1 : 0);
+  if (D.axis == 0) {
+    D.Rk = D.ny_kept; D.Ck = D.nx_kept; D.Ur = D.uy; D.Uc = D.ux;
+  } else {
+    D.Rk = D.nx_kept; D.Ck = D.ny_kept; D.Ur = D.ux; D.Uc = D.uy;
+  }
+  D.Rp = (int)round_up(D.Rk, kPadRows);
+  D.Cp = (int)round_up(D.Ck, kPadCols);
+  D.Urp = (int)round_up(D.Ur, kPadRows);
+  p->tile_fwd = choose_tile(D.Urp, D.Cp);
+  p->tile_bwd = choose_tile(D.Rp, D.Cp);
+
+  // ---- pool 1: kernel matrices, pupil and product buffers ----
+  const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc;
+  auto carve1 = [&](Carver &c) {
+    b.omt_r = c.take<float>(Rp * Urp); b.omt_i = c.take<float>(Rp * Urp);
+    b.omc_r = c.take<float>(Rp * Urp); b.omc_i = c.take<float>(Rp * Urp);
+    b.wc_r = c.take<float>(Uc * Cp); b.wc_i = c.take<float>(Uc * Cp);
+    b.amp = c.take<float>(Rp * Cp);
+    b.p_r = c.take<float>(Rp * Cp); b.p_i = c.take<float>(Rp * Cp);
+    b.l_r = c.take<float>(Urp * Cp); b.l_i = c.take<float>(Urp * Cp);
+    b.s_r = c.take<float>(Urp * Cp); b.s_i = c.take<float>(Urp * Cp);
+    b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
+  };
+  {
+    Carver c(nullptr);
+    carve1(c);
+    p->pool1_bytes = c.off;
+  }
+  if (hipMalloc(&p->pool1, p->pool1_bytes) != hipSuccess)
+    return fail(p, GSWMTP_E_NOMEM, "device allocation (product pool)");
+  {
+    Carver c(p->pool1);
+    carve1(c);
+  }
+  HIP_TRY(p, hipMemsetAsync(p->pool1, 0, p->pool1_bytes, s));
+
+  const int *ir = D.axis == 0 ? b.iy : b.ix;
+  const int *ic = D.axis == 0 ? b.ix : b.iy;
+  hipLaunchKernelGGL(k_csr_order, gf, dim3(256), 0, s, ir, ic, (int)nf, b.csr_foci);
+  hipLaunchKernelGGL(k_row_ptr, grid1(nf + 1), dim3(256), 0, s, ir, b.csr_foci, (int)nf, D.Ur,
+                     b.csr_ptr);
+  const double *rcoord = D.axis == 0 ? b.vcoord : b.ucoord;
+  const double *ccoord = D.axis == 0 ? b.ucoord : b.vcoord;
+  const int *rkept = D.axis == 0 ? b.rows : b.cols;
+  const int *ckept = D.axis == 0 ? b.cols : b.rows;
+  const double *rfu = D.axis == 0 ? b.yu : b.xu;
+  const double *cfu = D.axis == 0 ? b.xu : b.yu;
+  const double s_r = D.axis == 0 ? d->s_y : d->s_x;
+  const double s_c = D.axis == 0 ? d->s_x : d->s_y;
+  hipLaunchKernelGGL(k_omega_r, grid1(Rp * Urp), dim3(256), 0, s, rcoord, rkept, D.Rk, rfu,
+                     D.Ur, s_r, D.Rp, D.Urp, b.omt_r, b.omt_i, b.omc_r, b.omc_i);
+  hipLaunchKernelGGL(k_omega_c, grid1(Uc * Cp), dim3(256), 0, s, ccoord, ckept, D.Ck, cfu,
+                     D.Uc, s_c, D.Cp, b.wc_r, b.wc_i);
+  const Orient o = orient_of(p);
+  hipLaunchKernelGGL(k_encode_amp, grid1(Rp * Cp), dim3(256), 0, s, o, b.aeff, (int)nx, D.Rp,
+                     D.Cp, b.amp);
+  const float *phi_dev = nullptr;
+  if (d->phi0) {
+    HIP_TRY(p, hipMemcpyAsync(b.iobuf, d->phi0, np * 4, hipMemcpyHostToDevice, s));
+    phi_dev = b.iobuf;
+  }
+  hipLaunchKernelGGL(k_encode_phase, grid1(Rp * Cp), dim3(256), 0, s, o, phi_dev, b.amp,
+                     (int)nx, D.Rp, D.Cp, b.p_r, b.p_i);
+  hipLaunchKernelGGL(k_fill_d, grid1(nf), dim3(256), 0, s, b.w, 1.0, nf);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, hipStreamSynchronize(s));
+  HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+thread_local std::string g_last_create_error;
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int gswmtp_version(void) { return GSWMTP_VERSION; }
+
+const char *gswmtp_status_string(int status) {
+  switch (status) {
+    case GSWMTP_OK: return "GSWMTP_OK";
+    case GSWMTP_E_INVAL: return "GSWMTP_E_INVAL: invalid argument";
+    case GSWMTP_E_DUPFOCUS: return "GSWMTP_E_DUPFOCUS: duplicate focus";
+    case GSWMTP_E_EMPTYAPERTURE: return "GSWMTP_E_EMPTYAPERTURE: empty aperture";
+    case GSWMTP_E_NOMEM: return "GSWMTP_E_NOMEM: out of memory";
+    case GSWMTP_E_HIP: return "GSWMTP_E_HIP: HIP runtime error";
+    case GSWMTP_E_NONFINITE: return "GSWMTP_E_NONFINITE: non-finite focus intensities";
+    case GSWMTP_E_NODEV: return "GSWMTP_E_NODEV: no gfx950 device";
+    case GSWMTP_E_UNSUPPORTED: return "GSWMTP_E_UNSUPPORTED: not supported";
+  }
+  return "unknown status";
+}
+
+const char *gswmtp_last_error(const gswmtp_plan *p) {
+  if (!p) return g_last_create_error.c_str();
+  return p->err.c_str();
+}
+
+int gswmtp_desc_init(gswmtp_desc *d) {
+  if (!d) return GSWMTP_E_INVAL;
+  std::memset(d, 0, sizeof *d);
+  d->precision = GSWMTP_FP32;
+  d->axis = -1;
+  d->weighting = GSWMTP_WEIGHT_GSW;
+  return GSWMTP_OK;
+}
+
+int gswmtp_plan_create(gswmtp_plan **out, const gswmtp_desc *d, void *stream) {
+  if (!out) return GSWMTP_E_INVAL;
+  *out = nullptr;
+  g_last_create_error.clear();
+  const int v = validate(d);
+  if (v != GSWMTP_OK) {
+    g_last_create_error = "invalid plan descriptor";
+    return v;
+  }
+  gswmtp_plan *p = new (std::nothrow) gswmtp_plan();
+  if (!p) return GSWMTP_E_NOMEM;
+  p->user_stream = static_cast<hipStream_t>(stream);
+  int rc = check_device(p);
+  if (rc == GSWMTP_OK) {
+    try {
+      rc = plan_build(p, d);
+    } catch (const std::bad_alloc &) {
+      rc = fail(p, GSWMTP_E_NOMEM, "host allocation");
+    }
+  }
+  if (rc != GSWMTP_OK) {
+    g_last_create_error = p->err;
+    free_plan(p);
+    return rc;
+  }
+  *out = p;
+  return GSWMTP_OK;
+}
+
+int gswmtp_plan_destroy(gswmtp_plan *p) {
+  if (!p) return GSWMTP_OK;
+  DeviceGuard g(p->device);
+  free_plan(p);
+  return GSWMTP_OK;
+}
+
+int gswmtp_set_stream(gswmtp_plan *p, void *stream) {
+  if (!p) return GSWMTP_E_INVAL;
+  p->user_stream = static_cast<hipStream_t>(stream);
+  return GSWMTP_OK;
+}
+
+int gswmtp_sync(gswmtp_plan *p) {
+  if (!p) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+int gswmtp_iterate(gswmtp_plan *p, int n_iter, double stop_accuracy) {
+  if (!p || n_iter < 0 || !std::isfinite(stop_accuracy)) return GSWMTP_E_INVAL;
+  if (n_iter == 0) return GSWMTP_OK;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, p->stream, p->b.ctrl, p->b.stats,
+                     stop_accuracy);
+  HIP_TRY(p, hipGetLastError());
+  if (p->use_graph) {
+    if (!p->graph1) HIP_TRY(p, capture(p, 1, &p->graph1));
+    if (n_iter >= 8 && !p->graph8) HIP_TRY(p, capture(p, 8, &p->graph8));
+    int left = n_iter;
+    for (; left >= 8; left -= 8) HIP_TRY(p, hipGraphLaunch(p->graph8, p->stream));
+    for (; left > 0; --left) HIP_TRY(p, hipGraphLaunch(p->graph1, p->stream));
+  } else {
+    for (int i = 0; i < n_iter; ++i) HIP_TRY(p, enqueue_pass(p, p->stream));
+  }
+  p->fwd_valid = false;
+  HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+int gswmtp_iterations_done(gswmtp_plan *p, int *n) {
+  if (!p || !n) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  int c[CTRL_N];
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, hipMemcpyAsync(c, p->b.ctrl, sizeof c, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  *n = c[CTRL_ITERS];
+  if (c[CTRL_NONFINITE]) return fail(p, GSWMTP_E_NONFINITE, "focus intensities became non-finite");
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_phase_device(gswmtp_plan *p, float *dev_out) {
+  if (!p || !dev_out) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  const Dims &D = p->d;
+  hipLaunchKernelGGL(k_phase_out, grid1((size_t)D.ny * D.nx), dim3(256), 0, p->stream, p->b.p_r,
+                     p->b.p_i, p->b.amp, p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp,
+                     dev_out);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_phase(gswmtp_plan *p, float *out) {
+  if (!p || !out) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  const size_t np = (size_t)p->d.ny * p->d.nx;
+  HIP_TRY(p, enter(p));
+  hipLaunchKernelGGL(k_phase_out, grid1(np), dim3(256), 0, p->stream, p->b.p_r, p->b.p_i,
+                     p->b.amp, p->b.row_pos, p->b.col_pos, p->d.axis, p->d.ny, p->d.nx, p->d.Cp,
+                     p->b.iobuf);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, hipMemcpyAsync(out, p->b.iobuf, np * 4, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+static int set_phase_impl(gswmtp_plan *p, const float *dev_phi) {
+  const Dims &D = p->d;
+  hipLaunchKernelGGL(k_encode_phase, grid1((size_t)D.Rp * D.Cp), dim3(256), 0, p->stream,
+                     orient_of(p), dev_phi, p->b.amp, D.nx, D.Rp, D.Cp, p->b.p_r, p->b.p_i);
+  HIP_TRY(p, hipGetLastError());
+  p->fwd_valid = false;
+  return GSWMTP_OK;
+}
+
+int gswmtp_set_phase(gswmtp_plan *p, const float *phi) {
+  if (!p || !phi) return GSWMTP_E_INVAL;
+  const size_t np = (size_t)p->d.ny * p->d.nx;
+  if (!finite_all(phi, np)) return fail(p, GSWMTP_E_INVAL, "non-finite phase");
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, hipMemcpyAsync(p->b.iobuf, phi, np * 4, hipMemcpyHostToDevice, p->stream));
+  int rc = set_phase_impl(p, p->b.iobuf);
+  if (rc) return rc;
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+int gswmtp_set_phase_device(gswmtp_plan *p, const float *dev_phi) {
+  if (!p || !dev_phi) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  int rc = set_phase_impl(p, dev_phi);
+  if (rc) return rc;
+  HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_foci_field_device(gswmtp_plan *p, float *dev_field, float *dev_intensity) {
+  if (!p || !dev_field) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, ensure_forward(p));
+  const size_t nf = p->d.nf;
+  HIP_TRY(p, hipMemcpyAsync(dev_field, p->b.theta, 8 * nf, hipMemcpyDeviceToDevice, p->stream));
+  if (dev_intensity)
+    HIP_TRY(p, hipMemcpyAsync(dev_intensity, p->b.intensity, 4 * nf, hipMemcpyDeviceToDevice,
+                              p->stream));
+  HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_foci_field(gswmtp_plan *p, float *out) {
+  if (!p || !out) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, ensure_forward(p));
+  HIP_TRY(p, hipMemcpyAsync(out, p->b.theta, 8 * (size_t)p->d.nf, hipMemcpyDeviceToHost,
+                            p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_stats(gswmtp_plan *p, double *xi, double *eta, double *uniformity) {
+  if (!p) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, ensure_forward(p));
+  double st[ST_N];
+  HIP_TRY(p, hipMemcpyAsync(st, p->b.stats, sizeof st, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  if (xi) *xi = st[ST_XI];
+  if (eta) *eta = st[ST_ETA];
+  if (uniformity) *uniformity = st[ST_U];
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_weights(gswmtp_plan *p, double *out) {
+  if (!p || !out) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, hipMemcpyAsync(out, p->b.w, 8 * (size_t)p->d.nf, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+int gswmtp_set_weights(gswmtp_plan *p, const double *w) {
+  if (!p || !w) return GSWMTP_E_INVAL;
+  if (!finite_all(w, (size_t)p->d.nf)) return fail(p, GSWMTP_E_INVAL, "non-finite weights");
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, hipMemcpyAsync(p->b.w, w, 8 * (size_t)p->d.nf, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_history(gswmtp_plan *p, double *buf, int cap, int *n) {
+  if (!p || !n || cap < 0 || (cap > 0 && !buf)) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  int c[CTRL_N];
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, hipMemcpyAsync(c, p->b.ctrl, sizeof c, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  const int total = c[CTRL_HIST];
+  const int stored = total < kHistCap ? total : kHistCap;
+  const int take = stored < cap ? stored : cap;
+  std::vector<double> h(3 * (size_t)kHistCap);
+  if (take > 0) {
+    HIP_TRY(p, hipMemcpy(h.data(), p->b.hist, h.size() * 8, hipMemcpyDeviceToHost));
+    for (int k = 0; k < take; ++k) {
+      const int idx = (total - take + k) % kHistCap;
+      for (int q = 0; q < 3; ++q) buf[3 * k + q] = h[3 * (size_t)idx + q];
+    }
+  }
+  *n = take;
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_state(gswmtp_plan *p, float *phi, double *w, int *iters) {
+  if (!p) return GSWMTP_E_INVAL;
+  int rc;
+  if (phi && (rc = gswmtp_get_phase(p, phi)) != GSWMTP_OK) return rc;
+  if (w && (rc = gswmtp_get_weights(p, w)) != GSWMTP_OK) return rc;
+  if (iters && (rc = gswmtp_iterations_done(p, iters)) != GSWMTP_OK) return rc;
+  return GSWMTP_OK;
+}
+
+int gswmtp_set_state(gswmtp_plan *p, const float *phi, const double *w, int iters) {
+  if (!p || iters < 0) return GSWMTP_E_INVAL;
+  int rc;
+  if (phi && (rc = gswmtp_set_phase(p, phi)) != GSWMTP_OK) return rc;
+  if (w && (rc = gswmtp_set_weights(p, w)) != GSWMTP_OK) return rc;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, p->stream, p->b.ctrl, iters);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+int gswmtp_get_index(gswmtp_plan *p, gswmtp_index_info *info, int32_t *ix, int32_t *iy,
+                     double *xu, double *yu, int32_t *rows, int32_t *cols) {
+  if (!p || !info) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  const Dims &D = p->d;
+  info->n_foci = D.nf;
+  info->ux = D.ux;
+  info->uy = D.uy;
+  info->ny_kept = D.ny_kept;
+  info->nx_kept = D.nx_kept;
+  info->axis = D.axis;
+  info->n_aperture = D.n_ap;
+  info->sum_a2 = D.sum_a2;
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));
+  if (ix) HIP_TRY(p, hipMemcpy(ix, p->b.ix, 4 * (size_t)D.nf, hipMemcpyDeviceToHost));
+  if (iy) HIP_TRY(p, hipMemcpy(iy, p->b.iy, 4 * (size_t)D.nf, hipMemcpyDeviceToHost));
+  if (xu) HIP_TRY(p, hipMemcpy(xu, p->b.xu, 8 * (size_t)D.ux, hipMemcpyDeviceToHost));
+  if (yu) HIP_TRY(p, hipMemcpy(yu, p->b.yu, 8 * (size_t)D.uy, hipMemcpyDeviceToHost));
+  if (rows) HIP_TRY(p, hipMemcpy(rows, p->b.rows, 4 * (size_t)D.ny_kept, hipMemcpyDeviceToHost));
+  if (cols) HIP_TRY(p, hipMemcpy(cols, p->b.cols, 4 * (size_t)D.nx_kept, hipMemcpyDeviceToHost));
+  return GSWMTP_OK;
+}
+
+int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta) {
+  if (!p || !E || !theta) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  const Dims &D = p->d;
+  const size_t np = (size_t)D.ny * D.nx;
+  HIP_TRY(p, enter(p));
+  hipStream_t s = p->stream;
+  HIP_TRY(p, hipMemcpyAsync(p->b.iobuf, E, 8 * np, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_compact_complex, grid1((size_t)D.Rp * D.Cp), dim3(256), 0, s,
+                     orient_of(p), p->b.iobuf, D.nx, D.Rp, D.Cp, p->b.x_r, p->b.x_i);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, launch_cgemm(p, true, EPI_STORE, p->b.x_r, p->b.x_i, p->b.l_r, p->b.l_i, nullptr,
+                          nullptr, false, s));
+  HIP_TRY(p, launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta_new, false, s));
+  HIP_TRY(p, hipMemcpyAsync(theta, p->b.theta_new, 8 * (size_t)D.nf, hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  return GSWMTP_OK;
+}
+
+int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E) {
+  if (!p || !theta || !E) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  const Dims &D = p->d;
+  const size_t np = (size_t)D.ny * D.nx;
+  HIP_TRY(p, enter(p));
+  hipStream_t s = p->stream;
+  HIP_TRY(p, hipMemcpyAsync(p->b.theta_new, theta, 8 * (size_t)D.nf, hipMemcpyHostToDevice, s));
+  HIP_TRY(p, launch_scatter(p, p->b.theta_new, false, s));
+  HIP_TRY(p, launch_cgemm(p, false, EPI_STORE, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i, nullptr,
+                          nullptr, false, s));
+  hipLaunchKernelGGL(k_expand_complex, grid1(np), dim3(256), 0, s, p->b.x_r, p->b.x_i,
+                     p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, p->b.iobuf);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, hipMemcpyAsync(E, p->b.iobuf, 8 * np, hipMemcpyDeviceToHost, s));
+  HIP_TRY(p, hipStreamSynchronize(s));
+  return GSWMTP_OK;
+}
+
+int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad) {
+  if (!p || !dev_g || !dev_grad) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  const Dims &D = p->d;
+  HIP_TRY(p, enter(p));
+  hipStream_t s = p->stream;
+  HIP_TRY(p, ensure_forward(p));
+  HIP_TRY(p, launch_grad_field(p, dev_g, s));
+  HIP_TRY(p, launch_scatter(p, p->b.theta_new, false, s));
+  HIP_TRY(p, launch_cgemm(p, false, EPI_GRAD, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i, p->b.p_r,
+                          p->b.p_i, false, s));
+  hipLaunchKernelGGL(k_expand_real, grid1((size_t)D.ny * D.nx), dim3(256), 0, s, p->b.x_r,
+                     p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, dev_grad);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out) {
+  if (!p || n_iter < 1 || !ms_out) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  const int ne = (GSWMTP_N_STAGES + 1) * n_iter;
+  std::vector<hipEvent_t> ev(ne, nullptr);
+  for (auto &e : ev) HIP_TRY(p, hipEventCreate(&e));
+  hipStream_t s = p->stream;
+  int rc = GSWMTP_OK;
+  do {
+    if (enter(p) != hipSuccess) { rc = fail(p, GSWMTP_E_HIP, "enter"); break; }
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, p->b.ctrl, p->b.stats, 0.0);
+    for (int it = 0; it < n_iter && rc == GSWMTP_OK; ++it) {
+      hipEvent_t *e = &ev[(size_t)it * (GSWMTP_N_STAGES + 1)];
+      hipError_t er = hipEventRecord(e[0], s);
+      if (er == hipSuccess) er = launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r,
+                                              p->b.l_i, nullptr, nullptr, true, s);
+      if (er == hipSuccess) er = hipEventRecord(e[1], s);
+      if (er == hipSuccess) er = launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta, true, s);
+      if (er == hipSuccess) er = hipEventRecord(e[2], s);
+      if (er == hipSuccess) er = launch_update(p, UPD_ITERATE, s);
+      if (er == hipSuccess) er = hipEventRecord(e[3], s);
+      if (er == hipSuccess) er = launch_scatter(p, p->b.theta_new, true, s);
+      if (er == hipSuccess) er = hipEventRecord(e[4], s);
+      if (er == hipSuccess) er = launch_cgemm(p, false, EPI_PROJECT, p->b.s_r, p->b.s_i, p->b.p_r,
+                                              p->b.p_i, nullptr, nullptr, true, s);
+      if (er == hipSuccess) er = hipEventRecord(e[5], s);
+      if (er != hipSuccess) rc = fail(p, GSWMTP_E_HIP, "time_stages launch", er);
+    }
+    if (rc != GSWMTP_OK) break;
+    if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(p, GSWMTP_E_HIP, "sync"); break; }
+    for (int k = 0; k < GSWMTP_N_STAGES; ++k) ms_out[k] = 0.0;
+    for (int it = 0; it < n_iter; ++it) {
+      hipEvent_t *e = &ev[(size_t)it * (GSWMTP_N_STAGES + 1)];
+      for (int k = 0; k < GSWMTP_N_STAGES; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e[k], e[k + 1]);
+        ms_out[k] += ms / n_iter;
+      }
+    }
+    p->fwd_valid = false;
+    if (leave(p) != hipSuccess) rc = fail(p, GSWMTP_E_HIP, "leave");
+  } while (false);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return rc;
+}
+
+const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage) {
+  switch (stage) {
+    case 0: return cgemm_kernel_name(p, true, EPI_STORE);
+    case 1: return "focus_gather";
+    case 2: return "focus_update";
+    case 3: return "focus_scatter";
+    case 4: return cgemm_kernel_name(p, false, EPI_PROJECT);
+  }
+  return "";
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+"""The C-ABI library loads and exports every symbol its header declares, and
+host-side validation rejects bad descriptors before any GPU work (no compute
+calls here: these run without a GPU)."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gswmtp.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gswmtp_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2206_12661_amd as g
+    return g.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["gswmtp_plan_create", "gswmtp_iterate", "gswmtp_get_phase",
+                 "gswmtp_get_foci_field", "gswmtp_plan_destroy"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    so = os.path.join(ROOT, "paper_2206_12661_amd", "libgswmtp.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (gswmtp_\w+)", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    for n in _declared():
+        getattr(lib, n)
+
+
+def test_exports_no_cpp_or_oracle_symbols():
+    so = os.path.join(ROOT, "paper_2206_12661_amd", "libgswmtp.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True,
+                         check=True).stdout
+    assert "oracle_" not in out
+
+
+def test_status_strings_and_version(lib):
+    import paper_2206_12661_amd as g
+    assert lib.gswmtp_version() == 100
+    for code in range(-8, 1):
+        s = g.status_string(code)
+        assert s.startswith("GSWMTP_")
+    assert "unknown" in g.status_string(-99)
+
+
+def _desc(g, **over):
+    d = g.gswmtp_desc()
+    g.load_library().gswmtp_desc_init(ctypes.byref(d))
+    keep = []
+
+    def put(name, arr):
+        a = np.ascontiguousarray(arr)
+        keep.append(a)
+        setattr(d, name, a.ctypes.data)
+
+    d.ny, d.nx, d.n_foci = 8, 8, 3
+    d.s_x = d.s_y = 1 / 8
+    put("fx", np.array([0.0, 1.0, 2.0]))
+    put("fy", np.array([0.5, 0.5, 0.5]))
+    put("target", np.array([1.0, 1.0, 1.0]))
+    for k, v in over.items():
+        if isinstance(v, np.ndarray):
+            put(k, v)
+        else:
+            setattr(d, k, v)
+    return d, keep
+
+
+@pytest.mark.parametrize("case", [
+    "ny0", "nf0", "nfhuge", "sx0", "sxnan", "fxnan", "targetneg", "targetzero", "ampneg",
+    "ampnan", "phinan", "unan", "precision", "axis", "weighting"])
+def test_validation_rejects_bad_descriptors(case):
+    import paper_2206_12661_amd as g
+    lib = g.load_library()
+    over = {
+        "ny0": {"ny": 0}, "nf0": {"n_foci": 0}, "nfhuge": {"n_foci": 1 << 20},
+        "sx0": {"s_x": 0.0}, "sxnan": {"s_x": math.nan},
+        "fxnan": {"fx": np.array([0.0, math.nan, 2.0])},
+        "targetneg": {"target": np.array([1.0, -1.0, 1.0])},
+        "targetzero": {"target": np.zeros(3)},
+        "ampneg": {"amplitude": -np.ones(64, np.float32)},
+        "ampnan": {"amplitude": np.full(64, np.nan, np.float32)},
+        "phinan": {"phi0": np.full(64, np.inf, np.float32)},
+        "unan": {"u": np.full(8, np.nan)},
+        "precision": {"precision": 9}, "axis": {"axis": 2}, "weighting": {"weighting": 5},
+    }[case]
+    d, keep = _desc(g, **over)
+    h = ctypes.c_void_p()
+    rc = lib.gswmtp_plan_create(ctypes.byref(h), ctypes.byref(d), None)
+    assert rc == -1
+    assert not h.value
+    assert lib.gswmtp_last_error(None).decode() != ""
+
+
+def test_null_arguments(lib):
+    assert lib.gswmtp_plan_create(None, None, None) == -1
+    h = ctypes.c_void_p()
+    assert lib.gswmtp_plan_create(ctypes.byref(h), None, None) == -1
+    assert lib.gswmtp_plan_destroy(None) == 0
+    assert lib.gswmtp_desc_init(None) == -1
+    assert lib.gswmtp_iterate(None, 1, 0.0) == -1
+    assert lib.gswmtp_batch_destroy(None) == 0
+
+
+def test_product_path_does_not_import_oracle():
+    src = os.path.join(ROOT, "paper_2206_12661_amd")
+    for dirpath, _, files in os.walk(src):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "gsw_oracle" not in text and "liboracle" not in text, f
