@@ -13,12 +13,20 @@
 // 64 lanes, one float of A and one of B per lane, a 32x32 float32 block
 // accumulated over K = 2 per instruction.  A workgroup of four waves owns a
 // BM x BN complex tile; each wave a (BM/2) x (BN/2) quadrant.  K advances in
-// stages of 16 complex values staged through LDS with double buffering and a
-// register prefetch of the next stage.
+// stages of 16 complex values staged through LDS with double buffering, a
+// register prefetch of the next stage from global memory and a one-step-ahead
+// prefetch of the MFMA operands from LDS.
+//
+// Scheduling (256 CUs): full tiles are processed one workgroup each; when
+// the tile count leaves a short last round, those tail tiles are split along
+// K into `split` chunks so every CU gets about the same work.  Chunk partial
+// sums go to a workspace; the last chunk of a tile to finish (ticket from a
+// device-scope atomic counter, no waiting) adds the chunks in fixed order and
+// runs the epilogue, so results do not depend on arrival order.
 //
 // Epilogues: store C; project onto the amplitude constraint
 // (E = A C / |C|, phasor 1 where C = 0: the phase-only projection of
-// Algorithm 1, fused so E' never reaches HBM); or the phase-gradient
+// Algorithm 1, fused so E' never reaches HBM); or the phase gradient
 // 2 Im(conj(E) C).
 #include "gswmtp_internal.h"
 
@@ -39,9 +47,13 @@ struct CgemmArgs {
   const float *__restrict__ er;    // EPI_GRAD: pupil field planes [M][ldc]
   const float *__restrict__ ei;
   const int *done;                 // nullable: skip when *done != 0
+  float *part;                     // split-K partial tiles
+  int *cnt;                        // split-K tickets, one per tail tile (zero between launches)
   int lda, ldb, ldc;
   int M, N, K;
-  int tiles_m, tiles;
+  int tiles_m;
+  int t_dp;                        // tiles processed whole
+  int split;                       // K chunks per tail tile
 };
 
 constexpr int kBK = 16;            // complex k per LDS stage
@@ -56,119 +68,10 @@ __device__ __forceinline__ int xcd_tile(int bid, int tiles) {
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
-template <int BM, int BN, int EPI>
-__global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
-  if (a.done && *a.done) return;
-  constexpr int WTM = BM / 2, WTN = BN / 2;    // wave tile (complex)
-  constexpr int MB = WTM / 32, NB = WTN / 32;  // 32x32 blocks per wave
-  constexpr int SA = BM + 32, SB = BN + 32;    // padded LDS row pitch (floats)
-  constexpr int A4 = kBK * BM / 4;             // float4 per A plane per stage
-  constexpr int B4 = kBK * BN / 4;
-  constexpr int NA = 2 * A4 / kThreads, NBL = 2 * B4 / kThreads;
-  static_assert(2 * A4 % kThreads == 0 && 2 * B4 % kThreads == 0, "tile/thread mismatch");
-
-  __shared__ float sA[2][2][kBK * SA];
-  __shared__ float sB[2][2][kBK * SB];
-
-  const int tid = threadIdx.x;
-  const int t = xcd_tile(blockIdx.x, a.tiles);
-  const int m0 = (t % a.tiles_m) * BM;
-  const int n0 = (t / a.tiles_m) * BN;
-
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int l32 = lane & 31, h = lane >> 5;
-
-  v16f accR[MB][NB], accI[MB][NB];
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      accR[i][j] = v16f{0};
-      accI[i][j] = v16f{0};
-    }
-
-  // Staging map: float4 s of this thread covers plane s / (NA / 2) of the
-  // tile, row k = (idx % A4) / (BM / 4), columns 4 m4 .. 4 m4 + 3.
-  v4f ra[NA], rb[NBL];
-  const float *ga[NA];
-  const float *gb[NBL];
-  int la[NA], lb[NBL];
-#pragma unroll
-  for (int s = 0; s < NA; ++s) {
-    const int idx = tid + kThreads * s;
-    const int plane = idx / A4, rem = idx % A4;
-    const int k = rem / (BM / 4), m4 = rem % (BM / 4);
-    ga[s] = (plane ? a.ati : a.atr) + (size_t)k * a.lda + m0 + 4 * m4;
-    la[s] = plane * (kBK * SA) + k * SA + 4 * m4;
-  }
-#pragma unroll
-  for (int s = 0; s < NBL; ++s) {
-    const int idx = tid + kThreads * s;
-    const int plane = idx / B4, rem = idx % B4;
-    const int k = rem / (BN / 4), n4 = rem % (BN / 4);
-    gb[s] = (plane ? a.bi : a.br) + (size_t)k * a.ldb + n0 + 4 * n4;
-    lb[s] = plane * (kBK * SB) + k * SB + 4 * n4;
-  }
-  const size_t stepA = (size_t)kBK * a.lda, stepB = (size_t)kBK * a.ldb;
-
-  const int KT = a.K / kBK;
-#pragma unroll
-  for (int s = 0; s < NA; ++s) ra[s] = *reinterpret_cast<const v4f *>(ga[s]);
-#pragma unroll
-  for (int s = 0; s < NBL; ++s) rb[s] = *reinterpret_cast<const v4f *>(gb[s]);
-#pragma unroll
-  for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&sA[0][0][la[s]]) = ra[s];
-#pragma unroll
-  for (int s = 0; s < NBL; ++s) *reinterpret_cast<v4f *>(&sB[0][0][lb[s]]) = rb[s];
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < KT) {
-#pragma unroll
-      for (int s = 0; s < NA; ++s)
-        ra[s] = *reinterpret_cast<const v4f *>(ga[s] + (size_t)(kt + 1) * stepA);
-#pragma unroll
-      for (int s = 0; s < NBL; ++s)
-        rb[s] = *reinterpret_cast<const v4f *>(gb[s] + (size_t)(kt + 1) * stepB);
-    }
-    const float *pa = &sA[buf][0][0];
-    const float *pb = &sB[buf][0][0];
-#pragma unroll
-    for (int p = 0; p < kBK / 2; ++p) {
-      const int k = 2 * p + h;   // lanes 0-31 take k = 2p, lanes 32-63 k = 2p + 1
-      float ar[MB], ai[MB], br[NB], bi[NB];
-#pragma unroll
-      for (int i = 0; i < MB; ++i) {
-        ar[i] = pa[k * SA + wm * WTM + i * 32 + l32];
-        ai[i] = pa[kBK * SA + k * SA + wm * WTM + i * 32 + l32];
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        br[j] = pb[k * SB + wn * WTN + j * 32 + l32];
-        bi[j] = pb[kBK * SB + k * SB + wn * WTN + j * 32 + l32];
-      }
-#pragma unroll
-      for (int i = 0; i < MB; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], accR[i][j], 0, 0, 0);
-          accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[i], bi[j], accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], bi[j], accI[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], br[j], accI[i][j], 0, 0, 0);
-        }
-    }
-    if (kt + 1 < KT) {
-      float *qa = &sA[buf ^ 1][0][0];
-      float *qb = &sB[buf ^ 1][0][0];
-#pragma unroll
-      for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&qa[la[s]]) = ra[s];
-#pragma unroll
-      for (int s = 0; s < NBL; ++s) *reinterpret_cast<v4f *>(&qb[lb[s]]) = rb[s];
-    }
-    __syncthreads();
-  }
-
+template <int MB, int NB, int EPI>
+__device__ __forceinline__ void epilogue(const CgemmArgs &a, v16f (&accR)[MB][NB],
+                                         v16f (&accI)[MB][NB], int mw, int nw, int l32,
+                                         int h) {
   // Accumulator layout of the 32x32 f32 block: lane (l32, h), item r holds
   // row 8 (r / 4) + 4 h + r % 4, column l32.
 #pragma unroll
@@ -177,10 +80,10 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
     for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int m = m0 + wm * WTM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const int n = n0 + wn * WTN + j * 32 + l32;
+        const int m = mw + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int n = nw + j * 32 + l32;
         const size_t o = (size_t)m * a.ldc + n;
-        float cr = accR[i][j][r], ci = accI[i][j][r];
+        const float cr = accR[i][j][r], ci = accI[i][j][r];
         if (EPI == EPI_STORE) {
           a.cr[o] = cr;
           a.ci[o] = ci;
@@ -206,28 +109,247 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
 }
 
 template <int BM, int BN, int EPI>
-hipError_t launch_t(const CgemmArgs &args, hipStream_t s) {
-  hipLaunchKernelGGL((cgemm_f32_mfma<BM, BN, EPI>), dim3(args.tiles), dim3(kThreads), 0, s,
-                     args);
+__global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
+  if (a.done && *a.done) return;
+  constexpr int WTM = BM / 2, WTN = BN / 2;    // wave tile (complex)
+  constexpr int MB = WTM / 32, NB = WTN / 32;  // 32x32 blocks per wave
+  constexpr int SA = BM + 32, SB = BN + 32;    // padded LDS row pitch (floats)
+  constexpr int A4 = kBK * BM / 4;             // float4 per A plane per stage
+  constexpr int B4 = kBK * BN / 4;
+  constexpr int NA = 2 * A4 / kThreads, NBL = 2 * B4 / kThreads;
+  static_assert(2 * A4 % kThreads == 0 && 2 * B4 % kThreads == 0, "tile/thread mismatch");
+
+  __shared__ float sA[2][2][kBK * SA];
+  __shared__ float sB[2][2][kBK * SB];
+  __shared__ int s_last;
+
+  const int tid = threadIdx.x;
+  const int KT = a.K / kBK;
+  int t, kb, ke, tail = -1, chunk = 0;
+  if ((int)blockIdx.x < a.t_dp) {
+    t = xcd_tile(blockIdx.x, a.t_dp);
+    kb = 0;
+    ke = KT;
+  } else {
+    const int u = blockIdx.x - a.t_dp;
+    tail = u / a.split;
+    chunk = u % a.split;
+    t = a.t_dp + tail;
+    kb = chunk * KT / a.split;
+    ke = (chunk + 1) * KT / a.split;
+  }
+  const int m0 = (t % a.tiles_m) * BM;
+  const int n0 = (t / a.tiles_m) * BN;
+
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  v16f accR[MB][NB], accI[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      accR[i][j] = v16f{0};
+      accI[i][j] = v16f{0};
+    }
+
+  // Staging map: float4 s of this thread covers plane idx / A4 of the tile,
+  // row k = (idx % A4) / (BM / 4), columns 4 m4 .. 4 m4 + 3.
+  v4f ra[NA], rb[NBL];
+  const float *ga[NA];
+  const float *gb[NBL];
+  int la[NA], lb[NBL];
+#pragma unroll
+  for (int s = 0; s < NA; ++s) {
+    const int idx = tid + kThreads * s;
+    const int plane = idx / A4, rem = idx % A4;
+    const int k = rem / (BM / 4), m4 = rem % (BM / 4);
+    ga[s] = (plane ? a.ati : a.atr) + (size_t)k * a.lda + m0 + 4 * m4;
+    la[s] = plane * (kBK * SA) + k * SA + 4 * m4;
+  }
+#pragma unroll
+  for (int s = 0; s < NBL; ++s) {
+    const int idx = tid + kThreads * s;
+    const int plane = idx / B4, rem = idx % B4;
+    const int k = rem / (BN / 4), n4 = rem % (BN / 4);
+    gb[s] = (plane ? a.bi : a.br) + (size_t)k * a.ldb + n0 + 4 * n4;
+    lb[s] = plane * (kBK * SB) + k * SB + 4 * n4;
+  }
+  const size_t stepA = (size_t)kBK * a.lda, stepB = (size_t)kBK * a.ldb;
+
+  if (kb < ke) {
+#pragma unroll
+    for (int s = 0; s < NA; ++s)
+      ra[s] = *reinterpret_cast<const v4f *>(ga[s] + (size_t)kb * stepA);
+#pragma unroll
+    for (int s = 0; s < NBL; ++s)
+      rb[s] = *reinterpret_cast<const v4f *>(gb[s] + (size_t)kb * stepB);
+#pragma unroll
+    for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&sA[0][0][la[s]]) = ra[s];
+#pragma unroll
+    for (int s = 0; s < NBL; ++s) *reinterpret_cast<v4f *>(&sB[0][0][lb[s]]) = rb[s];
+  }
+  __syncthreads();
+  for (int kt = kb; kt < ke; ++kt) {
+    const int buf = (kt - kb) & 1;
+    const bool more = kt + 1 < ke;
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < NA; ++s)
+        ra[s] = *reinterpret_cast<const v4f *>(ga[s] + (size_t)(kt + 1) * stepA);
+#pragma unroll
+      for (int s = 0; s < NBL; ++s)
+        rb[s] = *reinterpret_cast<const v4f *>(gb[s] + (size_t)(kt + 1) * stepB);
+    }
+    const float *pa = &sA[buf][0][wm * WTM + l32];
+    const float *pb = &sB[buf][0][wn * WTN + l32];
+    // MFMA operands of k pair p sit in slot p & 1; the next pair's operands
+    // are read from LDS while the current pair's MFMAs run.  Lanes 0-31 take
+    // k = 2p, lanes 32-63 take k = 2p + 1.
+    float ar[2][MB], ai[2][MB], br[2][NB], bi[2][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      ar[0][i] = pa[h * SA + i * 32];
+      ai[0][i] = pa[kBK * SA + h * SA + i * 32];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      br[0][j] = pb[h * SB + j * 32];
+      bi[0][j] = pb[kBK * SB + h * SB + j * 32];
+    }
+#pragma unroll
+    for (int p = 0; p < kBK / 2; ++p) {
+      const int c = p & 1, q = c ^ 1;
+      if (p + 1 < kBK / 2) {
+        const int k = 2 * (p + 1) + h;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+          ar[q][i] = pa[k * SA + i * 32];
+          ai[q][i] = pa[kBK * SA + k * SA + i * 32];
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          br[q][j] = pb[k * SB + j * 32];
+          bi[q][j] = pb[kBK * SB + k * SB + j * 32];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[c][i], br[c][j], accR[i][j], 0, 0, 0);
+          accR[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[c][i], bi[c][j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[c][i], bi[c][j], accI[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[c][i], br[c][j], accI[i][j], 0, 0, 0);
+        }
+    }
+    if (more) {
+      float *qa = &sA[buf ^ 1][0][0];
+      float *qb = &sB[buf ^ 1][0][0];
+#pragma unroll
+      for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&qa[la[s]]) = ra[s];
+#pragma unroll
+      for (int s = 0; s < NBL; ++s) *reinterpret_cast<v4f *>(&qb[lb[s]]) = rb[s];
+    }
+    __syncthreads();
+  }
+
+  if (tail >= 0) {
+    // Partial tile of one K chunk in a thread-major layout (each store
+    // instruction writes one float per lane, contiguous across lanes).
+    constexpr int unit = 2 * MB * NB * 16 * kThreads;
+    float *pu = a.part + (size_t)(tail * a.split + chunk) * unit + tid;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int o = (((i * NB + j) * 16 + r) * 2) * kThreads;
+          pu[o] = accR[i][j][r];
+          pu[o + kThreads] = accI[i][j][r];
+        }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(a.cnt + tail, 1) == a.split - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    const float *pt = a.part + (size_t)tail * a.split * unit + tid;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        accR[i][j] = v16f{0};
+        accI[i][j] = v16f{0};
+      }
+    for (int c = 0; c < a.split; ++c) {
+      const float *pc = pt + (size_t)c * unit;
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int o = (((i * NB + j) * 16 + r) * 2) * kThreads;
+            accR[i][j][r] += pc[o];
+            accI[i][j][r] += pc[o + kThreads];
+          }
+    }
+    if (tid == 0) a.cnt[tail] = 0;
+  }
+  epilogue<MB, NB, EPI>(a, accR, accI, m0 + wm * WTM, n0 + wn * WTN, l32, h);
+}
+
+template <int BM, int BN, int EPI>
+hipError_t launch_t(const CgemmArgs &args, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((cgemm_f32_mfma<BM, BN, EPI>), dim3(grid), dim3(kThreads), 0, s, args);
   return hipGetLastError();
 }
 
 template <int EPI>
-hipError_t launch_e(int bm, int bn, const CgemmArgs &args, hipStream_t s) {
-  if (bm == 64 && bn == 64) return launch_t<64, 64, EPI>(args, s);
-  if (bm == 64 && bn == 128) return launch_t<64, 128, EPI>(args, s);
-  if (bm == 128 && bn == 64) return launch_t<128, 64, EPI>(args, s);
-  if (bm == 128 && bn == 128) return launch_t<128, 128, EPI>(args, s);
+hipError_t launch_e(int bm, int bn, const CgemmArgs &args, int grid, hipStream_t s) {
+  if (bm == 64 && bn == 64) return launch_t<64, 64, EPI>(args, grid, s);
+  if (bm == 64 && bn == 128) return launch_t<64, 128, EPI>(args, grid, s);
+  if (bm == 128 && bn == 64) return launch_t<128, 64, EPI>(args, grid, s);
+  if (bm == 128 && bn == 128) return launch_t<128, 128, EPI>(args, grid, s);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split) {
+  GemmSched s;
+  s.tile = tile;
+  s.tiles_m = M / tile.bm;
+  s.tiles = s.tiles_m * (N / tile.bn);
+  const int KT = K / kBK;
+  const int q = s.tiles / cus, r = s.tiles % cus;
+  s.t_dp = s.tiles;
+  s.n_tail = 0;
+  s.split = 1;
+  // Split the last round when it would leave more than a quarter of the CUs
+  // idle; each chunk keeps at least two K stages.
+  if (allow_split && r > 0 && r * 4 < cus * 3 && KT >= 4) {
+    int split = cus / r;
+    if (split > KT / 2) split = KT / 2;
+    if (split >= 2) {
+      s.t_dp = q * cus;
+      s.n_tail = r;
+      s.split = split;
+    }
+  }
+  s.grid = s.t_dp + s.n_tail * s.split;
+  s.part_floats = (size_t)s.n_tail * s.split * tile.bm * tile.bn * 2;
+  return s;
+}
+
 hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float *br,
                         const float *bi, float *cr, float *ci, const float *er,
                         const float *ei, bool honour_done, hipStream_t s) {
   const Dims &d = p->d;
-  const GemmTile &tl = forward ? p->tile_fwd : p->tile_bwd;
+  const GemmSched &sc = forward ? p->sched_fwd : p->sched_bwd;
   CgemmArgs a{};
   if (forward) {
     a.atr = p->b.omt_r; a.ati = p->b.omt_i; a.lda = d.Urp;
@@ -242,13 +364,18 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
   a.amp = p->b.amp;
   a.er = er; a.ei = ei;
   a.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
-  if (a.M % tl.bm || a.N % tl.bn || a.K % kBK) return hipErrorInvalidValue;
-  a.tiles_m = a.M / tl.bm;
-  a.tiles = a.tiles_m * (a.N / tl.bn);
+  a.part = p->b.part;
+  a.cnt = p->b.tickets;
+  if (a.M % sc.tile.bm || a.N % sc.tile.bn || a.K % kBK) return hipErrorInvalidValue;
+  if (sc.tiles_m * sc.tile.bm != a.M || sc.tiles * sc.tile.bm * sc.tile.bn != a.M * a.N)
+    return hipErrorInvalidValue;
+  a.tiles_m = sc.tiles_m;
+  a.t_dp = sc.t_dp;
+  a.split = sc.split;
   switch (epi) {
-    case EPI_STORE: return launch_e<EPI_STORE>(tl.bm, tl.bn, a, s);
-    case EPI_PROJECT: return launch_e<EPI_PROJECT>(tl.bm, tl.bn, a, s);
-    case EPI_GRAD: return launch_e<EPI_GRAD>(tl.bm, tl.bn, a, s);
+    case EPI_STORE: return launch_e<EPI_STORE>(sc.tile.bm, sc.tile.bn, a, sc.grid, s);
+    case EPI_PROJECT: return launch_e<EPI_PROJECT>(sc.tile.bm, sc.tile.bn, a, sc.grid, s);
+    case EPI_GRAD: return launch_e<EPI_GRAD>(sc.tile.bm, sc.tile.bn, a, sc.grid, s);
   }
   return hipErrorInvalidValue;
 }

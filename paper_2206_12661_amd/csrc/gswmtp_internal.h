@@ -73,9 +73,21 @@ struct Bufs {
   double *w = nullptr, *stats = nullptr, *hist = nullptr;
   int *ctrl = nullptr;
   float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
+  float *part = nullptr;                 // split-K partial tiles (shared by both products)
+  int *tickets = nullptr;                // split-K tickets
 };
 
 struct GemmTile { int bm = 64, bn = 64; };
+
+// Launch schedule of one complex product: t_dp whole tiles, then n_tail tiles
+// split along K into `split` chunks (grid = t_dp + n_tail * split).
+struct GemmSched {
+  GemmTile tile;
+  int tiles_m = 0, tiles = 0;
+  int t_dp = 0, n_tail = 0, split = 1;
+  int grid = 0;
+  size_t part_floats = 0;
+};
 
 }  // namespace gswmtp
 
@@ -89,7 +101,8 @@ struct gswmtp_plan {
   gswmtp::Bufs b;
   int precision = GSWMTP_FP32;
   int weighting = GSWMTP_WEIGHT_GSW;
-  gswmtp::GemmTile tile_fwd, tile_bwd;
+  gswmtp::GemmSched sched_fwd, sched_bwd;
+  int cus = 256;
   void *pool0 = nullptr, *pool1 = nullptr;
   size_t pool0_bytes = 0, pool1_bytes = 0;
   hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
@@ -113,6 +126,7 @@ hipError_t launch_grad_field(const gswmtp_plan *p, const float *g, hipStream_t s
 hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,
                           hipStream_t s);
 const char *cgemm_kernel_name(const gswmtp_plan *p, bool forward, int epi);
+GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split);
 
 enum { EPI_STORE = 0, EPI_PROJECT = 1, EPI_GRAD = 2 };
 enum { UPD_ITERATE = 0, UPD_STATS = 1, UPD_GRAD = 2 };

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -537,6 +538,7 @@ int check_device(gswmtp_plan *p) {
   HIP_TRY(p, hipGetDeviceProperties(&prop, p->device));
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(p, GSWMTP_E_NODEV, "device is not gfx950");
+  p->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   return GSWMTP_OK;
 }
 
@@ -555,22 +557,22 @@ void free_plan(gswmtp_plan *p) {
   delete p;
 }
 
-// GEMM tile choice per product shape (M, N): largest tile that keeps at least
-// one workgroup per CU, else the smallest.
+// GEMM tile per product: 64 x 64 complex tiles (four waves of 32 x 32),
+// which keeps three workgroups per CU resident; GSWMTP_TILE=BMxBN overrides.
 GemmTile choose_tile(int M, int N) {
-  static const int cand[4][2] = {{128, 128}, {64, 128}, {128, 64}, {64, 64}};
   const char *env = std::getenv("GSWMTP_TILE");
   if (env) {
     int bm = 0, bn = 0;
-    if (std::sscanf(env, "%dx%d", &bm, &bn) == 2 && M % bm == 0 && N % bn == 0 &&
-        (bm == 64 || bm == 128) && (bn == 64 || bn == 128))
+    if (std::sscanf(env, "%dx%d", &bm, &bn) == 2 && (bm == 64 || bm == 128) &&
+        (bn == 64 || bn == 128) && M % bm == 0 && N % bn == 0)
       return GemmTile{bm, bn};
   }
-  for (auto &c : cand) {
-    if (M % c[0] || N % c[1]) continue;
-    if ((long)(M / c[0]) * (N / c[1]) >= 256) return GemmTile{c[0], c[1]};
-  }
   return GemmTile{64, 64};
+}
+
+bool split_enabled() {
+  const char *env = std::getenv("GSWMTP_NO_SPLITK");
+  return !(env && std::atoi(env) != 0);
 }
 
 // One GSW pass (Algorithm 1 from forward propagation to the projected pupil).
@@ -739,8 +741,11 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   D.Rp = (int)round_up(D.Rk, kPadRows);
   D.Cp = (int)round_up(D.Ck, kPadCols);
   D.Urp = (int)round_up(D.Ur, kPadRows);
-  p->tile_fwd = choose_tile(D.Urp, D.Cp);
-  p->tile_bwd = choose_tile(D.Rp, D.Cp);
+  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp, choose_tile(D.Urp, D.Cp), p->cus, split_enabled());
+  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, choose_tile(D.Rp, D.Cp), p->cus, split_enabled());
+  const size_t part_floats =
+      std::max<size_t>(std::max(p->sched_fwd.part_floats, p->sched_bwd.part_floats), 1);
+  const size_t n_tickets = (size_t)std::max(std::max(p->sched_fwd.n_tail, p->sched_bwd.n_tail), 1);
 
   // ---- pool 1: kernel matrices, pupil and product buffers ----
   const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc;
@@ -753,6 +758,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     b.l_r = c.take<float>(Urp * Cp); b.l_i = c.take<float>(Urp * Cp);
     b.s_r = c.take<float>(Urp * Cp); b.s_i = c.take<float>(Urp * Cp);
     b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
+    b.part = c.take<float>(part_floats); b.tickets = c.take<int>(n_tickets);
   };
   {
     Carver c(nullptr);
