@@ -15,7 +15,7 @@ constexpr int kUpdThreads = 1024;
 __global__ __launch_bounds__(256) void focus_gather(
     const float *__restrict__ lr, const float *__restrict__ li, const float *__restrict__ wr,
     const float *__restrict__ wi, const int *__restrict__ ir, const int *__restrict__ ic,
-    float *__restrict__ theta, int nf, int Ck, int ld, const int *done) {
+    float *__restrict__ theta, int nf, int Ck, int ld, float scale, const int *done) {
   if (done && *done) return;
   const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -34,8 +34,8 @@ __global__ __launch_bounds__(256) void focus_gather(
     si += __shfl_xor(si, off, 64);
   }
   if (lane == 0) {
-    theta[2 * n] = sr;
-    theta[2 * n + 1] = si;
+    theta[2 * n] = sr * scale;
+    theta[2 * n + 1] = si * scale;
   }
 }
 
@@ -213,15 +213,93 @@ __global__ __launch_bounds__(256) void focus_scatter(
   si[(size_t)a * Cp + i] = acci;
 }
 
+// Split-precision scatter: the same S, written transposed as 16-bit term
+// planes S^T [re/im][term][Cp][Urp] (the k-contiguous B operand of the
+// split adjoint product).  A block computes a 32 (a) x 64 (i) tile of S with
+// coalesced reads of Wc, transposes it through LDS and writes 8 consecutive a
+// per thread and plane (16 bytes).
+template <bool BF, int NT>
+__global__ __launch_bounds__(256) void focus_scatter_split(
+    const float *__restrict__ tn, const float *__restrict__ wr, const float *__restrict__ wi,
+    const int *__restrict__ ic, const int *__restrict__ ptr, const int *__restrict__ foci,
+    unsigned short *__restrict__ st, int Ur, int Urp, int Cp, float scale, const int *done) {
+  if (done && *done) return;
+  __shared__ float tr[32][65], ti[32][65];
+  const int i0 = blockIdx.x * 64, a0 = blockIdx.y * 32;
+  const int tid = threadIdx.x;
+  const int il = tid & 63;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int al = (tid >> 6) + 4 * q;
+    const int a = a0 + al;
+    float accr = 0.f, acci = 0.f;
+    if (a < Ur) {
+      const int p0 = ptr[a], p1 = ptr[a + 1];
+      for (int pp = p0; pp < p1; ++pp) {
+        const int n = foci[pp];
+        const float xr = tn[2 * n] * scale, xi = tn[2 * n + 1] * scale;
+        const size_t o = (size_t)ic[n] * Cp + i0 + il;
+        const float yr = wr[o], yi = -wi[o];
+        accr = fmaf(xr, yr, fmaf(-xi, yi, accr));
+        acci = fmaf(xr, yi, fmaf(xi, yr, acci));
+      }
+    }
+    tr[al][il] = accr;
+    ti[al][il] = acci;
+  }
+  __syncthreads();
+  const int i = tid >> 2, part = tid & 3;   // 64 columns x 4 runs of 8 a
+  unsigned short vr[NT][8], vi[NT][8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    split_terms<BF, NT>(tr[8 * part + q][i], &vr[0][q], 8);
+    split_terms<BF, NT>(ti[8 * part + q][i], &vi[0][q], 8);
+  }
+  const size_t plane = (size_t)Cp * Urp;
+  const size_t off = (size_t)(i0 + i) * Urp + a0 + 8 * part;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    u4 wv, wiv;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      wv[e] = (unsigned)vr[q][2 * e] | ((unsigned)vr[q][2 * e + 1] << 16);
+      wiv[e] = (unsigned)vi[q][2 * e] | ((unsigned)vi[q][2 * e + 1] << 16);
+    }
+    *reinterpret_cast<u4 *>(st + (size_t)q * plane + off) = wv;
+    *reinterpret_cast<u4 *>(st + (size_t)(NT + q) * plane + off) = wiv;
+  }
+}
+
 }  // namespace
 
+hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
+                                bool honour_done, hipStream_t s) {
+  const Dims &d = p->d;
+  const int *ic = d.axis == 0 ? p->b.ix : p->b.iy;
+  const dim3 grid(d.Cp / 64, d.Urp / 32);
+  const int *done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+#define SCATTER_SPLIT(BF, NT)                                                                  \
+  hipLaunchKernelGGL((focus_scatter_split<BF, NT>), grid, dim3(256), 0, s, theta_new, p->b.wc_r, \
+                     p->b.wc_i, ic, p->b.csr_ptr, p->b.csr_foci, p->b.ss, d.Ur, d.Urp, d.Cp,     \
+                     scale, done)
+  switch (p->precision) {
+    case GSWMTP_BF16X3: SCATTER_SPLIT(true, 2); break;
+    case GSWMTP_FP16X3: SCATTER_SPLIT(false, 2); break;
+    case GSWMTP_BF16X6: SCATTER_SPLIT(true, 3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SCATTER_SPLIT
+  return hipGetLastError();
+}
+
 hipError_t launch_gather(const gswmtp_plan *p, const float *lr, const float *li, float *theta,
-                         bool honour_done, hipStream_t s) {
+                         float scale, bool honour_done, hipStream_t s) {
   const Dims &d = p->d;
   const int *ir = d.axis == 0 ? p->b.iy : p->b.ix;
   const int *ic = d.axis == 0 ? p->b.ix : p->b.iy;
   hipLaunchKernelGGL(focus_gather, dim3((d.nf + 3) / 4), dim3(256), 0, s, lr, li, p->b.wc_r,
-                     p->b.wc_i, ir, ic, theta, d.nf, d.Ck, d.Cp,
+                     p->b.wc_i, ir, ic, theta, d.nf, d.Ck, d.Cp, scale,
                      honour_done ? p->b.ctrl + CTRL_DONE : nullptr);
   return hipGetLastError();
 }

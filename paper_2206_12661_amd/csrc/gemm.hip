@@ -380,6 +380,8 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
   return hipErrorInvalidValue;
 }
 
-const char *cgemm_kernel_name(const gswmtp_plan *, bool, int) { return "cgemm_f32_mfma"; }
+const char *cgemm_kernel_name(const gswmtp_plan *p, bool, int) {
+  return split_terms_of(p->precision) ? "cgemm_split_mfma" : "cgemm_f32_mfma";
+}
 
 }  // namespace gswmtp

@@ -75,7 +75,58 @@ struct Bufs {
   float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
   float *part = nullptr;                 // split-K partial tiles (shared by both products)
   int *tickets = nullptr;                // split-K tickets
+  // split-precision modes: 16-bit term planes, k-contiguous ([re/im][term][row][K])
+  unsigned short *as_f = nullptr;        // Omega_r            [2][NT][Urp][Rp]
+  unsigned short *as_b = nullptr;        // Omega_r^H          [2][NT][Rp][Urp]
+  unsigned short *ps = nullptr;          // pupil field P^T    [2][NT][Cp][Rp]
+  unsigned short *ss = nullptr;          // scatter S^T        [2][NT][Cp][Urp]
+  unsigned short *xs = nullptr;          // operator-call P^T  [2][NT][Cp][Rp]
 };
+
+// Number of 16-bit terms per float32 operand of a precision mode (0: float32).
+__host__ __device__ inline int split_terms_of(int precision) {
+  return precision == GSWMTP_BF16X3 || precision == GSWMTP_FP16X3 ? 2
+         : precision == GSWMTP_BF16X6                             ? 3
+                                                                  : 0;
+}
+__host__ __device__ inline bool split_is_bf16(int precision) {
+  return precision == GSWMTP_BF16X3 || precision == GSWMTP_BF16X6;
+}
+
+// Round-to-nearest-even float32 -> bfloat16 / float16 bit patterns and back.
+__device__ __forceinline__ unsigned short f32_to_bf16_rn(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float((unsigned)h << 16);
+}
+__device__ __forceinline__ unsigned short f32_to_f16_rn(float f) {
+  return __builtin_bit_cast(unsigned short, (_Float16)f);
+}
+__device__ __forceinline__ float f16_to_f32(unsigned short h) {
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+
+// x = t0 + t1 (+ t2) in 16-bit terms: t0 = rn(x), t1 = rn(x - t0), ...; the
+// float32 remainders are exact.  out[q * stride] receives term q.
+template <bool BF, int NT>
+__device__ __forceinline__ void split_terms(float x, unsigned short *out, int stride) {
+  float r = x;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const unsigned short h = BF ? f32_to_bf16_rn(r) : f32_to_f16_rn(r);
+    out[q * stride] = h;
+    r = r - (BF ? bf16_to_f32(h) : f16_to_f32(h));
+  }
+}
+__device__ __forceinline__ float join_terms(bool bf, int nt, const unsigned short *t,
+                                            size_t stride) {
+  float v = 0.f;
+  for (int q = nt - 1; q >= 0; --q) v += bf ? bf16_to_f32(t[q * stride]) : f16_to_f32(t[q * stride]);
+  return v;
+}
 
 struct GemmTile { int bm = 64, bn = 64; };
 
@@ -103,6 +154,7 @@ struct gswmtp_plan {
   int weighting = GSWMTP_WEIGHT_GSW;
   gswmtp::GemmSched sched_fwd, sched_bwd;
   int cus = 256;
+  int amp_exp = 0;                        // split modes: P carries amp * 2^amp_exp
   void *pool0 = nullptr, *pool1 = nullptr;
   size_t pool0_bytes = 0, pool1_bytes = 0;
   hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
@@ -120,7 +172,12 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
                         const float *bi, float *cr, float *ci, const float *er,
                         const float *ei, bool honour_done, hipStream_t s);
 hipError_t launch_gather(const gswmtp_plan *p, const float *lr, const float *li, float *theta,
-                         bool honour_done, hipStream_t s);
+                         float scale, bool honour_done, hipStream_t s);
+hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
+                              const unsigned short *bt, float *cr, float *ci,
+                              unsigned short *pt_out, bool honour_done, hipStream_t s);
+hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
+                                bool honour_done, hipStream_t s);
 hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s);
 hipError_t launch_grad_field(const gswmtp_plan *p, const float *g, hipStream_t s);
 hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,

@@ -371,12 +371,14 @@ struct Orient {
   }
 };
 
-// Internal amplitude (zero in the padding).
-__global__ void k_encode_amp(Orient o, const float *aeff, int nx, int Rp, int Cp, float *amp) {
+// Internal amplitude times an exact power-of-two scale (zero in the padding).
+__global__ void k_encode_amp(Orient o, const float *aeff, float scale, int nx, int Rp, int Cp,
+                             float *amp) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (size_t)Rp * Cp) return;
   int y, x;
-  amp[id] = o.user((int)(id / Cp), (int)(id % Cp), &y, &x) ? aeff[(size_t)y * nx + x] : 0.f;
+  amp[id] = o.user((int)(id / Cp), (int)(id % Cp), &y, &x) ? aeff[(size_t)y * nx + x] * scale
+                                                            : 0.f;
 }
 
 // Pupil field E = A exp(i phi) from a user-layout phase (nullable = zeros).
@@ -446,14 +448,14 @@ __global__ void k_phase_out(const float *pr, const float *pi, const float *amp,
 // Internal planes -> user-layout interleaved complex (zero where compacted).
 __global__ void k_expand_complex(const float *xr, const float *xi, const int *row_pos,
                                  const int *col_pos, int axis, int ny, int nx, int Cp,
-                                 float *out) {
+                                 float scale, float *out) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (size_t)ny * nx) return;
   int r, c;
   float re = 0.f, im = 0.f;
   if (internal_of(row_pos, col_pos, axis, (int)(id / nx), (int)(id % nx), &r, &c)) {
-    re = xr[(size_t)r * Cp + c];
-    im = xi[(size_t)r * Cp + c];
+    re = xr[(size_t)r * Cp + c] * scale;
+    im = xi[(size_t)r * Cp + c] * scale;
   }
   out[2 * id] = re;
   out[2 * id + 1] = im;
@@ -470,6 +472,102 @@ __global__ void k_expand_real(const float *xr, const int *row_pos, const int *co
     v = xr[(size_t)r * Cp + c];
   out[id] = v;
 }
+
+
+// ---- split-precision layouts (16-bit term planes, k-contiguous) ----
+
+// Omega_r as split planes: forward A [re/im][term][Urp][Rp] and adjoint
+// A = Omega_r^H [re/im][term][Rp][Urp].
+template <bool BF, int NT>
+__global__ void k_omega_r_split(const double *coord, const int *kept, int Rk, const double *fu,
+                                int Ur, double s, int Rp, int Urp, unsigned short *af,
+                                unsigned short *ab) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Rp * Urp) return;
+  const int j = (int)(id / Urp), a = (int)(id % Urp);
+  float re = 0.f, im = 0.f;
+  if (j < Rk && a < Ur) kernel_phasor(s, coord[kept[j]], fu[a], &re, &im);
+  unsigned short tr[NT], ti[NT], tc[NT];
+  split_terms<BF, NT>(re, tr, 1);
+  split_terms<BF, NT>(im, ti, 1);
+  split_terms<BF, NT>(-im, tc, 1);
+  const size_t plane = (size_t)Rp * Urp;
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    af[(size_t)q * plane + (size_t)a * Rp + j] = tr[q];
+    af[(size_t)(NT + q) * plane + (size_t)a * Rp + j] = ti[q];
+    ab[(size_t)q * plane + (size_t)j * Urp + a] = tr[q];
+    ab[(size_t)(NT + q) * plane + (size_t)j * Urp + a] = tc[q];
+  }
+}
+
+// Pupil field from a phase as split planes P^T [re/im][term][Cp][Rp]
+// (amp already carries the power-of-two scale).
+template <bool BF, int NT>
+__global__ void k_encode_phase_split(Orient o, const float *phi, const float *amp, int nx,
+                                     int Rp, int Cp, unsigned short *pt) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Rp * Cp) return;
+  const int i = (int)(id / Rp), j = (int)(id % Rp);
+  int y, x;
+  float re = 0.f, im = 0.f;
+  if (o.user(j, i, &y, &x)) {
+    const float a = amp[(size_t)j * Cp + i];
+    const float ph = phi ? phi[(size_t)y * nx + x] : 0.f;
+    float sn, cs;
+    sincosf(ph, &sn, &cs);
+    re = a * cs;
+    im = a * sn;
+  }
+  const size_t plane = (size_t)Rp * Cp;
+  split_terms<BF, NT>(re, pt + id, (int)plane);
+  split_terms<BF, NT>(im, pt + (size_t)NT * plane + id, (int)plane);
+}
+
+// User-layout complex field (interleaved), times scale, as split planes P^T.
+template <bool BF, int NT>
+__global__ void k_compact_split(Orient o, const float *in, float scale, int nx, int Rp, int Cp,
+                                unsigned short *pt) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Rp * Cp) return;
+  const int i = (int)(id / Rp), j = (int)(id % Rp);
+  int y, x;
+  float re = 0.f, im = 0.f;
+  if (o.user(j, i, &y, &x)) {
+    re = in[2 * ((size_t)y * nx + x)] * scale;
+    im = in[2 * ((size_t)y * nx + x) + 1] * scale;
+  }
+  const size_t plane = (size_t)Rp * Cp;
+  split_terms<BF, NT>(re, pt + id, (int)plane);
+  split_terms<BF, NT>(im, pt + (size_t)NT * plane + id, (int)plane);
+}
+
+// Phase of the split pupil planes in the user's layout.
+__global__ void k_phase_out_split(const unsigned short *pt, bool bf, int nt, const float *amp,
+                                  const int *row_pos, const int *col_pos, int axis, int ny,
+                                  int nx, int Rp, int Cp, float *out) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)ny * nx) return;
+  const int y = (int)(id / nx), x = (int)(id % nx);
+  int r, c;
+  float ph = 0.f;
+  if (internal_of(row_pos, col_pos, axis, y, x, &r, &c) && amp[(size_t)r * Cp + c] > 0.f) {
+    const size_t plane = (size_t)Rp * Cp, o = (size_t)c * Rp + r;
+    const float re = join_terms(bf, nt, pt + o, plane);
+    const float im = join_terms(bf, nt, pt + (size_t)nt * plane + o, plane);
+    ph = atan2f(im, re);
+    if (ph == -3.14159274101257324f) ph = 3.14159274101257324f;
+  }
+  out[id] = ph;
+}
+
+#define DISPATCH_SPLIT(prec, X)          \
+  switch (prec) {                        \
+    case GSWMTP_BF16X3: X(true, 2); break; \
+    case GSWMTP_FP16X3: X(false, 2); break; \
+    case GSWMTP_BF16X6: X(true, 3); break; \
+    default: break;                      \
+  }
 
 // Run control written by a kernel (graph-safe, no memset): clear the done
 // flag and set the termination threshold.
@@ -575,31 +673,87 @@ bool split_enabled() {
   return !(env && std::atoi(env) != 0);
 }
 
+bool is_split(const gswmtp_plan *p) { return split_terms_of(p->precision) > 0; }
+
+// Stages of one pass, in either arithmetic.
+hipError_t stage_forward(gswmtp_plan *p, bool done, hipStream_t s) {
+  if (is_split(p))
+    return launch_cgemm_split(p, true, EPI_STORE, p->b.ps, p->b.l_r, p->b.l_i, nullptr, done, s);
+  return launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r, p->b.l_i, nullptr,
+                      nullptr, done, s);
+}
+hipError_t stage_gather(gswmtp_plan *p, float *theta, bool done, hipStream_t s) {
+  return launch_gather(p, p->b.l_r, p->b.l_i, theta, std::ldexp(1.f, -p->amp_exp), done, s);
+}
+hipError_t stage_scatter(gswmtp_plan *p, bool done, hipStream_t s) {
+  if (is_split(p)) return launch_scatter_split(p, p->b.theta_new, 1.f, done, s);
+  return launch_scatter(p, p->b.theta_new, done, s);
+}
+hipError_t stage_adjoint(gswmtp_plan *p, bool done, hipStream_t s) {
+  if (is_split(p))
+    return launch_cgemm_split(p, false, EPI_PROJECT, p->b.ss, nullptr, nullptr, p->b.ps, done, s);
+  return launch_cgemm(p, false, EPI_PROJECT, p->b.s_r, p->b.s_i, p->b.p_r, p->b.p_i, nullptr,
+                      nullptr, done, s);
+}
+
 // One GSW pass (Algorithm 1 from forward propagation to the projected pupil).
 hipError_t enqueue_pass(gswmtp_plan *p, hipStream_t s) {
   hipError_t e;
-  if ((e = launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r, p->b.l_i, nullptr,
-                        nullptr, true, s)) != hipSuccess)
-    return e;
-  if ((e = launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta, true, s)) != hipSuccess) return e;
+  if ((e = stage_forward(p, true, s)) != hipSuccess) return e;
+  if ((e = stage_gather(p, p->b.theta, true, s)) != hipSuccess) return e;
   if ((e = launch_update(p, UPD_ITERATE, s)) != hipSuccess) return e;
-  if ((e = launch_scatter(p, p->b.theta_new, true, s)) != hipSuccess) return e;
-  return launch_cgemm(p, false, EPI_PROJECT, p->b.s_r, p->b.s_i, p->b.p_r, p->b.p_i, nullptr,
-                      nullptr, true, s);
+  if ((e = stage_scatter(p, true, s)) != hipSuccess) return e;
+  return stage_adjoint(p, true, s);
 }
 
 // Forward field and statistics of the current phase (no weight update).
 hipError_t ensure_forward(gswmtp_plan *p) {
   if (p->fwd_valid) return hipSuccess;
   hipError_t e;
-  if ((e = launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r, p->b.l_i, nullptr,
-                        nullptr, false, p->stream)) != hipSuccess)
-    return e;
-  if ((e = launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta, false, p->stream)) != hipSuccess)
-    return e;
+  if ((e = stage_forward(p, false, p->stream)) != hipSuccess) return e;
+  if ((e = stage_gather(p, p->b.theta, false, p->stream)) != hipSuccess) return e;
   if ((e = launch_update(p, UPD_STATS, p->stream)) != hipSuccess) return e;
   p->fwd_valid = true;
   return hipSuccess;
+}
+
+// Encode a user-layout phase (device, nullable = zeros) into the pupil field.
+hipError_t encode_phase(gswmtp_plan *p, const float *dev_phi, hipStream_t s) {
+  const Dims &D = p->d;
+  const Orient o = orient_of(p);
+  const dim3 g = grid1((size_t)D.Rp * D.Cp);
+  if (is_split(p)) {
+#define ENC(BF, NT)                                                                              \
+  hipLaunchKernelGGL((k_encode_phase_split<BF, NT>), g, dim3(256), 0, s, o, dev_phi, p->b.amp, \
+                     D.nx, D.Rp, D.Cp, p->b.ps)
+    DISPATCH_SPLIT(p->precision, ENC)
+#undef ENC
+  } else {
+    hipLaunchKernelGGL(k_encode_phase, g, dim3(256), 0, s, o, dev_phi, p->b.amp, D.nx, D.Rp,
+                       D.Cp, p->b.p_r, p->b.p_i);
+  }
+  return hipGetLastError();
+}
+
+// Phase of the current pupil field into device memory (user layout).
+hipError_t phase_out(gswmtp_plan *p, float *dev_out, hipStream_t s) {
+  const Dims &D = p->d;
+  const dim3 g = grid1((size_t)D.ny * D.nx);
+  if (is_split(p)) {
+    hipLaunchKernelGGL(k_phase_out_split, g, dim3(256), 0, s, p->b.ps,
+                       split_is_bf16(p->precision), split_terms_of(p->precision), p->b.amp,
+                       p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Rp, D.Cp, dev_out);
+  } else {
+    hipLaunchKernelGGL(k_phase_out, g, dim3(256), 0, s, p->b.p_r, p->b.p_i, p->b.amp,
+                       p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, dev_out);
+  }
+  return hipGetLastError();
+}
+
+// Exponent e with max|v| * 2^e in [0.5, 1) (0 for an all-zero input).
+int scale_exponent(double amax) {
+  if (!(amax > 0.0) || !std::isfinite(amax)) return 0;
+  return -std::ilogb(amax) - 1;
 }
 
 hipError_t capture(gswmtp_plan *p, int passes, hipGraphExec_t *out) {
@@ -626,8 +780,17 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   D.nf = d->n_foci;
   p->precision = d->precision;
   p->weighting = d->weighting;
-  if (p->precision != GSWMTP_FP32)
-    return fail(p, GSWMTP_E_UNSUPPORTED, "precision mode not built in this version");
+  // float16 terms need operands near unit scale: the pupil carries
+  // A * 2^amp_exp with max A * 2^amp_exp in [0.5, 1); the gather undoes it.
+  if (p->precision == GSWMTP_FP16X3) {
+    double amax = 1.0;
+    if (d->amplitude) {
+      amax = 0.0;
+      for (size_t i = 0; i < (size_t)d->ny * d->nx; ++i)
+        amax = std::max(amax, (double)d->amplitude[i]);
+    }
+    p->amp_exp = scale_exponent(amax);
+  }
   const char *ng = std::getenv("GSWMTP_NO_GRAPH");
   p->use_graph = !(ng && std::atoi(ng) != 0);
 
@@ -749,16 +912,24 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
 
   // ---- pool 1: kernel matrices, pupil and product buffers ----
   const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc;
+  const bool split = is_split(p);
+  const size_t nt = (size_t)split_terms_of(p->precision);
+  const size_t f32 = split ? 0 : 1;       // float32-only buffers
   auto carve1 = [&](Carver &c) {
-    b.omt_r = c.take<float>(Rp * Urp); b.omt_i = c.take<float>(Rp * Urp);
-    b.omc_r = c.take<float>(Rp * Urp); b.omc_i = c.take<float>(Rp * Urp);
+    b.omt_r = c.take<float>(f32 * Rp * Urp); b.omt_i = c.take<float>(f32 * Rp * Urp);
+    b.omc_r = c.take<float>(f32 * Rp * Urp); b.omc_i = c.take<float>(f32 * Rp * Urp);
     b.wc_r = c.take<float>(Uc * Cp); b.wc_i = c.take<float>(Uc * Cp);
     b.amp = c.take<float>(Rp * Cp);
-    b.p_r = c.take<float>(Rp * Cp); b.p_i = c.take<float>(Rp * Cp);
+    b.p_r = c.take<float>(f32 * Rp * Cp); b.p_i = c.take<float>(f32 * Rp * Cp);
     b.l_r = c.take<float>(Urp * Cp); b.l_i = c.take<float>(Urp * Cp);
-    b.s_r = c.take<float>(Urp * Cp); b.s_i = c.take<float>(Urp * Cp);
+    b.s_r = c.take<float>(f32 * Urp * Cp); b.s_i = c.take<float>(f32 * Urp * Cp);
     b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
     b.part = c.take<float>(part_floats); b.tickets = c.take<int>(n_tickets);
+    b.as_f = c.take<unsigned short>(2 * nt * Urp * Rp);
+    b.as_b = c.take<unsigned short>(2 * nt * Rp * Urp);
+    b.ps = c.take<unsigned short>(2 * nt * Cp * Rp);
+    b.xs = c.take<unsigned short>(2 * nt * Cp * Rp);
+    b.ss = c.take<unsigned short>(2 * nt * Cp * Urp);
   };
   {
     Carver c(nullptr);
@@ -786,20 +957,27 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   const double *cfu = D.axis == 0 ? b.xu : b.yu;
   const double s_r = D.axis == 0 ? d->s_y : d->s_x;
   const double s_c = D.axis == 0 ? d->s_x : d->s_y;
-  hipLaunchKernelGGL(k_omega_r, grid1(Rp * Urp), dim3(256), 0, s, rcoord, rkept, D.Rk, rfu,
-                     D.Ur, s_r, D.Rp, D.Urp, b.omt_r, b.omt_i, b.omc_r, b.omc_i);
+  if (split) {
+#define OMEGA(BF, NT)                                                                          \
+  hipLaunchKernelGGL((k_omega_r_split<BF, NT>), grid1(Rp * Urp), dim3(256), 0, s, rcoord, rkept, \
+                     D.Rk, rfu, D.Ur, s_r, D.Rp, D.Urp, b.as_f, b.as_b)
+    DISPATCH_SPLIT(p->precision, OMEGA)
+#undef OMEGA
+  } else {
+    hipLaunchKernelGGL(k_omega_r, grid1(Rp * Urp), dim3(256), 0, s, rcoord, rkept, D.Rk, rfu,
+                       D.Ur, s_r, D.Rp, D.Urp, b.omt_r, b.omt_i, b.omc_r, b.omc_i);
+  }
   hipLaunchKernelGGL(k_omega_c, grid1(Uc * Cp), dim3(256), 0, s, ccoord, ckept, D.Ck, cfu,
                      D.Uc, s_c, D.Cp, b.wc_r, b.wc_i);
   const Orient o = orient_of(p);
-  hipLaunchKernelGGL(k_encode_amp, grid1(Rp * Cp), dim3(256), 0, s, o, b.aeff, (int)nx, D.Rp,
-                     D.Cp, b.amp);
+  hipLaunchKernelGGL(k_encode_amp, grid1(Rp * Cp), dim3(256), 0, s, o, b.aeff,
+                     std::ldexp(1.f, p->amp_exp), (int)nx, D.Rp, D.Cp, b.amp);
   const float *phi_dev = nullptr;
   if (d->phi0) {
     HIP_TRY(p, hipMemcpyAsync(b.iobuf, d->phi0, np * 4, hipMemcpyHostToDevice, s));
     phi_dev = b.iobuf;
   }
-  hipLaunchKernelGGL(k_encode_phase, grid1(Rp * Cp), dim3(256), 0, s, o, phi_dev, b.amp,
-                     (int)nx, D.Rp, D.Cp, b.p_r, b.p_i);
+  HIP_TRY(p, encode_phase(p, phi_dev, s));
   hipLaunchKernelGGL(k_fill_d, grid1(nf), dim3(256), 0, s, b.w, 1.0, nf);
   HIP_TRY(p, hipGetLastError());
   HIP_TRY(p, hipStreamSynchronize(s));
@@ -935,11 +1113,7 @@ int gswmtp_get_phase_device(gswmtp_plan *p, float *dev_out) {
   if (!p || !dev_out) return GSWMTP_E_INVAL;
   DeviceGuard g(p->device);
   HIP_TRY(p, enter(p));
-  const Dims &D = p->d;
-  hipLaunchKernelGGL(k_phase_out, grid1((size_t)D.ny * D.nx), dim3(256), 0, p->stream, p->b.p_r,
-                     p->b.p_i, p->b.amp, p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp,
-                     dev_out);
-  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, phase_out(p, dev_out, p->stream));
   HIP_TRY(p, leave(p));
   return GSWMTP_OK;
 }
@@ -949,20 +1123,14 @@ int gswmtp_get_phase(gswmtp_plan *p, float *out) {
   DeviceGuard g(p->device);
   const size_t np = (size_t)p->d.ny * p->d.nx;
   HIP_TRY(p, enter(p));
-  hipLaunchKernelGGL(k_phase_out, grid1(np), dim3(256), 0, p->stream, p->b.p_r, p->b.p_i,
-                     p->b.amp, p->b.row_pos, p->b.col_pos, p->d.axis, p->d.ny, p->d.nx, p->d.Cp,
-                     p->b.iobuf);
-  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, phase_out(p, p->b.iobuf, p->stream));
   HIP_TRY(p, hipMemcpyAsync(out, p->b.iobuf, np * 4, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(p, hipStreamSynchronize(p->stream));
   return GSWMTP_OK;
 }
 
 static int set_phase_impl(gswmtp_plan *p, const float *dev_phi) {
-  const Dims &D = p->d;
-  hipLaunchKernelGGL(k_encode_phase, grid1((size_t)D.Rp * D.Cp), dim3(256), 0, p->stream,
-                     orient_of(p), dev_phi, p->b.amp, D.nx, D.Rp, D.Cp, p->b.p_r, p->b.p_i);
-  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, encode_phase(p, dev_phi, p->stream));
   p->fwd_valid = false;
   return GSWMTP_OK;
 }
@@ -1121,15 +1289,36 @@ int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta) {
   DeviceGuard g(p->device);
   const Dims &D = p->d;
   const size_t np = (size_t)D.ny * D.nx;
+  if (!finite_all(E, 2 * np)) return fail(p, GSWMTP_E_INVAL, "non-finite pupil field");
   HIP_TRY(p, enter(p));
   hipStream_t s = p->stream;
   HIP_TRY(p, hipMemcpyAsync(p->b.iobuf, E, 8 * np, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_compact_complex, grid1((size_t)D.Rp * D.Cp), dim3(256), 0, s,
-                     orient_of(p), p->b.iobuf, D.nx, D.Rp, D.Cp, p->b.x_r, p->b.x_i);
-  HIP_TRY(p, hipGetLastError());
-  HIP_TRY(p, launch_cgemm(p, true, EPI_STORE, p->b.x_r, p->b.x_i, p->b.l_r, p->b.l_i, nullptr,
-                          nullptr, false, s));
-  HIP_TRY(p, launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta_new, false, s));
+  const dim3 gr = grid1((size_t)D.Rp * D.Cp);
+  const Orient o = orient_of(p);
+  float unscale = 1.f;
+  if (is_split(p)) {
+    // float16/bfloat16 terms: bring the field to unit scale by a power of two
+    double amax = 0.0;
+    for (size_t i = 0; i < 2 * np; ++i) amax = std::max(amax, (double)std::fabs(E[i]));
+    const int e = p->precision == GSWMTP_FP16X3 ? scale_exponent(amax) : 0;
+    const float sc = std::ldexp(1.f, e);
+    unscale = std::ldexp(1.f, -e);
+#define COMPACT(BF, NT)                                                                     \
+  hipLaunchKernelGGL((k_compact_split<BF, NT>), gr, dim3(256), 0, s, o, p->b.iobuf, sc, D.nx, \
+                     D.Rp, D.Cp, p->b.xs)
+    DISPATCH_SPLIT(p->precision, COMPACT)
+#undef COMPACT
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, launch_cgemm_split(p, true, EPI_STORE, p->b.xs, p->b.l_r, p->b.l_i, nullptr, false,
+                                  s));
+  } else {
+    hipLaunchKernelGGL(k_compact_complex, gr, dim3(256), 0, s, o, p->b.iobuf, D.nx, D.Rp, D.Cp,
+                       p->b.x_r, p->b.x_i);
+    HIP_TRY(p, hipGetLastError());
+    HIP_TRY(p, launch_cgemm(p, true, EPI_STORE, p->b.x_r, p->b.x_i, p->b.l_r, p->b.l_i, nullptr,
+                            nullptr, false, s));
+  }
+  HIP_TRY(p, launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta_new, unscale, false, s));
   HIP_TRY(p, hipMemcpyAsync(theta, p->b.theta_new, 8 * (size_t)D.nf, hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipStreamSynchronize(s));
   return GSWMTP_OK;
@@ -1140,14 +1329,27 @@ int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E) {
   DeviceGuard g(p->device);
   const Dims &D = p->d;
   const size_t np = (size_t)D.ny * D.nx;
+  if (!finite_all(theta, 2 * (size_t)D.nf)) return fail(p, GSWMTP_E_INVAL, "non-finite field");
   HIP_TRY(p, enter(p));
   hipStream_t s = p->stream;
   HIP_TRY(p, hipMemcpyAsync(p->b.theta_new, theta, 8 * (size_t)D.nf, hipMemcpyHostToDevice, s));
-  HIP_TRY(p, launch_scatter(p, p->b.theta_new, false, s));
-  HIP_TRY(p, launch_cgemm(p, false, EPI_STORE, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i, nullptr,
-                          nullptr, false, s));
+  float unscale = 1.f;
+  if (is_split(p)) {
+    double amax = 0.0;
+    for (size_t i = 0; i < 2 * (size_t)D.nf; ++i)
+      amax = std::max(amax, (double)std::fabs(theta[i]));
+    const int e = p->precision == GSWMTP_FP16X3 ? scale_exponent(amax) : 0;
+    unscale = std::ldexp(1.f, -e);
+    HIP_TRY(p, launch_scatter_split(p, p->b.theta_new, std::ldexp(1.f, e), false, s));
+    HIP_TRY(p, launch_cgemm_split(p, false, EPI_STORE, p->b.ss, p->b.x_r, p->b.x_i, nullptr,
+                                  false, s));
+  } else {
+    HIP_TRY(p, launch_scatter(p, p->b.theta_new, false, s));
+    HIP_TRY(p, launch_cgemm(p, false, EPI_STORE, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i,
+                            nullptr, nullptr, false, s));
+  }
   hipLaunchKernelGGL(k_expand_complex, grid1(np), dim3(256), 0, s, p->b.x_r, p->b.x_i,
-                     p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, p->b.iobuf);
+                     p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, unscale, p->b.iobuf);
   HIP_TRY(p, hipGetLastError());
   HIP_TRY(p, hipMemcpyAsync(E, p->b.iobuf, 8 * np, hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipStreamSynchronize(s));
@@ -1156,6 +1358,8 @@ int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E) {
 
 int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad) {
   if (!p || !dev_g || !dev_grad) return GSWMTP_E_INVAL;
+  if (is_split(p))
+    return fail(p, GSWMTP_E_UNSUPPORTED, "phase gradient is built for FP32 plans only");
   DeviceGuard g(p->device);
   const Dims &D = p->d;
   HIP_TRY(p, enter(p));
@@ -1186,17 +1390,15 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out) {
     for (int it = 0; it < n_iter && rc == GSWMTP_OK; ++it) {
       hipEvent_t *e = &ev[(size_t)it * (GSWMTP_N_STAGES + 1)];
       hipError_t er = hipEventRecord(e[0], s);
-      if (er == hipSuccess) er = launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r,
-                                              p->b.l_i, nullptr, nullptr, true, s);
+      if (er == hipSuccess) er = stage_forward(p, true, s);
       if (er == hipSuccess) er = hipEventRecord(e[1], s);
-      if (er == hipSuccess) er = launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta, true, s);
+      if (er == hipSuccess) er = stage_gather(p, p->b.theta, true, s);
       if (er == hipSuccess) er = hipEventRecord(e[2], s);
       if (er == hipSuccess) er = launch_update(p, UPD_ITERATE, s);
       if (er == hipSuccess) er = hipEventRecord(e[3], s);
-      if (er == hipSuccess) er = launch_scatter(p, p->b.theta_new, true, s);
+      if (er == hipSuccess) er = stage_scatter(p, true, s);
       if (er == hipSuccess) er = hipEventRecord(e[4], s);
-      if (er == hipSuccess) er = launch_cgemm(p, false, EPI_PROJECT, p->b.s_r, p->b.s_i, p->b.p_r,
-                                              p->b.p_i, nullptr, nullptr, true, s);
+      if (er == hipSuccess) er = stage_adjoint(p, true, s);
       if (er == hipSuccess) er = hipEventRecord(e[5], s);
       if (er != hipSuccess) rc = fail(p, GSWMTP_E_HIP, "time_stages launch", er);
     }
