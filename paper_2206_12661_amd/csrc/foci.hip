@@ -1,8 +1,10 @@
-// Focal-plane stages of a GSW-MTP pass: the focus gather that completes the
-// forward matrix triple product at the foci only, the focus statistics and
-// generalised weight update of Algorithm 1, and the scatter of the updated
-// focal field back onto the reduced focal rows (every non-focus sample of the
-// reduced focal grid is zero in the inverse propagation).
+// Focal-plane stages of a GSW-MTP pass: the focus statistics and generalised
+// weight update of Algorithm 1 (fed by the focus gather fused into the
+// forward product), and the scatter of the updated focal field back onto the
+// reduced focal rows (every non-focus sample of the reduced focal grid is zero
+// in the inverse propagation).
+#include <cmath>
+
 #include "gswmtp_internal.h"
 
 namespace gswmtp {
@@ -10,48 +12,30 @@ namespace {
 
 constexpr int kUpdThreads = 1024;
 
-// Theta_n = sum_i L[ir_n][i] Wc[ic_n][i]: one wave per focus, lanes stride
-// over the Ck kept columns, fixed-order 64-lane tree at the end.
-__global__ __launch_bounds__(256) void focus_gather(
-    const float *__restrict__ lr, const float *__restrict__ li, const float *__restrict__ wr,
-    const float *__restrict__ wi, const int *__restrict__ ir, const int *__restrict__ ic,
-    float *__restrict__ theta, int nf, int Ck, int ld, float scale, const int *done) {
-  if (done && *done) return;
-  const int n = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (n >= nf) return;
-  const float *a_r = lr + (size_t)ir[n] * ld, *a_i = li + (size_t)ir[n] * ld;
-  const float *b_r = wr + (size_t)ic[n] * ld, *b_i = wi + (size_t)ic[n] * ld;
-  float sr = 0.f, si = 0.f;
-  for (int i = lane; i < Ck; i += 64) {
-    const float xr = a_r[i], xi = a_i[i], yr = b_r[i], yi = b_i[i];
-    sr = fmaf(xr, yr, fmaf(-xi, yi, sr));
-    si = fmaf(xr, yi, fmaf(xi, yr, si));
-  }
+// Deterministic reductions over one 1024-thread workgroup: an xor-shuffle
+// tree inside each wave, then the 16 wave results added in wave order by
+// every thread (one barrier; each call site uses its own LDS slots).
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    sr += __shfl_xor(sr, off, 64);
-    si += __shfl_xor(si, off, 64);
-  }
-  if (lane == 0) {
-    theta[2 * n] = sr * scale;
-    theta[2 * n + 1] = si * scale;
-  }
+  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+  return v;
 }
-
-// Deterministic block reductions (fixed thread-to-element map, fixed tree).
-template <typename T, typename Op>
-__device__ T block_reduce(T v, T *sh, Op op) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int s = kUpdThreads / 2; s > 0; s >>= 1) {
-    if (t < s) sh[t] = op(sh[t], sh[t + s]);
-    __syncthreads();
+template <int NV, typename Op>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double (*slot)[16], Op op) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    v[q] = wave_reduce(v[q], op);
+    if (lane == 0) slot[q][wave] = v[q];
   }
-  T r = sh[0];
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double r = slot[q][0];
+    for (int w = 1; w < kUpdThreads / 64; ++w) r = op(r, slot[q][w]);
+    v[q] = r;
+  }
 }
 
 struct Sum { __device__ double operator()(double a, double b) const { return a + b; } };
@@ -59,7 +43,10 @@ struct Max { __device__ double operator()(double a, double b) const { return a >
 struct Min { __device__ double operator()(double a, double b) const { return a < b ? a : b; } };
 
 struct UpdateArgs {
-  float *theta;            // [2 nf] forward field (read); written as float32
+  const float *gpart;      // [T][2 nf] fused-gather partials of the forward product
+  int T;                   // partials per focus
+  float scale;             // power-of-two factor undoing the pupil scale
+  float *theta;            // [2 nf] forward field (written)
   float *theta_new;        // [2 nf] updated focal field (scaled by a power of 2)
   float *intensity;        // [nf] |Theta|^2
   const double *target;    // [nf] raw target intensities
@@ -75,6 +62,7 @@ struct UpdateArgs {
 };
 
 // Algorithm 1 between the two propagations, for all foci, in one workgroup:
+//   Theta_n = sum of the forward product's gather partials (fixed order);
 //   I_n = |Theta_n|^2; accuracy xi from unit-sum intensities; efficiency and
 //   uniformity; termination test (before any update); weight update
 //   w <- w sqrt(t / max(i, 1e-30)); new focal field w sqrt(target) Theta/|Theta|
@@ -82,48 +70,65 @@ struct UpdateArgs {
 //   magnitude is in [0.5, 1) - the phase projection discards the scale.
 // All reductions are float64 in a fixed order.
 __global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
-  __shared__ double sh[kUpdThreads];
-  __shared__ int stop_flag;
+  __shared__ double slots[8][16];
   const int t = threadIdx.x;
   if (a.mode == UPD_ITERATE && a.ctrl[CTRL_DONE]) return;
 
-  double sI = 0.0;
+  double v1[1] = {0.0};
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 *gp = reinterpret_cast<const f2 *>(a.gpart);
   for (int n = t; n < a.nf; n += kUpdThreads) {
-    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
-    const double I = re * re + im * im;
+    float sr = 0.f, si = 0.f;
+#pragma unroll 8
+    for (int q = 0; q < a.T; ++q) {
+      const f2 v = gp[(size_t)q * a.nf + n];
+      sr += v.x;
+      si += v.y;
+    }
+    sr *= a.scale;
+    si *= a.scale;
+    a.theta[2 * n] = sr;
+    a.theta[2 * n + 1] = si;
+    const double I = (double)sr * sr + (double)si * si;
     a.intensity[n] = (float)I;
-    sI += I;
+    v1[0] += I;
   }
-  sI = block_reduce(sI, sh, Sum());
+  block_reduce<1>(v1, &slots[0], Sum());
+  const double sI = v1[0];
 
-  double d2 = 0.0, i2 = 0.0, rmax = -INFINITY, rmin = INFINITY;
   const double inv = sI > 0.0 ? 1.0 / sI : 0.0;
+  double v2[2] = {0.0, 0.0}, v3[2] = {-INFINITY, -INFINITY};   // sums; max r, max -r
   for (int n = t; n < a.nf; n += kUpdThreads) {
     const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
     const double in = (re * re + im * im) * inv;
     const double tn = a.tnorm[n];
-    d2 += (tn - in) * (tn - in);
-    i2 += in * in;
+    v2[0] += (tn - in) * (tn - in);
+    v2[1] += in * in;
     if (tn > 0.0) {
       const double r = in / tn;
-      rmax = r > rmax ? r : rmax;
-      rmin = r < rmin ? r : rmin;
+      v3[0] = r > v3[0] ? r : v3[0];
+      v3[1] = -r > v3[1] ? -r : v3[1];
     }
   }
-  d2 = block_reduce(d2, sh, Sum());
-  i2 = block_reduce(i2, sh, Sum());
-  rmax = block_reduce(rmax, sh, Max());
-  rmin = block_reduce(rmin, sh, Min());
+  block_reduce<2>(v2, &slots[1], Sum());
+  block_reduce<2>(v3, &slots[3], Max());
+  const double d2 = v2[0], i2 = v2[1], rmax = v3[0], rmin = -v3[1];
 
+  const double xi = i2 > 0.0 ? 1.0 - sqrt(d2) / sqrt(i2) : -INFINITY;
+  const double eta = sI / (a.n_ap * a.sum_a2);
+  const double U = (rmax + rmin) > 0.0 ? 1.0 - (rmax - rmin) / (rmax + rmin) : 0.0;
+  int stop = 0;
+  if (a.mode == UPD_ITERATE) {
+    if (!isfinite(sI)) stop = 1;
+    const double X = a.stats[ST_STOP];
+    if (X > 0.0 && xi > X) stop = 1;
+  }
+  __syncthreads();   // every thread has read ST_STOP and ctrl before thread 0 writes
   if (t == 0) {
-    const double xi = i2 > 0.0 ? 1.0 - sqrt(d2) / sqrt(i2) : -INFINITY;
-    const double eta = sI / (a.n_ap * a.sum_a2);
-    const double U = (rmax + rmin) > 0.0 ? 1.0 - (rmax - rmin) / (rmax + rmin) : 0.0;
     a.stats[ST_XI] = xi;
     a.stats[ST_ETA] = eta;
     a.stats[ST_U] = U;
     a.stats[ST_SUMI] = sI;
-    int stop = 0;
     if (a.mode == UPD_ITERATE) {
       const int h = a.ctrl[CTRL_HIST];
       double *e = a.hist + 3 * (h % kHistCap);
@@ -131,21 +136,14 @@ __global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
       e[1] = eta;
       e[2] = U;
       a.ctrl[CTRL_HIST] = h + 1;
-      if (!isfinite(sI)) {
-        a.ctrl[CTRL_NONFINITE] = 1;
-        stop = 1;
-      }
-      const double X = a.stats[ST_STOP];
-      if (X > 0.0 && xi > X) stop = 1;
+      if (!isfinite(sI)) a.ctrl[CTRL_NONFINITE] = 1;
       if (stop) a.ctrl[CTRL_DONE] = 1;
     }
-    stop_flag = stop;
   }
-  __syncthreads();
-  if (a.mode != UPD_ITERATE || stop_flag) return;
+  if (a.mode != UPD_ITERATE || stop) return;
 
   // weight update and new focal field
-  double amax = 0.0;
+  double v4[1] = {0.0};
   for (int n = t; n < a.nf; n += kUpdThreads) {
     const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
     const double I = re * re + im * im;
@@ -156,9 +154,10 @@ __global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
       a.w[n] = w;
     }
     const double amag = w * sqrt(a.target[n]);
-    amax = amag > amax ? amag : amax;
+    v4[0] = amag > v4[0] ? amag : v4[0];
   }
-  amax = block_reduce(amax, sh, Max());
+  block_reduce<1>(v4, &slots[5], Max());
+  const double amax = v4[0];
   int e = 0;
   if (amax > 0.0 && isfinite(amax)) e = -ilogb(amax) - 1;
   const double scale = ldexp(1.0, e);
@@ -175,6 +174,21 @@ __global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
     a.theta_new[2 * n + 1] = (float)(amag * pi);
   }
   if (t == 0) a.ctrl[CTRL_ITERS] += 1;
+}
+
+// Theta_n from the gather partials alone (operator-level forward calls).
+__global__ void gather_reduce(const float *__restrict__ gpart, int T, int nf, float scale,
+                              float *__restrict__ theta) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nf) return;
+  float sr = 0.f, si = 0.f;
+#pragma unroll 8
+  for (int q = 0; q < T; ++q) {
+    sr += gpart[2 * ((size_t)q * nf + n)];
+    si += gpart[2 * ((size_t)q * nf + n) + 1];
+  }
+  theta[2 * n] = sr * scale;
+  theta[2 * n + 1] = si * scale;
 }
 
 // Focal values for the phase gradient: g_n Theta_n.
@@ -293,19 +307,18 @@ hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, fl
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const gswmtp_plan *p, const float *lr, const float *li, float *theta,
-                         float scale, bool honour_done, hipStream_t s) {
-  const Dims &d = p->d;
-  const int *ir = d.axis == 0 ? p->b.iy : p->b.ix;
-  const int *ic = d.axis == 0 ? p->b.ix : p->b.iy;
-  hipLaunchKernelGGL(focus_gather, dim3((d.nf + 3) / 4), dim3(256), 0, s, lr, li, p->b.wc_r,
-                     p->b.wc_i, ir, ic, theta, d.nf, d.Ck, d.Cp, scale,
-                     honour_done ? p->b.ctrl + CTRL_DONE : nullptr);
+hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s) {
+  const int nf = p->d.nf;
+  hipLaunchKernelGGL(gather_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.gpart,
+                     p->d.Cp / p->sched_fwd.tile.bn, nf, scale, theta);
   return hipGetLastError();
 }
 
 hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
   UpdateArgs a{};
+  a.gpart = p->b.gpart;
+  a.T = p->d.Cp / p->sched_fwd.tile.bn;
+  a.scale = std::ldexp(1.f, -p->amp_exp);
   a.theta = p->b.theta;
   a.theta_new = p->b.theta_new;
   a.intensity = p->b.intensity;

@@ -20,9 +20,9 @@
 // Scheduling (256 CUs): full tiles are processed one workgroup each; when
 // the tile count leaves a short last round, those tail tiles are split along
 // K into `split` chunks so every CU gets about the same work.  Chunk partial
-// sums go to a workspace; the last chunk of a tile to finish (ticket from a
-// device-scope atomic counter, no waiting) adds the chunks in fixed order and
-// runs the epilogue, so results do not depend on arrival order.
+// sums go to a workspace; a second launch over the tail tiles adds each
+// tile's chunks in fixed order and runs the epilogue (the launch boundary
+// orders the workspace writes; no inter-workgroup fences or atomics).
 //
 // Epilogues: store C; project onto the amplitude constraint
 // (E = A C / |C|, phasor 1 where C = 0: the phase-only projection of
@@ -48,7 +48,8 @@ struct CgemmArgs {
   const float *__restrict__ ei;
   const int *done;                 // nullable: skip when *done != 0
   float *part;                     // split-K partial tiles
-  int *cnt;                        // split-K tickets, one per tail tile (zero between launches)
+  GatherCtx g;                     // EPI_GATHER
+  int phase;                       // 0: whole tiles and K chunks; 1: reduce chunks of tail tiles
   int lda, ldb, ldc;
   int M, N, K;
   int tiles_m;
@@ -84,10 +85,10 @@ __device__ __forceinline__ void epilogue(const CgemmArgs &a, v16f (&accR)[MB][NB
         const int n = nw + j * 32 + l32;
         const size_t o = (size_t)m * a.ldc + n;
         const float cr = accR[i][j][r], ci = accI[i][j][r];
-        if (EPI == EPI_STORE) {
+        if constexpr (EPI == EPI_STORE) {
           a.cr[o] = cr;
           a.ci[o] = ci;
-        } else if (EPI == EPI_PROJECT) {
+        } else if constexpr (EPI == EPI_PROJECT) {
           const float am = a.amp[o];
           const float mag2 = cr * cr + ci * ci;
           float pr = 0.f, pi = 0.f;
@@ -119,14 +120,22 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
   constexpr int NA = 2 * A4 / kThreads, NBL = 2 * B4 / kThreads;
   static_assert(2 * A4 % kThreads == 0 && 2 * B4 % kThreads == 0, "tile/thread mismatch");
 
-  __shared__ float sA[2][2][kBK * SA];
-  __shared__ float sB[2][2][kBK * SB];
-  __shared__ int s_last;
+  // operand stages [buf][plane][k][row]; the gather epilogue reuses the space
+  constexpr int A_F = 2 * 2 * kBK * SA, B_F = 2 * 2 * kBK * SB;
+  constexpr int G_F = EPI == EPI_GATHER ? gather_lds_bytes<BM, BN>() / 4 : 0;
+  __shared__ __attribute__((aligned(16))) float lds[A_F + B_F > G_F ? A_F + B_F : G_F];
+  float *const sA = lds;
+  float *const sB = lds + A_F;
+  constexpr int BUF_A = 2 * kBK * SA, BUF_B = 2 * kBK * SB;
 
   const int tid = threadIdx.x;
   const int KT = a.K / kBK;
   int t, kb, ke, tail = -1, chunk = 0;
-  if ((int)blockIdx.x < a.t_dp) {
+  if (a.phase == 1) {
+    tail = blockIdx.x;
+    t = a.t_dp + tail;
+    kb = ke = 0;
+  } else if ((int)blockIdx.x < a.t_dp) {
     t = xcd_tile(blockIdx.x, a.t_dp);
     kb = 0;
     ke = KT;
@@ -186,9 +195,9 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
     for (int s = 0; s < NBL; ++s)
       rb[s] = *reinterpret_cast<const v4f *>(gb[s] + (size_t)kb * stepB);
 #pragma unroll
-    for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&sA[0][0][la[s]]) = ra[s];
+    for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&sA[la[s]]) = ra[s];
 #pragma unroll
-    for (int s = 0; s < NBL; ++s) *reinterpret_cast<v4f *>(&sB[0][0][lb[s]]) = rb[s];
+    for (int s = 0; s < NBL; ++s) *reinterpret_cast<v4f *>(&sB[lb[s]]) = rb[s];
   }
   __syncthreads();
   for (int kt = kb; kt < ke; ++kt) {
@@ -202,8 +211,8 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
       for (int s = 0; s < NBL; ++s)
         rb[s] = *reinterpret_cast<const v4f *>(gb[s] + (size_t)(kt + 1) * stepB);
     }
-    const float *pa = &sA[buf][0][wm * WTM + l32];
-    const float *pb = &sB[buf][0][wn * WTN + l32];
+    const float *pa = sA + buf * BUF_A + wm * WTM + l32;
+    const float *pb = sB + buf * BUF_B + wn * WTN + l32;
     // MFMA operands of k pair p sit in slot p & 1; the next pair's operands
     // are read from LDS while the current pair's MFMAs run.  Lanes 0-31 take
     // k = 2p, lanes 32-63 take k = 2p + 1.
@@ -245,8 +254,8 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
         }
     }
     if (more) {
-      float *qa = &sA[buf ^ 1][0][0];
-      float *qb = &sB[buf ^ 1][0][0];
+      float *qa = sA + (buf ^ 1) * BUF_A;
+      float *qb = sB + (buf ^ 1) * BUF_B;
 #pragma unroll
       for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&qa[la[s]]) = ra[s];
 #pragma unroll
@@ -255,10 +264,10 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
     __syncthreads();
   }
 
-  if (tail >= 0) {
+  constexpr int unit = 2 * MB * NB * 16 * kThreads;
+  if (a.phase == 0 && tail >= 0) {
     // Partial tile of one K chunk in a thread-major layout (each store
     // instruction writes one float per lane, contiguous across lanes).
-    constexpr int unit = 2 * MB * NB * 16 * kThreads;
     float *pu = a.part + (size_t)(tail * a.split + chunk) * unit + tid;
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -270,20 +279,11 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
           pu[o] = accR[i][j][r];
           pu[o + kThreads] = accI[i][j][r];
         }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(a.cnt + tail, 1) == a.split - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    return;
+  }
+  if (a.phase == 1) {
+    // sum the tile's chunks in chunk order
     const float *pt = a.part + (size_t)tail * a.split * unit + tid;
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        accR[i][j] = v16f{0};
-        accI[i][j] = v16f{0};
-      }
     for (int c = 0; c < a.split; ++c) {
       const float *pc = pt + (size_t)c * unit;
 #pragma unroll
@@ -297,9 +297,11 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
             accI[i][j][r] += pc[o + kThreads];
           }
     }
-    if (tid == 0) a.cnt[tail] = 0;
   }
-  epilogue<MB, NB, EPI>(a, accR, accI, m0 + wm * WTM, n0 + wn * WTN, l32, h);
+  if constexpr (EPI == EPI_GATHER)
+    gather_epilogue<BM, BN>(a.g, accR, accI, lds, m0, n0, tid);
+  else
+    epilogue<MB, NB, EPI>(a, accR, accI, m0 + wm * WTM, n0 + wn * WTN, l32, h);
 }
 
 template <int BM, int BN, int EPI>
@@ -319,12 +321,27 @@ hipError_t launch_e(int bm, int bn, const CgemmArgs &args, int grid, hipStream_t
 
 }  // namespace
 
+GatherCtx gather_ctx(const gswmtp_plan *p) {
+  GatherCtx g;
+  g.part = p->b.gpart;
+  g.ptr = p->b.csr_ptr;
+  g.foci = p->b.csr_foci;
+  g.ir = p->d.axis == 0 ? p->b.iy : p->b.ix;
+  g.ic = p->d.axis == 0 ? p->b.ix : p->b.iy;
+  g.wcr = p->b.wc_r;
+  g.wci = p->b.wc_i;
+  g.nf = p->d.nf;
+  g.Ur = p->d.Ur;
+  g.Cp = p->d.Cp;
+  return g;
+}
+
 GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split) {
   GemmSched s;
   s.tile = tile;
   s.tiles_m = M / tile.bm;
   s.tiles = s.tiles_m * (N / tile.bn);
-  const int KT = K / kBK;
+  const int KT = K / tile.bk;
   const int q = s.tiles / cus, r = s.tiles % cus;
   s.t_dp = s.tiles;
   s.n_tail = 0;
@@ -365,19 +382,27 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
   a.er = er; a.ei = ei;
   a.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
   a.part = p->b.part;
-  a.cnt = p->b.tickets;
+  a.g = gather_ctx(p);
+  if (epi == EPI_GATHER && !forward) return hipErrorInvalidValue;
   if (a.M % sc.tile.bm || a.N % sc.tile.bn || a.K % kBK) return hipErrorInvalidValue;
   if (sc.tiles_m * sc.tile.bm != a.M || sc.tiles * sc.tile.bm * sc.tile.bn != a.M * a.N)
     return hipErrorInvalidValue;
   a.tiles_m = sc.tiles_m;
   a.t_dp = sc.t_dp;
   a.split = sc.split;
-  switch (epi) {
-    case EPI_STORE: return launch_e<EPI_STORE>(sc.tile.bm, sc.tile.bn, a, sc.grid, s);
-    case EPI_PROJECT: return launch_e<EPI_PROJECT>(sc.tile.bm, sc.tile.bn, a, sc.grid, s);
-    case EPI_GRAD: return launch_e<EPI_GRAD>(sc.tile.bm, sc.tile.bn, a, sc.grid, s);
+  for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
+    a.phase = phase;
+    const int grid = phase == 0 ? sc.grid : sc.n_tail;
+    hipError_t e = hipErrorInvalidValue;
+    switch (epi) {
+      case EPI_STORE: e = launch_e<EPI_STORE>(sc.tile.bm, sc.tile.bn, a, grid, s); break;
+      case EPI_PROJECT: e = launch_e<EPI_PROJECT>(sc.tile.bm, sc.tile.bn, a, grid, s); break;
+      case EPI_GRAD: e = launch_e<EPI_GRAD>(sc.tile.bm, sc.tile.bn, a, grid, s); break;
+      case EPI_GATHER: e = launch_e<EPI_GATHER>(sc.tile.bm, sc.tile.bn, a, grid, s); break;
+    }
+    if (e != hipSuccess) return e;
   }
-  return hipErrorInvalidValue;
+  return hipSuccess;
 }
 
 const char *cgemm_kernel_name(const gswmtp_plan *p, bool, int) {

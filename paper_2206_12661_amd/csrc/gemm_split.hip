@@ -14,14 +14,15 @@
 //   forward   A = Omega_r [Urp][Rp],      B^T = P^T [Cp][Rp]
 //   adjoint   A = Omega_r^H [Rp][Urp],    B^T = S^T [Cp][Urp]
 // so each MFMA operand fragment (8 consecutive k of one row) is one 16-byte
-// LDS read.  LDS rows hold 16 k (two 16-byte chunks); the chunk index is
-// XOR-swizzled with row bits 2 and 3 so fragment reads of 8 or 16 lanes hit
-// distinct banks.
+// LDS read.  A stage holds BK complex k (BK / 16 MFMA k-steps) in rows of
+// BK / 8 16-byte chunks; the chunk index is XOR-swizzled with row bits so
+// fragment reads of 8 or 16 consecutive rows hit distinct banks.
 //
 // Scheduling, split-K tail and in-order reduction as in the float32 kernel.
 // Epilogues: store float32 C (forward, for the focus gather); or project onto
 // the amplitude constraint and write the pupil field directly as the split
-// B^T planes of the next forward product.
+// B^T planes of the next forward product, transposed through LDS so every
+// store covers whole rows of P^T.
 #include "gswmtp_internal.h"
 
 namespace gswmtp {
@@ -34,7 +35,7 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 256;
-constexpr int kBK = 16;
+constexpr int kKStep = 16;     // k per MFMA instruction
 
 template <bool BF>
 __device__ __forceinline__ v16f mfma16(u4 a, u4 b, v16f c) {
@@ -46,13 +47,28 @@ __device__ __forceinline__ v16f mfma16(u4 a, u4 b, v16f c) {
                                                   __builtin_bit_cast(v8h, b), c, 0, 0, 0);
 }
 
+// Chunk swizzle of an LDS row of CH 16-byte chunks (a permutation of the
+// chunks of each row; conflict-free fragment reads for 32 and 64 banks).
+template <int CH>
+__device__ __forceinline__ int swz(int row) {
+  if constexpr (CH == 2) return ((row >> 2) ^ (row >> 3)) & 1;
+  return ((row >> 1) & 1) ^ (((row >> 2) & 1) << 1) ^ ((row >> 3) & 1);
+}
+
+template <int BM, int BN, int BK, int NT, int EPI>
+constexpr int split_lds_bytes() {
+  constexpr int ops = 2 * 2 * NT * (BM + BN) * (BK / 8) * 16;
+  constexpr int tr = EPI == EPI_PROJECT   ? 2 * NT * BN * (BM + 8) * 2
+                     : EPI == EPI_GATHER ? gather_lds_bytes<BM, BN>()
+                                         : 0;
+  return ops > tr ? ops : tr;
+}
+
 __device__ __forceinline__ int xcd_tile(int bid, int tiles) {
   const int xcd = bid & 7, local = bid >> 3;
   const int per = tiles >> 3, rem = tiles & 7;
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
-
-__device__ __forceinline__ int swz(int row) { return ((row >> 2) ^ (row >> 3)) & 1; }
 
 struct SplitArgs {
   const unsigned short *__restrict__ a;   // [2][NT][M][K]
@@ -67,28 +83,85 @@ struct SplitArgs {
   size_t pt_plane;
   const int *done;
   float *part;
-  int *cnt;
+  GatherCtx g;                            // EPI_GATHER
+  int phase;                              // 0: tiles and K chunks; 1: reduce tail chunks
   int tiles_m, t_dp, split;
 };
 
-template <int BM, int BN, bool BF, int NT, int EPI>
+// MFMA work of one LDS stage: BK / 16 k-steps over the wave's MB x NB blocks.
+template <int BM, int BN, int BK, bool BF, int NT>
+__device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
+                                          v16f (&accR)[BM / 64][BN / 64],
+                                          v16f (&accI)[BM / 64][BN / 64], int wm, int wn,
+                                          int l32, int h) {
+  constexpr int WTM = BM / 2, WTN = BN / 2, MB = WTM / 32, NB = WTN / 32;
+  constexpr int PL = 2 * NT, KS = BK / kKStep, CH = BK / 8;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    // fragments: lane (l32, h) reads row l32 of its block, k = 16 ks + 8 h .. + 7
+    u4 fa[MB][PL], fb[NB][PL], na[MB][NT];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+      const int row = wm * WTM + i * 32 + l32;
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl)
+        fa[i][pl] = qa[(pl * BM + row) * CH + ((2 * ks + h) ^ swz<CH>(row))];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) na[i][q] = fa[i][NT + q] ^ 0x80008000u;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int row = wn * WTN + j * 32 + l32;
+#pragma unroll
+      for (int pl = 0; pl < PL; ++pl)
+        fb[j][pl] = qb[(pl * BN + row) * CH + ((2 * ks + h) ^ swz<CH>(row))];
+    }
+    // term pairs (ta, tb) with ta + tb < NT, small terms first
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int s = NT - 1; s >= 0; --s)
+#pragma unroll
+          for (int ta = 0; ta <= s; ++ta) {
+            const int tb = s - ta;
+            accR[i][j] = mfma16<BF>(fa[i][ta], fb[j][tb], accR[i][j]);
+            accR[i][j] = mfma16<BF>(na[i][ta], fb[j][NT + tb], accR[i][j]);
+            accI[i][j] = mfma16<BF>(fa[i][ta], fb[j][NT + tb], accI[i][j]);
+            accI[i][j] = mfma16<BF>(fa[i][NT + ta], fb[j][tb], accI[i][j]);
+          }
+  }
+}
+
+template <int BM, int BN, int BK, bool BF, int NT, int EPI>
 __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
   if (a.done && *a.done) return;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
   constexpr int PL = 2 * NT;                     // planes per operand
-  constexpr int LA = PL * BM * 2, LB = PL * BN * 2;   // 16-byte chunks per stage
+  constexpr int KS = BK / kKStep;                // MFMA k-steps per stage
+  constexpr int CH = BK / 8;                     // 16-byte chunks per row and stage
+  constexpr int LA = PL * BM * CH, LB = PL * BN * CH;   // chunks loaded per stage
   constexpr int NA = LA / kThreads, NBL = LB / kThreads;
   static_assert(LA % kThreads == 0 && LB % kThreads == 0, "tile/thread mismatch");
+  constexpr int SA_SZ = LA, SB_SZ = LB;
+  // epilogue transpose tile: [plane][n][m] 16-bit with rows padded by 8 elements
+  constexpr int TP = BM + 8;
+  constexpr int L_SZ = (split_lds_bytes<BM, BN, BK, NT, EPI>() + 15) / 16;
 
-  __shared__ u4 sA[2][LA];
-  __shared__ u4 sB[2][LB];
-  __shared__ int s_last;
+  __shared__ u4 lds[L_SZ];
+  u4 *sA = lds;                         // [2][SA_SZ]
+  u4 *sB = lds + 2 * SA_SZ;             // [2][SB_SZ]
 
   const int tid = threadIdx.x;
-  const int KT = a.K / kBK;
+  const int KT = a.K / BK;
   int t, kb, ke, tail = -1, chunk = 0;
-  if ((int)blockIdx.x < a.t_dp) {
+  if (a.phase == 1) {
+    tail = blockIdx.x;
+    t = a.t_dp + tail;
+    kb = ke = 0;
+  } else if ((int)blockIdx.x < a.t_dp) {
     t = xcd_tile(blockIdx.x, a.t_dp);
     kb = 0;
     ke = KT;
@@ -115,90 +188,66 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
       accI[i][j] = v16f{0};
     }
 
-  // staging: chunk id = (plane * rows + row) * 2 + c (16 bytes, 8 k values)
+  // staging: chunk id = (plane * rows + row) * CH + c (16 bytes, 8 k values)
   const unsigned short *ga[NA];
   const unsigned short *gb[NBL];
   int la[NA], lb[NBL];
 #pragma unroll
   for (int s = 0; s < NA; ++s) {
     const int id = tid + kThreads * s;
-    const int c = id & 1, row = (id >> 1) % BM, plane = (id >> 1) / BM;
+    const int c = id % CH, row = (id / CH) % BM, plane = id / (CH * BM);
     ga[s] = a.a + (size_t)plane * a.a_plane + (size_t)(m0 + row) * a.K + 8 * c;
-    la[s] = (plane * BM + row) * 2 + (c ^ swz(row));
+    la[s] = (plane * BM + row) * CH + (c ^ swz<CH>(row));
   }
 #pragma unroll
   for (int s = 0; s < NBL; ++s) {
     const int id = tid + kThreads * s;
-    const int c = id & 1, row = (id >> 1) % BN, plane = (id >> 1) / BN;
+    const int c = id % CH, row = (id / CH) % BN, plane = id / (CH * BN);
     gb[s] = a.b + (size_t)plane * a.b_plane + (size_t)(n0 + row) * a.K + 8 * c;
-    lb[s] = (plane * BN + row) * 2 + (c ^ swz(row));
+    lb[s] = (plane * BN + row) * CH + (c ^ swz<CH>(row));
   }
-  u4 ra[NA], rb[NBL];
+  // Two stages in flight: while stage kt is multiplied out of LDS buffer
+  // (kt - kb) & 1, the register set of stage kt + 1 waits to be written to
+  // the other buffer and the loads of stage kt + 2 are issued into the set
+  // just freed.
+  u4 r0a[NA], r0b[NBL], r1a[NA], r1b[NBL];
+#define LOAD_STAGE(RA, RB, KT)                                                         \
+  do {                                                                                 \
+    _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) RA[s_] =                         \
+        *reinterpret_cast<const u4 *>(ga[s_] + (KT) * BK);                              \
+    _Pragma("unroll") for (int s_ = 0; s_ < NBL; ++s_) RB[s_] =                        \
+        *reinterpret_cast<const u4 *>(gb[s_] + (KT) * BK);                              \
+  } while (0)
+#define STORE_STAGE(RA, RB, BUF)                                                       \
+  do {                                                                                 \
+    _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) sA[(BUF) * SA_SZ + la[s_]] = RA[s_]; \
+    _Pragma("unroll") for (int s_ = 0; s_ < NBL; ++s_) sB[(BUF) * SB_SZ + lb[s_]] = RB[s_]; \
+  } while (0)
   if (kb < ke) {
-#pragma unroll
-    for (int s = 0; s < NA; ++s) ra[s] = *reinterpret_cast<const u4 *>(ga[s] + kb * kBK);
-#pragma unroll
-    for (int s = 0; s < NBL; ++s) rb[s] = *reinterpret_cast<const u4 *>(gb[s] + kb * kBK);
-#pragma unroll
-    for (int s = 0; s < NA; ++s) sA[0][la[s]] = ra[s];
-#pragma unroll
-    for (int s = 0; s < NBL; ++s) sB[0][lb[s]] = rb[s];
+    LOAD_STAGE(r0a, r0b, kb);
+    STORE_STAGE(r0a, r0b, 0);
   }
+  if (kb + 1 < ke) LOAD_STAGE(r1a, r1b, kb + 1);
   __syncthreads();
 
-  for (int kt = kb; kt < ke; ++kt) {
-    const int buf = (kt - kb) & 1;
-    const bool more = kt + 1 < ke;
-    if (more) {
-#pragma unroll
-      for (int s = 0; s < NA; ++s)
-        ra[s] = *reinterpret_cast<const u4 *>(ga[s] + (kt + 1) * kBK);
-#pragma unroll
-      for (int s = 0; s < NBL; ++s)
-        rb[s] = *reinterpret_cast<const u4 *>(gb[s] + (kt + 1) * kBK);
-    }
-    // fragments: lane (l32, h) reads row l32 of its block, k = 8h .. 8h + 7
-    u4 fa[MB][PL], fb[NB][PL], na[MB][NT];
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-      const int row = wm * WTM + i * 32 + l32;
-#pragma unroll
-      for (int pl = 0; pl < PL; ++pl) fa[i][pl] = sA[buf][(pl * BM + row) * 2 + (h ^ swz(row))];
-#pragma unroll
-      for (int q = 0; q < NT; ++q) na[i][q] = fa[i][NT + q] ^ 0x80008000u;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int row = wn * WTN + j * 32 + l32;
-#pragma unroll
-      for (int pl = 0; pl < PL; ++pl) fb[j][pl] = sB[buf][(pl * BN + row) * 2 + (h ^ swz(row))];
-    }
-    // term pairs (ta, tb) with ta + tb < NT
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int s = NT - 1; s >= 0; --s)          // small terms first
-#pragma unroll
-          for (int ta = 0; ta <= s; ++ta) {
-            const int tb = s - ta;
-            accR[i][j] = mfma16<BF>(fa[i][ta], fb[j][tb], accR[i][j]);
-            accR[i][j] = mfma16<BF>(na[i][ta], fb[j][NT + tb], accR[i][j]);
-            accI[i][j] = mfma16<BF>(fa[i][ta], fb[j][NT + tb], accI[i][j]);
-            accI[i][j] = mfma16<BF>(fa[i][NT + ta], fb[j][tb], accI[i][j]);
-          }
-    if (more) {
-#pragma unroll
-      for (int s = 0; s < NA; ++s) sA[buf ^ 1][la[s]] = ra[s];
-#pragma unroll
-      for (int s = 0; s < NBL; ++s) sB[buf ^ 1][lb[s]] = rb[s];
-    }
+  for (int kt = kb; kt < ke; kt += 2) {
+    if (kt + 2 < ke) LOAD_STAGE(r0a, r0b, kt + 2);
+    stage_mma<BM, BN, BK, BF, NT>(sA, sB, accR, accI, wm, wn, l32, h);
+    if (kt + 1 < ke) STORE_STAGE(r1a, r1b, 1);
+    __syncthreads();
+    if (kt + 1 >= ke) break;
+    if (kt + 3 < ke) LOAD_STAGE(r1a, r1b, kt + 3);
+    stage_mma<BM, BN, BK, BF, NT>(sA + SA_SZ, sB + SB_SZ, accR, accI, wm, wn, l32, h);
+    if (kt + 2 < ke) STORE_STAGE(r0a, r0b, 0);
     __syncthreads();
   }
+#undef LOAD_STAGE
+#undef STORE_STAGE
 
-  if (tail >= 0) {
-    constexpr int unit = 2 * MB * NB * 16 * kThreads;
+  constexpr int unit = 2 * MB * NB * 16 * kThreads;
+  if (a.phase == 0 && tail >= 0) {
+    // Partial tile of one K chunk in a thread-major layout (each store
+    // instruction writes one float per lane, contiguous across lanes).
     float *pu = a.part + (size_t)(tail * a.split + chunk) * unit + tid;
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -210,20 +259,11 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
           pu[o] = accR[i][j][r];
           pu[o + kThreads] = accI[i][j][r];
         }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(a.cnt + tail, 1) == a.split - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+    return;
+  }
+  if (a.phase == 1) {
+    // sum the tile's chunks in chunk order
     const float *pt = a.part + (size_t)tail * a.split * unit + tid;
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        accR[i][j] = v16f{0};
-        accI[i][j] = v16f{0};
-      }
     for (int c = 0; c < a.split; ++c) {
       const float *pc = pt + (size_t)c * unit;
 #pragma unroll
@@ -237,31 +277,43 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
             accI[i][j][r] += pc[o + kThreads];
           }
     }
-    if (tid == 0) a.cnt[tail] = 0;
   }
 
   // epilogue; accumulator item r of lane (l32, h): row 8 (r/4) + 4 h + r % 4, column l32
+  if constexpr (EPI == EPI_GATHER) {
+    gather_epilogue<BM, BN>(a.g, accR, accI, reinterpret_cast<float *>(lds), m0, n0, tid);
+  } else if constexpr (EPI == EPI_STORE) {
 #pragma unroll
-  for (int i = 0; i < MB; ++i)
+    for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int n = n0 + wn * WTN + j * 32 + l32;
+      for (int j = 0; j < NB; ++j) {
+        const int n = n0 + wn * WTN + j * 32 + l32;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int mb = m0 + wm * WTM + i * 32 + 8 * g + 4 * h;
-        if (EPI == EPI_STORE) {
+        for (int r = 0; r < 16; ++r) {
+          const size_t o = (size_t)(m0 + wm * WTM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3)) *
+                               a.ldc + n;
+          a.cr[o] = accR[i][j][r];
+          a.ci[o] = accI[i][j][r];
+        }
+      }
+  } else if constexpr (EPI == EPI_PROJECT) {
+    // project, split into terms, transpose the tile through LDS, then write
+    // whole rows of P^T [plane][n][m0 .. m0 + BM)
+    unsigned short *tt = reinterpret_cast<unsigned short *>(lds);
+    __syncthreads();   // operand stages are no longer read
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const size_t o = (size_t)(mb + q) * a.ldc + n;
-            a.cr[o] = accR[i][j][4 * g + q];
-            a.ci[o] = accI[i][j][4 * g + q];
-          }
-        } else {
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int nl = wn * WTN + j * 32 + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int ml = wm * WTM + i * 32 + 8 * g + 4 * h;
           unsigned short tr[NT][4], ti[NT][4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const float cr = accR[i][j][4 * g + q], ci = accI[i][j][4 * g + q];
-            const float am = a.amp[(size_t)(mb + q) * a.ldc + n];
+            const float am = a.amp[(size_t)(m0 + ml + q) * a.ldc + n0 + nl];
             const float mag2 = cr * cr + ci * ci;
             float pr = 0.f, pi = 0.f;
             if (am > 0.f) {
@@ -282,38 +334,63 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
                            (unsigned)tr[s][2] | ((unsigned)tr[s][3] << 16)};
             const u2 vi = {(unsigned)ti[s][0] | ((unsigned)ti[s][1] << 16),
                            (unsigned)ti[s][2] | ((unsigned)ti[s][3] << 16)};
-            *reinterpret_cast<u2 *>(a.pt + (size_t)s * a.pt_plane + (size_t)n * a.M + mb) = vr;
-            *reinterpret_cast<u2 *>(a.pt + (size_t)(NT + s) * a.pt_plane + (size_t)n * a.M + mb) =
-                vi;
+            *reinterpret_cast<u2 *>(tt + ((size_t)s * BN + nl) * TP + ml) = vr;
+            *reinterpret_cast<u2 *>(tt + ((size_t)(NT + s) * BN + nl) * TP + ml) = vi;
           }
         }
       }
+    __syncthreads();
+    constexpr int RC = BM / 8;                  // 16-byte chunks per row
+    constexpr int NCH = PL * BN * RC;
+    static_assert(NCH % kThreads == 0, "epilogue chunking");
+#pragma unroll
+    for (int s = 0; s < NCH / kThreads; ++s) {
+      const int id = tid + kThreads * s;
+      const int c = id % RC, nl = (id / RC) % BN, pl = id / (RC * BN);
+      const u4 v = *reinterpret_cast<const u4 *>(tt + ((size_t)pl * BN + nl) * TP + 8 * c);
+      *reinterpret_cast<u4 *>(a.pt + (size_t)pl * a.pt_plane + (size_t)(n0 + nl) * a.M + m0 +
+                              8 * c) = v;
     }
+  }
 }
 
-template <int BM, int BN, bool BF, int NT, int EPI>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI>
 hipError_t launch_t(const SplitArgs &args, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BF, NT, EPI>), dim3(grid), dim3(kThreads), 0, s,
-                     args);
+  hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI>), dim3(grid), dim3(kThreads), 0,
+                     s, args);
   return hipGetLastError();
 }
 
+template <int BM, int BN, int BK, bool BF, int NT, int EPI>
+hipError_t launch_fit(const SplitArgs &args, int grid, hipStream_t s) {
+  if constexpr (split_lds_bytes<BM, BN, BK, NT, EPI>() <= 160 * 1024)
+    return launch_t<BM, BN, BK, BF, NT, EPI>(args, grid, s);
+  return hipErrorInvalidValue;
+}
+
 template <bool BF, int NT, int EPI>
-hipError_t launch_e(int bm, int bn, const SplitArgs &args, int grid, hipStream_t s) {
-  if (bm == 64 && bn == 64) return launch_t<64, 64, BF, NT, EPI>(args, grid, s);
-  if (bm == 128 && bn == 64) return launch_t<128, 64, BF, NT, EPI>(args, grid, s);
-  if (bm == 64 && bn == 128) return launch_t<64, 128, BF, NT, EPI>(args, grid, s);
-  if (bm == 128 && bn == 128) return launch_t<128, 128, BF, NT, EPI>(args, grid, s);
+hipError_t launch_e(const GemmTile &tl, const SplitArgs &args, int grid, hipStream_t s) {
+  if (tl.bk == 32) {
+    if (tl.bm == 64 && tl.bn == 64) return launch_fit<64, 64, 32, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 128 && tl.bn == 64) return launch_fit<128, 64, 32, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 64 && tl.bn == 128) return launch_fit<64, 128, 32, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 128 && tl.bn == 128) return launch_fit<128, 128, 32, BF, NT, EPI>(args, grid, s);
+  } else if (tl.bk == 16) {
+    if (tl.bm == 64 && tl.bn == 64) return launch_fit<64, 64, 16, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 128 && tl.bn == 64) return launch_fit<128, 64, 16, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 64 && tl.bn == 128) return launch_fit<64, 128, 16, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 128 && tl.bn == 128) return launch_fit<128, 128, 16, BF, NT, EPI>(args, grid, s);
+  }
   return hipErrorInvalidValue;
 }
 
 template <int EPI>
-hipError_t launch_p(int precision, int bm, int bn, const SplitArgs &args, int grid,
+hipError_t launch_p(int precision, const GemmTile &tl, const SplitArgs &args, int grid,
                     hipStream_t s) {
   switch (precision) {
-    case GSWMTP_BF16X3: return launch_e<true, 2, EPI>(bm, bn, args, grid, s);
-    case GSWMTP_FP16X3: return launch_e<false, 2, EPI>(bm, bn, args, grid, s);
-    case GSWMTP_BF16X6: return launch_e<true, 3, EPI>(bm, bn, args, grid, s);
+    case GSWMTP_BF16X3: return launch_e<true, 2, EPI>(tl, args, grid, s);
+    case GSWMTP_FP16X3: return launch_e<false, 2, EPI>(tl, args, grid, s);
+    case GSWMTP_BF16X6: return launch_e<true, 3, EPI>(tl, args, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -348,18 +425,26 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
   a.pt_plane = (size_t)d.Cp * d.Rp;
   a.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
   a.part = p->b.part;
-  a.cnt = p->b.tickets;
-  if (nt < 2 || a.M % sc.tile.bm || a.N % sc.tile.bn || a.K % kBK) return hipErrorInvalidValue;
+  a.g = gather_ctx(p);
+  if (nt < 2 || a.M % sc.tile.bm || a.N % sc.tile.bn || a.K % sc.tile.bk)
+    return hipErrorInvalidValue;
   if (sc.tiles_m * sc.tile.bm != a.M || sc.tiles * sc.tile.bm * sc.tile.bn != a.M * a.N)
     return hipErrorInvalidValue;
+  if (epi != EPI_STORE && epi != EPI_PROJECT && epi != EPI_GATHER) return hipErrorInvalidValue;
   if (epi == EPI_PROJECT && (forward || !pt_out)) return hipErrorInvalidValue;
+  if (epi == EPI_GATHER && !forward) return hipErrorInvalidValue;
   a.tiles_m = sc.tiles_m;
   a.t_dp = sc.t_dp;
   a.split = sc.split;
-  if (epi == EPI_STORE) return launch_p<EPI_STORE>(p->precision, sc.tile.bm, sc.tile.bn, a, sc.grid, s);
-  if (epi == EPI_PROJECT)
-    return launch_p<EPI_PROJECT>(p->precision, sc.tile.bm, sc.tile.bn, a, sc.grid, s);
-  return hipErrorInvalidValue;
+  for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
+    a.phase = phase;
+    const int grid = phase == 0 ? sc.grid : sc.n_tail;
+    const hipError_t e = epi == EPI_STORE    ? launch_p<EPI_STORE>(p->precision, sc.tile, a, grid, s)
+                         : epi == EPI_GATHER ? launch_p<EPI_GATHER>(p->precision, sc.tile, a, grid, s)
+                                             : launch_p<EPI_PROJECT>(p->precision, sc.tile, a, grid, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace gswmtp

@@ -11,10 +11,10 @@
 //     OmT  [Rp][Urp]  Omega_r^T: OmT[j][a] = exp(-2 pi i s_r ur_j R_a)
 //     OmC  [Urp][Rp]  conj(Omega_r):  OmC[a][j] = conj(OmT[j][a])
 //     Wc   [Uc][Cp]   Omega_c^T: Wc[b][i] = exp(-2 pi i s_c uc_i C_b)
-//     L    [Urp][Cp]  L = Omega_r P              (forward product)
 //     S    [Urp][Cp]  scatter of the new focal field onto its r rows
-//   One pass:  L = OmT^T P;  Theta_n = sum_i L[ir_n][i] Wc[ic_n][i];
-//   focus update;  S[a][i] = sum_{n: ir_n = a} Theta'_n conj(Wc[ic_n][i]);
+//   One pass:  L = OmT^T P with Theta_n = sum_i L[ir_n][i] Wc[ic_n][i] formed
+//   in the product's epilogue (L is never stored); focus update;
+//   S[a][i] = sum_{n: ir_n = a} Theta'_n conj(Wc[ic_n][i]);
 //   P = amp * normalise(OmC^T S).
 #pragma once
 
@@ -66,7 +66,7 @@ struct Bufs {
   float *omt_r = nullptr, *omt_i = nullptr, *omc_r = nullptr, *omc_i = nullptr;
   float *wc_r = nullptr, *wc_i = nullptr;
   float *amp = nullptr, *p_r = nullptr, *p_i = nullptr;
-  float *l_r = nullptr, *l_i = nullptr, *s_r = nullptr, *s_i = nullptr;
+  float *s_r = nullptr, *s_i = nullptr;
   float *x_r = nullptr, *x_i = nullptr;  // operator-call scratch pupil
   float *theta = nullptr, *theta_new = nullptr;   // interleaved [2*nf]
   float *intensity = nullptr;            // [nf]
@@ -74,7 +74,7 @@ struct Bufs {
   int *ctrl = nullptr;
   float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
   float *part = nullptr;                 // split-K partial tiles (shared by both products)
-  int *tickets = nullptr;                // split-K tickets
+  float *gpart = nullptr;                // fused-gather partials [tiles_n][nf] complex
   // split-precision modes: 16-bit term planes, k-contiguous ([re/im][term][row][K])
   unsigned short *as_f = nullptr;        // Omega_r            [2][NT][Urp][Rp]
   unsigned short *as_b = nullptr;        // Omega_r^H          [2][NT][Rp][Urp]
@@ -128,7 +128,7 @@ __device__ __forceinline__ float join_terms(bool bf, int nt, const unsigned shor
   return v;
 }
 
-struct GemmTile { int bm = 64, bn = 64; };
+struct GemmTile { int bm = 64, bn = 64, bk = 16; };   // complex tile M x N, K per stage
 
 // Launch schedule of one complex product: t_dp whole tiles, then n_tail tiles
 // split along K into `split` chunks (grid = t_dp + n_tail * split).
@@ -139,6 +139,106 @@ struct GemmSched {
   int grid = 0;
   size_t part_floats = 0;
 };
+
+typedef float gsw_v16f __attribute__((ext_vector_type(16)));
+
+// Where the fused focus gather reads and writes.
+struct GatherCtx {
+  float *part;                 // [tiles_n][nf] interleaved complex partial sums
+  const int *ptr;              // CSR row pointers over the reduced r rows [Ur + 1]
+  const int *foci;             // foci sorted by (ir, ic)
+  const int *ir, *ic;          // reduced-grid row / column of every focus
+  const float *wcr, *wci;      // Omega_c^T planes [Uc][Cp]
+  int nf, Ur, Cp;
+};
+
+// Focus gather fused into the forward product's epilogue (the second
+// product of Eq. 2, formed only at the foci).  The BM x BN complex tile of
+// L = Omega_r P held in the accumulators is staged in LDS; then for each
+// focus whose reduced row lies in the tile, one wave forms
+//   sum_{n in tile} L[ir][n] Wc[ic][n]
+// (per-lane partial sums, fixed xor-shuffle tree) and writes it as partial
+// number n0 / BN of that focus.  Accumulator item r of lane (l32, h) of a
+// 32x32 block holds row 8 (r/4) + 4 h + r % 4, column l32.
+template <int BM, int BN>
+__device__ __forceinline__ void gather_epilogue(const GatherCtx &g,
+                                                const gsw_v16f (&accR)[BM / 64][BN / 64],
+                                                const gsw_v16f (&accI)[BM / 64][BN / 64],
+                                                float *lds, int m0, int n0, int tid) {
+  constexpr int MB = BM / 64, NB = BN / 64, WTM = BM / 2, WTN = BN / 2, LD = BN + 1;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1, l32 = lane & 31, h = lane >> 5;
+  float *tr = lds, *ti = lds + BM * LD;
+  __syncthreads();   // operand stages are no longer read
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ml = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int nl = wn * WTN + j * 32 + l32;
+        tr[ml * LD + nl] = accR[i][j][r];
+        ti[ml * LD + nl] = accI[i][j][r];
+      }
+  __syncthreads();
+  const int r0 = m0 < g.Ur ? m0 : g.Ur, r1 = m0 + BM < g.Ur ? m0 + BM : g.Ur;
+  const int p0 = g.ptr[r0], p1 = g.ptr[r1];
+  float *out = g.part + 2 * (size_t)(n0 / BN) * g.nf;
+  // four foci per wave iteration so their operand loads are in flight together
+  constexpr int FB = 4;
+  for (int pb = p0 + wave * FB; pb < p1; pb += 4 * FB) {
+    int f[FB], a[FB];
+    size_t wrow[FB];
+#pragma unroll
+    for (int q = 0; q < FB; ++q) {
+      const int pp = pb + q < p1 ? pb + q : p1 - 1;
+      f[q] = g.foci[pp];
+    }
+#pragma unroll
+    for (int q = 0; q < FB; ++q) {
+      a[q] = g.ir[f[q]] - m0;
+      wrow[q] = (size_t)g.ic[f[q]] * g.Cp + n0;
+    }
+    float sr[FB], si[FB];
+#pragma unroll
+    for (int q = 0; q < FB; ++q) sr[q] = si[q] = 0.f;
+#pragma unroll
+    for (int nl0 = 0; nl0 < BN; nl0 += 64) {
+      const int nl = nl0 + lane;
+      float wr[FB], wi[FB];
+#pragma unroll
+      for (int q = 0; q < FB; ++q) {
+        wr[q] = g.wcr[wrow[q] + nl];
+        wi[q] = g.wci[wrow[q] + nl];
+      }
+#pragma unroll
+      for (int q = 0; q < FB; ++q) {
+        const float lr = tr[a[q] * LD + nl], li = ti[a[q] * LD + nl];
+        sr[q] = fmaf(lr, wr[q], fmaf(-li, wi[q], sr[q]));
+        si[q] = fmaf(lr, wi[q], fmaf(li, wr[q], si[q]));
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int q = 0; q < FB; ++q) {
+        sr[q] += __shfl_xor(sr[q], off, 64);
+        si[q] += __shfl_xor(si[q], off, 64);
+      }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < FB; ++q)
+        if (pb + q < p1) {
+          out[2 * f[q]] = sr[q];
+          out[2 * f[q] + 1] = si[q];
+        }
+    }
+  }
+}
+
+template <int BM, int BN>
+constexpr int gather_lds_bytes() { return 2 * BM * (BN + 1) * 4; }
 
 }  // namespace gswmtp
 
@@ -171,8 +271,8 @@ namespace gswmtp {
 hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float *br,
                         const float *bi, float *cr, float *ci, const float *er,
                         const float *ei, bool honour_done, hipStream_t s);
-hipError_t launch_gather(const gswmtp_plan *p, const float *lr, const float *li, float *theta,
-                         float scale, bool honour_done, hipStream_t s);
+hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s);
+GatherCtx gather_ctx(const gswmtp_plan *p);
 hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
                               const unsigned short *bt, float *cr, float *ci,
                               unsigned short *pt_out, bool honour_done, hipStream_t s);
@@ -185,7 +285,9 @@ hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool hon
 const char *cgemm_kernel_name(const gswmtp_plan *p, bool forward, int epi);
 GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split);
 
-enum { EPI_STORE = 0, EPI_PROJECT = 1, EPI_GRAD = 2 };
+// Product epilogues: store C; project onto the amplitude constraint; phase
+// gradient; focus gather (forward product only, C never stored).
+enum { EPI_STORE = 0, EPI_PROJECT = 1, EPI_GRAD = 2, EPI_GATHER = 3 };
 enum { UPD_ITERATE = 0, UPD_STATS = 1, UPD_GRAD = 2 };
 
 }  // namespace gswmtp

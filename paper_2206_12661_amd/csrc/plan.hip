@@ -655,17 +655,24 @@ void free_plan(gswmtp_plan *p) {
   delete p;
 }
 
-// GEMM tile per product: 64 x 64 complex tiles (four waves of 32 x 32),
-// which keeps three workgroups per CU resident; GSWMTP_TILE=BMxBN overrides.
-GemmTile choose_tile(int M, int N) {
+// GEMM tile per product.  float32: 64 x 64 complex tiles, 16 k per stage
+// (three workgroups per CU resident).  Split modes: 64 x 64 tiles with 32 k
+// per stage (16-bit operands need longer stages to cover load latency).
+// GSWMTP_TILE=BMxBN[xBK] overrides (BK only for split modes).
+GemmTile choose_tile(int M, int N, bool split) {
+  GemmTile t{64, 64, split ? 32 : 16};
   const char *env = std::getenv("GSWMTP_TILE");
   if (env) {
-    int bm = 0, bn = 0;
-    if (std::sscanf(env, "%dx%d", &bm, &bn) == 2 && (bm == 64 || bm == 128) &&
-        (bn == 64 || bn == 128) && M % bm == 0 && N % bn == 0)
-      return GemmTile{bm, bn};
+    int bm = 0, bn = 0, bk = 0;
+    const int n = std::sscanf(env, "%dx%dx%d", &bm, &bn, &bk);
+    if (n >= 2 && (bm == 64 || bm == 128) && (bn == 64 || bn == 128) && M % bm == 0 &&
+        N % bn == 0) {
+      t.bm = bm;
+      t.bn = bn;
+      if (split && n == 3 && (bk == 16 || bk == 32)) t.bk = bk;
+    }
   }
-  return GemmTile{64, 64};
+  return t;
 }
 
 bool split_enabled() {
@@ -676,14 +683,13 @@ bool split_enabled() {
 bool is_split(const gswmtp_plan *p) { return split_terms_of(p->precision) > 0; }
 
 // Stages of one pass, in either arithmetic.
+// Forward product with the focus gather fused into its epilogue (partials
+// reduced by the focus update).
 hipError_t stage_forward(gswmtp_plan *p, bool done, hipStream_t s) {
   if (is_split(p))
-    return launch_cgemm_split(p, true, EPI_STORE, p->b.ps, p->b.l_r, p->b.l_i, nullptr, done, s);
-  return launch_cgemm(p, true, EPI_STORE, p->b.p_r, p->b.p_i, p->b.l_r, p->b.l_i, nullptr,
+    return launch_cgemm_split(p, true, EPI_GATHER, p->b.ps, nullptr, nullptr, nullptr, done, s);
+  return launch_cgemm(p, true, EPI_GATHER, p->b.p_r, p->b.p_i, nullptr, nullptr, nullptr,
                       nullptr, done, s);
-}
-hipError_t stage_gather(gswmtp_plan *p, float *theta, bool done, hipStream_t s) {
-  return launch_gather(p, p->b.l_r, p->b.l_i, theta, std::ldexp(1.f, -p->amp_exp), done, s);
 }
 hipError_t stage_scatter(gswmtp_plan *p, bool done, hipStream_t s) {
   if (is_split(p)) return launch_scatter_split(p, p->b.theta_new, 1.f, done, s);
@@ -700,7 +706,6 @@ hipError_t stage_adjoint(gswmtp_plan *p, bool done, hipStream_t s) {
 hipError_t enqueue_pass(gswmtp_plan *p, hipStream_t s) {
   hipError_t e;
   if ((e = stage_forward(p, true, s)) != hipSuccess) return e;
-  if ((e = stage_gather(p, p->b.theta, true, s)) != hipSuccess) return e;
   if ((e = launch_update(p, UPD_ITERATE, s)) != hipSuccess) return e;
   if ((e = stage_scatter(p, true, s)) != hipSuccess) return e;
   return stage_adjoint(p, true, s);
@@ -711,7 +716,6 @@ hipError_t ensure_forward(gswmtp_plan *p) {
   if (p->fwd_valid) return hipSuccess;
   hipError_t e;
   if ((e = stage_forward(p, false, p->stream)) != hipSuccess) return e;
-  if ((e = stage_gather(p, p->b.theta, false, p->stream)) != hipSuccess) return e;
   if ((e = launch_update(p, UPD_STATS, p->stream)) != hipSuccess) return e;
   p->fwd_valid = true;
   return hipSuccess;
@@ -904,11 +908,13 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   D.Rp = (int)round_up(D.Rk, kPadRows);
   D.Cp = (int)round_up(D.Ck, kPadCols);
   D.Urp = (int)round_up(D.Ur, kPadRows);
-  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp, choose_tile(D.Urp, D.Cp), p->cus, split_enabled());
-  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, choose_tile(D.Rp, D.Cp), p->cus, split_enabled());
+  const bool split_mode = is_split(p);
+  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp, choose_tile(D.Urp, D.Cp, split_mode), p->cus,
+                            split_enabled());
+  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, choose_tile(D.Rp, D.Cp, split_mode), p->cus,
+                            split_enabled());
   const size_t part_floats =
       std::max<size_t>(std::max(p->sched_fwd.part_floats, p->sched_bwd.part_floats), 1);
-  const size_t n_tickets = (size_t)std::max(std::max(p->sched_fwd.n_tail, p->sched_bwd.n_tail), 1);
 
   // ---- pool 1: kernel matrices, pupil and product buffers ----
   const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc;
@@ -921,10 +927,10 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     b.wc_r = c.take<float>(Uc * Cp); b.wc_i = c.take<float>(Uc * Cp);
     b.amp = c.take<float>(Rp * Cp);
     b.p_r = c.take<float>(f32 * Rp * Cp); b.p_i = c.take<float>(f32 * Rp * Cp);
-    b.l_r = c.take<float>(Urp * Cp); b.l_i = c.take<float>(Urp * Cp);
+    b.gpart = c.take<float>(2 * (size_t)(Cp / p->sched_fwd.tile.bn) * nf);
     b.s_r = c.take<float>(f32 * Urp * Cp); b.s_i = c.take<float>(f32 * Urp * Cp);
     b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
-    b.part = c.take<float>(part_floats); b.tickets = c.take<int>(n_tickets);
+    b.part = c.take<float>(part_floats);
     b.as_f = c.take<unsigned short>(2 * nt * Urp * Rp);
     b.as_b = c.take<unsigned short>(2 * nt * Rp * Urp);
     b.ps = c.take<unsigned short>(2 * nt * Cp * Rp);
@@ -1309,16 +1315,16 @@ int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta) {
     DISPATCH_SPLIT(p->precision, COMPACT)
 #undef COMPACT
     HIP_TRY(p, hipGetLastError());
-    HIP_TRY(p, launch_cgemm_split(p, true, EPI_STORE, p->b.xs, p->b.l_r, p->b.l_i, nullptr, false,
+    HIP_TRY(p, launch_cgemm_split(p, true, EPI_GATHER, p->b.xs, nullptr, nullptr, nullptr, false,
                                   s));
   } else {
     hipLaunchKernelGGL(k_compact_complex, gr, dim3(256), 0, s, o, p->b.iobuf, D.nx, D.Rp, D.Cp,
                        p->b.x_r, p->b.x_i);
     HIP_TRY(p, hipGetLastError());
-    HIP_TRY(p, launch_cgemm(p, true, EPI_STORE, p->b.x_r, p->b.x_i, p->b.l_r, p->b.l_i, nullptr,
+    HIP_TRY(p, launch_cgemm(p, true, EPI_GATHER, p->b.x_r, p->b.x_i, nullptr, nullptr, nullptr,
                             nullptr, false, s));
   }
-  HIP_TRY(p, launch_gather(p, p->b.l_r, p->b.l_i, p->b.theta_new, unscale, false, s));
+  HIP_TRY(p, launch_gather_reduce(p, p->b.theta_new, unscale, s));
   HIP_TRY(p, hipMemcpyAsync(theta, p->b.theta_new, 8 * (size_t)D.nf, hipMemcpyDeviceToHost, s));
   HIP_TRY(p, hipStreamSynchronize(s));
   return GSWMTP_OK;
@@ -1392,7 +1398,7 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out) {
       hipError_t er = hipEventRecord(e[0], s);
       if (er == hipSuccess) er = stage_forward(p, true, s);
       if (er == hipSuccess) er = hipEventRecord(e[1], s);
-      if (er == hipSuccess) er = stage_gather(p, p->b.theta, true, s);
+      // the focus gather runs inside the forward product's epilogue
       if (er == hipSuccess) er = hipEventRecord(e[2], s);
       if (er == hipSuccess) er = launch_update(p, UPD_ITERATE, s);
       if (er == hipSuccess) er = hipEventRecord(e[3], s);
@@ -1424,7 +1430,7 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out) {
 const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage) {
   switch (stage) {
     case 0: return cgemm_kernel_name(p, true, EPI_STORE);
-    case 1: return "focus_gather";
+    case 1: return "";   // fused into the forward product
     case 2: return "focus_update";
     case 3: return "focus_scatter";
     case 4: return cgemm_kernel_name(p, false, EPI_PROJECT);
