@@ -226,13 +226,39 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out);
 /* Kernel names of the stages, for matching profiler output (static strings). */
 const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
 
-/* Batched form: run several independent plans together, one grouped launch per
- * stage for all of them, replayed from one captured HIP graph.  The plans must
- * outlive the batch and use FP32 precision; their results equal those of
- * gswmtp_iterate on each plan alone.  stream as for plans. */
+/* Batched form: several independent plans (one hologram each, any sizes)
+ * iterated together.  Each stage of a pass of Algorithm 1 (forward product of
+ * Eq. 2 with the focus gather, weight update of Eq. 1, scatter, adjoint
+ * product with the phase-only projection) is one grouped launch over the
+ * tiles of all plans, replayed from a captured HIP graph.
+ *
+ * batch_create: plans[n_plans] (1..65536 distinct plans on one device, all
+ *   FP32 precision, else GSWMTP_E_UNSUPPORTED) must outlive the batch; the
+ *   batch keeps pointers, copies nothing.  Chooses the product tiles (among
+ *   64/128 x 64/128 tiles that divide every plan, by timing a few grouped
+ *   launches when more than one is valid; GSWMTP_BATCH_TILE=BMxBN fixes it,
+ *   GSWMTP_BATCH_NO_TUNE=1 takes the first valid) without changing any plan's
+ *   state.  Allocates its own argument tables.  stream: hipStream_t or NULL.
+ * batch_iterate: n_iter passes on every plan, each plan stopping on its own
+ *   as gswmtp_iterate(p, n_iter, stop_accuracy) would; ordered after the
+ *   caller's stream and each plan's queued work, and before later calls on
+ *   the plans and the caller's stream.  Each plan's results equal those of
+ *   gswmtp_iterate on that plan alone with no K split
+ *   (GSWMTP_NO_SPLITK=1) bit for bit when the tiles are the same, and to
+ *   float32 rounding otherwise.  Read results through the plans.
+ * batch_set_stream: the caller stream later batch_iterate calls are ordered with.
+ * batch_sync: wait for the batch's queued passes.
+ * batch_tiles: tiles[4] = forward BM, BN, adjoint BM, BN; tune_ms (nullable)
+ *   [8] = mean grouped-launch milliseconds per candidate (64x64, 64x128,
+ *   128x64, 128x128; forward then adjoint; 0 = not timed).
+ * batch_last_error: message of the batch's last failed call, or of the last
+ *   failed batch_create on this thread when b == NULL. */
 int gswmtp_batch_create(gswmtp_batch **out, gswmtp_plan *const *plans, int n_plans, void *stream);
-int gswmtp_batch_iterate(gswmtp_batch *b, int n_iter);
+int gswmtp_batch_iterate(gswmtp_batch *b, int n_iter, double stop_accuracy);
+int gswmtp_batch_set_stream(gswmtp_batch *b, void *stream);
 int gswmtp_batch_sync(gswmtp_batch *b);
+int gswmtp_batch_tiles(const gswmtp_batch *b, int *tiles, double *tune_ms);
+const char *gswmtp_batch_last_error(const gswmtp_batch *b);
 int gswmtp_batch_destroy(gswmtp_batch *b);
 
 #ifdef __cplusplus

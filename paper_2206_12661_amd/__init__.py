@@ -90,8 +90,11 @@ _SIGNATURES = {
     "gswmtp_time_stages": ([_P, ctypes.c_int, _P], ctypes.c_int),
     "gswmtp_stage_kernel": ([_P, ctypes.c_int], ctypes.c_char_p),
     "gswmtp_batch_create": ([ctypes.POINTER(_P), _P, ctypes.c_int, _P], ctypes.c_int),
-    "gswmtp_batch_iterate": ([_P, ctypes.c_int], ctypes.c_int),
+    "gswmtp_batch_iterate": ([_P, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+    "gswmtp_batch_set_stream": ([_P, _P], ctypes.c_int),
     "gswmtp_batch_sync": ([_P], ctypes.c_int),
+    "gswmtp_batch_tiles": ([_P, _P, _P], ctypes.c_int),
+    "gswmtp_batch_last_error": ([_P], ctypes.c_char_p),
     "gswmtp_batch_destroy": ([_P], ctypes.c_int),
 }
 
@@ -366,7 +369,63 @@ class Plan:
         return self._lib.gswmtp_stage_kernel(self._h, stage).decode()
 
 
+class Batch:
+    """Several plans iterated together (one grouped launch per stage of a pass
+    for all of them, replayed from a captured HIP graph).  The plans stay
+    usable: their state is read and set through each ``Plan``; keep them open
+    while the batch lives."""
+
+    def __init__(self, plans):
+        lib = load_library()
+        self.plans = list(plans)
+        arr = (_P * len(self.plans))(*[p.handle for p in self.plans])
+        h = _P()
+        rc = lib.gswmtp_batch_create(ctypes.byref(h), arr, len(self.plans), _stream_handle())
+        if rc != 0:
+            raise GswmtpError(rc, lib.gswmtp_batch_last_error(None).decode())
+        self._h = h
+        self._lib = lib
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise GswmtpError(rc, self._lib.gswmtp_batch_last_error(self._h).decode())
+
+    def iterate(self, n_iter: int, stop_accuracy: float = 0.0):
+        self._check(self._lib.gswmtp_batch_set_stream(self._h, _stream_handle()))
+        self._check(self._lib.gswmtp_batch_iterate(self._h, int(n_iter), float(stop_accuracy)))
+
+    def sync(self):
+        self._check(self._lib.gswmtp_batch_sync(self._h))
+
+    def tiles(self) -> dict:
+        t = np.zeros(4, np.int32)
+        ms = np.zeros(8, np.float64)
+        self._check(self._lib.gswmtp_batch_tiles(self._h, t.ctypes.data, ms.ctypes.data))
+        cands = ("64x64", "64x128", "128x64", "128x128")
+        return {"forward": f"{t[0]}x{t[1]}", "adjoint": f"{t[2]}x{t[3]}",
+                "tune_ms": {"forward": {c: ms[i] for i, c in enumerate(cands) if ms[i] > 0},
+                            "adjoint": {c: ms[4 + i] for i, c in enumerate(cands)
+                                        if ms[4 + i] > 0}}}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gswmtp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 from .autograd import MTPIntensity, foci_intensity  # noqa: E402
 
-__all__ = ["Plan", "GswmtpError", "load_library", "status_string", "MTPIntensity",
+__all__ = ["Plan", "Batch", "GswmtpError", "load_library", "status_string", "MTPIntensity",
            "foci_intensity", "FP32", "BF16X3", "FP16X3", "BF16X6", "STAGES"]

@@ -4,6 +4,7 @@
 // reduced focal rows (every non-focus sample of the reduced focal grid is zero
 // in the inverse propagation).
 #include <cmath>
+#include <cstring>
 
 #include "gswmtp_internal.h"
 
@@ -69,8 +70,7 @@ struct UpdateArgs {
 //   (phasor 1 at a dark focus), written scaled by 2^e so its largest
 //   magnitude is in [0.5, 1) - the phase projection discards the scale.
 // All reductions are float64 in a fixed order.
-__global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
-  __shared__ double slots[8][16];
+__device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*slots)[16]) {
   const int t = threadIdx.x;
   if (a.mode == UPD_ITERATE && a.ctrl[CTRL_DONE]) return;
 
@@ -176,6 +176,18 @@ __global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
   if (t == 0) a.ctrl[CTRL_ITERS] += 1;
 }
 
+__global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
+  __shared__ double slots[8][16];
+  focus_update_body(a, slots);
+}
+
+// One workgroup per plan of a batch.
+__global__ __launch_bounds__(kUpdThreads) void focus_update_grouped(const UpdateArgs *items) {
+  __shared__ double slots[8][16];
+  const UpdateArgs a = items[blockIdx.x];
+  focus_update_body(a, slots);
+}
+
 // Theta_n from the gather partials alone (operator-level forward calls).
 __global__ void gather_reduce(const float *__restrict__ gpart, int T, int nf, float scale,
                               float *__restrict__ theta) {
@@ -203,13 +215,26 @@ __global__ void grad_field(const float *__restrict__ theta, const float *__restr
 // S[a][i] = sum_{n in row a} Theta'_n conj(Wc[ic_n][i]) for all a < Urp and
 // i < Cp (rows past Ur and padded columns come out zero).  Foci of a row are
 // summed in ascending (ic, n) order.
-__global__ __launch_bounds__(256) void focus_scatter(
-    const float *__restrict__ tn, const float *__restrict__ wr, const float *__restrict__ wi,
-    const int *__restrict__ ic, const int *__restrict__ ptr, const int *__restrict__ foci,
-    float *__restrict__ sr, float *__restrict__ si, int Ur, int Cp, const int *done) {
-  if (done && *done) return;
-  const int a = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+struct ScatterArgs {
+  const float *tn;
+  const float *wr, *wi;
+  const int *ic, *ptr, *foci;
+  float *sr, *si;
+  int Ur, Cp;
+  const int *done;
+};
+
+__device__ __forceinline__ void focus_scatter_body(const ScatterArgs &s_, int a, int i) {
+  const float *__restrict__ tn = s_.tn;
+  const float *__restrict__ wr = s_.wr;
+  const float *__restrict__ wi = s_.wi;
+  const int *__restrict__ ic = s_.ic;
+  const int *__restrict__ ptr = s_.ptr;
+  const int *__restrict__ foci = s_.foci;
+  float *__restrict__ sr = s_.sr;
+  float *__restrict__ si = s_.si;
+  const int Ur = s_.Ur, Cp = s_.Cp;
+  if (s_.done && *s_.done) return;
   if (i >= Cp) return;
   float accr = 0.f, acci = 0.f;
   if (a < Ur) {
@@ -225,6 +250,25 @@ __global__ __launch_bounds__(256) void focus_scatter(
   }
   sr[(size_t)a * Cp + i] = accr;
   si[(size_t)a * Cp + i] = acci;
+}
+
+__global__ __launch_bounds__(256) void focus_scatter(ScatterArgs a) {
+  focus_scatter_body(a, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Grouped over the plans of a batch: item h owns blocks [starts[h], starts[h+1]),
+// (Cp / 256) column blocks per reduced row.
+__global__ __launch_bounds__(256) void focus_scatter_grouped(const ScatterArgs *items,
+                                                             const int *starts, int n) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (starts[mid] <= b) lo = mid; else hi = mid;
+  }
+  const ScatterArgs a = items[lo];
+  const int lb = b - starts[lo], bx = (a.Cp + 255) / 256;
+  focus_scatter_body(a, lb / bx, (lb % bx) * 256 + threadIdx.x);
 }
 
 // Split-precision scatter: the same S, written transposed as 16-bit term
@@ -314,7 +358,7 @@ hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale,
   return hipGetLastError();
 }
 
-hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
+static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
   UpdateArgs a{};
   a.gpart = p->b.gpart;
   a.T = p->d.Cp / p->sched_fwd.tile.bn;
@@ -333,7 +377,23 @@ hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
   a.weighting = p->weighting;
   a.n_ap = (double)p->d.n_ap;
   a.sum_a2 = p->d.sum_a2;
-  hipLaunchKernelGGL(focus_update, dim3(1), dim3(kUpdThreads), 0, s, a);
+  return a;
+}
+
+hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(focus_update, dim3(1), dim3(kUpdThreads), 0, s, update_args(p, mode));
+  return hipGetLastError();
+}
+
+size_t update_args_bytes() { return sizeof(UpdateArgs); }
+void fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out) {
+  UpdateArgs a = update_args(p, mode);
+  a.T = p->d.Cp / gather_bn;   // partials per focus of the batch's forward tile
+  std::memcpy(out, &a, sizeof a);
+}
+hipError_t launch_update_grouped(const void *d_items, int n, hipStream_t s) {
+  hipLaunchKernelGGL(focus_update_grouped, dim3(n), dim3(kUpdThreads), 0, s,
+                     static_cast<const UpdateArgs *>(d_items));
   return hipGetLastError();
 }
 
@@ -343,13 +403,41 @@ hipError_t launch_grad_field(const gswmtp_plan *p, const float *g, hipStream_t s
   return hipGetLastError();
 }
 
+static ScatterArgs scatter_args(const gswmtp_plan *p, const float *theta_new, bool honour_done) {
+  const Dims &d = p->d;
+  ScatterArgs a{};
+  a.tn = theta_new;
+  a.wr = p->b.wc_r;
+  a.wi = p->b.wc_i;
+  a.ic = d.axis == 0 ? p->b.ix : p->b.iy;
+  a.ptr = p->b.csr_ptr;
+  a.foci = p->b.csr_foci;
+  a.sr = p->b.s_r;
+  a.si = p->b.s_i;
+  a.Ur = d.Ur;
+  a.Cp = d.Cp;
+  a.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+  return a;
+}
+
 hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,
                           hipStream_t s) {
   const Dims &d = p->d;
-  const int *ic = d.axis == 0 ? p->b.ix : p->b.iy;
-  hipLaunchKernelGGL(focus_scatter, dim3((d.Cp + 255) / 256, d.Urp), dim3(256), 0, s, theta_new,
-                     p->b.wc_r, p->b.wc_i, ic, p->b.csr_ptr, p->b.csr_foci, p->b.s_r, p->b.s_i,
-                     d.Ur, d.Cp, honour_done ? p->b.ctrl + CTRL_DONE : nullptr);
+  hipLaunchKernelGGL(focus_scatter, dim3((d.Cp + 255) / 256, d.Urp), dim3(256), 0, s,
+                     scatter_args(p, theta_new, honour_done));
+  return hipGetLastError();
+}
+
+size_t scatter_args_bytes() { return sizeof(ScatterArgs); }
+int fill_scatter_args(const gswmtp_plan *p, void *out) {
+  const ScatterArgs a = scatter_args(p, p->b.theta_new, true);
+  std::memcpy(out, &a, sizeof a);
+  return ((p->d.Cp + 255) / 256) * p->d.Urp;
+}
+hipError_t launch_scatter_grouped(const void *d_items, const int *d_starts, int n, int blocks,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(focus_scatter_grouped, dim3(blocks), dim3(256), 0, s,
+                     static_cast<const ScatterArgs *>(d_items), d_starts, n);
   return hipGetLastError();
 }
 

@@ -28,6 +28,8 @@
 // (E = A C / |C|, phasor 1 where C = 0: the phase-only projection of
 // Algorithm 1, fused so E' never reaches HBM); or the phase gradient
 // 2 Im(conj(E) C).
+#include <cstring>
+
 #include "gswmtp_internal.h"
 
 namespace gswmtp {
@@ -110,7 +112,16 @@ __device__ __forceinline__ void epilogue(const CgemmArgs &a, v16f (&accR)[MB][NB
 }
 
 template <int BM, int BN, int EPI>
-__global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
+constexpr int f32_lds_floats() {
+  constexpr int A_F = 2 * 2 * kBK * (BM + 32), B_F = 2 * 2 * kBK * (BN + 32);
+  constexpr int G_F = EPI == EPI_GATHER ? gather_lds_bytes<BM, BN>() / 4 : 0;
+  return A_F + B_F > G_F ? A_F + B_F : G_F;
+}
+
+// One workgroup's share of a product: whole tile, K chunk (phase 0) or tail
+// reduction (phase 1) number `bid` of the schedule in `a`.
+template <int BM, int BN, int EPI>
+__device__ __forceinline__ void cgemm_f32_body(const CgemmArgs &a, const int bid, float *lds) {
   if (a.done && *a.done) return;
   constexpr int WTM = BM / 2, WTN = BN / 2;    // wave tile (complex)
   constexpr int MB = WTM / 32, NB = WTN / 32;  // 32x32 blocks per wave
@@ -121,9 +132,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
   static_assert(2 * A4 % kThreads == 0 && 2 * B4 % kThreads == 0, "tile/thread mismatch");
 
   // operand stages [buf][plane][k][row]; the gather epilogue reuses the space
-  constexpr int A_F = 2 * 2 * kBK * SA, B_F = 2 * 2 * kBK * SB;
-  constexpr int G_F = EPI == EPI_GATHER ? gather_lds_bytes<BM, BN>() / 4 : 0;
-  __shared__ __attribute__((aligned(16))) float lds[A_F + B_F > G_F ? A_F + B_F : G_F];
+  constexpr int A_F = 2 * 2 * kBK * SA;
   float *const sA = lds;
   float *const sB = lds + A_F;
   constexpr int BUF_A = 2 * kBK * SA, BUF_B = 2 * kBK * SB;
@@ -132,15 +141,15 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
   const int KT = a.K / kBK;
   int t, kb, ke, tail = -1, chunk = 0;
   if (a.phase == 1) {
-    tail = blockIdx.x;
+    tail = bid;
     t = a.t_dp + tail;
     kb = ke = 0;
-  } else if ((int)blockIdx.x < a.t_dp) {
-    t = xcd_tile(blockIdx.x, a.t_dp);
+  } else if (bid < a.t_dp) {
+    t = xcd_tile(bid, a.t_dp);
     kb = 0;
     ke = KT;
   } else {
-    const int u = blockIdx.x - a.t_dp;
+    const int u = bid - a.t_dp;
     tail = u / a.split;
     chunk = u % a.split;
     t = a.t_dp + tail;
@@ -305,6 +314,28 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
 }
 
 template <int BM, int BN, int EPI>
+__global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
+  __shared__ __attribute__((aligned(16))) float lds[f32_lds_floats<BM, BN, EPI>()];
+  cgemm_f32_body<BM, BN, EPI>(a, blockIdx.x, lds);
+}
+
+// Grouped launch: the concatenated schedules of several products (one per
+// plan of a batch); workgroup b runs item h's block b - starts[h].
+template <int BM, int BN, int EPI>
+__global__ __launch_bounds__(kThreads) void cgemm_f32_grouped(const CgemmArgs *items,
+                                                              const int *starts, int n) {
+  __shared__ __attribute__((aligned(16))) float lds[f32_lds_floats<BM, BN, EPI>()];
+  const int b = blockIdx.x;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (starts[mid] <= b) lo = mid; else hi = mid;
+  }
+  const CgemmArgs a = items[lo];
+  cgemm_f32_body<BM, BN, EPI>(a, b - starts[lo], lds);
+}
+
+template <int BM, int BN, int EPI>
 hipError_t launch_t(const CgemmArgs &args, int grid, hipStream_t s) {
   hipLaunchKernelGGL((cgemm_f32_mfma<BM, BN, EPI>), dim3(grid), dim3(kThreads), 0, s, args);
   return hipGetLastError();
@@ -403,6 +434,64 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+size_t cgemm_args_bytes() { return sizeof(CgemmArgs); }
+
+// Arguments of plan p's product for a grouped (batched) launch with tile
+// (bm, bn): every tile whole (no K split).  honour_done: return at once when
+// the plan's done flag is set.  cr / ci (adjoint only, nullable): write the
+// projected field there instead of the plan's pupil field.  Returns the
+// block count (tiles).
+int fill_cgemm_args(const gswmtp_plan *p, bool forward, int bm, int bn, bool honour_done,
+                    float *cr, float *ci, void *out) {
+  const Dims &d = p->d;
+  CgemmArgs a{};
+  if (forward) {
+    a.atr = p->b.omt_r; a.ati = p->b.omt_i; a.lda = d.Urp;
+    a.M = d.Urp; a.K = d.Rp;
+    a.br = p->b.p_r; a.bi = p->b.p_i;
+  } else {
+    a.atr = p->b.omc_r; a.ati = p->b.omc_i; a.lda = d.Rp;
+    a.M = d.Rp; a.K = d.Urp;
+    a.br = p->b.s_r; a.bi = p->b.s_i;
+    a.cr = cr ? cr : p->b.p_r;
+    a.ci = ci ? ci : p->b.p_i;
+  }
+  a.ldb = d.Cp;
+  a.ldc = d.Cp;
+  a.N = d.Cp;
+  a.amp = p->b.amp;
+  a.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+  a.part = p->b.part;
+  a.g = gather_ctx(p);
+  a.tiles_m = a.M / bm;
+  a.t_dp = a.tiles_m * (a.N / bn);
+  a.split = 1;
+  a.phase = 0;
+  std::memcpy(out, &a, sizeof a);
+  return a.t_dp;
+}
+
+hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s) {
+  const auto *items = static_cast<const CgemmArgs *>(g.d_items);
+#define GROUPED(BM, BN, EPI)                                                                   \
+  hipLaunchKernelGGL((cgemm_f32_grouped<BM, BN, EPI>), dim3(g.blocks), dim3(kThreads), 0, s, \
+                     items, g.d_starts, g.n_items)
+#define GROUPED_EPI(BM, BN)                                  \
+  do {                                                       \
+    if (g.epi == EPI_GATHER) GROUPED(BM, BN, EPI_GATHER);    \
+    else if (g.epi == EPI_PROJECT) GROUPED(BM, BN, EPI_PROJECT); \
+    else return hipErrorInvalidValue;                        \
+  } while (0)
+  if (g.bm == 64 && g.bn == 64) GROUPED_EPI(64, 64);
+  else if (g.bm == 64 && g.bn == 128) GROUPED_EPI(64, 128);
+  else if (g.bm == 128 && g.bn == 64) GROUPED_EPI(128, 64);
+  else if (g.bm == 128 && g.bn == 128) GROUPED_EPI(128, 128);
+  else return hipErrorInvalidValue;
+#undef GROUPED_EPI
+#undef GROUPED
+  return hipGetLastError();
 }
 
 const char *cgemm_kernel_name(const gswmtp_plan *p, bool, int) {

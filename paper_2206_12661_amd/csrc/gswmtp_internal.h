@@ -285,6 +285,25 @@ hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool hon
 const char *cgemm_kernel_name(const gswmtp_plan *p, bool forward, int epi);
 GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split);
 
+// Grouped launches over the plans of a batch (float32 products).
+struct GroupedLaunch {
+  int bm = 64, bn = 64, epi = 0;
+  int n_items = 0, blocks = 0;
+  void *d_items = nullptr;   // per-plan kernel arguments
+  int *d_starts = nullptr;   // [n_items + 1] first block of each item
+};
+size_t cgemm_args_bytes();
+int fill_cgemm_args(const gswmtp_plan *p, bool forward, int bm, int bn, bool honour_done,
+                    float *cr, float *ci, void *out);
+hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s);
+size_t update_args_bytes();
+void fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out);
+hipError_t launch_update_grouped(const void *d_items, int n, hipStream_t s);
+size_t scatter_args_bytes();
+int fill_scatter_args(const gswmtp_plan *p, void *out);
+hipError_t launch_scatter_grouped(const void *d_items, const int *d_starts, int n, int blocks,
+                                  hipStream_t s);
+
 // Product epilogues: store C; project onto the amplitude constraint; phase
 // gradient; focus gather (forward product only, C never stored).
 enum { EPI_STORE = 0, EPI_PROJECT = 1, EPI_GRAD = 2, EPI_GATHER = 3 };

@@ -117,6 +117,18 @@ def test_null_arguments(lib):
     assert lib.gswmtp_desc_init(None) == -1
     assert lib.gswmtp_iterate(None, 1, 0.0) == -1
     assert lib.gswmtp_batch_destroy(None) == 0
+    b = ctypes.c_void_p()
+    assert lib.gswmtp_batch_create(None, None, 1, None) == -1
+    assert lib.gswmtp_batch_create(ctypes.byref(b), None, 1, None) == -1
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert lib.gswmtp_batch_create(ctypes.byref(b), arr, 0, None) == -1
+    assert lib.gswmtp_batch_create(ctypes.byref(b), arr, 2, None) == -1
+    assert not b.value
+    assert lib.gswmtp_batch_last_error(None).decode() != ""
+    assert lib.gswmtp_batch_iterate(None, 1, 0.0) == -1
+    assert lib.gswmtp_batch_sync(None) == -1
+    assert lib.gswmtp_batch_set_stream(None, None) == -1
+    assert lib.gswmtp_batch_tiles(None, None, None) == -1
 
 
 def test_product_path_does_not_import_oracle():

@@ -1,0 +1,190 @@
+"""Batched form: several plans iterated together through the C ABI.
+
+A plan's batched result must equal its single-plan result: bit for bit when
+both run the same tiles with no K split (the batch never splits K; single
+plans do not when GSWMTP_NO_SPLITK=1), and within float32 rounding of the
+oracle-tested single path otherwise.  Graph replay must equal eager launches
+bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth_ofa
+from gpu_util import announce, cuda_ok, rel_l2
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not cuda_ok(), reason="needs a gfx950 GPU")]
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2206_12661_amd as g
+    return g
+
+
+def _ragged_set():
+    """Holograms of uneven sizes, both product axes, grid and random foci."""
+    return [
+        synth_ofa.random_case(40, 100, 150, 70, amplitude="random"),
+        synth_ofa.random_case(41, 130, 200, 130, radius=60.0),
+        synth_ofa.random_case(42, 96, 96, 0, grid=(7, 5)),
+        synth_ofa.random_case(43, 64, 300, 9, roi=20.0),
+        synth_ofa.random_case(44, 257, 129, 300, radius=100.0, amplitude="random"),
+        synth_ofa.config1(),
+        synth_ofa.config2(),
+    ]
+
+
+def _state(p):
+    phi, w, it = p.state()
+    return phi, w, it, p.foci_field()
+
+
+def _assert_same(a, b):
+    assert np.array_equal(a[0], b[0]), "phase differs"
+    assert np.array_equal(a[1], b[1]), "weights differ"
+    assert a[2] == b[2], "pass count differs"
+    assert np.array_equal(a[3], b[3]), "foci field differs"
+
+
+@pytest.mark.parametrize("n_iter", [1, 11])
+def test_batch_bit_exact_vs_single(g, monkeypatch, n_iter):
+    monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
+    monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    hs = _ragged_set()
+    announce(f"batch of {len(hs)} vs single plans, {n_iter} passes")
+    single = []
+    for h in hs:
+        with g.Plan(h) as p:
+            p.iterate(n_iter)
+            single.append(_state(p))
+    plans = [g.Plan(h) for h in hs]
+    with g.Batch(plans) as b:
+        assert b.tiles()["forward"] == "64x64" and b.tiles()["adjoint"] == "64x64"
+        b.iterate(n_iter)
+        b.sync()
+    for k, p in enumerate(plans):
+        _assert_same(_state(p), single[k])
+        p.close()
+
+
+def test_batch_graph_equals_eager(g, monkeypatch):
+    hs = _ragged_set()[:4]
+    outs = []
+    for env in ("0", "1", "0"):
+        monkeypatch.setenv("GSWMTP_NO_GRAPH", env)
+        announce(f"batch graph={env == '0'}")
+        plans = [g.Plan(h) for h in hs]
+        with g.Batch(plans) as b:
+            b.iterate(9)
+        outs.append([_state(p) for p in plans])
+        for p in plans:
+            p.close()
+    for o in outs[1:]:
+        for a, c in zip(outs[0], o):
+            _assert_same(a, c)
+
+
+def test_batch_then_plan_continues(g, monkeypatch):
+    """Batched passes followed by single-plan passes equal single passes alone."""
+    monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
+    monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    hs = _ragged_set()[:3]
+    announce("batch 4 passes then plan 3 passes")
+    ref = []
+    for h in hs:
+        with g.Plan(h) as p:
+            p.iterate(7)
+            ref.append(_state(p))
+    plans = [g.Plan(h) for h in hs]
+    with g.Batch(plans) as b:
+        b.iterate(4)
+    for k, p in enumerate(plans):
+        p.iterate(3)
+        _assert_same(_state(p), ref[k])
+        p.close()
+
+
+def test_batch_stop_threshold_per_plan(g, monkeypatch):
+    """Each plan of a batch stops on its own, exactly where it would alone:
+    the threshold lies between the accuracies of passes of the first plan, so
+    the plans stop after different numbers of passes (or run them all)."""
+    monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
+    monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    hs = [synth_ofa.config1()] + _ragged_set()[:4]
+    with g.Plan(hs[0]) as p:
+        p.iterate(30)
+        xi = p.history()[:, 0]
+    k = next(k for k in range(3, 30) if xi[k] > np.max(xi[:k]) + 1e-3)
+    stop = 0.5 * (np.max(xi[:k]) + xi[k])
+    announce(f"batch stop threshold {stop:.4f}")
+    ref = []
+    for h in hs:
+        with g.Plan(h) as p:
+            p.iterate(30, stop)
+            ref.append(_state(p))
+    plans = [g.Plan(h) for h in hs]
+    with g.Batch(plans) as b:
+        b.iterate(30, stop)
+    done = []
+    for k_, p in enumerate(plans):
+        s = _state(p)
+        _assert_same(s, ref[k_])
+        done.append(s[2])
+        p.close()
+    print("  passes done:", done)
+    assert done[0] == k and len(set(done)) > 1
+
+
+def test_batch_against_oracle(g):
+    """Default (tuned) tiles: every plan within the float32 field bar of the
+    oracle after two passes.  (The 512 x 512 jittered-grid case is left out:
+    its weight update amplifies float32 rounding past the plain bar, which the
+    single-plan tests bound by its condition number; the batch equals the
+    single plan bit for bit above.)"""
+    hs = _ragged_set()[:-1]
+    announce("batch vs oracle, 2 passes")
+    plans = [g.Plan(h) for h in hs]
+    with g.Batch(plans) as b:
+        b.iterate(2)
+        print("  tiles:", b.tiles())
+    for h, p in zip(hs, plans):
+        r = oracle.gsw(h, n_iter=2)
+        e = rel_l2(p.foci_field(), r["theta"])
+        print(f"  {h.name}: theta rel err {e:.2e}")
+        assert e <= 1e-5
+        p.close()
+
+
+def test_batch_config4_subset(g):
+    """The 64-hologram workload's smallest 8 plus its largest: batched result
+    against single plans (tiles may differ: float32 rounding bar)."""
+    hs = synth_ofa.config4()
+    order = sorted(range(len(hs)), key=lambda k: hs[k].ny * hs[k].nx * hs[k].fx.shape[0])
+    sel = [hs[k] for k in order[:8] + order[-1:]]
+    announce(f"config4 subset of {len(sel)}")
+    single = []
+    for h in sel:
+        with g.Plan(h) as p:
+            p.iterate(3)
+            single.append(p.foci_field())
+    plans = [g.Plan(h) for h in sel]
+    with g.Batch(plans) as b:
+        b.iterate(3)
+    for h, p, s in zip(sel, plans, single):
+        e = rel_l2(p.foci_field(), s)
+        print(f"  {h.name}: batched vs single {e:.2e}")
+        assert e <= 1e-5
+        p.close()
+
+
+def test_batch_rejects(g):
+    h = synth_ofa.random_case(45, 40, 50, 8)
+    with g.Plan(h) as p, g.Plan(h, precision="fp16x3") as q:
+        with pytest.raises(g.GswmtpError) as e:
+            g.Batch([p, p])
+        assert e.value.status == -1
+        with pytest.raises(g.GswmtpError) as e:
+            g.Batch([p, q])
+        assert e.value.status == -8
