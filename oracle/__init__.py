@@ -169,6 +169,55 @@ def phase_gradient(holo, phi, g):
     return grad, th
 
 
+def design_loss(I, target, n_ap: int, sum_a2: float, eta_weight: float = 0.1):
+    """Loss of the differentiable phase design and its gradient in I:
+
+        L = sum_n (i_n - t_n)^2 - eta_weight * eta,
+        i_n = I_n / sum_m I_m,   eta = sum_m I_m / (n_ap * sum A^2)
+
+    (normalised intensities against normalised targets t = T / sum T, as in
+    the weight update of Eq. 1; eta is the efficiency of Sec. 3 in the units
+    of Table 1).  Returns (L, dL/dI)."""
+    I = np.asarray(I, dtype=np.float64)
+    t = np.asarray(target, dtype=np.float64)
+    t = t / t.sum()
+    S = I.sum()
+    i = I / S
+    r = i - t
+    c = 1.0 / (float(n_ap) * float(sum_a2))
+    L = float(np.sum(r * r) - eta_weight * S * c)
+    # d i_m / d I_n = (delta_mn - i_m) / S
+    dI = 2.0 * r / S - 2.0 * np.sum(r * i) / S - eta_weight * c
+    return L, dI
+
+
+def adam_design(holo, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
+                eta_weight: float = 0.1, phi=None):
+    """Gradient-descent phase design: Adam (Kingma and Ba, bias-corrected
+    moments) on ``design_loss`` of the foci intensities, with the gradient
+    dL/dphi = 2 Im(conj(E) P^H(dL/dI * Theta)) from ``phase_gradient``.
+    Returns (phi after the last step, loss before each step [steps])."""
+    ph = _f64(holo.phi0 if phi is None else phi).copy()
+    amp = _f64(holo.amplitude)
+    n_ap = int(np.count_nonzero(amp > 0))
+    sum_a2 = float(np.sum(amp * amp))
+    b1, b2 = betas
+    m = np.zeros_like(ph)
+    v = np.zeros_like(ph)
+    hist = np.zeros(steps)
+    for k in range(1, steps + 1):
+        th = forward(pupil_field(holo, ph), holo.u, holo.v, holo.s_x, holo.s_y, holo.fx, holo.fy)
+        L, gI = design_loss(np.abs(th) ** 2, holo.target, n_ap, sum_a2, eta_weight)
+        hist[k - 1] = L
+        grad, _ = phase_gradient(holo, ph, gI)
+        m = b1 * m + (1.0 - b1) * grad
+        v = b2 * v + (1.0 - b2) * grad * grad
+        mh = m / (1.0 - b1 ** k)
+        vh = v / (1.0 - b2 ** k)
+        ph = ph - lr * mh / (np.sqrt(vh) + eps)
+    return ph, hist
+
+
 def pupil_field(holo, phi=None) -> np.ndarray:
     """E = A exp(i phi) in complex128 (phi defaults to the initial phase)."""
     ph = np.asarray(holo.phi0 if phi is None else phi, dtype=np.float64)

@@ -425,7 +425,7 @@ class Batch:
         self.close()
 
 
-from .autograd import MTPIntensity, foci_intensity  # noqa: E402
+from .autograd import MTPIntensity, adam_design, design_loss, foci_intensity  # noqa: E402
 
 __all__ = ["Plan", "Batch", "GswmtpError", "load_library", "status_string", "MTPIntensity",
-           "foci_intensity", "FP32", "BF16X3", "FP16X3", "BF16X6", "STAGES"]
+           "foci_intensity", "design_loss", "adam_design", "FP32", "BF16X3", "FP16X3", "BF16X6", "STAGES"]

@@ -47,3 +47,37 @@ class MTPIntensity(torch.autograd.Function):
 def foci_intensity(phi: torch.Tensor, plan) -> torch.Tensor:
     """I_n(phi) for the plan's pupil and foci, differentiable in phi."""
     return MTPIntensity.apply(phi, plan)
+
+
+def design_loss(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
+                eta_weight: float = 0.1) -> torch.Tensor:
+    """L = sum_n (i_n - t_n)^2 - eta_weight * eta, with normalised
+    intensities i = I / sum I against normalised targets t = T / sum T and
+    the efficiency eta = sum I / (n_ap * sum A^2) (Sec. 3, Table 1 units)."""
+    S = I.sum()
+    r = I / S - target / target.sum()
+    return (r * r).sum() - eta_weight * S / (float(n_ap) * float(sum_a2))
+
+
+def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
+                eta_weight: float = 0.1, phi0=None, target=None):
+    """Phase design by gradient descent: Adam on ``design_loss`` of the plan's
+    foci intensities, differentiated through ``MTPIntensity``.  Returns
+    (phi [ny, nx] float32 CUDA tensor, loss before each step [steps] tensor)."""
+    idx = plan.index()
+    n_ap, sum_a2 = idx["n_aperture"], idx["sum_a2"]
+    if target is None:
+        raise ValueError("target intensities are required")
+    t = torch.as_tensor(target, dtype=torch.float32, device="cuda")
+    if phi0 is None:
+        phi0 = torch.zeros(plan.ny, plan.nx)
+    phi = torch.nn.Parameter(torch.as_tensor(phi0, dtype=torch.float32, device="cuda").clone())
+    opt = torch.optim.Adam([phi], lr=lr, betas=betas, eps=eps)
+    hist = torch.empty(steps, dtype=torch.float32, device="cuda")
+    for k in range(steps):
+        opt.zero_grad(set_to_none=False)
+        loss = design_loss(foci_intensity(phi, plan), t, n_ap, sum_a2, eta_weight)
+        loss.backward()
+        hist[k] = loss.detach()
+        opt.step()
+    return phi.detach(), hist

@@ -1,0 +1,123 @@
+"""Differentiable form: phase design by gradient descent through the library's
+forward product and adjoint-gradient epilogue, against the FP64 oracle.
+
+Bars: gradients of the design loss within 1e-4 relative L2 of the oracle's
+chain rule (dL/dI has a cancellation between its two terms that float32
+intensities feed with ~1e-6 relative error, amplified by up to ~10x at these
+cases; 1e-4 keeps a further 10x margin).  Adam trajectories: the oracle's own
+sensitivity to a float32-sized (1e-6 rad) perturbation of the start phase,
+times ten, floored at 1e-5 - Adam normalises every coordinate's step, so
+float32 rounding of tiny gradient components moves phases by up to lr per
+step and nothing tighter holds over many steps.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth_ofa
+from gpu_util import announce, cuda_ok, rel_l2
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not cuda_ok(), reason="needs a gfx950 GPU")]
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2206_12661_amd as g
+    return g
+
+
+def _medium():
+    h = synth_ofa.random_case(50, 200, 300, 0, radius=90.0, grid=(8, 8))
+    return h
+
+
+def _oracle_grad(h, phi):
+    amp = np.asarray(h.amplitude, np.float64)
+    th = oracle.forward(oracle.pupil_field(h, phi), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    I = np.abs(th) ** 2
+    L, gI = oracle.design_loss(I, h.target, int(np.count_nonzero(amp > 0)),
+                               float(np.sum(amp * amp)))
+    grad, _ = oracle.phase_gradient(h, phi, gI)
+    return L, grad, I
+
+
+@pytest.mark.parametrize("case", ["gradcheck-64x64-4x4", "disc-200x300-8x8"])
+def test_design_loss_gradient(g, case):
+    import torch
+    h = synth_ofa.config5_gradcheck() if case.startswith("gradcheck") else _medium()
+    announce(f"design-loss gradient {case}")
+    with g.Plan(h) as p:
+        idx = p.index()
+        phi = torch.tensor(h.phi0, device="cuda", requires_grad=True)
+        t = torch.tensor(h.target, device="cuda", dtype=torch.float32)
+        loss = g.design_loss(g.foci_intensity(phi, p), t, idx["n_aperture"], idx["sum_a2"])
+        loss.backward()
+        gphi = phi.grad.cpu().numpy()
+        L_gpu = float(loss)
+    L, ref, _ = _oracle_grad(h, np.asarray(h.phi0, np.float64))
+    err = rel_l2(gphi, ref)
+    print(f"  loss {L_gpu:.6e} vs {L:.6e}; gradient rel err {err:.2e}")
+    assert L_gpu == pytest.approx(L, rel=1e-5, abs=1e-7)
+    assert err <= 1e-4
+    assert np.all(gphi[h.amplitude == 0] == 0)
+
+
+def test_adam_trajectory(g):
+    import torch
+    h = synth_ofa.config5_gradcheck()
+    steps = 30
+    announce(f"Adam {steps} steps, 64x64 / 16 foci")
+    with g.Plan(h) as p:
+        phi, hist = g.adam_design(p, steps, phi0=h.phi0, target=h.target)
+        phi = phi.cpu().numpy().astype(np.float64)
+        hist = hist.cpu().numpy().astype(np.float64)
+    phi_o, hist_o = oracle.adam_design(h, steps)
+    # the oracle against itself from a start phase perturbed by 1e-6 rad
+    rng = np.random.default_rng(3)
+    phi_p, hist_p = oracle.adam_design(h, steps, phi=np.asarray(h.phi0, np.float64) +
+                                       1e-6 * rng.standard_normal(h.phi0.shape))
+    amp = np.asarray(h.amplitude, np.float64)
+    field = lambda ph: amp * np.exp(1j * ph)  # noqa: E731
+    sens_f = rel_l2(field(phi_p), field(phi_o))
+    sens_l = np.max(np.abs(hist_p - hist_o))
+    e_f = rel_l2(field(phi), field(phi_o))
+    e_l = np.max(np.abs(hist - hist_o))
+    print(f"  field {e_f:.2e} (oracle self-sensitivity {sens_f:.2e}); "
+          f"loss {e_l:.2e} (self {sens_l:.2e}); loss {hist_o[0]:.4e} -> {hist_o[-1]:.4e}")
+    assert e_f <= max(10 * sens_f, 1e-5)
+    assert e_l <= max(10 * sens_l, 1e-5 * np.max(np.abs(hist_o)))
+
+
+def test_c5_adam_200_steps(g):
+    """The full 1152 x 1920 / 50 x 50 design: 200 Adam steps (lr 0.05).  The
+    loss before the first step and the foci intensities of the final phase
+    are checked against the oracle's forward at the same phases."""
+    import torch
+    h = synth_ofa.config5()
+    announce("C-5 Adam 200 steps")
+    with g.Plan(h) as p:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, hist = g.adam_design(p, 200, phi0=h.phi0, target=h.target)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        phi_np = phi.cpu().numpy()
+        p.set_phase(phi_np)
+        I_gpu = np.abs(p.foci_field().astype(np.complex128)) ** 2
+        st = p.stats()
+    hist = hist.cpu().numpy().astype(np.float64)
+    print(f"  {200 / dt:.1f} steps/s; loss {hist[0]:.5e} -> {hist[-1]:.5e}; "
+          f"uniformity {st['uniformity']:.4f} efficiency {st['eta']:.4f}")
+    assert np.all(np.isfinite(hist)) and np.all(np.isfinite(phi_np))
+    amp = np.asarray(h.amplitude, np.float64)
+    n_ap, sum_a2 = int(np.count_nonzero(amp > 0)), float(np.sum(amp * amp))
+    th0 = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    L0, _ = oracle.design_loss(np.abs(th0) ** 2, h.target, n_ap, sum_a2)
+    assert hist[0] == pytest.approx(L0, rel=1e-5)
+    th1 = oracle.forward(oracle.pupil_field(h, phi_np.astype(np.float64)), h.u, h.v, h.s_x,
+                         h.s_y, h.fx, h.fy)
+    assert rel_l2(I_gpu, np.abs(th1) ** 2) <= 1e-5
+    assert hist[-1] < hist[0]

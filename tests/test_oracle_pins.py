@@ -306,6 +306,57 @@ def test_phase_gradient_matches_central_differences():
     assert np.all(grad[off] == 0.0)
 
 
+def test_design_loss_gradient_matches_central_differences():
+    """dL/dI of the design loss against central differences of L itself."""
+    rng = np.random.default_rng(12)
+    I = rng.uniform(0.1, 2.0, 25)
+    t = rng.uniform(0.5, 1.0, 25)
+    t /= t.sum()
+    n_ap, sum_a2 = 3000, 2500.0
+    L0, dI = oracle.design_loss(I, t, n_ap, sum_a2)
+    eps = 1e-6
+    for n in range(25):
+        ip, im = I.copy(), I.copy()
+        ip[n] += eps
+        im[n] -= eps
+        fd = (oracle.design_loss(ip, t, n_ap, sum_a2)[0] -
+              oracle.design_loss(im, t, n_ap, sum_a2)[0]) / (2 * eps)
+        assert fd == pytest.approx(dI[n], rel=1e-6, abs=1e-9)
+    # special cases: intensities proportional to the target leave only the
+    # efficiency term, L = -0.1 eta, and the loss is invariant to the
+    # scale of I apart from that term
+    L1, _ = oracle.design_loss(7.0 * t, t, n_ap, sum_a2)
+    assert L1 == pytest.approx(-0.1 * 7.0 / (n_ap * sum_a2), rel=1e-12)
+    La, _ = oracle.design_loss(I, t, n_ap, sum_a2, eta_weight=0.0)
+    Lb, _ = oracle.design_loss(3.0 * I, t, n_ap, sum_a2, eta_weight=0.0)
+    assert La == pytest.approx(Lb, rel=1e-12)
+
+
+def test_adam_design_first_step_and_descent():
+    """Adam's bias-corrected first step has m^ = g and v^ = g^2, so every
+    coordinate moves by lr |g| / (|g| + eps) against the sign of its gradient
+    (lr to within lr eps / |g|); coordinates with no gradient (outside the
+    aperture) do not move; the loss goes down."""
+    h = synth_ofa.config5_gradcheck()
+    lr = 0.05
+    phi1, hist1 = oracle.adam_design(h, 1, lr=lr)
+    phi0 = np.asarray(h.phi0, np.float64)
+    amp = np.asarray(h.amplitude, np.float64)
+    th = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    _, gI = oracle.design_loss(np.abs(th) ** 2, h.target, int(np.count_nonzero(amp > 0)),
+                               float(np.sum(amp * amp)))
+    grad, _ = oracle.phase_gradient(h, phi0, gI)
+    step = phi1 - phi0
+    on = amp > 0
+    assert np.allclose(step[on], -lr * grad[on] / (np.abs(grad[on]) + 1e-8), rtol=0, atol=1e-12)
+    big = np.abs(grad) > 1e-4 * np.max(np.abs(grad))
+    assert np.all(np.abs(np.abs(step[big]) - lr) <= lr * 1e-8 / np.abs(grad[big]) * 1.0001)
+    assert np.all(phi1[amp == 0] == phi0[amp == 0])
+    _, hist = oracle.adam_design(h, 25, lr=lr)
+    assert hist[0] == pytest.approx(hist1[0], rel=1e-14)
+    assert hist[-1] < 0.5 * hist[0]
+
+
 # --------------------------------------------------------------------------
 # Index work
 # --------------------------------------------------------------------------
