@@ -46,6 +46,9 @@ def parse():
                     help="host time budget of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-iters", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 128 MiB device copy 3 times (the known-size "
+                         "reference that scales FETCH_SIZE / WRITE_SIZE counters) and exit")
     ap.add_argument("--adam-steps", type=int, default=200,
                     help="Adam steps of the differentiable 50x50-grid design (0 disables)")
     ap.add_argument("--batch-steps", type=int, default=20,
@@ -194,6 +197,15 @@ def main():
               "multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        n = 128 * 1024 * 1024 // 4
+        x = torch.rand(n, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}), flush=True)
+        return
     import paper_2206_12661_amd as g
     import synth_ofa
 

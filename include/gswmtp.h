@@ -228,7 +228,7 @@ const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
 
 /* Batched form: several independent plans (one hologram each, any sizes)
  * iterated together.  Each stage of a pass of Algorithm 1 (forward product of
- * Eq. 2 with the focus gather, weight update of Eq. 1, scatter, adjoint
+ * Eq. 2 with the focus gather, weight update of Algorithm 1, scatter, adjoint
  * product with the phase-only projection) is one grouped launch over the
  * tiles of all plans, replayed from a captured HIP graph.
  *

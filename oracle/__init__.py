@@ -176,8 +176,10 @@ def design_loss(I, target, n_ap: int, sum_a2: float, eta_weight: float = 0.1):
         i_n = I_n / sum_m I_m,   eta = sum_m I_m / (n_ap * sum A^2)
 
     (normalised intensities against normalised targets t = T / sum T, as in
-    the weight update of Eq. 1; eta is the efficiency of Sec. 3 in the units
-    of Table 1).  Returns (L, dL/dI)."""
+    the weight update of Algorithm 1; eta is the diffraction efficiency of
+    Sec. 2, energy at the foci over the energy through the aperture, with the
+    incident energy of the discrete sums taken as n_ap * sum A^2).
+    Returns (L, dL/dI)."""
     I = np.asarray(I, dtype=np.float64)
     t = np.asarray(target, dtype=np.float64)
     t = t / t.sum()

@@ -53,7 +53,8 @@ def design_loss(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
                 eta_weight: float = 0.1) -> torch.Tensor:
     """L = sum_n (i_n - t_n)^2 - eta_weight * eta, with normalised
     intensities i = I / sum I against normalised targets t = T / sum T and
-    the efficiency eta = sum I / (n_ap * sum A^2) (Sec. 3, Table 1 units)."""
+    the diffraction efficiency eta = sum I / (n_ap * sum A^2) (Sec. 2; the
+    incident energy of the discrete sums is n_ap * sum A^2)."""
     S = I.sum()
     r = I / S - target / target.sum()
     return (r * r).sum() - eta_weight * S / (float(n_ap) * float(sum_a2))
