@@ -217,13 +217,16 @@ int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_
 
 /* Profiling: run n_iter passes eagerly with HIP events around each stage on
  * the plan's stream and return the mean milliseconds per launch of each stage
- * in ms_out[GSWMTP_N_STAGES] (order: forward product, gather, focus update,
- * scatter, adjoint product + projection).  Changes the plan state exactly as
- * gswmtp_iterate(p, n_iter, 0) would. */
+ * in ms_out[GSWMTP_N_STAGES] (order: forward product with the fused focus
+ * gather, focus update, scatter, adjoint product with the projection, and the
+ * adjoint's split-K tail launch (0 work when the schedule has no tail: the
+ * figure is then the event overhead alone)).  Changes the plan state exactly
+ * as gswmtp_iterate(p, n_iter, 0) would. */
 #define GSWMTP_N_STAGES 5
 int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out);
 
-/* Kernel names of the stages, for matching profiler output (static strings). */
+/* Kernel names of the stages, for matching profiler output (static strings,
+ * "" for a stage without a launch). */
 const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
 
 /* Batched form: several independent plans (one hologram each, any sizes)

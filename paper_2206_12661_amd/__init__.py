@@ -25,7 +25,8 @@ FP32, BF16X3, FP16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3, "bf16x6": BF16X6}
 WEIGHT_GSW, WEIGHT_GS = 0, 1
 N_STAGES = 5
-STAGES = ("forward_product", "gather", "focus_update", "scatter", "adjoint_product_project")
+STAGES = ("forward_product", "focus_update", "scatter", "adjoint_product_project",
+          "adjoint_split_k_tail")
 
 STATUS = {0: "OK", -1: "E_INVAL", -2: "E_DUPFOCUS", -3: "E_EMPTYAPERTURE", -4: "E_NOMEM",
           -5: "E_HIP", -6: "E_NONFINITE", -7: "E_NODEV", -8: "E_UNSUPPORTED"}

@@ -40,6 +40,7 @@ struct gswmtp_batch {
   void *d_sc = nullptr;
   int *d_sc_starts = nullptr;
   int sc_blocks = 0;
+  int max_nf = 0;
   int **d_ctrl = nullptr;
   double **d_stats = nullptr;
   void *pool = nullptr;
@@ -98,7 +99,8 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 hipError_t enqueue_batch_pass(gswmtp_batch *b, hipStream_t s) {
   hipError_t e;
   if ((e = launch_cgemm_grouped(b->fwd, s)) != hipSuccess) return e;
-  if ((e = launch_update_grouped(b->d_upd, (int)b->plans.size(), s)) != hipSuccess) return e;
+  if ((e = launch_update_grouped(b->d_upd, (int)b->plans.size(), b->max_nf, s)) != hipSuccess)
+    return e;
   if ((e = launch_scatter_grouped(b->d_sc, b->d_sc_starts, (int)b->plans.size(), b->sc_blocks,
                                   s)) != hipSuccess)
     return e;
@@ -308,6 +310,7 @@ int batch_build(gswmtp_batch *b) {
     sc_starts[i] = blocks;
     blocks += fill_scatter_args(p, sc.data() + i * ssz);
     ctrl[i] = p->b.ctrl;
+    b->max_nf = std::max(b->max_nf, p->d.nf);
     stats[i] = p->b.stats;
   }
   sc_starts[n] = blocks;

@@ -11,10 +11,10 @@
 namespace gswmtp {
 namespace {
 
-constexpr int kUpdThreads = 1024;
+constexpr int kUpdThreads = 512;
 
-// Deterministic reductions over one 1024-thread workgroup: an xor-shuffle
-// tree inside each wave, then the 16 wave results added in wave order by
+// Deterministic reductions over one kUpdThreads workgroup: an xor-shuffle
+// tree inside each wave, then the kUpdThreads / 64 wave results added in wave order by
 // every thread (one barrier; each call site uses its own LDS slots).
 template <typename Op>
 __device__ __forceinline__ double wave_reduce(double v, Op op) {
@@ -70,7 +70,179 @@ struct UpdateArgs {
 //   (phasor 1 at a dark focus), written scaled by 2^e so its largest
 //   magnitude is in [0.5, 1) - the phase projection discards the scale.
 // All reductions are float64 in a fixed order.
+// Sums and maxima of several values in one pass: one barrier for all.
+template <int NS, int NM>
+__device__ __forceinline__ void block_reduce_mixed(double (&sv)[NS], double (&mv)[NM],
+                                                   double (*slot)[16]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    sv[q] = wave_reduce(sv[q], Sum());
+    if (lane == 0) slot[q][wave] = sv[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NM; ++q) {
+    mv[q] = wave_reduce(mv[q], Max());
+    if (lane == 0) slot[NS + q][wave] = mv[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    double r = slot[q][0];
+    for (int w = 1; w < kUpdThreads / 64; ++w) r += slot[q][w];
+    sv[q] = r;
+  }
+#pragma unroll
+  for (int q = 0; q < NM; ++q) {
+    double r = slot[NS + q][0];
+    for (int w = 1; w < kUpdThreads / 64; ++w) r = r > slot[NS + q][w] ? r : slot[NS + q][w];
+    mv[q] = r;
+  }
+}
+
+// Per-focus values live in registers (FPT foci per thread, n = t + f * kUpdThreads).
+// Two reductions: sum I first; then, from it, the accuracy and uniformity
+// terms and the new weights' amplitude maximum together (everything needed
+// for the termination test and the update), so only one more barrier.  The
+// partials are read in predicated chunks of 16 loads, all in flight at once.
+template <int FPT>
 __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*slots)[16]) {
+  const int t = threadIdx.x;
+  const bool upd = a.mode == UPD_ITERATE;
+  double tn[FPT], tg[FPT], wv[FPT];
+  float thr[FPT], thi[FPT];
+#pragma unroll
+  for (int f = 0; f < FPT; ++f) {
+    const int n = t + f * kUpdThreads;
+    const bool ok = n < a.nf;
+    tn[f] = ok ? a.tnorm[n] : 0.0;
+    tg[f] = ok && upd ? a.target[n] : 0.0;
+    wv[f] = ok && upd ? a.w[n] : 0.0;
+  }
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  const f2 *gp = reinterpret_cast<const f2 *>(a.gpart);
+  constexpr int CHUNK = 16;
+#pragma unroll
+  for (int f = 0; f < FPT; ++f) thr[f] = thi[f] = 0.f;
+  // partials in ascending order; one chunk of every focus of the thread in flight
+  for (int q = 0; q < a.T; q += CHUNK) {
+    f2 v[FPT][CHUNK];
+#pragma unroll
+    for (int f = 0; f < FPT; ++f) {
+      const int n = t + f * kUpdThreads;
+#pragma unroll
+      for (int j = 0; j < CHUNK; ++j)
+        v[f][j] = q + j < a.T && n < a.nf ? gp[(size_t)(q + j) * a.nf + n] : f2{0.f, 0.f};
+    }
+#pragma unroll
+    for (int f = 0; f < FPT; ++f)
+#pragma unroll
+      for (int j = 0; j < CHUNK; ++j)
+        if (q + j < a.T) {
+          thr[f] += v[f][j].x;
+          thi[f] += v[f][j].y;
+        }
+  }
+#pragma unroll
+  for (int f = 0; f < FPT; ++f) {
+    thr[f] *= a.scale;
+    thi[f] *= a.scale;
+  }
+  if (upd && a.ctrl[CTRL_DONE]) return;   // read while the partials were in flight
+  double v1[1] = {0.0};
+#pragma unroll
+  for (int f = 0; f < FPT; ++f) {
+    const int n = t + f * kUpdThreads;
+    if (n >= a.nf) continue;
+    a.theta[2 * n] = thr[f];
+    a.theta[2 * n + 1] = thi[f];
+    const double I = (double)thr[f] * thr[f] + (double)thi[f] * thi[f];
+    a.intensity[n] = (float)I;
+    v1[0] += I;
+  }
+  block_reduce<1>(v1, &slots[0], Sum());
+  const double sI = v1[0];
+  const double inv = sI > 0.0 ? 1.0 / sI : 0.0;
+
+  // accuracy / uniformity terms and the new weights (not yet written)
+  double sv[2] = {0.0, 0.0};                       // sum (t - i)^2, sum i^2
+  double mv[3] = {-INFINITY, -INFINITY, 0.0};      // max r, max -r, max new amplitude
+  double amag[FPT];
+#pragma unroll
+  for (int f = 0; f < FPT; ++f) {
+    amag[f] = 0.0;
+    if (t + f * kUpdThreads >= a.nf) continue;
+    const double re = thr[f], im = thi[f];
+    const double in = (re * re + im * im) * inv;
+    sv[0] += (tn[f] - in) * (tn[f] - in);
+    sv[1] += in * in;
+    if (tn[f] > 0.0) {
+      const double r = in / tn[f];
+      mv[0] = r > mv[0] ? r : mv[0];
+      mv[1] = -r > mv[1] ? -r : mv[1];
+    }
+    if (upd) {
+      if (a.weighting == GSWMTP_WEIGHT_GSW) wv[f] *= sqrt(tn[f] / (in > 1e-30 ? in : 1e-30));
+      amag[f] = wv[f] * sqrt(tg[f]);
+      mv[2] = amag[f] > mv[2] ? amag[f] : mv[2];
+    }
+  }
+  block_reduce_mixed<2, 3>(sv, mv, &slots[1]);
+  const double d2 = sv[0], i2 = sv[1], rmax = mv[0], rmin = -mv[1], amax = mv[2];
+
+  const double xi = i2 > 0.0 ? 1.0 - sqrt(d2) / sqrt(i2) : -INFINITY;
+  const double eta = sI / (a.n_ap * a.sum_a2);
+  const double U = (rmax + rmin) > 0.0 ? 1.0 - (rmax - rmin) / (rmax + rmin) : 0.0;
+  int stop = 0;
+  if (upd) {
+    if (!isfinite(sI)) stop = 1;
+    const double X = a.stats[ST_STOP];
+    if (X > 0.0 && xi > X) stop = 1;
+  }
+  __syncthreads();   // every thread has read ST_STOP and ctrl before thread 0 writes
+  if (t == 0) {
+    a.stats[ST_XI] = xi;
+    a.stats[ST_ETA] = eta;
+    a.stats[ST_U] = U;
+    a.stats[ST_SUMI] = sI;
+    if (upd) {
+      const int h = a.ctrl[CTRL_HIST];
+      double *e = a.hist + 3 * (h % kHistCap);
+      e[0] = xi;
+      e[1] = eta;
+      e[2] = U;
+      a.ctrl[CTRL_HIST] = h + 1;
+      if (!isfinite(sI)) a.ctrl[CTRL_NONFINITE] = 1;
+      if (stop) a.ctrl[CTRL_DONE] = 1;
+    }
+  }
+  if (!upd || stop) return;
+
+  // weights and the new focal field, scaled by 2^e (max magnitude in [0.5, 1))
+  int e = 0;
+  if (amax > 0.0 && isfinite(amax)) e = -ilogb(amax) - 1;
+  const double scale = ldexp(1.0, e);
+#pragma unroll
+  for (int f = 0; f < FPT; ++f) {
+    const int n = t + f * kUpdThreads;
+    if (n >= a.nf) continue;
+    if (a.weighting == GSWMTP_WEIGHT_GSW) a.w[n] = wv[f];
+    const double re = thr[f], im = thi[f];
+    const double mag = sqrt(re * re + im * im);
+    double pr = 1.0, pi = 0.0;
+    if (mag > 0.0) {
+      pr = re / mag;
+      pi = im / mag;
+    }
+    const double am = amag[f] * scale;
+    a.theta_new[2 * n] = (float)(am * pr);
+    a.theta_new[2 * n + 1] = (float)(am * pi);
+  }
+  if (t == 0) a.ctrl[CTRL_ITERS] += 1;
+}
+
+// Any number of foci: per-focus values re-read from memory in each phase.
+__device__ __forceinline__ void focus_update_body_any(const UpdateArgs &a, double (*slots)[16]) {
   const int t = threadIdx.x;
   if (a.mode == UPD_ITERATE && a.ctrl[CTRL_DONE]) return;
 
@@ -176,16 +348,27 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   if (t == 0) a.ctrl[CTRL_ITERS] += 1;
 }
 
+constexpr int kUpdRegFoci = 2;   // foci per thread held in registers
+
+// REG: every focus of the plan(s) fits the register-resident form.
+template <bool REG>
 __global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
   __shared__ double slots[8][16];
-  focus_update_body(a, slots);
+  if constexpr (REG)
+    focus_update_body<kUpdRegFoci>(a, slots);
+  else
+    focus_update_body_any(a, slots);
 }
 
 // One workgroup per plan of a batch.
+template <bool REG>
 __global__ __launch_bounds__(kUpdThreads) void focus_update_grouped(const UpdateArgs *items) {
   __shared__ double slots[8][16];
   const UpdateArgs a = items[blockIdx.x];
-  focus_update_body(a, slots);
+  if constexpr (REG)
+    focus_update_body<kUpdRegFoci>(a, slots);
+  else
+    focus_update_body_any(a, slots);
 }
 
 // Theta_n from the gather partials alone (operator-level forward calls).
@@ -234,7 +417,6 @@ __device__ __forceinline__ void focus_scatter_body(const ScatterArgs &s_, int a,
   float *__restrict__ sr = s_.sr;
   float *__restrict__ si = s_.si;
   const int Ur = s_.Ur, Cp = s_.Cp;
-  if (s_.done && *s_.done) return;
   if (i >= Cp) return;
   float accr = 0.f, acci = 0.f;
   if (a < Ur) {
@@ -248,6 +430,7 @@ __device__ __forceinline__ void focus_scatter_body(const ScatterArgs &s_, int a,
       acci = fmaf(xr, yi, fmaf(xi, yr, acci));
     }
   }
+  if (s_.done && *s_.done) return;   // read after the sums' loads were issued
   sr[(size_t)a * Cp + i] = accr;
   si[(size_t)a * Cp + i] = acci;
 }
@@ -281,7 +464,6 @@ __global__ __launch_bounds__(256) void focus_scatter_split(
     const float *__restrict__ tn, const float *__restrict__ wr, const float *__restrict__ wi,
     const int *__restrict__ ic, const int *__restrict__ ptr, const int *__restrict__ foci,
     unsigned short *__restrict__ st, int Ur, int Urp, int Cp, float scale, const int *done) {
-  if (done && *done) return;
   __shared__ float tr[32][65], ti[32][65];
   const int i0 = blockIdx.x * 64, a0 = blockIdx.y * 32;
   const int tid = threadIdx.x;
@@ -305,6 +487,7 @@ __global__ __launch_bounds__(256) void focus_scatter_split(
     tr[al][il] = accr;
     ti[al][il] = acci;
   }
+  if (done && *done) return;   // uniform; read after the sums' loads were issued
   __syncthreads();
   const int i = tid >> 2, part = tid & 3;   // 64 columns x 4 runs of 8 a
   unsigned short vr[NT][8], vi[NT][8];
@@ -381,7 +564,10 @@ static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
 }
 
 hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(focus_update, dim3(1), dim3(kUpdThreads), 0, s, update_args(p, mode));
+  if (p->d.nf <= kUpdRegFoci * kUpdThreads)
+    hipLaunchKernelGGL(focus_update<true>, dim3(1), dim3(kUpdThreads), 0, s, update_args(p, mode));
+  else
+    hipLaunchKernelGGL(focus_update<false>, dim3(1), dim3(kUpdThreads), 0, s, update_args(p, mode));
   return hipGetLastError();
 }
 
@@ -391,9 +577,13 @@ void fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out) 
   a.T = p->d.Cp / gather_bn;   // partials per focus of the batch's forward tile
   std::memcpy(out, &a, sizeof a);
 }
-hipError_t launch_update_grouped(const void *d_items, int n, hipStream_t s) {
-  hipLaunchKernelGGL(focus_update_grouped, dim3(n), dim3(kUpdThreads), 0, s,
-                     static_cast<const UpdateArgs *>(d_items));
+int update_reg_max_foci() { return kUpdRegFoci * kUpdThreads; }
+hipError_t launch_update_grouped(const void *d_items, int n, int max_nf, hipStream_t s) {
+  const UpdateArgs *items = static_cast<const UpdateArgs *>(d_items);
+  if (max_nf <= kUpdRegFoci * kUpdThreads)
+    hipLaunchKernelGGL(focus_update_grouped<true>, dim3(n), dim3(kUpdThreads), 0, s, items);
+  else
+    hipLaunchKernelGGL(focus_update_grouped<false>, dim3(n), dim3(kUpdThreads), 0, s, items);
   return hipGetLastError();
 }
 

@@ -91,18 +91,8 @@ __device__ __forceinline__ void epilogue(const CgemmArgs &a, v16f (&accR)[MB][NB
           a.cr[o] = cr;
           a.ci[o] = ci;
         } else if constexpr (EPI == EPI_PROJECT) {
-          const float am = a.amp[o];
-          const float mag2 = cr * cr + ci * ci;
-          float pr = 0.f, pi = 0.f;
-          if (am > 0.f) {
-            if (mag2 > 0.f) {
-              const float sc = am * rsqrtf(mag2);
-              pr = cr * sc;
-              pi = ci * sc;
-            } else {
-              pr = am;
-            }
-          }
+          float pr, pi;
+          project_amp(cr, ci, a.amp[o], pr, pi);
           a.cr[o] = pr;
           a.ci[o] = pi;
         } else {
@@ -122,7 +112,6 @@ constexpr int f32_lds_floats() {
 // reduction (phase 1) number `bid` of the schedule in `a`.
 template <int BM, int BN, int EPI>
 __device__ __forceinline__ void cgemm_f32_body(const CgemmArgs &a, const int bid, float *lds) {
-  if (a.done && *a.done) return;
   constexpr int WTM = BM / 2, WTN = BN / 2;    // wave tile (complex)
   constexpr int MB = WTM / 32, NB = WTN / 32;  // 32x32 blocks per wave
   constexpr int SA = BM + 32, SB = BN + 32;    // padded LDS row pitch (floats)
@@ -203,6 +192,13 @@ __device__ __forceinline__ void cgemm_f32_body(const CgemmArgs &a, const int bid
 #pragma unroll
     for (int s = 0; s < NBL; ++s)
       rb[s] = *reinterpret_cast<const v4f *>(gb[s] + (size_t)kb * stepB);
+  }
+  // The done flag is read while the first stage is in flight (the loads are
+  // kept above the test), not before it.
+  const int stop = a.done ? *a.done : 0;
+  asm volatile("" ::: "memory");
+  if (stop) return;
+  if (kb < ke) {
 #pragma unroll
     for (int s = 0; s < NA; ++s) *reinterpret_cast<v4f *>(&sA[la[s]]) = ra[s];
 #pragma unroll
@@ -335,6 +331,48 @@ __global__ __launch_bounds__(kThreads) void cgemm_f32_grouped(const CgemmArgs *i
   cgemm_f32_body<BM, BN, EPI>(a, b - starts[lo], lds);
 }
 
+// Split-K tail with the projection epilogue: adds the K-chunk partials of
+// each tail tile in chunk order (the sums the product's own reduction
+// launch would form) and projects, with many workgroups per tile so the
+// partial reads are spread over the chip.  Block (tail, g) covers slots
+// r = 4g .. 4g + 3 of every (i, j) block of the tile.
+template <int BM, int BN>
+__global__ __launch_bounds__(kThreads) void cgemm_tail_project(CgemmArgs a) {
+  constexpr int MB = BM / 64, NB = BN / 64;
+  constexpr int unit = 2 * MB * NB * 16 * kThreads;
+  const int tail = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+  const int t = a.t_dp + tail;
+  const int m0 = (t % a.tiles_m) * BM, n0 = (t / a.tiles_m) * BN;
+  const float *pt = a.part + (size_t)tail * a.split * unit + tid;
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      float sr[4] = {0.f, 0.f, 0.f, 0.f}, si[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+      for (int c = 0; c < a.split; ++c) {
+        const float *pc = pt + (size_t)c * unit;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int o = (((i * NB + j) * 16 + 4 * g + q) * 2) * kThreads;
+          sr[q] += pc[o];
+          si[q] += pc[o + kThreads];
+        }
+      }
+      if (a.done && *a.done) return;   // read after the partial sums
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int m, n;
+        tile_slot_pos<BM, BN>(tid, i, j, 4 * g + q, m, n);
+        const size_t o = (size_t)(m0 + m) * a.ldc + n0 + n;
+        float pr, pi;
+        project_amp(sr[q], si[q], a.amp[o], pr, pi);
+        a.cr[o] = pr;
+        a.ci[o] = pi;
+      }
+    }
+}
+
 template <int BM, int BN, int EPI>
 hipError_t launch_t(const CgemmArgs &args, int grid, hipStream_t s) {
   hipLaunchKernelGGL((cgemm_f32_mfma<BM, BN, EPI>), dim3(grid), dim3(kThreads), 0, s, args);
@@ -395,7 +433,7 @@ GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_spl
 
 hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float *br,
                         const float *bi, float *cr, float *ci, const float *er,
-                        const float *ei, bool honour_done, hipStream_t s) {
+                        const float *ei, bool honour_done, hipStream_t s, int phases) {
   const Dims &d = p->d;
   const GemmSched &sc = forward ? p->sched_fwd : p->sched_bwd;
   CgemmArgs a{};
@@ -422,9 +460,23 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
   a.t_dp = sc.t_dp;
   a.split = sc.split;
   for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
+    if (!(phases & (1 << phase))) continue;
     a.phase = phase;
     const int grid = phase == 0 ? sc.grid : sc.n_tail;
     hipError_t e = hipErrorInvalidValue;
+    if (phase == 1 && epi == EPI_PROJECT) {
+      const dim3 tg(sc.n_tail, 4);
+#define TAIL(BM, BN) hipLaunchKernelGGL((cgemm_tail_project<BM, BN>), tg, dim3(kThreads), 0, s, a)
+      if (sc.tile.bm == 64 && sc.tile.bn == 64) TAIL(64, 64);
+      else if (sc.tile.bm == 64 && sc.tile.bn == 128) TAIL(64, 128);
+      else if (sc.tile.bm == 128 && sc.tile.bn == 64) TAIL(128, 64);
+      else if (sc.tile.bm == 128 && sc.tile.bn == 128) TAIL(128, 128);
+      else return hipErrorInvalidValue;
+#undef TAIL
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      continue;
+    }
     switch (epi) {
       case EPI_STORE: e = launch_e<EPI_STORE>(sc.tile.bm, sc.tile.bn, a, grid, s); break;
       case EPI_PROJECT: e = launch_e<EPI_PROJECT>(sc.tile.bm, sc.tile.bn, a, grid, s); break;

@@ -136,7 +136,6 @@ __device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
 
 template <int BM, int BN, int BK, bool BF, int NT, int EPI>
 __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
-  if (a.done && *a.done) return;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
   constexpr int PL = 2 * NT;                     // planes per operand
@@ -223,11 +222,14 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
     _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) sA[(BUF) * SA_SZ + la[s_]] = RA[s_]; \
     _Pragma("unroll") for (int s_ = 0; s_ < NBL; ++s_) sB[(BUF) * SB_SZ + lb[s_]] = RB[s_]; \
   } while (0)
-  if (kb < ke) {
-    LOAD_STAGE(r0a, r0b, kb);
-    STORE_STAGE(r0a, r0b, 0);
-  }
+  if (kb < ke) LOAD_STAGE(r0a, r0b, kb);
   if (kb + 1 < ke) LOAD_STAGE(r1a, r1b, kb + 1);
+  // The done flag is read while the first two stages are in flight (the
+  // loads are kept above the test), not before them.
+  const int stop = a.done ? *a.done : 0;
+  asm volatile("" ::: "memory");
+  if (stop) return;
+  if (kb < ke) STORE_STAGE(r0a, r0b, 0);
   __syncthreads();
 
   for (int kt = kb; kt < ke; kt += 2) {
@@ -313,18 +315,8 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const float cr = accR[i][j][4 * g + q], ci = accI[i][j][4 * g + q];
-            const float am = a.amp[(size_t)(m0 + ml + q) * a.ldc + n0 + nl];
-            const float mag2 = cr * cr + ci * ci;
-            float pr = 0.f, pi = 0.f;
-            if (am > 0.f) {
-              if (mag2 > 0.f) {
-                const float sc = am * rsqrtf(mag2);
-                pr = cr * sc;
-                pi = ci * sc;
-              } else {
-                pr = am;
-              }
-            }
+            float pr, pi;
+            project_amp(cr, ci, a.amp[(size_t)(m0 + ml + q) * a.ldc + n0 + nl], pr, pi);
             split_terms<BF, NT>(pr, &tr[0][q], 4);
             split_terms<BF, NT>(pi, &ti[0][q], 4);
           }
@@ -354,6 +346,58 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
   }
 }
 
+// Split-K tail with the projection epilogue: adds the K-chunk partials of
+// each tail tile in chunk order and projects, then writes the 16-bit term
+// planes of P^T (four consecutive rows of one column per thread: one 8-byte
+// store per plane).  Block (tail, g) covers slots r = 4g .. 4g + 3 of every
+// (i, j) block of the tile.
+template <int BM, int BN, bool BF, int NT>
+__global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a) {
+  constexpr int MB = BM / 64, NB = BN / 64;
+  constexpr int unit = 2 * MB * NB * 16 * kThreads;
+  const int tail = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+  const int t = a.t_dp + tail;
+  const int m0 = (t % a.tiles_m) * BM, n0 = (t / a.tiles_m) * BN;
+  const float *pt = a.part + (size_t)tail * a.split * unit + tid;
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      float sr[4] = {0.f, 0.f, 0.f, 0.f}, si[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+      for (int c = 0; c < a.split; ++c) {
+        const float *pc = pt + (size_t)c * unit;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int o = (((i * NB + j) * 16 + 4 * g + q) * 2) * kThreads;
+          sr[q] += pc[o];
+          si[q] += pc[o + kThreads];
+        }
+      }
+      if (a.done && *a.done) return;   // read after the partial sums
+      int m, n;
+      tile_slot_pos<BM, BN>(tid, i, j, 4 * g, m, n);   // rows m .. m + 3, column n
+      unsigned short tr[NT][4], ti[NT][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float pr, pi;
+        project_amp(sr[q], si[q], a.amp[(size_t)(m0 + m + q) * a.ldc + n0 + n], pr, pi);
+        split_terms<BF, NT>(pr, &tr[0][q], 4);
+        split_terms<BF, NT>(pi, &ti[0][q], 4);
+      }
+      const size_t base = (size_t)(n0 + n) * a.M + m0 + m;
+#pragma unroll
+      for (int s = 0; s < NT; ++s) {
+        const u2 vr = {(unsigned)tr[s][0] | ((unsigned)tr[s][1] << 16),
+                       (unsigned)tr[s][2] | ((unsigned)tr[s][3] << 16)};
+        const u2 vi = {(unsigned)ti[s][0] | ((unsigned)ti[s][1] << 16),
+                       (unsigned)ti[s][2] | ((unsigned)ti[s][3] << 16)};
+        *reinterpret_cast<u2 *>(a.pt + (size_t)s * a.pt_plane + base) = vr;
+        *reinterpret_cast<u2 *>(a.pt + (size_t)(NT + s) * a.pt_plane + base) = vi;
+      }
+    }
+}
+
 template <int BM, int BN, int BK, bool BF, int NT, int EPI>
 hipError_t launch_t(const SplitArgs &args, int grid, hipStream_t s) {
   hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI>), dim3(grid), dim3(kThreads), 0,
@@ -365,6 +409,30 @@ template <int BM, int BN, int BK, bool BF, int NT, int EPI>
 hipError_t launch_fit(const SplitArgs &args, int grid, hipStream_t s) {
   if constexpr (split_lds_bytes<BM, BN, BK, NT, EPI>() <= 160 * 1024)
     return launch_t<BM, BN, BK, BF, NT, EPI>(args, grid, s);
+  return hipErrorInvalidValue;
+}
+
+template <bool BF, int NT>
+hipError_t launch_tail_t(const GemmTile &tl, const SplitArgs &a, int n_tail, hipStream_t s) {
+  const dim3 g(n_tail, 4);
+#define TAIL(BM, BN) \
+  hipLaunchKernelGGL((cgemm_tail_project_split<BM, BN, BF, NT>), g, dim3(kThreads), 0, s, a)
+  if (tl.bm == 64 && tl.bn == 64) TAIL(64, 64);
+  else if (tl.bm == 64 && tl.bn == 128) TAIL(64, 128);
+  else if (tl.bm == 128 && tl.bn == 64) TAIL(128, 64);
+  else if (tl.bm == 128 && tl.bn == 128) TAIL(128, 128);
+  else return hipErrorInvalidValue;
+#undef TAIL
+  return hipGetLastError();
+}
+
+hipError_t launch_tail_split(int precision, const GemmTile &tl, const SplitArgs &a, int n_tail,
+                             hipStream_t s) {
+  switch (precision) {
+    case GSWMTP_BF16X3: return launch_tail_t<true, 2>(tl, a, n_tail, s);
+    case GSWMTP_FP16X3: return launch_tail_t<false, 2>(tl, a, n_tail, s);
+    case GSWMTP_BF16X6: return launch_tail_t<true, 3>(tl, a, n_tail, s);
+  }
   return hipErrorInvalidValue;
 }
 
@@ -399,7 +467,8 @@ hipError_t launch_p(int precision, const GemmTile &tl, const SplitArgs &args, in
 
 hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
                               const unsigned short *bt, float *cr, float *ci,
-                              unsigned short *pt_out, bool honour_done, hipStream_t s) {
+                              unsigned short *pt_out, bool honour_done, hipStream_t s,
+                              int phases) {
   const Dims &d = p->d;
   const GemmSched &sc = forward ? p->sched_fwd : p->sched_bwd;
   const int nt = split_terms_of(p->precision);
@@ -437,8 +506,14 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
   a.t_dp = sc.t_dp;
   a.split = sc.split;
   for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
+    if (!(phases & (1 << phase))) continue;
     a.phase = phase;
     const int grid = phase == 0 ? sc.grid : sc.n_tail;
+    if (phase == 1 && epi == EPI_PROJECT) {
+      const hipError_t e = launch_tail_split(p->precision, sc.tile, a, sc.n_tail, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     const hipError_t e = epi == EPI_STORE    ? launch_p<EPI_STORE>(p->precision, sc.tile, a, grid, s)
                          : epi == EPI_GATHER ? launch_p<EPI_GATHER>(p->precision, sc.tile, a, grid, s)
                                              : launch_p<EPI_PROJECT>(p->precision, sc.tile, a, grid, s);

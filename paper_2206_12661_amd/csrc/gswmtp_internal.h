@@ -128,6 +128,34 @@ __device__ __forceinline__ float join_terms(bool bf, int nt, const unsigned shor
   return v;
 }
 
+// Phase-only projection of one back-propagated sample onto the amplitude
+// constraint: A c / |c|, phasor 1 where c = 0, 0 outside the aperture.
+__device__ __forceinline__ void project_amp(float cr, float ci, float am, float &pr, float &pi) {
+  const float mag2 = cr * cr + ci * ci;
+  pr = 0.f;
+  pi = 0.f;
+  if (am > 0.f) {
+    if (mag2 > 0.f) {
+      const float sc = am * rsqrtf(mag2);
+      pr = cr * sc;
+      pi = ci * sc;
+    } else {
+      pr = am;
+    }
+  }
+}
+
+// Position in the BM x BN tile of partial-sum slot (i, j, r) of thread tid
+// of a four-wave product workgroup (wave quadrants of (BM/2) x (BN/2), 32x32
+// MFMA blocks; item r of lane (l32, h) is row 8 (r/4) + 4 h + r % 4, column l32).
+template <int BM, int BN>
+__device__ __forceinline__ void tile_slot_pos(int tid, int i, int j, int r, int &m, int &n) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1, l32 = lane & 31, h = lane >> 5;
+  m = wm * (BM / 2) + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+  n = wn * (BN / 2) + j * 32 + l32;
+}
+
 struct GemmTile { int bm = 64, bn = 64, bk = 16; };   // complex tile M x N, K per stage
 
 // Launch schedule of one complex product: t_dp whole tiles, then n_tail tiles
@@ -268,14 +296,16 @@ namespace gswmtp {
 // Kernel launchers (stream-ordered, no synchronisation).
 // honour_done: the kernel returns at once when the plan's done flag is set
 // (early termination inside a queued / graph-replayed run of passes).
+// phases: bit 0 the product launch, bit 1 the split-K tail launch (if any).
 hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float *br,
                         const float *bi, float *cr, float *ci, const float *er,
-                        const float *ei, bool honour_done, hipStream_t s);
+                        const float *ei, bool honour_done, hipStream_t s, int phases = 3);
 hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s);
 GatherCtx gather_ctx(const gswmtp_plan *p);
 hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
                               const unsigned short *bt, float *cr, float *ci,
-                              unsigned short *pt_out, bool honour_done, hipStream_t s);
+                              unsigned short *pt_out, bool honour_done, hipStream_t s,
+                              int phases = 3);
 hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
                                 bool honour_done, hipStream_t s);
 hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s);
@@ -298,7 +328,7 @@ int fill_cgemm_args(const gswmtp_plan *p, bool forward, int bm, int bn, bool hon
 hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s);
 size_t update_args_bytes();
 void fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out);
-hipError_t launch_update_grouped(const void *d_items, int n, hipStream_t s);
+hipError_t launch_update_grouped(const void *d_items, int n, int max_nf, hipStream_t s);
 size_t scatter_args_bytes();
 int fill_scatter_args(const gswmtp_plan *p, void *out);
 hipError_t launch_scatter_grouped(const void *d_items, const int *d_starts, int n, int blocks,

@@ -695,11 +695,13 @@ hipError_t stage_scatter(gswmtp_plan *p, bool done, hipStream_t s) {
   if (is_split(p)) return launch_scatter_split(p, p->b.theta_new, 1.f, done, s);
   return launch_scatter(p, p->b.theta_new, done, s);
 }
-hipError_t stage_adjoint(gswmtp_plan *p, bool done, hipStream_t s) {
+// phases: 1 the product launch, 2 its split-K tail launch, 3 both.
+hipError_t stage_adjoint(gswmtp_plan *p, bool done, hipStream_t s, int phases = 3) {
   if (is_split(p))
-    return launch_cgemm_split(p, false, EPI_PROJECT, p->b.ss, nullptr, nullptr, p->b.ps, done, s);
+    return launch_cgemm_split(p, false, EPI_PROJECT, p->b.ss, nullptr, nullptr, p->b.ps, done, s,
+                              phases);
   return launch_cgemm(p, false, EPI_PROJECT, p->b.s_r, p->b.s_i, p->b.p_r, p->b.p_i, nullptr,
-                      nullptr, done, s);
+                      nullptr, done, s, phases);
 }
 
 // One GSW pass (Algorithm 1 from forward propagation to the projected pupil).
@@ -1396,15 +1398,15 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out) {
     for (int it = 0; it < n_iter && rc == GSWMTP_OK; ++it) {
       hipEvent_t *e = &ev[(size_t)it * (GSWMTP_N_STAGES + 1)];
       hipError_t er = hipEventRecord(e[0], s);
-      if (er == hipSuccess) er = stage_forward(p, true, s);
+      if (er == hipSuccess) er = stage_forward(p, true, s);   // with the fused focus gather
       if (er == hipSuccess) er = hipEventRecord(e[1], s);
-      // the focus gather runs inside the forward product's epilogue
-      if (er == hipSuccess) er = hipEventRecord(e[2], s);
       if (er == hipSuccess) er = launch_update(p, UPD_ITERATE, s);
-      if (er == hipSuccess) er = hipEventRecord(e[3], s);
+      if (er == hipSuccess) er = hipEventRecord(e[2], s);
       if (er == hipSuccess) er = stage_scatter(p, true, s);
+      if (er == hipSuccess) er = hipEventRecord(e[3], s);
+      if (er == hipSuccess) er = stage_adjoint(p, true, s, 1);
       if (er == hipSuccess) er = hipEventRecord(e[4], s);
-      if (er == hipSuccess) er = stage_adjoint(p, true, s);
+      if (er == hipSuccess) er = stage_adjoint(p, true, s, 2);
       if (er == hipSuccess) er = hipEventRecord(e[5], s);
       if (er != hipSuccess) rc = fail(p, GSWMTP_E_HIP, "time_stages launch", er);
     }
@@ -1428,12 +1430,16 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out) {
 }
 
 const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage) {
+  if (!p) return "";
+  const bool split = is_split(p);
   switch (stage) {
-    case 0: return cgemm_kernel_name(p, true, EPI_STORE);
-    case 1: return "";   // fused into the forward product
-    case 2: return "focus_update";
-    case 3: return "focus_scatter";
-    case 4: return cgemm_kernel_name(p, false, EPI_PROJECT);
+    case 0: return cgemm_kernel_name(p, true, EPI_GATHER);
+    case 1: return "focus_update";
+    case 2: return split ? "focus_scatter_split" : "focus_scatter";
+    case 3: return cgemm_kernel_name(p, false, EPI_PROJECT);
+    case 4:
+      if (p->sched_bwd.n_tail == 0) return "";
+      return split ? "cgemm_tail_project_split" : "cgemm_tail_project";
   }
   return "";
 }
