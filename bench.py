@@ -19,6 +19,7 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -46,6 +47,8 @@ def parse():
                     help="host time budget of the oracle sample (0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-iters", type=int, default=20)
+    ap.add_argument("--no-library-reference", action="store_true",
+                    help="skip timing the vendor BLAS on the product shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 128 MiB device copy 3 times (the known-size "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -54,6 +57,77 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="timed passes of the 64-hologram batch (0 disables)")
     return ap.parse_args()
+
+
+# HBM traffic of the product kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs (committed summary, scaled by the copy calibration); valid only while
+# the kernel sources hash to what they were when the counters were taken.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic__gsw-1152x1920-1000foci.md")
+KERNEL_SOURCES = {
+    "f32": ["paper_2206_12661_amd/csrc/gemm.hip", "paper_2206_12661_amd/csrc/gswmtp_internal.h"],
+    "split": ["paper_2206_12661_amd/csrc/gemm_split.hip",
+              "paper_2206_12661_amd/csrc/gswmtp_internal.h"],
+}
+
+
+def sources_sha(kind: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(mode: str, stage: str):
+    """HBM bytes per launch of the mode's product kernel for `stage`, or None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kind = "f32" if mode == "fp32" else "split"
+    sha = sources_sha(kind)
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if not line.startswith("traffic-record: "):
+                continue
+            r = json.loads(line[len("traffic-record: "):])
+            if r["mode"] == mode and r["stage"] == stage:
+                if r["sources_sha256"] != sha:
+                    return None
+                return {"bytes": r["fetch_kib"] * 1024 * r["fetch_scale"] +
+                        r["write_kib"] * 1024 * r["write_scale"],
+                        "fetch_bytes": r["fetch_kib"] * 1024 * r["fetch_scale"],
+                        "write_bytes": r["write_kib"] * 1024 * r["write_scale"]}
+    return None
+
+
+def library_reference(torch, idx, reps: int = 20) -> dict:
+    """The vendor BLAS (torch.bmm -> hipBLASLt) on plain real GEMMs of the
+    forward product's shape (U_r x R' by R' x C'): 4 float32 products (the
+    4M complex product) and 12 float16 products (the same, split into three
+    16-bit term products each).  A ceiling reference for the hand-written
+    kernels, not part of the path."""
+    if idx["axis"] == 0:
+        M, K, N = idx["uy"], idx["ny_kept"], idx["nx_kept"]
+    else:
+        M, K, N = idx["ux"], idx["nx_kept"], idx["ny_kept"]
+    out = {"shape": [M, K, N]}
+    for name, dt, B in (("f32_x4", torch.float32, 4), ("f16_x12", torch.float16, 12)):
+        a = torch.randn(B, M, K, device="cuda", dtype=dt)
+        b = torch.randn(B, K, N, device="cuda", dtype=dt)
+        for _ in range(3):
+            torch.bmm(a, b)
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch.bmm(a, b)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = sorted(ts)[len(ts) // 2]
+        out[name] = {"ms": round(ms, 5), "tflops": round(2.0 * B * M * N * K / ms / 1e9, 1)}
+        del a, b
+    return out
 
 
 def algorithmic_flops(idx, n_foci) -> dict:
@@ -120,13 +194,18 @@ def run_mode(g, torch, h, mode, args):
             "stage": dom, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": None,
             "flops_per_launch": fl[dom], "mean_launch_ms": round(stages[dom], 5)}
+    tr = traffic_for(mode, dom)
+    if tr is not None:
+        roof["traffic"] = round(tr["bytes"])
+        roof["traffic_fetch"] = round(tr["fetch_bytes"])
+        roof["traffic_write"] = round(tr["write_bytes"])
     if terms > 1:
         # each algorithmic real product issues `terms` 16-bit MFMA products
         roof["term_products"] = terms
         roof["issued_tflops"] = round(achieved * terms, 3)
         roof["issued_frac"] = round(achieved * terms / peak, 4)
     plan.close()
-    return {"mode": mode, "value": ips, "ms_per_step": 1e3 / ips, "roofline": roof,
+    return {"mode": mode, "value": ips, "ms_per_step": 1e3 / ips, "roofline": roof, "index": idx,
             "stage_ms": {k: round(v, 5) for k, v in stages.items()}, "plan_ms": plan_ms,
             "pass_tflops": fl["pass"] * ips / 1e12, "theta0": theta0, "dtype": dt}
 
@@ -237,6 +316,7 @@ def main():
         ok = [m for m in modes if res[m]["traj_err"] <= 2 * ref_err]
         head = max(ok, key=lambda m: res[m]["value"])
     hr = res[head]
+    libref = library_reference(torch, hr["index"]) if not args.no_library_reference else None
     batch = run_batch(g, torch, args) if args.batch_steps > 0 else None
     adam = run_adam(g, torch, args) if args.adam_steps > 0 else None
     out = {
@@ -262,6 +342,7 @@ def main():
                       "roofline": v["roofline"], "stage_ms": v["stage_ms"]}
                   for m, v in res.items()},
         "error_passes": k,
+        "library_gemm_reference": libref,
         "batch": batch,
         "differentiable": adam,
     }
