@@ -113,20 +113,21 @@ def library_reference(torch, idx, reps: int = 20) -> dict:
     for name, dt, B in (("f32_x4", torch.float32, 4), ("f16_x12", torch.float16, 12)):
         a = torch.randn(B, M, K, device="cuda", dtype=dt)
         b = torch.randn(B, K, N, device="cuda", dtype=dt)
+        c = torch.empty(B, M, N, device="cuda", dtype=dt)
         for _ in range(3):
-            torch.bmm(a, b)
-        ts = []
+            torch.bmm(a, b, out=c)
+        torch.cuda.synchronize()
+        # back-to-back launches between one event pair: per-launch kernel time
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            torch.bmm(a, b)
-            e1.record()
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        ms = sorted(ts)[len(ts) // 2]
+            torch.bmm(a, b, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
         out[name] = {"ms": round(ms, 5), "tflops": round(2.0 * B * M * N * K / ms / 1e9, 1)}
-        del a, b
+        del a, b, c
     return out
 
 

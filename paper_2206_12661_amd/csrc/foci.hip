@@ -109,6 +109,11 @@ template <int FPT>
 __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*slots)[16]) {
   const int t = threadIdx.x;
   const bool upd = a.mode == UPD_ITERATE;
+  // every small control value is read up front, beside the per-focus data,
+  // so no load latency is left on the path after the reductions
+  const double X = upd ? a.stats[ST_STOP] : 0.0;
+  const int hist0 = upd && t == 0 ? a.ctrl[CTRL_HIST] : 0;
+  const int iters0 = upd && t == 0 ? a.ctrl[CTRL_ITERS] : 0;
   double tn[FPT], tg[FPT], wv[FPT];
   float thr[FPT], thi[FPT];
 #pragma unroll
@@ -121,7 +126,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   }
   typedef float f2 __attribute__((ext_vector_type(2)));
   const f2 *gp = reinterpret_cast<const f2 *>(a.gpart);
-  constexpr int CHUNK = 16;
+  constexpr int CHUNK = 32;
 #pragma unroll
   for (int f = 0; f < FPT; ++f) thr[f] = thi[f] = 0.f;
   // partials in ascending order; one chunk of every focus of the thread in flight
@@ -196,22 +201,19 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   int stop = 0;
   if (upd) {
     if (!isfinite(sI)) stop = 1;
-    const double X = a.stats[ST_STOP];
     if (X > 0.0 && xi > X) stop = 1;
   }
-  __syncthreads();   // every thread has read ST_STOP and ctrl before thread 0 writes
   if (t == 0) {
     a.stats[ST_XI] = xi;
     a.stats[ST_ETA] = eta;
     a.stats[ST_U] = U;
     a.stats[ST_SUMI] = sI;
     if (upd) {
-      const int h = a.ctrl[CTRL_HIST];
-      double *e = a.hist + 3 * (h % kHistCap);
+      double *e = a.hist + 3 * (hist0 % kHistCap);
       e[0] = xi;
       e[1] = eta;
       e[2] = U;
-      a.ctrl[CTRL_HIST] = h + 1;
+      a.ctrl[CTRL_HIST] = hist0 + 1;
       if (!isfinite(sI)) a.ctrl[CTRL_NONFINITE] = 1;
       if (stop) a.ctrl[CTRL_DONE] = 1;
     }
@@ -238,7 +240,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
     a.theta_new[2 * n] = (float)(am * pr);
     a.theta_new[2 * n + 1] = (float)(am * pi);
   }
-  if (t == 0) a.ctrl[CTRL_ITERS] += 1;
+  if (t == 0) a.ctrl[CTRL_ITERS] = iters0 + 1;
 }
 
 // Any number of foci: per-focus values re-read from memory in each phase.
@@ -401,7 +403,7 @@ __global__ void grad_field(const float *__restrict__ theta, const float *__restr
 struct ScatterArgs {
   const float *tn;
   const float *wr, *wi;
-  const int *ic, *ptr, *foci;
+  const int *ic, *ptr, *foci;     // column index in CSR order; CSR row pointers; foci
   float *sr, *si;
   int Ur, Cp;
   const int *done;
@@ -424,7 +426,7 @@ __device__ __forceinline__ void focus_scatter_body(const ScatterArgs &s_, int a,
     for (int p = p0; p < p1; ++p) {
       const int n = foci[p];
       const float xr = tn[2 * n], xi = tn[2 * n + 1];
-      const size_t o = (size_t)ic[n] * Cp + i;
+      const size_t o = (size_t)ic[p] * Cp + i;   // ic in CSR order
       const float yr = wr[o], yi = -wi[o];
       accr = fmaf(xr, yr, fmaf(-xi, yi, accr));
       acci = fmaf(xr, yi, fmaf(xi, yr, acci));
@@ -458,7 +460,9 @@ __global__ __launch_bounds__(256) void focus_scatter_grouped(const ScatterArgs *
 // planes S^T [re/im][term][Cp][Urp] (the k-contiguous B operand of the
 // split adjoint product).  A block computes a 32 (a) x 64 (i) tile of S with
 // coalesced reads of Wc, transposes it through LDS and writes 8 consecutive a
-// per thread and plane (16 bytes).
+// per thread and plane (16 bytes).  A thread's eight rows advance together
+// (entry k of every row at once), so their loads are in flight together.
+// ic: reduced-grid column of the focus at each CSR position.
 template <bool BF, int NT>
 __global__ __launch_bounds__(256) void focus_scatter_split(
     const float *__restrict__ tn, const float *__restrict__ wr, const float *__restrict__ wi,
@@ -468,24 +472,48 @@ __global__ __launch_bounds__(256) void focus_scatter_split(
   const int i0 = blockIdx.x * 64, a0 = blockIdx.y * 32;
   const int tid = threadIdx.x;
   const int il = tid & 63;
+  constexpr int R = 8;   // rows per thread: a0 + (tid >> 6) + 4 q
+  int p0[R], len[R], kmax = 0;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int al = (tid >> 6) + 4 * q;
-    const int a = a0 + al;
-    float accr = 0.f, acci = 0.f;
-    if (a < Ur) {
-      const int p0 = ptr[a], p1 = ptr[a + 1];
-      for (int pp = p0; pp < p1; ++pp) {
-        const int n = foci[pp];
-        const float xr = tn[2 * n] * scale, xi = tn[2 * n + 1] * scale;
-        const size_t o = (size_t)ic[n] * Cp + i0 + il;
-        const float yr = wr[o], yi = -wi[o];
-        accr = fmaf(xr, yr, fmaf(-xi, yi, accr));
-        acci = fmaf(xr, yi, fmaf(xi, yr, acci));
-      }
+  for (int q = 0; q < R; ++q) {
+    const int a = a0 + (tid >> 6) + 4 * q;
+    const int lo = a < Ur ? ptr[a] : 0, hi = a < Ur ? ptr[a + 1] : 0;
+    p0[q] = lo;
+    len[q] = hi - lo;
+    kmax = len[q] > kmax ? len[q] : kmax;   // uniform across the wave
+  }
+  float accr[R], acci[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) accr[q] = acci[q] = 0.f;
+  for (int k = 0; k < kmax; ++k) {
+    int n[R], c[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const bool on = k < len[q];
+      n[q] = on ? foci[p0[q] + k] : 0;
+      c[q] = on ? ic[p0[q] + k] : 0;
     }
-    tr[al][il] = accr;
-    ti[al][il] = acci;
+    float xr[R], xi[R], yr[R], yi[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const bool on = k < len[q];
+      const size_t o = (size_t)c[q] * Cp + i0 + il;
+      xr[q] = on ? tn[2 * n[q]] * scale : 0.f;
+      xi[q] = on ? tn[2 * n[q] + 1] * scale : 0.f;
+      yr[q] = on ? wr[o] : 0.f;
+      yi[q] = on ? -wi[o] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (k < len[q]) {
+        accr[q] = fmaf(xr[q], yr[q], fmaf(-xi[q], yi[q], accr[q]));
+        acci[q] = fmaf(xr[q], yi[q], fmaf(xi[q], yr[q], acci[q]));
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    tr[(tid >> 6) + 4 * q][il] = accr[q];
+    ti[(tid >> 6) + 4 * q][il] = acci[q];
   }
   if (done && *done) return;   // uniform; read after the sums' loads were issued
   __syncthreads();
@@ -517,7 +545,7 @@ __global__ __launch_bounds__(256) void focus_scatter_split(
 hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
                                 bool honour_done, hipStream_t s) {
   const Dims &d = p->d;
-  const int *ic = d.axis == 0 ? p->b.ix : p->b.iy;
+  const int *ic = p->b.csr_ic;
   const dim3 grid(d.Cp / 64, d.Urp / 32);
   const int *done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
 #define SCATTER_SPLIT(BF, NT)                                                                  \
@@ -599,7 +627,7 @@ static ScatterArgs scatter_args(const gswmtp_plan *p, const float *theta_new, bo
   a.tn = theta_new;
   a.wr = p->b.wc_r;
   a.wi = p->b.wc_i;
-  a.ic = d.axis == 0 ? p->b.ix : p->b.iy;
+  a.ic = p->b.csr_ic;   // CSR order
   a.ptr = p->b.csr_ptr;
   a.foci = p->b.csr_foci;
   a.sr = p->b.s_r;

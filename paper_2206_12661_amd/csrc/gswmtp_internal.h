@@ -59,6 +59,7 @@ struct Bufs {
   float *aeff = nullptr;                 // [ny][nx] effective amplitude (user orientation)
   double *ucoord = nullptr, *vcoord = nullptr;
   int *csr_ptr = nullptr, *csr_foci = nullptr;
+  int *csr_ic = nullptr;                 // reduced-grid column of the focus at each CSR position
   int *scalars = nullptr;                // plan-time integer results
   double *dscalars = nullptr;            // plan-time float64 results
   int *dup = nullptr;

@@ -272,6 +272,13 @@ __global__ __launch_bounds__(256) void k_dup(const int *ix, const int *iy, int n
 }
 
 // Foci sorted by (ir, ic): foci[pos] = n with pos = #{m : key_m < key_n}.
+// Column index of the focus at each CSR position (the scatter reads it
+// beside the focus number instead of through it).
+__global__ void k_csr_gather(const int *ic, const int *foci, int n, int *out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) out[p] = ic[foci[p]];
+}
+
 __global__ __launch_bounds__(256) void k_csr_order(const int *ir, const int *ic, int n,
                                                    int *foci) {
   __shared__ long long tk[256];
@@ -819,7 +826,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     b.cols = c.take<int>(nx); b.col_pos = c.take<int>(nx); b.keep_col = c.take<int>(nx);
     b.aeff = c.take<float>(np);
     b.ucoord = c.take<double>(nx); b.vcoord = c.take<double>(ny);
-    b.csr_foci = c.take<int>(nf); b.csr_ptr = c.take<int>(nf + 1);
+    b.csr_foci = c.take<int>(nf); b.csr_ptr = c.take<int>(nf + 1); b.csr_ic = c.take<int>(nf);
     b.scalars = c.take<int>(16); b.dscalars = c.take<double>(8); b.dup = c.take<int>(1);
     b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
     b.intensity = c.take<float>(nf);
@@ -957,6 +964,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   hipLaunchKernelGGL(k_csr_order, gf, dim3(256), 0, s, ir, ic, (int)nf, b.csr_foci);
   hipLaunchKernelGGL(k_row_ptr, grid1(nf + 1), dim3(256), 0, s, ir, b.csr_foci, (int)nf, D.Ur,
                      b.csr_ptr);
+  hipLaunchKernelGGL(k_csr_gather, grid1(nf), dim3(256), 0, s, ic, b.csr_foci, (int)nf, b.csr_ic);
   const double *rcoord = D.axis == 0 ? b.vcoord : b.ucoord;
   const double *ccoord = D.axis == 0 ? b.ucoord : b.vcoord;
   const int *rkept = D.axis == 0 ? b.rows : b.cols;
