@@ -54,6 +54,9 @@ def _load():
     lib.oracle_gsw.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
                                ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, ctypes.c_int,
                                ctypes.c_double, _D, _I, _D]
+    lib.oracle_gsw_ex.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, ctypes.c_int,
+                                  ctypes.c_double, _D, _I, _D, ctypes.c_int, ctypes.c_int]
     lib.oracle_phase_gradient.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
                                           _D, _D, _D, _D, _D]
@@ -131,10 +134,13 @@ def weight_update(theta, target, w):
     return w, out
 
 
-def gsw(holo, n_iter: Optional[int] = None, stop: float = 0.0, phi=None, w=None) -> dict:
+def gsw(holo, n_iter: Optional[int] = None, stop: float = 0.0, phi=None, w=None,
+        weighting: str = "gsw", phase_fix: int = 0) -> dict:
     """Run Algorithm 1 on a ``synth_ofa.Hologram`` (or any object with the same
     fields).  Returns phi (float64 [ny, nx]), w, history [passes, 3],
-    iters_done and the field of the returned phase."""
+    iters_done and the field of the returned phase.  weighting "gs" keeps
+    unit weights (plain GS); phase_fix = k > 0 freezes the focal phases from
+    the k-th updating pass on (Sec. 2)."""
     n_iter = holo.n_iter if n_iter is None else n_iter
     ny, nx = holo.ny, holo.nx
     amp = _f64(holo.amplitude)
@@ -143,11 +149,12 @@ def gsw(holo, n_iter: Optional[int] = None, stop: float = 0.0, phi=None, w=None)
     hist = np.zeros((max(n_iter, 1), 3))
     done = ctypes.c_int(0)
     th = np.zeros(holo.n_foci, dtype=np.complex128)
-    rc = _load().oracle_gsw(ny, nx, _d(amp), _d(_f64(holo.u)), _d(_f64(holo.v)),
-                            float(holo.s_x), float(holo.s_y), holo.n_foci, _d(_f64(holo.fx)),
-                            _d(_f64(holo.fy)), _d(_f64(holo.target)), _d(ph), _d(ww),
-                            int(n_iter), float(stop), _d(hist), ctypes.byref(done),
-                            th.view(np.float64).ctypes.data_as(_D))
+    rc = _load().oracle_gsw_ex(ny, nx, _d(amp), _d(_f64(holo.u)), _d(_f64(holo.v)),
+                               float(holo.s_x), float(holo.s_y), holo.n_foci, _d(_f64(holo.fx)),
+                               _d(_f64(holo.fy)), _d(_f64(holo.target)), _d(ph), _d(ww),
+                               int(n_iter), float(stop), _d(hist), ctypes.byref(done),
+                               th.view(np.float64).ctypes.data_as(_D),
+                               {"gsw": 0, "gs": 1}[weighting], int(phase_fix))
     if rc:
         raise MemoryError("oracle_gsw")
     passes = done.value + (1 if (stop > 0 and done.value < n_iter) else 0)

@@ -252,17 +252,68 @@ static void project(int np, const double *amp, const double *Ep, double *phi, do
     }
 }
 
-/* Algorithm 1.  phi: in = initial phase, out = phase after the run.  w: in/out
- * weights (pass ones for a fresh start).  hist (nullable): 3 doubles per pass
- * (xi, eta, U of that pass's forward field).  The termination test (xi > stop,
- * disabled when stop <= 0) runs before the update, so a stopping pass leaves
- * phi unchanged and is not counted in iters_done.  theta_final (nullable)
- * receives the field of the returned phase.  Returns 0, or -1 on allocation
- * failure. */
-int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double *v,
-               double sx, double sy, int nf, const double *fx, const double *fy,
-               const double *target, double *phi, double *w, int n_iter, double stop,
-               double *hist, int *iters_done, double *theta_final)
+/* New focal field of one pass with the variants of Sec. 2:
+ *   weighting 0 (GSW, Algorithm 1): w <- w sqrt(t / max(i, tau));
+ *   weighting 1 (plain GS, the comparison method): w unchanged;
+ *   phasor: arg Theta of this pass, or, when fixed != NULL, the stored
+ *   phasors (phase fixing: the focal phases are frozen).
+ * theta_new = w sqrt(target) * phasor. */
+static void weight_update_ex(int nf, const double *theta, const double *target, double *w,
+                             double *theta_new, int weighting, const double *fixed)
+{
+    double sI = 0.0, sT = 0.0;
+    for (int n = 0; n < nf; ++n) {
+        sI += theta[2 * n] * theta[2 * n] + theta[2 * n + 1] * theta[2 * n + 1];
+        sT += target[n];
+    }
+    for (int n = 0; n < nf; ++n) {
+        double re = theta[2 * n], im = theta[2 * n + 1];
+        double I = re * re + im * im;
+        if (weighting == 0) {
+            double in = sI > 0.0 ? I / sI : 0.0;
+            double tn = target[n] / sT;
+            w[n] *= sqrt(tn / (in > ORACLE_TAU ? in : ORACLE_TAU));
+        }
+        double pr = 1.0, pi = 0.0;
+        if (fixed) {
+            pr = fixed[2 * n];
+            pi = fixed[2 * n + 1];
+        } else {
+            double mag = sqrt(I);
+            if (mag > 0.0) { pr = re / mag; pi = im / mag; }
+        }
+        double a = w[n] * sqrt(target[n]);
+        theta_new[2 * n] = a * pr;
+        theta_new[2 * n + 1] = a * pi;
+    }
+}
+
+/* Phasors arg Theta_n (1 where Theta_n = 0). */
+static void phasors(int nf, const double *theta, double *out)
+{
+    for (int n = 0; n < nf; ++n) {
+        double re = theta[2 * n], im = theta[2 * n + 1];
+        double mag = sqrt(re * re + im * im);
+        out[2 * n] = mag > 0.0 ? re / mag : 1.0;
+        out[2 * n + 1] = mag > 0.0 ? im / mag : 0.0;
+    }
+}
+
+/* Algorithm 1 with the variants of Sec. 2.  phi: in = initial phase, out =
+ * phase after the run.  w: in/out weights (pass ones for a fresh start).
+ * hist (nullable): 3 doubles per pass (xi, eta, U of that pass's forward
+ * field).  The termination test (xi > stop, disabled when stop <= 0) runs
+ * before the update, so a stopping pass leaves phi unchanged and is not
+ * counted in iters_done.  theta_final (nullable) receives the field of the
+ * returned phase.  weighting: 0 GSW, 1 GS.  phase_fix > 0: the focal phases
+ * are frozen from the phase_fix-th updating pass on (the phasors of that
+ * pass's forward field are recorded and used by it and every later pass;
+ * <= 0 disables).  Returns 0, or -1 on allocation failure. */
+int oracle_gsw_ex(int ny, int nx, const double *amp, const double *u, const double *v,
+                  double sx, double sy, int nf, const double *fx, const double *fy,
+                  const double *target, double *phi, double *w, int n_iter, double stop,
+                  double *hist, int *iters_done, double *theta_final, int weighting,
+                  int phase_fix)
 {
     const size_t np = (size_t)ny * nx;
     tables t;
@@ -270,8 +321,9 @@ int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double 
     double *Ep = malloc(sizeof(double) * 2 * np);
     double *th = malloc(sizeof(double) * 2 * (size_t)nf);
     double *thn = malloc(sizeof(double) * 2 * (size_t)nf);
+    double *fix = malloc(sizeof(double) * 2 * (size_t)nf);
     int rc = -1;
-    if (!E || !Ep || !th || !thn) goto done;
+    if (!E || !Ep || !th || !thn || !fix) goto done;
     if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); goto done; }
 
     double n_ap = 0.0, sum_a2 = 0.0;
@@ -284,14 +336,19 @@ int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double 
         E[2 * p] = amp[p] * cos(phi[p]);
         E[2 * p + 1] = amp[p] * sin(phi[p]);
     }
-    int done_passes = 0;
+    int done_passes = 0, recorded = 0;
     for (int it = 0; it < n_iter; ++it) {
         forward_t(&t, E, th);                         /* forward propagation */
         double st[4];
         oracle_stats(nf, th, target, n_ap, sum_a2, st); /* intensity, accuracy */
         if (hist) { hist[3 * it] = st[0]; hist[3 * it + 1] = st[1]; hist[3 * it + 2] = st[2]; }
         if (stop > 0.0 && st[0] > stop) break;        /* termination test */
-        oracle_weight_update(nf, th, target, w, thn); /* weights, focal field */
+        const int j = done_passes + 1;                /* this updating pass, from 1 */
+        if (phase_fix > 0 && j >= phase_fix && !recorded) {
+            phasors(nf, th, fix);                     /* freeze the focal phases */
+            recorded = 1;
+        }
+        weight_update_ex(nf, th, target, w, thn, weighting, recorded ? fix : NULL);
         adjoint_t(&t, thn, Ep);                       /* inverse propagation */
         project((int)np, amp, Ep, phi, E);            /* phase-only constraint */
         ++done_passes;
@@ -301,8 +358,18 @@ int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double 
     tables_free(&t);
     rc = 0;
 done:
-    free(E); free(Ep); free(th); free(thn);
+    free(E); free(Ep); free(th); free(thn); free(fix);
     return rc;
+}
+
+/* Algorithm 1 as printed (GSW weighting, no phase fixing). */
+int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double *v,
+               double sx, double sy, int nf, const double *fx, const double *fy,
+               const double *target, double *phi, double *w, int n_iter, double stop,
+               double *hist, int *iters_done, double *theta_final)
+{
+    return oracle_gsw_ex(ny, nx, amp, u, v, sx, sy, nf, fx, fy, target, phi, w, n_iter, stop,
+                         hist, iters_done, theta_final, 0, 0);
 }
 
 /* Gradient of L(phi) = sum_n g_n I_n(phi) with I_n = |Theta_n|^2 and
