@@ -194,6 +194,15 @@ int gswmtp_get_history(gswmtp_plan *p, double *buf, int cap, int *n);
 int gswmtp_get_state(gswmtp_plan *p, float *phi, double *w, int *iters);
 int gswmtp_set_state(gswmtp_plan *p, const float *phi, const double *w, int iters);
 
+/* Phase fixing (the variant of Sec. 2 after Kim et al.): from the
+ * from_pass-th updating pass on (counted like gswmtp_iterations_done, from 1),
+ * the new focal field keeps the focal phases recorded by the first pass that
+ * applies the rule, instead of arg Theta of each pass; the weights keep
+ * updating.  from_pass = 0 turns it off.  Setting it (and set_phase /
+ * set_state) clears the recorded phases.  Stream-ordered; GSWMTP_E_INVAL for
+ * from_pass < 0. */
+int gswmtp_set_phase_fixing(gswmtp_plan *p, int from_pass);
+
 /* Index results (host).  info is required; each array may be NULL:
  * ix, iy [n_foci] gather indices; xu [ux], yu [uy] sorted unique
  * coordinates; rows [ny_kept], cols [nx_kept] kept pupil rows/columns. */

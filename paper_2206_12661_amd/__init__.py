@@ -83,6 +83,7 @@ _SIGNATURES = {
     "gswmtp_get_history": ([_P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "gswmtp_get_state": ([_P, _P, _P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "gswmtp_set_state": ([_P, _P, _P, ctypes.c_int], ctypes.c_int),
+    "gswmtp_set_phase_fixing": ([_P, ctypes.c_int], ctypes.c_int),
     "gswmtp_get_index": ([_P, ctypes.POINTER(gswmtp_index_info), _P, _P, _P, _P, _P, _P],
                          ctypes.c_int),
     "gswmtp_forward_field": ([_P, _P, _P], ctypes.c_int),
@@ -223,6 +224,11 @@ class Plan:
     def iterate(self, n_iter: int, stop_accuracy: float = 0.0):
         self._sync_stream()
         self._check(self._lib.gswmtp_iterate(self._h, int(n_iter), float(stop_accuracy)))
+
+    def set_phase_fixing(self, from_pass: int):
+        """Freeze the focal phases from updating pass `from_pass` on (0: off)."""
+        self._sync_stream()
+        self._check(self._lib.gswmtp_set_phase_fixing(self._h, int(from_pass)))
 
     def iterations_done(self) -> int:
         n = ctypes.c_int(0)

@@ -53,6 +53,7 @@ struct UpdateArgs {
   const double *target;    // [nf] raw target intensities
   const double *tnorm;     // [nf] target / sum(target)
   double *w;               // [nf]
+  double *fixph;           // [2 nf] frozen focal phasors (phase fixing)
   double *stats;           // ST_*
   double *hist;            // [3 kHistCap]
   int *ctrl;               // CTRL_*
@@ -113,8 +114,13 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   // so no load latency is left on the path after the reductions
   const double X = upd ? a.stats[ST_STOP] : 0.0;
   const int hist0 = upd && t == 0 ? a.ctrl[CTRL_HIST] : 0;
-  const int iters0 = upd && t == 0 ? a.ctrl[CTRL_ITERS] : 0;
-  double tn[FPT], tg[FPT], wv[FPT];
+  const int iters0 = upd ? a.ctrl[CTRL_ITERS] : 0;
+  // phase fixing (Sec. 2): from updating pass fix_k on, the focal phasors
+  // are the ones recorded by the first such pass
+  const int fix_k = upd ? a.ctrl[CTRL_FIX] : 0;
+  const bool fixing = fix_k > 0 && iters0 + 1 >= fix_k;
+  const bool recorded = fixing && a.ctrl[CTRL_FIXED] != 0;
+  double tn[FPT], tg[FPT], wv[FPT], fpr[FPT], fpi[FPT];
   float thr[FPT], thi[FPT];
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
@@ -123,6 +129,8 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
     tn[f] = ok ? a.tnorm[n] : 0.0;
     tg[f] = ok && upd ? a.target[n] : 0.0;
     wv[f] = ok && upd ? a.w[n] : 0.0;
+    fpr[f] = ok && recorded ? a.fixph[2 * n] : 1.0;
+    fpi[f] = ok && recorded ? a.fixph[2 * n + 1] : 0.0;
   }
   typedef float f2 __attribute__((ext_vector_type(2)));
   const f2 *gp = reinterpret_cast<const f2 *>(a.gpart);
@@ -229,18 +237,30 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
     const int n = t + f * kUpdThreads;
     if (n >= a.nf) continue;
     if (a.weighting == GSWMTP_WEIGHT_GSW) a.w[n] = wv[f];
-    const double re = thr[f], im = thi[f];
-    const double mag = sqrt(re * re + im * im);
     double pr = 1.0, pi = 0.0;
-    if (mag > 0.0) {
-      pr = re / mag;
-      pi = im / mag;
+    if (recorded) {
+      pr = fpr[f];
+      pi = fpi[f];
+    } else {
+      const double re = thr[f], im = thi[f];
+      const double mag = sqrt(re * re + im * im);
+      if (mag > 0.0) {
+        pr = re / mag;
+        pi = im / mag;
+      }
+      if (fixing) {
+        a.fixph[2 * n] = pr;
+        a.fixph[2 * n + 1] = pi;
+      }
     }
     const double am = amag[f] * scale;
     a.theta_new[2 * n] = (float)(am * pr);
     a.theta_new[2 * n + 1] = (float)(am * pi);
   }
-  if (t == 0) a.ctrl[CTRL_ITERS] = iters0 + 1;
+  if (t == 0) {
+    a.ctrl[CTRL_ITERS] = iters0 + 1;
+    if (fixing && !recorded) a.ctrl[CTRL_FIXED] = 1;
+  }
 }
 
 // Any number of foci: per-focus values re-read from memory in each phase.
@@ -335,19 +355,35 @@ __device__ __forceinline__ void focus_update_body_any(const UpdateArgs &a, doubl
   int e = 0;
   if (amax > 0.0 && isfinite(amax)) e = -ilogb(amax) - 1;
   const double scale = ldexp(1.0, e);
+  const int iters0 = a.ctrl[CTRL_ITERS], fix_k = a.ctrl[CTRL_FIX];
+  const bool fixing = fix_k > 0 && iters0 + 1 >= fix_k;
+  const bool recorded = fixing && a.ctrl[CTRL_FIXED] != 0;
+  __syncthreads();   // every thread has read the control block before thread 0 writes it
   for (int n = t; n < a.nf; n += kUpdThreads) {
-    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
-    const double mag = sqrt(re * re + im * im);
     double pr = 1.0, pi = 0.0;
-    if (mag > 0.0) {
-      pr = re / mag;
-      pi = im / mag;
+    if (recorded) {
+      pr = a.fixph[2 * n];
+      pi = a.fixph[2 * n + 1];
+    } else {
+      const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
+      const double mag = sqrt(re * re + im * im);
+      if (mag > 0.0) {
+        pr = re / mag;
+        pi = im / mag;
+      }
+      if (fixing) {
+        a.fixph[2 * n] = pr;
+        a.fixph[2 * n + 1] = pi;
+      }
     }
     const double amag = a.w[n] * sqrt(a.target[n]) * scale;
     a.theta_new[2 * n] = (float)(amag * pr);
     a.theta_new[2 * n + 1] = (float)(amag * pi);
   }
-  if (t == 0) a.ctrl[CTRL_ITERS] += 1;
+  if (t == 0) {
+    a.ctrl[CTRL_ITERS] = iters0 + 1;
+    if (fixing && !recorded) a.ctrl[CTRL_FIXED] = 1;
+  }
 }
 
 constexpr int kUpdRegFoci = 2;   // foci per thread held in registers
@@ -580,6 +616,7 @@ static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
   a.target = p->b.target;
   a.tnorm = p->b.tnorm;
   a.w = p->b.w;
+  a.fixph = p->b.fixph;
   a.stats = p->b.stats;
   a.hist = p->b.hist;
   a.ctrl = p->b.ctrl;

@@ -33,8 +33,12 @@ constexpr int kPadCols = 64;       // padding granule of the N dimension
 constexpr int kMaxFoci = 262144;
 constexpr int kMaxSide = 16384;
 
-// Control block (device ints): done flag, passes done, history count, non-finite flag.
-enum { CTRL_DONE = 0, CTRL_ITERS = 1, CTRL_HIST = 2, CTRL_NONFINITE = 3, CTRL_N = 8 };
+// Control block (device ints): done flag, passes done, history count,
+// non-finite flag, phase-fixing pass (0: off), phase-fixing phasors recorded.
+enum {
+  CTRL_DONE = 0, CTRL_ITERS = 1, CTRL_HIST = 2, CTRL_NONFINITE = 3, CTRL_FIX = 4, CTRL_FIXED = 5,
+  CTRL_N = 8
+};
 // Stats block (device doubles): xi, eta, U, sum I, stop threshold, ...
 enum { ST_XI = 0, ST_ETA = 1, ST_U = 2, ST_SUMI = 3, ST_STOP = 4, ST_N = 8 };
 
@@ -72,6 +76,7 @@ struct Bufs {
   float *theta = nullptr, *theta_new = nullptr;   // interleaved [2*nf]
   float *intensity = nullptr;            // [nf]
   double *w = nullptr, *stats = nullptr, *hist = nullptr;
+  double *fixph = nullptr;               // [2 nf] frozen focal phasors (phase fixing)
   int *ctrl = nullptr;
   float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
   float *part = nullptr;                 // split-K partial tiles (shared by both products)

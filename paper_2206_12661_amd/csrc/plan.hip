@@ -588,7 +588,17 @@ __global__ void k_set_state(int *ctrl, int iters) {
   ctrl[CTRL_ITERS] = iters;
   ctrl[CTRL_HIST] = 0;
   ctrl[CTRL_DONE] = 0;
+  ctrl[CTRL_FIXED] = 0;
 }
+
+// Phase fixing from updating pass `from` on (0: off); frozen phasors are
+// recorded afresh by the next pass that uses them.
+__global__ void k_set_fix(int *ctrl, int from) {
+  ctrl[CTRL_FIX] = from;
+  ctrl[CTRL_FIXED] = 0;
+}
+
+__global__ void k_clear_fixed(int *ctrl) { ctrl[CTRL_FIXED] = 0; }
 
 inline dim3 grid1(size_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
@@ -830,7 +840,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     b.scalars = c.take<int>(16); b.dscalars = c.take<double>(8); b.dup = c.take<int>(1);
     b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
     b.intensity = c.take<float>(nf);
-    b.w = c.take<double>(nf); b.stats = c.take<double>(ST_N);
+    b.w = c.take<double>(nf); b.stats = c.take<double>(ST_N); b.fixph = c.take<double>(2 * nf);
     b.hist = c.take<double>(3 * (size_t)kHistCap); b.ctrl = c.take<int>(CTRL_N);
     b.iobuf = c.take<float>(2 * np);
   };
@@ -1147,6 +1157,8 @@ int gswmtp_get_phase(gswmtp_plan *p, float *out) {
 
 static int set_phase_impl(gswmtp_plan *p, const float *dev_phi) {
   HIP_TRY(p, encode_phase(p, dev_phi, p->stream));
+  hipLaunchKernelGGL(k_clear_fixed, dim3(1), dim3(1), 0, p->stream, p->b.ctrl);
+  HIP_TRY(p, hipGetLastError());
   p->fwd_valid = false;
   return GSWMTP_OK;
 }
@@ -1273,6 +1285,16 @@ int gswmtp_set_state(gswmtp_plan *p, const float *phi, const double *w, int iter
   hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, p->stream, p->b.ctrl, iters);
   HIP_TRY(p, hipGetLastError());
   HIP_TRY(p, hipStreamSynchronize(p->stream));
+  return GSWMTP_OK;
+}
+
+int gswmtp_set_phase_fixing(gswmtp_plan *p, int from_pass) {
+  if (!p || from_pass < 0) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  hipLaunchKernelGGL(k_set_fix, dim3(1), dim3(1), 0, p->stream, p->b.ctrl, from_pass);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, leave(p));
   return GSWMTP_OK;
 }
 

@@ -116,6 +116,7 @@ def test_null_arguments(lib):
     assert lib.gswmtp_plan_destroy(None) == 0
     assert lib.gswmtp_desc_init(None) == -1
     assert lib.gswmtp_iterate(None, 1, 0.0) == -1
+    assert lib.gswmtp_set_phase_fixing(None, 1) == -1
     assert lib.gswmtp_batch_destroy(None) == 0
     b = ctypes.c_void_p()
     assert lib.gswmtp_batch_create(None, None, 1, None) == -1
