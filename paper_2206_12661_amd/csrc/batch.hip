@@ -36,11 +36,10 @@ struct gswmtp_batch {
   std::vector<gswmtp_plan *> plans;
   std::vector<hipEvent_t> ev_plan;
   GroupedLaunch fwd, bwd;
-  void *d_upd = nullptr;
+  GroupedUpdate upd;
   void *d_sc = nullptr;
   int *d_sc_starts = nullptr;
   int sc_blocks = 0;
-  int max_nf = 0;
   int **d_ctrl = nullptr;
   double **d_stats = nullptr;
   void *pool = nullptr;
@@ -99,8 +98,7 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 hipError_t enqueue_batch_pass(gswmtp_batch *b, hipStream_t s) {
   hipError_t e;
   if ((e = launch_cgemm_grouped(b->fwd, s)) != hipSuccess) return e;
-  if ((e = launch_update_grouped(b->d_upd, (int)b->plans.size(), b->max_nf, s)) != hipSuccess)
-    return e;
+  if ((e = launch_update_grouped(b->upd, s)) != hipSuccess) return e;
   if ((e = launch_scatter_grouped(b->d_sc, b->d_sc_starts, (int)b->plans.size(), b->sc_blocks,
                                   s)) != hipSuccess)
     return e;
@@ -297,35 +295,54 @@ int batch_build(gswmtp_batch *b) {
   b->fwd.epi = EPI_GATHER;
   b->bwd.epi = EPI_PROJECT;
 
-  // update / scatter items in plan order
+  // update / scatter items in plan order; the many-focus plans' update
+  // items also go to a second table for the update's phases 2 and 3
   const size_t usz = update_args_bytes(), ssz = scatter_args_bytes();
-  std::vector<unsigned char> upd(usz * n), sc(ssz * n);
-  std::vector<int> sc_starts(n + 1);
+  std::vector<unsigned char> upd(usz * n), sc(ssz * n), big;
+  std::vector<int> upd_starts(n + 1), big_starts(1, 0), sc_starts(n + 1);
   std::vector<int *> ctrl(n);
   std::vector<double *> stats(n);
-  int blocks = 0;
+  int blocks = 0, ublocks = 0;
   for (int i = 0; i < n; ++i) {
     gswmtp_plan *p = b->plans[i];
-    fill_update_args(p, UPD_ITERATE, b->fwd.bn, upd.data() + i * usz);
+    const int nwg = fill_update_args(p, UPD_ITERATE, b->fwd.bn, upd.data() + i * usz);
+    upd_starts[i] = ublocks;
+    ublocks += nwg > 0 ? nwg : 1;
+    if (nwg > 0) {
+      big.insert(big.end(), upd.begin() + i * usz, upd.begin() + (i + 1) * usz);
+      big_starts.push_back(big_starts.back() + nwg);
+    }
     sc_starts[i] = blocks;
     blocks += fill_scatter_args(p, sc.data() + i * ssz);
     ctrl[i] = p->b.ctrl;
-    b->max_nf = std::max(b->max_nf, p->d.nf);
     stats[i] = p->b.stats;
   }
+  upd_starts[n] = ublocks;
   sc_starts[n] = blocks;
   b->sc_blocks = blocks;
+  const int nb = (int)big_starts.size() - 1;
 
   const size_t bytes = 2 * grouped_bytes(n) + align256(usz * n) + align256(ssz * n) +
-                       align256((n + 1) * sizeof(int)) + 2 * align256(n * sizeof(void *));
+                       2 * align256((n + 1) * sizeof(int)) + 2 * align256(n * sizeof(void *)) +
+                       align256(usz * (nb > 0 ? nb : 1)) + align256((nb + 1) * sizeof(int));
   BHIP_TRY(b, hipMalloc(&b->pool, bytes));
   char *base = static_cast<char *>(b->pool);
   const GroupedHost hf = build_grouped(b->plans, ofwd, true, b->fwd.bm, b->fwd.bn, false, nullptr);
   const GroupedHost hb = build_grouped(b->plans, obwd, false, b->bwd.bm, b->bwd.bn, false, nullptr);
   if ((rc = upload_grouped(b, hf, base, b->fwd)) != GSWMTP_OK) return rc;
   if ((rc = upload_grouped(b, hb, base, b->bwd)) != GSWMTP_OK) return rc;
-  b->d_upd = base;
+  b->upd.d_items = base;
   base += align256(usz * n);
+  b->upd.d_starts = reinterpret_cast<int *>(base);
+  base += align256((n + 1) * sizeof(int));
+  b->upd.n_items = n;
+  b->upd.blocks = ublocks;
+  b->upd.d_big = base;
+  base += align256(usz * (nb > 0 ? nb : 1));
+  b->upd.d_big_starts = reinterpret_cast<int *>(base);
+  base += align256((nb + 1) * sizeof(int));
+  b->upd.n_big = nb;
+  b->upd.big_blocks = big_starts.back();
   b->d_sc = base;
   base += align256(ssz * n);
   b->d_sc_starts = reinterpret_cast<int *>(base);
@@ -333,7 +350,14 @@ int batch_build(gswmtp_batch *b) {
   b->d_ctrl = reinterpret_cast<int **>(base);
   base += align256(n * sizeof(void *));
   b->d_stats = reinterpret_cast<double **>(base);
-  BHIP_TRY(b, hipMemcpy(b->d_upd, upd.data(), upd.size(), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->upd.d_items, upd.data(), upd.size(), hipMemcpyHostToDevice));
+  BHIP_TRY(b, hipMemcpy(b->upd.d_starts, upd_starts.data(), upd_starts.size() * sizeof(int),
+                        hipMemcpyHostToDevice));
+  if (nb > 0) {
+    BHIP_TRY(b, hipMemcpy(b->upd.d_big, big.data(), big.size(), hipMemcpyHostToDevice));
+    BHIP_TRY(b, hipMemcpy(b->upd.d_big_starts, big_starts.data(), big_starts.size() * sizeof(int),
+                          hipMemcpyHostToDevice));
+  }
   BHIP_TRY(b, hipMemcpy(b->d_sc, sc.data(), sc.size(), hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->d_sc_starts, sc_starts.data(), sc_starts.size() * sizeof(int),
                         hipMemcpyHostToDevice));

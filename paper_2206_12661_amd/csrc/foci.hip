@@ -11,7 +11,6 @@
 namespace gswmtp {
 namespace {
 
-constexpr int kUpdThreads = 512;
 
 // Deterministic reductions over one kUpdThreads workgroup: an xor-shuffle
 // tree inside each wave, then the kUpdThreads / 64 wave results added in wave order by
@@ -57,6 +56,9 @@ struct UpdateArgs {
   double *stats;           // ST_*
   double *hist;            // [3 kHistCap]
   int *ctrl;               // CTRL_*
+  double *s1, *s2;         // many-focus form: per-workgroup partial sums [nwg], [5 nwg]
+  int *snap;               // many-focus form: control values at the start of the pass
+  int nwg;                 // many-focus form: workgroups (ceil(nf / kUpdThreads))
   int nf;
   int mode;                // UPD_ITERATE or UPD_STATS
   int weighting;           // GSWMTP_WEIGHT_*
@@ -263,68 +265,148 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   }
 }
 
-// Any number of foci: per-focus values re-read from memory in each phase.
-__device__ __forceinline__ void focus_update_body_any(const UpdateArgs &a, double (*slots)[16]) {
-  const int t = threadIdx.x;
-  if (a.mode == UPD_ITERATE && a.ctrl[CTRL_DONE]) return;
+// Many foci (more than one workgroup holds in registers): the same update in
+// three launches over nwg = ceil(nf / kUpdThreads) workgroups, one focus per
+// thread, with no synchronisation between workgroups.  Phase 1 forms Theta,
+// I and per-workgroup sums of I; phase 2 reduces those sums (every workgroup
+// alike, fixed order), forms the accuracy / uniformity terms and the new
+// amplitudes, and writes their per-workgroup sums and maxima; phase 3
+// reduces those, takes the termination test and writes the weights and the
+// new focal field.  Control values are read by phase 1 into a snapshot, so
+// phase 3's writes to the control block cannot race with its own reads.
+enum { SNAP_DONE = 0, SNAP_ITERS = 1, SNAP_FIX = 2, SNAP_FIXED = 3, SNAP_HIST = 4 };
 
-  double v1[1] = {0.0};
+__device__ __forceinline__ void big_phase1(const UpdateArgs &a, int b, double (*slots)[16]) {
+  const int t = threadIdx.x, n = b * kUpdThreads + t;
+  const bool upd = a.mode == UPD_ITERATE;
+  if (b == 0 && t == 0) {
+    a.snap[SNAP_DONE] = upd ? a.ctrl[CTRL_DONE] : 0;
+    a.snap[SNAP_ITERS] = a.ctrl[CTRL_ITERS];
+    a.snap[SNAP_FIX] = a.ctrl[CTRL_FIX];
+    a.snap[SNAP_FIXED] = a.ctrl[CTRL_FIXED];
+    a.snap[SNAP_HIST] = a.ctrl[CTRL_HIST];
+  }
   typedef float f2 __attribute__((ext_vector_type(2)));
   const f2 *gp = reinterpret_cast<const f2 *>(a.gpart);
-  for (int n = t; n < a.nf; n += kUpdThreads) {
-    float sr = 0.f, si = 0.f;
-#pragma unroll 8
-    for (int q = 0; q < a.T; ++q) {
-      const f2 v = gp[(size_t)q * a.nf + n];
-      sr += v.x;
-      si += v.y;
-    }
-    sr *= a.scale;
-    si *= a.scale;
+  constexpr int CHUNK = 32;
+  float sr = 0.f, si = 0.f;
+  for (int q = 0; q < a.T; q += CHUNK) {
+    f2 v[CHUNK];
+#pragma unroll
+    for (int j = 0; j < CHUNK; ++j)
+      v[j] = q + j < a.T && n < a.nf ? gp[(size_t)(q + j) * a.nf + n] : f2{0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < CHUNK; ++j)
+      if (q + j < a.T) {
+        sr += v[j].x;
+        si += v[j].y;
+      }
+  }
+  sr *= a.scale;
+  si *= a.scale;
+  if (upd && a.ctrl[CTRL_DONE]) return;
+  double v1[1] = {0.0};
+  if (n < a.nf) {
     a.theta[2 * n] = sr;
     a.theta[2 * n + 1] = si;
     const double I = (double)sr * sr + (double)si * si;
     a.intensity[n] = (float)I;
-    v1[0] += I;
+    v1[0] = I;
   }
   block_reduce<1>(v1, &slots[0], Sum());
-  const double sI = v1[0];
+  if (t == 0) a.s1[b] = v1[0];
+}
 
-  const double inv = sI > 0.0 ? 1.0 / sI : 0.0;
-  double v2[2] = {0.0, 0.0}, v3[2] = {-INFINITY, -INFINITY};   // sums; max r, max -r
-  for (int n = t; n < a.nf; n += kUpdThreads) {
-    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
-    const double in = (re * re + im * im) * inv;
-    const double tn = a.tnorm[n];
-    v2[0] += (tn - in) * (tn - in);
-    v2[1] += in * in;
-    if (tn > 0.0) {
-      const double r = in / tn;
-      v3[0] = r > v3[0] ? r : v3[0];
-      v3[1] = -r > v3[1] ? -r : v3[1];
-    }
+// Sum of the phase-1 partials, identical in every workgroup.
+__device__ __forceinline__ double big_sum_I(const UpdateArgs &a, double (*slots)[16]) {
+  double v[1] = {0.0};
+  for (int j = threadIdx.x; j < a.nwg; j += kUpdThreads) v[0] += a.s1[j];
+  block_reduce<1>(v, &slots[0], Sum());
+  return v[0];
+}
+
+// Per-focus terms of phase 2 / phase 3 (the same arithmetic in both).
+struct BigFocus {
+  double in, tn, tg, w_new, amag;
+  float re, im;
+};
+__device__ __forceinline__ BigFocus big_focus(const UpdateArgs &a, int n, double inv, bool upd) {
+  BigFocus f{};
+  f.re = a.theta[2 * n];
+  f.im = a.theta[2 * n + 1];
+  const double re = f.re, im = f.im;
+  f.in = (re * re + im * im) * inv;
+  f.tn = a.tnorm[n];
+  if (upd) {
+    f.tg = a.target[n];
+    double w = a.w[n];
+    if (a.weighting == GSWMTP_WEIGHT_GSW) w *= sqrt(f.tn / (f.in > 1e-30 ? f.in : 1e-30));
+    f.w_new = w;
+    f.amag = w * sqrt(f.tg);
   }
-  block_reduce<2>(v2, &slots[1], Sum());
-  block_reduce<2>(v3, &slots[3], Max());
-  const double d2 = v2[0], i2 = v2[1], rmax = v3[0], rmin = -v3[1];
+  return f;
+}
 
+__device__ __forceinline__ void big_phase2(const UpdateArgs &a, int b, double (*slots)[16]) {
+  const bool upd = a.mode == UPD_ITERATE;
+  if (upd && a.snap[SNAP_DONE]) return;
+  const int t = threadIdx.x, n = b * kUpdThreads + t;
+  const double sI = big_sum_I(a, slots);
+  const double inv = sI > 0.0 ? 1.0 / sI : 0.0;
+  double sv[2] = {0.0, 0.0}, mv[3] = {-INFINITY, -INFINITY, 0.0};
+  if (n < a.nf) {
+    const BigFocus f = big_focus(a, n, inv, upd);
+    sv[0] = (f.tn - f.in) * (f.tn - f.in);
+    sv[1] = f.in * f.in;
+    if (f.tn > 0.0) {
+      const double r = f.in / f.tn;
+      mv[0] = r;
+      mv[1] = -r;
+    }
+    if (upd) mv[2] = f.amag;
+  }
+  block_reduce_mixed<2, 3>(sv, mv, &slots[1]);
+  if (t == 0) {
+    a.s2[5 * b] = sv[0];
+    a.s2[5 * b + 1] = sv[1];
+    a.s2[5 * b + 2] = mv[0];
+    a.s2[5 * b + 3] = mv[1];
+    a.s2[5 * b + 4] = mv[2];
+  }
+}
+
+__device__ __forceinline__ void big_phase3(const UpdateArgs &a, int b, double (*slots)[16]) {
+  const bool upd = a.mode == UPD_ITERATE;
+  if (upd && a.snap[SNAP_DONE]) return;
+  const int t = threadIdx.x, n = b * kUpdThreads + t;
+  const double sI = big_sum_I(a, slots);
+  const double inv = sI > 0.0 ? 1.0 / sI : 0.0;
+  double sv[2] = {0.0, 0.0}, mv[3] = {-INFINITY, -INFINITY, 0.0};
+  for (int j = t; j < a.nwg; j += kUpdThreads) {
+    sv[0] += a.s2[5 * j];
+    sv[1] += a.s2[5 * j + 1];
+    mv[0] = a.s2[5 * j + 2] > mv[0] ? a.s2[5 * j + 2] : mv[0];
+    mv[1] = a.s2[5 * j + 3] > mv[1] ? a.s2[5 * j + 3] : mv[1];
+    mv[2] = a.s2[5 * j + 4] > mv[2] ? a.s2[5 * j + 4] : mv[2];
+  }
+  block_reduce_mixed<2, 3>(sv, mv, &slots[1]);
+  const double d2 = sv[0], i2 = sv[1], rmax = mv[0], rmin = -mv[1], amax = mv[2];
   const double xi = i2 > 0.0 ? 1.0 - sqrt(d2) / sqrt(i2) : -INFINITY;
   const double eta = sI / (a.n_ap * a.sum_a2);
   const double U = (rmax + rmin) > 0.0 ? 1.0 - (rmax - rmin) / (rmax + rmin) : 0.0;
   int stop = 0;
-  if (a.mode == UPD_ITERATE) {
+  if (upd) {
     if (!isfinite(sI)) stop = 1;
     const double X = a.stats[ST_STOP];
     if (X > 0.0 && xi > X) stop = 1;
   }
-  __syncthreads();   // every thread has read ST_STOP and ctrl before thread 0 writes
-  if (t == 0) {
+  if (b == 0 && t == 0) {
     a.stats[ST_XI] = xi;
     a.stats[ST_ETA] = eta;
     a.stats[ST_U] = U;
     a.stats[ST_SUMI] = sI;
-    if (a.mode == UPD_ITERATE) {
-      const int h = a.ctrl[CTRL_HIST];
+    if (upd) {
+      const int h = a.snap[SNAP_HIST];
       double *e = a.hist + 3 * (h % kHistCap);
       e[0] = xi;
       e[1] = eta;
@@ -334,38 +416,22 @@ __device__ __forceinline__ void focus_update_body_any(const UpdateArgs &a, doubl
       if (stop) a.ctrl[CTRL_DONE] = 1;
     }
   }
-  if (a.mode != UPD_ITERATE || stop) return;
-
-  // weight update and new focal field
-  double v4[1] = {0.0};
-  for (int n = t; n < a.nf; n += kUpdThreads) {
-    const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
-    const double I = re * re + im * im;
-    double w = a.w[n];
-    if (a.weighting == GSWMTP_WEIGHT_GSW) {
-      const double in = I * inv;
-      w *= sqrt(a.tnorm[n] / (in > 1e-30 ? in : 1e-30));
-      a.w[n] = w;
-    }
-    const double amag = w * sqrt(a.target[n]);
-    v4[0] = amag > v4[0] ? amag : v4[0];
-  }
-  block_reduce<1>(v4, &slots[5], Max());
-  const double amax = v4[0];
+  if (!upd || stop) return;
   int e = 0;
   if (amax > 0.0 && isfinite(amax)) e = -ilogb(amax) - 1;
   const double scale = ldexp(1.0, e);
-  const int iters0 = a.ctrl[CTRL_ITERS], fix_k = a.ctrl[CTRL_FIX];
+  const int iters0 = a.snap[SNAP_ITERS], fix_k = a.snap[SNAP_FIX];
   const bool fixing = fix_k > 0 && iters0 + 1 >= fix_k;
-  const bool recorded = fixing && a.ctrl[CTRL_FIXED] != 0;
-  __syncthreads();   // every thread has read the control block before thread 0 writes it
-  for (int n = t; n < a.nf; n += kUpdThreads) {
+  const bool recorded = fixing && a.snap[SNAP_FIXED] != 0;
+  if (n < a.nf) {
+    const BigFocus f = big_focus(a, n, inv, true);
+    if (a.weighting == GSWMTP_WEIGHT_GSW) a.w[n] = f.w_new;
     double pr = 1.0, pi = 0.0;
     if (recorded) {
       pr = a.fixph[2 * n];
       pi = a.fixph[2 * n + 1];
     } else {
-      const double re = a.theta[2 * n], im = a.theta[2 * n + 1];
+      const double re = f.re, im = f.im;
       const double mag = sqrt(re * re + im * im);
       if (mag > 0.0) {
         pr = re / mag;
@@ -376,37 +442,56 @@ __device__ __forceinline__ void focus_update_body_any(const UpdateArgs &a, doubl
         a.fixph[2 * n + 1] = pi;
       }
     }
-    const double amag = a.w[n] * sqrt(a.target[n]) * scale;
-    a.theta_new[2 * n] = (float)(amag * pr);
-    a.theta_new[2 * n + 1] = (float)(amag * pi);
+    const double am = f.amag * scale;
+    a.theta_new[2 * n] = (float)(am * pr);
+    a.theta_new[2 * n + 1] = (float)(am * pi);
   }
-  if (t == 0) {
+  if (b == 0 && t == 0) {
     a.ctrl[CTRL_ITERS] = iters0 + 1;
     if (fixing && !recorded) a.ctrl[CTRL_FIXED] = 1;
   }
 }
 
-constexpr int kUpdRegFoci = 2;   // foci per thread held in registers
+constexpr int kUpdRegFoci = kUpdRegFociMax / kUpdThreads;   // foci per thread in registers
 
-// REG: every focus of the plan(s) fits the register-resident form.
-template <bool REG>
 __global__ __launch_bounds__(kUpdThreads) void focus_update(UpdateArgs a) {
   __shared__ double slots[8][16];
-  if constexpr (REG)
-    focus_update_body<kUpdRegFoci>(a, slots);
-  else
-    focus_update_body_any(a, slots);
+  focus_update_body<kUpdRegFoci>(a, slots);
 }
 
-// One workgroup per plan of a batch.
-template <bool REG>
-__global__ __launch_bounds__(kUpdThreads) void focus_update_grouped(const UpdateArgs *items) {
+template <int PHASE>
+__global__ __launch_bounds__(kUpdThreads) void focus_update_big(UpdateArgs a) {
   __shared__ double slots[8][16];
-  const UpdateArgs a = items[blockIdx.x];
-  if constexpr (REG)
-    focus_update_body<kUpdRegFoci>(a, slots);
-  else
-    focus_update_body_any(a, slots);
+  if constexpr (PHASE == 1) big_phase1(a, blockIdx.x, slots);
+  else if constexpr (PHASE == 2) big_phase2(a, blockIdx.x, slots);
+  else big_phase3(a, blockIdx.x, slots);
+}
+
+// Grouped over the plans of a batch.  Phase 1 launch: item h owns blocks
+// [starts[h], starts[h+1]); a plan in the register form (nwg == 0 in its
+// arguments) has one block that runs its whole update; a many-focus plan
+// runs phase 1 on nwg blocks.  Phases 2 and 3 run over the many-focus plans
+// only (their own item table).
+template <int PHASE>
+__global__ __launch_bounds__(kUpdThreads) void focus_update_grouped(const UpdateArgs *items,
+                                                                    const int *starts, int n) {
+  __shared__ double slots[8][16];
+  const int bid = blockIdx.x;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (starts[mid] <= bid) lo = mid; else hi = mid;
+  }
+  const UpdateArgs a = items[lo];
+  const int b = bid - starts[lo];
+  if constexpr (PHASE == 1) {
+    if (a.nwg == 0) focus_update_body<kUpdRegFoci>(a, slots);
+    else big_phase1(a, b, slots);
+  } else if constexpr (PHASE == 2) {
+    big_phase2(a, b, slots);
+  } else {
+    big_phase3(a, b, slots);
+  }
 }
 
 // Theta_n from the gather partials alone (operator-level forward calls).
@@ -620,6 +705,10 @@ static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
   a.stats = p->b.stats;
   a.hist = p->b.hist;
   a.ctrl = p->b.ctrl;
+  a.s1 = p->b.upd_s1;
+  a.s2 = p->b.upd_s2;
+  a.snap = p->b.upd_snap;
+  a.nwg = update_workgroups(p->d.nf);
   a.nf = p->d.nf;
   a.mode = mode;
   a.weighting = p->weighting;
@@ -629,26 +718,35 @@ static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
 }
 
 hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
-  if (p->d.nf <= kUpdRegFoci * kUpdThreads)
-    hipLaunchKernelGGL(focus_update<true>, dim3(1), dim3(kUpdThreads), 0, s, update_args(p, mode));
-  else
-    hipLaunchKernelGGL(focus_update<false>, dim3(1), dim3(kUpdThreads), 0, s, update_args(p, mode));
+  const UpdateArgs a = update_args(p, mode);
+  if (a.nwg == 0) {
+    hipLaunchKernelGGL(focus_update, dim3(1), dim3(kUpdThreads), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(focus_update_big<1>, dim3(a.nwg), dim3(kUpdThreads), 0, s, a);
+    hipLaunchKernelGGL(focus_update_big<2>, dim3(a.nwg), dim3(kUpdThreads), 0, s, a);
+    hipLaunchKernelGGL(focus_update_big<3>, dim3(a.nwg), dim3(kUpdThreads), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 size_t update_args_bytes() { return sizeof(UpdateArgs); }
-void fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out) {
+int fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out) {
   UpdateArgs a = update_args(p, mode);
   a.T = p->d.Cp / gather_bn;   // partials per focus of the batch's forward tile
   std::memcpy(out, &a, sizeof a);
+  return a.nwg;
 }
-int update_reg_max_foci() { return kUpdRegFoci * kUpdThreads; }
-hipError_t launch_update_grouped(const void *d_items, int n, int max_nf, hipStream_t s) {
-  const UpdateArgs *items = static_cast<const UpdateArgs *>(d_items);
-  if (max_nf <= kUpdRegFoci * kUpdThreads)
-    hipLaunchKernelGGL(focus_update_grouped<true>, dim3(n), dim3(kUpdThreads), 0, s, items);
-  else
-    hipLaunchKernelGGL(focus_update_grouped<false>, dim3(n), dim3(kUpdThreads), 0, s, items);
+hipError_t launch_update_grouped(const GroupedUpdate &g, hipStream_t s) {
+  const UpdateArgs *all = static_cast<const UpdateArgs *>(g.d_items);
+  hipLaunchKernelGGL(focus_update_grouped<1>, dim3(g.blocks), dim3(kUpdThreads), 0, s, all,
+                     g.d_starts, g.n_items);
+  if (g.n_big > 0) {
+    const UpdateArgs *big = static_cast<const UpdateArgs *>(g.d_big);
+    hipLaunchKernelGGL(focus_update_grouped<2>, dim3(g.big_blocks), dim3(kUpdThreads), 0, s,
+                       big, g.d_big_starts, g.n_big);
+    hipLaunchKernelGGL(focus_update_grouped<3>, dim3(g.big_blocks), dim3(kUpdThreads), 0, s,
+                       big, g.d_big_starts, g.n_big);
+  }
   return hipGetLastError();
 }
 

@@ -77,6 +77,8 @@ struct Bufs {
   float *intensity = nullptr;            // [nf]
   double *w = nullptr, *stats = nullptr, *hist = nullptr;
   double *fixph = nullptr;               // [2 nf] frozen focal phasors (phase fixing)
+  double *upd_s1 = nullptr, *upd_s2 = nullptr;   // many-focus update partials
+  int *upd_snap = nullptr;
   int *ctrl = nullptr;
   float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
   float *part = nullptr;                 // split-K partial tiles (shared by both products)
@@ -332,9 +334,26 @@ size_t cgemm_args_bytes();
 int fill_cgemm_args(const gswmtp_plan *p, bool forward, int bm, int bn, bool honour_done,
                     float *cr, float *ci, void *out);
 hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s);
+// Focus update: one workgroup of kUpdThreads holds up to kUpdRegFociMax foci
+// in registers; more foci take the three-launch form over
+// update_workgroups(nf) workgroups.
+constexpr int kUpdThreads = 512;
+constexpr int kUpdRegFociMax = 2 * kUpdThreads;
+inline int update_workgroups(int nf) {
+  return nf <= kUpdRegFociMax ? 0 : (nf + kUpdThreads - 1) / kUpdThreads;
+}
+struct GroupedUpdate {
+  void *d_items = nullptr;     // every plan, phase-1 launch
+  int *d_starts = nullptr;
+  int n_items = 0, blocks = 0;
+  void *d_big = nullptr;       // many-focus plans, phase-2 and -3 launches
+  int *d_big_starts = nullptr;
+  int n_big = 0, big_blocks = 0;
+};
 size_t update_args_bytes();
-void fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out);
-hipError_t launch_update_grouped(const void *d_items, int n, int max_nf, hipStream_t s);
+// Returns the plan's many-focus workgroup count (0: register form, one block).
+int fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out);
+hipError_t launch_update_grouped(const GroupedUpdate &g, hipStream_t s);
 size_t scatter_args_bytes();
 int fill_scatter_args(const gswmtp_plan *p, void *out);
 hipError_t launch_scatter_grouped(const void *d_items, const int *d_starts, int n, int blocks,

@@ -841,6 +841,9 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
     b.intensity = c.take<float>(nf);
     b.w = c.take<double>(nf); b.stats = c.take<double>(ST_N); b.fixph = c.take<double>(2 * nf);
+    b.upd_s1 = c.take<double>((nf + kUpdThreads - 1) / kUpdThreads);
+    b.upd_s2 = c.take<double>(5 * ((nf + kUpdThreads - 1) / kUpdThreads));
+    b.upd_snap = c.take<int>(8);
     b.hist = c.take<double>(3 * (size_t)kHistCap); b.ctrl = c.take<int>(CTRL_N);
     b.iobuf = c.take<float>(2 * np);
   };

@@ -179,6 +179,28 @@ def test_batch_config4_subset(g):
         p.close()
 
 
+def test_batch_many_foci_plans_bit_exact(g, monkeypatch):
+    """Plans over one workgroup's focus capacity (three-launch update) mixed
+    with small ones: batched equals single, bit for bit."""
+    monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
+    monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    hs = [synth_ofa.random_case(71, 150, 170, 1500, roi=60.0),
+          synth_ofa.random_case(72, 90, 100, 40),
+          synth_ofa.random_case(73, 130, 120, 2600, roi=55.0, radius=60.0)]
+    announce("batch with many-foci plans")
+    single = []
+    for h in hs:
+        with g.Plan(h) as p:
+            p.iterate(6)
+            single.append(_state(p))
+    plans = [g.Plan(h) for h in hs]
+    with g.Batch(plans) as b:
+        b.iterate(6)
+    for k, p in enumerate(plans):
+        _assert_same(_state(p), single[k])
+        p.close()
+
+
 def test_batch_rejects(g):
     h = synth_ofa.random_case(45, 40, 50, 8)
     with g.Plan(h) as p, g.Plan(h, precision="fp16x3") as q:

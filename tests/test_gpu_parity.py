@@ -467,3 +467,49 @@ def test_autograd_function(g):
     err = rel_l2(gphi, ref)
     print(f"  autograd grad rel err {err:.2e}")
     assert err <= 1e-4
+
+
+# --------------------------------------------------------------------------
+# Many foci: the focus update in its multi-workgroup form (> 1024 foci)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n_foci", [1025, 3000])
+def test_many_foci_passes(g, n_foci):
+    """More foci than one workgroup holds: the update runs over several
+    workgroups in three launches.  Passes against the oracle (trajectory
+    bar), the stop threshold, and graph replay against eager launches."""
+    h = synth_ofa.random_case(70, 150, 170, n_foci, roi=60.0)
+    n = 4
+    announce(f"many foci {n_foci}")
+    with g.Plan(h) as p:
+        th0 = p.foci_field()
+        p.iterate(n)
+        th = p.foci_field()
+        phi, w = p.phase(), p.weights()
+        hist = p.history()
+    r = oracle.gsw(h, n_iter=n)
+    ref0 = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    assert rel_l2(th0, ref0) <= FIELD_TOL
+    rng = np.random.default_rng(99)
+    rp = oracle.gsw(h, n_iter=n, phi=np.asarray(h.phi0, np.float64) +
+                    1e-6 * rng.standard_normal(h.phi0.shape))
+    bound = max(FIELD_TOL, rel_l2(rp["theta"], r["theta"]))
+    err = rel_l2(th, r["theta"])
+    print(f"  theta after {n} passes {err:.2e} (bound {bound:.2e}); w {rel_l2(w, r['w']):.2e}")
+    assert err <= bound
+    assert np.max(np.abs(hist[:, 0] - r["history"][:, 0])) <= max(1e-5, bound)
+    import os
+    os.environ["GSWMTP_NO_GRAPH"] = "1"
+    try:
+        with g.Plan(h) as p:
+            p.iterate(n)
+            assert np.array_equal(p.phase(), phi) and np.array_equal(p.weights(), w)
+    finally:
+        del os.environ["GSWMTP_NO_GRAPH"]
+    xi = r["history"][:, 0]
+    stop = 0.5 * (xi[1] + xi[2]) if xi[2] > xi[1] else None
+    if stop is not None:
+        with g.Plan(h) as p:
+            p.iterate(n, stop)
+            ro = oracle.gsw(h, n_iter=n, stop=stop)
+            assert p.iterations_done() == ro["iters_done"]
