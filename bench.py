@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 128 MiB device copy 3 times (the known-size "
                          "reference that scales FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the foci-count sweep (k x k arrays up to 227 x 227 on a "
+                         "1000 x 1000 pupil) and the continuous double-heart pattern")
     ap.add_argument("--adam-steps", type=int, default=200,
                     help="Adam steps of the differentiable 50x50-grid design (0 disables)")
     ap.add_argument("--batch-steps", type=int, default=20,
@@ -243,6 +246,37 @@ def run_batch(g, torch, args):
             "tiles": tiles, "setup_ms": round(setup_ms, 1), "steps": args.batch_steps}
 
 
+def run_sweep(g, torch, args):
+    """Foci-count sweep (Sec. 2, Fig. 2(e)): time of 100 passes for uniform
+    k x k arrays on the 1000 x 1000 pupil, FP32 and FP16x3, and the
+    continuous double-heart pattern; accuracy / efficiency after the run."""
+    import synth_ofa
+    cases = [synth_ofa.sweep_case(k) for k in (9, 25, 51, 101, 151, 227)]
+    cases.append(synth_ofa.double_heart())
+    out = []
+    for h in cases:
+        row = {"case": h.name, "n_foci": int(h.n_foci)}
+        for mode in ("fp32", "fp16x3"):
+            with g.Plan(h, precision=mode) as p:
+                idx = p.index()
+                p.iterate(10)
+                p.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                p.iterate(100)
+                p.sync()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                st = p.stats()
+            row["reduced_grid"] = [idx["uy"], idx["ux"]]
+            row[mode] = {"ms_per_100_passes": round(dt * 1e3, 3), "iter_s": round(100 / dt, 1),
+                         "xi": round(st["xi"], 5), "eta": round(st["eta"], 4),
+                         "uniformity": round(st["uniformity"], 4)}
+        out.append(row)
+        print(f"[sweep] {row}", file=sys.stderr, flush=True)
+    return out
+
+
 def run_adam(g, torch, args):
     """The differentiable form: phase design of a 50 x 50 grid on the
     1152 x 1920 pupil by Adam (lr 0.05) through the forward product and the
@@ -320,6 +354,7 @@ def main():
     libref = library_reference(torch, hr["index"]) if not args.no_library_reference else None
     batch = run_batch(g, torch, args) if args.batch_steps > 0 else None
     adam = run_adam(g, torch, args) if args.adam_steps > 0 else None
+    sweep = run_sweep(g, torch, args) if args.sweep else None
     out = {
         "metric": METRIC,
         "value": round(hr["value"], 3), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,
@@ -346,6 +381,7 @@ def main():
         "library_gemm_reference": libref,
         "batch": batch,
         "differentiable": adam,
+        "sweep": sweep,
     }
     print(json.dumps(out), flush=True)
 

@@ -232,6 +232,60 @@ def config5_gradcheck() -> Hologram:
     return _assemble("gradcheck-64x64-4x4grid", ny, nx, amp, fx, fy, t / t.sum(), phi0, 1)
 
 
+# Foci-count sweep (Sec. 2, Fig. 2(e)): uniform k x k arrays on the
+# 1000 x 1000 SLM area of Table 1 at the 20-camera-pixel minimum gap, which is
+# 4.39 focal units in the units of Table 1 (at most 227 x 227 foci).
+SWEEP_PITCH = 4.39
+
+
+def sweep_case(k: int, n_iter: int = 100) -> Hologram:
+    """1000 x 1000 unit-amplitude pupil (the full SLM area); k x k grid at
+    pitch 4.39 focal units; equal targets."""
+    rng = np.random.default_rng([SEED_BASE, 6, k])
+    ny = nx = 1000
+    amp = np.ones((ny, nx), dtype=np.float32)
+    fx, fy = grid_foci(k, k, SWEEP_PITCH)
+    phi0 = initial_phase(rng, ny, nx)
+    return _assemble(f"sweep-{k}x{k}", ny, nx, amp, fx, fy, np.ones(fx.shape[0]), phi0, n_iter)
+
+
+def double_heart(pitch: float = 0.8, n_iter: int = 100) -> Hologram:
+    """A continuous pattern (Sec. 2, Fig. 3(k)-(m) stand-in): two heart
+    shapes filled with samples at a pitch below the diffraction limit (0.8
+    focal units), with a smooth nonuniform target ramp across the pattern, on
+    the 1000 x 1000 pupil.  Heart outline: x = 16 sin^3 t,
+    y = 13 cos t - 5 cos 2t - 2 cos 3t - cos 4t, scaled to 60 focal units
+    wide, the two centred at x = -40 and x = +40."""
+    rng = np.random.default_rng([SEED_BASE, 7])
+    ny = nx = 1000
+    amp = np.ones((ny, nx), dtype=np.float32)
+    t = np.linspace(0.0, 2.0 * np.pi, 2001)
+    hx = 16.0 * np.sin(t) ** 3
+    hy = 13.0 * np.cos(t) - 5.0 * np.cos(2 * t) - 2.0 * np.cos(3 * t) - np.cos(4 * t)
+    sc = 60.0 / 32.0
+    hx, hy = hx * sc, hy * sc
+
+    def inside(px, py):   # even-odd rule against the closed outline
+        c = np.zeros(px.shape, dtype=bool)
+        x0, y0 = hx[:-1], hy[:-1]
+        x1, y1 = hx[1:], hy[1:]
+        for a, b, cc, d in zip(x0, y0, x1, y1):
+            cond = (b > py) != (d > py)
+            xi = a + (py - b) * (cc - a) / np.where(d != b, d - b, 1.0)
+            c ^= cond & (px < xi)
+        return c
+
+    g = np.arange(-40.0, 40.0 + 1e-9, pitch)
+    gx, gy = np.meshgrid(g, g)
+    keep = inside(gx.ravel(), gy.ravel())
+    px, py = gx.ravel()[keep], gy.ravel()[keep]
+    fx = np.concatenate([px - 40.0, px + 40.0])
+    fy = np.concatenate([py, py])
+    target = 0.5 + 0.5 * (fx - fx.min()) / (fx.max() - fx.min())
+    phi0 = initial_phase(rng, ny, nx)
+    return _assemble("double-heart", ny, nx, amp, fx, fy, target, phi0, n_iter)
+
+
 def config(k: int):
     return {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k]()
 
