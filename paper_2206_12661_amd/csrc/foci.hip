@@ -494,6 +494,30 @@ __global__ __launch_bounds__(kUpdThreads) void focus_update_grouped(const Update
   }
 }
 
+// Grid form of the focus gather: Theta_n is entry (ir_n, ic_n) of the dense
+// reduced grid G (written as the single gather partial of focus n).
+__global__ void grid_gather(const float *__restrict__ gr, const float *__restrict__ gi, int ldg,
+                            const int *__restrict__ ir, const int *__restrict__ ic, int nf,
+                            float *__restrict__ gpart) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nf) return;
+  const size_t o = (size_t)ir[n] * ldg + ic[n];
+  gpart[2 * n] = gr[o];
+  gpart[2 * n + 1] = gi[o];
+}
+
+// Grid form of the scatter: Theta'_n onto the transposed grid at (ic_n, ir_n);
+// every other entry of the grid stays zero from plan creation.
+__global__ void grid_scatter(const float *__restrict__ tn, float scale, const int *__restrict__ ir,
+                             const int *__restrict__ ic, int nf, float *__restrict__ tr,
+                             float *__restrict__ ti, int ldt) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nf) return;
+  const size_t o = (size_t)ic[n] * ldt + ir[n];
+  tr[o] = tn[2 * n] * scale;
+  ti[o] = tn[2 * n + 1] * scale;
+}
+
 // Theta_n from the gather partials alone (operator-level forward calls).
 __global__ void gather_reduce(const float *__restrict__ gpart, int T, int nf, float scale,
                               float *__restrict__ theta) {
@@ -686,14 +710,35 @@ hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, fl
 hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s) {
   const int nf = p->d.nf;
   hipLaunchKernelGGL(gather_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.gpart,
-                     p->d.Cp / p->sched_fwd.tile.bn, nf, scale, theta);
+                     gather_partials(p), nf, scale, theta);
+  return hipGetLastError();
+}
+
+int gather_partials(const gswmtp_plan *p) {
+  return p->grid_form ? 1 : p->d.Cp / p->sched_fwd.tile.bn;
+}
+
+hipError_t launch_grid_gather(const gswmtp_plan *p, hipStream_t s) {
+  const Dims &d = p->d;
+  hipLaunchKernelGGL(grid_gather, dim3((d.nf + 255) / 256), dim3(256), 0, s, p->b.g_r, p->b.g_i,
+                     d.Ucp, d.axis == 0 ? p->b.iy : p->b.ix, d.axis == 0 ? p->b.ix : p->b.iy,
+                     d.nf, p->b.gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_scatter(const gswmtp_plan *p, const float *theta_new, float scale,
+                               hipStream_t s) {
+  const Dims &d = p->d;
+  hipLaunchKernelGGL(grid_scatter, dim3((d.nf + 255) / 256), dim3(256), 0, s, theta_new, scale,
+                     d.axis == 0 ? p->b.iy : p->b.ix, d.axis == 0 ? p->b.ix : p->b.iy, d.nf,
+                     p->b.tg_r, p->b.tg_i, d.Urp);
   return hipGetLastError();
 }
 
 static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
   UpdateArgs a{};
   a.gpart = p->b.gpart;
-  a.T = p->d.Cp / p->sched_fwd.tile.bn;
+  a.T = gather_partials(p);
   a.scale = std::ldexp(1.f, -p->amp_exp);
   a.theta = p->b.theta;
   a.theta_new = p->b.theta_new;

@@ -488,6 +488,33 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
   return hipSuccess;
 }
 
+hipError_t launch_cgemm_ex(const gswmtp_plan *p, const GemmSched &sc, const float *atr,
+                           const float *ati, int lda, const float *br, const float *bi, int ldb,
+                           float *cr, float *ci, int ldc, int M, int N, int K, int epi,
+                           bool honour_done, hipStream_t s) {
+  if (epi != EPI_STORE) return hipErrorInvalidValue;
+  if (M % sc.tile.bm || N % sc.tile.bn || K % kBK) return hipErrorInvalidValue;
+  if (sc.tiles_m * sc.tile.bm != M || sc.tiles * sc.tile.bm * sc.tile.bn != M * N)
+    return hipErrorInvalidValue;
+  CgemmArgs a{};
+  a.atr = atr; a.ati = ati; a.lda = lda;
+  a.br = br; a.bi = bi; a.ldb = ldb;
+  a.cr = cr; a.ci = ci; a.ldc = ldc;
+  a.M = M; a.N = N; a.K = K;
+  a.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+  a.part = p->b.part;
+  a.tiles_m = sc.tiles_m;
+  a.t_dp = sc.t_dp;
+  a.split = sc.split;
+  for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
+    a.phase = phase;
+    const hipError_t e = launch_e<EPI_STORE>(sc.tile.bm, sc.tile.bn, a,
+                                             phase == 0 ? sc.grid : sc.n_tail, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 size_t cgemm_args_bytes() { return sizeof(CgemmArgs); }
 
 // Arguments of plan p's product for a grouped (batched) launch with tile

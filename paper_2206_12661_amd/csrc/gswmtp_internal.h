@@ -48,6 +48,7 @@ struct Dims {
   int axis = 0;
   int Rk = 0, Ck = 0, Ur = 0, Uc = 0;   // internal orientation
   int Rp = 0, Cp = 0, Urp = 0;          // padded
+  int Ucp = 0;                          // padded Uc (grid form)
   int n_ap = 0;
   double sum_a2 = 0.0;
 };
@@ -89,6 +90,12 @@ struct Bufs {
   unsigned short *ps = nullptr;          // pupil field P^T    [2][NT][Cp][Rp]
   unsigned short *ss = nullptr;          // scatter S^T        [2][NT][Cp][Urp]
   unsigned short *xs = nullptr;          // operator-call P^T  [2][NT][Cp][Rp]
+  // grid form (float32): the second product of Eq. 2 formed densely
+  float *lt_r = nullptr, *lt_i = nullptr;   // L^T            [Cp][Urp]
+  float *wt_r = nullptr, *wt_i = nullptr;   // Omega_c        [Cp][Ucp]
+  float *wn_i = nullptr;                    // -Im Omega_c^T  [Ucp][Cp] (with wc_r: conj)
+  float *g_r = nullptr, *g_i = nullptr;     // reduced grid   [Urp][Ucp]
+  float *tg_r = nullptr, *tg_i = nullptr;   // new field on the grid, transposed [Ucp][Urp]
 };
 
 // Number of 16-bit terms per float32 operand of a precision mode (0: float32).
@@ -289,6 +296,10 @@ struct gswmtp_plan {
   int precision = GSWMTP_FP32;
   int weighting = GSWMTP_WEIGHT_GSW;
   gswmtp::GemmSched sched_fwd, sched_bwd;
+  // grid form: first product transposed (L^T = P^T Omega_r^T), grid product
+  // G = L Omega_c^T, and the scatter product S = Theta'_grid conj(Omega_c)
+  bool grid_form = false;
+  gswmtp::GemmSched sched_f1, sched_f2, sched_a1;
   int cus = 256;
   int amp_exp = 0;                        // split modes: P carries amp * 2^amp_exp
   void *pool0 = nullptr, *pool1 = nullptr;
@@ -321,6 +332,19 @@ hipError_t launch_grad_field(const gswmtp_plan *p, const float *g, hipStream_t s
 hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,
                           hipStream_t s);
 const char *cgemm_kernel_name(const gswmtp_plan *p, bool forward, int epi);
+// A float32 complex product with explicit operands: C[M][N] = sum_k A[m][k] B[k][n]
+// with A given k-major (AT[k][m], row pitch lda) and B row-major (pitch ldb).
+hipError_t launch_cgemm_ex(const gswmtp_plan *p, const GemmSched &sc, const float *atr,
+                           const float *ati, int lda, const float *br, const float *bi, int ldb,
+                           float *cr, float *ci, int ldc, int M, int N, int K, int epi,
+                           bool honour_done, hipStream_t s);
+// Grid form: Theta_n = G[ir_n][ic_n] into the gather partials (one per focus);
+// Theta'_n onto the transposed grid at (ic_n, ir_n).
+hipError_t launch_grid_gather(const gswmtp_plan *p, hipStream_t s);
+hipError_t launch_grid_scatter(const gswmtp_plan *p, const float *theta_new, float scale,
+                               hipStream_t s);
+// Gather partials per focus of the plan's forward form.
+int gather_partials(const gswmtp_plan *p);
 GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split);
 
 // Grouped launches over the plans of a batch (float32 products).

@@ -350,6 +350,22 @@ __global__ void k_omega_r(const double *coord, const int *kept, int Rk, const do
 }
 
 // Wc[b][i] = exp(-2 pi i s_c uc_i C_b) for b < Uc, i < Cp (0 past Ck).
+// Grid form tables: Omega_c transposed ([Cp][Ucp], B operand of the grid
+// product) and the negated imaginary plane of Omega_c^T ([Ucp][Cp], with the
+// real plane the conjugate, B operand of the scatter product).  Rows and
+// columns past Uc stay zero.
+__global__ void k_grid_tables(const float *wr, const float *wi, int Uc, int Cp, int Ucp,
+                              float *wt_r, float *wt_i, float *wn_i) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Ucp * Cp) return;
+  const int b = (int)(id / Cp), i = (int)(id % Cp);
+  const float re = b < Uc ? wr[(size_t)b * Cp + i] : 0.f;
+  const float im = b < Uc ? wi[(size_t)b * Cp + i] : 0.f;
+  wt_r[(size_t)i * Ucp + b] = re;
+  wt_i[(size_t)i * Ucp + b] = im;
+  wn_i[id] = -im;
+}
+
 __global__ void k_omega_c(const double *coord, const int *kept, int Ck, const double *fu,
                           int Uc, double s, int Cp, float *wr, float *wi) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -702,15 +718,47 @@ bool is_split(const gswmtp_plan *p) { return split_terms_of(p->precision) > 0; }
 // Stages of one pass, in either arithmetic.
 // Forward product with the focus gather fused into its epilogue (partials
 // reduced by the focus update).
+// Float32 forward products for a compacted pupil field (er, ei) [Rp][Cp],
+// leaving Theta's gather partials: the gather form (second product at the
+// foci, in the first product's epilogue) or the grid form (L^T = P^T
+// Omega_r^T, then G = L Omega_c^T on the matrix cores, then Theta_n = G at
+// the focus).
+hipError_t forward_products(gswmtp_plan *p, const float *er, const float *ei, bool done,
+                            hipStream_t s) {
+  if (!p->grid_form)
+    return launch_cgemm(p, true, EPI_GATHER, er, ei, nullptr, nullptr, nullptr, nullptr, done, s);
+  const Dims &D = p->d;
+  Bufs &b = p->b;
+  hipError_t e = launch_cgemm_ex(p, p->sched_f1, er, ei, D.Cp, b.omt_r, b.omt_i, D.Urp, b.lt_r,
+                                 b.lt_i, D.Urp, D.Cp, D.Urp, D.Rp, EPI_STORE, done, s);
+  if (e != hipSuccess) return e;
+  e = launch_cgemm_ex(p, p->sched_f2, b.lt_r, b.lt_i, D.Urp, b.wt_r, b.wt_i, D.Ucp, b.g_r, b.g_i,
+                      D.Ucp, D.Urp, D.Ucp, D.Cp, EPI_STORE, done, s);
+  if (e != hipSuccess) return e;
+  return launch_grid_gather(p, s);
+}
+
+// Float32 scatter of focal values theta (device, interleaved) into S: per
+// row of foci (gather form) or as the product Theta'_grid conj(Omega_c)
+// (grid form).
+hipError_t scatter_products(gswmtp_plan *p, const float *theta, bool done, hipStream_t s) {
+  if (!p->grid_form) return launch_scatter(p, theta, done, s);
+  const Dims &D = p->d;
+  Bufs &b = p->b;
+  hipError_t e = launch_grid_scatter(p, theta, 1.f, s);
+  if (e != hipSuccess) return e;
+  return launch_cgemm_ex(p, p->sched_a1, b.tg_r, b.tg_i, D.Urp, b.wc_r, b.wn_i, D.Cp, b.s_r,
+                         b.s_i, D.Cp, D.Urp, D.Cp, D.Ucp, EPI_STORE, done, s);
+}
+
 hipError_t stage_forward(gswmtp_plan *p, bool done, hipStream_t s) {
   if (is_split(p))
     return launch_cgemm_split(p, true, EPI_GATHER, p->b.ps, nullptr, nullptr, nullptr, done, s);
-  return launch_cgemm(p, true, EPI_GATHER, p->b.p_r, p->b.p_i, nullptr, nullptr, nullptr,
-                      nullptr, done, s);
+  return forward_products(p, p->b.p_r, p->b.p_i, done, s);
 }
 hipError_t stage_scatter(gswmtp_plan *p, bool done, hipStream_t s) {
   if (is_split(p)) return launch_scatter_split(p, p->b.theta_new, 1.f, done, s);
-  return launch_scatter(p, p->b.theta_new, done, s);
+  return scatter_products(p, p->b.theta_new, done, s);
 }
 // phases: 1 the product launch, 2 its split-K tail launch, 3 both.
 hipError_t stage_adjoint(gswmtp_plan *p, bool done, hipStream_t s, int phases = 3) {
@@ -935,18 +983,39 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
                             split_enabled());
   p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, choose_tile(D.Rp, D.Cp, split_mode), p->cus,
                             split_enabled());
-  const size_t part_floats =
+  // Grid form (float32): when the foci fill a quarter or more of the reduced
+  // grid, the second product of Eq. 2 is formed densely on the matrix cores
+  // (as the paper does) instead of per focus.  GSWMTP_SECOND=gather|grid
+  // forces either form.
+  p->grid_form = !split_mode && (double)D.Ur * D.Uc <= 4.0 * D.nf;
+  if (const char *sf = std::getenv("GSWMTP_SECOND")) {
+    if (std::strcmp(sf, "gather") == 0) p->grid_form = false;
+    if (std::strcmp(sf, "grid") == 0 && !split_mode) p->grid_form = true;
+  }
+  D.Ucp = (int)round_up(D.Uc, kPadCols);
+  size_t part_floats =
       std::max<size_t>(std::max(p->sched_fwd.part_floats, p->sched_bwd.part_floats), 1);
+  if (p->grid_form) {
+    p->sched_f1 = make_sched(D.Cp, D.Urp, D.Rp, choose_tile(D.Cp, D.Urp, false), p->cus,
+                             split_enabled());
+    p->sched_f2 = make_sched(D.Urp, D.Ucp, D.Cp, choose_tile(D.Urp, D.Ucp, false), p->cus,
+                             split_enabled());
+    p->sched_a1 = make_sched(D.Urp, D.Cp, D.Ucp, choose_tile(D.Urp, D.Cp, false), p->cus,
+                             split_enabled());
+    part_floats = std::max({part_floats, p->sched_f1.part_floats, p->sched_f2.part_floats,
+                            p->sched_a1.part_floats});
+  }
 
   // ---- pool 1: kernel matrices, pupil and product buffers ----
-  const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc;
+  const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc, Ucp = D.Ucp;
+  const size_t Ucr = p->grid_form ? Ucp : Uc;   // Omega_c rows (zero-padded in the grid form)
   const bool split = is_split(p);
   const size_t nt = (size_t)split_terms_of(p->precision);
   const size_t f32 = split ? 0 : 1;       // float32-only buffers
   auto carve1 = [&](Carver &c) {
     b.omt_r = c.take<float>(f32 * Rp * Urp); b.omt_i = c.take<float>(f32 * Rp * Urp);
     b.omc_r = c.take<float>(f32 * Rp * Urp); b.omc_i = c.take<float>(f32 * Rp * Urp);
-    b.wc_r = c.take<float>(Uc * Cp); b.wc_i = c.take<float>(Uc * Cp);
+    b.wc_r = c.take<float>(Ucr * Cp); b.wc_i = c.take<float>(Ucr * Cp);
     b.amp = c.take<float>(Rp * Cp);
     b.p_r = c.take<float>(f32 * Rp * Cp); b.p_i = c.take<float>(f32 * Rp * Cp);
     b.gpart = c.take<float>(2 * (size_t)(Cp / p->sched_fwd.tile.bn) * nf);
@@ -958,6 +1027,12 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     b.ps = c.take<unsigned short>(2 * nt * Cp * Rp);
     b.xs = c.take<unsigned short>(2 * nt * Cp * Rp);
     b.ss = c.take<unsigned short>(2 * nt * Cp * Urp);
+    const size_t gf = p->grid_form ? 1 : 0;
+    b.lt_r = c.take<float>(gf * Cp * Urp); b.lt_i = c.take<float>(gf * Cp * Urp);
+    b.wt_r = c.take<float>(gf * Cp * Ucp); b.wt_i = c.take<float>(gf * Cp * Ucp);
+    b.wn_i = c.take<float>(gf * Ucp * Cp);
+    b.g_r = c.take<float>(gf * Urp * Ucp); b.g_i = c.take<float>(gf * Urp * Ucp);
+    b.tg_r = c.take<float>(gf * Ucp * Urp); b.tg_i = c.take<float>(gf * Ucp * Urp);
   };
   {
     Carver c(nullptr);
@@ -998,6 +1073,9 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   }
   hipLaunchKernelGGL(k_omega_c, grid1(Uc * Cp), dim3(256), 0, s, ccoord, ckept, D.Ck, cfu,
                      D.Uc, s_c, D.Cp, b.wc_r, b.wc_i);
+  if (p->grid_form)
+    hipLaunchKernelGGL(k_grid_tables, grid1(Ucp * Cp), dim3(256), 0, s, b.wc_r, b.wc_i, D.Uc,
+                       D.Cp, D.Ucp, b.wt_r, b.wt_i, b.wn_i);
   const Orient o = orient_of(p);
   hipLaunchKernelGGL(k_encode_amp, grid1(Rp * Cp), dim3(256), 0, s, o, b.aeff,
                      std::ldexp(1.f, p->amp_exp), (int)nx, D.Rp, D.Cp, b.amp);
@@ -1356,8 +1434,7 @@ int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta) {
     hipLaunchKernelGGL(k_compact_complex, gr, dim3(256), 0, s, o, p->b.iobuf, D.nx, D.Rp, D.Cp,
                        p->b.x_r, p->b.x_i);
     HIP_TRY(p, hipGetLastError());
-    HIP_TRY(p, launch_cgemm(p, true, EPI_GATHER, p->b.x_r, p->b.x_i, nullptr, nullptr, nullptr,
-                            nullptr, false, s));
+    HIP_TRY(p, forward_products(p, p->b.x_r, p->b.x_i, false, s));
   }
   HIP_TRY(p, launch_gather_reduce(p, p->b.theta_new, unscale, s));
   HIP_TRY(p, hipMemcpyAsync(theta, p->b.theta_new, 8 * (size_t)D.nf, hipMemcpyDeviceToHost, s));
@@ -1385,7 +1462,7 @@ int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E) {
     HIP_TRY(p, launch_cgemm_split(p, false, EPI_STORE, p->b.ss, p->b.x_r, p->b.x_i, nullptr,
                                   false, s));
   } else {
-    HIP_TRY(p, launch_scatter(p, p->b.theta_new, false, s));
+    HIP_TRY(p, scatter_products(p, p->b.theta_new, false, s));
     HIP_TRY(p, launch_cgemm(p, false, EPI_STORE, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i,
                             nullptr, nullptr, false, s));
   }
@@ -1407,7 +1484,7 @@ int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_
   hipStream_t s = p->stream;
   HIP_TRY(p, ensure_forward(p));
   HIP_TRY(p, launch_grad_field(p, dev_g, s));
-  HIP_TRY(p, launch_scatter(p, p->b.theta_new, false, s));
+  HIP_TRY(p, scatter_products(p, p->b.theta_new, false, s));
   HIP_TRY(p, launch_cgemm(p, false, EPI_GRAD, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i, p->b.p_r,
                           p->b.p_i, false, s));
   hipLaunchKernelGGL(k_expand_real, grid1((size_t)D.ny * D.nx), dim3(256), 0, s, p->b.x_r,

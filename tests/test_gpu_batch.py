@@ -1,9 +1,10 @@
 """Batched form: several plans iterated together through the C ABI.
 
 A plan's batched result must equal its single-plan result: bit for bit when
-both run the same tiles with no K split (the batch never splits K; single
-plans do not when GSWMTP_NO_SPLITK=1), and within float32 rounding of the
-oracle-tested single path otherwise.  Graph replay must equal eager launches
+both run the same tiles with no K split and the per-focus form of the second
+product (the batch never splits K and always gathers per focus; single
+plans do the same under GSWMTP_NO_SPLITK=1 and GSWMTP_SECOND=gather), and
+within float32 rounding of the oracle-tested single path otherwise.  Graph replay must equal eager launches
 bit for bit.
 """
 import numpy as np
@@ -52,6 +53,7 @@ def _assert_same(a, b):
 def test_batch_bit_exact_vs_single(g, monkeypatch, n_iter):
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
     monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    monkeypatch.setenv("GSWMTP_SECOND", "gather")
     hs = _ragged_set()
     announce(f"batch of {len(hs)} vs single plans, {n_iter} passes")
     single = []
@@ -90,6 +92,7 @@ def test_batch_then_plan_continues(g, monkeypatch):
     """Batched passes followed by single-plan passes equal single passes alone."""
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
     monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    monkeypatch.setenv("GSWMTP_SECOND", "gather")
     hs = _ragged_set()[:3]
     announce("batch 4 passes then plan 3 passes")
     ref = []
@@ -112,6 +115,7 @@ def test_batch_stop_threshold_per_plan(g, monkeypatch):
     the plans stop after different numbers of passes (or run them all)."""
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
     monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    monkeypatch.setenv("GSWMTP_SECOND", "gather")
     hs = [synth_ofa.config1()] + _ragged_set()[:4]
     with g.Plan(hs[0]) as p:
         p.iterate(30)
@@ -184,6 +188,7 @@ def test_batch_many_foci_plans_bit_exact(g, monkeypatch):
     with small ones: batched equals single, bit for bit."""
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
     monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    monkeypatch.setenv("GSWMTP_SECOND", "gather")
     hs = [synth_ofa.random_case(71, 150, 170, 1500, roi=60.0),
           synth_ofa.random_case(72, 90, 100, 40),
           synth_ofa.random_case(73, 130, 120, 2600, roi=55.0, radius=60.0)]

@@ -513,3 +513,69 @@ def test_many_foci_passes(g, n_foci):
             p.iterate(n, stop)
             ro = oracle.gsw(h, n_iter=n, stop=stop)
             assert p.iterations_done() == ro["iters_done"]
+
+
+# --------------------------------------------------------------------------
+# Grid form: the second product formed densely (foci filling the reduced grid)
+# --------------------------------------------------------------------------
+
+def _grid_cases():
+    return {
+        "config1": synth_ofa.config1(),
+        "grid-96x96-7x5": synth_ofa.random_case(12, 96, 96, 0, grid=(7, 5)),
+        "grid-200x300-12x9-disc": synth_ofa.random_case(80, 200, 300, 0, grid=(12, 9),
+                                                        radius=90.0, amplitude="random"),
+        "random-100x150-N70": synth_ofa.random_case(10, 100, 150, 70, amplitude="random"),
+    }
+
+
+@pytest.mark.parametrize("form", ["grid", "gather"])
+@pytest.mark.parametrize("name", list(_grid_cases().keys()))
+def test_second_product_forms_operators(g, monkeypatch, form, name):
+    """Both forms of the second product (forced), forward and adjoint
+    operators against the oracle; float32 bar."""
+    monkeypatch.setenv("GSWMTP_SECOND", form)
+    h = _grid_cases()[name]
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal((h.ny, h.nx)) + 1j * rng.standard_normal((h.ny, h.nx))
+    E = np.where(h.amplitude > 0, E, 0).astype(np.complex64)
+    T = (rng.standard_normal(h.n_foci) + 1j * rng.standard_normal(h.n_foci)).astype(np.complex64)
+    announce(f"second product {form} {name}")
+    with g.Plan(h) as p:
+        got_f = p.forward_field(E)
+        got_a = p.adjoint_field(T)
+        th0 = p.foci_field()
+        idx = p.index()
+    ref_f = oracle.forward(E.astype(np.complex128), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    ref_a = oracle.adjoint(T.astype(np.complex128), h.ny, h.nx, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    ref0 = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    kept = np.zeros((h.ny, h.nx), bool)
+    kept[np.ix_(idx["rows"], idx["cols"])] = True
+    e1, e2, e3 = rel_l2(got_f, ref_f), rel_l2(got_a[kept], ref_a[kept]), rel_l2(th0, ref0)
+    print(f"  forward {e1:.2e} adjoint {e2:.2e} phi0 field {e3:.2e}")
+    assert e1 <= FIELD_TOL and e2 <= FIELD_TOL and e3 <= FIELD_TOL
+    assert np.all(got_a[~kept] == 0)
+
+
+def test_grid_form_passes_against_oracle(g, monkeypatch):
+    """Passes in the grid form (chosen automatically for a full grid) against
+    the oracle's trajectory, and graph replay against eager launches."""
+    h = synth_ofa.random_case(81, 160, 200, 0, grid=(15, 11), radius=75.0)
+    n = 8
+    announce("grid form passes")
+    with g.Plan(h) as p:
+        p.iterate(n)
+        th = p.foci_field()
+        phi = p.phase()
+    r = oracle.gsw(h, n_iter=n)
+    rng = np.random.default_rng(99)
+    rp = oracle.gsw(h, n_iter=n, phi=np.asarray(h.phi0, np.float64) +
+                    1e-6 * rng.standard_normal(h.phi0.shape))
+    bound = max(FIELD_TOL, rel_l2(rp["theta"], r["theta"]))
+    err = rel_l2(th, r["theta"])
+    print(f"  theta {err:.2e} (bound {bound:.2e})")
+    assert err <= bound
+    monkeypatch.setenv("GSWMTP_NO_GRAPH", "1")
+    with g.Plan(h) as p:
+        p.iterate(n)
+        assert np.array_equal(p.phase(), phi)

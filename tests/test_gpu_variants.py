@@ -99,6 +99,7 @@ def test_phase_fixing_persists_across_calls(g):
 def test_phase_fixing_batched_equals_single(g, monkeypatch):
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
     monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x64")
+    monkeypatch.setenv("GSWMTP_SECOND", "gather")
     hs = [synth_ofa.config1(), synth_ofa.random_case(62, 100, 80, 30)]
     announce("phase fixing batched")
     single = []
