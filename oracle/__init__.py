@@ -44,9 +44,9 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_forward.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_int, _D, _D, _D]
-    lib.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]
+    lib.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D]
     lib.oracle_stats.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_double, _D]
     lib.oracle_stats.restype = None
     lib.oracle_weight_update.argtypes = [ctypes.c_int, _D, _D, _D, _D]
@@ -55,11 +55,12 @@ def _load():
                                ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, ctypes.c_int,
                                ctypes.c_double, _D, _I, _D]
     lib.oracle_gsw_ex.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, ctypes.c_int,
+                                  ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, _D,
+                                  ctypes.c_int,
                                   ctypes.c_double, _D, _I, _D, ctypes.c_int, ctypes.c_int]
     lib.oracle_phase_gradient.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
-                                          _D, _D, _D, _D, _D]
+                                          _D, _D, _D, _D, _D, _D]
     _lib = lib
     return lib
 
@@ -75,6 +76,12 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+def _fz(holo):
+    """Axial positions of a hologram's foci (None: all on the focal plane)."""
+    fz = getattr(holo, "fz", None)
+    return None if fz is None else _f64(fz)
+
+
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
 
@@ -83,27 +90,30 @@ def num_threads() -> int:
 # Propagation operators (Eq. 1 / Eq. 2 and its adjoint)
 # ----------------------------------------------------------------------------
 
-def forward(E, u, v, s_x, s_y, fx, fy) -> np.ndarray:
-    """Focal field Theta_n of the complex pupil field E[ny, nx] (complex128)."""
+def forward(E, u, v, s_x, s_y, fx, fy, fz=None) -> np.ndarray:
+    """Focal field Theta_n of the complex pupil field E[ny, nx] (complex128);
+    fz (optional): axial positions (defocus phase of the pupil)."""
     E = np.ascontiguousarray(np.asarray(E, dtype=np.complex128))
     ny, nx = E.shape
     u, v, fx, fy = _f64(u), _f64(v), _f64(fx), _f64(fy)
+    fz = None if fz is None else _f64(fz)
     out = np.zeros(fx.shape[0], dtype=np.complex128)
     rc = _load().oracle_forward(ny, nx, E.view(np.float64).ctypes.data_as(_D), _d(u), _d(v),
-                                float(s_x), float(s_y), fx.shape[0], _d(fx), _d(fy),
+                                float(s_x), float(s_y), fx.shape[0], _d(fx), _d(fy), _d(fz),
                                 out.view(np.float64).ctypes.data_as(_D))
     if rc:
         raise MemoryError("oracle_forward")
     return out
 
 
-def adjoint(theta, ny, nx, u, v, s_x, s_y, fx, fy) -> np.ndarray:
+def adjoint(theta, ny, nx, u, v, s_x, s_y, fx, fy, fz=None) -> np.ndarray:
     """Adjoint field E'[ny, nx] of focal values theta[N] (zero off the foci)."""
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.complex128))
     u, v, fx, fy = _f64(u), _f64(v), _f64(fx), _f64(fy)
+    fz = None if fz is None else _f64(fz)
     out = np.zeros((ny, nx), dtype=np.complex128)
     rc = _load().oracle_adjoint(ny, nx, _d(u), _d(v), float(s_x), float(s_y), fx.shape[0],
-                                _d(fx), _d(fy), theta.view(np.float64).ctypes.data_as(_D),
+                                _d(fx), _d(fy), _d(fz), theta.view(np.float64).ctypes.data_as(_D),
                                 out.view(np.float64).ctypes.data_as(_D))
     if rc:
         raise MemoryError("oracle_adjoint")
@@ -151,7 +161,8 @@ def gsw(holo, n_iter: Optional[int] = None, stop: float = 0.0, phi=None, w=None,
     th = np.zeros(holo.n_foci, dtype=np.complex128)
     rc = _load().oracle_gsw_ex(ny, nx, _d(amp), _d(_f64(holo.u)), _d(_f64(holo.v)),
                                float(holo.s_x), float(holo.s_y), holo.n_foci, _d(_f64(holo.fx)),
-                               _d(_f64(holo.fy)), _d(_f64(holo.target)), _d(ph), _d(ww),
+                               _d(_f64(holo.fy)), _d(_fz(holo)), _d(_f64(holo.target)), _d(ph),
+                               _d(ww),
                                int(n_iter), float(stop), _d(hist), ctypes.byref(done),
                                th.view(np.float64).ctypes.data_as(_D),
                                {"gsw": 0, "gs": 1}[weighting], int(phase_fix))
@@ -170,7 +181,8 @@ def phase_gradient(holo, phi, g):
     rc = _load().oracle_phase_gradient(
         ny, nx, _d(_f64(holo.amplitude)), _d(_f64(holo.u)), _d(_f64(holo.v)),
         float(holo.s_x), float(holo.s_y), holo.n_foci, _d(_f64(holo.fx)), _d(_f64(holo.fy)),
-        _d(_f64(phi)), _d(_f64(g)), _d(grad), th.view(np.float64).ctypes.data_as(_D))
+        _d(_fz(holo)), _d(_f64(phi)), _d(_f64(g)), _d(grad),
+        th.view(np.float64).ctypes.data_as(_D))
     if rc:
         raise MemoryError("oracle_phase_gradient")
     return grad, th
@@ -215,7 +227,8 @@ def adam_design(holo, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     v = np.zeros_like(ph)
     hist = np.zeros(steps)
     for k in range(1, steps + 1):
-        th = forward(pupil_field(holo, ph), holo.u, holo.v, holo.s_x, holo.s_y, holo.fx, holo.fy)
+        th = forward(pupil_field(holo, ph), holo.u, holo.v, holo.s_x, holo.s_y, holo.fx, holo.fy,
+                     _fz(holo))
         L, gI = design_loss(np.abs(th) ** 2, holo.target, n_ap, sum_a2, eta_weight)
         hist[k - 1] = L
         grad, _ = phase_gradient(holo, ph, gI)
@@ -243,15 +256,23 @@ def canonical(c) -> np.ndarray:
     return np.where(c == 0.0, 0.0, c)
 
 
-def unique_coords(c):
-    """Sorted unique coordinates and the gather index of every focus into them.
-    The reduced focal grid of the paper keeps one sample row (column) per
-    distinct focus y (x) coordinate: k x l grid foci give l unique x and k
-    unique y values."""
+def unique_coords(c, z=None):
+    """Sorted unique focal coordinates and the gather index of every focus
+    into them.  The reduced focal grid of the paper keeps one sample row
+    (column) per distinct focus y (x) coordinate: k x l grid foci give l
+    unique x and k unique y values.  With axial positions z, a reduced row is
+    a distinct (coordinate, z) pair (its kernel row carries that plane's
+    defocus phase), ordered by coordinate, then z."""
     key = canonical(c)
-    uniq = np.unique(key)
-    idx = np.searchsorted(uniq, key).astype(np.int32)
-    return uniq, idx
+    if z is None:
+        uniq = np.unique(key)
+        idx = np.searchsorted(uniq, key).astype(np.int32)
+        return uniq, idx
+    zk = canonical(z)
+    pairs = sorted(set(zip(key.tolist(), zk.tolist())))
+    pos = {pz: i for i, pz in enumerate(pairs)}
+    idx = np.array([pos[(a, b)] for a, b in zip(key.tolist(), zk.tolist())], dtype=np.int32)
+    return np.array([a for a, _ in pairs]), idx
 
 
 def compaction(amplitude):
@@ -269,15 +290,16 @@ def axis_choice(ux: int, uy: int) -> int:
     return 1 if ux < uy else 0
 
 
-def has_duplicate_foci(fx, fy) -> bool:
-    pts = np.stack([canonical(fx), canonical(fy)], axis=1)
+def has_duplicate_foci(fx, fy, fz=None) -> bool:
+    cols = [canonical(fx), canonical(fy)] + ([] if fz is None else [canonical(fz)])
+    pts = np.stack(cols, axis=1)
     return np.unique(pts, axis=0).shape[0] != pts.shape[0]
 
 
-def index_plan(fx, fy, amplitude) -> dict:
+def index_plan(fx, fy, amplitude, fz=None) -> dict:
     """Every integer the GPU plan derives from the foci and the aperture."""
-    xu, ix = unique_coords(fx)
-    yu, iy = unique_coords(fy)
+    xu, ix = unique_coords(fx, fz)
+    yu, iy = unique_coords(fy, fz)
     rows, cols = compaction(amplitude)
     axis = axis_choice(xu.shape[0], yu.shape[0])
     ir, ic = (iy, ix) if axis == 0 else (ix, iy)
@@ -286,4 +308,4 @@ def index_plan(fx, fy, amplitude) -> dict:
     row_ptr = np.searchsorted(ir[order], np.arange(ur + 1)).astype(np.int32)
     return {"xu": xu, "yu": yu, "ix": ix, "iy": iy, "rows": rows, "cols": cols,
             "axis": axis, "order": order, "row_ptr": row_ptr,
-            "duplicate": has_duplicate_foci(fx, fy)}
+            "duplicate": has_duplicate_foci(fx, fy, fz)}

@@ -48,13 +48,18 @@
 /* Smallest normalised intensity used in the weight update (division guard). */
 #define ORACLE_TAU 1e-30
 
-/* exp(-2 pi i s c f) for every sample coordinate c, one focal coordinate f.
- * The exponent follows Eq. 1 (negative sign in the forward direction). */
-static void phasor_row(int n, const double *coord, double s, double f,
+/* exp(-2 pi i s c f) exp(i pi z (s c)^2) for every sample coordinate c, one
+ * focal coordinate f at axial position z.  The first factor follows Eq. 1
+ * (negative sign in the forward direction); the second is the defocus phase
+ * of the pupil that places a focus off the focal plane (Sec. 3: the axial
+ * position of a focus is set by a defocus phase of the pupil function),
+ * separable over the two pupil axes; z = 0 is the focal plane. */
+static void phasor_row(int n, const double *coord, double s, double f, double z,
                        double *re, double *im)
 {
     for (int p = 0; p < n; ++p) {
-        double arg = -2.0 * M_PI * s * coord[p] * f;
+        double sc = s * coord[p];
+        double arg = -2.0 * M_PI * sc * f + M_PI * z * sc * sc;
         re[p] = cos(arg);
         im[p] = sin(arg);
     }
@@ -67,7 +72,8 @@ typedef struct {
 } tables;
 
 static int tables_build(tables *t, int ny, int nx, const double *u, const double *v,
-                        double sx, double sy, int nf, const double *fx, const double *fy)
+                        double sx, double sy, int nf, const double *fx, const double *fy,
+                        const double *fz)
 {
     t->nf = nf; t->nx = nx; t->ny = ny;
     t->axr = malloc(sizeof(double) * (size_t)nf * nx);
@@ -77,8 +83,9 @@ static int tables_build(tables *t, int ny, int nx, const double *u, const double
     if (!t->axr || !t->axi || !t->ayr || !t->ayi) return -1;
 #pragma omp parallel for schedule(static)
     for (int n = 0; n < nf; ++n) {
-        phasor_row(nx, u, sx, fx[n], t->axr + (size_t)n * nx, t->axi + (size_t)n * nx);
-        phasor_row(ny, v, sy, fy[n], t->ayr + (size_t)n * ny, t->ayi + (size_t)n * ny);
+        const double z = fz ? fz[n] : 0.0;
+        phasor_row(nx, u, sx, fx[n], z, t->axr + (size_t)n * nx, t->axi + (size_t)n * nx);
+        phasor_row(ny, v, sy, fy[n], z, t->ayr + (size_t)n * ny, t->ayi + (size_t)n * ny);
     }
     return 0;
 }
@@ -147,10 +154,10 @@ int oracle_num_threads(void)
 /* Forward propagation, Eq. 1 / Eq. 2, evaluated at the foci. */
 int oracle_forward(int ny, int nx, const double *E, const double *u, const double *v,
                    double sx, double sy, int nf, const double *fx, const double *fy,
-                   double *theta)
+                   const double *fz, double *theta)
 {
     tables t;
-    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); return -1; }
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy, fz)) { tables_free(&t); return -1; }
     forward_t(&t, E, theta);
     tables_free(&t);
     return 0;
@@ -158,10 +165,11 @@ int oracle_forward(int ny, int nx, const double *E, const double *u, const doubl
 
 /* Inverse propagation read as the adjoint of the forward map. */
 int oracle_adjoint(int ny, int nx, const double *u, const double *v, double sx, double sy,
-                   int nf, const double *fx, const double *fy, const double *theta, double *E)
+                   int nf, const double *fx, const double *fy, const double *fz,
+                   const double *theta, double *E)
 {
     tables t;
-    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); return -1; }
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy, fz)) { tables_free(&t); return -1; }
     adjoint_t(&t, theta, E);
     tables_free(&t);
     return 0;
@@ -311,7 +319,7 @@ static void phasors(int nf, const double *theta, double *out)
  * <= 0 disables).  Returns 0, or -1 on allocation failure. */
 int oracle_gsw_ex(int ny, int nx, const double *amp, const double *u, const double *v,
                   double sx, double sy, int nf, const double *fx, const double *fy,
-                  const double *target, double *phi, double *w, int n_iter, double stop,
+                  const double *fz, const double *target, double *phi, double *w, int n_iter, double stop,
                   double *hist, int *iters_done, double *theta_final, int weighting,
                   int phase_fix)
 {
@@ -324,7 +332,7 @@ int oracle_gsw_ex(int ny, int nx, const double *amp, const double *u, const doub
     double *fix = malloc(sizeof(double) * 2 * (size_t)nf);
     int rc = -1;
     if (!E || !Ep || !th || !thn || !fix) goto done;
-    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); goto done; }
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy, fz)) { tables_free(&t); goto done; }
 
     double n_ap = 0.0, sum_a2 = 0.0;
     for (size_t p = 0; p < np; ++p) {
@@ -368,8 +376,8 @@ int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double 
                const double *target, double *phi, double *w, int n_iter, double stop,
                double *hist, int *iters_done, double *theta_final)
 {
-    return oracle_gsw_ex(ny, nx, amp, u, v, sx, sy, nf, fx, fy, target, phi, w, n_iter, stop,
-                         hist, iters_done, theta_final, 0, 0);
+    return oracle_gsw_ex(ny, nx, amp, u, v, sx, sy, nf, fx, fy, NULL, target, phi, w, n_iter,
+                         stop, hist, iters_done, theta_final, 0, 0);
 }
 
 /* Gradient of L(phi) = sum_n g_n I_n(phi) with I_n = |Theta_n|^2 and
@@ -377,7 +385,7 @@ int oracle_gsw(int ny, int nx, const double *amp, const double *u, const double 
  *   dL/dphi_p = 2 Im( conj(E_p) * [adjoint(g * Theta)]_p ).
  * theta (nullable) receives the forward field at phi. */
 int oracle_phase_gradient(int ny, int nx, const double *amp, const double *u, const double *v,
-                          double sx, double sy, int nf, const double *fx, const double *fy,
+                          double sx, double sy, int nf, const double *fx, const double *fy, const double *fz,
                           const double *phi, const double *g, double *grad, double *theta)
 {
     const size_t np = (size_t)ny * nx;
@@ -387,7 +395,7 @@ int oracle_phase_gradient(int ny, int nx, const double *amp, const double *u, co
     double *th = malloc(sizeof(double) * 2 * (size_t)nf);
     int rc = -1;
     if (!E || !Ep || !th) goto done;
-    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy)) { tables_free(&t); goto done; }
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy, fz)) { tables_free(&t); goto done; }
     for (size_t p = 0; p < np; ++p) {
         E[2 * p] = amp[p] * cos(phi[p]);
         E[2 * p + 1] = amp[p] * sin(phi[p]);

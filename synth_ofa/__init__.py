@@ -52,6 +52,7 @@ class Hologram:
     phi0: np.ndarray           # float32 [ny, nx], initial phase
     n_iter: int = 20
     meta: dict = field(default_factory=dict)
+    fz: Optional[np.ndarray] = None   # float64 [N], axial positions (None: focal plane)
 
     @property
     def n_foci(self) -> int:
@@ -284,6 +285,36 @@ def double_heart(pitch: float = 0.8, n_iter: int = 100) -> Hologram:
     target = 0.5 + 0.5 * (fx - fx.min()) / (fx.max() - fx.min())
     phi0 = initial_phase(rng, ny, nx)
     return _assemble("double-heart", ny, nx, amp, fx, fy, target, phi0, n_iter)
+
+
+def volume_case(seed: int, ny: int, nx: int, n_per_plane: int, planes=(-30.0, 0.0, 30.0), *,
+                radius: Optional[float] = None, roi: Optional[float] = None,
+                grid: Optional[tuple] = None, n_iter: int = 20) -> Hologram:
+    """3-D foci (Sec. 3 outlook: the axial position of a focus set by a
+    defocus phase of the pupil): ``n_per_plane`` random foci (or a k x l grid,
+    shifted by half a pitch from plane to plane) on each axial plane z of
+    ``planes``; targets uniform in [0.3, 1]."""
+    rng = np.random.default_rng([SEED_BASE, 2000 + seed])
+    lim = roi if roi is not None else 0.3 * min(ny, nx)
+    fxs, fys, fzs = [], [], []
+    for q, z in enumerate(planes):
+        if grid is not None:
+            gx, gy = grid_foci(grid[0], grid[1], 3.1)
+            gx, gy = gx + 1.55 * q, gy + 1.55 * q
+        else:
+            pts = rng.uniform(-lim, lim, size=(n_per_plane, 2))
+            gx, gy = pts[:, 0], pts[:, 1]
+        fxs.append(gx)
+        fys.append(gy)
+        fzs.append(np.full(gx.shape[0], float(z)))
+    fx, fy, fz = np.concatenate(fxs), np.concatenate(fys), np.concatenate(fzs)
+    target = rng.uniform(0.3, 1.0, size=fx.shape[0])
+    amp = np.ones((ny, nx)) if radius is None else disc(ny, nx, radius).astype(np.float64)
+    phi0 = initial_phase(rng, ny, nx)
+    h = _assemble(f"volume-{seed}-{ny}x{nx}-{fx.shape[0]}", ny, nx, amp, fx, fy, target, phi0,
+                  n_iter)
+    h.fz = np.ascontiguousarray(fz)
+    return h
 
 
 def config(k: int):

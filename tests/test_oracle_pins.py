@@ -498,3 +498,62 @@ def test_config1_aperture_pixel_count():
     assert int(np.count_nonzero(h.amplitude)) == 3228
     rows, cols = oracle.compaction(h.amplitude)
     assert rows.shape[0] == 64 and cols.shape[0] == 64
+
+
+# --------------------------------------------------------------------------
+# 3-D foci: the axial position as a defocus phase of the pupil
+# --------------------------------------------------------------------------
+
+def test_volume_focal_plane_equals_2d():
+    """All foci at z = 0: the 3-D operators are the 2-D ones, exactly."""
+    h = synth_ofa.random_case(90, 40, 36, 12)
+    E = oracle.pupil_field(h)
+    a = oracle.forward(E, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    b = oracle.forward(E, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy, np.zeros(h.n_foci))
+    assert np.array_equal(a, b)
+
+
+def test_volume_defocus_compensated_pupil_focuses_perfectly():
+    """A pupil carrying the conjugate of a plane's defocus phase (a lens of
+    the opposite power) focuses on that plane as a flat pupil does on the
+    focal plane: the on-axis field of plane z is sum A, and off-axis foci on
+    that plane see the plain Fourier kernel."""
+    ny, nx = 48, 56
+    u, v = synth_ofa.centred(nx), synth_ofa.centred(ny)
+    sx, sy = 1.0 / nx, 1.0 / ny
+    amp = synth_ofa.disc(ny, nx, 22.0).astype(np.float64)
+    for z in (-25.0, 12.5, 40.0):
+        lens = np.exp(-1j * np.pi * z * ((sy * v[:, None]) ** 2 + (sx * u[None, :]) ** 2))
+        th = oracle.forward(amp * lens, u, v, sx, sy, np.array([0.0, 3.0]), np.array([0.0, -2.0]),
+                            np.array([z, z]))
+        flat = oracle.forward(amp.astype(np.complex128), u, v, sx, sy, np.array([0.0, 3.0]),
+                              np.array([0.0, -2.0]))
+        assert th[0] == pytest.approx(amp.sum(), rel=1e-12)
+        assert abs(th[1] - flat[1]) <= 1e-10 * amp.sum()
+
+
+def test_volume_adjoint_identity():
+    """<P(E), T> = <E, P^H(T)> with foci on several planes."""
+    h = synth_ofa.volume_case(91, 30, 34, 5)
+    rng = np.random.default_rng(4)
+    E = rng.standard_normal((h.ny, h.nx)) + 1j * rng.standard_normal((h.ny, h.nx))
+    T = rng.standard_normal(h.n_foci) + 1j * rng.standard_normal(h.n_foci)
+    pe = oracle.forward(E, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy, h.fz)
+    pt = oracle.adjoint(T, h.ny, h.nx, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy, h.fz)
+    lhs = np.vdot(T, pe)
+    rhs = np.vdot(pt, E)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_volume_index_pairs_brute_force():
+    """Reduced rows and columns are distinct (coordinate, z) pairs, ordered by
+    coordinate then z; foci sharing (x, y) on different planes are distinct."""
+    fx = np.array([1.0, 1.0, -0.0, 0.0, 2.5, 1.0])
+    fy = np.array([0.5, 0.5, 0.5, 0.5, -1.0, 0.5])
+    fz = np.array([0.0, 10.0, 10.0, -0.0, 10.0, -5.0])
+    xu, ix = oracle.unique_coords(fx, fz)
+    # pairs (x, z): (0, 0) (0, 10) (1, -5) (1, 0) (1, 10) (2.5, 10)
+    assert list(xu) == [0.0, 0.0, 1.0, 1.0, 1.0, 2.5]
+    assert list(ix) == [3, 4, 1, 0, 5, 2]
+    assert not oracle.has_duplicate_foci(fx, fy, fz)
+    assert oracle.has_duplicate_foci(fx[:2], fy[:2], np.array([10.0, 10.0]))
