@@ -97,12 +97,23 @@ typedef struct gswmtp_desc {
     int precision;                /* gswmtp_precision */
     int axis;                     /* -1 auto, 0 reduce along y, 1 along x */
     int weighting;                /* gswmtp_weighting */
+    const double *fz;             /* [n_foci] axial focus positions, finite;
+                                     NULL = all foci on the focal plane.  A
+                                     focus at z multiplies its kernel rows and
+                                     columns by the pupil's defocus phase
+                                     exp(i pi z (s u)^2) along x and
+                                     exp(i pi z (s v)^2) along y (the 3-D
+                                     extension of Eq. 2 through the lens's
+                                     quadratic phase; separable per axis), so
+                                     the reduced grid holds (coordinate, z)
+                                     pairs per axis. */
 } gswmtp_desc;
 
 /* Index information of a plan (the reduced focal grid and pupil compaction). */
 typedef struct gswmtp_index_info {
     int n_foci;
-    int ux, uy;                   /* unique focus x / y coordinates */
+    int ux, uy;                   /* unique focus (x, z) / (y, z) pairs
+                                     (unique x / y when every z is 0) */
     int ny_kept, nx_kept;         /* pupil rows / columns with any non-zero amplitude */
     int axis;                     /* 0: dense product over the y foci (M = uy); 1: over x */
     int n_aperture;               /* samples with amplitude > 0 */
@@ -129,7 +140,7 @@ int gswmtp_desc_init(gswmtp_desc *d);
  * target intensities, w0 = 1, focus coordinates).
  * Validates every input on the host first (GSWMTP_E_INVAL, no GPU use), then
  * runs the plan kernels: effective amplitude and compaction, unique focal
- * coordinates and gather indices (GSWMTP_E_DUPFOCUS on a repeated (x, y);
+ * coordinates and gather indices (GSWMTP_E_DUPFOCUS on a repeated (x, y, z);
  * -0.0 and +0.0 are one coordinate), axis choice (fewer unique coordinates,
  * ties to y), kernel matrices (phase reduced in float64), E0 = A exp(i phi0).
  * Synchronises once to size the product buffers.  stream: hipStream_t or NULL.

@@ -48,6 +48,7 @@ class gswmtp_desc(ctypes.Structure):
         ("fx", ctypes.c_void_p), ("fy", ctypes.c_void_p), ("target", ctypes.c_void_p),
         ("phi0", ctypes.c_void_p),
         ("precision", ctypes.c_int), ("axis", ctypes.c_int), ("weighting", ctypes.c_int),
+        ("fz", ctypes.c_void_p),
     ]
 
 
@@ -143,13 +144,14 @@ class Plan:
 
     Parameters mirror ``gswmtp_desc`` (see ``include/gswmtp.h``).  All host
     arrays are copied at creation.  ``holo`` may be any object with the fields
-    ny, nx, amplitude, u, v, s_x, s_y, fx, fy, target, phi0 (for example a
-    ``synth_ofa.Hologram``); keyword arguments override its fields.
+    ny, nx, amplitude, u, v, s_x, s_y, fx, fy, target, phi0 and optionally fz
+    (axial focus positions; for example a ``synth_ofa.Hologram``); keyword
+    arguments override its fields.
     """
 
     def __init__(self, holo=None, *, ny=None, nx=None, amplitude=None, mask=None, u=None,
                  v=None, s_x=None, s_y=None, fx=None, fy=None, target=None, phi0=None,
-                 precision="fp32", axis=-1, weighting="gsw"):
+                 fz=None, precision="fp32", axis=-1, weighting="gsw"):
         lib = load_library()
         g = (lambda k, val: val if val is not None else getattr(holo, k, None)) if holo is not None \
             else (lambda k, val: val)
@@ -179,6 +181,7 @@ class Plan:
         d.fy = arr(g("fy", fy), np.float64)
         d.target = arr(g("target", target), np.float64)
         d.phi0 = arr(g("phi0", phi0), np.float32)
+        d.fz = arr(g("fz", fz), np.float64)
         d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         d.axis = int(axis)
         d.weighting = {"gsw": WEIGHT_GSW, "gs": WEIGHT_GS}[weighting] \

@@ -57,6 +57,8 @@ struct Dims {
 struct Bufs {
   // inputs and index work (sized by ny, nx, nf)
   double *fx = nullptr, *fy = nullptr, *target = nullptr, *tnorm = nullptr;
+  double *fz = nullptr;                  // axial positions (zeros: the focal plane)
+  double *xzu = nullptr, *yzu = nullptr;  // z of each unique (x, z) / (y, z) key
   double *xu = nullptr, *yu = nullptr;
   int *ix = nullptr, *iy = nullptr, *firstx = nullptr, *firsty = nullptr;
   int *rows = nullptr, *cols = nullptr, *row_pos = nullptr, *col_pos = nullptr;

@@ -195,46 +195,61 @@ __global__ __launch_bounds__(1024) void k_aperture(const float *a, size_t n, int
   }
 }
 
-// first[i] = 1 when no focus m < i has the same canonical coordinate.
-__global__ __launch_bounds__(256) void k_first(const double *c, int n, int *first) {
-  __shared__ double tile[256];
+// Reduced-grid keys are (coordinate, z) pairs: the focal coordinate and the
+// axial position of the focus (all z = 0 for foci on the focal plane), both
+// canonical, ordered by coordinate, then z.
+__device__ __forceinline__ bool pair_less(double c0, double z0, double c1, double z1) {
+  return c0 < c1 || (c0 == c1 && z0 < z1);
+}
+
+// first[i] = 1 when no focus m < i has the same canonical (coordinate, z).
+__global__ __launch_bounds__(256) void k_first(const double *c, const double *z, int n,
+                                               int *first) {
+  __shared__ double tile[256], tz[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const double key = i < n ? canon(c[i]) : 0.0;
+  const double kz = i < n ? canon(z[i]) : 0.0;
   int seen = 0;
   const int last = (blockIdx.x + 1) * 256;  // only m < i matter
   for (int base = 0; base < n && base < last; base += 256) {
     const int j = base + threadIdx.x;
     tile[threadIdx.x] = j < n ? canon(c[j]) : 0.0;
+    tz[threadIdx.x] = j < n ? canon(z[j]) : 0.0;
     __syncthreads();
     const int lim = n - base < 256 ? n - base : 256;
     for (int q = 0; q < lim; ++q)
-      if (base + q < i && tile[q] == key) seen = 1;
+      if (base + q < i && tile[q] == key && tz[q] == kz) seen = 1;
     __syncthreads();
   }
   if (i < n) first[i] = !seen;
 }
 
-// idx[i] = number of distinct coordinates below coordinate i (its position in
-// the sorted unique list); the first occurrence writes uniq[idx[i]].
-__global__ __launch_bounds__(256) void k_rank(const double *c, const int *first, int n, int *idx,
-                                              double *uniq) {
-  __shared__ double tile[256];
+// idx[i] = number of distinct keys below key i (its position in the sorted
+// unique list); the first occurrence writes uniq[idx[i]] and uniq_z[idx[i]].
+__global__ __launch_bounds__(256) void k_rank(const double *c, const double *z, const int *first,
+                                              int n, int *idx, double *uniq, double *uniq_z) {
+  __shared__ double tile[256], tz[256];
   __shared__ int tf[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const double key = i < n ? canon(c[i]) : 0.0;
+  const double kz = i < n ? canon(z[i]) : 0.0;
   int cnt = 0;
   for (int base = 0; base < n; base += 256) {
     const int j = base + threadIdx.x;
     tile[threadIdx.x] = j < n ? canon(c[j]) : 0.0;
+    tz[threadIdx.x] = j < n ? canon(z[j]) : 0.0;
     tf[threadIdx.x] = j < n ? first[j] : 0;
     __syncthreads();
     const int lim = n - base < 256 ? n - base : 256;
-    for (int q = 0; q < lim; ++q) cnt += (tf[q] && tile[q] < key) ? 1 : 0;
+    for (int q = 0; q < lim; ++q) cnt += (tf[q] && pair_less(tile[q], tz[q], key, kz)) ? 1 : 0;
     __syncthreads();
   }
   if (i < n) {
     idx[i] = cnt;
-    if (first[i]) uniq[cnt] = key;
+    if (first[i]) {
+      uniq[cnt] = key;
+      uniq_z[cnt] = kz;
+    }
   }
 }
 
@@ -324,9 +339,14 @@ __global__ __launch_bounds__(1024) void k_tnorm(const double *target, int n, dou
 
 // exp(-2 pi i s c f) with the argument reduced exactly in float64:
 // t = s c f, r = t - rint(t), then sincospi(-2 r).
-__device__ __forceinline__ void kernel_phasor(double s, double c, double f, float *re,
+// exp(-2 pi i s c f) exp(i pi z (s c)^2): the kernel phasor of Eq. 2 for
+// sample coordinate c and focal coordinate f, times the defocus phase of a
+// focus at axial position z (z = 0: the focal plane).  The phase in cycles
+// is reduced to [-1/2, 1/2] in float64 before sincospi.
+__device__ __forceinline__ void kernel_phasor(double s, double c, double f, double z, float *re,
                                               float *im) {
-  const double t = s * c * f;
+  const double sc = s * c;
+  const double t = sc * f - 0.5 * z * sc * sc;
   const double r = t - rint(t);
   double sn, cs;
   sincospi(-2.0 * r, &sn, &cs);
@@ -336,13 +356,13 @@ __device__ __forceinline__ void kernel_phasor(double s, double c, double f, floa
 
 // Omega_r in both layouts: OmT[j][a] and OmC[a][j] = conj(OmT[j][a]).
 __global__ void k_omega_r(const double *coord, const int *kept, int Rk, const double *fu,
-                          int Ur, double s, int Rp, int Urp, float *omt_r, float *omt_i,
-                          float *omc_r, float *omc_i) {
+                          const double *fuz, int Ur, double s, int Rp, int Urp, float *omt_r,
+                          float *omt_i, float *omc_r, float *omc_i) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (size_t)Rp * Urp) return;
   const int j = (int)(id / Urp), a = (int)(id % Urp);
   float re = 0.f, im = 0.f;
-  if (j < Rk && a < Ur) kernel_phasor(s, coord[kept[j]], fu[a], &re, &im);
+  if (j < Rk && a < Ur) kernel_phasor(s, coord[kept[j]], fu[a], fuz[a], &re, &im);
   omt_r[(size_t)j * Urp + a] = re;
   omt_i[(size_t)j * Urp + a] = im;
   omc_r[(size_t)a * Rp + j] = re;
@@ -367,12 +387,12 @@ __global__ void k_grid_tables(const float *wr, const float *wi, int Uc, int Cp, 
 }
 
 __global__ void k_omega_c(const double *coord, const int *kept, int Ck, const double *fu,
-                          int Uc, double s, int Cp, float *wr, float *wi) {
+                          const double *fuz, int Uc, double s, int Cp, float *wr, float *wi) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (size_t)Uc * Cp) return;
   const int b = (int)(id / Cp), i = (int)(id % Cp);
   float re = 0.f, im = 0.f;
-  if (i < Ck) kernel_phasor(s, coord[kept[i]], fu[b], &re, &im);
+  if (i < Ck) kernel_phasor(s, coord[kept[i]], fu[b], fuz[b], &re, &im);
   wr[id] = re;
   wi[id] = im;
 }
@@ -503,13 +523,13 @@ __global__ void k_expand_real(const float *xr, const int *row_pos, const int *co
 // A = Omega_r^H [re/im][term][Rp][Urp].
 template <bool BF, int NT>
 __global__ void k_omega_r_split(const double *coord, const int *kept, int Rk, const double *fu,
-                                int Ur, double s, int Rp, int Urp, unsigned short *af,
-                                unsigned short *ab) {
+                                const double *fuz, int Ur, double s, int Rp, int Urp,
+                                unsigned short *af, unsigned short *ab) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (size_t)Rp * Urp) return;
   const int j = (int)(id / Urp), a = (int)(id % Urp);
   float re = 0.f, im = 0.f;
-  if (j < Rk && a < Ur) kernel_phasor(s, coord[kept[j]], fu[a], &re, &im);
+  if (j < Rk && a < Ur) kernel_phasor(s, coord[kept[j]], fu[a], fuz[a], &re, &im);
   unsigned short tr[NT], ti[NT], tc[NT];
   split_terms<BF, NT>(re, tr, 1);
   split_terms<BF, NT>(im, ti, 1);
@@ -645,6 +665,7 @@ int validate(const gswmtp_desc *d) {
   const size_t nf = (size_t)d->n_foci, np = (size_t)d->ny * d->nx;
   if (!finite_all(d->fx, nf) || !finite_all(d->fy, nf) || !finite_all(d->target, nf))
     return GSWMTP_E_INVAL;
+  if (d->fz && !finite_all(d->fz, nf)) return GSWMTP_E_INVAL;
   double tsum = 0.0;
   for (size_t i = 0; i < nf; ++i) {
     if (d->target[i] < 0.0) return GSWMTP_E_INVAL;
@@ -875,7 +896,8 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   // ---- pool 0: inputs, index work, per-focus state ----
   auto carve0 = [&](Carver &c) {
     Bufs &b = p->b;
-    b.fx = c.take<double>(nf); b.fy = c.take<double>(nf);
+    b.fx = c.take<double>(nf); b.fy = c.take<double>(nf); b.fz = c.take<double>(nf);
+    b.xzu = c.take<double>(nf); b.yzu = c.take<double>(nf);
     b.target = c.take<double>(nf); b.tnorm = c.take<double>(nf);
     b.xu = c.take<double>(nf); b.yu = c.take<double>(nf);
     b.ix = c.take<int>(nf); b.iy = c.take<int>(nf);
@@ -914,6 +936,10 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   for (size_t i = 0; i < nx; ++i) uc[i] = d->u ? d->u[i] : (double)i - (double)(nx - 1) / 2.0;
   for (size_t j = 0; j < ny; ++j) vc[j] = d->v ? d->v[j] : (double)j - (double)(ny - 1) / 2.0;
   HIP_TRY(p, hipMemcpyAsync(b.fx, d->fx, nf * 8, hipMemcpyHostToDevice, s));
+  if (d->fz)
+    HIP_TRY(p, hipMemcpyAsync(b.fz, d->fz, nf * 8, hipMemcpyHostToDevice, s));
+  else
+    hipLaunchKernelGGL(k_fill_d, grid1(nf), dim3(256), 0, s, b.fz, 0.0, nf);
   HIP_TRY(p, hipMemcpyAsync(b.fy, d->fy, nf * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(p, hipMemcpyAsync(b.target, d->target, nf * 8, hipMemcpyHostToDevice, s));
   HIP_TRY(p, hipMemcpyAsync(b.ucoord, uc.data(), nx * 8, hipMemcpyHostToDevice, s));
@@ -941,10 +967,12 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
                      b.col_pos, sc + 3);
   hipLaunchKernelGGL(k_aperture, dim3(1), dim3(1024), 0, s, b.aeff, np, sc + 4, b.dscalars);
   const dim3 gf = grid1(nf);
-  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fx, (int)nf, b.firstx);
-  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fy, (int)nf, b.firsty);
-  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fx, b.firstx, (int)nf, b.ix, b.xu);
-  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fy, b.firsty, (int)nf, b.iy, b.yu);
+  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fx, b.fz, (int)nf, b.firstx);
+  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fy, b.fz, (int)nf, b.firsty);
+  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fx, b.fz, b.firstx, (int)nf, b.ix, b.xu,
+                     b.xzu);
+  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fy, b.fz, b.firsty, (int)nf, b.iy, b.yu,
+                     b.yzu);
   hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firstx, (int)nf, sc + 0);
   hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firsty, (int)nf, sc + 1);
   hipLaunchKernelGGL(k_dup, gf, dim3(256), 0, s, b.ix, b.iy, (int)nf, b.dup);
@@ -964,7 +992,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   D.nx_kept = hs[3];
   D.n_ap = hs[4];
   D.sum_a2 = hsum;
-  if (hdup) return fail(p, GSWMTP_E_DUPFOCUS, "two foci share the same (x, y)");
+  if (hdup) return fail(p, GSWMTP_E_DUPFOCUS, "two foci share the same (x, y, z)");
   if (D.n_ap == 0 || D.ny_kept == 0 || D.nx_kept == 0 || !(D.sum_a2 > 0.0))
     return fail(p, GSWMTP_E_EMPTYAPERTURE, "amplitude is zero everywhere");
 
@@ -1059,19 +1087,21 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   const int *ckept = D.axis == 0 ? b.cols : b.rows;
   const double *rfu = D.axis == 0 ? b.yu : b.xu;
   const double *cfu = D.axis == 0 ? b.xu : b.yu;
+  const double *rfz = D.axis == 0 ? b.yzu : b.xzu;
+  const double *cfz = D.axis == 0 ? b.xzu : b.yzu;
   const double s_r = D.axis == 0 ? d->s_y : d->s_x;
   const double s_c = D.axis == 0 ? d->s_x : d->s_y;
   if (split) {
 #define OMEGA(BF, NT)                                                                          \
   hipLaunchKernelGGL((k_omega_r_split<BF, NT>), grid1(Rp * Urp), dim3(256), 0, s, rcoord, rkept, \
-                     D.Rk, rfu, D.Ur, s_r, D.Rp, D.Urp, b.as_f, b.as_b)
+                     D.Rk, rfu, rfz, D.Ur, s_r, D.Rp, D.Urp, b.as_f, b.as_b)
     DISPATCH_SPLIT(p->precision, OMEGA)
 #undef OMEGA
   } else {
     hipLaunchKernelGGL(k_omega_r, grid1(Rp * Urp), dim3(256), 0, s, rcoord, rkept, D.Rk, rfu,
-                       D.Ur, s_r, D.Rp, D.Urp, b.omt_r, b.omt_i, b.omc_r, b.omc_i);
+                       rfz, D.Ur, s_r, D.Rp, D.Urp, b.omt_r, b.omt_i, b.omc_r, b.omc_i);
   }
-  hipLaunchKernelGGL(k_omega_c, grid1(Uc * Cp), dim3(256), 0, s, ccoord, ckept, D.Ck, cfu,
+  hipLaunchKernelGGL(k_omega_c, grid1(Uc * Cp), dim3(256), 0, s, ccoord, ckept, D.Ck, cfu, cfz,
                      D.Uc, s_c, D.Cp, b.wc_r, b.wc_i);
   if (p->grid_form)
     hipLaunchKernelGGL(k_grid_tables, grid1(Ucp * Cp), dim3(256), 0, s, b.wc_r, b.wc_i, D.Uc,
