@@ -165,6 +165,21 @@ int gswmtp_sync(gswmtp_plan *p);
  * variable GSWMTP_NO_GRAPH is set to a non-zero value. */
 int gswmtp_iterate(gswmtp_plan *p, int n_iter, double stop_accuracy);
 
+/* Camera in the loop (the experiments of Sec. 2): queue ONE pass of
+ * Algorithm 1 whose weight update takes the focus intensities from
+ * measured [n_foci] (host, caller order; finite, >= 0, positive sum) -
+ * intensities captured for the CURRENT phase - in place of the computed
+ * |Theta|^2; they are normalised to unit sum on the device like the computed
+ * ones.  Everything else is an ordinary pass: the new focal field keeps
+ * arg Theta of the computed forward field (or the frozen phases under phase
+ * fixing), the history records the computed field's statistics, the pass
+ * is counted, no termination test is taken.  With GS weighting the
+ * intensities have no effect.  The caller decides when to switch (the paper
+ * switches once the computed accuracy xi reaches 0.95).  Synchronises
+ * before returning, so measured may be reused at once.  Runs eagerly (not
+ * from the captured graph of gswmtp_iterate). */
+int gswmtp_iterate_measured(gswmtp_plan *p, const double *measured);
+
 /* Total passes that updated the phase since creation or the last set_state
  * (synchronises). */
 int gswmtp_iterations_done(gswmtp_plan *p, int *n);

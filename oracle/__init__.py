@@ -58,6 +58,9 @@ def _load():
                                   ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, _D,
                                   ctypes.c_int,
                                   ctypes.c_double, _D, _I, _D, ctypes.c_int, ctypes.c_int]
+    lib.oracle_gsw_measured_pass.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                             _D, _D, _D, _D, _D, _D, _D, _D]
     lib.oracle_phase_gradient.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D,
                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, _D,
                                           _D, _D, _D, _D, _D, _D]
@@ -170,6 +173,53 @@ def gsw(holo, n_iter: Optional[int] = None, stop: float = 0.0, phi=None, w=None,
         raise MemoryError("oracle_gsw")
     passes = done.value + (1 if (stop > 0 and done.value < n_iter) else 0)
     return {"phi": ph, "w": ww, "history": hist[:passes], "iters_done": done.value,
+            "theta": th}
+
+
+def gsw_measured_pass(holo, phi, w, measured) -> dict:
+    """One pass of Algorithm 1 whose weight update takes the focus
+    intensities from ``measured`` (a camera capture of the field of phi,
+    normalised to unit sum) instead of |Theta|^2: the camera-in-the-loop
+    strategy of the experiments in Sec. 2.  Returns phi, w and the
+    statistics (xi, eta, U) of the computed field the pass started from."""
+    ph = _f64(phi).copy()
+    ww = _f64(w).copy()
+    hist = np.zeros(3)
+    rc = _load().oracle_gsw_measured_pass(
+        holo.ny, holo.nx, _d(_f64(holo.amplitude)), _d(_f64(holo.u)), _d(_f64(holo.v)),
+        float(holo.s_x), float(holo.s_y), holo.n_foci, _d(_f64(holo.fx)), _d(_f64(holo.fy)),
+        _d(_fz(holo)), _d(_f64(holo.target)), _d(ph), _d(ww), _d(_f64(measured)), _d(hist))
+    if rc:
+        raise MemoryError("oracle_gsw_measured_pass")
+    return {"phi": ph, "w": ww, "history": hist}
+
+
+def camera_loop(holo, n_iter: int, capture, xi_switch: float = 0.95, phi=None, w=None) -> dict:
+    """Algorithm 1 with a camera in the loop (Sec. 2 experiments): plain
+    passes until the accuracy xi of the current phase's computed field
+    reaches xi_switch, then every pass takes its weight-update intensities
+    from ``capture(theta)`` - a camera model mapping the computed focal field
+    of the current phase to measured intensities.  Returns phi, w, the
+    per-pass history, the pass at which the loop switched (None if never)
+    and the field of the returned phase."""
+    ph = _f64(holo.phi0 if phi is None else phi).copy()
+    ww = np.ones(holo.n_foci) if w is None else _f64(w).copy()
+    hist, switched = [], None
+    fz = _fz(holo)
+    for k in range(n_iter):
+        th = forward(pupil_field(holo, ph), holo.u, holo.v, holo.s_x, holo.s_y, holo.fx,
+                     holo.fy, fz)
+        if switched is None and stats(th, holo.target, holo.amplitude)["xi"] >= xi_switch:
+            switched = k
+        if switched is not None:
+            r = gsw_measured_pass(holo, ph, ww, capture(th))
+        else:
+            r = gsw(holo, n_iter=1, phi=ph, w=ww)
+            r["history"] = r["history"][0]
+        ph, ww = r["phi"], r["w"]
+        hist.append(r["history"])
+    th = forward(pupil_field(holo, ph), holo.u, holo.v, holo.s_x, holo.s_y, holo.fx, holo.fy, fz)
+    return {"phi": ph, "w": ww, "history": np.array(hist).reshape(-1, 3), "switched": switched,
             "theta": th}
 
 

@@ -264,21 +264,28 @@ static void project(int np, const double *amp, const double *Ep, double *phi, do
  *   weighting 0 (GSW, Algorithm 1): w <- w sqrt(t / max(i, tau));
  *   weighting 1 (plain GS, the comparison method): w unchanged;
  *   phasor: arg Theta of this pass, or, when fixed != NULL, the stored
- *   phasors (phase fixing: the focal phases are frozen).
+ *   phasors (phase fixing: the focal phases are frozen);
+ *   measured (nullable): intensities captured by a camera for this pass's
+ *   phase (the camera-in-the-loop strategy of the experiments in Sec. 2):
+ *   the weight update takes i from them (normalised to unit sum) instead of
+ *   from |Theta|^2; the phasors still come from Theta.
  * theta_new = w sqrt(target) * phasor. */
 static void weight_update_ex(int nf, const double *theta, const double *target, double *w,
-                             double *theta_new, int weighting, const double *fixed)
+                             double *theta_new, int weighting, const double *fixed,
+                             const double *measured)
 {
     double sI = 0.0, sT = 0.0;
     for (int n = 0; n < nf; ++n) {
-        sI += theta[2 * n] * theta[2 * n] + theta[2 * n + 1] * theta[2 * n + 1];
+        sI += measured ? measured[n]
+                       : theta[2 * n] * theta[2 * n] + theta[2 * n + 1] * theta[2 * n + 1];
         sT += target[n];
     }
     for (int n = 0; n < nf; ++n) {
         double re = theta[2 * n], im = theta[2 * n + 1];
         double I = re * re + im * im;
         if (weighting == 0) {
-            double in = sI > 0.0 ? I / sI : 0.0;
+            double Iw = measured ? measured[n] : I;
+            double in = sI > 0.0 ? Iw / sI : 0.0;
             double tn = target[n] / sT;
             w[n] *= sqrt(tn / (in > ORACLE_TAU ? in : ORACLE_TAU));
         }
@@ -356,7 +363,7 @@ int oracle_gsw_ex(int ny, int nx, const double *amp, const double *u, const doub
             phasors(nf, th, fix);                     /* freeze the focal phases */
             recorded = 1;
         }
-        weight_update_ex(nf, th, target, w, thn, weighting, recorded ? fix : NULL);
+        weight_update_ex(nf, th, target, w, thn, weighting, recorded ? fix : NULL, NULL);
         adjoint_t(&t, thn, Ep);                       /* inverse propagation */
         project((int)np, amp, Ep, phi, E);            /* phase-only constraint */
         ++done_passes;
@@ -367,6 +374,47 @@ int oracle_gsw_ex(int ny, int nx, const double *amp, const double *u, const doub
     rc = 0;
 done:
     free(E); free(Ep); free(th); free(thn); free(fix);
+    return rc;
+}
+
+/* One pass of Algorithm 1 (GSW weighting) whose weight update uses measured
+ * focus intensities (camera in the loop, Sec. 2 experiments): forward field
+ * of phi, its statistics into hist3 (nullable, xi / eta / U of the computed
+ * field), weight update with i = measured / sum(measured), new focal field
+ * w sqrt(target) arg Theta, adjoint, phase-only projection.  phi and w are
+ * updated in place.  Returns 0, or -1 on allocation failure. */
+int oracle_gsw_measured_pass(int ny, int nx, const double *amp, const double *u, const double *v,
+                             double sx, double sy, int nf, const double *fx, const double *fy,
+                             const double *fz, const double *target, double *phi, double *w,
+                             const double *measured, double *hist3)
+{
+    const size_t np = (size_t)ny * nx;
+    tables t;
+    double *E = malloc(sizeof(double) * 2 * np);
+    double *Ep = malloc(sizeof(double) * 2 * np);
+    double *th = malloc(sizeof(double) * 2 * (size_t)nf);
+    double *thn = malloc(sizeof(double) * 2 * (size_t)nf);
+    int rc = -1;
+    if (!E || !Ep || !th || !thn) goto done;
+    if (tables_build(&t, ny, nx, u, v, sx, sy, nf, fx, fy, fz)) { tables_free(&t); goto done; }
+    double n_ap = 0.0, sum_a2 = 0.0;
+    for (size_t p = 0; p < np; ++p) {
+        if (amp[p] > 0.0) n_ap += 1.0;
+        sum_a2 += amp[p] * amp[p];
+        E[2 * p] = amp[p] * cos(phi[p]);
+        E[2 * p + 1] = amp[p] * sin(phi[p]);
+    }
+    forward_t(&t, E, th);
+    double st[4];
+    oracle_stats(nf, th, target, n_ap, sum_a2, st);
+    if (hist3) { hist3[0] = st[0]; hist3[1] = st[1]; hist3[2] = st[2]; }
+    weight_update_ex(nf, th, target, w, thn, 0, NULL, measured);
+    adjoint_t(&t, thn, Ep);
+    project((int)np, amp, Ep, phi, E);
+    tables_free(&t);
+    rc = 0;
+done:
+    free(E); free(Ep); free(th); free(thn);
     return rc;
 }
 

@@ -71,6 +71,7 @@ _SIGNATURES = {
     "gswmtp_set_stream": ([_P, _P], ctypes.c_int),
     "gswmtp_sync": ([_P], ctypes.c_int),
     "gswmtp_iterate": ([_P, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+    "gswmtp_iterate_measured": ([_P, _P], ctypes.c_int),
     "gswmtp_iterations_done": ([_P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "gswmtp_get_phase": ([_P, _P], ctypes.c_int),
     "gswmtp_get_phase_device": ([_P, _P], ctypes.c_int),
@@ -227,6 +228,31 @@ class Plan:
     def iterate(self, n_iter: int, stop_accuracy: float = 0.0):
         self._sync_stream()
         self._check(self._lib.gswmtp_iterate(self._h, int(n_iter), float(stop_accuracy)))
+
+    def iterate_measured(self, measured):
+        """One pass whose weight update uses measured focus intensities of the
+        current phase (caller order) in place of the computed ones."""
+        m = np.ascontiguousarray(np.asarray(measured, dtype=np.float64))
+        if m.shape != (self.n_foci,):
+            raise ValueError(f"measured must have shape ({self.n_foci},)")
+        self._sync_stream()
+        self._check(self._lib.gswmtp_iterate_measured(self._h, m.ctypes.data))
+
+    def camera_loop(self, n_iter: int, capture, xi_switch: float = 0.95):
+        """n_iter passes with a camera in the loop: ordinary passes until the
+        accuracy of the current phase's computed field reaches xi_switch,
+        then measured passes with intensities from ``capture(plan)`` (a
+        callable that captures the current phase's foci intensities).
+        Returns the pass index at which the loop switched, or None."""
+        switched = None
+        for k in range(int(n_iter)):
+            if switched is None and self.stats()["xi"] >= xi_switch:
+                switched = k
+            if switched is None:
+                self.iterate(1)
+            else:
+                self.iterate_measured(capture(self))
+        return switched
 
     def set_phase_fixing(self, from_pass: int):
         """Freeze the focal phases from updating pass `from_pass` on (0: off)."""

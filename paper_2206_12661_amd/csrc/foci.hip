@@ -63,6 +63,8 @@ struct UpdateArgs {
   int mode;                // UPD_ITERATE or UPD_STATS
   int weighting;           // GSWMTP_WEIGHT_*
   double n_ap, sum_a2;
+  const double *meas;      // [nf] measured intensities at unit sum (camera in the loop):
+                           // the weight update's i, in place of |Theta|^2 / sum; or null
 };
 
 // Algorithm 1 between the two propagations, for all foci, in one workgroup:
@@ -122,12 +124,13 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   const int fix_k = upd ? a.ctrl[CTRL_FIX] : 0;
   const bool fixing = fix_k > 0 && iters0 + 1 >= fix_k;
   const bool recorded = fixing && a.ctrl[CTRL_FIXED] != 0;
-  double tn[FPT], tg[FPT], wv[FPT], fpr[FPT], fpi[FPT];
+  double tn[FPT], tg[FPT], wv[FPT], fpr[FPT], fpi[FPT], mi[FPT];
   float thr[FPT], thi[FPT];
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
     const int n = t + f * kUpdThreads;
     const bool ok = n < a.nf;
+    mi[f] = ok && upd && a.meas ? a.meas[n] : 0.0;
     tn[f] = ok ? a.tnorm[n] : 0.0;
     tg[f] = ok && upd ? a.target[n] : 0.0;
     wv[f] = ok && upd ? a.w[n] : 0.0;
@@ -197,7 +200,8 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
       mv[1] = -r > mv[1] ? -r : mv[1];
     }
     if (upd) {
-      if (a.weighting == GSWMTP_WEIGHT_GSW) wv[f] *= sqrt(tn[f] / (in > 1e-30 ? in : 1e-30));
+      const double iw = a.meas ? mi[f] : in;
+      if (a.weighting == GSWMTP_WEIGHT_GSW) wv[f] *= sqrt(tn[f] / (iw > 1e-30 ? iw : 1e-30));
       amag[f] = wv[f] * sqrt(tg[f]);
       mv[2] = amag[f] > mv[2] ? amag[f] : mv[2];
     }
@@ -340,7 +344,8 @@ __device__ __forceinline__ BigFocus big_focus(const UpdateArgs &a, int n, double
   if (upd) {
     f.tg = a.target[n];
     double w = a.w[n];
-    if (a.weighting == GSWMTP_WEIGHT_GSW) w *= sqrt(f.tn / (f.in > 1e-30 ? f.in : 1e-30));
+    const double iw = a.meas ? a.meas[n] : f.in;
+    if (a.weighting == GSWMTP_WEIGHT_GSW) w *= sqrt(f.tn / (iw > 1e-30 ? iw : 1e-30));
     f.w_new = w;
     f.amag = w * sqrt(f.tg);
   }
@@ -759,6 +764,7 @@ static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
   a.weighting = p->weighting;
   a.n_ap = (double)p->d.n_ap;
   a.sum_a2 = p->d.sum_a2;
+  a.meas = p->meas_active;
   return a;
 }
 

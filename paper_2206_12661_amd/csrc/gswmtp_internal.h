@@ -58,6 +58,7 @@ struct Bufs {
   // inputs and index work (sized by ny, nx, nf)
   double *fx = nullptr, *fy = nullptr, *target = nullptr, *tnorm = nullptr;
   double *fz = nullptr;                  // axial positions (zeros: the focal plane)
+  double *meas = nullptr;                // [nf] measured intensities, then at unit sum
   double *xzu = nullptr, *yzu = nullptr;  // z of each unique (x, z) / (y, z) key
   double *xu = nullptr, *yu = nullptr;
   int *ix = nullptr, *iy = nullptr, *firstx = nullptr, *firsty = nullptr;
@@ -308,6 +309,7 @@ struct gswmtp_plan {
   size_t pool0_bytes = 0, pool1_bytes = 0;
   hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
   bool fwd_valid = false;                 // theta/stats match the current phase
+  const double *meas_active = nullptr;    // b.meas while a measured pass is queued, else null
   bool use_graph = true;
   std::string err;
 };

@@ -268,6 +268,23 @@ __global__ __launch_bounds__(1024) void k_count(const int *flags, int n, int *ou
 }
 
 // Any two foci with the same (ix, iy) pair.
+// Measured focus intensities (camera in the loop) divided by their sum, as
+// the weight update normalises computed intensities: one workgroup, the sum
+// in float64 in a fixed order.  The host has checked that the sum is > 0.
+__global__ __launch_bounds__(1024) void k_meas_norm(double *m, int n) {
+  __shared__ double part[1024];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) acc += m[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double sum = part[0];
+  for (int i = threadIdx.x; i < n; i += 1024) m[i] = m[i] / sum;
+}
+
 __global__ __launch_bounds__(256) void k_dup(const int *ix, const int *iy, int n, int *dup) {
   __shared__ int tx[256], ty[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -897,7 +914,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   auto carve0 = [&](Carver &c) {
     Bufs &b = p->b;
     b.fx = c.take<double>(nf); b.fy = c.take<double>(nf); b.fz = c.take<double>(nf);
-    b.xzu = c.take<double>(nf); b.yzu = c.take<double>(nf);
+    b.xzu = c.take<double>(nf); b.yzu = c.take<double>(nf); b.meas = c.take<double>(nf);
     b.target = c.take<double>(nf); b.tnorm = c.take<double>(nf);
     b.xu = c.take<double>(nf); b.yu = c.take<double>(nf);
     b.ix = c.take<int>(nf); b.iy = c.take<int>(nf);
@@ -1231,6 +1248,33 @@ int gswmtp_iterate(gswmtp_plan *p, int n_iter, double stop_accuracy) {
   }
   p->fwd_valid = false;
   HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+int gswmtp_iterate_measured(gswmtp_plan *p, const double *measured) {
+  if (!p || !measured) return GSWMTP_E_INVAL;
+  const size_t nf = (size_t)p->d.nf;
+  double sum = 0.0;
+  for (size_t n = 0; n < nf; ++n) {
+    if (!std::isfinite(measured[n]) || measured[n] < 0.0)
+      return fail(p, GSWMTP_E_INVAL, "measured intensities must be finite and >= 0");
+    sum += measured[n];
+  }
+  if (!(sum > 0.0) || !std::isfinite(sum))
+    return fail(p, GSWMTP_E_INVAL, "measured intensities must have a finite positive sum");
+  DeviceGuard g(p->device);
+  HIP_TRY(p, enter(p));
+  HIP_TRY(p, hipMemcpyAsync(p->b.meas, measured, 8 * nf, hipMemcpyHostToDevice, p->stream));
+  hipLaunchKernelGGL(k_meas_norm, dim3(1), dim3(1024), 0, p->stream, p->b.meas, (int)nf);
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, p->stream, p->b.ctrl, p->b.stats, 0.0);
+  HIP_TRY(p, hipGetLastError());
+  p->meas_active = p->b.meas;
+  const hipError_t e = enqueue_pass(p, p->stream);   // eager: graphs hold no measured pass
+  p->meas_active = nullptr;
+  HIP_TRY(p, e);
+  p->fwd_valid = false;
+  HIP_TRY(p, leave(p));
+  HIP_TRY(p, hipStreamSynchronize(p->stream));        // the caller may reuse `measured`
   return GSWMTP_OK;
 }
 

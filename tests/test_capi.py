@@ -85,7 +85,7 @@ def _desc(g, **over):
 
 @pytest.mark.parametrize("case", [
     "ny0", "nf0", "nfhuge", "sx0", "sxnan", "fxnan", "targetneg", "targetzero", "ampneg",
-    "ampnan", "phinan", "unan", "precision", "axis", "weighting"])
+    "ampnan", "phinan", "unan", "precision", "axis", "weighting", "fznan", "fzinf"])
 def test_validation_rejects_bad_descriptors(case):
     import paper_2206_12661_amd as g
     lib = g.load_library()
@@ -100,6 +100,8 @@ def test_validation_rejects_bad_descriptors(case):
         "phinan": {"phi0": np.full(64, np.inf, np.float32)},
         "unan": {"u": np.full(8, np.nan)},
         "precision": {"precision": 9}, "axis": {"axis": 2}, "weighting": {"weighting": 5},
+        "fznan": {"fz": np.array([0.0, math.nan, 0.0])},
+        "fzinf": {"fz": np.array([math.inf, 0.0, 0.0])},
     }[case]
     d, keep = _desc(g, **over)
     h = ctypes.c_void_p()
@@ -117,6 +119,7 @@ def test_null_arguments(lib):
     assert lib.gswmtp_desc_init(None) == -1
     assert lib.gswmtp_iterate(None, 1, 0.0) == -1
     assert lib.gswmtp_set_phase_fixing(None, 1) == -1
+    assert lib.gswmtp_iterate_measured(None, None) == -1
     assert lib.gswmtp_batch_destroy(None) == 0
     b = ctypes.c_void_p()
     assert lib.gswmtp_batch_create(None, None, 1, None) == -1

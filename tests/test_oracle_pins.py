@@ -557,3 +557,53 @@ def test_volume_index_pairs_brute_force():
     assert list(ix) == [3, 4, 1, 0, 5, 2]
     assert not oracle.has_duplicate_foci(fx, fy, fz)
     assert oracle.has_duplicate_foci(fx[:2], fy[:2], np.array([10.0, 10.0]))
+
+
+# --------------------------------------------------------------------------
+# Camera in the loop: measured intensities in the weight update
+# --------------------------------------------------------------------------
+
+def test_camera_never_switching_is_plain_gsw():
+    """A threshold no field reaches leaves Algorithm 1 untouched, bit for bit."""
+    h = synth_ofa.config1()
+    r = oracle.gsw(h, n_iter=6)
+    c = oracle.camera_loop(h, 6, lambda th: np.abs(th) ** 2, xi_switch=2.0)
+    assert c["switched"] is None
+    assert np.array_equal(c["phi"], r["phi"]) and np.array_equal(c["w"], r["w"])
+    assert np.array_equal(c["history"], r["history"])
+
+
+def test_camera_ideal_and_scaled_match_plain_gsw():
+    """A camera that reports |Theta|^2, or any constant multiple of it (its
+    gain is unknown), gives Algorithm 1's result: intensities enter the
+    weight update only through their unit-sum normalisation."""
+    h = synth_ofa.random_case(92, 40, 48, 9, radius=18.0)
+    r = oracle.gsw(h, n_iter=5)
+    amp = np.asarray(h.amplitude, np.float64)
+    for gain in (1.0, 37.5):
+        c = oracle.camera_loop(h, 5, lambda th: gain * np.abs(th) ** 2, xi_switch=-np.inf)
+        assert c["switched"] == 0
+        err = np.linalg.norm(amp * np.exp(1j * c["phi"]) - amp * np.exp(1j * r["phi"]))
+        assert err <= 1e-9 * np.linalg.norm(amp)
+        assert np.allclose(c["w"], r["w"], rtol=1e-9, atol=0)
+
+
+def test_camera_compensates_a_per_focus_system_gain():
+    """The point of the strategy: with a system that delivers g_n I_n to the
+    camera (uneven transmission), feedback from the camera drives the
+    MEASURED intensities to the targets, so the computed ones settle near
+    t_n / g_n; plain GSW drives the computed ones to the targets instead."""
+    h = synth_ofa.config1()
+    g = np.random.default_rng(93).uniform(0.6, 1.4, h.n_foci)
+
+    def acc(i, t):
+        i, t = i / i.sum(), t / t.sum()
+        return 1.0 - np.linalg.norm(t - i) / np.linalg.norm(i)
+
+    r = oracle.gsw(h, n_iter=40)
+    c = oracle.camera_loop(h, 40, lambda th: g * np.abs(th) ** 2, xi_switch=0.9)
+    assert c["switched"] is not None and c["switched"] > 0
+    I_c, I_r = np.abs(c["theta"]) ** 2, np.abs(r["theta"]) ** 2
+    assert acc(g * I_c, h.target) > 0.99          # the camera sees the targets
+    assert acc(I_c, h.target / g) > 0.99          # the field pre-compensates g
+    assert acc(g * I_r, h.target) < 0.95          # plain GSW does not
