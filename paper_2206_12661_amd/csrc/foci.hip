@@ -675,7 +675,7 @@ __global__ __launch_bounds__(256) void focus_scatter_split(
     split_terms<BF, NT>(ti[8 * part + q][i], &vi[0][q], 8);
   }
   const size_t plane = (size_t)Cp * Urp;
-  const size_t off = (size_t)(i0 + i) * Urp + a0 + 8 * part;
+  const size_t off = kblk_index(i0 + i, a0 + 8 * part, Cp);   // 8 a in one k-block
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int q = 0; q < NT; ++q) {

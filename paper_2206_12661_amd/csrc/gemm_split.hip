@@ -10,10 +10,12 @@
 // (Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br); -Ai is formed in registers by
 // flipping sign bits.
 //
-// Layout: both operands k-contiguous, 16-bit planes [re/im][term][row][K]:
+// Layout: both operands as 16-bit planes [re/im][term] of a [row][K]
+// matrix, stored k-blocked (blocks of kKB = 32 k for all rows, so a stage of
+// a row tile is one contiguous run of whole cache lines):
 //   forward   A = Omega_r [Urp][Rp],      B^T = P^T [Cp][Rp]
 //   adjoint   A = Omega_r^H [Rp][Urp],    B^T = S^T [Cp][Urp]
-// so each MFMA operand fragment (8 consecutive k of one row) is one 16-byte
+// and each MFMA operand fragment (8 consecutive k of one row) is one 16-byte
 // LDS read.  A stage holds BK complex k (BK / 16 MFMA k-steps) in rows of
 // BK / 8 16-byte chunks; the chunk index is XOR-swizzled with row bits so
 // fragment reads of 8 or 16 consecutive rows hit distinct banks.
@@ -22,7 +24,7 @@
 // Epilogues: store float32 C (forward, for the focus gather); or project onto
 // the amplitude constraint and write the pupil field directly as the split
 // B^T planes of the next forward product, transposed through LDS so every
-// store covers whole rows of P^T.
+// store is a 16-byte run of one row of P^T.
 #include "gswmtp_internal.h"
 
 namespace gswmtp {
@@ -89,15 +91,19 @@ struct SplitArgs {
 };
 
 // MFMA work of one LDS stage: BK / 16 k-steps over the wave's MB x NB blocks.
-template <int BM, int BN, int BK, bool BF, int NT>
+// With KG k-groups the stage's k-steps are dealt out in KG contiguous runs:
+// group kg takes k-steps kg KS / KG .. (kg + 1) KS / KG - 1.
+template <int BM, int BN, int BK, bool BF, int NT, int KG>
 __device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
                                           v16f (&accR)[BM / 64][BN / 64],
                                           v16f (&accI)[BM / 64][BN / 64], int wm, int wn,
-                                          int l32, int h) {
+                                          int l32, int h, int kg) {
   constexpr int WTM = BM / 2, WTN = BN / 2, MB = WTM / 32, NB = WTN / 32;
-  constexpr int PL = 2 * NT, KS = BK / kKStep, CH = BK / 8;
+  constexpr int PL = 2 * NT, KS = BK / kKStep, CH = BK / 8, KSG = KS / KG;
+  static_assert(KS % KG == 0, "k-steps per stage must divide among the k-groups");
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
+  for (int q_ = 0; q_ < KSG; ++q_) {
+    const int ks = kg * KSG + q_;
     // fragments: lane (l32, h) reads row l32 of its block, k = 16 ks + 8 h .. + 7
     u4 fa[MB][PL], fb[NB][PL], na[MB][NT];
 #pragma unroll
@@ -134,16 +140,25 @@ __device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
   }
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI>
-__global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
+// KG = 2: two k-groups of four waves each (512 threads) share every LDS
+// stage, each multiplying half of its k-steps into its own accumulators;
+// after the last stage group 1 hands its sums to group 0 through LDS
+// (group 0 adds them: acc0 + acc1, a fixed order) and exits, and group 0
+// runs the epilogue alone (a barrier waits only for the waves still
+// running).  The tile count of these products is small (about two 64 x 64
+// tiles per CU), so this doubles the waves per SIMD that hide LDS and
+// barrier latency without shrinking the tiles.
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG>
+__global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
+  constexpr int NTH = kThreads * KG;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
   constexpr int PL = 2 * NT;                     // planes per operand
   constexpr int KS = BK / kKStep;                // MFMA k-steps per stage
   constexpr int CH = BK / 8;                     // 16-byte chunks per row and stage
   constexpr int LA = PL * BM * CH, LB = PL * BN * CH;   // chunks loaded per stage
-  constexpr int NA = LA / kThreads, NBL = LB / kThreads;
-  static_assert(LA % kThreads == 0 && LB % kThreads == 0, "tile/thread mismatch");
+  constexpr int NA = LA / NTH, NBL = LB / NTH;
+  static_assert(LA % NTH == 0 && LB % NTH == 0, "tile/thread mismatch");
   constexpr int SA_SZ = LA, SB_SZ = LB;
   // epilogue transpose tile: [plane][n][m] 16-bit with rows padded by 8 elements
   constexpr int TP = BM + 8;
@@ -174,7 +189,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
   }
   const int m0 = (t % a.tiles_m) * BM;
   const int n0 = (t / a.tiles_m) * BN;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = (tid >> 6) & 3, kg = tid >> 8;
   const int wm = wave & 1, wn = wave >> 1;
   const int l32 = lane & 31, h = lane >> 5;
 
@@ -193,56 +208,110 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
   int la[NA], lb[NBL];
 #pragma unroll
   for (int s = 0; s < NA; ++s) {
-    const int id = tid + kThreads * s;
+    const int id = tid + NTH * s;
     const int c = id % CH, row = (id / CH) % BM, plane = id / (CH * BM);
-    ga[s] = a.a + (size_t)plane * a.a_plane + (size_t)(m0 + row) * a.K + 8 * c;
+    ga[s] = a.a + (size_t)plane * a.a_plane + (size_t)(m0 + row) * kKB + 8 * c;
     la[s] = (plane * BM + row) * CH + (c ^ swz<CH>(row));
   }
 #pragma unroll
   for (int s = 0; s < NBL; ++s) {
-    const int id = tid + kThreads * s;
+    const int id = tid + NTH * s;
     const int c = id % CH, row = (id / CH) % BN, plane = id / (CH * BN);
-    gb[s] = a.b + (size_t)plane * a.b_plane + (size_t)(n0 + row) * a.K + 8 * c;
+    gb[s] = a.b + (size_t)plane * a.b_plane + (size_t)(n0 + row) * kKB + 8 * c;
     lb[s] = (plane * BN + row) * CH + (c ^ swz<CH>(row));
   }
   // Two stages in flight: while stage kt is multiplied out of LDS buffer
   // (kt - kb) & 1, the register set of stage kt + 1 waits to be written to
   // the other buffer and the loads of stage kt + 2 are issued into the set
-  // just freed.
+  // just freed.  Loads and stores are unconditional (stage indices clamped
+  // to the last stage; the extra copies land in a buffer nobody reads), so
+  // every store waits only for its own set's loads, never for the set issued
+  // after it.
   u4 r0a[NA], r0b[NBL], r1a[NA], r1b[NBL];
+  // stage kt starts at k = kt BK: k-block (kt BK) / kKB, offset (kt BK) % kKB
 #define LOAD_STAGE(RA, RB, KT)                                                         \
   do {                                                                                 \
+    const size_t k_ = (size_t)(KT) * BK;                                               \
+    const size_t oa_ = k_ / kKB * ((size_t)a.M * kKB) + k_ % kKB;                      \
+    const size_t ob_ = k_ / kKB * ((size_t)a.N * kKB) + k_ % kKB;                      \
     _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) RA[s_] =                         \
-        *reinterpret_cast<const u4 *>(ga[s_] + (KT) * BK);                              \
+        *reinterpret_cast<const u4 *>(ga[s_] + oa_);                                   \
     _Pragma("unroll") for (int s_ = 0; s_ < NBL; ++s_) RB[s_] =                        \
-        *reinterpret_cast<const u4 *>(gb[s_] + (KT) * BK);                              \
+        *reinterpret_cast<const u4 *>(gb[s_] + ob_);                                   \
   } while (0)
 #define STORE_STAGE(RA, RB, BUF)                                                       \
   do {                                                                                 \
     _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) sA[(BUF) * SA_SZ + la[s_]] = RA[s_]; \
     _Pragma("unroll") for (int s_ = 0; s_ < NBL; ++s_) sB[(BUF) * SB_SZ + lb[s_]] = RB[s_]; \
   } while (0)
-  if (kb < ke) LOAD_STAGE(r0a, r0b, kb);
-  if (kb + 1 < ke) LOAD_STAGE(r1a, r1b, kb + 1);
-  // The done flag is read while the first two stages are in flight (the
-  // loads are kept above the test), not before them.
-  const int stop = a.done ? *a.done : 0;
-  asm volatile("" ::: "memory");
-  if (stop) return;
-  if (kb < ke) STORE_STAGE(r0a, r0b, 0);
-  __syncthreads();
-
-  for (int kt = kb; kt < ke; kt += 2) {
-    if (kt + 2 < ke) LOAD_STAGE(r0a, r0b, kt + 2);
-    stage_mma<BM, BN, BK, BF, NT>(sA, sB, accR, accI, wm, wn, l32, h);
-    if (kt + 1 < ke) STORE_STAGE(r1a, r1b, 1);
-    __syncthreads();
-    if (kt + 1 >= ke) break;
-    if (kt + 3 < ke) LOAD_STAGE(r1a, r1b, kt + 3);
-    stage_mma<BM, BN, BK, BF, NT>(sA + SA_SZ, sB + SB_SZ, accR, accI, wm, wn, l32, h);
-    if (kt + 2 < ke) STORE_STAGE(r0a, r0b, 0);
-    __syncthreads();
+  if (kb < ke) {
+    const int last = ke - 1;
+    LOAD_STAGE(r0a, r0b, kb);
+    LOAD_STAGE(r1a, r1b, kb + 1 < last ? kb + 1 : last);
+    // The done flag is read while the first two stages are in flight (the
+    // loads are kept above the test), not before them.
+    const int stop = a.done ? *a.done : 0;
+    asm volatile("" ::: "memory");
+    if (stop) return;
+    // Stages in pairs with one exit, so the loop is entered from the
+    // prologue and from its back edge in the same state (set 0 older, set 1
+    // newer, both in flight); an odd last stage follows the loop.
+    int kt = kb;
+    for (; kt + 1 < ke; kt += 2) {
+      STORE_STAGE(r0a, r0b, 0);
+      __syncthreads();
+      LOAD_STAGE(r0a, r0b, kt + 2 < last ? kt + 2 : last);
+      __builtin_amdgcn_sched_barrier(0);   // issue the loads here, ahead of the MFMAs
+      stage_mma<BM, BN, BK, BF, NT, KG>(sA, sB, accR, accI, wm, wn, l32, h, kg);
+      STORE_STAGE(r1a, r1b, 1);
+      __syncthreads();
+      LOAD_STAGE(r1a, r1b, kt + 3 < last ? kt + 3 : last);
+      __builtin_amdgcn_sched_barrier(0);
+      stage_mma<BM, BN, BK, BF, NT, KG>(sA + SA_SZ, sB + SB_SZ, accR, accI, wm, wn, l32, h,
+                                        kg);
+    }
+    if (kt < ke) {
+      STORE_STAGE(r0a, r0b, 0);
+      __syncthreads();
+      stage_mma<BM, BN, BK, BF, NT, KG>(sA, sB, accR, accI, wm, wn, l32, h, kg);
+    }
+    __syncthreads();   // the epilogues reuse the operand buffers
+    if constexpr (KG == 2) {
+      // group 1's sums to group 0, thread-major (one float per lane per store)
+      float *red = reinterpret_cast<float *>(lds);
+      const int t4 = tid & (kThreads - 1);
+      if (kg == 1) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int o = (((i * NB + j) * 16 + r) * 2) * kThreads + t4;
+              red[o] = accR[i][j][r];
+              red[o + kThreads] = accI[i][j][r];
+            }
+      }
+      __syncthreads();
+      if (kg == 1) return;
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int o = (((i * NB + j) * 16 + r) * 2) * kThreads + t4;
+            accR[i][j][r] += red[o];
+            accI[i][j][r] += red[o + kThreads];
+          }
+      __syncthreads();   // the reduction buffer is read before any epilogue writes
+    }
+  } else {
+    const int stop = a.done ? *a.done : 0;
+    if (stop) return;
   }
+  if constexpr (KG == 2)
+    if (kg == 1) return;   // tail-reduction blocks: group 0 alone
 #undef LOAD_STAGE
 #undef STORE_STAGE
 
@@ -300,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
       }
   } else if constexpr (EPI == EPI_PROJECT) {
     // project, split into terms, transpose the tile through LDS, then write
-    // whole rows of P^T [plane][n][m0 .. m0 + BM)
+    // rows of P^T [plane][n][m0 .. m0 + BM) in 16-byte runs
     unsigned short *tt = reinterpret_cast<unsigned short *>(lds);
     __syncthreads();   // operand stages are no longer read
 #pragma unroll
@@ -340,8 +409,8 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_mfma(SplitArgs a) {
       const int id = tid + kThreads * s;
       const int c = id % RC, nl = (id / RC) % BN, pl = id / (RC * BN);
       const u4 v = *reinterpret_cast<const u4 *>(tt + ((size_t)pl * BN + nl) * TP + 8 * c);
-      *reinterpret_cast<u4 *>(a.pt + (size_t)pl * a.pt_plane + (size_t)(n0 + nl) * a.M + m0 +
-                              8 * c) = v;
+      *reinterpret_cast<u4 *>(a.pt + (size_t)pl * a.pt_plane +
+                              kblk_index(n0 + nl, m0 + 8 * c, a.N)) = v;   // 8 m, one k-block
     }
   }
 }
@@ -385,7 +454,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
         split_terms<BF, NT>(pr, &tr[0][q], 4);
         split_terms<BF, NT>(pi, &ti[0][q], 4);
       }
-      const size_t base = (size_t)(n0 + n) * a.M + m0 + m;
+      const size_t base = kblk_index(n0 + n, m0 + m, a.N);   // rows m .. m + 3, one k-block
 #pragma unroll
       for (int s = 0; s < NT; ++s) {
         const u2 vr = {(unsigned)tr[s][0] | ((unsigned)tr[s][1] << 16),
@@ -398,17 +467,17 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
     }
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG>
 hipError_t launch_t(const SplitArgs &args, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI>), dim3(grid), dim3(kThreads), 0,
-                     s, args);
+  hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI, KG>), dim3(grid),
+                     dim3(kThreads * KG), 0, s, args);
   return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG = 1>
 hipError_t launch_fit(const SplitArgs &args, int grid, hipStream_t s) {
   if constexpr (split_lds_bytes<BM, BN, BK, NT, EPI>() <= 160 * 1024)
-    return launch_t<BM, BN, BK, BF, NT, EPI>(args, grid, s);
+    return launch_t<BM, BN, BK, BF, NT, EPI, KG>(args, grid, s);
   return hipErrorInvalidValue;
 }
 
@@ -439,7 +508,9 @@ hipError_t launch_tail_split(int precision, const GemmTile &tl, const SplitArgs 
 template <bool BF, int NT, int EPI>
 hipError_t launch_e(const GemmTile &tl, const SplitArgs &args, int grid, hipStream_t s) {
   if (tl.bk == 32) {
-    if (tl.bm == 64 && tl.bn == 64) return launch_fit<64, 64, 32, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 64 && tl.bn == 64)
+      return tl.kg == 2 ? launch_fit<64, 64, 32, BF, NT, EPI, 2>(args, grid, s)
+                        : launch_fit<64, 64, 32, BF, NT, EPI>(args, grid, s);
     if (tl.bm == 128 && tl.bn == 64) return launch_fit<128, 64, 32, BF, NT, EPI>(args, grid, s);
     if (tl.bm == 64 && tl.bn == 128) return launch_fit<64, 128, 32, BF, NT, EPI>(args, grid, s);
     if (tl.bm == 128 && tl.bn == 128) return launch_fit<128, 128, 32, BF, NT, EPI>(args, grid, s);

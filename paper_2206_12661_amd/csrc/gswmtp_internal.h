@@ -29,6 +29,15 @@ namespace gswmtp {
 
 constexpr int kHistCap = 4096;     // history ring entries
 constexpr int kPadRows = 64;       // padding granule of M / K dimensions
+
+// K-blocked storage of a split operand plane [rows][K] (K a multiple of
+// kKB): K / kKB blocks of [rows][kKB], so kKB consecutive k of consecutive
+// rows - one product stage of a row tile - are one contiguous run and every
+// stage load covers whole cache lines.
+constexpr int kKB = 32;
+__host__ __device__ __forceinline__ size_t kblk_index(size_t row, size_t k, size_t rows) {
+  return (k / kKB) * rows * kKB + row * kKB + (k % kKB);
+}
 constexpr int kPadCols = 64;       // padding granule of the N dimension
 constexpr int kMaxFoci = 262144;
 constexpr int kMaxSide = 16384;
@@ -87,12 +96,13 @@ struct Bufs {
   float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
   float *part = nullptr;                 // split-K partial tiles (shared by both products)
   float *gpart = nullptr;                // fused-gather partials [tiles_n][nf] complex
-  // split-precision modes: 16-bit term planes, k-contiguous ([re/im][term][row][K])
-  unsigned short *as_f = nullptr;        // Omega_r            [2][NT][Urp][Rp]
-  unsigned short *as_b = nullptr;        // Omega_r^H          [2][NT][Rp][Urp]
-  unsigned short *ps = nullptr;          // pupil field P^T    [2][NT][Cp][Rp]
-  unsigned short *ss = nullptr;          // scatter S^T        [2][NT][Cp][Urp]
-  unsigned short *xs = nullptr;          // operator-call P^T  [2][NT][Cp][Rp]
+  // split-precision modes: 16-bit term planes [re/im][term] of a [row][K]
+  // matrix each, stored k-blocked (kblk_index)
+  unsigned short *as_f = nullptr;        // Omega_r            [2][NT] x [Urp][Rp]
+  unsigned short *as_b = nullptr;        // Omega_r^H          [2][NT] x [Rp][Urp]
+  unsigned short *ps = nullptr;          // pupil field P^T    [2][NT] x [Cp][Rp]
+  unsigned short *ss = nullptr;          // scatter S^T        [2][NT] x [Cp][Urp]
+  unsigned short *xs = nullptr;          // operator-call P^T  [2][NT] x [Cp][Rp]
   // grid form (float32): the second product of Eq. 2 formed densely
   float *lt_r = nullptr, *lt_i = nullptr;   // L^T            [Cp][Urp]
   float *wt_r = nullptr, *wt_i = nullptr;   // Omega_c        [Cp][Ucp]
@@ -174,7 +184,8 @@ __device__ __forceinline__ void tile_slot_pos(int tid, int i, int j, int r, int 
   n = wn * (BN / 2) + j * 32 + l32;
 }
 
-struct GemmTile { int bm = 64, bn = 64, bk = 16; };   // complex tile M x N, K per stage
+// complex tile M x N, K per stage; kg: k-groups of four waves (split products)
+struct GemmTile { int bm = 64, bn = 64, bk = 16, kg = 1; };
 
 // Launch schedule of one complex product: t_dp whole tiles, then n_tail tiles
 // split along K into `split` chunks (grid = t_dp + n_tail * split).

@@ -536,8 +536,8 @@ __global__ void k_expand_real(const float *xr, const int *row_pos, const int *co
 
 // ---- split-precision layouts (16-bit term planes, k-contiguous) ----
 
-// Omega_r as split planes: forward A [re/im][term][Urp][Rp] and adjoint
-// A = Omega_r^H [re/im][term][Rp][Urp].
+// Omega_r as split planes (k-blocked): forward A [re/im][term] x [Urp][Rp]
+// and adjoint A = Omega_r^H [re/im][term] x [Rp][Urp].
 template <bool BF, int NT>
 __global__ void k_omega_r_split(const double *coord, const int *kept, int Rk, const double *fu,
                                 const double *fuz, int Ur, double s, int Rp, int Urp,
@@ -552,16 +552,18 @@ __global__ void k_omega_r_split(const double *coord, const int *kept, int Rk, co
   split_terms<BF, NT>(im, ti, 1);
   split_terms<BF, NT>(-im, tc, 1);
   const size_t plane = (size_t)Rp * Urp;
+  const size_t of = kblk_index(a, j, Urp), ob = kblk_index(j, a, Rp);
 #pragma unroll
   for (int q = 0; q < NT; ++q) {
-    af[(size_t)q * plane + (size_t)a * Rp + j] = tr[q];
-    af[(size_t)(NT + q) * plane + (size_t)a * Rp + j] = ti[q];
-    ab[(size_t)q * plane + (size_t)j * Urp + a] = tr[q];
-    ab[(size_t)(NT + q) * plane + (size_t)j * Urp + a] = tc[q];
+    af[(size_t)q * plane + of] = tr[q];
+    af[(size_t)(NT + q) * plane + of] = ti[q];
+    ab[(size_t)q * plane + ob] = tr[q];
+    ab[(size_t)(NT + q) * plane + ob] = tc[q];
   }
 }
 
-// Pupil field from a phase as split planes P^T [re/im][term][Cp][Rp]
+// Pupil field from a phase as split planes P^T [re/im][term] x [Cp][Rp]
+// (k-blocked)
 // (amp already carries the power-of-two scale).
 template <bool BF, int NT>
 __global__ void k_encode_phase_split(Orient o, const float *phi, const float *amp, int nx,
@@ -579,9 +581,9 @@ __global__ void k_encode_phase_split(Orient o, const float *phi, const float *am
     re = a * cs;
     im = a * sn;
   }
-  const size_t plane = (size_t)Rp * Cp;
-  split_terms<BF, NT>(re, pt + id, (int)plane);
-  split_terms<BF, NT>(im, pt + (size_t)NT * plane + id, (int)plane);
+  const size_t plane = (size_t)Rp * Cp, at = kblk_index(i, j, Cp);
+  split_terms<BF, NT>(re, pt + at, (int)plane);
+  split_terms<BF, NT>(im, pt + (size_t)NT * plane + at, (int)plane);
 }
 
 // User-layout complex field (interleaved), times scale, as split planes P^T.
@@ -597,9 +599,9 @@ __global__ void k_compact_split(Orient o, const float *in, float scale, int nx, 
     re = in[2 * ((size_t)y * nx + x)] * scale;
     im = in[2 * ((size_t)y * nx + x) + 1] * scale;
   }
-  const size_t plane = (size_t)Rp * Cp;
-  split_terms<BF, NT>(re, pt + id, (int)plane);
-  split_terms<BF, NT>(im, pt + (size_t)NT * plane + id, (int)plane);
+  const size_t plane = (size_t)Rp * Cp, at = kblk_index(i, j, Cp);
+  split_terms<BF, NT>(re, pt + at, (int)plane);
+  split_terms<BF, NT>(im, pt + (size_t)NT * plane + at, (int)plane);
 }
 
 // Phase of the split pupil planes in the user's layout.
@@ -612,7 +614,7 @@ __global__ void k_phase_out_split(const unsigned short *pt, bool bf, int nt, con
   int r, c;
   float ph = 0.f;
   if (internal_of(row_pos, col_pos, axis, y, x, &r, &c) && amp[(size_t)r * Cp + c] > 0.f) {
-    const size_t plane = (size_t)Rp * Cp, o = (size_t)c * Rp + r;
+    const size_t plane = (size_t)Rp * Cp, o = kblk_index(c, r, Cp);
     const float re = join_terms(bf, nt, pt + o, plane);
     const float im = join_terms(bf, nt, pt + (size_t)nt * plane + o, plane);
     ph = atan2f(im, re);
@@ -728,10 +730,16 @@ void free_plan(gswmtp_plan *p) {
 
 // GEMM tile per product.  float32: 64 x 64 complex tiles, 16 k per stage
 // (three workgroups per CU resident).  Split modes: 64 x 64 tiles with 32 k
-// per stage (16-bit operands need longer stages to cover load latency).
-// GSWMTP_TILE=BMxBN[xBK] overrides (BK only for split modes).
+// per stage (16-bit operands need longer stages to cover load latency),
+// each stage's two k-steps taken by two groups of four waves.
+// GSWMTP_TILE=BMxBN[xBK] overrides (BK only for split modes; other tiles
+// use one k-group); GSWMTP_SPLIT_KG=1 keeps one k-group.
 GemmTile choose_tile(int M, int N, bool split) {
-  GemmTile t{64, 64, split ? 32 : 16};
+  GemmTile t{64, 64, split ? 32 : 16, 1};
+  if (split) {
+    const char *kg = std::getenv("GSWMTP_SPLIT_KG");
+    t.kg = kg && std::atoi(kg) == 1 ? 1 : 2;
+  }
   const char *env = std::getenv("GSWMTP_TILE");
   if (env) {
     int bm = 0, bn = 0, bk = 0;
@@ -741,6 +749,7 @@ GemmTile choose_tile(int M, int N, bool split) {
       t.bm = bm;
       t.bn = bn;
       if (split && n == 3 && (bk == 16 || bk == 32)) t.bk = bk;
+      if (t.bm != 64 || t.bn != 64 || t.bk != 32) t.kg = 1;
     }
   }
   return t;
