@@ -90,6 +90,83 @@ struct SplitArgs {
   int tiles_m, t_dp, split;
 };
 
+// Operand fragments of one MFMA k-step for the wave's MB x NB blocks: lane
+// (l32, h) holds row l32 of its block, k = 16 ks + 8 h .. + 7, every plane.
+template <int BM, int BN, int NT>
+struct Frags {
+  u4 a[BM / 64][2 * NT];
+  u4 b[BN / 64][2 * NT];
+};
+
+template <int BM, int BN, int BK, int NT>
+__device__ __forceinline__ void load_frags(const u4 *qa, const u4 *qb, int ks, int wm, int wn,
+                                           int l32, int h, Frags<BM, BN, NT> &f) {
+  constexpr int WTM = BM / 2, WTN = BN / 2, MB = WTM / 32, NB = WTN / 32;
+  constexpr int PL = 2 * NT, CH = BK / 8;
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    const int row = wm * WTM + i * 32 + l32;
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl)
+      f.a[i][pl] = qa[(pl * BM + row) * CH + ((2 * ks + h) ^ swz<CH>(row))];
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int row = wn * WTN + j * 32 + l32;
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl)
+      f.b[j][pl] = qb[(pl * BN + row) * CH + ((2 * ks + h) ^ swz<CH>(row))];
+  }
+}
+
+// The MFMAs of one k-step: term pairs (ta, tb) with ta + tb < NT, small
+// terms first; -Ai by flipping the sign bits of the imaginary A terms.
+template <int BM, int BN, bool BF, int NT>
+__device__ __forceinline__ void mma_frags(const Frags<BM, BN, NT> &f,
+                                          v16f (&accR)[BM / 64][BN / 64],
+                                          v16f (&accI)[BM / 64][BN / 64]) {
+  constexpr int MB = BM / 64, NB = BN / 64;
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    u4 na[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) na[q] = f.a[i][NT + q] ^ 0x80008000u;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int s = NT - 1; s >= 0; --s)
+#pragma unroll
+        for (int ta = 0; ta <= s; ++ta) {
+          const int tb = s - ta;
+          accR[i][j] = mfma16<BF>(f.a[i][ta], f.b[j][tb], accR[i][j]);
+          accR[i][j] = mfma16<BF>(na[ta], f.b[j][NT + tb], accR[i][j]);
+          accI[i][j] = mfma16<BF>(f.a[i][ta], f.b[j][NT + tb], accI[i][j]);
+          accI[i][j] = mfma16<BF>(f.a[i][NT + ta], f.b[j][tb], accI[i][j]);
+        }
+  }
+}
+
+// Scheduling requests for the pipelined loop (instruction classes of
+// sched_group_barrier: 0x008 MFMA, 0x020 VMEM read, 0x100 DS read, 0x200 DS
+// write).  N pairs of (one DS read, one MFMA).
+template <int N>
+__device__ __forceinline__ void sched_read_mfma() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    sched_read_mfma<N - 1>();
+  }
+}
+// N groups of (W DS writes, one MFMA).
+template <int N, int W>
+__device__ __forceinline__ void sched_write_mfma() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x200, W, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    sched_write_mfma<N - 1, W>();
+  }
+}
+
 // MFMA work of one LDS stage: BK / 16 k-steps over the wave's MB x NB blocks.
 // With KG k-groups the stage's k-steps are dealt out in KG contiguous runs:
 // group kg takes k-steps kg KS / KG .. (kg + 1) KS / KG - 1.
@@ -98,45 +175,13 @@ __device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
                                           v16f (&accR)[BM / 64][BN / 64],
                                           v16f (&accI)[BM / 64][BN / 64], int wm, int wn,
                                           int l32, int h, int kg) {
-  constexpr int WTM = BM / 2, WTN = BN / 2, MB = WTM / 32, NB = WTN / 32;
-  constexpr int PL = 2 * NT, KS = BK / kKStep, CH = BK / 8, KSG = KS / KG;
+  constexpr int KS = BK / kKStep, KSG = KS / KG;
   static_assert(KS % KG == 0, "k-steps per stage must divide among the k-groups");
 #pragma unroll
   for (int q_ = 0; q_ < KSG; ++q_) {
-    const int ks = kg * KSG + q_;
-    // fragments: lane (l32, h) reads row l32 of its block, k = 16 ks + 8 h .. + 7
-    u4 fa[MB][PL], fb[NB][PL], na[MB][NT];
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-      const int row = wm * WTM + i * 32 + l32;
-#pragma unroll
-      for (int pl = 0; pl < PL; ++pl)
-        fa[i][pl] = qa[(pl * BM + row) * CH + ((2 * ks + h) ^ swz<CH>(row))];
-#pragma unroll
-      for (int q = 0; q < NT; ++q) na[i][q] = fa[i][NT + q] ^ 0x80008000u;
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int row = wn * WTN + j * 32 + l32;
-#pragma unroll
-      for (int pl = 0; pl < PL; ++pl)
-        fb[j][pl] = qb[(pl * BN + row) * CH + ((2 * ks + h) ^ swz<CH>(row))];
-    }
-    // term pairs (ta, tb) with ta + tb < NT, small terms first
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int s = NT - 1; s >= 0; --s)
-#pragma unroll
-          for (int ta = 0; ta <= s; ++ta) {
-            const int tb = s - ta;
-            accR[i][j] = mfma16<BF>(fa[i][ta], fb[j][tb], accR[i][j]);
-            accR[i][j] = mfma16<BF>(na[i][ta], fb[j][NT + tb], accR[i][j]);
-            accI[i][j] = mfma16<BF>(fa[i][ta], fb[j][NT + tb], accI[i][j]);
-            accI[i][j] = mfma16<BF>(fa[i][NT + ta], fb[j][tb], accI[i][j]);
-          }
+    Frags<BM, BN, NT> f;
+    load_frags<BM, BN, BK, NT>(qa, qb, kg * KSG + q_, wm, wn, l32, h, f);
+    mma_frags<BM, BN, BF, NT>(f, accR, accI);
   }
 }
 
@@ -148,7 +193,16 @@ __device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
 // running).  The tile count of these products is small (about two 64 x 64
 // tiles per CU), so this doubles the waves per SIMD that hide LDS and
 // barrier latency without shrinking the tiles.
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG>
+//
+// PIPE (one k-group, two k-steps per stage): the fragment reads are
+// software-pipelined so LDS traffic overlaps the MFMAs of the same wave.
+// Per stage S (LDS buffer S & 1, fragments of k-step 0 already in f0): read
+// k-step 1 into f1 while f0's MFMAs run; one barrier (every read of the
+// buffer is done, stage S + 1 is published); read stage S + 1's k-step 0
+// into f0 while f1's MFMAs run; then store stage S + 2 (held in registers
+// since two stages ago) into the buffer just left and issue the loads of
+// stage S + 4.
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
 __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
   constexpr int NTH = kThreads * KG;
   constexpr int WTM = BM / 2, WTN = BN / 2;
@@ -253,6 +307,46 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
     const int stop = a.done ? *a.done : 0;
     asm volatile("" ::: "memory");
     if (stop) return;
+    if constexpr (PIPE) {
+      static_assert(KG == 1 && BK == 2 * kKStep, "pipelined loop: one group, two k-steps");
+      STORE_STAGE(r0a, r0b, 0);
+      LOAD_STAGE(r0a, r0b, kb + 2 < last ? kb + 2 : last);
+      STORE_STAGE(r1a, r1b, 1);
+      LOAD_STAGE(r1a, r1b, kb + 3 < last ? kb + 3 : last);
+      __syncthreads();
+      Frags<BM, BN, NT> f0, f1;
+      load_frags<BM, BN, BK, NT>(sA, sB, 0, wm, wn, l32, h, f0);
+      // per k-step: NR fragment reads, NM MFMAs; NS stage stores / loads per thread
+      constexpr int NR = (BM / 64 + BN / 64) * 2 * NT;
+      constexpr int NM = (BM / 64) * (BN / 64) * 2 * NT * (NT + 1);
+      constexpr int NS = NA + NBL;
+      static_assert(NM >= NR && NS % (NM - NR > 0 ? NM - NR : 1) == 0, "interleave pattern");
+      // The read of the next stage's k-step 0 is unconditional: after the
+      // last stage it reads the clamped copy in the other buffer, unused.
+#define PIPE_STEP(BUF, RA, RB, S)                                                              \
+  do {                                                                                         \
+    load_frags<BM, BN, BK, NT>(sA + (BUF) * SA_SZ, sB + (BUF) * SB_SZ, 1, wm, wn, l32, h, f1); \
+    mma_frags<BM, BN, BF, NT>(f0, accR, accI);                                                 \
+    sched_read_mfma<NR>();                                                                     \
+    __builtin_amdgcn_sched_group_barrier(0x008, NM - NR, 0);                                   \
+    __syncthreads();                                                                           \
+    load_frags<BM, BN, BK, NT>(sA + (1 - (BUF)) * SA_SZ, sB + (1 - (BUF)) * SB_SZ, 0, wm, wn,   \
+                               l32, h, f0);                                                    \
+    mma_frags<BM, BN, BF, NT>(f1, accR, accI);                                                 \
+    STORE_STAGE(RA, RB, BUF);                                                                  \
+    LOAD_STAGE(RA, RB, (S) + 4 < last ? (S) + 4 : last);                                       \
+    sched_read_mfma<NR>();                                                                     \
+    sched_write_mfma<NM - NR, NS / (NM - NR > 0 ? NM - NR : 1)>();                             \
+    __builtin_amdgcn_sched_group_barrier(0x020, NS, 0);                                        \
+  } while (0)
+      int kt = kb;
+      for (; kt + 1 < ke; kt += 2) {
+        PIPE_STEP(0, r0a, r0b, kt);
+        PIPE_STEP(1, r1a, r1b, kt + 1);
+      }
+      if (kt < ke) PIPE_STEP(0, r0a, r0b, kt);
+#undef PIPE_STEP
+    } else {
     // Stages in pairs with one exit, so the loop is entered from the
     // prologue and from its back edge in the same state (set 0 older, set 1
     // newer, both in flight); an odd last stage follows the loop.
@@ -274,6 +368,7 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
       STORE_STAGE(r0a, r0b, 0);
       __syncthreads();
       stage_mma<BM, BN, BK, BF, NT, KG>(sA, sB, accR, accI, wm, wn, l32, h, kg);
+    }
     }
     __syncthreads();   // the epilogues reuse the operand buffers
     if constexpr (KG == 2) {
@@ -467,17 +562,17 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
     }
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
 hipError_t launch_t(const SplitArgs &args, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI, KG>), dim3(grid),
+  hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI, KG, PIPE>), dim3(grid),
                      dim3(kThreads * KG), 0, s, args);
   return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG = 1>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG = 1, bool PIPE = false>
 hipError_t launch_fit(const SplitArgs &args, int grid, hipStream_t s) {
   if constexpr (split_lds_bytes<BM, BN, BK, NT, EPI>() <= 160 * 1024)
-    return launch_t<BM, BN, BK, BF, NT, EPI, KG>(args, grid, s);
+    return launch_t<BM, BN, BK, BF, NT, EPI, KG, PIPE>(args, grid, s);
   return hipErrorInvalidValue;
 }
 
@@ -508,9 +603,11 @@ hipError_t launch_tail_split(int precision, const GemmTile &tl, const SplitArgs 
 template <bool BF, int NT, int EPI>
 hipError_t launch_e(const GemmTile &tl, const SplitArgs &args, int grid, hipStream_t s) {
   if (tl.bk == 32) {
-    if (tl.bm == 64 && tl.bn == 64)
+    if (tl.bm == 64 && tl.bn == 64) {
+      if (tl.pipe) return launch_fit<64, 64, 32, BF, NT, EPI, 1, true>(args, grid, s);
       return tl.kg == 2 ? launch_fit<64, 64, 32, BF, NT, EPI, 2>(args, grid, s)
                         : launch_fit<64, 64, 32, BF, NT, EPI>(args, grid, s);
+    }
     if (tl.bm == 128 && tl.bn == 64) return launch_fit<128, 64, 32, BF, NT, EPI>(args, grid, s);
     if (tl.bm == 64 && tl.bn == 128) return launch_fit<64, 128, 32, BF, NT, EPI>(args, grid, s);
     if (tl.bm == 128 && tl.bn == 128) return launch_fit<128, 128, 32, BF, NT, EPI>(args, grid, s);

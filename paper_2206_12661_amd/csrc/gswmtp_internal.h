@@ -184,8 +184,9 @@ __device__ __forceinline__ void tile_slot_pos(int tid, int i, int j, int r, int 
   n = wn * (BN / 2) + j * 32 + l32;
 }
 
-// complex tile M x N, K per stage; kg: k-groups of four waves (split products)
-struct GemmTile { int bm = 64, bn = 64, bk = 16, kg = 1; };
+// complex tile M x N, K per stage; split products: kg k-groups of four waves,
+// pipe: software-pipelined fragment reads (one k-group)
+struct GemmTile { int bm = 64, bn = 64, bk = 16, kg = 1, pipe = 0; };
 
 // Launch schedule of one complex product: t_dp whole tiles, then n_tail tiles
 // split along K into `split` chunks (grid = t_dp + n_tail * split).

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <string>
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -730,15 +731,21 @@ void free_plan(gswmtp_plan *p) {
 
 // GEMM tile per product.  float32: 64 x 64 complex tiles, 16 k per stage
 // (three workgroups per CU resident).  Split modes: 64 x 64 tiles with 32 k
-// per stage (16-bit operands need longer stages to cover load latency),
-// each stage's two k-steps taken by two groups of four waves.
-// GSWMTP_TILE=BMxBN[xBK] overrides (BK only for split modes; other tiles
-// use one k-group); GSWMTP_SPLIT_KG=1 keeps one k-group.
-GemmTile choose_tile(int M, int N, bool split) {
-  GemmTile t{64, 64, split ? 32 : 16, 1};
+// per stage (16-bit operands need longer stages to cover load latency) and
+// the software-pipelined stage loop (two-term modes) or two k-groups
+// (three-term).  GSWMTP_SPLIT_LOOP=pipe|kg2|plain picks
+// the split products' loop (kg2: each stage's two k-steps taken by two
+// groups of four waves); GSWMTP_TILE=BMxBN[xBK] overrides the tile (BK only
+// for split modes; other tiles use the plain loop).
+GemmTile choose_tile(int M, int N, bool split, int terms = 2) {
+  GemmTile t{64, 64, split ? 32 : 16, 1, 0};
   if (split) {
-    const char *kg = std::getenv("GSWMTP_SPLIT_KG");
-    t.kg = kg && std::atoi(kg) == 1 ? 1 : 2;
+    // three-term operands hold too many fragment registers to pipeline
+    // them at two workgroups per CU: two k-groups instead
+    const char *lp = std::getenv("GSWMTP_SPLIT_LOOP");
+    const std::string v = lp ? lp : terms > 2 ? "kg2" : "pipe";
+    t.kg = v == "kg2" ? 2 : 1;
+    t.pipe = v == "pipe" ? 1 : 0;
   }
   const char *env = std::getenv("GSWMTP_TILE");
   if (env) {
@@ -749,7 +756,7 @@ GemmTile choose_tile(int M, int N, bool split) {
       t.bm = bm;
       t.bn = bn;
       if (split && n == 3 && (bk == 16 || bk == 32)) t.bk = bk;
-      if (t.bm != 64 || t.bn != 64 || t.bk != 32) t.kg = 1;
+      if (t.bm != 64 || t.bn != 64 || t.bk != 32) t.kg = 1, t.pipe = 0;
     }
   }
   return t;
@@ -1033,10 +1040,11 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   D.Cp = (int)round_up(D.Ck, kPadCols);
   D.Urp = (int)round_up(D.Ur, kPadRows);
   const bool split_mode = is_split(p);
-  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp, choose_tile(D.Urp, D.Cp, split_mode), p->cus,
-                            split_enabled());
-  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, choose_tile(D.Rp, D.Cp, split_mode), p->cus,
-                            split_enabled());
+  const int terms = split_terms_of(p->precision);
+  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp, choose_tile(D.Urp, D.Cp, split_mode, terms),
+                            p->cus, split_enabled());
+  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, choose_tile(D.Rp, D.Cp, split_mode, terms),
+                            p->cus, split_enabled());
   // Grid form (float32): when the foci fill a quarter or more of the reduced
   // grid, the second product of Eq. 2 is formed densely on the matrix cores
   // (as the paper does) instead of per focus.  GSWMTP_SECOND=gather|grid
