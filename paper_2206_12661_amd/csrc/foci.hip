@@ -51,6 +51,8 @@ struct UpdateArgs {
   float *intensity;        // [nf] |Theta|^2
   const double *target;    // [nf] raw target intensities
   const double *tnorm;     // [nf] target / sum(target)
+  const double *tinv;      // [nf] 1 / tnorm (0 where tnorm is 0)
+  const double *tsqrt;     // [nf] sqrt(target)
   double *w;               // [nf]
   double *fixph;           // [2 nf] frozen focal phasors (phase fixing)
   double *stats;           // ST_*
@@ -66,6 +68,19 @@ struct UpdateArgs {
   const double *meas;      // [nf] measured intensities at unit sum (camera in the loop):
                            // the weight update's i, in place of |Theta|^2 / sum; or null
 };
+
+// Unit phasor Theta / |Theta| (1 at a dark focus) from float64 parts: one
+// reciprocal square root, accurate far beyond the float32 field it scales.
+__device__ __forceinline__ void unit_phasor(double re, double im, double &pr, double &pi) {
+  const double m2 = re * re + im * im;
+  pr = 1.0;
+  pi = 0.0;
+  if (m2 > 0.0) {
+    const double r = __builtin_amdgcn_rsq(m2);
+    pr = re * r;
+    pi = im * r;
+  }
+}
 
 // Algorithm 1 between the two propagations, for all foci, in one workgroup:
 //   Theta_n = sum of the forward product's gather partials (fixed order);
@@ -124,7 +139,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   const int fix_k = upd ? a.ctrl[CTRL_FIX] : 0;
   const bool fixing = fix_k > 0 && iters0 + 1 >= fix_k;
   const bool recorded = fixing && a.ctrl[CTRL_FIXED] != 0;
-  double tn[FPT], tg[FPT], wv[FPT], fpr[FPT], fpi[FPT], mi[FPT];
+  double tn[FPT], tiv[FPT], tg[FPT], wv[FPT], fpr[FPT], fpi[FPT], mi[FPT];
   float thr[FPT], thi[FPT];
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
@@ -132,7 +147,8 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
     const bool ok = n < a.nf;
     mi[f] = ok && upd && a.meas ? a.meas[n] : 0.0;
     tn[f] = ok ? a.tnorm[n] : 0.0;
-    tg[f] = ok && upd ? a.target[n] : 0.0;
+    tiv[f] = ok ? a.tinv[n] : 0.0;
+    tg[f] = ok && upd ? a.tsqrt[n] : 0.0;
     wv[f] = ok && upd ? a.w[n] : 0.0;
     fpr[f] = ok && recorded ? a.fixph[2 * n] : 1.0;
     fpi[f] = ok && recorded ? a.fixph[2 * n + 1] : 0.0;
@@ -155,11 +171,10 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
 #pragma unroll
     for (int f = 0; f < FPT; ++f)
 #pragma unroll
-      for (int j = 0; j < CHUNK; ++j)
-        if (q + j < a.T) {
-          thr[f] += v[f][j].x;
-          thi[f] += v[f][j].y;
-        }
+      for (int j = 0; j < CHUNK; ++j) {   // zeros past T: exact no-ops
+        thr[f] += v[f][j].x;
+        thi[f] += v[f][j].y;
+      }
   }
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
@@ -195,14 +210,14 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
     sv[0] += (tn[f] - in) * (tn[f] - in);
     sv[1] += in * in;
     if (tn[f] > 0.0) {
-      const double r = in / tn[f];
+      const double r = in * tiv[f];
       mv[0] = r > mv[0] ? r : mv[0];
       mv[1] = -r > mv[1] ? -r : mv[1];
     }
     if (upd) {
       const double iw = a.meas ? mi[f] : in;
       if (a.weighting == GSWMTP_WEIGHT_GSW) wv[f] *= sqrt(tn[f] / (iw > 1e-30 ? iw : 1e-30));
-      amag[f] = wv[f] * sqrt(tg[f]);
+      amag[f] = wv[f] * tg[f];
       mv[2] = amag[f] > mv[2] ? amag[f] : mv[2];
     }
   }
@@ -248,12 +263,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
       pr = fpr[f];
       pi = fpi[f];
     } else {
-      const double re = thr[f], im = thi[f];
-      const double mag = sqrt(re * re + im * im);
-      if (mag > 0.0) {
-        pr = re / mag;
-        pi = im / mag;
-      }
+      unit_phasor(thr[f], thi[f], pr, pi);
       if (fixing) {
         a.fixph[2 * n] = pr;
         a.fixph[2 * n + 1] = pi;
@@ -300,11 +310,10 @@ __device__ __forceinline__ void big_phase1(const UpdateArgs &a, int b, double (*
     for (int j = 0; j < CHUNK; ++j)
       v[j] = q + j < a.T && n < a.nf ? gp[(size_t)(q + j) * a.nf + n] : f2{0.f, 0.f};
 #pragma unroll
-    for (int j = 0; j < CHUNK; ++j)
-      if (q + j < a.T) {
-        sr += v[j].x;
-        si += v[j].y;
-      }
+    for (int j = 0; j < CHUNK; ++j) {   // zeros past T: exact no-ops
+      sr += v[j].x;
+      si += v[j].y;
+    }
   }
   sr *= a.scale;
   si *= a.scale;
@@ -331,7 +340,7 @@ __device__ __forceinline__ double big_sum_I(const UpdateArgs &a, double (*slots)
 
 // Per-focus terms of phase 2 / phase 3 (the same arithmetic in both).
 struct BigFocus {
-  double in, tn, tg, w_new, amag;
+  double in, tn, w_new, amag;
   float re, im;
 };
 __device__ __forceinline__ BigFocus big_focus(const UpdateArgs &a, int n, double inv, bool upd) {
@@ -342,12 +351,11 @@ __device__ __forceinline__ BigFocus big_focus(const UpdateArgs &a, int n, double
   f.in = (re * re + im * im) * inv;
   f.tn = a.tnorm[n];
   if (upd) {
-    f.tg = a.target[n];
     double w = a.w[n];
     const double iw = a.meas ? a.meas[n] : f.in;
     if (a.weighting == GSWMTP_WEIGHT_GSW) w *= sqrt(f.tn / (iw > 1e-30 ? iw : 1e-30));
     f.w_new = w;
-    f.amag = w * sqrt(f.tg);
+    f.amag = w * a.tsqrt[n];
   }
   return f;
 }
@@ -364,7 +372,7 @@ __device__ __forceinline__ void big_phase2(const UpdateArgs &a, int b, double (*
     sv[0] = (f.tn - f.in) * (f.tn - f.in);
     sv[1] = f.in * f.in;
     if (f.tn > 0.0) {
-      const double r = f.in / f.tn;
+      const double r = f.in * a.tinv[n];
       mv[0] = r;
       mv[1] = -r;
     }
@@ -436,12 +444,7 @@ __device__ __forceinline__ void big_phase3(const UpdateArgs &a, int b, double (*
       pr = a.fixph[2 * n];
       pi = a.fixph[2 * n + 1];
     } else {
-      const double re = f.re, im = f.im;
-      const double mag = sqrt(re * re + im * im);
-      if (mag > 0.0) {
-        pr = re / mag;
-        pi = im / mag;
-      }
+      unit_phasor(f.re, f.im, pr, pi);
       if (fixing) {
         a.fixph[2 * n] = pr;
         a.fixph[2 * n + 1] = pi;
@@ -750,6 +753,8 @@ static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
   a.intensity = p->b.intensity;
   a.target = p->b.target;
   a.tnorm = p->b.tnorm;
+  a.tinv = p->b.tinv;
+  a.tsqrt = p->b.tsqrt;
   a.w = p->b.w;
   a.fixph = p->b.fixph;
   a.stats = p->b.stats;

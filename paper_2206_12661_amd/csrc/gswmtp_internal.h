@@ -66,6 +66,7 @@ struct Dims {
 struct Bufs {
   // inputs and index work (sized by ny, nx, nf)
   double *fx = nullptr, *fy = nullptr, *target = nullptr, *tnorm = nullptr;
+  double *tinv = nullptr, *tsqrt = nullptr;   // 1 / tnorm (0 at tnorm 0), sqrt(target)
   double *fz = nullptr;                  // axial positions (zeros: the focal plane)
   double *meas = nullptr;                // [nf] measured intensities, then at unit sum
   double *xzu = nullptr, *yzu = nullptr;  // z of each unique (x, z) / (y, z) key

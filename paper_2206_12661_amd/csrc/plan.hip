@@ -340,7 +340,11 @@ __global__ void k_row_ptr(const int *ir, const int *foci, int n, int ur, int *pt
 }
 
 // Target intensities normalised to unit sum (float64, fixed order).
-__global__ __launch_bounds__(1024) void k_tnorm(const double *target, int n, double *tnorm) {
+// Unit-sum targets and the per-focus constants of the weight update:
+// tnorm = target / sum, tinv = 1 / tnorm (0 where tnorm is 0), tsqrt =
+// sqrt(target).  One workgroup, the sum in a fixed order.
+__global__ __launch_bounds__(1024) void k_tnorm(const double *target, int n, double *tnorm,
+                                                double *tinv, double *tsqrt) {
   __shared__ double s[1024];
   const int t = threadIdx.x;
   double acc = 0.0;
@@ -352,7 +356,12 @@ __global__ __launch_bounds__(1024) void k_tnorm(const double *target, int n, dou
     __syncthreads();
   }
   const double tot = s[0];
-  for (int i = t; i < n; i += 1024) tnorm[i] = target[i] / tot;
+  for (int i = t; i < n; i += 1024) {
+    const double tn = target[i] / tot;
+    tnorm[i] = tn;
+    tinv[i] = tn > 0.0 ? 1.0 / tn : 0.0;
+    tsqrt[i] = sqrt(target[i]);
+  }
 }
 
 // exp(-2 pi i s c f) with the argument reduced exactly in float64:
@@ -932,6 +941,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     b.fx = c.take<double>(nf); b.fy = c.take<double>(nf); b.fz = c.take<double>(nf);
     b.xzu = c.take<double>(nf); b.yzu = c.take<double>(nf); b.meas = c.take<double>(nf);
     b.target = c.take<double>(nf); b.tnorm = c.take<double>(nf);
+    b.tinv = c.take<double>(nf); b.tsqrt = c.take<double>(nf);
     b.xu = c.take<double>(nf); b.yu = c.take<double>(nf);
     b.ix = c.take<int>(nf); b.iy = c.take<int>(nf);
     b.firstx = c.take<int>(nf); b.firsty = c.take<int>(nf);
@@ -1009,7 +1019,8 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firstx, (int)nf, sc + 0);
   hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firsty, (int)nf, sc + 1);
   hipLaunchKernelGGL(k_dup, gf, dim3(256), 0, s, b.ix, b.iy, (int)nf, b.dup);
-  hipLaunchKernelGGL(k_tnorm, dim3(1), dim3(1024), 0, s, b.target, (int)nf, b.tnorm);
+  hipLaunchKernelGGL(k_tnorm, dim3(1), dim3(1024), 0, s, b.target, (int)nf, b.tnorm, b.tinv,
+                     b.tsqrt);
   HIP_TRY(p, hipGetLastError());
 
   int hs[8] = {0};
