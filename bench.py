@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--modes", default="fp32,bf16x3,fp16x3,bf16x6")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="host time budget of the oracle sample (0 disables)")
+    ap.add_argument("--cpu-passes", type=int, default=40,
+                    help="oracle passes of the CPU sample and of the trajectory-error "
+                         "check (about 11 s on 16 host cores; 0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-iters", type=int, default=20)
     ap.add_argument("--no-library-reference", action="store_true",
@@ -148,21 +149,20 @@ def algorithmic_flops(idx, n_foci) -> dict:
             "scatter": gath, "pass": 2 * prod + 2 * gath}
 
 
-def cpu_baseline(h, seconds: float):
-    """Time the oracle (as it stands) on the first passes of the same workload:
-    one probe pass sizes a run of k passes that takes about ``seconds``."""
+def cpu_baseline(h, passes: int):
+    """Time the oracle (as it stands) on the first ``passes`` passes of the same
+    workload from the same start phase.  A fixed pass count (not a time
+    budget) keeps the trajectory-error point, and so the equal-error
+    decision, the same on every host."""
     import oracle
     t0 = time.perf_counter()
-    oracle.gsw(h, n_iter=1)
-    t_probe = time.perf_counter() - t0          # tables + 1 pass + final forward
-    k = max(1, int(seconds / max(t_probe / 1.5, 1e-3)))
-    t0 = time.perf_counter()
-    r = oracle.gsw(h, n_iter=k)
+    r = oracle.gsw(h, n_iter=passes)
     t = time.perf_counter() - t0
-    return {"value": k / t, "unit": "iter/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{k} passes of the same 1152x1920 / 1000-foci workload from the same "
+    return {"value": passes / t, "unit": "iter/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{passes} passes of the same 1152x1920 / 1000-foci workload from the same "
                       f"start phase in one FP64 oracle call ({t:.1f} s, including its phasor "
-                      f"tables and one final forward)"}, r, k
+                      f"tables and one final forward)"}, r, passes
 
 
 def run_mode(g, torch, h, mode, args):
@@ -329,8 +329,8 @@ def main():
     res = {m: run_mode(g, torch, h, m, args) for m in modes}
 
     base, r_or, k = None, None, 0
-    if not args.no_cpu_baseline and args.cpu_seconds > 0:
-        base, r_or, k = cpu_baseline(h, args.cpu_seconds)
+    if not args.no_cpu_baseline and args.cpu_passes > 0:
+        base, r_or, k = cpu_baseline(h, args.cpu_passes)
     if r_or is not None:
         import oracle
         theta_ref0 = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
