@@ -320,7 +320,8 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
       constexpr int NR = (BM / 64 + BN / 64) * 2 * NT;
       constexpr int NM = (BM / 64) * (BN / 64) * 2 * NT * (NT + 1);
       constexpr int NS = NA + NBL;
-      static_assert(NM >= NR && NS % (NM - NR > 0 ? NM - NR : 1) == 0, "interleave pattern");
+      static_assert(NM >= NR, "interleave pattern");
+      constexpr int NW = NS < NM - NR ? NS : NM - NR;   // (store, MFMA) pairs
       // The read of the next stage's k-step 0 is unconditional: after the
       // last stage it reads the clamped copy in the other buffer, unused.
 #define PIPE_STEP(BUF, RA, RB, S)                                                              \
@@ -336,7 +337,9 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
     STORE_STAGE(RA, RB, BUF);                                                                  \
     LOAD_STAGE(RA, RB, (S) + 4 < last ? (S) + 4 : last);                                       \
     sched_read_mfma<NR>();                                                                     \
-    sched_write_mfma<NM - NR, NS / (NM - NR > 0 ? NM - NR : 1)>();                             \
+    sched_write_mfma<NW, 1>();                                                                 \
+    if constexpr (NM - NR - NW > 0) __builtin_amdgcn_sched_group_barrier(0x008, NM - NR - NW, 0); \
+    if constexpr (NS - NW > 0) __builtin_amdgcn_sched_group_barrier(0x200, NS - NW, 0);       \
     __builtin_amdgcn_sched_group_barrier(0x020, NS, 0);                                        \
   } while (0)
       int kt = kb;
@@ -608,8 +611,12 @@ hipError_t launch_e(const GemmTile &tl, const SplitArgs &args, int grid, hipStre
       return tl.kg == 2 ? launch_fit<64, 64, 32, BF, NT, EPI, 2>(args, grid, s)
                         : launch_fit<64, 64, 32, BF, NT, EPI>(args, grid, s);
     }
-    if (tl.bm == 128 && tl.bn == 64) return launch_fit<128, 64, 32, BF, NT, EPI>(args, grid, s);
-    if (tl.bm == 64 && tl.bn == 128) return launch_fit<64, 128, 32, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 128 && tl.bn == 64)
+      return tl.pipe ? launch_fit<128, 64, 32, BF, NT, EPI, 1, true>(args, grid, s)
+                     : launch_fit<128, 64, 32, BF, NT, EPI>(args, grid, s);
+    if (tl.bm == 64 && tl.bn == 128)
+      return tl.pipe ? launch_fit<64, 128, 32, BF, NT, EPI, 1, true>(args, grid, s)
+                     : launch_fit<64, 128, 32, BF, NT, EPI>(args, grid, s);
     if (tl.bm == 128 && tl.bn == 128) return launch_fit<128, 128, 32, BF, NT, EPI>(args, grid, s);
   } else if (tl.bk == 16) {
     if (tl.bm == 64 && tl.bn == 64) return launch_fit<64, 64, 16, BF, NT, EPI>(args, grid, s);

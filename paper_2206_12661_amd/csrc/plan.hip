@@ -741,12 +741,12 @@ void free_plan(gswmtp_plan *p) {
 // GEMM tile per product.  float32: 64 x 64 complex tiles, 16 k per stage
 // (three workgroups per CU resident).  Split modes: 64 x 64 tiles with 32 k
 // per stage (16-bit operands need longer stages to cover load latency) and
-// the software-pipelined stage loop (two-term modes) or two k-groups
-// (three-term).  GSWMTP_SPLIT_LOOP=pipe|kg2|plain picks
+// the software-pipelined stage loop (two-term modes, 64 x 128 tiles where
+// they fill one round of workgroups) or two k-groups (three-term).  GSWMTP_SPLIT_LOOP=pipe|kg2|plain picks
 // the split products' loop (kg2: each stage's two k-steps taken by two
 // groups of four waves); GSWMTP_TILE=BMxBN[xBK] overrides the tile (BK only
 // for split modes; other tiles use the plain loop).
-GemmTile choose_tile(int M, int N, bool split, int terms = 2) {
+GemmTile choose_tile(int M, int N, bool split, int terms = 2, int cus = 256) {
   GemmTile t{64, 64, split ? 32 : 16, 1, 0};
   if (split) {
     // three-term operands hold too many fragment registers to pipeline
@@ -755,6 +755,11 @@ GemmTile choose_tile(int M, int N, bool split, int terms = 2) {
     const std::string v = lp ? lp : terms > 2 ? "kg2" : "pipe";
     t.kg = v == "kg2" ? 2 : 1;
     t.pipe = v == "pipe" ? 1 : 0;
+    // 64 x 128 tiles (one workgroup per CU, a quarter fewer LDS and L2 bytes
+    // per MFMA) when they fill at least half of the CUs in one round and do
+    // not spill into a second
+    const long wide = (long)(M / 64) * (N / 128);
+    if (t.pipe && N % 128 == 0 && wide <= cus && 2 * wide >= cus) t.bn = 128;
   }
   const char *env = std::getenv("GSWMTP_TILE");
   if (env) {
@@ -765,7 +770,8 @@ GemmTile choose_tile(int M, int N, bool split, int terms = 2) {
       t.bm = bm;
       t.bn = bn;
       if (split && n == 3 && (bk == 16 || bk == 32)) t.bk = bk;
-      if (t.bm != 64 || t.bn != 64 || t.bk != 32) t.kg = 1, t.pipe = 0;
+      if (t.bk != 32 || (t.bm == 128 && t.bn == 128)) t.kg = 1, t.pipe = 0;
+      if (t.bm != 64 || t.bn != 64) t.kg = 1;
     }
   }
   return t;
@@ -1052,10 +1058,12 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   D.Urp = (int)round_up(D.Ur, kPadRows);
   const bool split_mode = is_split(p);
   const int terms = split_terms_of(p->precision);
-  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp, choose_tile(D.Urp, D.Cp, split_mode, terms),
-                            p->cus, split_enabled());
-  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, choose_tile(D.Rp, D.Cp, split_mode, terms),
-                            p->cus, split_enabled());
+  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp,
+                            choose_tile(D.Urp, D.Cp, split_mode, terms, p->cus), p->cus,
+                            split_enabled());
+  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp,
+                            choose_tile(D.Rp, D.Cp, split_mode, terms, p->cus), p->cus,
+                            split_enabled());
   // Grid form (float32): when the foci fill a quarter or more of the reduced
   // grid, the second product of Eq. 2 is formed densely on the matrix cores
   // (as the paper does) instead of per focus.  GSWMTP_SECOND=gather|grid
