@@ -108,6 +108,46 @@ def test_full_size_forward_split(g, mode):
     assert err <= TOL[mode]
 
 
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16x3"])
+def test_full_size_pass_split(g, mode):
+    """One split-precision pass at the benchmark size (1152 x 1920, 1000
+    foci: the 64 x 128 forward tiles and the 64 x 64 adjoint with its split-K
+    tail) from an identical state after 5 float32 passes; the weights at the
+    mode's bar times the oracle's kappa (the weight update's first-order
+    gain), the new foci field times kappa and c_E (the projection's)."""
+    h = synth_ofa.config3()
+    announce(f"full size pass {mode}")
+    with g.Plan(h) as p:
+        p.iterate(5)
+        phi_k, w_k, _ = p.state()
+    with g.Plan(h, precision=mode) as q:
+        q.set_state(phi_k, w_k, 0)
+        q.iterate(1)
+        w1 = q.weights()
+        th1 = q.foci_field()
+    hk = synth_ofa.Hologram(h.name, h.ny, h.nx, h.amplitude, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy,
+                            h.target, phi_k, 1)
+    r = oracle.gsw(hk, n_iter=1, w=w_k)
+    thk = oracle.forward(oracle.pupil_field(hk), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    x = np.abs(thk) ** 2 / np.mean(np.abs(thk) ** 2)
+    _, tn = oracle.weight_update(thk, h.target, w_k)
+    a2 = np.abs(tn) ** 2
+    kap = max(1.0, float(np.sqrt(np.sum(a2 / np.maximum(x, 1e-300)) / np.sum(a2))))
+    # c_E: the phase projection divides the back-propagated field's error by
+    # |E'| sample by sample (first-order gain, from the oracle's own E')
+    Ep = oracle.adjoint(tn, h.ny, h.nx, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    A2 = np.asarray(h.amplitude, np.float64).ravel() ** 2
+    m2 = np.abs(Ep).ravel() ** 2
+    on = A2 > 0
+    rms2 = np.sum(A2[on] * m2[on]) / np.sum(A2[on])
+    cE = max(1.0, float(np.sqrt(np.sum(A2[on] * rms2 / np.maximum(m2[on], 1e-300))
+                                / np.sum(A2[on]))))
+    ew, et = rel_l2(w1, r["w"]), rel_l2(th1, r["theta"])
+    print(f"  {mode}: kappa {kap:.2f} c_E {cE:.2f} w {ew:.2e} theta {et:.2e}")
+    assert ew <= TOL[mode] * kap
+    assert et <= TOL[mode] * kap * cE
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_local_pass_split(g, mode):
     """One pass from an identical, well-conditioned state (after 10 float32
