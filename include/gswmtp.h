@@ -47,9 +47,9 @@ extern "C" {
 enum {
     GSWMTP_OK = 0,
     GSWMTP_E_INVAL = -1,          /* bad size, pointer, non-finite or negative input */
-    GSWMTP_E_DUPFOCUS = -2,       /* two foci with identical (x, y) */
+    GSWMTP_E_DUPFOCUS = -2,       /* two foci with identical (x, y, z) */
     GSWMTP_E_EMPTYAPERTURE = -3,  /* amplitude (after mask) is zero everywhere */
-    GSWMTP_E_NOMEM = -4,          /* host or device allocation failed */
+    GSWMTP_E_NOMEM = -4,          /* host or device allocation failed, or workspace too small */
     GSWMTP_E_HIP = -5,            /* a HIP runtime call failed */
     GSWMTP_E_NONFINITE = -6,      /* a focus intensity sum became non-finite */
     GSWMTP_E_NODEV = -7,          /* no usable gfx950 device */
@@ -146,6 +146,27 @@ int gswmtp_desc_init(gswmtp_desc *d);
  * Synchronises once to size the product buffers.  stream: hipStream_t or NULL.
  * On failure *out is NULL and nothing is leaked. */
 int gswmtp_plan_create(gswmtp_plan **out, const gswmtp_desc *d, void *stream);
+
+/* Device memory a plan for d needs (both of its pools), in bytes, computed on
+ * the host from the descriptor alone (no GPU work, no allocation): the same
+ * index counts and layout the plan derives (unique focal coordinates, kept
+ * pupil rows and columns, axis, padded product sizes, tile schedules for the
+ * current device's CU count, or 256 without one).  The environment switches
+ * that change the layout must be the same at plan creation.  GSWMTP_E_INVAL
+ * or GSWMTP_E_EMPTYAPERTURE as gswmtp_plan_create would return them. */
+int gswmtp_plan_workspace_size(const gswmtp_desc *d, size_t *bytes);
+
+/* gswmtp_plan_create with the plan's device memory carved from dev_ws, a
+ * DEVICE buffer of `bytes` bytes (at least gswmtp_plan_workspace_size),
+ * 256-byte aligned, owned by the caller and left untouched by the library
+ * except as the plan's storage; it must stay valid until
+ * gswmtp_plan_destroy, which does not free it (e.g. a torch tensor from the
+ * caching allocator).  The plan makes no device allocation of its own
+ * besides what HIP's stream, event and graph objects hold.
+ * GSWMTP_E_INVAL for a null, empty or misaligned buffer; GSWMTP_E_NOMEM,
+ * with the size needed in gswmtp_last_error(NULL), when it is too small. */
+int gswmtp_plan_create_with_workspace(gswmtp_plan **out, const gswmtp_desc *d, void *dev_ws,
+                                      size_t bytes, void *stream);
 
 /* Free a plan (NULL-safe).  Waits for its queued work first. */
 int gswmtp_plan_destroy(gswmtp_plan *p);

@@ -67,6 +67,10 @@ _SIGNATURES = {
     "gswmtp_last_error": ([_P], ctypes.c_char_p),
     "gswmtp_desc_init": ([ctypes.POINTER(gswmtp_desc)], ctypes.c_int),
     "gswmtp_plan_create": ([ctypes.POINTER(_P), ctypes.POINTER(gswmtp_desc), _P], ctypes.c_int),
+    "gswmtp_plan_workspace_size": ([ctypes.POINTER(gswmtp_desc), ctypes.POINTER(ctypes.c_size_t)],
+                                   ctypes.c_int),
+    "gswmtp_plan_create_with_workspace": ([ctypes.POINTER(_P), ctypes.POINTER(gswmtp_desc), _P,
+                                           ctypes.c_size_t, _P], ctypes.c_int),
     "gswmtp_plan_destroy": ([_P], ctypes.c_int),
     "gswmtp_set_stream": ([_P, _P], ctypes.c_int),
     "gswmtp_sync": ([_P], ctypes.c_int),
@@ -140,11 +144,53 @@ def status_string(status: int) -> str:
     return load_library().gswmtp_status_string(status).decode()
 
 
+def _make_desc(holo=None, *, ny=None, nx=None, amplitude=None, mask=None, u=None, v=None,
+               s_x=None, s_y=None, fx=None, fy=None, target=None, phi0=None, fz=None,
+               precision="fp32", axis=-1, weighting="gsw"):
+    """A filled ``gswmtp_desc`` and the host arrays it points into (keep them
+    alive until the call that reads the descriptor returns)."""
+    lib = load_library()
+    g = (lambda k, val: val if val is not None else getattr(holo, k, None)) if holo is not None \
+        else (lambda k, val: val)
+    keep = []
+
+    def arr(x, dt):
+        if x is None:
+            return None
+        a = np.ascontiguousarray(np.asarray(x, dtype=dt))
+        keep.append(a)
+        return a.ctypes.data
+
+    d = gswmtp_desc()
+    lib.gswmtp_desc_init(ctypes.byref(d))
+    d.ny, d.nx = int(g("ny", ny)), int(g("nx", nx))
+    d.amplitude = arr(g("amplitude", amplitude), np.float32)
+    d.mask = arr(mask, np.uint8)
+    d.u = arr(g("u", u), np.float64)
+    d.v = arr(g("v", v), np.float64)
+    d.s_x = float(g("s_x", s_x))
+    d.s_y = float(g("s_y", s_y))
+    fxa = np.ascontiguousarray(np.asarray(g("fx", fx), dtype=np.float64))
+    d.n_foci = int(fxa.shape[0])
+    d.fx = arr(fxa, np.float64)
+    d.fy = arr(g("fy", fy), np.float64)
+    d.target = arr(g("target", target), np.float64)
+    d.phi0 = arr(g("phi0", phi0), np.float32)
+    d.fz = arr(g("fz", fz), np.float64)
+    d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d.axis = int(axis)
+    d.weighting = {"gsw": WEIGHT_GSW, "gs": WEIGHT_GS}[weighting] \
+        if isinstance(weighting, str) else int(weighting)
+    return d, keep
+
+
 class Plan:
     """A GSW-MTP plan: pupil, sampling and foci of one hologram, and its state.
 
     Parameters mirror ``gswmtp_desc`` (see ``include/gswmtp.h``).  All host
-    arrays are copied at creation.  ``holo`` may be any object with the fields
+    arrays are copied at creation; ``workspace`` (optional) is a contiguous
+    device tensor of at least ``Plan.workspace_size(...)`` bytes that holds the
+    plan's device memory.  ``holo`` may be any object with the fields
     ny, nx, amplitude, u, v, s_x, s_y, fx, fy, target, phi0 and optionally fz
     (axial focus positions; for example a ``synth_ofa.Hologram``); keyword
     arguments override its fields.
@@ -152,48 +198,41 @@ class Plan:
 
     def __init__(self, holo=None, *, ny=None, nx=None, amplitude=None, mask=None, u=None,
                  v=None, s_x=None, s_y=None, fx=None, fy=None, target=None, phi0=None,
-                 fz=None, precision="fp32", axis=-1, weighting="gsw"):
+                 fz=None, precision="fp32", axis=-1, weighting="gsw", workspace=None):
         lib = load_library()
-        g = (lambda k, val: val if val is not None else getattr(holo, k, None)) if holo is not None \
-            else (lambda k, val: val)
-        self.ny, self.nx = int(g("ny", ny)), int(g("nx", nx))
-        keep = []
-
-        def arr(x, dt):
-            if x is None:
-                return None
-            a = np.ascontiguousarray(np.asarray(x, dtype=dt))
-            keep.append(a)
-            return a.ctypes.data
-
-        d = gswmtp_desc()
-        lib.gswmtp_desc_init(ctypes.byref(d))
-        d.ny, d.nx = self.ny, self.nx
-        d.amplitude = arr(g("amplitude", amplitude), np.float32)
-        d.mask = arr(mask, np.uint8)
-        d.u = arr(g("u", u), np.float64)
-        d.v = arr(g("v", v), np.float64)
-        d.s_x = float(g("s_x", s_x))
-        d.s_y = float(g("s_y", s_y))
-        fxa = np.ascontiguousarray(np.asarray(g("fx", fx), dtype=np.float64))
-        self.n_foci = int(fxa.shape[0])
-        d.n_foci = self.n_foci
-        d.fx = arr(fxa, np.float64)
-        d.fy = arr(g("fy", fy), np.float64)
-        d.target = arr(g("target", target), np.float64)
-        d.phi0 = arr(g("phi0", phi0), np.float32)
-        d.fz = arr(g("fz", fz), np.float64)
-        d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        d.axis = int(axis)
-        d.weighting = {"gsw": WEIGHT_GSW, "gs": WEIGHT_GS}[weighting] \
-            if isinstance(weighting, str) else int(weighting)
+        d, keep = _make_desc(holo, ny=ny, nx=nx, amplitude=amplitude, mask=mask, u=u, v=v,
+                             s_x=s_x, s_y=s_y, fx=fx, fy=fy, target=target, phi0=phi0, fz=fz,
+                             precision=precision, axis=axis, weighting=weighting)
+        self.ny, self.nx, self.n_foci = d.ny, d.nx, d.n_foci
         self.precision = d.precision
         h = _P()
-        rc = lib.gswmtp_plan_create(ctypes.byref(h), ctypes.byref(d), _stream_handle())
+        if workspace is None:
+            rc = lib.gswmtp_plan_create(ctypes.byref(h), ctypes.byref(d), _stream_handle())
+        else:
+            # a device tensor owned by the caller; kept alive with the plan
+            if not workspace.is_cuda or not workspace.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
+            nbytes = workspace.numel() * workspace.element_size()
+            rc = lib.gswmtp_plan_create_with_workspace(ctypes.byref(h), ctypes.byref(d),
+                                                       workspace.data_ptr(), nbytes,
+                                                       _stream_handle())
+            self._workspace = workspace
         if rc != 0:
             raise GswmtpError(rc, lib.gswmtp_last_error(None).decode())
         self._h = h
         self._lib = lib
+
+    @staticmethod
+    def workspace_size(holo=None, **kw) -> int:
+        """Bytes of device workspace a plan with these arguments needs
+        (``gswmtp_plan_workspace_size``; host-only, no GPU work)."""
+        lib = load_library()
+        d, _keep = _make_desc(holo, **kw)
+        n = ctypes.c_size_t(0)
+        rc = lib.gswmtp_plan_workspace_size(ctypes.byref(d), ctypes.byref(n))
+        if rc != 0:
+            raise GswmtpError(rc, "gswmtp_plan_workspace_size")
+        return n.value
 
     # -- lifetime ----------------------------------------------------------
     def close(self):

@@ -320,6 +320,8 @@ struct gswmtp_plan {
   int amp_exp = 0;                        // split modes: P carries amp * 2^amp_exp
   void *pool0 = nullptr, *pool1 = nullptr;
   size_t pool0_bytes = 0, pool1_bytes = 0;
+  void *ws = nullptr;                     // caller's workspace holding both pools, or null
+  size_t ws_bytes = 0;
   hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
   bool fwd_valid = false;                 // theta/stats match the current phase
   const double *meas_active = nullptr;    // b.meas while a measured pass is queued, else null

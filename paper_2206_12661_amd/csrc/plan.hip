@@ -13,6 +13,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <utility>
 #include <new>
 #include <vector>
 
@@ -728,8 +729,10 @@ void free_plan(gswmtp_plan *p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   if (p->graph1) (void)hipGraphExecDestroy(p->graph1);
   if (p->graph8) (void)hipGraphExecDestroy(p->graph8);
-  if (p->pool0) (void)hipFree(p->pool0);
-  if (p->pool1) (void)hipFree(p->pool1);
+  if (!p->ws) {   // a caller's workspace is the caller's to free
+    if (p->pool0) (void)hipFree(p->pool0);
+    if (p->pool1) (void)hipFree(p->pool1);
+  }
   for (auto &e : p->ev_t)
     if (e) (void)hipEventDestroy(e);
   if (p->ev_user) (void)hipEventDestroy(p->ev_user);
@@ -913,6 +916,117 @@ hipError_t capture(gswmtp_plan *p, int passes, hipGraphExec_t *out) {
   return e;
 }
 
+// Pool 0 (inputs, index work, per-focus state): every buffer carved in a
+// fixed order from a bump allocator (a null base only measures).
+void carve_pool0(Carver &c, Bufs &b, size_t nf, size_t ny, size_t nx) {
+  const size_t np = ny * nx;
+  b.fx = c.take<double>(nf); b.fy = c.take<double>(nf); b.fz = c.take<double>(nf);
+  b.xzu = c.take<double>(nf); b.yzu = c.take<double>(nf); b.meas = c.take<double>(nf);
+  b.target = c.take<double>(nf); b.tnorm = c.take<double>(nf);
+  b.tinv = c.take<double>(nf); b.tsqrt = c.take<double>(nf);
+  b.xu = c.take<double>(nf); b.yu = c.take<double>(nf);
+  b.ix = c.take<int>(nf); b.iy = c.take<int>(nf);
+  b.firstx = c.take<int>(nf); b.firsty = c.take<int>(nf);
+  b.rows = c.take<int>(ny); b.row_pos = c.take<int>(ny); b.keep_row = c.take<int>(ny);
+  b.cols = c.take<int>(nx); b.col_pos = c.take<int>(nx); b.keep_col = c.take<int>(nx);
+  b.aeff = c.take<float>(np);
+  b.ucoord = c.take<double>(nx); b.vcoord = c.take<double>(ny);
+  b.csr_foci = c.take<int>(nf); b.csr_ptr = c.take<int>(nf + 1); b.csr_ic = c.take<int>(nf);
+  b.scalars = c.take<int>(16); b.dscalars = c.take<double>(8); b.dup = c.take<int>(1);
+  b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
+  b.intensity = c.take<float>(nf);
+  b.w = c.take<double>(nf); b.stats = c.take<double>(ST_N); b.fixph = c.take<double>(2 * nf);
+  b.upd_s1 = c.take<double>((nf + kUpdThreads - 1) / kUpdThreads);
+  b.upd_s2 = c.take<double>(5 * ((nf + kUpdThreads - 1) / kUpdThreads));
+  b.upd_snap = c.take<int>(8);
+  b.hist = c.take<double>(3 * (size_t)kHistCap); b.ctrl = c.take<int>(CTRL_N);
+  b.iobuf = c.take<float>(2 * np);
+}
+
+// The sizes and schedules that follow from the index counts (unique focal
+// coordinates, kept pupil rows and columns) and the descriptor: the axis,
+// the padded product sizes, the product schedules and the form of the
+// second product.
+void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
+  Dims &D = p->d;
+  D.axis = d->axis >= 0 ? d->axis : (D.ux < D.uy ? 1 : 0);
+  if (D.axis == 0) {
+    D.Rk = D.ny_kept; D.Ck = D.nx_kept; D.Ur = D.uy; D.Uc = D.ux;
+  } else {
+    D.Rk = D.nx_kept; D.Ck = D.ny_kept; D.Ur = D.ux; D.Uc = D.uy;
+  }
+  D.Rp = (int)round_up(D.Rk, kPadRows);
+  D.Cp = (int)round_up(D.Ck, kPadCols);
+  D.Urp = (int)round_up(D.Ur, kPadRows);
+  const bool split_mode = is_split(p);
+  const int terms = split_terms_of(p->precision);
+  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp,
+                            choose_tile(D.Urp, D.Cp, split_mode, terms, p->cus), p->cus,
+                            split_enabled());
+  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp,
+                            choose_tile(D.Rp, D.Cp, split_mode, terms, p->cus), p->cus,
+                            split_enabled());
+  // Grid form (float32): when the foci fill a quarter or more of the reduced
+  // grid, the second product of Eq. 2 is formed densely on the matrix cores
+  // (as the paper does) instead of per focus.  GSWMTP_SECOND=gather|grid
+  // forces either form.
+  p->grid_form = !split_mode && (double)D.Ur * D.Uc <= 4.0 * D.nf;
+  if (const char *sf = std::getenv("GSWMTP_SECOND")) {
+    if (std::strcmp(sf, "gather") == 0) p->grid_form = false;
+    if (std::strcmp(sf, "grid") == 0 && !split_mode) p->grid_form = true;
+  }
+  D.Ucp = (int)round_up(D.Uc, kPadCols);
+  if (p->grid_form) {
+    p->sched_f1 = make_sched(D.Cp, D.Urp, D.Rp, choose_tile(D.Cp, D.Urp, false), p->cus,
+                             split_enabled());
+    p->sched_f2 = make_sched(D.Urp, D.Ucp, D.Cp, choose_tile(D.Urp, D.Ucp, false), p->cus,
+                             split_enabled());
+    p->sched_a1 = make_sched(D.Urp, D.Cp, D.Ucp, choose_tile(D.Urp, D.Cp, false), p->cus,
+                             split_enabled());
+  }
+
+}
+
+// Split-K partials of the plan's products (floats, at least 1).
+size_t part_floats_of(const gswmtp_plan *p) {
+  size_t f = std::max<size_t>(std::max(p->sched_fwd.part_floats, p->sched_bwd.part_floats), 1);
+  if (p->grid_form)
+    f = std::max({f, p->sched_f1.part_floats, p->sched_f2.part_floats, p->sched_a1.part_floats});
+  return f;
+}
+
+// Pool 1 (kernel matrices, pupil and product buffers), after derive_layout.
+void carve_pool1(Carver &c, Bufs &b, const gswmtp_plan *p) {
+  const Dims &D = p->d;
+  const size_t nf = D.nf;
+  const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc, Ucp = D.Ucp;
+  const size_t Ucr = p->grid_form ? Ucp : Uc;   // Omega_c rows (zero-padded in the grid form)
+  const bool split = is_split(p);
+  const size_t nt = (size_t)split_terms_of(p->precision);
+  const size_t f32 = split ? 0 : 1;       // float32-only buffers
+  const size_t part_floats = part_floats_of(p);
+  b.omt_r = c.take<float>(f32 * Rp * Urp); b.omt_i = c.take<float>(f32 * Rp * Urp);
+  b.omc_r = c.take<float>(f32 * Rp * Urp); b.omc_i = c.take<float>(f32 * Rp * Urp);
+  b.wc_r = c.take<float>(Ucr * Cp); b.wc_i = c.take<float>(Ucr * Cp);
+  b.amp = c.take<float>(Rp * Cp);
+  b.p_r = c.take<float>(f32 * Rp * Cp); b.p_i = c.take<float>(f32 * Rp * Cp);
+  b.gpart = c.take<float>(2 * (size_t)(Cp / p->sched_fwd.tile.bn) * nf);
+  b.s_r = c.take<float>(f32 * Urp * Cp); b.s_i = c.take<float>(f32 * Urp * Cp);
+  b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
+  b.part = c.take<float>(part_floats);
+  b.as_f = c.take<unsigned short>(2 * nt * Urp * Rp);
+  b.as_b = c.take<unsigned short>(2 * nt * Rp * Urp);
+  b.ps = c.take<unsigned short>(2 * nt * Cp * Rp);
+  b.xs = c.take<unsigned short>(2 * nt * Cp * Rp);
+  b.ss = c.take<unsigned short>(2 * nt * Cp * Urp);
+  const size_t gf = p->grid_form ? 1 : 0;
+  b.lt_r = c.take<float>(gf * Cp * Urp); b.lt_i = c.take<float>(gf * Cp * Urp);
+  b.wt_r = c.take<float>(gf * Cp * Ucp); b.wt_i = c.take<float>(gf * Cp * Ucp);
+  b.wn_i = c.take<float>(gf * Ucp * Cp);
+  b.g_r = c.take<float>(gf * Urp * Ucp); b.g_i = c.take<float>(gf * Urp * Ucp);
+  b.tg_r = c.take<float>(gf * Ucp * Urp); b.tg_i = c.take<float>(gf * Ucp * Urp);
+}
+
 int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   Dims &D = p->d;
   D.ny = d->ny;
@@ -942,40 +1056,22 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   hipStream_t s = p->stream;
 
   // ---- pool 0: inputs, index work, per-focus state ----
-  auto carve0 = [&](Carver &c) {
-    Bufs &b = p->b;
-    b.fx = c.take<double>(nf); b.fy = c.take<double>(nf); b.fz = c.take<double>(nf);
-    b.xzu = c.take<double>(nf); b.yzu = c.take<double>(nf); b.meas = c.take<double>(nf);
-    b.target = c.take<double>(nf); b.tnorm = c.take<double>(nf);
-    b.tinv = c.take<double>(nf); b.tsqrt = c.take<double>(nf);
-    b.xu = c.take<double>(nf); b.yu = c.take<double>(nf);
-    b.ix = c.take<int>(nf); b.iy = c.take<int>(nf);
-    b.firstx = c.take<int>(nf); b.firsty = c.take<int>(nf);
-    b.rows = c.take<int>(ny); b.row_pos = c.take<int>(ny); b.keep_row = c.take<int>(ny);
-    b.cols = c.take<int>(nx); b.col_pos = c.take<int>(nx); b.keep_col = c.take<int>(nx);
-    b.aeff = c.take<float>(np);
-    b.ucoord = c.take<double>(nx); b.vcoord = c.take<double>(ny);
-    b.csr_foci = c.take<int>(nf); b.csr_ptr = c.take<int>(nf + 1); b.csr_ic = c.take<int>(nf);
-    b.scalars = c.take<int>(16); b.dscalars = c.take<double>(8); b.dup = c.take<int>(1);
-    b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
-    b.intensity = c.take<float>(nf);
-    b.w = c.take<double>(nf); b.stats = c.take<double>(ST_N); b.fixph = c.take<double>(2 * nf);
-    b.upd_s1 = c.take<double>((nf + kUpdThreads - 1) / kUpdThreads);
-    b.upd_s2 = c.take<double>(5 * ((nf + kUpdThreads - 1) / kUpdThreads));
-    b.upd_snap = c.take<int>(8);
-    b.hist = c.take<double>(3 * (size_t)kHistCap); b.ctrl = c.take<int>(CTRL_N);
-    b.iobuf = c.take<float>(2 * np);
-  };
+
   {
     Carver c(nullptr);
-    carve0(c);
+    carve_pool0(c, p->b, nf, ny, nx);
     p->pool0_bytes = c.off;
   }
-  if (hipMalloc(&p->pool0, p->pool0_bytes) != hipSuccess)
+  if (p->ws) {
+    if (p->pool0_bytes > p->ws_bytes)
+      return fail(p, GSWMTP_E_NOMEM, "workspace smaller than the index pool");
+    p->pool0 = p->ws;
+  } else if (hipMalloc(&p->pool0, p->pool0_bytes) != hipSuccess) {
     return fail(p, GSWMTP_E_NOMEM, "device allocation (index pool)");
+  }
   {
     Carver c(p->pool0);
-    carve0(c);
+    carve_pool0(c, p->b, nf, ny, nx);
   }
   Bufs &b = p->b;
   HIP_TRY(p, hipMemsetAsync(p->pool0, 0, p->pool0_bytes, s));
@@ -1046,85 +1142,32 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   if (D.n_ap == 0 || D.ny_kept == 0 || D.nx_kept == 0 || !(D.sum_a2 > 0.0))
     return fail(p, GSWMTP_E_EMPTYAPERTURE, "amplitude is zero everywhere");
 
-  // ---- axis and sizes ----
-  D.axis = d->axis >= 0 ? d->axis : (D.ux < D.uy ? 1 : 0);
-  if (D.axis == 0) {
-    D.Rk = D.ny_kept; D.Ck = D.nx_kept; D.Ur = D.uy; D.Uc = D.ux;
-  } else {
-    D.Rk = D.nx_kept; D.Ck = D.ny_kept; D.Ur = D.ux; D.Uc = D.uy;
-  }
-  D.Rp = (int)round_up(D.Rk, kPadRows);
-  D.Cp = (int)round_up(D.Ck, kPadCols);
-  D.Urp = (int)round_up(D.Ur, kPadRows);
-  const bool split_mode = is_split(p);
-  const int terms = split_terms_of(p->precision);
-  p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp,
-                            choose_tile(D.Urp, D.Cp, split_mode, terms, p->cus), p->cus,
-                            split_enabled());
-  p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp,
-                            choose_tile(D.Rp, D.Cp, split_mode, terms, p->cus), p->cus,
-                            split_enabled());
-  // Grid form (float32): when the foci fill a quarter or more of the reduced
-  // grid, the second product of Eq. 2 is formed densely on the matrix cores
-  // (as the paper does) instead of per focus.  GSWMTP_SECOND=gather|grid
-  // forces either form.
-  p->grid_form = !split_mode && (double)D.Ur * D.Uc <= 4.0 * D.nf;
-  if (const char *sf = std::getenv("GSWMTP_SECOND")) {
-    if (std::strcmp(sf, "gather") == 0) p->grid_form = false;
-    if (std::strcmp(sf, "grid") == 0 && !split_mode) p->grid_form = true;
-  }
-  D.Ucp = (int)round_up(D.Uc, kPadCols);
-  size_t part_floats =
-      std::max<size_t>(std::max(p->sched_fwd.part_floats, p->sched_bwd.part_floats), 1);
-  if (p->grid_form) {
-    p->sched_f1 = make_sched(D.Cp, D.Urp, D.Rp, choose_tile(D.Cp, D.Urp, false), p->cus,
-                             split_enabled());
-    p->sched_f2 = make_sched(D.Urp, D.Ucp, D.Cp, choose_tile(D.Urp, D.Ucp, false), p->cus,
-                             split_enabled());
-    p->sched_a1 = make_sched(D.Urp, D.Cp, D.Ucp, choose_tile(D.Urp, D.Cp, false), p->cus,
-                             split_enabled());
-    part_floats = std::max({part_floats, p->sched_f1.part_floats, p->sched_f2.part_floats,
-                            p->sched_a1.part_floats});
-  }
+  // ---- axis, sizes, schedules ----
+  derive_layout(p, d);
 
   // ---- pool 1: kernel matrices, pupil and product buffers ----
   const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Uc = D.Uc, Ucp = D.Ucp;
-  const size_t Ucr = p->grid_form ? Ucp : Uc;   // Omega_c rows (zero-padded in the grid form)
   const bool split = is_split(p);
-  const size_t nt = (size_t)split_terms_of(p->precision);
-  const size_t f32 = split ? 0 : 1;       // float32-only buffers
-  auto carve1 = [&](Carver &c) {
-    b.omt_r = c.take<float>(f32 * Rp * Urp); b.omt_i = c.take<float>(f32 * Rp * Urp);
-    b.omc_r = c.take<float>(f32 * Rp * Urp); b.omc_i = c.take<float>(f32 * Rp * Urp);
-    b.wc_r = c.take<float>(Ucr * Cp); b.wc_i = c.take<float>(Ucr * Cp);
-    b.amp = c.take<float>(Rp * Cp);
-    b.p_r = c.take<float>(f32 * Rp * Cp); b.p_i = c.take<float>(f32 * Rp * Cp);
-    b.gpart = c.take<float>(2 * (size_t)(Cp / p->sched_fwd.tile.bn) * nf);
-    b.s_r = c.take<float>(f32 * Urp * Cp); b.s_i = c.take<float>(f32 * Urp * Cp);
-    b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
-    b.part = c.take<float>(part_floats);
-    b.as_f = c.take<unsigned short>(2 * nt * Urp * Rp);
-    b.as_b = c.take<unsigned short>(2 * nt * Rp * Urp);
-    b.ps = c.take<unsigned short>(2 * nt * Cp * Rp);
-    b.xs = c.take<unsigned short>(2 * nt * Cp * Rp);
-    b.ss = c.take<unsigned short>(2 * nt * Cp * Urp);
-    const size_t gf = p->grid_form ? 1 : 0;
-    b.lt_r = c.take<float>(gf * Cp * Urp); b.lt_i = c.take<float>(gf * Cp * Urp);
-    b.wt_r = c.take<float>(gf * Cp * Ucp); b.wt_i = c.take<float>(gf * Cp * Ucp);
-    b.wn_i = c.take<float>(gf * Ucp * Cp);
-    b.g_r = c.take<float>(gf * Urp * Ucp); b.g_i = c.take<float>(gf * Urp * Ucp);
-    b.tg_r = c.take<float>(gf * Ucp * Urp); b.tg_i = c.take<float>(gf * Ucp * Urp);
-  };
   {
     Carver c(nullptr);
-    carve1(c);
+    carve_pool1(c, p->b, p);
     p->pool1_bytes = c.off;
   }
-  if (hipMalloc(&p->pool1, p->pool1_bytes) != hipSuccess)
+  if (p->ws) {
+    const size_t off = round_up(p->pool0_bytes, 256);
+    if (off + p->pool1_bytes > p->ws_bytes) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "workspace too small: %zu bytes needed",
+                    off + p->pool1_bytes);
+      return fail(p, GSWMTP_E_NOMEM, msg);
+    }
+    p->pool1 = static_cast<char *>(p->ws) + off;
+  } else if (hipMalloc(&p->pool1, p->pool1_bytes) != hipSuccess) {
     return fail(p, GSWMTP_E_NOMEM, "device allocation (product pool)");
+  }
   {
     Carver c(p->pool1);
-    carve1(c);
+    carve_pool1(c, p->b, p);
   }
   HIP_TRY(p, hipMemsetAsync(p->pool1, 0, p->pool1_bytes, s));
 
@@ -1216,10 +1259,85 @@ int gswmtp_desc_init(gswmtp_desc *d) {
   return GSWMTP_OK;
 }
 
+static int create_impl(gswmtp_plan **out, const gswmtp_desc *d, void *ws, size_t ws_bytes,
+                       void *stream);
+
+// Distinct canonical (coordinate, z) keys of one axis, counted on the host
+// (sizing only; the plan's own index work runs on the device).
+static int count_keys(const double *c, const double *z, size_t n) {
+  std::vector<std::pair<double, double>> k(n);
+  for (size_t i = 0; i < n; ++i) {
+    const double a = c[i] == 0.0 ? 0.0 : c[i];
+    const double b = z ? (z[i] == 0.0 ? 0.0 : z[i]) : 0.0;
+    k[i] = {a, b};
+  }
+  std::sort(k.begin(), k.end());
+  return (int)(std::unique(k.begin(), k.end()) - k.begin());
+}
+
+int gswmtp_plan_workspace_size(const gswmtp_desc *d, size_t *bytes) {
+  if (!bytes) return GSWMTP_E_INVAL;
+  *bytes = 0;
+  const int v = validate(d);
+  if (v != GSWMTP_OK) return v;
+  gswmtp_plan t;
+  try {
+    Dims &D = t.d;
+    D.ny = d->ny;
+    D.nx = d->nx;
+    D.nf = d->n_foci;
+    D.ux = count_keys(d->fx, d->fz, D.nf);
+    D.uy = count_keys(d->fy, d->fz, D.nf);
+    std::vector<char> keep_r(d->ny, 0), keep_c(d->nx, 0);
+    for (int y = 0; y < d->ny; ++y)
+      for (int x = 0; x < d->nx; ++x) {
+        const size_t i = (size_t)y * d->nx + x;
+        const float a = d->mask && !d->mask[i] ? 0.f : d->amplitude ? d->amplitude[i] : 1.f;
+        if (a > 0.f) keep_r[y] = keep_c[x] = 1;
+      }
+    D.ny_kept = (int)std::count(keep_r.begin(), keep_r.end(), 1);
+    D.nx_kept = (int)std::count(keep_c.begin(), keep_c.end(), 1);
+  } catch (const std::bad_alloc &) {
+    return GSWMTP_E_NOMEM;
+  }
+  if (t.d.ny_kept == 0 || t.d.nx_kept == 0) return GSWMTP_E_EMPTYAPERTURE;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      cus > 0)
+    t.cus = cus;
+  else
+    t.cus = 256;
+  t.precision = d->precision;
+  derive_layout(&t, d);
+  Carver c0(nullptr), c1(nullptr);
+  carve_pool0(c0, t.b, t.d.nf, t.d.ny, t.d.nx);
+  carve_pool1(c1, t.b, &t);
+  *bytes = round_up(c0.off, 256) + c1.off;
+  return GSWMTP_OK;
+}
+
+int gswmtp_plan_create_with_workspace(gswmtp_plan **out, const gswmtp_desc *d, void *dev_ws,
+                                      size_t bytes, void *stream) {
+  if (!out) return GSWMTP_E_INVAL;
+  *out = nullptr;
+  g_last_create_error.clear();
+  if (!dev_ws || bytes == 0 || reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0) {
+    g_last_create_error = "workspace must be non-null, non-empty and 256-byte aligned";
+    return GSWMTP_E_INVAL;
+  }
+  return create_impl(out, d, dev_ws, bytes, stream);
+}
+
 int gswmtp_plan_create(gswmtp_plan **out, const gswmtp_desc *d, void *stream) {
   if (!out) return GSWMTP_E_INVAL;
   *out = nullptr;
   g_last_create_error.clear();
+  return create_impl(out, d, nullptr, 0, stream);
+}
+
+static int create_impl(gswmtp_plan **out, const gswmtp_desc *d, void *ws, size_t ws_bytes,
+                       void *stream) {
   const int v = validate(d);
   if (v != GSWMTP_OK) {
     g_last_create_error = "invalid plan descriptor";
@@ -1227,6 +1345,8 @@ int gswmtp_plan_create(gswmtp_plan **out, const gswmtp_desc *d, void *stream) {
   }
   gswmtp_plan *p = new (std::nothrow) gswmtp_plan();
   if (!p) return GSWMTP_E_NOMEM;
+  p->ws = ws;
+  p->ws_bytes = ws_bytes;
   p->user_stream = static_cast<hipStream_t>(stream);
   int rc = check_device(p);
   if (rc == GSWMTP_OK) {

@@ -143,3 +143,44 @@ def test_product_path_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "gsw_oracle" not in text and "liboracle" not in text, f
+
+
+def test_workspace_size_host_only():
+    """Sizing needs no GPU: validation codes as at creation, and the size
+    grows with what the plan holds."""
+    import paper_2206_12661_amd as g
+    import synth_ofa
+    lib = g.load_library()
+    n = ctypes.c_size_t(123)
+    assert lib.gswmtp_plan_workspace_size(None, ctypes.byref(n)) == -1
+    d, keep = _desc(g)
+    assert lib.gswmtp_plan_workspace_size(ctypes.byref(d), None) == -1
+    assert lib.gswmtp_plan_workspace_size(ctypes.byref(d), ctypes.byref(n)) == 0
+    assert n.value > 0
+    d, keep = _desc(g, s_x=0.0)
+    assert lib.gswmtp_plan_workspace_size(ctypes.byref(d), ctypes.byref(n)) == -1
+    d, keep = _desc(g, amplitude=np.zeros(64, np.float32))
+    assert lib.gswmtp_plan_workspace_size(ctypes.byref(d), ctypes.byref(n)) == -3
+    small = g.Plan.workspace_size(synth_ofa.config1())
+    big = g.Plan.workspace_size(synth_ofa.config3())
+    assert 0 < small < big
+    # three-term split planes hold more than two-term ones
+    h = synth_ofa.config2()
+    assert g.Plan.workspace_size(h, precision="bf16x6") > g.Plan.workspace_size(
+        h, precision="bf16x3")
+
+
+def test_create_with_workspace_rejects_bad_buffers():
+    import paper_2206_12661_amd as g
+    lib = g.load_library()
+    d, keep = _desc(g)
+    h = ctypes.c_void_p()
+    assert lib.gswmtp_plan_create_with_workspace(None, ctypes.byref(d), None, 0, None) == -1
+    assert lib.gswmtp_plan_create_with_workspace(ctypes.byref(h), ctypes.byref(d), None, 4096,
+                                                 None) == -1
+    assert lib.gswmtp_plan_create_with_workspace(ctypes.byref(h), ctypes.byref(d), 256, 0,
+                                                 None) == -1
+    assert lib.gswmtp_plan_create_with_workspace(ctypes.byref(h), ctypes.byref(d), 4096 + 8,
+                                                 4096, None) == -1
+    assert not h.value
+    assert "aligned" in lib.gswmtp_last_error(None).decode()
