@@ -43,9 +43,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--modes", default="fp32,bf16x3,fp16x3,bf16x6")
-    ap.add_argument("--cpu-passes", type=int, default=40,
+    ap.add_argument("--cpu-passes", type=int, default=100,
                     help="oracle passes of the CPU sample and of the trajectory-error "
-                         "check (about 11 s on 16 host cores; 0 disables)")
+                         "check (the workload's 100 iterations, about 28 s on 16 host "
+                         "cores; 0 disables)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stage-iters", type=int, default=20)
     ap.add_argument("--no-library-reference", action="store_true",
@@ -58,6 +59,8 @@ def parse():
                          "1000 x 1000 pupil) and the continuous double-heart pattern")
     ap.add_argument("--adam-steps", type=int, default=200,
                     help="Adam steps of the differentiable 50x50-grid design (0 disables)")
+    ap.add_argument("--small-steps", type=int, default=1000,
+                    help="graph-replayed passes per small configuration (0 skips)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="timed passes of the 64-hologram batch (0 disables)")
     return ap.parse_args()
@@ -214,6 +217,27 @@ def run_mode(g, torch, h, mode, args):
             "pass_tflops": fl["pass"] * ips / 1e12, "theta0": theta0, "dtype": dt}
 
 
+def run_small(g, torch, args, modes):
+    """The latency-bound configurations (64 x 64 / 16 foci and 512 x 512 /
+    100 foci): microseconds per pass under graph replay."""
+    import synth_ofa
+    out = {}
+    for name, h in (("config1-64x64-16foci", synth_ofa.config1()),
+                    ("config2-512x512-100foci", synth_ofa.config2())):
+        out[name] = {}
+        for m in dict.fromkeys(modes):
+            with g.Plan(h, precision=m) as p:
+                p.iterate(20)
+                p.sync()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                p.iterate(args.small_steps)
+                p.sync()
+                dt = time.perf_counter() - t0
+            out[name][m] = {"us_per_pass": round(1e6 * dt / args.small_steps, 2)}
+    return out
+
+
 def run_batch(g, torch, args):
     """The 64-hologram batch (uneven sides 256-1024, 16-2000 foci), float32:
     batched passes per second, each pass advancing every hologram by one."""
@@ -331,18 +355,27 @@ def main():
     base, r_or, k = None, None, 0
     if not args.no_cpu_baseline and args.cpu_passes > 0:
         base, r_or, k = cpu_baseline(h, args.cpu_passes)
+    xi_ckpt = [c for c in (1, 2, 5, 10, 20, 50, 100, 200) if c <= k]
+    xi_oracle = None
     if r_or is not None:
         import oracle
         theta_ref0 = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+        theta_ref1 = oracle.gsw(h, n_iter=1)["theta"]          # one pass from phi0
         I_ref = np.abs(r_or["theta"]) ** 2
+        xi_oracle = [round(float(r_or["history"][c - 1, 0]), 6) for c in xi_ckpt]
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))  # noqa: E731
         for m in modes:
             with g.Plan(h, precision=m) as p2:
-                p2.iterate(k)
+                p2.iterate(1)
+                th1 = p2.foci_field().astype(np.complex128)
+                p2.iterate(k - 1)
                 th = p2.foci_field()
+                hist = p2.history()
             I = np.abs(th.astype(np.complex128)) ** 2
-            res[m]["traj_err"] = float(np.linalg.norm(I - I_ref) / np.linalg.norm(I_ref))
-            t0 = res[m]["theta0"].astype(np.complex128)
-            res[m]["op_err"] = float(np.linalg.norm(t0 - theta_ref0) / np.linalg.norm(theta_ref0))
+            res[m]["traj_err"] = rel(I, I_ref)
+            res[m]["one_step_err"] = rel(th1, theta_ref1)
+            res[m]["op_err"] = rel(res[m]["theta0"].astype(np.complex128), theta_ref0)
+            res[m]["xi"] = [round(float(hist[c - 1, 0]), 6) for c in xi_ckpt]
 
     # headline: fastest mode at equal error (trajectory error <= 2x float32's)
     head = "fp32" if "fp32" in res else modes[0]
@@ -352,6 +385,7 @@ def main():
         head = max(ok, key=lambda m: res[m]["value"])
     hr = res[head]
     libref = library_reference(torch, hr["index"]) if not args.no_library_reference else None
+    small = run_small(g, torch, args, ("fp32", head)) if args.small_steps > 0 else None
     batch = run_batch(g, torch, args) if args.batch_steps > 0 else None
     adam = run_adam(g, torch, args) if args.adam_steps > 0 else None
     sweep = run_sweep(g, torch, args) if args.sweep else None
@@ -372,12 +406,15 @@ def main():
         "modes": {m: {"iter_s": round(v["value"], 2), "ms_per_step": round(v["ms_per_step"], 5),
                       "speedup_vs_fp32": (round(v["value"] / res["fp32"]["value"], 3)
                                           if "fp32" in res else None),
-                      "op_err": v.get("op_err"), "traj_err": v.get("traj_err"),
+                      "op_err": v.get("op_err"), "one_step_err": v.get("one_step_err"),
+                      "traj_err": v.get("traj_err"), "xi": v.get("xi"),
                       "equal_error": (v.get("traj_err") is not None and "fp32" in res and
                                       v["traj_err"] <= 2 * res["fp32"]["traj_err"]),
                       "roofline": v["roofline"], "stage_ms": v["stage_ms"]}
                   for m, v in res.items()},
         "error_passes": k,
+        "xi_passes": xi_ckpt, "xi_oracle": xi_oracle,
+        "small_configs": small,
         "library_gemm_reference": libref,
         "batch": batch,
         "differentiable": adam,
