@@ -85,7 +85,8 @@ def _desc(g, **over):
 
 @pytest.mark.parametrize("case", [
     "ny0", "nf0", "nfhuge", "sx0", "sxnan", "fxnan", "targetneg", "targetzero", "ampneg",
-    "ampnan", "phinan", "unan", "precision", "axis", "weighting", "fznan", "fzinf"])
+    "ampnan", "phinan", "unan", "precision", "axis", "weighting", "fznan", "fzinf", "side_over",
+    "nf_over"])
 def test_validation_rejects_bad_descriptors(case):
     import paper_2206_12661_amd as g
     lib = g.load_library()
@@ -102,6 +103,7 @@ def test_validation_rejects_bad_descriptors(case):
         "precision": {"precision": 9}, "axis": {"axis": 2}, "weighting": {"weighting": 5},
         "fznan": {"fz": np.array([0.0, math.nan, 0.0])},
         "fzinf": {"fz": np.array([math.inf, 0.0, 0.0])},
+        "side_over": {"nx": 16385}, "nf_over": {"n_foci": 262145},
     }[case]
     d, keep = _desc(g, **over)
     h = ctypes.c_void_p()
