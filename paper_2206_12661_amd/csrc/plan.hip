@@ -967,10 +967,13 @@ void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
                             choose_tile(D.Rp, D.Cp, split_mode, terms, p->cus), p->cus,
                             split_enabled());
   // Grid form (float32): when the foci fill a quarter or more of the reduced
-  // grid, the second product of Eq. 2 is formed densely on the matrix cores
+  // grid and are many enough to repay its extra launches (measured
+  // crossover: the per-focus gather and scatter cost ~0.09 us per focus and
+  // pass, the grid form ~0.02 us plus ~20 us of launches, even at about 370
+  // foci), the second product of Eq. 2 is formed densely on the matrix cores
   // (as the paper does) instead of per focus.  GSWMTP_SECOND=gather|grid
   // forces either form.
-  p->grid_form = !split_mode && (double)D.Ur * D.Uc <= 4.0 * D.nf;
+  p->grid_form = !split_mode && (double)D.Ur * D.Uc <= 4.0 * D.nf && D.nf >= 384;
   if (const char *sf = std::getenv("GSWMTP_SECOND")) {
     if (std::strcmp(sf, "gather") == 0) p->grid_form = false;
     if (std::strcmp(sf, "grid") == 0 && !split_mode) p->grid_form = true;

@@ -558,9 +558,10 @@ def test_second_product_forms_operators(g, monkeypatch, form, name):
 
 
 def test_grid_form_passes_against_oracle(g, monkeypatch):
-    """Passes in the grid form (chosen automatically for a full grid) against
-    the oracle's trajectory, and graph replay against eager launches."""
-    h = synth_ofa.random_case(81, 160, 200, 0, grid=(15, 11), radius=75.0)
+    """Passes in the grid form (chosen automatically for a full grid of at
+    least 384 foci) against the oracle's trajectory, and graph replay against
+    eager launches."""
+    h = synth_ofa.random_case(81, 160, 200, 0, grid=(24, 20), radius=75.0)
     n = 8
     announce("grid form passes")
     with g.Plan(h) as p:
