@@ -350,28 +350,28 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
       if (kt < ke) PIPE_STEP(0, r0a, r0b, kt);
 #undef PIPE_STEP
     } else {
-    // Stages in pairs with one exit, so the loop is entered from the
-    // prologue and from its back edge in the same state (set 0 older, set 1
-    // newer, both in flight); an odd last stage follows the loop.
-    int kt = kb;
-    for (; kt + 1 < ke; kt += 2) {
-      STORE_STAGE(r0a, r0b, 0);
-      __syncthreads();
-      LOAD_STAGE(r0a, r0b, kt + 2 < last ? kt + 2 : last);
-      __builtin_amdgcn_sched_barrier(0);   // issue the loads here, ahead of the MFMAs
-      stage_mma<BM, BN, BK, BF, NT, KG>(sA, sB, accR, accI, wm, wn, l32, h, kg);
-      STORE_STAGE(r1a, r1b, 1);
-      __syncthreads();
-      LOAD_STAGE(r1a, r1b, kt + 3 < last ? kt + 3 : last);
-      __builtin_amdgcn_sched_barrier(0);
-      stage_mma<BM, BN, BK, BF, NT, KG>(sA + SA_SZ, sB + SB_SZ, accR, accI, wm, wn, l32, h,
-                                        kg);
-    }
-    if (kt < ke) {
-      STORE_STAGE(r0a, r0b, 0);
-      __syncthreads();
-      stage_mma<BM, BN, BK, BF, NT, KG>(sA, sB, accR, accI, wm, wn, l32, h, kg);
-    }
+      // Stages in pairs with one exit, so the loop is entered from the
+      // prologue and from its back edge in the same state (set 0 older, set 1
+      // newer, both in flight); an odd last stage follows the loop.
+      int kt = kb;
+      for (; kt + 1 < ke; kt += 2) {
+        STORE_STAGE(r0a, r0b, 0);
+        __syncthreads();
+        LOAD_STAGE(r0a, r0b, kt + 2 < last ? kt + 2 : last);
+        __builtin_amdgcn_sched_barrier(0);   // issue the loads here, ahead of the MFMAs
+        stage_mma<BM, BN, BK, BF, NT, KG>(sA, sB, accR, accI, wm, wn, l32, h, kg);
+        STORE_STAGE(r1a, r1b, 1);
+        __syncthreads();
+        LOAD_STAGE(r1a, r1b, kt + 3 < last ? kt + 3 : last);
+        __builtin_amdgcn_sched_barrier(0);
+        stage_mma<BM, BN, BK, BF, NT, KG>(sA + SA_SZ, sB + SB_SZ, accR, accI, wm, wn, l32, h,
+                                          kg);
+      }
+      if (kt < ke) {
+        STORE_STAGE(r0a, r0b, 0);
+        __syncthreads();
+        stage_mma<BM, BN, BK, BF, NT, KG>(sA, sB, accR, accI, wm, wn, l32, h, kg);
+      }
     }
     __syncthreads();   // the epilogues reuse the operand buffers
     if constexpr (KG == 2) {
