@@ -239,35 +239,42 @@ def run_small(g, torch, args, modes):
 
 
 def run_batch(g, torch, args):
-    """The 64-hologram batch (uneven sides 256-1024, 16-2000 foci), float32:
-    batched passes per second, each pass advancing every hologram by one."""
+    """The 64-hologram batch (uneven sides 256-1024, 16-2000 foci) in float32
+    and in BF16x3: batched passes per second, each pass advancing every
+    hologram by one."""
     import synth_ofa
     hs = synth_ofa.config4()
-    t0 = time.perf_counter()
-    plans = [g.Plan(h) for h in hs]
-    flops = sum(algorithmic_flops(p.index(), p.n_foci)["pass"] for p in plans)
-    b = g.Batch(plans)
-    b.sync()
-    setup_ms = (time.perf_counter() - t0) * 1e3
-    b.iterate(max(1, args.warmup // 4))
-    b.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.iterate(args.batch_steps)
-    b.sync()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    tiles = b.tiles()
-    b.close()
-    for p in plans:
-        p.close()
-    ips = args.batch_steps / dt
-    return {"workload": "gsw-batch-64-holograms-256to1024px-16to2000foci", "holograms": len(hs),
-            "batch_iter_s": round(ips, 3), "hologram_iter_s": round(ips * len(hs), 2),
-            "ms_per_batch_iter": round(1e3 / ips, 4), "flops_per_batch_iter": flops,
-            "tflops": round(flops * ips / 1e12, 3),
-            "frac_f32_peak": round(flops * ips / 1e12 / PEAK_TFLOPS["f32"], 4),
-            "tiles": tiles, "setup_ms": round(setup_ms, 1), "steps": args.batch_steps}
+    out = {"workload": "gsw-batch-64-holograms-256to1024px-16to2000foci",
+           "holograms": len(hs), "steps": args.batch_steps}
+    for mode in ("fp32", "bf16x3"):
+        t0 = time.perf_counter()
+        plans = [g.Plan(h, precision=mode) for h in hs]
+        flops = sum(algorithmic_flops(p.index(), p.n_foci)["pass"] for p in plans)
+        b = g.Batch(plans)
+        b.sync()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        b.iterate(max(1, args.warmup // 4))
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.iterate(args.batch_steps)
+        b.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tiles = b.tiles()
+        b.close()
+        for p in plans:
+            p.close()
+        ips = args.batch_steps / dt
+        r = {"batch_iter_s": round(ips, 3), "hologram_iter_s": round(ips * len(hs), 2),
+             "ms_per_batch_iter": round(1e3 / ips, 4), "flops_per_batch_iter": flops,
+             "tflops": round(flops * ips / 1e12, 3),
+             "tiles": {"forward": tiles["forward"], "adjoint": tiles["adjoint"]},
+             "setup_ms": round(setup_ms, 1)}
+        if mode == "fp32":
+            r["frac_f32_peak"] = round(flops * ips / 1e12 / PEAK_TFLOPS["f32"], 4)
+        out[mode] = r
+    return out
 
 
 def run_sweep(g, torch, args):

@@ -292,12 +292,16 @@ const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
  * tiles of all plans, replayed from a captured HIP graph.
  *
  * batch_create: plans[n_plans] (1..65536 distinct plans on one device, all
- *   FP32 precision, else GSWMTP_E_UNSUPPORTED) must outlive the batch; the
- *   batch keeps pointers, copies nothing.  Chooses the product tiles (among
- *   64/128 x 64/128 tiles that divide every plan, by timing a few grouped
- *   launches when more than one is valid; GSWMTP_BATCH_TILE=BMxBN fixes it,
- *   GSWMTP_BATCH_NO_TUNE=1 takes the first valid) without changing any plan's
- *   state.  Allocates its own argument tables.  stream: hipStream_t or NULL.
+ *   of one precision, else GSWMTP_E_INVAL) must outlive the batch; the
+ *   batch keeps pointers, copies nothing.  FP32: chooses the product tiles
+ *   (among 64/128 x 64/128 tiles that divide every plan, by timing a few
+ *   grouped launches when more than one is valid; GSWMTP_BATCH_TILE=BMxBN
+ *   fixes it, GSWMTP_BATCH_NO_TUNE=1 takes the first valid) without changing
+ *   any plan's state.  Split precisions: the single-plan form's product
+ *   loops on 64 x 64 tiles (the forward 64 x 128 when a plan's own forward
+ *   tile is that wide, or when GSWMTP_BATCH_TILE=64x128 and every plan
+ *   allows it).  Allocates its own argument tables.  stream: hipStream_t or
+ *   NULL.
  * batch_iterate: n_iter passes on every plan, each plan stopping on its own
  *   as gswmtp_iterate(p, n_iter, stop_accuracy) would; ordered after the
  *   caller's stream and each plan's queued work, and before later calls on
@@ -309,7 +313,8 @@ const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
  * batch_sync: wait for the batch's queued passes.
  * batch_tiles: tiles[4] = forward BM, BN, adjoint BM, BN; tune_ms (nullable)
  *   [8] = mean grouped-launch milliseconds per candidate (64x64, 64x128,
- *   128x64, 128x128; forward then adjoint; 0 = not timed).
+ *   128x64, 128x128; forward then adjoint; 0 = not timed, always for split
+ *   precisions).
  * batch_last_error: message of the batch's last failed call, or of the last
  *   failed batch_create on this thread when b == NULL. */
 int gswmtp_batch_create(gswmtp_batch **out, gswmtp_plan *const *plans, int n_plans, void *stream);

@@ -6,7 +6,9 @@
 // tile lists of the plans' products, each workgroup finding its plan by a
 // binary search over the item start offsets.  A pass of the whole batch is
 // thus four launches whatever the number of plans, and it is replayed from a
-// captured HIP graph.  Items are ordered by descending K (the longest tiles
+// captured HIP graph.  The plans share one precision: float32 products with
+// autotuned tiles, or the split-precision products with the single-plan
+// form's loops.  Items are ordered by descending K (the longest tiles
 // are dispatched first) so that the short products of small holograms fill
 // the tail of the launch.
 //
@@ -46,6 +48,7 @@ struct gswmtp_batch {
   hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
   bool use_graph = true;
   double tune_ms[2][4] = {};   // [forward/adjoint][candidate] mean launch ms (0: not timed)
+  int precision = GSWMTP_FP32; // common precision of the plans
   std::string err;
 };
 
@@ -97,10 +100,18 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 hipError_t enqueue_batch_pass(gswmtp_batch *b, hipStream_t s) {
   hipError_t e;
+  const int n = (int)b->plans.size();
+  if (b->precision != GSWMTP_FP32) {
+    if ((e = launch_cgemm_split_grouped(b->fwd, s)) != hipSuccess) return e;
+    if ((e = launch_update_grouped(b->upd, s)) != hipSuccess) return e;
+    if ((e = launch_scatter_split_grouped(b->d_sc, b->d_sc_starts, n, b->sc_blocks, b->precision,
+                                          s)) != hipSuccess)
+      return e;
+    return launch_cgemm_split_grouped(b->bwd, s);
+  }
   if ((e = launch_cgemm_grouped(b->fwd, s)) != hipSuccess) return e;
   if ((e = launch_update_grouped(b->upd, s)) != hipSuccess) return e;
-  if ((e = launch_scatter_grouped(b->d_sc, b->d_sc_starts, (int)b->plans.size(), b->sc_blocks,
-                                  s)) != hipSuccess)
+  if ((e = launch_scatter_grouped(b->d_sc, b->d_sc_starts, n, b->sc_blocks, s)) != hipSuccess)
     return e;
   return launch_cgemm_grouped(b->bwd, s);
 }
@@ -173,8 +184,6 @@ bool tile_valid(const std::vector<gswmtp_plan *> &plans, bool forward, int bm, i
   for (const auto *p : plans) {
     const int M = forward ? p->d.Urp : p->d.Rp;
     if (M % bm || p->d.Cp % bn) return false;
-    // the gather partials of a plan hold Cp / (its own tile width) entries per focus
-    if (forward && bn < p->sched_fwd.tile.bn) return false;
   }
   return true;
 }
@@ -193,8 +202,49 @@ int upload_grouped(gswmtp_batch *b, const GroupedHost &h, char *&base, GroupedLa
   return GSWMTP_OK;
 }
 
-size_t grouped_bytes(size_t n) {
-  return align256(cgemm_args_bytes() * n) + align256((n + 1) * sizeof(int));
+size_t grouped_bytes(size_t n, size_t item = cgemm_args_bytes()) {
+  return align256(item * n) + align256((n + 1) * sizeof(int));
+}
+
+// Split-precision products: one plan's whole-tile schedule per item.
+GroupedHost build_grouped_split(const std::vector<gswmtp_plan *> &plans,
+                                const std::vector<int> &order, bool forward, const GemmTile &tl) {
+  const size_t sz = split_args_bytes();
+  GroupedHost g;
+  g.items.resize(sz * order.size());
+  g.starts.resize(order.size() + 1);
+  for (size_t k = 0; k < order.size(); ++k) {
+    g.starts[k] = g.blocks;
+    g.blocks += fill_split_args(plans[order[k]], forward, tl, true, g.items.data() + k * sz);
+  }
+  g.starts[order.size()] = g.blocks;
+  return g;
+}
+
+// Split-precision tiles: the product loops of the single-plan form (the
+// software-pipelined loop for two terms, two k-groups for three), 64 x 64,
+// or a 64 x 128 forward tile (two terms) when GSWMTP_BATCH_TILE=64x128 asks
+// and it divides every plan.
+int choose_split_tile(gswmtp_batch *b, bool forward, GemmTile &t) {
+  const int nt = split_terms_of(b->precision);
+  t = GemmTile{64, 64, 32, nt > 2 ? 2 : 1, nt > 2 ? 0 : 1};
+  if (nt > 2) {
+    if (tile_valid(b->plans, forward, 64, 64)) return GSWMTP_OK;
+    return bfail(b, GSWMTP_E_INVAL, "no split tile divides every plan");
+  }
+  const bool v64 = tile_valid(b->plans, forward, 64, 64);
+  const bool v128 = tile_valid(b->plans, forward, 64, 128);
+  const char *env = std::getenv("GSWMTP_BATCH_TILE");
+  if (env && std::strcmp(env, "64x128") == 0 && v128) {
+    t.bn = 128;
+    return GSWMTP_OK;
+  }
+  if (v64) return GSWMTP_OK;
+  if (v128) {
+    t.bn = 128;
+    return GSWMTP_OK;
+  }
+  return bfail(b, GSWMTP_E_INVAL, "no split tile divides every plan");
 }
 
 // Autotuning: among the tiles valid for every plan, the one with the lowest
@@ -290,14 +340,26 @@ int batch_build(gswmtp_batch *b) {
                    [&](int x, int y) { return b->plans[x]->d.Urp > b->plans[y]->d.Urp; });
 
   int rc;
-  if ((rc = choose_batch_tile(b, true, ofwd, b->fwd.bm, b->fwd.bn)) != GSWMTP_OK) return rc;
-  if ((rc = choose_batch_tile(b, false, obwd, b->bwd.bm, b->bwd.bn)) != GSWMTP_OK) return rc;
+  const bool split = b->precision != GSWMTP_FP32;
+  if (split) {
+    if ((rc = choose_split_tile(b, true, b->fwd.tile)) != GSWMTP_OK) return rc;
+    if ((rc = choose_split_tile(b, false, b->bwd.tile)) != GSWMTP_OK) return rc;
+    b->fwd.bm = b->fwd.tile.bm;
+    b->fwd.bn = b->fwd.tile.bn;
+    b->bwd.bm = b->bwd.tile.bm;
+    b->bwd.bn = b->bwd.tile.bn;
+    b->fwd.precision = b->bwd.precision = b->precision;
+  } else {
+    if ((rc = choose_batch_tile(b, true, ofwd, b->fwd.bm, b->fwd.bn)) != GSWMTP_OK) return rc;
+    if ((rc = choose_batch_tile(b, false, obwd, b->bwd.bm, b->bwd.bn)) != GSWMTP_OK) return rc;
+  }
   b->fwd.epi = EPI_GATHER;
   b->bwd.epi = EPI_PROJECT;
 
   // update / scatter items in plan order; the many-focus plans' update
   // items also go to a second table for the update's phases 2 and 3
-  const size_t usz = update_args_bytes(), ssz = scatter_args_bytes();
+  const size_t usz = update_args_bytes();
+  const size_t ssz = split ? scatter_split_args_bytes() : scatter_args_bytes();
   std::vector<unsigned char> upd(usz * n), sc(ssz * n), big;
   std::vector<int> upd_starts(n + 1), big_starts(1, 0), sc_starts(n + 1);
   std::vector<int *> ctrl(n);
@@ -313,7 +375,8 @@ int batch_build(gswmtp_batch *b) {
       big_starts.push_back(big_starts.back() + nwg);
     }
     sc_starts[i] = blocks;
-    blocks += fill_scatter_args(p, sc.data() + i * ssz);
+    blocks += split ? fill_scatter_split_args(p, sc.data() + i * ssz)
+                    : fill_scatter_args(p, sc.data() + i * ssz);
     ctrl[i] = p->b.ctrl;
     stats[i] = p->b.stats;
   }
@@ -322,13 +385,18 @@ int batch_build(gswmtp_batch *b) {
   b->sc_blocks = blocks;
   const int nb = (int)big_starts.size() - 1;
 
-  const size_t bytes = 2 * grouped_bytes(n) + align256(usz * n) + align256(ssz * n) +
+  const size_t isz = split ? split_args_bytes() : cgemm_args_bytes();
+  const size_t bytes = 2 * grouped_bytes(n, isz) + align256(usz * n) + align256(ssz * n) +
                        2 * align256((n + 1) * sizeof(int)) + 2 * align256(n * sizeof(void *)) +
                        align256(usz * (nb > 0 ? nb : 1)) + align256((nb + 1) * sizeof(int));
   BHIP_TRY(b, hipMalloc(&b->pool, bytes));
   char *base = static_cast<char *>(b->pool);
-  const GroupedHost hf = build_grouped(b->plans, ofwd, true, b->fwd.bm, b->fwd.bn, false, nullptr);
-  const GroupedHost hb = build_grouped(b->plans, obwd, false, b->bwd.bm, b->bwd.bn, false, nullptr);
+  const GroupedHost hf =
+      split ? build_grouped_split(b->plans, ofwd, true, b->fwd.tile)
+            : build_grouped(b->plans, ofwd, true, b->fwd.bm, b->fwd.bn, false, nullptr);
+  const GroupedHost hb =
+      split ? build_grouped_split(b->plans, obwd, false, b->bwd.tile)
+            : build_grouped(b->plans, obwd, false, b->bwd.bm, b->bwd.bn, false, nullptr);
   if ((rc = upload_grouped(b, hf, base, b->fwd)) != GSWMTP_OK) return rc;
   if ((rc = upload_grouped(b, hb, base, b->bwd)) != GSWMTP_OK) return rc;
   b->upd.d_items = base;
@@ -389,9 +457,9 @@ int gswmtp_batch_create(gswmtp_batch **out, gswmtp_plan *const *plans, int n_pla
       g_batch_create_error = "NULL plan";
       return GSWMTP_E_INVAL;
     }
-    if (p->precision != GSWMTP_FP32) {
-      g_batch_create_error = "batched plans must use FP32 precision";
-      return GSWMTP_E_UNSUPPORTED;
+    if (p->precision != ps[0]->precision) {
+      g_batch_create_error = "batched plans must share one precision";
+      return GSWMTP_E_INVAL;
     }
     if (p->device != ps[0]->device) {
       g_batch_create_error = "batched plans must share one device";
@@ -409,6 +477,7 @@ int gswmtp_batch_create(gswmtp_batch **out, gswmtp_plan *const *plans, int n_pla
   gswmtp_batch *b = new (std::nothrow) gswmtp_batch();
   if (!b) return GSWMTP_E_NOMEM;
   b->device = ps[0]->device;
+  b->precision = ps[0]->precision;
   b->user_stream = static_cast<hipStream_t>(stream);
   b->plans = ps;
   const char *ng = std::getenv("GSWMTP_NO_GRAPH");

@@ -617,12 +617,12 @@ __global__ __launch_bounds__(256) void focus_scatter_grouped(const ScatterArgs *
 // (entry k of every row at once), so their loads are in flight together.
 // ic: reduced-grid column of the focus at each CSR position.
 template <bool BF, int NT>
-__global__ __launch_bounds__(256) void focus_scatter_split(
+__device__ __forceinline__ void focus_scatter_split_body(
     const float *__restrict__ tn, const float *__restrict__ wr, const float *__restrict__ wi,
     const int *__restrict__ ic, const int *__restrict__ ptr, const int *__restrict__ foci,
-    unsigned short *__restrict__ st, int Ur, int Urp, int Cp, float scale, const int *done) {
-  __shared__ float tr[32][65], ti[32][65];
-  const int i0 = blockIdx.x * 64, a0 = blockIdx.y * 32;
+    unsigned short *__restrict__ st, int Ur, int Urp, int Cp, float scale, const int *done,
+    int bx, int by, float (*tr)[65], float (*ti)[65]) {
+  const int i0 = bx * 64, a0 = by * 32;
   const int tid = threadIdx.x;
   const int il = tid & 63;
   constexpr int R = 8;   // rows per thread: a0 + (tid >> 6) + 4 q
@@ -693,6 +693,43 @@ __global__ __launch_bounds__(256) void focus_scatter_split(
   }
 }
 
+template <bool BF, int NT>
+__global__ __launch_bounds__(256) void focus_scatter_split(
+    const float *__restrict__ tn, const float *__restrict__ wr, const float *__restrict__ wi,
+    const int *__restrict__ ic, const int *__restrict__ ptr, const int *__restrict__ foci,
+    unsigned short *__restrict__ st, int Ur, int Urp, int Cp, float scale, const int *done) {
+  __shared__ float tr[32][65], ti[32][65];
+  focus_scatter_split_body<BF, NT>(tn, wr, wi, ic, ptr, foci, st, Ur, Urp, Cp, scale, done,
+                                   blockIdx.x, blockIdx.y, tr, ti);
+}
+
+// One plan's scatter as an item of the batched form's grouped launch.
+struct ScatterSplitArgs {
+  const float *tn, *wr, *wi;
+  const int *ic, *ptr, *foci;
+  unsigned short *st;
+  int Ur, Urp, Cp;
+  float scale;
+  const int *done;
+};
+
+template <bool BF, int NT>
+__global__ __launch_bounds__(256) void focus_scatter_split_grouped(const ScatterSplitArgs *items,
+                                                                   const int *starts, int n) {
+  __shared__ float tr[32][65], ti[32][65];
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (starts[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const ScatterSplitArgs &a = items[lo];
+  const int u = b - starts[lo], gx = a.Cp / 64;
+  focus_scatter_split_body<BF, NT>(a.tn, a.wr, a.wi, a.ic, a.ptr, a.foci, a.st, a.Ur, a.Urp,
+                                   a.Cp, a.scale, a.done, u % gx, u / gx, tr, ti);
+}
+
 }  // namespace
 
 hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
@@ -712,6 +749,32 @@ hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, fl
     default: return hipErrorInvalidValue;
   }
 #undef SCATTER_SPLIT
+  return hipGetLastError();
+}
+
+size_t scatter_split_args_bytes() { return sizeof(ScatterSplitArgs); }
+
+int fill_scatter_split_args(const gswmtp_plan *p, void *out) {
+  const Dims &d = p->d;
+  ScatterSplitArgs a{p->b.theta_new, p->b.wc_r, p->b.wc_i, p->b.csr_ic, p->b.csr_ptr,
+                     p->b.csr_foci, p->b.ss, d.Ur, d.Urp, d.Cp, 1.f, p->b.ctrl + CTRL_DONE};
+  std::memcpy(out, &a, sizeof a);
+  return (d.Cp / 64) * (d.Urp / 32);
+}
+
+hipError_t launch_scatter_split_grouped(const void *items, const int *starts, int n, int blocks,
+                                        int precision, hipStream_t s) {
+  const ScatterSplitArgs *it = static_cast<const ScatterSplitArgs *>(items);
+#define SCATTER_GROUPED(BF, NT)                                                                \
+  hipLaunchKernelGGL((focus_scatter_split_grouped<BF, NT>), dim3(blocks), dim3(256), 0, s, it, \
+                     starts, n)
+  switch (precision) {
+    case GSWMTP_BF16X3: SCATTER_GROUPED(true, 2); break;
+    case GSWMTP_FP16X3: SCATTER_GROUPED(false, 2); break;
+    case GSWMTP_BF16X6: SCATTER_GROUPED(true, 3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SCATTER_GROUPED
   return hipGetLastError();
 }
 

@@ -25,6 +25,8 @@
 // the amplitude constraint and write the pupil field directly as the split
 // B^T planes of the next forward product, transposed through LDS so every
 // store is a 16-byte run of one row of P^T.
+#include <cstring>
+
 #include "gswmtp_internal.h"
 
 namespace gswmtp {
@@ -203,7 +205,14 @@ __device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
 // since two stages ago) into the buffer just left and issue the loads of
 // stage S + 4.
 template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
-__global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
+constexpr int split_lds_u4() {
+  return (split_lds_bytes<BM, BN, BK, NT, EPI>() + 15) / 16;
+}
+
+// The product for block `bid` of one schedule (whole tile, K chunk or tail
+// reduction), LDS `lds` of split_lds_u4 entries.
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+__device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int bid, u4 *lds) {
   constexpr int NTH = kThreads * KG;
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int MB = WTM / 32, NB = WTN / 32;
@@ -216,9 +225,7 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
   constexpr int SA_SZ = LA, SB_SZ = LB;
   // epilogue transpose tile: [plane][n][m] 16-bit with rows padded by 8 elements
   constexpr int TP = BM + 8;
-  constexpr int L_SZ = (split_lds_bytes<BM, BN, BK, NT, EPI>() + 15) / 16;
 
-  __shared__ u4 lds[L_SZ];
   u4 *sA = lds;                         // [2][SA_SZ]
   u4 *sB = lds + 2 * SA_SZ;             // [2][SB_SZ]
 
@@ -226,15 +233,15 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
   const int KT = a.K / BK;
   int t, kb, ke, tail = -1, chunk = 0;
   if (a.phase == 1) {
-    tail = blockIdx.x;
+    tail = bid;
     t = a.t_dp + tail;
     kb = ke = 0;
-  } else if ((int)blockIdx.x < a.t_dp) {
-    t = xcd_tile(blockIdx.x, a.t_dp);
+  } else if (bid < a.t_dp) {
+    t = xcd_tile(bid, a.t_dp);
     kb = 0;
     ke = KT;
   } else {
-    const int u = blockIdx.x - a.t_dp;
+    const int u = bid - a.t_dp;
     tail = u / a.split;
     chunk = u % a.split;
     t = a.t_dp + tail;
@@ -513,6 +520,29 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
   }
 }
 
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+__global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
+  __shared__ u4 lds[split_lds_u4<BM, BN, BK, BF, NT, EPI, KG, PIPE>()];
+  cgemm_split_body<BM, BN, BK, BF, NT, EPI, KG, PIPE>(a, blockIdx.x, lds);
+}
+
+// Grouped launch (batched form): the concatenated whole-tile schedules of
+// several plans' products; block b belongs to the item whose start offset is
+// the largest one <= b (binary search) and runs its local block b - start.
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+__global__ __launch_bounds__(kThreads * KG) void cgemm_split_grouped(const SplitArgs *items,
+                                                                     const int *starts, int n) {
+  __shared__ u4 lds[split_lds_u4<BM, BN, BK, BF, NT, EPI, KG, PIPE>()];
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (starts[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  cgemm_split_body<BM, BN, BK, BF, NT, EPI, KG, PIPE>(items[lo], b - starts[lo], lds);
+}
+
 // Split-K tail with the projection epilogue: adds the K-chunk partials of
 // each tail tile in chunk order and projects, then writes the 16-bit term
 // planes of P^T (four consecutive rows of one column per thread: one 8-byte
@@ -640,13 +670,12 @@ hipError_t launch_p(int precision, const GemmTile &tl, const SplitArgs &args, in
 
 }  // namespace
 
-hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
-                              const unsigned short *bt, float *cr, float *ci,
-                              unsigned short *pt_out, bool honour_done, hipStream_t s,
-                              int phases) {
+namespace {
+
+// Operand, output and epilogue pointers of one plan's split product.
+SplitArgs split_args(const gswmtp_plan *p, bool forward, const unsigned short *bt, float *cr,
+                     float *ci, unsigned short *pt_out, bool honour_done) {
   const Dims &d = p->d;
-  const GemmSched &sc = forward ? p->sched_fwd : p->sched_bwd;
-  const int nt = split_terms_of(p->precision);
   SplitArgs a{};
   if (forward) {
     a.a = p->b.as_f;
@@ -670,6 +699,18 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
   a.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
   a.part = p->b.part;
   a.g = gather_ctx(p);
+  return a;
+}
+
+}  // namespace
+
+hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
+                              const unsigned short *bt, float *cr, float *ci,
+                              unsigned short *pt_out, bool honour_done, hipStream_t s,
+                              int phases) {
+  const GemmSched &sc = forward ? p->sched_fwd : p->sched_bwd;
+  const int nt = split_terms_of(p->precision);
+  SplitArgs a = split_args(p, forward, bt, cr, ci, pt_out, honour_done);
   if (nt < 2 || a.M % sc.tile.bm || a.N % sc.tile.bn || a.K % sc.tile.bk)
     return hipErrorInvalidValue;
   if (sc.tiles_m * sc.tile.bm != a.M || sc.tiles * sc.tile.bm * sc.tile.bn != a.M * a.N)
@@ -695,6 +736,69 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+
+// ---- batched form -----------------------------------------------------------
+
+size_t split_args_bytes() { return sizeof(SplitArgs); }
+
+int fill_split_args(const gswmtp_plan *p, bool forward, const GemmTile &tl, bool honour_done,
+                    void *out) {
+  SplitArgs a = forward ? split_args(p, true, p->b.ps, nullptr, nullptr, nullptr, honour_done)
+                        : split_args(p, false, p->b.ss, nullptr, nullptr, p->b.ps, honour_done);
+  a.tiles_m = a.M / tl.bm;
+  a.t_dp = a.tiles_m * (a.N / tl.bn);
+  a.split = 1;
+  a.phase = 0;
+  std::memcpy(out, &a, sizeof a);
+  return a.t_dp;
+}
+
+namespace {
+
+template <int BM, int BN, bool BF, int NT, int EPI, int KG, bool PIPE>
+hipError_t grouped_t(const GroupedLaunch &g, hipStream_t s) {
+  if constexpr (split_lds_bytes<BM, BN, 32, NT, EPI>() <= 160 * 1024) {
+    hipLaunchKernelGGL((cgemm_split_grouped<BM, BN, 32, BF, NT, EPI, KG, PIPE>), dim3(g.blocks),
+                       dim3(kThreads * KG), 0, s, static_cast<const SplitArgs *>(g.d_items),
+                       g.d_starts, g.n_items);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool BF, int NT, int EPI>
+hipError_t grouped_e(const GroupedLaunch &g, hipStream_t s) {
+  const GemmTile &t = g.tile;
+  if (t.bk != 32 || t.bm != 64) return hipErrorInvalidValue;
+  if constexpr (NT == 2) {
+    if (!t.pipe) return hipErrorInvalidValue;
+    if (t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 1, true>(g, s);
+    if (t.bn == 128) return grouped_t<64, 128, BF, NT, EPI, 1, true>(g, s);
+  } else {
+    if (t.kg == 2 && t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 2, false>(g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int EPI>
+hipError_t grouped_p(const GroupedLaunch &g, hipStream_t s) {
+  switch (g.precision) {
+    case GSWMTP_BF16X3: return grouped_e<true, 2, EPI>(g, s);
+    case GSWMTP_FP16X3: return grouped_e<false, 2, EPI>(g, s);
+    case GSWMTP_BF16X6: return grouped_e<true, 3, EPI>(g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_cgemm_split_grouped(const GroupedLaunch &g, hipStream_t s) {
+  if (g.blocks == 0) return hipSuccess;
+  if (g.epi == EPI_GATHER) return grouped_p<EPI_GATHER>(g, s);
+  if (g.epi == EPI_PROJECT) return grouped_p<EPI_PROJECT>(g, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace gswmtp

@@ -369,6 +369,8 @@ GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_spl
 // Grouped launches over the plans of a batch (float32 products).
 struct GroupedLaunch {
   int bm = 64, bn = 64, epi = 0;
+  GemmTile tile;             // split products: the full tile (BK, k-groups, loop)
+  int precision = 0;         // split products: the plans' common precision
   int n_items = 0, blocks = 0;
   void *d_items = nullptr;   // per-plan kernel arguments
   int *d_starts = nullptr;   // [n_items + 1] first block of each item
@@ -377,6 +379,17 @@ size_t cgemm_args_bytes();
 int fill_cgemm_args(const gswmtp_plan *p, bool forward, int bm, int bn, bool honour_done,
                     float *cr, float *ci, void *out);
 hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s);
+// Split-precision products of the batched form: one plan's whole-tile
+// schedule of tile `tl` (no K split) as an item; the grouped launch.
+size_t split_args_bytes();
+int fill_split_args(const gswmtp_plan *p, bool forward, const GemmTile &tl, bool honour_done,
+                    void *out);
+hipError_t launch_cgemm_split_grouped(const GroupedLaunch &g, hipStream_t s);
+// Split-precision scatter of the batched form.
+size_t scatter_split_args_bytes();
+int fill_scatter_split_args(const gswmtp_plan *p, void *out);
+hipError_t launch_scatter_split_grouped(const void *items, const int *starts, int n, int blocks,
+                                        int precision, hipStream_t s);
 // Focus update: one workgroup of kUpdThreads holds up to kUpdRegFociMax foci
 // in registers; more foci take the three-launch form over
 // update_workgroups(nf) workgroups.

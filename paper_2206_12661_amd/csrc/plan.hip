@@ -1013,7 +1013,9 @@ void carve_pool1(Carver &c, Bufs &b, const gswmtp_plan *p) {
   b.wc_r = c.take<float>(Ucr * Cp); b.wc_i = c.take<float>(Ucr * Cp);
   b.amp = c.take<float>(Rp * Cp);
   b.p_r = c.take<float>(f32 * Rp * Cp); b.p_i = c.take<float>(f32 * Rp * Cp);
-  b.gpart = c.take<float>(2 * (size_t)(Cp / p->sched_fwd.tile.bn) * nf);
+  // gather partials: one per forward column tile and focus, sized for the
+  // narrowest tile (64 columns) so that a batch may run any tile width
+  b.gpart = c.take<float>(2 * (size_t)(Cp / 64) * nf);
   b.s_r = c.take<float>(f32 * Urp * Cp); b.s_i = c.take<float>(f32 * Urp * Cp);
   b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
   b.part = c.take<float>(part_floats);
