@@ -59,9 +59,10 @@ __device__ __forceinline__ int swz(int row) {
   return ((row >> 1) & 1) ^ (((row >> 2) & 1) << 1) ^ ((row >> 3) & 1);
 }
 
-template <int BM, int BN, int BK, int NT, int EPI>
+template <int BM, int BN, int BK, int NT, int EPI, int PIPE = 0>
 constexpr int split_lds_bytes() {
-  constexpr int ops = 2 * 2 * NT * (BM + BN) * (BK / 8) * 16;
+  // two stages of every operand plane held in LDS (the direct loop: A only)
+  constexpr int ops = 2 * 2 * NT * (BM + (PIPE == 2 ? 0 : BN)) * (BK / 8) * 16;
   constexpr int tr = EPI == EPI_PROJECT   ? 2 * NT * BN * (BM + 8) * 2
                      : EPI == EPI_GATHER ? gather_lds_bytes<BM, BN>()
                                          : 0;
@@ -123,29 +124,44 @@ __device__ __forceinline__ void load_frags(const u4 *qa, const u4 *qb, int ks, i
 
 // The MFMAs of one k-step: term pairs (ta, tb) with ta + tb < NT, small
 // terms first; -Ai by flipping the sign bits of the imaginary A terms.
+template <int MB, int NB, bool BF, int NT>
+__device__ __forceinline__ void mma_ab(const u4 (&fa)[MB][2 * NT], const u4 (&fb)[NB][2 * NT],
+                                       v16f (&accR)[MB][NB], v16f (&accI)[MB][NB]) {
+  u4 na[MB][NT];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int q = 0; q < NT; ++q) na[i][q] = fa[i][NT + q] ^ 0x80008000u;
+  // Each accumulator takes its products in the same order (per term pair:
+  // real part Ar Br then -Ai Bi, imaginary part Ar Bi then Ai Br); the
+  // accumulators are interleaved so that consecutive MFMAs are independent.
+#pragma unroll
+  for (int s = NT - 1; s >= 0; --s)
+#pragma unroll
+    for (int ta = 0; ta <= s; ++ta) {
+      const int tb = s - ta;
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accR[i][j] = mfma16<BF>(fa[i][ta], fb[j][tb], accR[i][j]);
+          accI[i][j] = mfma16<BF>(fa[i][ta], fb[j][NT + tb], accI[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accR[i][j] = mfma16<BF>(na[i][ta], fb[j][NT + tb], accR[i][j]);
+          accI[i][j] = mfma16<BF>(fa[i][NT + ta], fb[j][tb], accI[i][j]);
+        }
+    }
+}
+
 template <int BM, int BN, bool BF, int NT>
 __device__ __forceinline__ void mma_frags(const Frags<BM, BN, NT> &f,
                                           v16f (&accR)[BM / 64][BN / 64],
                                           v16f (&accI)[BM / 64][BN / 64]) {
-  constexpr int MB = BM / 64, NB = BN / 64;
-#pragma unroll
-  for (int i = 0; i < MB; ++i) {
-    u4 na[NT];
-#pragma unroll
-    for (int q = 0; q < NT; ++q) na[q] = f.a[i][NT + q] ^ 0x80008000u;
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int s = NT - 1; s >= 0; --s)
-#pragma unroll
-        for (int ta = 0; ta <= s; ++ta) {
-          const int tb = s - ta;
-          accR[i][j] = mfma16<BF>(f.a[i][ta], f.b[j][tb], accR[i][j]);
-          accR[i][j] = mfma16<BF>(na[ta], f.b[j][NT + tb], accR[i][j]);
-          accI[i][j] = mfma16<BF>(f.a[i][ta], f.b[j][NT + tb], accI[i][j]);
-          accI[i][j] = mfma16<BF>(f.a[i][NT + ta], f.b[j][tb], accI[i][j]);
-        }
-  }
+  mma_ab<BM / 64, BN / 64, BF, NT>(f.a, f.b, accR, accI);
 }
 
 // Scheduling requests for the pipelined loop (instruction classes of
@@ -166,6 +182,16 @@ __device__ __forceinline__ void sched_write_mfma() {
     __builtin_amdgcn_sched_group_barrier(0x200, W, 0);
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
     sched_write_mfma<N - 1, W>();
+  }
+}
+
+// N pairs of (one VMEM read, one MFMA).
+template <int N>
+__device__ __forceinline__ void sched_vmem_mfma() {
+  if constexpr (N > 0) {
+    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    sched_vmem_mfma<N - 1>();
   }
 }
 
@@ -204,18 +230,145 @@ __device__ __forceinline__ void stage_mma(const u4 *qa, const u4 *qb,
 // into f0 while f1's MFMAs run; then store stage S + 2 (held in registers
 // since two stages ago) into the buffer just left and issue the loads of
 // stage S + 4.
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
 constexpr int split_lds_u4() {
-  return (split_lds_bytes<BM, BN, BK, NT, EPI>() + 15) / 16;
+  return (split_lds_bytes<BM, BN, BK, NT, EPI, PIPE>() + 15) / 16;
+}
+
+// The direct loop (two terms, 64 x 128 tiles): the four waves side by side
+// along N, each owning BN/4 rows of B^T, which it loads straight from HBM
+// into its MFMA fragment registers four stages ahead (no two waves read the
+// same B row, so B needs no LDS); A is shared through two LDS stages as in
+// the pipelined loop.  Per stage S (LDS buffer S & 1, B register set S % 4,
+// A fragments of k-step 0 already in f0): read A's k-step 1 into f1 while
+// f0's MFMAs run; one barrier; read stage S + 1's k-step 0 into f0 while
+// f1's MFMAs run; store stage S + 2 of A (in registers since two stages ago)
+// into the buffer just left and issue the loads of stage S + 4 of A and B.
+// Returns false when the done flag stops the product.
+template <int BM, int BK, int NT>
+__device__ __forceinline__ void load_fa(const u4 *qa, int ks, int l32, int h,
+                                        u4 (&fa)[BM / 32][2 * NT]) {
+  constexpr int CH = BK / 8;
+#pragma unroll
+  for (int i = 0; i < BM / 32; ++i) {
+    const int row = i * 32 + l32;
+#pragma unroll
+    for (int pl = 0; pl < 2 * NT; ++pl)
+      fa[i][pl] = qa[(pl * BM + row) * CH + ((2 * ks + h) ^ swz<CH>(row))];
+  }
+}
+
+template <int BM, int BN, int BK, bool BF, int NT>
+__device__ __forceinline__ bool direct_loop(const SplitArgs &a, int m0, int n0, int kb, int ke,
+                                            int tid, u4 *lds, v16f (&accR)[BM / 32][1],
+                                            v16f (&accI)[BM / 32][1]) {
+  using L = WaveLayout<BM, BN, true>;
+  constexpr int MB = L::MB, PL = 2 * NT, KS = BK / kKStep, CH = BK / 8;
+  static_assert(L::NB == 1 && KS == 2 && BK == kKB, "direct loop: 32 B rows per wave, one k-block per stage");
+  constexpr int LA = PL * BM * CH, NA = LA / kThreads;
+  static_assert(LA % kThreads == 0, "tile/thread mismatch");
+  constexpr int SA_SZ = LA;
+  u4 *sA = lds;
+  const int lane = tid & 63, wave = tid >> 6, l32 = lane & 31, h = lane >> 5;
+  const unsigned short *ga[NA];
+  int la[NA];
+#pragma unroll
+  for (int s = 0; s < NA; ++s) {
+    const int id = tid + kThreads * s;
+    const int c = id % CH, row = (id / CH) % BM, plane = id / (CH * BM);
+    ga[s] = a.a + (size_t)plane * a.a_plane + (size_t)(m0 + row) * kKB + 8 * c;
+    la[s] = (plane * BM + row) * CH + (c ^ swz<CH>(row));
+  }
+  // B^T row of lane (l32, h): n0 + WTN wave + l32; it holds k 8h .. 8h + 7 of each k-step
+  const unsigned short *gb = a.b + (size_t)(n0 + L::WTN * wave + l32) * kKB + 8 * h;
+  if (kb >= ke) return !(a.done && *a.done);
+  const int last = ke - 1;
+  u4 ra0[NA], ra1[NA];
+  u4 bq0[KS][1][PL], bq1[KS][1][PL], bq2[KS][1][PL], bq3[KS][1][PL];
+#define D_LOAD_A(RA, KT)                                                                   \
+  do {                                                                                     \
+    const size_t k_ = (size_t)(KT) * BK;                                                   \
+    const size_t o_ = k_ / kKB * ((size_t)a.M * kKB) + k_ % kKB;                           \
+    _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) RA[s_] =                             \
+        *reinterpret_cast<const u4 *>(ga[s_] + o_);                                        \
+  } while (0)
+#define D_LOAD_B(BQ, KT)                                                                   \
+  do {                                                                                     \
+    _Pragma("unroll") for (int ks_ = 0; ks_ < KS; ++ks_) {                                 \
+      const size_t k_ = (size_t)(KT) * BK + ks_ * kKStep;                                  \
+      const size_t o_ = k_ / kKB * ((size_t)a.N * kKB) + k_ % kKB;                         \
+      _Pragma("unroll") for (int pl_ = 0; pl_ < PL; ++pl_) BQ[ks_][0][pl_] =               \
+          *reinterpret_cast<const u4 *>(gb + pl_ * a.b_plane + o_);                        \
+    }                                                                                      \
+  } while (0)
+#define D_STORE_A(RA, BUF)                                                                 \
+  do {                                                                                     \
+    _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) sA[(BUF) * SA_SZ + la[s_]] = RA[s_]; \
+  } while (0)
+  D_LOAD_A(ra0, kb);
+  D_LOAD_A(ra1, kb + 1 < last ? kb + 1 : last);
+  D_LOAD_B(bq0, kb);
+  D_LOAD_B(bq1, kb + 1 < last ? kb + 1 : last);
+  D_LOAD_B(bq2, kb + 2 < last ? kb + 2 : last);
+  D_LOAD_B(bq3, kb + 3 < last ? kb + 3 : last);
+  const int stop = a.done ? *a.done : 0;
+  asm volatile("" ::: "memory");
+  if (stop) return false;
+  D_STORE_A(ra0, 0);
+  D_LOAD_A(ra0, kb + 2 < last ? kb + 2 : last);
+  D_STORE_A(ra1, 1);
+  D_LOAD_A(ra1, kb + 3 < last ? kb + 3 : last);
+  __syncthreads();
+  u4 f0[MB][PL], f1[MB][PL];
+  load_fa<BM, BK, NT>(sA, 0, l32, h, f0);
+  // per k-step: NR fragment reads, NM MFMAs; per stage NA stores and NV loads
+  constexpr int NR = MB * PL, NM = MB * 2 * NT * (NT + 1), NV = NA + KS * PL;
+  static_assert(NM >= NR + NA, "interleave pattern");
+  constexpr int NVM = NV < NM - NR - NA ? NV : NM - NR - NA;   // (load, MFMA) pairs
+#define D_STEP(BUF, RA, BQ, S)                                                            \
+  do {                                                                                    \
+    load_fa<BM, BK, NT>(sA + (BUF) * SA_SZ, 1, l32, h, f1);                               \
+    mma_ab<MB, 1, BF, NT>(f0, BQ[0], accR, accI);                                         \
+    sched_read_mfma<NR>();                                                                \
+    __builtin_amdgcn_sched_group_barrier(0x008, NM - NR, 0);                              \
+    __syncthreads();                                                                      \
+    load_fa<BM, BK, NT>(sA + (1 - (BUF)) * SA_SZ, 0, l32, h, f0);                         \
+    mma_ab<MB, 1, BF, NT>(f1, BQ[1], accR, accI);                                         \
+    D_STORE_A(RA, BUF);                                                                   \
+    D_LOAD_A(RA, (S) + 4 < last ? (S) + 4 : last);                                        \
+    D_LOAD_B(BQ, (S) + 4 < last ? (S) + 4 : last);                                        \
+    sched_read_mfma<NR>();                                                                \
+    sched_write_mfma<NA, 1>();                                                            \
+    sched_vmem_mfma<NVM>();                                                               \
+    if constexpr (NM - NR - NA - NVM > 0)                                                 \
+      __builtin_amdgcn_sched_group_barrier(0x008, NM - NR - NA - NVM, 0);                 \
+    if constexpr (NV - NVM > 0) __builtin_amdgcn_sched_group_barrier(0x020, NV - NVM, 0); \
+  } while (0)
+  int kt = kb;
+  for (; kt + 3 < ke; kt += 4) {
+    D_STEP(0, ra0, bq0, kt);
+    D_STEP(1, ra1, bq1, kt + 1);
+    D_STEP(0, ra0, bq2, kt + 2);
+    D_STEP(1, ra1, bq3, kt + 3);
+  }
+  if (kt < ke) D_STEP(0, ra0, bq0, kt);
+  if (kt + 1 < ke) D_STEP(1, ra1, bq1, kt + 1);
+  if (kt + 2 < ke) D_STEP(0, ra0, bq2, kt + 2);
+#undef D_STEP
+#undef D_LOAD_A
+#undef D_LOAD_B
+#undef D_STORE_A
+  return true;
 }
 
 // The product for block `bid` of one schedule (whole tile, K chunk or tail
 // reduction), LDS `lds` of split_lds_u4 entries.
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
 __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int bid, u4 *lds) {
   constexpr int NTH = kThreads * KG;
-  constexpr int WTM = BM / 2, WTN = BN / 2;
-  constexpr int MB = WTM / 32, NB = WTN / 32;
+  using L = WaveLayout<BM, BN, PIPE == 2>;
+  constexpr int WTM = L::WTM, WTN = L::WTN;
+  constexpr int MB = L::MB, NB = L::NB;
   constexpr int PL = 2 * NT;                     // planes per operand
   constexpr int KS = BK / kKStep;                // MFMA k-steps per stage
   constexpr int CH = BK / 8;                     // 16-byte chunks per row and stage
@@ -251,7 +404,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
   const int m0 = (t % a.tiles_m) * BM;
   const int n0 = (t / a.tiles_m) * BN;
   const int lane = tid & 63, wave = (tid >> 6) & 3, kg = tid >> 8;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = L::wm(wave), wn = L::wn(wave);
   const int l32 = lane & 31, h = lane >> 5;
 
   v16f accR[MB][NB], accI[MB][NB];
@@ -263,6 +416,11 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
       accI[i][j] = v16f{0};
     }
 
+  if constexpr (PIPE == 2) {
+    static_assert(KG == 1, "direct loop: one k-group");
+    if (!direct_loop<BM, BN, BK, BF, NT>(a, m0, n0, kb, ke, tid, lds, accR, accI)) return;
+    __syncthreads();   // the epilogues reuse the operand buffers
+  } else {
   // staging: chunk id = (plane * rows + row) * CH + c (16 bytes, 8 k values)
   const unsigned short *ga[NA];
   const unsigned short *gb[NBL];
@@ -314,7 +472,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
     const int stop = a.done ? *a.done : 0;
     asm volatile("" ::: "memory");
     if (stop) return;
-    if constexpr (PIPE) {
+    if constexpr (PIPE == 1) {
       static_assert(KG == 1 && BK == 2 * kKStep, "pipelined loop: one group, two k-steps");
       STORE_STAGE(r0a, r0b, 0);
       LOAD_STAGE(r0a, r0b, kb + 2 < last ? kb + 2 : last);
@@ -419,6 +577,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
     if (kg == 1) return;   // tail-reduction blocks: group 0 alone
 #undef LOAD_STAGE
 #undef STORE_STAGE
+  }
 
   constexpr int unit = 2 * MB * NB * 16 * kThreads;
   if (a.phase == 0 && tail >= 0) {
@@ -457,7 +616,8 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
 
   // epilogue; accumulator item r of lane (l32, h): row 8 (r/4) + 4 h + r % 4, column l32
   if constexpr (EPI == EPI_GATHER) {
-    gather_epilogue<BM, BN>(a.g, accR, accI, reinterpret_cast<float *>(lds), m0, n0, tid);
+    gather_epilogue<BM, BN, PIPE == 2>(a.g, accR, accI, reinterpret_cast<float *>(lds), m0, n0,
+                                       tid);
   } else if constexpr (EPI == EPI_STORE) {
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -520,7 +680,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
   }
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
 __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
   __shared__ u4 lds[split_lds_u4<BM, BN, BK, BF, NT, EPI, KG, PIPE>()];
   cgemm_split_body<BM, BN, BK, BF, NT, EPI, KG, PIPE>(a, blockIdx.x, lds);
@@ -529,7 +689,7 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
 // Grouped launch (batched form): the concatenated whole-tile schedules of
 // several plans' products; block b belongs to the item whose start offset is
 // the largest one <= b (binary search) and runs its local block b - start.
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
 __global__ __launch_bounds__(kThreads * KG) void cgemm_split_grouped(const SplitArgs *items,
                                                                      const int *starts, int n) {
   __shared__ u4 lds[split_lds_u4<BM, BN, BK, BF, NT, EPI, KG, PIPE>()];
@@ -548,9 +708,9 @@ __global__ __launch_bounds__(kThreads * KG) void cgemm_split_grouped(const Split
 // planes of P^T (four consecutive rows of one column per thread: one 8-byte
 // store per plane).  Block (tail, g) covers slots r = 4g .. 4g + 3 of every
 // (i, j) block of the tile.
-template <int BM, int BN, bool BF, int NT>
+template <int BM, int BN, bool BF, int NT, bool COLS>
 __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a) {
-  constexpr int MB = BM / 64, NB = BN / 64;
+  constexpr int MB = WaveLayout<BM, BN, COLS>::MB, NB = WaveLayout<BM, BN, COLS>::NB;
   constexpr int unit = 2 * MB * NB * 16 * kThreads;
   const int tail = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
   const int t = a.t_dp + tail;
@@ -573,7 +733,7 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
       }
       if (a.done && *a.done) return;   // read after the partial sums
       int m, n;
-      tile_slot_pos<BM, BN>(tid, i, j, 4 * g, m, n);   // rows m .. m + 3, column n
+      tile_slot_pos<BM, BN, COLS>(tid, i, j, 4 * g, m, n);   // rows m .. m + 3, column n
       unsigned short tr[NT][4], ti[NT][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -595,16 +755,16 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
     }
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, bool PIPE>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
 hipError_t launch_t(const SplitArgs &args, int grid, hipStream_t s) {
   hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI, KG, PIPE>), dim3(grid),
                      dim3(kThreads * KG), 0, s, args);
   return hipGetLastError();
 }
 
-template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG = 1, bool PIPE = false>
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG = 1, int PIPE = 0>
 hipError_t launch_fit(const SplitArgs &args, int grid, hipStream_t s) {
-  if constexpr (split_lds_bytes<BM, BN, BK, NT, EPI>() <= 160 * 1024)
+  if constexpr (split_lds_bytes<BM, BN, BK, NT, EPI, PIPE>() <= 160 * 1024)
     return launch_t<BM, BN, BK, BF, NT, EPI, KG, PIPE>(args, grid, s);
   return hipErrorInvalidValue;
 }
@@ -612,12 +772,13 @@ hipError_t launch_fit(const SplitArgs &args, int grid, hipStream_t s) {
 template <bool BF, int NT>
 hipError_t launch_tail_t(const GemmTile &tl, const SplitArgs &a, int n_tail, hipStream_t s) {
   const dim3 g(n_tail, 4);
-#define TAIL(BM, BN) \
-  hipLaunchKernelGGL((cgemm_tail_project_split<BM, BN, BF, NT>), g, dim3(kThreads), 0, s, a)
-  if (tl.bm == 64 && tl.bn == 64) TAIL(64, 64);
-  else if (tl.bm == 64 && tl.bn == 128) TAIL(64, 128);
-  else if (tl.bm == 128 && tl.bn == 64) TAIL(128, 64);
-  else if (tl.bm == 128 && tl.bn == 128) TAIL(128, 128);
+#define TAIL(BM, BN, COLS) \
+  hipLaunchKernelGGL((cgemm_tail_project_split<BM, BN, BF, NT, COLS>), g, dim3(kThreads), 0, s, a)
+  if (tl.pipe == 2 && tl.bm == 64 && tl.bn == 128) TAIL(64, 128, true);
+  else if (tl.bm == 64 && tl.bn == 64) TAIL(64, 64, false);
+  else if (tl.bm == 64 && tl.bn == 128) TAIL(64, 128, false);
+  else if (tl.bm == 128 && tl.bn == 64) TAIL(128, 64, false);
+  else if (tl.bm == 128 && tl.bn == 128) TAIL(128, 128, false);
   else return hipErrorInvalidValue;
 #undef TAIL
   return hipGetLastError();
@@ -637,16 +798,19 @@ template <bool BF, int NT, int EPI>
 hipError_t launch_e(const GemmTile &tl, const SplitArgs &args, int grid, hipStream_t s) {
   if (tl.bk == 32) {
     if (tl.bm == 64 && tl.bn == 64) {
-      if (tl.pipe) return launch_fit<64, 64, 32, BF, NT, EPI, 1, true>(args, grid, s);
+      if (tl.pipe) return launch_fit<64, 64, 32, BF, NT, EPI, 1, 1>(args, grid, s);
       return tl.kg == 2 ? launch_fit<64, 64, 32, BF, NT, EPI, 2>(args, grid, s)
                         : launch_fit<64, 64, 32, BF, NT, EPI>(args, grid, s);
     }
     if (tl.bm == 128 && tl.bn == 64)
-      return tl.pipe ? launch_fit<128, 64, 32, BF, NT, EPI, 1, true>(args, grid, s)
+      return tl.pipe ? launch_fit<128, 64, 32, BF, NT, EPI, 1, 1>(args, grid, s)
                      : launch_fit<128, 64, 32, BF, NT, EPI>(args, grid, s);
-    if (tl.bm == 64 && tl.bn == 128)
-      return tl.pipe ? launch_fit<64, 128, 32, BF, NT, EPI, 1, true>(args, grid, s)
+    if (tl.bm == 64 && tl.bn == 128) {
+      if constexpr (NT == 2)
+        if (tl.pipe == 2) return launch_fit<64, 128, 32, BF, NT, EPI, 1, 2>(args, grid, s);
+      return tl.pipe ? launch_fit<64, 128, 32, BF, NT, EPI, 1, 1>(args, grid, s)
                      : launch_fit<64, 128, 32, BF, NT, EPI>(args, grid, s);
+    }
     if (tl.bm == 128 && tl.bn == 128) return launch_fit<128, 128, 32, BF, NT, EPI>(args, grid, s);
   } else if (tl.bk == 16) {
     if (tl.bm == 64 && tl.bn == 64) return launch_fit<64, 64, 16, BF, NT, EPI>(args, grid, s);
@@ -757,9 +921,9 @@ int fill_split_args(const gswmtp_plan *p, bool forward, const GemmTile &tl, bool
 
 namespace {
 
-template <int BM, int BN, bool BF, int NT, int EPI, int KG, bool PIPE>
+template <int BM, int BN, bool BF, int NT, int EPI, int KG, int PIPE>
 hipError_t grouped_t(const GroupedLaunch &g, hipStream_t s) {
-  if constexpr (split_lds_bytes<BM, BN, 32, NT, EPI>() <= 160 * 1024) {
+  if constexpr (split_lds_bytes<BM, BN, 32, NT, EPI, PIPE>() <= 160 * 1024) {
     hipLaunchKernelGGL((cgemm_split_grouped<BM, BN, 32, BF, NT, EPI, KG, PIPE>), dim3(g.blocks),
                        dim3(kThreads * KG), 0, s, static_cast<const SplitArgs *>(g.d_items),
                        g.d_starts, g.n_items);
@@ -774,10 +938,12 @@ hipError_t grouped_e(const GroupedLaunch &g, hipStream_t s) {
   if (t.bk != 32 || t.bm != 64) return hipErrorInvalidValue;
   if constexpr (NT == 2) {
     if (!t.pipe) return hipErrorInvalidValue;
-    if (t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 1, true>(g, s);
-    if (t.bn == 128) return grouped_t<64, 128, BF, NT, EPI, 1, true>(g, s);
+    if (t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 1, 1>(g, s);
+    if (t.bn == 128)
+      return t.pipe == 2 ? grouped_t<64, 128, BF, NT, EPI, 1, 2>(g, s)
+                         : grouped_t<64, 128, BF, NT, EPI, 1, 1>(g, s);
   } else {
-    if (t.kg == 2 && t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 2, false>(g, s);
+    if (t.kg == 2 && t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 2, 0>(g, s);
   }
   return hipErrorInvalidValue;
 }

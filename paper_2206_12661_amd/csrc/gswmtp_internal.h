@@ -174,19 +174,32 @@ __device__ __forceinline__ void project_amp(float cr, float ci, float am, float 
   }
 }
 
-// Position in the BM x BN tile of partial-sum slot (i, j, r) of thread tid
-// of a four-wave product workgroup (wave quadrants of (BM/2) x (BN/2), 32x32
-// MFMA blocks; item r of lane (l32, h) is row 8 (r/4) + 4 h + r % 4, column l32).
-template <int BM, int BN>
+// Placement of the four waves of a product workgroup: 2 x 2 waves of
+// BM/2 x BN/2 each, or (COLS, the loop that reads B straight into registers)
+// 1 x 4 waves of BM x BN/4, so that no two waves share a B row.  MB x NB
+// 32x32 MFMA blocks per wave; item r of lane (l32, h) of a block is row
+// 8 (r/4) + 4 h + r % 4, column l32.
+template <int BM, int BN, bool COLS = false>
+struct WaveLayout {
+  static constexpr int WTM = COLS ? BM : BM / 2, WTN = COLS ? BN / 4 : BN / 2;
+  static constexpr int MB = WTM / 32, NB = WTN / 32;
+  __device__ static int wm(int wave) { return COLS ? 0 : (wave & 1); }
+  __device__ static int wn(int wave) { return COLS ? wave : (wave >> 1); }
+};
+
+// Position in the BM x BN tile of partial-sum slot (i, j, r) of thread tid.
+template <int BM, int BN, bool COLS = false>
 __device__ __forceinline__ void tile_slot_pos(int tid, int i, int j, int r, int &m, int &n) {
+  using L = WaveLayout<BM, BN, COLS>;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1, l32 = lane & 31, h = lane >> 5;
-  m = wm * (BM / 2) + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-  n = wn * (BN / 2) + j * 32 + l32;
+  const int l32 = lane & 31, h = lane >> 5;
+  m = L::wm(wave) * L::WTM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+  n = L::wn(wave) * L::WTN + j * 32 + l32;
 }
 
 // complex tile M x N, K per stage; split products: kg k-groups of four waves,
-// pipe: software-pipelined fragment reads (one k-group)
+// pipe: 1 software-pipelined fragment reads (one k-group), 2 the same with
+// the B operand read straight into registers (1 x 4 waves, two terms)
 struct GemmTile { int bm = 64, bn = 64, bk = 16, kg = 1, pipe = 0; };
 
 // Launch schedule of one complex product: t_dp whole tiles, then n_tail tiles
@@ -219,14 +232,16 @@ struct GatherCtx {
 // (per-lane partial sums, fixed xor-shuffle tree) and writes it as partial
 // number n0 / BN of that focus.  Accumulator item r of lane (l32, h) of a
 // 32x32 block holds row 8 (r/4) + 4 h + r % 4, column l32.
-template <int BM, int BN>
-__device__ __forceinline__ void gather_epilogue(const GatherCtx &g,
-                                                const gsw_v16f (&accR)[BM / 64][BN / 64],
-                                                const gsw_v16f (&accI)[BM / 64][BN / 64],
-                                                float *lds, int m0, int n0, int tid) {
-  constexpr int MB = BM / 64, NB = BN / 64, WTM = BM / 2, WTN = BN / 2, LD = BN + 1;
+template <int BM, int BN, bool COLS = false>
+__device__ __forceinline__ void gather_epilogue(
+    const GatherCtx &g,
+    const gsw_v16f (&accR)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
+    const gsw_v16f (&accI)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
+    float *lds, int m0, int n0, int tid) {
+  using L = WaveLayout<BM, BN, COLS>;
+  constexpr int MB = L::MB, NB = L::NB, WTM = L::WTM, WTN = L::WTN, LD = BN + 1;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1, l32 = lane & 31, h = lane >> 5;
+  const int wm = L::wm(wave), wn = L::wn(wave), l32 = lane & 31, h = lane >> 5;
   float *tr = lds, *ti = lds + BM * LD;
   __syncthreads();   // operand stages are no longer read
 #pragma unroll

@@ -751,13 +751,14 @@ void free_plan(gswmtp_plan *p) {
 // for split modes; other tiles use the plain loop).
 GemmTile choose_tile(int M, int N, bool split, int terms = 2, int cus = 256) {
   GemmTile t{64, 64, split ? 32 : 16, 1, 0};
+  // three-term operands hold too many fragment registers to pipeline them at
+  // two workgroups per CU: two k-groups instead; two-term 64 x 128 tiles take
+  // the direct loop (B straight into registers, ~3% faster than pipe there)
+  const char *lp = std::getenv("GSWMTP_SPLIT_LOOP");
+  const std::string v = lp ? lp : terms > 2 ? "kg2" : "direct";
   if (split) {
-    // three-term operands hold too many fragment registers to pipeline
-    // them at two workgroups per CU: two k-groups instead
-    const char *lp = std::getenv("GSWMTP_SPLIT_LOOP");
-    const std::string v = lp ? lp : terms > 2 ? "kg2" : "pipe";
     t.kg = v == "kg2" ? 2 : 1;
-    t.pipe = v == "pipe" ? 1 : 0;
+    t.pipe = v == "pipe" || v == "direct" ? 1 : 0;
     // 64 x 128 tiles (one workgroup per CU, a quarter fewer LDS and L2 bytes
     // per MFMA) when they fill at least half of the CUs in one round and do
     // not spill into a second
@@ -777,6 +778,9 @@ GemmTile choose_tile(int M, int N, bool split, int terms = 2, int cus = 256) {
       if (t.bm != 64 || t.bn != 64) t.kg = 1;
     }
   }
+  if (split && v == "direct" && t.pipe && t.bm == 64 && t.bn == 128 && t.bk == 32 &&
+      terms == 2)
+    t.pipe = 2;
   return t;
 }
 
