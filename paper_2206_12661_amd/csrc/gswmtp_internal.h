@@ -160,7 +160,10 @@ __device__ __forceinline__ float join_terms(bool bf, int nt, const unsigned shor
 // Phase-only projection of one back-propagated sample onto the amplitude
 // constraint: A c / |c|, phasor 1 where c = 0, 0 outside the aperture.
 __device__ __forceinline__ void project_amp(float cr, float ci, float am, float &pr, float &pi) {
-  const float mag2 = cr * cr + ci * ci;
+  // one explicit fma, so every kernel that projects (the product epilogues
+  // and the split-K tail kernels) rounds |c|^2 alike; left to the compiler,
+  // the contraction may differ between kernels
+  const float mag2 = fmaf(cr, cr, ci * ci);
   pr = 0.f;
   pi = 0.f;
   if (am > 0.f) {
