@@ -96,10 +96,17 @@ def test_fp16_amplitude_scaling(g, scale):
     assert np.all(np.isfinite(phi))
 
 
+def _large_case(name):
+    if name == "config3":
+        return synth_ofa.config3()
+    return synth_ofa.random_case(47, 512, 2048, 1060)
+
+
 @pytest.mark.parametrize("mode", MODES)
-def test_full_size_forward_split(g, mode):
-    h = synth_ofa.config3()
-    announce(f"full size forward {mode}")
+@pytest.mark.parametrize("case", ["config3", "512x2048-1060"])
+def test_full_size_forward_split(g, mode, case):
+    h = _large_case(case)
+    announce(f"large forward {case} {mode}")
     with g.Plan(h, precision=mode) as p:
         th = p.foci_field()
     ref = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
@@ -109,14 +116,19 @@ def test_full_size_forward_split(g, mode):
 
 
 @pytest.mark.parametrize("mode", ["bf16x3", "fp16x3"])
-def test_full_size_pass_split(g, mode):
-    """One split-precision pass at the benchmark size (1152 x 1920, 1000
-    foci: the 64 x 128 forward tiles and the 64 x 64 adjoint with its split-K
-    tail) from an identical state after 5 float32 passes; the weights at the
-    mode's bar times the oracle's kappa (the weight update's first-order
-    gain), the new foci field times kappa and c_E (the projection's)."""
-    h = synth_ofa.config3()
-    announce(f"full size pass {mode}")
+@pytest.mark.parametrize("case", ["config3", "512x2048-1060"])
+def test_full_size_pass_split(g, mode, case):
+    """One split-precision pass at a large size from an identical state after
+    5 float32 passes; the weights at the mode's bar times the oracle's kappa
+    (the weight update's first-order gain), the new foci field times kappa
+    and c_E (the projection's).  The benchmark size (1152 x 1920, 1000 foci)
+    runs the 64 x 128 forward tiles on the direct loop and the 64 x 64
+    adjoint with its split-K tail; 512 x 2048 with 1060 foci runs 544 forward
+    tiles of 64 x 64 with 32 split-K tail tiles (gather epilogue in the tail
+    launch) and the adjoint's 128 tiles of 64 x 128 on the direct loop, every
+    one split in two K chunks (the tail kernel of the column-wave layout)."""
+    h = _large_case(case)
+    announce(f"large pass {case} {mode}")
     with g.Plan(h) as p:
         p.iterate(5)
         phi_k, w_k, _ = p.state()
