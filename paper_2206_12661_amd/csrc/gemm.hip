@@ -397,6 +397,8 @@ GatherCtx gather_ctx(const gswmtp_plan *p) {
   g.foci = p->b.csr_foci;
   g.ir = p->d.axis == 0 ? p->b.iy : p->b.ix;
   g.ic = p->d.axis == 0 ? p->b.ix : p->b.iy;
+  g.cir = p->b.csr_ir;
+  g.cic = p->b.csr_ic;
   g.wcr = p->b.wc_r;
   g.wci = p->b.wc_i;
   g.nf = p->d.nf;

@@ -123,15 +123,18 @@ __device__ __forceinline__ void load_frags(const u4 *qa, const u4 *qb, int ks, i
 }
 
 // The MFMAs of one k-step: term pairs (ta, tb) with ta + tb < NT, small
-// terms first; -Ai by flipping the sign bits of the imaginary A terms.
-template <int MB, int NB, bool BF, int NT>
+// terms first; -Ai Bi by flipping the sign bits of the imaginary terms of A (NEGB: of B,
+// for B fragments that sit in registers long before their MFMAs, so the
+// flips never wait on a fresh LDS read); the same products either way.
+template <int MB, int NB, bool BF, int NT, bool NEGB = false>
 __device__ __forceinline__ void mma_ab(const u4 (&fa)[MB][2 * NT], const u4 (&fb)[NB][2 * NT],
                                        v16f (&accR)[MB][NB], v16f (&accI)[MB][NB]) {
-  u4 na[MB][NT];
+  constexpr int NX = NEGB ? NB : MB;
+  u4 nx[NX][NT];
 #pragma unroll
-  for (int i = 0; i < MB; ++i)
+  for (int i = 0; i < NX; ++i)
 #pragma unroll
-    for (int q = 0; q < NT; ++q) na[i][q] = fa[i][NT + q] ^ 0x80008000u;
+    for (int q = 0; q < NT; ++q) nx[i][q] = (NEGB ? fb[i][NT + q] : fa[i][NT + q]) ^ 0x80008000u;
   // Each accumulator takes its products in the same order (per term pair:
   // real part Ar Br then -Ai Bi, imaginary part Ar Bi then Ai Br); the
   // accumulators are interleaved so that consecutive MFMAs are independent.
@@ -151,7 +154,10 @@ __device__ __forceinline__ void mma_ab(const u4 (&fa)[MB][2 * NT], const u4 (&fb
       for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-          accR[i][j] = mfma16<BF>(na[i][ta], fb[j][NT + tb], accR[i][j]);
+          if constexpr (NEGB)
+            accR[i][j] = mfma16<BF>(fa[i][NT + ta], nx[j][tb], accR[i][j]);
+          else
+            accR[i][j] = mfma16<BF>(nx[i][ta], fb[j][NT + tb], accR[i][j]);
           accI[i][j] = mfma16<BF>(fa[i][NT + ta], fb[j][tb], accI[i][j]);
         }
     }
@@ -239,8 +245,9 @@ constexpr int split_lds_u4() {
 // along N, each owning BN/4 rows of B^T, which it loads straight from HBM
 // into its MFMA fragment registers four stages ahead (no two waves read the
 // same B row, so B needs no LDS); A is shared through two LDS stages as in
-// the pipelined loop.  Per stage S (LDS buffer S & 1, B register set S % 4,
-// A fragments of k-step 0 already in f0): read A's k-step 1 into f1 while
+// the pipelined loop (a deeper A prefetch, four stages, measured no
+// faster).  Per stage S (LDS buffer S & 1, B register set S % 4, A
+// fragments of k-step 0 already in f0): read A's k-step 1 into f1 while
 // f0's MFMAs run; one barrier; read stage S + 1's k-step 0 into f0 while
 // f1's MFMAs run; store stage S + 2 of A (in registers since two stages ago)
 // into the buffer just left and issue the loads of stage S + 4 of A and B.
@@ -258,10 +265,10 @@ __device__ __forceinline__ void load_fa(const u4 *qa, int ks, int l32, int h,
   }
 }
 
-template <int BM, int BN, int BK, bool BF, int NT>
+template <int BM, int BN, int BK, bool BF, int NT, bool PRE>
 __device__ __forceinline__ bool direct_loop(const SplitArgs &a, int m0, int n0, int kb, int ke,
                                             int tid, u4 *lds, v16f (&accR)[BM / 32][1],
-                                            v16f (&accI)[BM / 32][1]) {
+                                            v16f (&accI)[BM / 32][1], GatherPre &gp) {
   using L = WaveLayout<BM, BN, true>;
   constexpr int MB = L::MB, PL = 2 * NT, KS = BK / kKStep, CH = BK / 8;
   static_assert(L::NB == 1 && KS == 2 && BK == kKB, "direct loop: 32 B rows per wave, one k-block per stage");
@@ -311,6 +318,7 @@ __device__ __forceinline__ bool direct_loop(const SplitArgs &a, int m0, int n0, 
   D_LOAD_B(bq1, kb + 1 < last ? kb + 1 : last);
   D_LOAD_B(bq2, kb + 2 < last ? kb + 2 : last);
   D_LOAD_B(bq3, kb + 3 < last ? kb + 3 : last);
+  if constexpr (PRE) gather_pre_foci(a.g, m0, tid, gp);   // behind the operand loads
   const int stop = a.done ? *a.done : 0;
   asm volatile("" ::: "memory");
   if (stop) return false;
@@ -328,12 +336,13 @@ __device__ __forceinline__ bool direct_loop(const SplitArgs &a, int m0, int n0, 
 #define D_STEP(BUF, RA, BQ, S)                                                            \
   do {                                                                                    \
     load_fa<BM, BK, NT>(sA + (BUF) * SA_SZ, 1, l32, h, f1);                               \
-    mma_ab<MB, 1, BF, NT>(f0, BQ[0], accR, accI);                                         \
+    mma_ab<MB, 1, BF, NT, true>(f0, BQ[0], accR, accI);                                   \
     sched_read_mfma<NR>();                                                                \
     __builtin_amdgcn_sched_group_barrier(0x008, NM - NR, 0);                              \
     __syncthreads();                                                                      \
+    __builtin_amdgcn_sched_barrier(0);                                                    \
     load_fa<BM, BK, NT>(sA + (1 - (BUF)) * SA_SZ, 0, l32, h, f0);                         \
-    mma_ab<MB, 1, BF, NT>(f1, BQ[1], accR, accI);                                         \
+    mma_ab<MB, 1, BF, NT, true>(f1, BQ[1], accR, accI);                                   \
     D_STORE_A(RA, BUF);                                                                   \
     D_LOAD_A(RA, (S) + 4 < last ? (S) + 4 : last);                                        \
     D_LOAD_B(BQ, (S) + 4 < last ? (S) + 4 : last);                                        \
@@ -343,6 +352,7 @@ __device__ __forceinline__ bool direct_loop(const SplitArgs &a, int m0, int n0, 
     if constexpr (NM - NR - NA - NVM > 0)                                                 \
       __builtin_amdgcn_sched_group_barrier(0x008, NM - NR - NA - NVM, 0);                 \
     if constexpr (NV - NVM > 0) __builtin_amdgcn_sched_group_barrier(0x020, NV - NVM, 0); \
+    __builtin_amdgcn_sched_barrier(0);                                                    \
   } while (0)
   int kt = kb;
   for (; kt + 3 < ke; kt += 4) {
@@ -416,9 +426,30 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
       accI[i][j] = v16f{0};
     }
 
+  // the gather's focus indices: row range now, foci behind the operand loads
+  GatherPre gp;
+  if constexpr (EPI == EPI_GATHER) gather_pre_rows(a.g, m0, BM, gp);
+  // the projection's amplitudes, read now and used after the main loop
+  // (whole tiles only: K-chunk blocks write partials)
+  float ampv[EPI == EPI_PROJECT ? MB : 1][EPI == EPI_PROJECT ? NB : 1][16];
+  if constexpr (EPI == EPI_PROJECT) {
+    if (tail < 0) {
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int ml = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            ampv[i][j][r] = a.amp[(size_t)(m0 + ml) * a.ldc + n0 + wn * WTN + j * 32 + l32];
+          }
+    }
+  }
   if constexpr (PIPE == 2) {
     static_assert(KG == 1, "direct loop: one k-group");
-    if (!direct_loop<BM, BN, BK, BF, NT>(a, m0, n0, kb, ke, tid, lds, accR, accI)) return;
+    if (!direct_loop<BM, BN, BK, BF, NT, EPI == EPI_GATHER>(a, m0, n0, kb, ke, tid, lds, accR,
+                                                             accI, gp))
+      return;
     __syncthreads();   // the epilogues reuse the operand buffers
   } else {
   // staging: chunk id = (plane * rows + row) * CH + c (16 bytes, 8 k values)
@@ -467,6 +498,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
     const int last = ke - 1;
     LOAD_STAGE(r0a, r0b, kb);
     LOAD_STAGE(r1a, r1b, kb + 1 < last ? kb + 1 : last);
+    if constexpr (EPI == EPI_GATHER) gather_pre_foci(a.g, m0, tid, gp);
     // The done flag is read while the first two stages are in flight (the
     // loads are kept above the test), not before them.
     const int stop = a.done ? *a.done : 0;
@@ -496,6 +528,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
     sched_read_mfma<NR>();                                                                     \
     __builtin_amdgcn_sched_group_barrier(0x008, NM - NR, 0);                                   \
     __syncthreads();                                                                           \
+    __builtin_amdgcn_sched_barrier(0);                                                         \
     load_frags<BM, BN, BK, NT>(sA + (1 - (BUF)) * SA_SZ, sB + (1 - (BUF)) * SB_SZ, 0, wm, wn,   \
                                l32, h, f0);                                                    \
     mma_frags<BM, BN, BF, NT>(f1, accR, accI);                                                 \
@@ -506,6 +539,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
     if constexpr (NM - NR - NW > 0) __builtin_amdgcn_sched_group_barrier(0x008, NM - NR - NW, 0); \
     if constexpr (NS - NW > 0) __builtin_amdgcn_sched_group_barrier(0x200, NS - NW, 0);       \
     __builtin_amdgcn_sched_group_barrier(0x020, NS, 0);                                        \
+    __builtin_amdgcn_sched_barrier(0);                                                         \
   } while (0)
       int kt = kb;
       for (; kt + 1 < ke; kt += 2) {
@@ -617,7 +651,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
   // epilogue; accumulator item r of lane (l32, h): row 8 (r/4) + 4 h + r % 4, column l32
   if constexpr (EPI == EPI_GATHER) {
     gather_epilogue<BM, BN, PIPE == 2>(a.g, accR, accI, reinterpret_cast<float *>(lds), m0, n0,
-                                       tid);
+                                       tid, gp);
   } else if constexpr (EPI == EPI_STORE) {
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -650,7 +684,9 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
           for (int q = 0; q < 4; ++q) {
             const float cr = accR[i][j][4 * g + q], ci = accI[i][j][4 * g + q];
             float pr, pi;
-            project_amp(cr, ci, a.amp[(size_t)(m0 + ml + q) * a.ldc + n0 + nl], pr, pi);
+            const float am = tail < 0 ? ampv[i][j][4 * g + q]
+                                      : a.amp[(size_t)(m0 + ml + q) * a.ldc + n0 + nl];
+            project_amp(cr, ci, am, pr, pi);
             split_terms<BF, NT>(pr, &tr[0][q], 4);
             split_terms<BF, NT>(pi, &ti[0][q], 4);
           }

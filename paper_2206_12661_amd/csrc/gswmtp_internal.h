@@ -78,6 +78,7 @@ struct Bufs {
   double *ucoord = nullptr, *vcoord = nullptr;
   int *csr_ptr = nullptr, *csr_foci = nullptr;
   int *csr_ic = nullptr;                 // reduced-grid column of the focus at each CSR position
+  int *csr_ir = nullptr;                 // reduced-grid row of the focus at each CSR position
   int *scalars = nullptr;                // plan-time integer results
   double *dscalars = nullptr;            // plan-time float64 results
   int *dup = nullptr;
@@ -223,9 +224,36 @@ struct GatherCtx {
   const int *ptr;              // CSR row pointers over the reduced r rows [Ur + 1]
   const int *foci;             // foci sorted by (ir, ic)
   const int *ir, *ic;          // reduced-grid row / column of every focus
+  const int *cir, *cic;        // the same at each CSR position (sorted foci)
   const float *wcr, *wci;      // Omega_c^T planes [Uc][Cp]
   int nf, Ur, Cp;
 };
+
+// Focus indices of a tile's gather, read ahead of the product's main loop so
+// that the epilogue waits only for the Omega_c rows: the CSR range of the
+// tile's reduced rows (first, with the operand loads), then thread
+// (wave w, lane l) takes CSR position p0 + 4 l + w (the tile's first 256
+// foci, dealt out round-robin over the four waves).
+struct GatherPre {
+  int p0 = 0, p1 = 0;       // CSR positions of the tile's reduced rows
+  int f = 0, a = 0, c = 0;  // this thread's focus, its row in the tile, its column
+  bool loaded = false;
+};
+__device__ __forceinline__ void gather_pre_rows(const GatherCtx &g, int m0, int bm,
+                                                GatherPre &q) {
+  const int r0 = m0 < g.Ur ? m0 : g.Ur, r1 = m0 + bm < g.Ur ? m0 + bm : g.Ur;
+  q.p0 = g.ptr[r0];
+  q.p1 = g.ptr[r1];
+}
+__device__ __forceinline__ void gather_pre_foci(const GatherCtx &g, int m0, int tid,
+                                                GatherPre &q) {
+  const int pp = q.p0 + 4 * (tid & 63) + ((tid >> 6) & 3);
+  const bool ok = pp < q.p1;
+  q.f = ok ? g.foci[pp] : 0;
+  q.a = ok ? g.cir[pp] - m0 : 0;
+  q.c = ok ? g.cic[pp] : 0;
+  q.loaded = true;
+}
 
 // Focus gather fused into the forward product's epilogue (the second
 // product of Eq. 2, formed only at the foci).  The BM x BN complex tile of
@@ -233,19 +261,26 @@ struct GatherCtx {
 // focus whose reduced row lies in the tile, one wave forms
 //   sum_{n in tile} L[ir][n] Wc[ic][n]
 // (per-lane partial sums, fixed xor-shuffle tree) and writes it as partial
-// number n0 / BN of that focus.  Accumulator item r of lane (l32, h) of a
-// 32x32 block holds row 8 (r/4) + 4 h + r % 4, column l32.
+// number n0 / BN of that focus.  A wave takes its prefetched foci sixteen at
+// a time (all their Omega_c loads in flight together), then any foci past
+// the tile's first 256 four at a time.  Accumulator item r of lane (l32, h)
+// of a 32x32 block holds row 8 (r/4) + 4 h + r % 4, column l32.
 template <int BM, int BN, bool COLS = false>
 __device__ __forceinline__ void gather_epilogue(
     const GatherCtx &g,
     const gsw_v16f (&accR)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
     const gsw_v16f (&accI)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
-    float *lds, int m0, int n0, int tid) {
+    float *lds, int m0, int n0, int tid, GatherPre q) {
   using L = WaveLayout<BM, BN, COLS>;
   constexpr int MB = L::MB, NB = L::NB, WTM = L::WTM, WTN = L::WTN, LD = BN + 1;
+  constexpr int NC = BN / 64;   // columns per lane
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = L::wm(wave), wn = L::wn(wave), l32 = lane & 31, h = lane >> 5;
   float *tr = lds, *ti = lds + BM * LD;
+  if (!q.loaded) {
+    gather_pre_rows(g, m0, BM, q);
+    gather_pre_foci(g, m0, tid, q);
+  }
   __syncthreads();   // operand stages are no longer read
 #pragma unroll
   for (int i = 0; i < MB; ++i)
@@ -259,59 +294,115 @@ __device__ __forceinline__ void gather_epilogue(
         ti[ml * LD + nl] = accI[i][j][r];
       }
   __syncthreads();
-  const int r0 = m0 < g.Ur ? m0 : g.Ur, r1 = m0 + BM < g.Ur ? m0 + BM : g.Ur;
-  const int p0 = g.ptr[r0], p1 = g.ptr[r1];
+  const int p0 = q.p0, p1 = q.p1;
   float *out = g.part + 2 * (size_t)(n0 / BN) * g.nf;
-  // four foci per wave iteration so their operand loads are in flight together
+  // the wave's prefetched positions p0 + 4 l + wave, l < nl
+  const int nw = p1 - p0 - wave;
+  const int nl = nw <= 0 ? 0 : (nw + 3) / 4 < 64 ? (nw + 3) / 4 : 64;
+  constexpr int FA = 16;
+  for (int l0 = 0; l0 < nl; l0 += FA) {
+    int f[FA], ar[FA];
+    size_t wrow[FA];
+#pragma unroll
+    for (int u = 0; u < FA; ++u) {
+      const int src = l0 + u < nl ? l0 + u : nl - 1;
+      f[u] = __builtin_amdgcn_readlane(q.f, src);
+      ar[u] = __builtin_amdgcn_readlane(q.a, src);
+      wrow[u] = (size_t)__builtin_amdgcn_readlane(q.c, src) * g.Cp + n0;
+    }
+    float wr[FA][NC], wi[FA][NC];
+#pragma unroll
+    for (int u = 0; u < FA; ++u)
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        wr[u][j] = g.wcr[wrow[u] + 64 * j + lane];
+        wi[u][j] = g.wci[wrow[u] + 64 * j + lane];
+      }
+    float sr[FA], si[FA];
+#pragma unroll
+    for (int u = 0; u < FA; ++u) sr[u] = si[u] = 0.f;
+#pragma unroll
+    for (int j = 0; j < NC; ++j)
+#pragma unroll
+      for (int u = 0; u < FA; ++u) {
+        const int nlc = 64 * j + lane;
+        const float lr = tr[ar[u] * LD + nlc], li = ti[ar[u] * LD + nlc];
+        sr[u] = fmaf(lr, wr[u][j], fmaf(-li, wi[u][j], sr[u]));
+        si[u] = fmaf(lr, wi[u][j], fmaf(li, wr[u][j], si[u]));
+      }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int u = 0; u < FA; ++u) {
+        sr[u] += __shfl_xor(sr[u], off, 64);
+        si[u] += __shfl_xor(si[u], off, 64);
+      }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < FA; ++u)
+        if (l0 + u < nl) {
+          out[2 * f[u]] = sr[u];
+          out[2 * f[u] + 1] = si[u];
+        }
+    }
+  }
+  // foci past the tile's first 256, four per wave iteration
   constexpr int FB = 4;
-  for (int pb = p0 + wave * FB; pb < p1; pb += 4 * FB) {
+  for (int pb = p0 + 256 + wave * FB; pb < p1; pb += 4 * FB) {
     int f[FB], a[FB];
     size_t wrow[FB];
 #pragma unroll
-    for (int q = 0; q < FB; ++q) {
-      const int pp = pb + q < p1 ? pb + q : p1 - 1;
-      f[q] = g.foci[pp];
-    }
-#pragma unroll
-    for (int q = 0; q < FB; ++q) {
-      a[q] = g.ir[f[q]] - m0;
-      wrow[q] = (size_t)g.ic[f[q]] * g.Cp + n0;
+    for (int u = 0; u < FB; ++u) {
+      const int pp = pb + u < p1 ? pb + u : p1 - 1;
+      f[u] = g.foci[pp];
+      a[u] = g.cir[pp] - m0;
+      wrow[u] = (size_t)g.cic[pp] * g.Cp + n0;
     }
     float sr[FB], si[FB];
 #pragma unroll
-    for (int q = 0; q < FB; ++q) sr[q] = si[q] = 0.f;
+    for (int u = 0; u < FB; ++u) sr[u] = si[u] = 0.f;
 #pragma unroll
     for (int nl0 = 0; nl0 < BN; nl0 += 64) {
-      const int nl = nl0 + lane;
+      const int nlc = nl0 + lane;
       float wr[FB], wi[FB];
 #pragma unroll
-      for (int q = 0; q < FB; ++q) {
-        wr[q] = g.wcr[wrow[q] + nl];
-        wi[q] = g.wci[wrow[q] + nl];
+      for (int u = 0; u < FB; ++u) {
+        wr[u] = g.wcr[wrow[u] + nlc];
+        wi[u] = g.wci[wrow[u] + nlc];
       }
 #pragma unroll
-      for (int q = 0; q < FB; ++q) {
-        const float lr = tr[a[q] * LD + nl], li = ti[a[q] * LD + nl];
-        sr[q] = fmaf(lr, wr[q], fmaf(-li, wi[q], sr[q]));
-        si[q] = fmaf(lr, wi[q], fmaf(li, wr[q], si[q]));
+      for (int u = 0; u < FB; ++u) {
+        const float lr = tr[a[u] * LD + nlc], li = ti[a[u] * LD + nlc];
+        sr[u] = fmaf(lr, wr[u], fmaf(-li, wi[u], sr[u]));
+        si[u] = fmaf(lr, wi[u], fmaf(li, wr[u], si[u]));
       }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-      for (int q = 0; q < FB; ++q) {
-        sr[q] += __shfl_xor(sr[q], off, 64);
-        si[q] += __shfl_xor(si[q], off, 64);
+      for (int u = 0; u < FB; ++u) {
+        sr[u] += __shfl_xor(sr[u], off, 64);
+        si[u] += __shfl_xor(si[u], off, 64);
       }
     if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < FB; ++q)
-        if (pb + q < p1) {
-          out[2 * f[q]] = sr[q];
-          out[2 * f[q] + 1] = si[q];
+      for (int u = 0; u < FB; ++u)
+        if (pb + u < p1) {
+          out[2 * f[u]] = sr[u];
+          out[2 * f[u] + 1] = si[u];
         }
     }
   }
+}
+
+// The same without indices read ahead (they are read at the epilogue).
+template <int BM, int BN, bool COLS = false>
+__device__ __forceinline__ void gather_epilogue(
+    const GatherCtx &g,
+    const gsw_v16f (&accR)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
+    const gsw_v16f (&accI)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
+    float *lds, int m0, int n0, int tid) {
+  gather_epilogue<BM, BN, COLS>(g, accR, accI, lds, m0, n0, tid, GatherPre{});
 }
 
 template <int BM, int BN>

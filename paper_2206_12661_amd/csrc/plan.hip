@@ -936,6 +936,7 @@ void carve_pool0(Carver &c, Bufs &b, size_t nf, size_t ny, size_t nx) {
   b.aeff = c.take<float>(np);
   b.ucoord = c.take<double>(nx); b.vcoord = c.take<double>(ny);
   b.csr_foci = c.take<int>(nf); b.csr_ptr = c.take<int>(nf + 1); b.csr_ic = c.take<int>(nf);
+  b.csr_ir = c.take<int>(nf);
   b.scalars = c.take<int>(16); b.dscalars = c.take<double>(8); b.dup = c.take<int>(1);
   b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
   b.intensity = c.take<float>(nf);
@@ -1186,6 +1187,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   hipLaunchKernelGGL(k_row_ptr, grid1(nf + 1), dim3(256), 0, s, ir, b.csr_foci, (int)nf, D.Ur,
                      b.csr_ptr);
   hipLaunchKernelGGL(k_csr_gather, grid1(nf), dim3(256), 0, s, ic, b.csr_foci, (int)nf, b.csr_ic);
+  hipLaunchKernelGGL(k_csr_gather, grid1(nf), dim3(256), 0, s, ir, b.csr_foci, (int)nf, b.csr_ir);
   const double *rcoord = D.axis == 0 ? b.vcoord : b.ucoord;
   const double *ccoord = D.axis == 0 ? b.ucoord : b.vcoord;
   const int *rkept = D.axis == 0 ? b.rows : b.cols;
