@@ -231,12 +231,11 @@ struct GatherCtx {
 
 // Focus indices of a tile's gather, read ahead of the product's main loop so
 // that the epilogue waits only for the Omega_c rows: the CSR range of the
-// tile's reduced rows (first, with the operand loads), then thread
-// (wave w, lane l) takes CSR position p0 + 4 l + w (the tile's first 256
-// foci, dealt out round-robin over the four waves).
+// tile's reduced rows (first, with the operand loads), then lane l of every
+// wave takes CSR position p0 + l (the tile's first 64 foci).
 struct GatherPre {
   int p0 = 0, p1 = 0;       // CSR positions of the tile's reduced rows
-  int f = 0, a = 0, c = 0;  // this thread's focus, its row in the tile, its column
+  int f = 0, a = 0, c = 0;  // this lane's focus, its row in the tile, its column
   bool loaded = false;
 };
 __device__ __forceinline__ void gather_pre_rows(const GatherCtx &g, int m0, int bm,
@@ -247,7 +246,7 @@ __device__ __forceinline__ void gather_pre_rows(const GatherCtx &g, int m0, int 
 }
 __device__ __forceinline__ void gather_pre_foci(const GatherCtx &g, int m0, int tid,
                                                 GatherPre &q) {
-  const int pp = q.p0 + 4 * (tid & 63) + ((tid >> 6) & 3);
+  const int pp = q.p0 + (tid & 63);
   const bool ok = pp < q.p1;
   q.f = ok ? g.foci[pp] : 0;
   q.a = ok ? g.cir[pp] - m0 : 0;
@@ -257,14 +256,14 @@ __device__ __forceinline__ void gather_pre_foci(const GatherCtx &g, int m0, int 
 
 // Focus gather fused into the forward product's epilogue (the second
 // product of Eq. 2, formed only at the foci).  The BM x BN complex tile of
-// L = Omega_r P held in the accumulators is staged in LDS; then for each
-// focus whose reduced row lies in the tile, one wave forms
-//   sum_{n in tile} L[ir][n] Wc[ic][n]
-// (per-lane partial sums, fixed xor-shuffle tree) and writes it as partial
-// number n0 / BN of that focus.  A wave takes its prefetched foci sixteen at
-// a time (all their Omega_c loads in flight together), then any foci past
-// the tile's first 256 four at a time.  Accumulator item r of lane (l32, h)
-// of a 32x32 block holds row 8 (r/4) + 4 h + r % 4, column l32.
+// L = Omega_r P held in the accumulators is staged in LDS; then the tile's
+// foci are taken 64 at a time, one per lane: wave w forms
+//   sum_{n in its BN/4 columns} L[ir][n] Wc[ic][n]
+// for the lane's focus (its Omega_c run read as 16-byte loads, all in
+// flight together), the four waves' sums are added in wave order and the
+// result written as partial number n0 / BN of that focus.  Accumulator item
+// r of lane (l32, h) of a 32x32 block holds row 8 (r/4) + 4 h + r % 4,
+// column l32.
 template <int BM, int BN, bool COLS = false>
 __device__ __forceinline__ void gather_epilogue(
     const GatherCtx &g,
@@ -273,10 +272,12 @@ __device__ __forceinline__ void gather_epilogue(
     float *lds, int m0, int n0, int tid, GatherPre q) {
   using L = WaveLayout<BM, BN, COLS>;
   constexpr int MB = L::MB, NB = L::NB, WTM = L::WTM, WTN = L::WTN, LD = BN + 1;
-  constexpr int NC = BN / 64;   // columns per lane
+  constexpr int CW = BN / 4;   // columns per wave
+  typedef float f4 __attribute__((ext_vector_type(4)));
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = L::wm(wave), wn = L::wn(wave), l32 = lane & 31, h = lane >> 5;
   float *tr = lds, *ti = lds + BM * LD;
+  float *red = lds + 2 * BM * LD;   // [4 waves][64 lanes][re, im]
   if (!q.loaded) {
     gather_pre_rows(g, m0, BM, q);
     gather_pre_foci(g, m0, tid, q);
@@ -294,104 +295,50 @@ __device__ __forceinline__ void gather_epilogue(
         ti[ml * LD + nl] = accI[i][j][r];
       }
   __syncthreads();
-  const int p0 = q.p0, p1 = q.p1;
+  const int p0 = q.p0, nfoc = q.p1 - q.p0;
   float *out = g.part + 2 * (size_t)(n0 / BN) * g.nf;
-  // the wave's prefetched positions p0 + 4 l + wave, l < nl
-  const int nw = p1 - p0 - wave;
-  const int nl = nw <= 0 ? 0 : (nw + 3) / 4 < 64 ? (nw + 3) / 4 : 64;
-  constexpr int FA = 16;
-  for (int l0 = 0; l0 < nl; l0 += FA) {
-    int f[FA], ar[FA];
-    size_t wrow[FA];
-#pragma unroll
-    for (int u = 0; u < FA; ++u) {
-      const int src = l0 + u < nl ? l0 + u : nl - 1;
-      f[u] = __builtin_amdgcn_readlane(q.f, src);
-      ar[u] = __builtin_amdgcn_readlane(q.a, src);
-      wrow[u] = (size_t)__builtin_amdgcn_readlane(q.c, src) * g.Cp + n0;
+  for (int u0 = 0; u0 < nfoc; u0 += 64) {
+    const bool on = u0 + lane < nfoc;
+    int f = q.f, a = q.a, c = q.c;
+    if (u0 > 0) {
+      const int pp = on ? p0 + u0 + lane : p0;
+      f = g.foci[pp];
+      a = g.cir[pp] - m0;
+      c = g.cic[pp];
     }
-    float wr[FA][NC], wi[FA][NC];
+    float sr = 0.f, si = 0.f;
+    if (on) {
+      const size_t wrow = (size_t)c * g.Cp + n0 + wave * CW;
+      f4 wr[CW / 4], wi[CW / 4];
 #pragma unroll
-    for (int u = 0; u < FA; ++u)
-#pragma unroll
-      for (int j = 0; j < NC; ++j) {
-        wr[u][j] = g.wcr[wrow[u] + 64 * j + lane];
-        wi[u][j] = g.wci[wrow[u] + 64 * j + lane];
+      for (int k = 0; k < CW / 4; ++k) {
+        wr[k] = *reinterpret_cast<const f4 *>(g.wcr + wrow + 4 * k);
+        wi[k] = *reinterpret_cast<const f4 *>(g.wci + wrow + 4 * k);
       }
-    float sr[FA], si[FA];
+      const float *lr = tr + a * LD + wave * CW, *li = ti + a * LD + wave * CW;
 #pragma unroll
-    for (int u = 0; u < FA; ++u) sr[u] = si[u] = 0.f;
+      for (int k = 0; k < CW / 4; ++k)
 #pragma unroll
-    for (int j = 0; j < NC; ++j)
-#pragma unroll
-      for (int u = 0; u < FA; ++u) {
-        const int nlc = 64 * j + lane;
-        const float lr = tr[ar[u] * LD + nlc], li = ti[ar[u] * LD + nlc];
-        sr[u] = fmaf(lr, wr[u][j], fmaf(-li, wi[u][j], sr[u]));
-        si[u] = fmaf(lr, wi[u][j], fmaf(li, wr[u][j], si[u]));
-      }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int u = 0; u < FA; ++u) {
-        sr[u] += __shfl_xor(sr[u], off, 64);
-        si[u] += __shfl_xor(si[u], off, 64);
-      }
-    if (lane == 0) {
-#pragma unroll
-      for (int u = 0; u < FA; ++u)
-        if (l0 + u < nl) {
-          out[2 * f[u]] = sr[u];
-          out[2 * f[u] + 1] = si[u];
+        for (int e = 0; e < 4; ++e) {
+          const float xr = lr[4 * k + e], xi = li[4 * k + e];
+          sr = fmaf(xr, wr[k][e], fmaf(-xi, wi[k][e], sr));
+          si = fmaf(xr, wi[k][e], fmaf(xi, wr[k][e], si));
         }
     }
-  }
-  // foci past the tile's first 256, four per wave iteration
-  constexpr int FB = 4;
-  for (int pb = p0 + 256 + wave * FB; pb < p1; pb += 4 * FB) {
-    int f[FB], a[FB];
-    size_t wrow[FB];
+    red[2 * (wave * 64 + lane)] = sr;
+    red[2 * (wave * 64 + lane) + 1] = si;
+    __syncthreads();
+    if (wave == 0 && on) {
+      float tr_ = red[2 * lane], ti_ = red[2 * lane + 1];
 #pragma unroll
-    for (int u = 0; u < FB; ++u) {
-      const int pp = pb + u < p1 ? pb + u : p1 - 1;
-      f[u] = g.foci[pp];
-      a[u] = g.cir[pp] - m0;
-      wrow[u] = (size_t)g.cic[pp] * g.Cp + n0;
-    }
-    float sr[FB], si[FB];
-#pragma unroll
-    for (int u = 0; u < FB; ++u) sr[u] = si[u] = 0.f;
-#pragma unroll
-    for (int nl0 = 0; nl0 < BN; nl0 += 64) {
-      const int nlc = nl0 + lane;
-      float wr[FB], wi[FB];
-#pragma unroll
-      for (int u = 0; u < FB; ++u) {
-        wr[u] = g.wcr[wrow[u] + nlc];
-        wi[u] = g.wci[wrow[u] + nlc];
+      for (int w = 1; w < 4; ++w) {
+        tr_ += red[2 * (w * 64 + lane)];
+        ti_ += red[2 * (w * 64 + lane) + 1];
       }
-#pragma unroll
-      for (int u = 0; u < FB; ++u) {
-        const float lr = tr[a[u] * LD + nlc], li = ti[a[u] * LD + nlc];
-        sr[u] = fmaf(lr, wr[u], fmaf(-li, wi[u], sr[u]));
-        si[u] = fmaf(lr, wi[u], fmaf(li, wr[u], si[u]));
-      }
+      out[2 * f] = tr_;
+      out[2 * f + 1] = ti_;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int u = 0; u < FB; ++u) {
-        sr[u] += __shfl_xor(sr[u], off, 64);
-        si[u] += __shfl_xor(si[u], off, 64);
-      }
-    if (lane == 0) {
-#pragma unroll
-      for (int u = 0; u < FB; ++u)
-        if (pb + u < p1) {
-          out[2 * f[u]] = sr[u];
-          out[2 * f[u] + 1] = si[u];
-        }
-    }
+    __syncthreads();   // the sums are read before the next round writes them
   }
 }
 
@@ -406,7 +353,7 @@ __device__ __forceinline__ void gather_epilogue(
 }
 
 template <int BM, int BN>
-constexpr int gather_lds_bytes() { return 2 * BM * (BN + 1) * 4; }
+constexpr int gather_lds_bytes() { return 2 * BM * (BN + 1) * 4 + 4 * 64 * 2 * 4; }
 
 }  // namespace gswmtp
 
