@@ -12,14 +12,41 @@ namespace gswmtp {
 namespace {
 
 
-// Deterministic reductions over one kUpdThreads workgroup: an xor-shuffle
-// tree inside each wave, then the kUpdThreads / 64 wave results added in wave order by
-// every thread (one barrier; each call site uses its own LDS slots).
+struct Sum {
+  static constexpr double identity = 0.0;
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct Max {
+  static constexpr double identity = -__builtin_inf();
+  __device__ double operator()(double a, double b) const { return a > b ? a : b; }
+};
+
+// One step of a wave reduction on DPP lane moves (no LDS round trip): lanes
+// of the rows in ROWS combine with the value CTRL moves to them, the other
+// lanes with the identity.
+template <int CTRL, int ROWS, typename Op>
+__device__ __forceinline__ double dpp_step(double v, Op op) {
+  const long long b = __double_as_longlong(v), e = __double_as_longlong(Op::identity);
+  const int lo = __builtin_amdgcn_update_dpp((int)e, (int)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(e >> 32), (int)(b >> 32), CTRL, ROWS, 0xf,
+                                             false);
+  return op(v, __longlong_as_double(((long long)hi << 32) | (unsigned)lo));
+}
+
+// Deterministic reductions over one kUpdThreads workgroup: a fixed DPP
+// sequence inside each wave (lane pairs, quads, half rows, rows by mirroring,
+// then rows 0 + 1 and 2 + 3 and the two halves by row broadcasts; the total
+// ends in lane 63), then the kUpdThreads / 64 wave results added in wave
+// order by every thread (one barrier; each call site uses its own LDS slots).
 template <typename Op>
 __device__ __forceinline__ double wave_reduce(double v, Op op) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
-  return v;
+  v = dpp_step<0xB1, 0xf>(v, op);    // quad_perm [1, 0, 3, 2]
+  v = dpp_step<0x4E, 0xf>(v, op);    // quad_perm [2, 3, 0, 1]
+  v = dpp_step<0x141, 0xf>(v, op);   // row_half_mirror
+  v = dpp_step<0x140, 0xf>(v, op);   // row_mirror
+  v = dpp_step<0x142, 0xa>(v, op);   // row_bcast:15 into rows 1 and 3
+  v = dpp_step<0x143, 0xc>(v, op);   // row_bcast:31 into rows 2 and 3
+  return v;                          // complete in lane 63
 }
 template <int NV, typename Op>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], double (*slot)[16], Op op) {
@@ -27,7 +54,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double (*slot)[16]
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     v[q] = wave_reduce(v[q], op);
-    if (lane == 0) slot[q][wave] = v[q];
+    if (lane == 63) slot[q][wave] = v[q];
   }
   __syncthreads();
 #pragma unroll
@@ -38,9 +65,6 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double (*slot)[16]
   }
 }
 
-struct Sum { __device__ double operator()(double a, double b) const { return a + b; } };
-struct Max { __device__ double operator()(double a, double b) const { return a > b ? a : b; } };
-struct Min { __device__ double operator()(double a, double b) const { return a < b ? a : b; } };
 
 struct UpdateArgs {
   const float *gpart;      // [T][2 nf] fused-gather partials of the forward product
@@ -98,12 +122,12 @@ __device__ __forceinline__ void block_reduce_mixed(double (&sv)[NS], double (&mv
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
     sv[q] = wave_reduce(sv[q], Sum());
-    if (lane == 0) slot[q][wave] = sv[q];
+    if (lane == 63) slot[q][wave] = sv[q];
   }
 #pragma unroll
   for (int q = 0; q < NM; ++q) {
     mv[q] = wave_reduce(mv[q], Max());
-    if (lane == 0) slot[NS + q][wave] = mv[q];
+    if (lane == 63) slot[NS + q][wave] = mv[q];
   }
   __syncthreads();
 #pragma unroll
