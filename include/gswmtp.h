@@ -298,10 +298,9 @@ const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
  *   grouped launches when more than one is valid; GSWMTP_BATCH_TILE=BMxBN
  *   fixes it, GSWMTP_BATCH_NO_TUNE=1 takes the first valid) without changing
  *   any plan's state.  Split precisions: the single-plan form's product
- *   loops on 64 x 64 tiles (the forward 64 x 128 when a plan's own forward
- *   tile is that wide, or when GSWMTP_BATCH_TILE=64x128 and every plan
- *   allows it).  Allocates its own argument tables.  stream: hipStream_t or
- *   NULL.
+ *   loops on 64 x 64 tiles (the forward 64 x 128 when
+ *   GSWMTP_BATCH_TILE=64x128 and every plan allows it).  Allocates its own
+ *   argument tables.  stream: hipStream_t or NULL.
  * batch_iterate: n_iter passes on every plan, each plan stopping on its own
  *   as gswmtp_iterate(p, n_iter, stop_accuracy) would; ordered after the
  *   caller's stream and each plan's queued work, and before later calls on
