@@ -53,7 +53,7 @@ enum {
     GSWMTP_E_HIP = -5,            /* a HIP runtime call failed */
     GSWMTP_E_NONFINITE = -6,      /* a focus intensity sum became non-finite */
     GSWMTP_E_NODEV = -7,          /* no usable gfx950 device */
-    GSWMTP_E_UNSUPPORTED = -8     /* valid request this build does not implement */
+    GSWMTP_E_UNSUPPORTED = -8     /* valid request the library does not implement */
 };
 
 /* Arithmetic of the two dense complex products (forward and adjoint MTP).
