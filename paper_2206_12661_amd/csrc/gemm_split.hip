@@ -380,7 +380,6 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
   constexpr int WTM = L::WTM, WTN = L::WTN;
   constexpr int MB = L::MB, NB = L::NB;
   constexpr int PL = 2 * NT;                     // planes per operand
-  constexpr int KS = BK / kKStep;                // MFMA k-steps per stage
   constexpr int CH = BK / 8;                     // 16-byte chunks per row and stage
   constexpr int LA = PL * BM * CH, LB = PL * BN * CH;   // chunks loaded per stage
   constexpr int NA = LA / NTH, NBL = LB / NTH;

@@ -39,6 +39,9 @@ def _cases():
         "grid-96x96-7x5": synth_ofa.random_case(12, 96, 96, 0, grid=(7, 5)),
         "config1": synth_ofa.config1(),
         "config2": synth_ofa.config2(),
+        # split-K tail tiles: the forward's (gather, axis 0) and the adjoint's
+        # 64 x 128 direct-loop tiles (store epilogue of the operator call)
+        "512x2048-1060": synth_ofa.random_case(47, 512, 2048, 1060),
     }
 
 
