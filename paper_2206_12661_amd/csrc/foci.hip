@@ -67,8 +67,9 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], double (*slot)[16]
 
 
 struct UpdateArgs {
-  const float *gpart;      // [T][2 nf] fused-gather partials of the forward product
+  const float *gpart;      // [T][2 ldp] fused-gather partials of the forward product
   int T;                   // partials per focus
+  int ldp;                 // foci per partial row (nf rounded up to even)
   float scale;             // power-of-two factor undoing the pupil scale
   float *theta;            // [2 nf] forward field (written)
   float *theta_new;        // [2 nf] updated focal field (scaled by a power of 2)
@@ -144,7 +145,8 @@ __device__ __forceinline__ void block_reduce_mixed(double (&sv)[NS], double (&mv
   }
 }
 
-// Per-focus values live in registers (FPT foci per thread, n = t + f * kUpdThreads).
+// Per-focus values live in registers (FPT consecutive foci per thread,
+// n = FPT t + f, so one 16-byte load reads a partial of a pair of foci).
 // Two reductions: sum I first; then, from it, the accuracy and uniformity
 // terms and the new weights' amplitude maximum together (everything needed
 // for the termination test and the update), so only one more barrier.  The
@@ -167,7 +169,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   float thr[FPT], thi[FPT];
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
-    const int n = t + f * kUpdThreads;
+    const int n = FPT * t + f;
     const bool ok = n < a.nf;
     mi[f] = ok && upd && a.meas ? a.meas[n] : 0.0;
     tn[f] = ok ? a.tnorm[n] : 0.0;
@@ -177,28 +179,29 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
     fpr[f] = ok && recorded ? a.fixph[2 * n] : 1.0;
     fpi[f] = ok && recorded ? a.fixph[2 * n + 1] : 0.0;
   }
-  typedef float f2 __attribute__((ext_vector_type(2)));
-  const f2 *gp = reinterpret_cast<const f2 *>(a.gpart);
-  constexpr int CHUNK = 32;
+  static_assert(FPT == 2, "one 16-byte partial load per pair of foci");
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int CHUNK = 16;
 #pragma unroll
   for (int f = 0; f < FPT; ++f) thr[f] = thi[f] = 0.f;
-  // partials in ascending order; one chunk of every focus of the thread in flight
+  // partials in ascending order; one chunk in flight.  Row q holds the pair
+  // (2t, 2t + 1) in 16 bytes (rows of ldp foci, ldp even); the second focus
+  // of the last pair is padding when nf is odd, and ignored.
+  const bool pair_on = 2 * t < a.nf;
   for (int q = 0; q < a.T; q += CHUNK) {
-    f2 v[FPT][CHUNK];
+    f4 v[CHUNK];
 #pragma unroll
-    for (int f = 0; f < FPT; ++f) {
-      const int n = t + f * kUpdThreads;
+    for (int j = 0; j < CHUNK; ++j)
+      v[j] = q + j < a.T && pair_on
+                 ? *reinterpret_cast<const f4 *>(a.gpart + 2 * ((size_t)(q + j) * a.ldp + 2 * t))
+                 : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int j = 0; j < CHUNK; ++j)
-        v[f][j] = q + j < a.T && n < a.nf ? gp[(size_t)(q + j) * a.nf + n] : f2{0.f, 0.f};
+    for (int j = 0; j < CHUNK; ++j) {   // zeros past T: exact no-ops
+      thr[0] += v[j].x;
+      thi[0] += v[j].y;
+      thr[1] += v[j].z;
+      thi[1] += v[j].w;
     }
-#pragma unroll
-    for (int f = 0; f < FPT; ++f)
-#pragma unroll
-      for (int j = 0; j < CHUNK; ++j) {   // zeros past T: exact no-ops
-        thr[f] += v[f][j].x;
-        thi[f] += v[f][j].y;
-      }
   }
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
@@ -209,7 +212,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   double v1[1] = {0.0};
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
-    const int n = t + f * kUpdThreads;
+    const int n = FPT * t + f;
     if (n >= a.nf) continue;
     a.theta[2 * n] = thr[f];
     a.theta[2 * n + 1] = thi[f];
@@ -228,7 +231,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
     amag[f] = 0.0;
-    if (t + f * kUpdThreads >= a.nf) continue;
+    if (FPT * t + f >= a.nf) continue;
     const double re = thr[f], im = thi[f];
     const double in = (re * re + im * im) * inv;
     sv[0] += (tn[f] - in) * (tn[f] - in);
@@ -279,7 +282,7 @@ __device__ __forceinline__ void focus_update_body(const UpdateArgs &a, double (*
   const double scale = ldexp(1.0, e);
 #pragma unroll
   for (int f = 0; f < FPT; ++f) {
-    const int n = t + f * kUpdThreads;
+    const int n = FPT * t + f;
     if (n >= a.nf) continue;
     if (a.weighting == GSWMTP_WEIGHT_GSW) a.w[n] = wv[f];
     double pr = 1.0, pi = 0.0;
@@ -332,7 +335,7 @@ __device__ __forceinline__ void big_phase1(const UpdateArgs &a, int b, double (*
     f2 v[CHUNK];
 #pragma unroll
     for (int j = 0; j < CHUNK; ++j)
-      v[j] = q + j < a.T && n < a.nf ? gp[(size_t)(q + j) * a.nf + n] : f2{0.f, 0.f};
+      v[j] = q + j < a.T && n < a.nf ? gp[(size_t)(q + j) * a.ldp + n] : f2{0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < CHUNK; ++j) {   // zeros past T: exact no-ops
       sr += v[j].x;
@@ -551,15 +554,15 @@ __global__ void grid_scatter(const float *__restrict__ tn, float scale, const in
 }
 
 // Theta_n from the gather partials alone (operator-level forward calls).
-__global__ void gather_reduce(const float *__restrict__ gpart, int T, int nf, float scale,
-                              float *__restrict__ theta) {
+__global__ void gather_reduce(const float *__restrict__ gpart, int T, int nf, int ldp,
+                              float scale, float *__restrict__ theta) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nf) return;
   float sr = 0.f, si = 0.f;
 #pragma unroll 8
   for (int q = 0; q < T; ++q) {
-    sr += gpart[2 * ((size_t)q * nf + n)];
-    si += gpart[2 * ((size_t)q * nf + n) + 1];
+    sr += gpart[2 * ((size_t)q * ldp + n)];
+    si += gpart[2 * ((size_t)q * ldp + n) + 1];
   }
   theta[2 * n] = sr * scale;
   theta[2 * n + 1] = si * scale;
@@ -805,9 +808,11 @@ hipError_t launch_scatter_split_grouped(const void *items, const int *starts, in
 hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s) {
   const int nf = p->d.nf;
   hipLaunchKernelGGL(gather_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.gpart,
-                     gather_partials(p), nf, scale, theta);
+                     gather_partials(p), nf, gather_ld(p), scale, theta);
   return hipGetLastError();
 }
+
+int gather_ld(const gswmtp_plan *p) { return (p->d.nf + 1) & ~1; }
 
 int gather_partials(const gswmtp_plan *p) {
   return p->grid_form ? 1 : p->d.Cp / p->sched_fwd.tile.bn;
@@ -834,6 +839,7 @@ static UpdateArgs update_args(const gswmtp_plan *p, int mode) {
   UpdateArgs a{};
   a.gpart = p->b.gpart;
   a.T = gather_partials(p);
+  a.ldp = gather_ld(p);
   a.scale = std::ldexp(1.f, -p->amp_exp);
   a.theta = p->b.theta;
   a.theta_new = p->b.theta_new;

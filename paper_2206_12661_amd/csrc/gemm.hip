@@ -404,6 +404,7 @@ GatherCtx gather_ctx(const gswmtp_plan *p) {
   g.nf = p->d.nf;
   g.Ur = p->d.Ur;
   g.Cp = p->d.Cp;
+  g.ldp = gather_ld(p);
   return g;
 }
 

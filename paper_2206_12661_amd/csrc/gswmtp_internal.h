@@ -97,7 +97,7 @@ struct Bufs {
   int *ctrl = nullptr;
   float *iobuf = nullptr;                // [2*ny*nx] staging for operator calls
   float *part = nullptr;                 // split-K partial tiles (shared by both products)
-  float *gpart = nullptr;                // fused-gather partials [tiles_n][nf] complex
+  float *gpart = nullptr;                // fused-gather partials [tiles_n][ldp] complex
   // split-precision modes: 16-bit term planes [re/im][term] of a [row][K]
   // matrix each, stored k-blocked (kblk_index)
   unsigned short *as_f = nullptr;        // Omega_r            [2][NT] x [Urp][Rp]
@@ -220,13 +220,14 @@ typedef float gsw_v16f __attribute__((ext_vector_type(16)));
 
 // Where the fused focus gather reads and writes.
 struct GatherCtx {
-  float *part;                 // [tiles_n][nf] interleaved complex partial sums
+  float *part;                 // [tiles_n][ldp] interleaved complex partial sums
   const int *ptr;              // CSR row pointers over the reduced r rows [Ur + 1]
   const int *foci;             // foci sorted by (ir, ic)
   const int *ir, *ic;          // reduced-grid row / column of every focus
   const int *cir, *cic;        // the same at each CSR position (sorted foci)
   const float *wcr, *wci;      // Omega_c^T planes [Uc][Cp]
   int nf, Ur, Cp;
+  int ldp;                     // foci per partial row (nf rounded up to even)
 };
 
 // Focus indices of a tile's gather, read ahead of the product's main loop so
@@ -296,7 +297,7 @@ __device__ __forceinline__ void gather_epilogue(
       }
   __syncthreads();
   const int p0 = q.p0, nfoc = q.p1 - q.p0;
-  float *out = g.part + 2 * (size_t)(n0 / BN) * g.nf;
+  float *out = g.part + 2 * (size_t)(n0 / BN) * g.ldp;
   for (int u0 = 0; u0 < nfoc; u0 += 64) {
     const bool on = u0 + lane < nfoc;
     int f = q.f, a = q.a, c = q.c;
@@ -420,6 +421,7 @@ hipError_t launch_grid_scatter(const gswmtp_plan *p, const float *theta_new, flo
                                hipStream_t s);
 // Gather partials per focus of the plan's forward form.
 int gather_partials(const gswmtp_plan *p);
+int gather_ld(const gswmtp_plan *p);   // gather partial row stride: nf rounded up to even
 GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split);
 
 // Grouped launches over the plans of a batch (float32 products).

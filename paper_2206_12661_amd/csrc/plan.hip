@@ -1020,7 +1020,7 @@ void carve_pool1(Carver &c, Bufs &b, const gswmtp_plan *p) {
   b.p_r = c.take<float>(f32 * Rp * Cp); b.p_i = c.take<float>(f32 * Rp * Cp);
   // gather partials: one per forward column tile and focus, sized for the
   // narrowest tile (64 columns) so that a batch may run any tile width
-  b.gpart = c.take<float>(2 * (size_t)(Cp / 64) * nf);
+  b.gpart = c.take<float>(2 * (size_t)(Cp / 64) * ((nf + 1) & ~(size_t)1));
   b.s_r = c.take<float>(f32 * Urp * Cp); b.s_i = c.take<float>(f32 * Urp * Cp);
   b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
   b.part = c.take<float>(part_floats);
