@@ -639,9 +639,10 @@ __global__ __launch_bounds__(256) void focus_scatter_grouped(const ScatterArgs *
 // Split-precision scatter: the same S, written transposed as 16-bit term
 // planes S^T [re/im][term][Cp][Urp] (the k-contiguous B operand of the
 // split adjoint product).  A block computes a 32 (a) x 64 (i) tile of S with
-// coalesced reads of Wc, transposes it through LDS and writes 8 consecutive a
-// per thread and plane (16 bytes).  A thread's eight rows advance together
-// (entry k of every row at once), so their loads are in flight together.
+// coalesced 16-byte reads of Wc (four columns of two rows per thread),
+// transposes it through LDS and writes 8 consecutive a per thread and plane
+// (16 bytes).  A thread's rows advance together (entry k of both rows at
+// once), so their loads are in flight together.
 // ic: reduced-grid column of the focus at each CSR position.
 template <bool BF, int NT>
 __device__ __forceinline__ void focus_scatter_split_body(
@@ -651,20 +652,23 @@ __device__ __forceinline__ void focus_scatter_split_body(
     int bx, int by, float (*tr)[65], float (*ti)[65]) {
   const int i0 = bx * 64, a0 = by * 32;
   const int tid = threadIdx.x;
-  const int il = tid & 63;
-  constexpr int R = 8;   // rows per thread: a0 + (tid >> 6) + 4 q
+  // four consecutive columns i0 + 4 c4 .. + 3 (16-byte loads of Wc), two
+  // rows a0 + rg + 16 q; a wave covers 64 columns of four rows
+  const int c4 = tid & 15, rg = tid >> 4;
+  constexpr int R = 2;
+  typedef float f4 __attribute__((ext_vector_type(4)));
   int p0[R], len[R], kmax = 0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int a = a0 + (tid >> 6) + 4 * q;
+    const int a = a0 + rg + 16 * q;
     const int lo = a < Ur ? ptr[a] : 0, hi = a < Ur ? ptr[a + 1] : 0;
     p0[q] = lo;
     len[q] = hi - lo;
-    kmax = len[q] > kmax ? len[q] : kmax;   // uniform across the wave
+    kmax = len[q] > kmax ? len[q] : kmax;
   }
-  float accr[R], acci[R];
+  f4 accr[R], acci[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) accr[q] = acci[q] = 0.f;
+  for (int q = 0; q < R; ++q) accr[q] = acci[q] = f4{0.f, 0.f, 0.f, 0.f};
   for (int k = 0; k < kmax; ++k) {
     int n[R], c[R];
 #pragma unroll
@@ -673,28 +677,33 @@ __device__ __forceinline__ void focus_scatter_split_body(
       n[q] = on ? foci[p0[q] + k] : 0;
       c[q] = on ? ic[p0[q] + k] : 0;
     }
-    float xr[R], xi[R], yr[R], yi[R];
+    float xr[R], xi[R];
+    f4 yr[R], yi[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const bool on = k < len[q];
-      const size_t o = (size_t)c[q] * Cp + i0 + il;
+      const size_t o = (size_t)c[q] * Cp + i0 + 4 * c4;
       xr[q] = on ? tn[2 * n[q]] * scale : 0.f;
       xi[q] = on ? tn[2 * n[q] + 1] * scale : 0.f;
-      yr[q] = on ? wr[o] : 0.f;
-      yi[q] = on ? -wi[o] : 0.f;
+      yr[q] = on ? *reinterpret_cast<const f4 *>(wr + o) : f4{0.f, 0.f, 0.f, 0.f};
+      yi[q] = on ? -*reinterpret_cast<const f4 *>(wi + o) : f4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int q = 0; q < R; ++q)
-      if (k < len[q]) {
-        accr[q] = fmaf(xr[q], yr[q], fmaf(-xi[q], yi[q], accr[q]));
-        acci[q] = fmaf(xr[q], yi[q], fmaf(xi[q], yr[q], acci[q]));
-      }
+      if (k < len[q])
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          accr[q][e] = fmaf(xr[q], yr[q][e], fmaf(-xi[q], yi[q][e], accr[q][e]));
+          acci[q][e] = fmaf(xr[q], yi[q][e], fmaf(xi[q], yr[q][e], acci[q][e]));
+        }
   }
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    tr[(tid >> 6) + 4 * q][il] = accr[q];
-    ti[(tid >> 6) + 4 * q][il] = acci[q];
-  }
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      tr[rg + 16 * q][4 * c4 + e] = accr[q][e];
+      ti[rg + 16 * q][4 * c4 + e] = acci[q][e];
+    }
   if (done && *done) return;   // uniform; read after the sums' loads were issued
   __syncthreads();
   const int i = tid >> 2, part = tid & 3;   // 64 columns x 4 runs of 8 a
