@@ -589,7 +589,10 @@ struct ScatterArgs {
   const int *done;
 };
 
+// Row a, columns i .. i + 3 (i a multiple of 4; Cp is a multiple of 64):
+// 16-byte reads of Wc and 16-byte stores of S.
 __device__ __forceinline__ void focus_scatter_body(const ScatterArgs &s_, int a, int i) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
   const float *__restrict__ tn = s_.tn;
   const float *__restrict__ wr = s_.wr;
   const float *__restrict__ wi = s_.wi;
@@ -600,29 +603,33 @@ __device__ __forceinline__ void focus_scatter_body(const ScatterArgs &s_, int a,
   float *__restrict__ si = s_.si;
   const int Ur = s_.Ur, Cp = s_.Cp;
   if (i >= Cp) return;
-  float accr = 0.f, acci = 0.f;
+  f4 accr = {0.f, 0.f, 0.f, 0.f}, acci = {0.f, 0.f, 0.f, 0.f};
   if (a < Ur) {
     const int p0 = ptr[a], p1 = ptr[a + 1];
     for (int p = p0; p < p1; ++p) {
       const int n = foci[p];
       const float xr = tn[2 * n], xi = tn[2 * n + 1];
       const size_t o = (size_t)ic[p] * Cp + i;   // ic in CSR order
-      const float yr = wr[o], yi = -wi[o];
-      accr = fmaf(xr, yr, fmaf(-xi, yi, accr));
-      acci = fmaf(xr, yi, fmaf(xi, yr, acci));
+      const f4 yr = *reinterpret_cast<const f4 *>(wr + o);
+      const f4 yi = -*reinterpret_cast<const f4 *>(wi + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        accr[e] = fmaf(xr, yr[e], fmaf(-xi, yi[e], accr[e]));
+        acci[e] = fmaf(xr, yi[e], fmaf(xi, yr[e], acci[e]));
+      }
     }
   }
   if (s_.done && *s_.done) return;   // read after the sums' loads were issued
-  sr[(size_t)a * Cp + i] = accr;
-  si[(size_t)a * Cp + i] = acci;
+  *reinterpret_cast<f4 *>(sr + (size_t)a * Cp + i) = accr;
+  *reinterpret_cast<f4 *>(si + (size_t)a * Cp + i) = acci;
 }
 
 __global__ __launch_bounds__(256) void focus_scatter(ScatterArgs a) {
-  focus_scatter_body(a, blockIdx.y, blockIdx.x * blockDim.x + threadIdx.x);
+  focus_scatter_body(a, blockIdx.y, 4 * (blockIdx.x * blockDim.x + threadIdx.x));
 }
 
 // Grouped over the plans of a batch: item h owns blocks [starts[h], starts[h+1]),
-// (Cp / 256) column blocks per reduced row.
+// (Cp / 1024) column blocks per reduced row.
 __global__ __launch_bounds__(256) void focus_scatter_grouped(const ScatterArgs *items,
                                                              const int *starts, int n) {
   const int b = blockIdx.x;
@@ -632,8 +639,8 @@ __global__ __launch_bounds__(256) void focus_scatter_grouped(const ScatterArgs *
     if (starts[mid] <= b) lo = mid; else hi = mid;
   }
   const ScatterArgs a = items[lo];
-  const int lb = b - starts[lo], bx = (a.Cp + 255) / 256;
-  focus_scatter_body(a, lb / bx, (lb % bx) * 256 + threadIdx.x);
+  const int lb = b - starts[lo], bx = (a.Cp + 1023) / 1024;
+  focus_scatter_body(a, lb / bx, 4 * ((lb % bx) * 256 + threadIdx.x));
 }
 
 // Split-precision scatter: the same S, written transposed as 16-bit term
@@ -934,7 +941,7 @@ static ScatterArgs scatter_args(const gswmtp_plan *p, const float *theta_new, bo
 hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,
                           hipStream_t s) {
   const Dims &d = p->d;
-  hipLaunchKernelGGL(focus_scatter, dim3((d.Cp + 255) / 256, d.Urp), dim3(256), 0, s,
+  hipLaunchKernelGGL(focus_scatter, dim3((d.Cp + 1023) / 1024, d.Urp), dim3(256), 0, s,
                      scatter_args(p, theta_new, honour_done));
   return hipGetLastError();
 }
@@ -943,7 +950,7 @@ size_t scatter_args_bytes() { return sizeof(ScatterArgs); }
 int fill_scatter_args(const gswmtp_plan *p, void *out) {
   const ScatterArgs a = scatter_args(p, p->b.theta_new, true);
   std::memcpy(out, &a, sizeof a);
-  return ((p->d.Cp + 255) / 256) * p->d.Urp;
+  return ((p->d.Cp + 1023) / 1024) * p->d.Urp;
 }
 hipError_t launch_scatter_grouped(const void *d_items, const int *d_starts, int n, int blocks,
                                   hipStream_t s) {
