@@ -408,7 +408,8 @@ GatherCtx gather_ctx(const gswmtp_plan *p) {
   return g;
 }
 
-GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split) {
+GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split,
+                     int min_chunk_div) {
   GemmSched s;
   s.tile = tile;
   s.tiles_m = M / tile.bm;
@@ -419,10 +420,11 @@ GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_spl
   s.n_tail = 0;
   s.split = 1;
   // Split the last round when it would leave more than a quarter of the CUs
-  // idle; each chunk keeps at least two K stages.
+  // idle; each chunk keeps at least two K stages and KT / min_chunk_div.
   if (allow_split && r > 0 && r * 4 < cus * 3 && KT >= 4) {
     int split = cus / r;
     if (split > KT / 2) split = KT / 2;
+    if (min_chunk_div > 0 && split > min_chunk_div) split = min_chunk_div;
     if (split >= 2) {
       s.t_dp = q * cus;
       s.n_tail = r;

@@ -422,7 +422,10 @@ hipError_t launch_grid_scatter(const gswmtp_plan *p, const float *theta_new, flo
 // Gather partials per focus of the plan's forward form.
 int gather_partials(const gswmtp_plan *p);
 int gather_ld(const gswmtp_plan *p);   // gather partial row stride: nf rounded up to even
-GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split);
+// min_chunk_div > 0: at most that many K chunks per tail tile, so each keeps
+// at least KT / min_chunk_div stages (and never fewer than two).
+GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split,
+                     int min_chunk_div = 0);
 
 // Grouped launches over the plans of a batch (float32 products).
 struct GroupedLaunch {

@@ -965,12 +965,18 @@ void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
   D.Urp = (int)round_up(D.Ur, kPadRows);
   const bool split_mode = is_split(p);
   const int terms = split_terms_of(p->precision);
+  // K chunks of the 16-bit products keep at least a quarter of K: their
+  // stages are short, so the chunks' fixed cost and the partials' traffic
+  // outweigh a shorter last round (1152 x 1920 pupil, 1000 foci: 4 chunks
+  // per tail tile beat 9 by 1.8% per pass; float32, whose stages take ~2.7x
+  // longer, is fastest at 9).
+  const int chunk_div = split_mode ? 4 : 0;
   p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp,
                             choose_tile(D.Urp, D.Cp, split_mode, terms, p->cus), p->cus,
-                            split_enabled());
+                            split_enabled(), chunk_div);
   p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp,
                             choose_tile(D.Rp, D.Cp, split_mode, terms, p->cus), p->cus,
-                            split_enabled());
+                            split_enabled(), chunk_div);
   // Grid form (float32): when the foci fill a quarter or more of the reduced
   // grid and are many enough to repay its extra launches (measured
   // crossover: the per-focus gather and scatter cost ~0.09 us per focus and
