@@ -348,6 +348,15 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project(CgemmArgs a) {
   for (int i = 0; i < MB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
+      size_t oc[4];
+      float av[4];   // amplitudes read with the partials, not after them
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int m, n;
+        tile_slot_pos<BM, BN>(tid, i, j, 4 * g + q, m, n);
+        oc[q] = (size_t)(m0 + m) * a.ldc + n0 + n;
+        av[q] = a.amp[oc[q]];
+      }
       float sr[4] = {0.f, 0.f, 0.f, 0.f}, si[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
       for (int c = 0; c < a.split; ++c) {
@@ -362,13 +371,10 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project(CgemmArgs a) {
       if (a.done && *a.done) return;   // read after the partial sums
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        int m, n;
-        tile_slot_pos<BM, BN>(tid, i, j, 4 * g + q, m, n);
-        const size_t o = (size_t)(m0 + m) * a.ldc + n0 + n;
         float pr, pi;
-        project_amp(sr[q], si[q], a.amp[o], pr, pi);
-        a.cr[o] = pr;
-        a.ci[o] = pi;
+        project_amp(sr[q], si[q], av[q], pr, pi);
+        a.cr[oc[q]] = pr;
+        a.ci[oc[q]] = pi;
       }
     }
 }

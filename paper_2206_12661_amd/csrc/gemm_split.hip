@@ -755,6 +755,11 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
   for (int i = 0; i < MB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
+      int m, n;
+      tile_slot_pos<BM, BN, COLS>(tid, i, j, 4 * g, m, n);   // rows m .. m + 3, column n
+      float av[4];   // amplitudes read with the partials, not after them
+#pragma unroll
+      for (int q = 0; q < 4; ++q) av[q] = a.amp[(size_t)(m0 + m + q) * a.ldc + n0 + n];
       float sr[4] = {0.f, 0.f, 0.f, 0.f}, si[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
       for (int c = 0; c < a.split; ++c) {
@@ -767,13 +772,11 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
         }
       }
       if (a.done && *a.done) return;   // read after the partial sums
-      int m, n;
-      tile_slot_pos<BM, BN, COLS>(tid, i, j, 4 * g, m, n);   // rows m .. m + 3, column n
       unsigned short tr[NT][4], ti[NT][4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         float pr, pi;
-        project_amp(sr[q], si[q], a.amp[(size_t)(m0 + m + q) * a.ldc + n0 + n], pr, pi);
+        project_amp(sr[q], si[q], av[q], pr, pi);
         split_terms<BF, NT>(pr, &tr[0][q], 4);
         split_terms<BF, NT>(pi, &ti[0][q], 4);
       }
