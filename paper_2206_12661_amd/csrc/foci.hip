@@ -776,15 +776,16 @@ __global__ __launch_bounds__(256) void focus_scatter_split_grouped(const Scatter
 }  // namespace
 
 hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
-                                bool honour_done, hipStream_t s) {
+                                bool honour_done, hipStream_t s, unsigned short *out) {
   const Dims &d = p->d;
   const int *ic = p->b.csr_ic;
+  unsigned short *st = out ? out : p->b.ss;
   const dim3 grid(d.Cp / 64, d.Urp / 32);
   const int *done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
 #define SCATTER_SPLIT(BF, NT)                                                                  \
   hipLaunchKernelGGL((focus_scatter_split<BF, NT>), grid, dim3(256), 0, s, theta_new, p->b.wc_r, \
-                     p->b.wc_i, ic, p->b.csr_ptr, p->b.csr_foci, p->b.ss, d.Ur, d.Urp, d.Cp,     \
-                     scale, done)
+                     p->b.wc_i, ic, p->b.csr_ptr, p->b.csr_foci, st, d.Ur, d.Urp, d.Cp, scale,   \
+                     done)
   switch (p->precision) {
     case GSWMTP_BF16X3: SCATTER_SPLIT(true, 2); break;
     case GSWMTP_FP16X3: SCATTER_SPLIT(false, 2); break;
@@ -792,6 +793,79 @@ hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, fl
     default: return hipErrorInvalidValue;
   }
 #undef SCATTER_SPLIT
+  return hipGetLastError();
+}
+
+namespace {
+
+// Left operand of the re-associated adjoint, for plans in which every
+// reduced row a holds exactly one focus (its CSR position is then a): column
+// a of Omega_r^H times that focus's new value, A_s = Omega_r^H diag(Theta'),
+// as split planes in the layout of Omega_r^H's (k-blocked, K = reduced row).
+// Then E' = Omega_r^H S = A_s B with B the conjugated Omega_c rows of the
+// foci, fixed at plan time: the same sum as with the scatter's S, grouped
+// the other way.  Four consecutive k of one row per thread.
+template <bool BF, int NT>
+__global__ __launch_bounds__(256) void k_scale_adjoint_split(
+    const float *__restrict__ obr, const float *__restrict__ obi, const float *__restrict__ tn,
+    const int *__restrict__ foci, int Ur, int Rp, int Urp, unsigned short *__restrict__ as,
+    const int *done) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const size_t plane = (size_t)Rp * Urp;
+  const size_t idx = 4 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (idx >= plane) return;
+  // kblk_index(j, a, Rp) = (a / kKB) Rp kKB + j kKB + a % kKB
+  const int a0 = (int)(idx / ((size_t)Rp * kKB)) * kKB + (int)(idx % kKB);
+  const f4 vr = *reinterpret_cast<const f4 *>(obr + idx);
+  const f4 vi = *reinterpret_cast<const f4 *>(obi + idx);
+  float xr[4], xi[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int a = a0 + q;
+    const int n = a < Ur ? foci[a] : 0;
+    xr[q] = a < Ur ? tn[2 * n] : 0.f;
+    xi[q] = a < Ur ? tn[2 * n + 1] : 0.f;
+  }
+  if (done && *done) return;   // read after the loads were issued
+  unsigned short tr[NT][4], ti[NT][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float pr = fmaf(vr[q], xr[q], -vi[q] * xi[q]);
+    const float pi = fmaf(vr[q], xi[q], vi[q] * xr[q]);
+    split_terms<BF, NT>(pr, &tr[0][q], 4);
+    split_terms<BF, NT>(pi, &ti[0][q], 4);
+  }
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int s = 0; s < NT; ++s) {
+    const u2 wr = {(unsigned)tr[s][0] | ((unsigned)tr[s][1] << 16),
+                   (unsigned)tr[s][2] | ((unsigned)tr[s][3] << 16)};
+    const u2 wi = {(unsigned)ti[s][0] | ((unsigned)ti[s][1] << 16),
+                   (unsigned)ti[s][2] | ((unsigned)ti[s][3] << 16)};
+    *reinterpret_cast<u2 *>(as + (size_t)s * plane + idx) = wr;
+    *reinterpret_cast<u2 *>(as + (size_t)(NT + s) * plane + idx) = wi;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_scale_adjoint_split(const gswmtp_plan *p, bool honour_done, hipStream_t s) {
+  const Dims &d = p->d;
+  if (!p->scaled_adj || d.nf != d.Ur || d.Urp % kKB) return hipErrorInvalidValue;
+  const size_t quads = (size_t)d.Rp * d.Urp / 4;
+  const dim3 grid((unsigned)((quads + 255) / 256));
+  const int *done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+#define SCALE_ADJ(BF, NT)                                                                  \
+  hipLaunchKernelGGL((k_scale_adjoint_split<BF, NT>), grid, dim3(256), 0, s, p->b.ob_r,    \
+                     p->b.ob_i, p->b.theta_new, p->b.csr_foci, d.Ur, d.Rp, d.Urp, p->b.as_s, \
+                     done)
+  switch (p->precision) {
+    case GSWMTP_BF16X3: SCALE_ADJ(true, 2); break;
+    case GSWMTP_FP16X3: SCALE_ADJ(false, 2); break;
+    case GSWMTP_BF16X6: SCALE_ADJ(true, 3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SCALE_ADJ
   return hipGetLastError();
 }
 

@@ -909,10 +909,11 @@ SplitArgs split_args(const gswmtp_plan *p, bool forward, const unsigned short *b
 hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
                               const unsigned short *bt, float *cr, float *ci,
                               unsigned short *pt_out, bool honour_done, hipStream_t s,
-                              int phases) {
+                              int phases, const unsigned short *at) {
   const GemmSched &sc = forward ? p->sched_fwd : p->sched_bwd;
   const int nt = split_terms_of(p->precision);
   SplitArgs a = split_args(p, forward, bt, cr, ci, pt_out, honour_done);
+  if (at) a.a = at;   // same shape and layout as the default left operand
   if (nt < 2 || a.M % sc.tile.bm || a.N % sc.tile.bn || a.K % sc.tile.bk)
     return hipErrorInvalidValue;
   if (sc.tiles_m * sc.tile.bm != a.M || sc.tiles * sc.tile.bm * sc.tile.bn != a.M * a.N)

@@ -105,6 +105,12 @@ struct Bufs {
   unsigned short *ps = nullptr;          // pupil field P^T    [2][NT] x [Cp][Rp]
   unsigned short *ss = nullptr;          // scatter S^T        [2][NT] x [Cp][Urp]
   unsigned short *xs = nullptr;          // operator-call P^T  [2][NT] x [Cp][Rp]
+  // adjoint re-associated when every reduced row holds one focus:
+  // E' = (Omega_r^H diag Theta') conj(Omega_c rows of the foci)
+  float *ob_r = nullptr, *ob_i = nullptr;   // Omega_r^H float32, as_b's layout [Rp][Urp]
+  unsigned short *as_s = nullptr;        // Omega_r^H diag Theta' [2][NT] x [Rp][Urp]
+  unsigned short *bs = nullptr;          // conj Omega_c rows      [2][NT] x [Cp][Urp]
+  float *unit = nullptr;                 // [2 nf] unit focal values (plan time)
   // grid form (float32): the second product of Eq. 2 formed densely
   float *lt_r = nullptr, *lt_i = nullptr;   // L^T            [Cp][Urp]
   float *wt_r = nullptr, *wt_i = nullptr;   // Omega_c        [Cp][Ucp]
@@ -373,6 +379,9 @@ struct gswmtp_plan {
   // G = L Omega_c^T, and the scatter product S = Theta'_grid conj(Omega_c)
   bool grid_form = false;
   gswmtp::GemmSched sched_f1, sched_f2, sched_a1;
+  // split modes with one focus in every reduced row: the adjoint's left
+  // operand carries Theta' (no scatter; the right operand is fixed)
+  bool scaled_adj = false;
   int cus = 256;
   int amp_exp = 0;                        // split modes: P carries amp * 2^amp_exp
   void *pool0 = nullptr, *pool1 = nullptr;
@@ -400,9 +409,12 @@ GatherCtx gather_ctx(const gswmtp_plan *p);
 hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
                               const unsigned short *bt, float *cr, float *ci,
                               unsigned short *pt_out, bool honour_done, hipStream_t s,
-                              int phases = 3);
+                              int phases = 3, const unsigned short *at = nullptr);
+// out: the S^T planes written (null: the plan's scatter buffer)
 hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
-                                bool honour_done, hipStream_t s);
+                                bool honour_done, hipStream_t s, unsigned short *out = nullptr);
+// Omega_r^H diag(Theta') as split planes (plans with scaled_adj)
+hipError_t launch_scale_adjoint_split(const gswmtp_plan *p, bool honour_done, hipStream_t s);
 hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s);
 hipError_t launch_grad_field(const gswmtp_plan *p, const float *g, hipStream_t s);
 hipError_t launch_scatter(const gswmtp_plan *p, const float *theta_new, bool honour_done,

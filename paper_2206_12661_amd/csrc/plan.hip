@@ -552,7 +552,7 @@ __global__ void k_expand_real(const float *xr, const int *row_pos, const int *co
 template <bool BF, int NT>
 __global__ void k_omega_r_split(const double *coord, const int *kept, int Rk, const double *fu,
                                 const double *fuz, int Ur, double s, int Rp, int Urp,
-                                unsigned short *af, unsigned short *ab) {
+                                unsigned short *af, unsigned short *ab, float *obr, float *obi) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (size_t)Rp * Urp) return;
   const int j = (int)(id / Urp), a = (int)(id % Urp);
@@ -571,6 +571,17 @@ __global__ void k_omega_r_split(const double *coord, const int *kept, int Rk, co
     ab[(size_t)q * plane + ob] = tr[q];
     ab[(size_t)(NT + q) * plane + ob] = tc[q];
   }
+  if (obr) {   // the float32 values the planes split, for the scaled adjoint
+    obr[ob] = re;
+    obi[ob] = -im;
+  }
+}
+
+__global__ void k_fill_unit(float *t, int nf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  t[2 * i] = 1.f;
+  t[2 * i + 1] = 0.f;
 }
 
 // Pupil field from a phase as split planes P^T [re/im][term] x [Cp][Rp]
@@ -833,11 +844,15 @@ hipError_t stage_forward(gswmtp_plan *p, bool done, hipStream_t s) {
   return forward_products(p, p->b.p_r, p->b.p_i, done, s);
 }
 hipError_t stage_scatter(gswmtp_plan *p, bool done, hipStream_t s) {
+  if (p->scaled_adj) return launch_scale_adjoint_split(p, done, s);
   if (is_split(p)) return launch_scatter_split(p, p->b.theta_new, 1.f, done, s);
   return scatter_products(p, p->b.theta_new, done, s);
 }
 // phases: 1 the product launch, 2 its split-K tail launch, 3 both.
 hipError_t stage_adjoint(gswmtp_plan *p, bool done, hipStream_t s, int phases = 3) {
+  if (p->scaled_adj)
+    return launch_cgemm_split(p, false, EPI_PROJECT, p->b.bs, nullptr, nullptr, p->b.ps, done, s,
+                              phases, p->b.as_s);
   if (is_split(p))
     return launch_cgemm_split(p, false, EPI_PROJECT, p->b.ss, nullptr, nullptr, p->b.ps, done, s,
                               phases);
@@ -990,6 +1005,14 @@ void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
     if (std::strcmp(sf, "grid") == 0 && !split_mode) p->grid_form = true;
   }
   D.Ucp = (int)round_up(D.Uc, kPadCols);
+  // Split modes with one focus in every reduced row (N = U_r, e.g. random
+  // foci): the adjoint takes Omega_r^H diag(Theta') as its left operand and
+  // the conjugated Omega_c rows of the foci, fixed at plan time, as its
+  // right one, in place of the per-pass scatter into S.
+  // GSWMTP_ADJOINT=scatter keeps the scatter.
+  p->scaled_adj = split_mode && !p->grid_form && D.nf == D.Ur;
+  if (const char *sa = std::getenv("GSWMTP_ADJOINT"))
+    if (std::strcmp(sa, "scatter") == 0) p->scaled_adj = false;
   if (p->grid_form) {
     p->sched_f1 = make_sched(D.Cp, D.Urp, D.Rp, choose_tile(D.Cp, D.Urp, false), p->cus,
                              split_enabled());
@@ -1035,6 +1058,11 @@ void carve_pool1(Carver &c, Bufs &b, const gswmtp_plan *p) {
   b.ps = c.take<unsigned short>(2 * nt * Cp * Rp);
   b.xs = c.take<unsigned short>(2 * nt * Cp * Rp);
   b.ss = c.take<unsigned short>(2 * nt * Cp * Urp);
+  const size_t sa = p->scaled_adj ? 1 : 0;
+  b.ob_r = c.take<float>(sa * Rp * Urp); b.ob_i = c.take<float>(sa * Rp * Urp);
+  b.as_s = c.take<unsigned short>(sa * 2 * nt * Rp * Urp);
+  b.bs = c.take<unsigned short>(sa * 2 * nt * Cp * Urp);
+  b.unit = c.take<float>(sa * 2 * nf);
   const size_t gf = p->grid_form ? 1 : 0;
   b.lt_r = c.take<float>(gf * Cp * Urp); b.lt_i = c.take<float>(gf * Cp * Urp);
   b.wt_r = c.take<float>(gf * Cp * Ucp); b.wt_i = c.take<float>(gf * Cp * Ucp);
@@ -1207,7 +1235,8 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   if (split) {
 #define OMEGA(BF, NT)                                                                          \
   hipLaunchKernelGGL((k_omega_r_split<BF, NT>), grid1(Rp * Urp), dim3(256), 0, s, rcoord, rkept, \
-                     D.Rk, rfu, rfz, D.Ur, s_r, D.Rp, D.Urp, b.as_f, b.as_b)
+                     D.Rk, rfu, rfz, D.Ur, s_r, D.Rp, D.Urp, b.as_f, b.as_b,             \
+                     p->scaled_adj ? b.ob_r : nullptr, p->scaled_adj ? b.ob_i : nullptr)
     DISPATCH_SPLIT(p->precision, OMEGA)
 #undef OMEGA
   } else {
@@ -1216,6 +1245,10 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
   }
   hipLaunchKernelGGL(k_omega_c, grid1(Uc * Cp), dim3(256), 0, s, ccoord, ckept, D.Ck, cfu, cfz,
                      D.Uc, s_c, D.Cp, b.wc_r, b.wc_i);
+  if (p->scaled_adj) {   // right operand of the scaled adjoint: S^T for unit Theta'
+    hipLaunchKernelGGL(k_fill_unit, grid1(nf), dim3(256), 0, s, b.unit, (int)nf);
+    HIP_TRY(p, launch_scatter_split(p, b.unit, 1.f, false, s, b.bs));
+  }
   if (p->grid_form)
     hipLaunchKernelGGL(k_grid_tables, grid1(Ucp * Cp), dim3(256), 0, s, b.wc_r, b.wc_i, D.Uc,
                        D.Cp, D.Ucp, b.wt_r, b.wt_i, b.wn_i);
@@ -1792,7 +1825,9 @@ const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage) {
   switch (stage) {
     case 0: return cgemm_kernel_name(p, true, EPI_GATHER);
     case 1: return "focus_update";
-    case 2: return split ? "focus_scatter_split" : "focus_scatter";
+    case 2:
+      if (p->scaled_adj) return "k_scale_adjoint_split";
+      return split ? "focus_scatter_split" : "focus_scatter";
     case 3: return cgemm_kernel_name(p, false, EPI_PROJECT);
     case 4:
       if (p->sched_bwd.n_tail == 0) return "";

@@ -3,7 +3,8 @@
 A plan's batched result must equal its single-plan result: bit for bit when
 both run the same tiles with no K split and the per-focus form of the second
 product (the batch never splits K and always gathers per focus; single
-plans do the same under GSWMTP_NO_SPLITK=1 and GSWMTP_SECOND=gather), and
+plans do the same under GSWMTP_NO_SPLITK=1 and GSWMTP_SECOND=gather, and in
+the split modes, where the batch always scatters into S, GSWMTP_ADJOINT=scatter), and
 within float32 rounding of the oracle-tested single path otherwise.  Graph replay must equal eager launches
 bit for bit.
 """
@@ -223,9 +224,12 @@ def test_batch_rejects(g):
 @pytest.mark.parametrize("mode", ["bf16x3", "fp16x3", "bf16x6"])
 def test_split_batch_bit_exact_vs_single(g, monkeypatch, mode):
     """Split-precision plans batched: the single-plan product loops on the
-    same tiles with no K split, so every plan's result equals its
-    single-plan result (GSWMTP_NO_SPLITK=1) bit for bit."""
+    same tiles with no K split, and the batch always scatters into S, so
+    every plan's result equals its single-plan result bit for bit under
+    GSWMTP_NO_SPLITK=1 and GSWMTP_ADJOINT=scatter (single plans with one
+    focus per reduced row otherwise re-associate the adjoint)."""
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
+    monkeypatch.setenv("GSWMTP_ADJOINT", "scatter")
     hs = _ragged_set()
     n_iter = 6
     announce(f"{mode} batch of {len(hs)} vs single plans, {n_iter} passes")
