@@ -746,58 +746,6 @@ __global__ __launch_bounds__(256) void focus_scatter_split(
                                    blockIdx.x, blockIdx.y, tr, ti);
 }
 
-// One plan's scatter as an item of the batched form's grouped launch.
-struct ScatterSplitArgs {
-  const float *tn, *wr, *wi;
-  const int *ic, *ptr, *foci;
-  unsigned short *st;
-  int Ur, Urp, Cp;
-  float scale;
-  const int *done;
-};
-
-template <bool BF, int NT>
-__global__ __launch_bounds__(256) void focus_scatter_split_grouped(const ScatterSplitArgs *items,
-                                                                   const int *starts, int n) {
-  __shared__ float tr[32][65], ti[32][65];
-  const int b = blockIdx.x;
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (starts[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  const ScatterSplitArgs &a = items[lo];
-  const int u = b - starts[lo], gx = a.Cp / 64;
-  focus_scatter_split_body<BF, NT>(a.tn, a.wr, a.wi, a.ic, a.ptr, a.foci, a.st, a.Ur, a.Urp,
-                                   a.Cp, a.scale, a.done, u % gx, u / gx, tr, ti);
-}
-
-}  // namespace
-
-hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
-                                bool honour_done, hipStream_t s, unsigned short *out) {
-  const Dims &d = p->d;
-  const int *ic = p->b.csr_ic;
-  unsigned short *st = out ? out : p->b.ss;
-  const dim3 grid(d.Cp / 64, d.Urp / 32);
-  const int *done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
-#define SCATTER_SPLIT(BF, NT)                                                                  \
-  hipLaunchKernelGGL((focus_scatter_split<BF, NT>), grid, dim3(256), 0, s, theta_new, p->b.wc_r, \
-                     p->b.wc_i, ic, p->b.csr_ptr, p->b.csr_foci, st, d.Ur, d.Urp, d.Cp, scale,   \
-                     done)
-  switch (p->precision) {
-    case GSWMTP_BF16X3: SCATTER_SPLIT(true, 2); break;
-    case GSWMTP_FP16X3: SCATTER_SPLIT(false, 2); break;
-    case GSWMTP_BF16X6: SCATTER_SPLIT(true, 3); break;
-    default: return hipErrorInvalidValue;
-  }
-#undef SCATTER_SPLIT
-  return hipGetLastError();
-}
-
-namespace {
-
 // Left operand of the re-associated adjoint, for plans in which every
 // reduced row a holds exactly one focus (its CSR position is then a): column
 // a of Omega_r^H times that focus's new value, A_s = Omega_r^H diag(Theta'),
@@ -806,13 +754,13 @@ namespace {
 // foci, fixed at plan time: the same sum as with the scatter's S, grouped
 // the other way.  Four consecutive k of one row per thread.
 template <bool BF, int NT>
-__global__ __launch_bounds__(256) void k_scale_adjoint_split(
+__device__ __forceinline__ void scale_adjoint_body(
     const float *__restrict__ obr, const float *__restrict__ obi, const float *__restrict__ tn,
     const int *__restrict__ foci, int Ur, int Rp, int Urp, unsigned short *__restrict__ as,
-    const int *done) {
+    const int *done, size_t quad) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   const size_t plane = (size_t)Rp * Urp;
-  const size_t idx = 4 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const size_t idx = 4 * quad;
   if (idx >= plane) return;
   // kblk_index(j, a, Rp) = (a / kKB) Rp kKB + j kKB + a % kKB
   const int a0 = (int)(idx / ((size_t)Rp * kKB)) * kKB + (int)(idx % kKB);
@@ -847,7 +795,74 @@ __global__ __launch_bounds__(256) void k_scale_adjoint_split(
   }
 }
 
+template <bool BF, int NT>
+__global__ __launch_bounds__(256) void k_scale_adjoint_split(
+    const float *__restrict__ obr, const float *__restrict__ obi, const float *__restrict__ tn,
+    const int *__restrict__ foci, int Ur, int Rp, int Urp, unsigned short *__restrict__ as,
+    const int *done) {
+  scale_adjoint_body<BF, NT>(obr, obi, tn, foci, Ur, Rp, Urp, as, done,
+                             (size_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// One plan's scatter as an item of the batched form's grouped launch.
+// Plans with the re-associated adjoint (scaled != 0) form Omega_r^H diag
+// Theta' instead (obr, obi, as, Rp), one quad of k per thread.
+struct ScatterSplitArgs {
+  const float *tn, *wr, *wi;
+  const int *ic, *ptr, *foci;
+  unsigned short *st;
+  int Ur, Urp, Cp;
+  float scale;
+  const int *done;
+  const float *obr, *obi;
+  unsigned short *as;
+  int Rp, scaled;
+};
+
+template <bool BF, int NT>
+__global__ __launch_bounds__(256) void focus_scatter_split_grouped(const ScatterSplitArgs *items,
+                                                                   const int *starts, int n) {
+  __shared__ float tr[32][65], ti[32][65];
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (starts[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const ScatterSplitArgs &a = items[lo];
+  const int u = b - starts[lo], gx = a.Cp / 64;
+  if (a.scaled) {   // uniform per block
+    scale_adjoint_body<BF, NT>(a.obr, a.obi, a.tn, a.foci, a.Ur, a.Rp, a.Urp, a.as, a.done,
+                               (size_t)u * 256 + threadIdx.x);
+    return;
+  }
+  focus_scatter_split_body<BF, NT>(a.tn, a.wr, a.wi, a.ic, a.ptr, a.foci, a.st, a.Ur, a.Urp,
+                                   a.Cp, a.scale, a.done, u % gx, u / gx, tr, ti);
+}
+
 }  // namespace
+
+hipError_t launch_scatter_split(const gswmtp_plan *p, const float *theta_new, float scale,
+                                bool honour_done, hipStream_t s, unsigned short *out) {
+  const Dims &d = p->d;
+  const int *ic = p->b.csr_ic;
+  unsigned short *st = out ? out : p->b.ss;
+  const dim3 grid(d.Cp / 64, d.Urp / 32);
+  const int *done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+#define SCATTER_SPLIT(BF, NT)                                                                  \
+  hipLaunchKernelGGL((focus_scatter_split<BF, NT>), grid, dim3(256), 0, s, theta_new, p->b.wc_r, \
+                     p->b.wc_i, ic, p->b.csr_ptr, p->b.csr_foci, st, d.Ur, d.Urp, d.Cp, scale,   \
+                     done)
+  switch (p->precision) {
+    case GSWMTP_BF16X3: SCATTER_SPLIT(true, 2); break;
+    case GSWMTP_FP16X3: SCATTER_SPLIT(false, 2); break;
+    case GSWMTP_BF16X6: SCATTER_SPLIT(true, 3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SCATTER_SPLIT
+  return hipGetLastError();
+}
 
 hipError_t launch_scale_adjoint_split(const gswmtp_plan *p, bool honour_done, hipStream_t s) {
   const Dims &d = p->d;
@@ -874,8 +889,10 @@ size_t scatter_split_args_bytes() { return sizeof(ScatterSplitArgs); }
 int fill_scatter_split_args(const gswmtp_plan *p, void *out) {
   const Dims &d = p->d;
   ScatterSplitArgs a{p->b.theta_new, p->b.wc_r, p->b.wc_i, p->b.csr_ic, p->b.csr_ptr,
-                     p->b.csr_foci, p->b.ss, d.Ur, d.Urp, d.Cp, 1.f, p->b.ctrl + CTRL_DONE};
+                     p->b.csr_foci, p->b.ss, d.Ur, d.Urp, d.Cp, 1.f, p->b.ctrl + CTRL_DONE,
+                     p->b.ob_r, p->b.ob_i, p->b.as_s, d.Rp, p->scaled_adj ? 1 : 0};
   std::memcpy(out, &a, sizeof a);
+  if (p->scaled_adj) return (int)(((size_t)d.Rp * d.Urp / 4 + 255) / 256);
   return (d.Cp / 64) * (d.Urp / 32);
 }
 

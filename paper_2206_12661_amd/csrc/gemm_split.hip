@@ -949,7 +949,9 @@ size_t split_args_bytes() { return sizeof(SplitArgs); }
 int fill_split_args(const gswmtp_plan *p, bool forward, const GemmTile &tl, bool honour_done,
                     void *out) {
   SplitArgs a = forward ? split_args(p, true, p->b.ps, nullptr, nullptr, nullptr, honour_done)
-                        : split_args(p, false, p->b.ss, nullptr, nullptr, p->b.ps, honour_done);
+                        : split_args(p, false, p->scaled_adj ? p->b.bs : p->b.ss, nullptr,
+                                     nullptr, p->b.ps, honour_done);
+  if (!forward && p->scaled_adj) a.a = p->b.as_s;   // the re-associated adjoint
   a.tiles_m = a.M / tl.bm;
   a.t_dp = a.tiles_m * (a.N / tl.bn);
   a.split = 1;

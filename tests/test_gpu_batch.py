@@ -3,8 +3,8 @@
 A plan's batched result must equal its single-plan result: bit for bit when
 both run the same tiles with no K split and the per-focus form of the second
 product (the batch never splits K and always gathers per focus; single
-plans do the same under GSWMTP_NO_SPLITK=1 and GSWMTP_SECOND=gather, and in
-the split modes, where the batch always scatters into S, GSWMTP_ADJOINT=scatter), and
+plans do the same under GSWMTP_NO_SPLITK=1 and GSWMTP_SECOND=gather; in the
+split modes every plan keeps its own adjoint form, scatter or re-associated), and
 within float32 rounding of the oracle-tested single path otherwise.  Graph replay must equal eager launches
 bit for bit.
 """
@@ -221,24 +221,30 @@ def test_batch_rejects(g):
         assert e.value.status == -1
 
 
+@pytest.mark.parametrize("form", ["own", "scatter"])
 @pytest.mark.parametrize("mode", ["bf16x3", "fp16x3", "bf16x6"])
-def test_split_batch_bit_exact_vs_single(g, monkeypatch, mode):
+def test_split_batch_bit_exact_vs_single(g, monkeypatch, mode, form):
     """Split-precision plans batched: the single-plan product loops on the
-    same tiles with no K split, and the batch always scatters into S, so
-    every plan's result equals its single-plan result bit for bit under
-    GSWMTP_NO_SPLITK=1 and GSWMTP_ADJOINT=scatter (single plans with one
-    focus per reduced row otherwise re-associate the adjoint)."""
+    same tiles with no K split (GSWMTP_NO_SPLITK=1), and every plan keeps its
+    adjoint form in the batch (re-associated where each reduced row holds one
+    focus, the random cases here; scatter for the grid cases; scatter for
+    all under GSWMTP_ADJOINT=scatter), so every plan's result equals its
+    single-plan result bit for bit."""
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
-    monkeypatch.setenv("GSWMTP_ADJOINT", "scatter")
+    if form == "scatter":
+        monkeypatch.setenv("GSWMTP_ADJOINT", "scatter")
     hs = _ragged_set()
     n_iter = 6
-    announce(f"{mode} batch of {len(hs)} vs single plans, {n_iter} passes")
+    announce(f"{mode} batch of {len(hs)} vs single plans, {n_iter} passes, {form} adjoints")
     single = []
     for h in hs:
         with g.Plan(h, precision=mode) as p:
             p.iterate(n_iter)
             single.append(_state(p))
     plans = [g.Plan(h, precision=mode) for h in hs]
+    kinds = {p.stage_kernel(2) for p in plans}
+    assert kinds == ({"focus_scatter_split"} if form == "scatter"
+                     else {"focus_scatter_split", "k_scale_adjoint_split"})
     with g.Batch(plans) as b:
         assert b.tiles()["forward"] == "64x64" and b.tiles()["adjoint"] == "64x64"
         b.iterate(n_iter)
