@@ -276,8 +276,11 @@ int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_
  * in ms_out[GSWMTP_N_STAGES] (order: forward product with the fused focus
  * gather, focus update, scatter, adjoint product with the projection, and the
  * adjoint's split-K tail launch (0 work when the schedule has no tail: the
- * figure is then the event overhead alone)).  Changes the plan state exactly
- * as gswmtp_iterate(p, n_iter, 0) would. */
+ * figure is then the event overhead alone)).  In the split precisions, when
+ * every reduced row holds one focus, the scatter stage is the scaling of
+ * Omega^H by the new focal values (the adjoint of Eq. 2 bracketed the other
+ * way; no S is formed).  Changes the plan state exactly as
+ * gswmtp_iterate(p, n_iter, 0) would. */
 #define GSWMTP_N_STAGES 5
 int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out);
 
