@@ -51,6 +51,10 @@ def _load():
     lib.oracle_stats.restype = None
     lib.oracle_weight_update.argtypes = [ctypes.c_int, _D, _D, _D, _D]
     lib.oracle_weight_update.restype = None
+    lib.oracle_weight_update_ex.argtypes = [ctypes.c_int, _D, _D, _D, _D, ctypes.c_int, _D, _D]
+    lib.oracle_weight_update_ex.restype = None
+    lib.oracle_project.argtypes = [ctypes.c_int, _D, _D, _D, _D]
+    lib.oracle_project.restype = None
     lib.oracle_gsw.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
                                ctypes.c_double, ctypes.c_int, _D, _D, _D, _D, _D, ctypes.c_int,
                                ctypes.c_double, _D, _I, _D]
@@ -136,15 +140,39 @@ def stats(theta, target, amplitude) -> dict:
     return {"xi": out[0], "eta": out[1], "uniformity": out[2], "sum_I": out[3]}
 
 
-def weight_update(theta, target, w):
-    """One weight update + focal-field update; returns (w_new, theta_new)."""
+def weight_update(theta, target, w, weighting: str = "gsw", fixed=None, measured=None):
+    """One weight update + focal-field update (Algorithm 1); returns
+    (w_new, theta_new).  This calls the same C function that every pass of
+    ``gsw`` and ``gsw_measured_pass`` runs.  weighting "gs" keeps the weights
+    (plain GS, Sec. 2); fixed (complex [N], optional): frozen focal phasors
+    (phase fixing); measured (optional): camera intensities that replace
+    |theta|^2 in the weight update (Sec. 2 experiments)."""
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.complex128))
     target = _f64(target)
     w = _f64(w).copy()
     out = np.zeros_like(theta)
-    _load().oracle_weight_update(theta.shape[0], theta.view(np.float64).ctypes.data_as(_D),
-                                 _d(target), _d(w), out.view(np.float64).ctypes.data_as(_D))
+    fx = None if fixed is None else np.ascontiguousarray(np.asarray(fixed, dtype=np.complex128))
+    ms = None if measured is None else _f64(measured)
+    _load().oracle_weight_update_ex(theta.shape[0], theta.view(np.float64).ctypes.data_as(_D),
+                                    _d(target), _d(w), out.view(np.float64).ctypes.data_as(_D),
+                                    {"gsw": 0, "gs": 1}[weighting],
+                                    None if fx is None else fx.view(np.float64).ctypes.data_as(_D),
+                                    _d(ms))
     return w, out
+
+
+def project(amplitude, Ep):
+    """Phase-only projection of Algorithm 1 (the C function every pass runs):
+    phi = arg E' where A > 0 and E' != 0 (0 elsewhere), range (-pi, pi];
+    returns (phi, E = A exp(i phi))."""
+    amp = np.ascontiguousarray(np.asarray(amplitude, dtype=np.float64))
+    Ep = np.ascontiguousarray(np.asarray(Ep, dtype=np.complex128))
+    assert amp.shape == Ep.shape
+    phi = np.zeros(amp.shape)
+    E = np.zeros(amp.shape, dtype=np.complex128)
+    _load().oracle_project(amp.size, _d(amp), Ep.view(np.float64).ctypes.data_as(_D), _d(phi),
+                           E.view(np.float64).ctypes.data_as(_D))
+    return phi, E
 
 
 def gsw(holo, n_iter: Optional[int] = None, stop: float = 0.0, phi=None, w=None,

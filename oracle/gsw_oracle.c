@@ -215,38 +215,9 @@ void oracle_stats(int nf, const double *theta, const double *target, double n_ap
     out[3] = sI;
 }
 
-/* Weight update and focal-field update of Algorithm 1:
- *   w_n <- w_n sqrt(t_n / max(i_n, tau))          (generalised weighting)
- *   Theta'_n = w_n sqrt(target_n) Theta_n / |Theta_n|   (phasor 1 when Theta_n = 0)
- * The ratio uses the unit-sum intensities t and i (the paper's raw target / I
- * ratio would shrink every weight by the arbitrary field scale at every step);
- * tau keeps it finite when a focus is dark. */
-void oracle_weight_update(int nf, const double *theta, const double *target, double *w,
-                          double *theta_new)
-{
-    double sI = 0.0, sT = 0.0;
-    for (int n = 0; n < nf; ++n) {
-        sI += theta[2 * n] * theta[2 * n] + theta[2 * n + 1] * theta[2 * n + 1];
-        sT += target[n];
-    }
-    for (int n = 0; n < nf; ++n) {
-        double re = theta[2 * n], im = theta[2 * n + 1];
-        double I = re * re + im * im;
-        double in = sI > 0.0 ? I / sI : 0.0;
-        double tn = target[n] / sT;
-        w[n] *= sqrt(tn / (in > ORACLE_TAU ? in : ORACLE_TAU));
-        double mag = sqrt(I);
-        double pr = 1.0, pi = 0.0;
-        if (mag > 0.0) { pr = re / mag; pi = im / mag; }
-        double a = w[n] * sqrt(target[n]);
-        theta_new[2 * n] = a * pr;
-        theta_new[2 * n + 1] = a * pi;
-    }
-}
-
 /* Phase-only projection of Algorithm 1: phi = arg E' where A > 0 (0 elsewhere
  * and where E' = 0), range (-pi, pi]; then E = A exp(i phi). */
-static void project(int np, const double *amp, const double *Ep, double *phi, double *E)
+void oracle_project(int np, const double *amp, const double *Ep, double *phi, double *E)
 {
     for (int p = 0; p < np; ++p) {
         double ph = 0.0;
@@ -260,8 +231,13 @@ static void project(int np, const double *amp, const double *Ep, double *phi, do
     }
 }
 
-/* New focal field of one pass with the variants of Sec. 2:
- *   weighting 0 (GSW, Algorithm 1): w <- w sqrt(t / max(i, tau));
+/* Weight update and focal-field update of one pass (Algorithm 1), with the
+ * variants of Sec. 2:
+ *   weighting 0 (GSW, Algorithm 1): w <- w sqrt(t / max(i, tau)), where
+ *   t = target / sum target and i = I / sum I.  The ratio uses these
+ *   unit-sum intensities (the paper's raw target / I ratio would shrink every
+ *   weight by the arbitrary field scale at every pass); tau keeps it finite
+ *   when a focus is dark;
  *   weighting 1 (plain GS, the comparison method): w unchanged;
  *   phasor: arg Theta of this pass, or, when fixed != NULL, the stored
  *   phasors (phase fixing: the focal phases are frozen);
@@ -269,8 +245,10 @@ static void project(int np, const double *amp, const double *Ep, double *phi, do
  *   phase (the camera-in-the-loop strategy of the experiments in Sec. 2):
  *   the weight update takes i from them (normalised to unit sum) instead of
  *   from |Theta|^2; the phasors still come from Theta.
- * theta_new = w sqrt(target) * phasor. */
-static void weight_update_ex(int nf, const double *theta, const double *target, double *w,
+ * theta_new = w sqrt(target) * phasor (phasor 1 where Theta_n = 0).  This is
+ * the one implementation of the update: the iteration, the measured pass and
+ * oracle_weight_update all call it. */
+void oracle_weight_update_ex(int nf, const double *theta, const double *target, double *w,
                              double *theta_new, int weighting, const double *fixed,
                              const double *measured)
 {
@@ -301,6 +279,15 @@ static void weight_update_ex(int nf, const double *theta, const double *target, 
         theta_new[2 * n] = a * pr;
         theta_new[2 * n + 1] = a * pi;
     }
+}
+
+/* Weight update and focal-field update of Algorithm 1 as printed (GSW
+ * weighting, phasors of this pass, computed intensities): the same function
+ * every pass of the iteration below runs. */
+void oracle_weight_update(int nf, const double *theta, const double *target, double *w,
+                          double *theta_new)
+{
+    oracle_weight_update_ex(nf, theta, target, w, theta_new, 0, NULL, NULL);
 }
 
 /* Phasors arg Theta_n (1 where Theta_n = 0). */
@@ -363,9 +350,9 @@ int oracle_gsw_ex(int ny, int nx, const double *amp, const double *u, const doub
             phasors(nf, th, fix);                     /* freeze the focal phases */
             recorded = 1;
         }
-        weight_update_ex(nf, th, target, w, thn, weighting, recorded ? fix : NULL, NULL);
+        oracle_weight_update_ex(nf, th, target, w, thn, weighting, recorded ? fix : NULL, NULL);
         adjoint_t(&t, thn, Ep);                       /* inverse propagation */
-        project((int)np, amp, Ep, phi, E);            /* phase-only constraint */
+        oracle_project((int)np, amp, Ep, phi, E);            /* phase-only constraint */
         ++done_passes;
     }
     if (iters_done) *iters_done = done_passes;
@@ -408,9 +395,9 @@ int oracle_gsw_measured_pass(int ny, int nx, const double *amp, const double *u,
     double st[4];
     oracle_stats(nf, th, target, n_ap, sum_a2, st);
     if (hist3) { hist3[0] = st[0]; hist3[1] = st[1]; hist3[2] = st[2]; }
-    weight_update_ex(nf, th, target, w, thn, 0, NULL, measured);
+    oracle_weight_update_ex(nf, th, target, w, thn, 0, NULL, measured);
     adjoint_t(&t, thn, Ep);
-    project((int)np, amp, Ep, phi, E);
+    oracle_project((int)np, amp, Ep, phi, E);
     tables_free(&t);
     rc = 0;
 done:

@@ -165,6 +165,97 @@ def test_weight_update_dark_focus_stays_finite():
     assert tn[0].imag == 0.0 and tn[0].real > 0.0          # phasor 1 for a zero field
 
 
+def _q(x):
+    return float(Fraction(str(x)))
+
+
+@pytest.mark.parametrize("case", ["gsw", "gs", "fixed", "measured"])
+def test_weight_update_branches_hand_worked(case):
+    """Hand-worked cases (exact rationals) of every branch of the one update
+    function that each pass of the iteration runs: GSW with non-unit start
+    weights, plain GS, frozen focal phasors and camera intensities.  Target 2
+    at the second focus separates w sqrt(target) from w target; non-unit
+    start weights separate w0 sqrt(t/i) from sqrt(t/i)."""
+    g = json.load(open(os.path.join(GOLDEN, "weight_update_branches.json")))
+    c = g["cases"][case]
+    theta = np.array([complex(a, b) for a, b in g["theta"]])
+    target = np.array(g["target"], dtype=float)
+    fixed = None if "fixed" not in c else np.array([complex(_q(a), _q(b)) for a, b in c["fixed"]])
+    measured = None if "measured" not in c else np.array(c["measured"], dtype=float)
+    w, tn = oracle.weight_update(theta, target, np.array(g["w0"], dtype=float),
+                                 weighting=c["weighting"], fixed=fixed, measured=measured)
+    assert np.allclose(w, np.sqrt([_q(s) for s in c["w_squared"]]), rtol=1e-15, atol=0)
+    re = [math.sqrt(_q(a)) * _q(b) for a, b in c["theta_new_re"]]
+    im = [math.sqrt(_q(a)) * _q(b) for a, b in c["theta_new_im"]]
+    assert np.allclose(tn.real, re, rtol=1e-14, atol=1e-15)
+    assert np.allclose(tn.imag, im, rtol=1e-14, atol=1e-15)
+
+
+def test_projection_closed_form():
+    """Phase-only projection: the phase of E' at known angles, 0 where the
+    amplitude or E' is zero, -pi reported as +pi, and E = A exp(i phi)."""
+    ang = np.array([[0.3, -2.9, np.pi / 2], [-np.pi, 1.0, 2.0]])
+    mag = np.array([[2.0, 0.5, 7.0], [3.0, 0.0, 1.0]])
+    Ep = mag * np.exp(1j * ang)
+    Ep[1, 0] = complex(-3.0, -0.0)                 # angle -pi
+    amp = np.array([[1.0, 2.0, 0.0], [0.5, 1.0, 4.0]])
+    phi, E = oracle.project(amp, Ep)
+    expect = np.array([[0.3, -2.9, 0.0], [np.pi, 0.0, 2.0]])
+    assert np.allclose(phi, expect, rtol=0, atol=1e-15)
+    assert phi[1, 0] == np.pi
+    assert np.allclose(E, amp * np.exp(1j * expect), rtol=0, atol=1e-15)
+
+
+def _one_pass_composed(h, phi, w, weighting="gsw", fixed=None, measured=None):
+    """One pass of Algorithm 1 composed from the separately pinned pieces:
+    forward operator, weight/field update, adjoint operator, projection."""
+    th = oracle.forward(oracle.pupil_field(h, phi), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    w2, thn = oracle.weight_update(th, h.target, w, weighting=weighting, fixed=fixed,
+                                   measured=measured)
+    Ep = oracle.adjoint(thn, h.ny, h.nx, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    phi2, _ = oracle.project(h.amplitude, Ep)
+    return phi2, w2, th
+
+
+@pytest.mark.parametrize("weighting", ["gsw", "gs"])
+def test_gsw_pass_is_the_composition_of_pinned_pieces(weighting):
+    """Two passes of the iteration equal forward -> update -> adjoint ->
+    projection, twice, built from the functions pinned above (FFT, adjoint
+    identity, hand-worked update, projection)."""
+    h = _small(11, radius=7.0)
+    w0 = np.linspace(0.5, 2.0, h.n_foci)
+    r = oracle.gsw(h, n_iter=2, w=w0, weighting=weighting)
+    phi, w = np.asarray(h.phi0, np.float64), w0
+    for _ in range(2):
+        phi, w, _th = _one_pass_composed(h, phi, w, weighting)
+    on = h.amplitude > 0
+    assert np.max(np.abs(np.angle(np.exp(1j * (r["phi"] - phi)))[on])) < 1e-12
+    assert np.allclose(r["w"], w, rtol=1e-13, atol=0)
+
+
+def test_phase_fixed_and_measured_passes_are_compositions():
+    """Phase fixing from the second pass uses the second pass's own phasors
+    from then on; a measured pass takes its weights from the capture; both
+    are the composed pinned pieces."""
+    h = _small(12, radius=7.0)
+    r = oracle.gsw(h, n_iter=3, phase_fix=2)
+    phi, w = np.asarray(h.phi0, np.float64), np.ones(h.n_foci)
+    phi, w, _ = _one_pass_composed(h, phi, w)
+    th = oracle.forward(oracle.pupil_field(h, phi), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    frozen = th / np.abs(th)
+    for _ in range(2):
+        phi, w, _ = _one_pass_composed(h, phi, w, fixed=frozen)
+    on = h.amplitude > 0
+    assert np.max(np.abs(np.angle(np.exp(1j * (r["phi"] - phi)))[on])) < 1e-12
+    assert np.allclose(r["w"], w, rtol=1e-13, atol=0)
+    meas = np.random.default_rng(3).uniform(0.2, 1.0, h.n_foci)
+    w0 = np.linspace(1.0, 1.5, h.n_foci)
+    m = oracle.gsw_measured_pass(h, h.phi0, w0, meas)
+    phi_c, w_c, _ = _one_pass_composed(h, np.asarray(h.phi0, np.float64), w0, measured=meas)
+    assert np.max(np.abs(np.angle(np.exp(1j * (m["phi"] - phi_c)))[on])) < 1e-12
+    assert np.allclose(m["w"], w_c, rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("aperture", ["rect", "disc"])
 def test_single_focus_grating_closed_form(aperture):
     """One focus at a non-grid point, uniform amplitude: after one pass the
