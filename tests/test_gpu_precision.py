@@ -118,18 +118,18 @@ def test_full_size_forward_split(g, mode, case):
     assert err <= TOL[mode]
 
 
-@pytest.mark.parametrize("mode", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("case", ["config3", "512x2048-1060"])
 def test_full_size_pass_split(g, mode, case):
     """One split-precision pass at a large size from an identical state after
-    5 float32 passes; the weights at the mode's bar times the oracle's kappa
-    (the weight update's first-order gain), the new foci field times kappa
-    and c_E (the projection's).  The benchmark size (1152 x 1920, 1000 foci)
-    runs the 64 x 128 forward tiles on the direct loop and the 64 x 64
-    adjoint with its split-K tail; 512 x 2048 with 1060 foci runs 544 forward
-    tiles of 64 x 64 with 32 split-K tail tiles (gather epilogue in the tail
-    launch) and the adjoint's 128 tiles of 64 x 128 on the direct loop, every
-    one split in two K chunks (the tail kernel of the column-wave layout)."""
+    5 float32 passes, where the weight update's gain kappa is 1 (asserted):
+    weights and the new foci field at the mode's plain bar.  The benchmark
+    size (1152 x 1920, 1000 foci) runs the 64 x 128 forward tiles on the
+    direct loop and the re-associated 64 x 64 adjoint with its split-K tail;
+    512 x 2048 with 1060 foci runs 544 forward tiles of 64 x 64 with 32
+    split-K tail tiles (gather epilogue in the tail launch) and the adjoint's
+    128 tiles of 64 x 128 on the direct loop, every one split in two K chunks
+    (the tail kernel of the column-wave layout)."""
     h = _large_case(case)
     announce(f"large pass {case} {mode}")
     with g.Plan(h) as p:
@@ -148,19 +148,11 @@ def test_full_size_pass_split(g, mode, case):
     _, tn = oracle.weight_update(thk, h.target, w_k)
     a2 = np.abs(tn) ** 2
     kap = max(1.0, float(np.sqrt(np.sum(a2 / np.maximum(x, 1e-300)) / np.sum(a2))))
-    # c_E: the phase projection divides the back-propagated field's error by
-    # |E'| sample by sample (first-order gain, from the oracle's own E')
-    Ep = oracle.adjoint(tn, h.ny, h.nx, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
-    A2 = np.asarray(h.amplitude, np.float64).ravel() ** 2
-    m2 = np.abs(Ep).ravel() ** 2
-    on = A2 > 0
-    rms2 = np.sum(A2[on] * m2[on]) / np.sum(A2[on])
-    cE = max(1.0, float(np.sqrt(np.sum(A2[on] * rms2 / np.maximum(m2[on], 1e-300))
-                                / np.sum(A2[on]))))
     ew, et = rel_l2(w1, r["w"]), rel_l2(th1, r["theta"])
-    print(f"  {mode}: kappa {kap:.2f} c_E {cE:.2f} w {ew:.2e} theta {et:.2e}")
-    assert ew <= TOL[mode] * kap
-    assert et <= TOL[mode] * kap * cE
+    print(f"  {mode}: kappa {kap:.3f} w {ew:.2e} theta {et:.2e}")
+    assert kap < 1.01
+    assert ew <= TOL[mode]
+    assert et <= TOL[mode]
 
 
 @pytest.mark.parametrize("mode", MODES)

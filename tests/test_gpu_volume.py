@@ -187,6 +187,37 @@ def test_one_pass(g, name):
     assert rel_l2(th1, r["theta"]) <= FIELD_TOL * kap
 
 
+@pytest.mark.parametrize("mode", list(SPLIT_TOL))
+@pytest.mark.parametrize("name", ["random-3planes-96x128", "random-5planes-130x200-disc"])
+def test_one_pass_split_scaled_adjoint(g, mode, name):
+    """Split modes on random multi-plane foci: every reduced (row, z) pair
+    holds one focus, so the pass runs the re-associated adjoint (Omega_r^H
+    with its defocus factor, scaled by Theta', times the fixed conjugated
+    Omega_c rows).  One pass from the state after 5 float32 passes against
+    the oracle: weights and foci field at the mode's plain bar, the pupil
+    field at twice it (as for the focal-plane split passes)."""
+    h = _cases()[name]
+    announce(f"volume split one pass {mode} {name}")
+    with g.Plan(h) as p:
+        p.iterate(5)
+        phi_k, w_k, _ = p.state()
+    with g.Plan(h, precision=mode) as q:
+        assert q.stage_kernel(2) == "k_scale_adjoint_split"
+        q.set_state(phi_k, w_k, 0)
+        q.iterate(1)
+        phi1, w1, th1 = q.phase(), q.weights(), q.foci_field()
+    hk = synth_ofa.Hologram(h.name, h.ny, h.nx, h.amplitude, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy,
+                            h.target, phi_k, 1)
+    hk.fz = h.fz
+    r = oracle.gsw(hk, n_iter=1, w=w_k)
+    amp = np.asarray(h.amplitude, np.float64)
+    e = rel_l2(amp * np.exp(1j * phi1.astype(np.float64)), amp * np.exp(1j * r["phi"]))
+    ew, et = rel_l2(w1, r["w"]), rel_l2(th1, r["theta"])
+    print(f"  {mode}: w {ew:.2e} theta {et:.2e} E {e:.2e}")
+    assert ew <= SPLIT_TOL[mode] and et <= SPLIT_TOL[mode]
+    assert e <= 2 * SPLIT_TOL[mode]
+
+
 def test_trajectory_three_planes(g):
     """20 passes on three planes from the seeded start, bounded by the
     oracle's self-sensitivity (floored at 1e-5)."""
