@@ -265,6 +265,23 @@ int gswmtp_get_index(gswmtp_plan *p, gswmtp_index_info *info, int32_t *ix, int32
 int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta);
 int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E);
 
+/* gswmtp_forward_field for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid it): the same arguments, kernels and result,
+ * bit for bit, but the call's scratch (staging of E, the compacted pupil or
+ * its split planes, the grid form's intermediate products, the gather and
+ * split-K partials, the output staging) lives in one static device array of
+ * 64 MiB that the library holds on each GPU it runs on until the process
+ * ends, instead of the plan's own buffers.  The call allocates nothing and
+ * leaves the plan's buffers untouched.  Every call on a GPU shares that GPU's
+ * array (it keeps the last call's contents; the call clears it first), so
+ * calls that overlap on one GPU - from several host threads, on any plans -
+ * race; calls from one thread are ordered, since each returns after its
+ * result is copied out.  GSWMTP_E_NOMEM, with the bytes needed in
+ * gswmtp_last_error(p), when the plan's sizes need more than 64 MiB
+ * (roughly beyond 2.9 M pupil samples in FP32); GSWMTP_E_HIP if the array
+ * cannot be located on the device. */
+int gswmtp_forward_field_noalloc(gswmtp_plan *p, const float *E, float *theta);
+
 /* Gradient of L = sum_n g_n |Theta_n|^2 with respect to the current phase:
  *   dL/dphi = 2 Im(conj(E) * P^H(g * Theta)),
  * with Theta the field of the current phase.  dev_g: device float [n_foci];

@@ -93,6 +93,7 @@ _SIGNATURES = {
     "gswmtp_get_index": ([_P, ctypes.POINTER(gswmtp_index_info), _P, _P, _P, _P, _P, _P],
                          ctypes.c_int),
     "gswmtp_forward_field": ([_P, _P, _P], ctypes.c_int),
+    "gswmtp_forward_field_noalloc": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_adjoint_field": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_phase_gradient_device": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_time_stages": ([_P, ctypes.c_int, _P], ctypes.c_int),
@@ -402,14 +403,17 @@ class Plan:
                 "nx_kept": info.nx_kept, "n_aperture": info.n_aperture, "sum_a2": info.sum_a2}
 
     # -- operators ---------------------------------------------------------
-    def forward_field(self, E) -> np.ndarray:
-        """Theta = P(E) at the foci for a complex pupil field E [ny, nx]."""
+    def forward_field(self, E, noalloc: bool = False) -> np.ndarray:
+        """Theta = P(E) at the foci for a complex pupil field E [ny, nx].
+        noalloc: through gswmtp_forward_field_noalloc (scratch in the
+        library's static device array, same result)."""
         e = np.asarray(E, dtype=np.complex64)
         assert e.shape == (self.ny, self.nx)
         inter = np.ascontiguousarray(np.stack([e.real, e.imag], axis=-1).astype(np.float32))
         out = np.empty(2 * self.n_foci, np.float32)
         self._sync_stream()
-        self._check(self._lib.gswmtp_forward_field(self._h, inter.ctypes.data, out.ctypes.data))
+        fn = self._lib.gswmtp_forward_field_noalloc if noalloc else self._lib.gswmtp_forward_field
+        self._check(fn(self._h, inter.ctypes.data, out.ctypes.data))
         return out[0::2] + 1j * out[1::2]
 
     def adjoint_field(self, theta) -> np.ndarray:

@@ -14,6 +14,7 @@
 #include <string>
 #include <algorithm>
 #include <utility>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1276,6 +1277,36 @@ thread_local std::string g_last_create_error;
 // C ABI
 // ===========================================================================
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free operator call: one array per device
+// ---------------------------------------------------------------------------
+
+// 64 MiB covers the forward operator's scratch up to ~2.9 M pupil samples
+// (float32 or two-term split), e.g. 1152 x 1920 with 1000 foci (~36 MB).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of this device's copy of `scratch` (looked up once per
+// device, with that device current; host code never passes the array's name).
+hipError_t static_scratch_of(int device, char **out) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<char *>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 int gswmtp_version(void) { return GSWMTP_VERSION; }
@@ -1683,9 +1714,57 @@ int gswmtp_get_index(gswmtp_plan *p, gswmtp_index_info *info, int32_t *ix, int32
   return GSWMTP_OK;
 }
 
+static int forward_field_impl(gswmtp_plan *p, const float *E, float *theta);
+
 int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta) {
   if (!p || !E || !theta) return GSWMTP_E_INVAL;
   DeviceGuard g(p->device);
+  return forward_field_impl(p, E, theta);
+}
+
+int gswmtp_forward_field_noalloc(gswmtp_plan *p, const float *E, float *theta) {
+  if (!p || !E || !theta) return GSWMTP_E_INVAL;
+  DeviceGuard g(p->device);
+  char *base = nullptr;
+  HIP_TRY(p, static_scratch_of(p->device, &base));
+  // the forward call's scratch, carved from the static array in the plan's
+  // own sizes; the plan's buffers are put back however the call ends
+  const Dims &D = p->d;
+  const size_t np = (size_t)D.ny * D.nx, nf = D.nf;
+  const size_t Rp = D.Rp, Cp = D.Cp, Urp = D.Urp, Ucp = D.Ucp;
+  const size_t nt = (size_t)split_terms_of(p->precision);
+  const size_t gf = p->grid_form ? 1 : 0;
+  Carver c(base);
+  Bufs b = p->b;
+  b.iobuf = c.take<float>(2 * np);
+  b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
+  b.xs = c.take<unsigned short>(2 * nt * Cp * Rp);
+  b.lt_r = c.take<float>(gf * Cp * Urp); b.lt_i = c.take<float>(gf * Cp * Urp);
+  b.g_r = c.take<float>(gf * Urp * Ucp); b.g_i = c.take<float>(gf * Urp * Ucp);
+  b.gpart = c.take<float>(2 * (size_t)(Cp / 64) * ((nf + 1) & ~(size_t)1));
+  b.part = c.take<float>(part_floats_of(p));
+  b.theta_new = c.take<float>(2 * nf);
+  if (c.off > kStaticScratchBytes) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "forward_field_noalloc needs %zu bytes of scratch; the static "
+             "array holds %zu", c.off, kStaticScratchBytes);
+    return fail(p, GSWMTP_E_NOMEM, msg);
+  }
+  struct Restore {
+    gswmtp_plan *p;
+    Bufs saved;
+    ~Restore() { p->b = saved; }
+  } restore{p, p->b};
+  // the plan's own scratch starts zeroed at creation: so does this one
+  HIP_TRY(p, enter(p));
+  hipLaunchKernelGGL(k_fill_f, grid1(c.off / 4), dim3(256), 0, p->stream,
+                     reinterpret_cast<float *>(base), 0.f, c.off / 4);
+  HIP_TRY(p, hipGetLastError());
+  p->b = b;
+  return forward_field_impl(p, E, theta);
+}
+
+static int forward_field_impl(gswmtp_plan *p, const float *E, float *theta) {
   const Dims &D = p->d;
   const size_t np = (size_t)D.ny * D.nx;
   if (!finite_all(E, 2 * np)) return fail(p, GSWMTP_E_INVAL, "non-finite pupil field");
