@@ -584,8 +584,10 @@ hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-const char *cgemm_kernel_name(const gswmtp_plan *p, bool, int) {
-  return split_terms_of(p->precision) ? "cgemm_split_mfma" : "cgemm_f32_mfma";
+const char *cgemm_kernel_name(const gswmtp_plan *p, bool forward, int) {
+  if (!split_terms_of(p->precision)) return "cgemm_f32_mfma";
+  const GemmSched &sc = forward ? p->sched_fwd : p->sched_bwd;
+  return sc.tile.pipe == 3 ? "cgemm_split_d16" : "cgemm_split_mfma";
 }
 
 }  // namespace gswmtp

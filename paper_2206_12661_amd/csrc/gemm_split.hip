@@ -91,6 +91,7 @@ struct SplitArgs {
   GatherCtx g;                            // EPI_GATHER
   int phase;                              // 0: tiles and K chunks; 1: reduce tail chunks
   int tiles_m, t_dp, split;
+  int xgm;                                // 16x16-block loop: XCD groups along M (<= 1: none)
 };
 
 // Operand fragments of one MFMA k-step for the wave's MB x NB blocks: lane
@@ -793,6 +794,284 @@ __global__ __launch_bounds__(kThreads) void cgemm_tail_project_split(SplitArgs a
     }
 }
 
+// ---------------------------------------------------------------------------
+// The 16x16-block loop: tiles of BM x BN with BM a multiple of 16 (e.g.
+// 48 x 192, which covers a 1152 x 1920 product in 240 tiles, one round on
+// 256 CUs, where 64 x 64 tiles leave a split-K second round).  Four waves
+// side by side along N, each owning BN/4 rows of B^T, which it loads from HBM
+// straight into its MFMA fragment registers four k-steps ahead (no two waves
+// read the same B row); A is shared through a ring of four LDS stages, its
+// loads issued two stages before they are stored.  One k-step (32 k) per
+// stage, v_mfma_f32_16x16x32_{bf16,f16}: lane (l16, q) holds row l16 of a
+// 16-row block, k = 8 q .. 8 q + 7; accumulator item r is row 4 q + r,
+// column l16.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool BF>
+__device__ __forceinline__ v4f mfma16x16(u4 a, u4 b, v4f c) {
+  if constexpr (BF)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
+                                                  __builtin_bit_cast(v8h, b), c, 0, 0, 0);
+}
+
+// One k-step of MB x NB blocks; nb holds -Im B (sign bits flipped).  Each
+// accumulator takes its products in the order of mma_ab: per term pair
+// (small terms first) real part Ar Br then -Ai Bi, imaginary part Ar Bi then
+// Ai Br; consecutive MFMAs go to different accumulators.
+template <int MB, int NB, bool BF, int NT>
+__device__ __forceinline__ void mma16(const u4 (&fa)[MB][2 * NT], const u4 (&fb)[NB][2 * NT],
+                                      v4f (&accR)[MB][NB], v4f (&accI)[MB][NB]) {
+  u4 nb[NB][NT];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) nb[j][t] = fb[j][NT + t] ^ 0x80008000u;
+#pragma unroll
+  for (int s = NT - 1; s >= 0; --s)
+#pragma unroll
+    for (int ta = 0; ta <= s; ++ta) {
+      const int tb = s - ta;
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accR[i][j] = mfma16x16<BF>(fa[i][ta], fb[j][tb], accR[i][j]);
+          accI[i][j] = mfma16x16<BF>(fa[i][ta], fb[j][NT + tb], accI[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accR[i][j] = mfma16x16<BF>(fa[i][NT + ta], nb[j][tb], accR[i][j]);
+          accI[i][j] = mfma16x16<BF>(fa[i][NT + ta], fb[j][tb], accI[i][j]);
+        }
+    }
+}
+
+template <int BM, int BN, int NT, int EPI>
+constexpr int d16_lds_bytes() {
+  constexpr int ring = 4 * 2 * NT * BM * 4 * 16;              // four A stages
+  constexpr int tr = EPI == EPI_PROJECT ? 2 * NT * BN * (BM + 8) * 2 : 0;
+  return ring > tr ? ring : tr;
+}
+
+// Tile of schedule rank r with the ranks laid out in gm groups along M: group
+// g holds the M tiles g tiles_m / gm .. (g + 1) tiles_m / gm - 1 of every N
+// tile, M fastest, so that the ranks an XCD runs (one contiguous range of
+// them) read about 1/gm of A and a band of B instead of all of A.
+__device__ __forceinline__ int rank_tile(int r, int tiles_m, int tiles, int gm) {
+  if (gm <= 1 || tiles_m % gm) return r;
+  const int G = tiles / gm, tm = tiles_m / gm;
+  const int g = r / G, w = r % G;
+  return (w / tm) * tiles_m + g * tm + w % tm;
+}
+
+// The main loop over all of K; false when the done flag stops the product.
+template <int BM, int BN, bool BF, int NT>
+__device__ __forceinline__ bool d16_loop(const SplitArgs &a, int m0, int n0, int tid, u4 *lds,
+                                         v4f (&accR)[BM / 16][BN / 64],
+                                         v4f (&accI)[BM / 16][BN / 64]) {
+  constexpr int WTN = BN / 4, MB = BM / 16, NB = WTN / 16, PL = 2 * NT, CH = 4;
+  constexpr int LA = PL * BM * CH, NA = LA / kThreads, SA = LA;
+  static_assert(LA % kThreads == 0 && WTN % 16 == 0 && BM % 16 == 0, "d16 tile");
+  const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, q = lane >> 4;
+  const unsigned short *ga[NA];
+  int la[NA];
+#pragma unroll
+  for (int s_ = 0; s_ < NA; ++s_) {
+    const int id = tid + kThreads * s_;
+    const int c = id % CH, row = (id / CH) % BM, plane = id / (CH * BM);
+    ga[s_] = a.a + (size_t)plane * a.a_plane + (size_t)(m0 + row) * kKB + 8 * c;
+    la[s_] = (plane * BM + row) * CH + c;
+  }
+  // B^T row of lane (l16, q) in block j: n0 + WTN wave + 16 j + l16, k 8q .. 8q + 7
+  const unsigned short *gb = a.b + (size_t)(n0 + WTN * wave + l16) * kKB + 8 * q;
+  const int KT = a.K / kKB;
+  if (KT <= 0) return !(a.done && *a.done);
+  const int last = KT - 1;
+  u4 ra0[NA], ra1[NA];
+  u4 bq0[NB][PL], bq1[NB][PL], bq2[NB][PL], bq3[NB][PL];
+#define E_LOAD_A(RA, KT_)                                                                 \
+  do {                                                                                    \
+    const size_t o_ = (size_t)(KT_) * a.M * kKB;                                          \
+    _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) RA[s_] =                            \
+        *reinterpret_cast<const u4 *>(ga[s_] + o_);                                       \
+  } while (0)
+#define E_LOAD_B(BQ, KT_)                                                                 \
+  do {                                                                                    \
+    const size_t o_ = (size_t)(KT_) * a.N * kKB;                                          \
+    _Pragma("unroll") for (int j_ = 0; j_ < NB; ++j_)                                     \
+        _Pragma("unroll") for (int p_ = 0; p_ < PL; ++p_) BQ[j_][p_] =                    \
+            *reinterpret_cast<const u4 *>(gb + p_ * a.b_plane + (size_t)16 * j_ * kKB + o_); \
+  } while (0)
+#define E_STORE_A(RA, BUF)                                                                \
+  do {                                                                                    \
+    _Pragma("unroll") for (int s_ = 0; s_ < NA; ++s_) lds[(BUF) * SA + la[s_]] = RA[s_];  \
+  } while (0)
+#define E_READ_A(F, BUF)                                                                  \
+  do {                                                                                    \
+    _Pragma("unroll") for (int i_ = 0; i_ < MB; ++i_)                                     \
+        _Pragma("unroll") for (int p_ = 0; p_ < PL; ++p_) F[i_][p_] =                     \
+            lds[(BUF) * SA + (p_ * BM + 16 * i_ + l16) * CH + q];                         \
+  } while (0)
+  E_LOAD_A(ra0, 0);
+  E_LOAD_A(ra1, 1 < last ? 1 : last);
+  E_LOAD_B(bq0, 0);
+  E_LOAD_B(bq1, 1 < last ? 1 : last);
+  E_LOAD_B(bq2, 2 < last ? 2 : last);
+  E_LOAD_B(bq3, 3 < last ? 3 : last);
+  const int stop = a.done ? *a.done : 0;
+  asm volatile("" ::: "memory");
+  if (stop) return false;
+  E_STORE_A(ra0, 0);
+  E_LOAD_A(ra0, 2 < last ? 2 : last);
+  E_STORE_A(ra1, 1);
+  E_LOAD_A(ra1, 3 < last ? 3 : last);
+  __syncthreads();
+  u4 f0[MB][PL], f1[MB][PL];
+  E_READ_A(f0, 0);
+  // per step: NR fragment reads, NM MFMAs, NA stores, NV loads
+  constexpr int NR = MB * PL, NM = MB * NB * 2 * NT * (NT + 1), NV = NA + NB * PL;
+  static_assert(NM >= NR + NA + NV, "interleave pattern");
+  // Step s (stage s in LDS buffer s & 3, its A fragments in FA, its B in
+  // BQ): read stage s + 1's A fragments into FB while the MFMAs run, store
+  // stage s + 2 (in registers since two steps ago) into buffer (s + 2) & 3,
+  // issue the loads of stage s + 4 of A and B, one barrier.
+#define E_STEP(S, FA, FB, RA, BQ, B1, B2)                                                 \
+  do {                                                                                    \
+    E_READ_A(FB, B1);                                                                     \
+    mma16<MB, NB, BF, NT>(FA, BQ, accR, accI);                                            \
+    E_STORE_A(RA, B2);                                                                    \
+    E_LOAD_A(RA, (S) + 4 < last ? (S) + 4 : last);                                        \
+    E_LOAD_B(BQ, (S) + 4 < last ? (S) + 4 : last);                                        \
+    sched_read_mfma<NR>();                                                                \
+    sched_write_mfma<NA, 1>();                                                            \
+    sched_vmem_mfma<NV>();                                                                \
+    __builtin_amdgcn_sched_group_barrier(0x008, NM - NR - NA - NV, 0);                    \
+    __builtin_amdgcn_sched_barrier(0);                                                    \
+    __syncthreads();                                                                      \
+  } while (0)
+  int s = 0;
+  for (; s + 3 < KT; s += 4) {
+    E_STEP(s, f0, f1, ra0, bq0, 1, 2);
+    E_STEP(s + 1, f1, f0, ra1, bq1, 2, 3);
+    E_STEP(s + 2, f0, f1, ra0, bq2, 3, 0);
+    E_STEP(s + 3, f1, f0, ra1, bq3, 0, 1);
+  }
+  if (s < KT) E_STEP(s, f0, f1, ra0, bq0, 1, 2);
+  if (s + 1 < KT) E_STEP(s + 1, f1, f0, ra1, bq1, 2, 3);
+  if (s + 2 < KT) E_STEP(s + 2, f0, f1, ra0, bq2, 3, 0);
+#undef E_STEP
+#undef E_LOAD_A
+#undef E_LOAD_B
+#undef E_STORE_A
+#undef E_READ_A
+  return true;
+}
+
+// One whole tile per workgroup (no K split); epilogues: store float32 C, or
+// project onto the amplitude constraint and write the split planes of P^T.
+template <int BM, int BN, bool BF, int NT, int EPI>
+__global__ __launch_bounds__(kThreads) void cgemm_split_d16(SplitArgs a) {
+  constexpr int WTN = BN / 4, MB = BM / 16, NB = WTN / 16, PL = 2 * NT, TP = BM + 8;
+  __shared__ u4 lds[(d16_lds_bytes<BM, BN, NT, EPI>() + 15) / 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, q = lane >> 4;
+  const int t = rank_tile(xcd_tile(blockIdx.x, a.t_dp), a.tiles_m, a.t_dp, a.xgm);
+  const int m0 = (t % a.tiles_m) * BM, n0 = (t / a.tiles_m) * BN;
+  v4f accR[MB][NB], accI[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      accR[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  // the projection's amplitudes, read now and used after the main loop
+  float ampv[EPI == EPI_PROJECT ? MB : 1][EPI == EPI_PROJECT ? NB : 1][4];
+  if constexpr (EPI == EPI_PROJECT) {
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          ampv[i][j][r] = a.amp[(size_t)(m0 + 16 * i + 4 * q + r) * a.ldc + n0 + wave * WTN +
+                                16 * j + l16];
+  }
+  if (!d16_loop<BM, BN, BF, NT>(a, m0, n0, tid, lds, accR, accI)) return;
+  if constexpr (EPI == EPI_STORE) {
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int n = n0 + wave * WTN + 16 * j + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const size_t o = (size_t)(m0 + 16 * i + 4 * q + r) * a.ldc + n;
+          a.cr[o] = accR[i][j][r];
+          a.ci[o] = accI[i][j][r];
+        }
+      }
+  } else if constexpr (EPI == EPI_PROJECT) {
+    // project, split into terms, transpose the tile through LDS, then write
+    // rows of P^T [plane][n][m0 .. m0 + BM) in 16-byte runs
+    unsigned short *tt = reinterpret_cast<unsigned short *>(lds);
+    __syncthreads();   // operand stages are no longer read
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int nl = wave * WTN + 16 * j + l16, ml = 16 * i + 4 * q;
+        unsigned short tr[NT][4], ti[NT][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float pr, pi;
+          project_amp(accR[i][j][r], accI[i][j][r], ampv[i][j][r], pr, pi);
+          split_terms<BF, NT>(pr, &tr[0][r], 4);
+          split_terms<BF, NT>(pi, &ti[0][r], 4);
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const u2 vr = {(unsigned)tr[u][0] | ((unsigned)tr[u][1] << 16),
+                         (unsigned)tr[u][2] | ((unsigned)tr[u][3] << 16)};
+          const u2 vi = {(unsigned)ti[u][0] | ((unsigned)ti[u][1] << 16),
+                         (unsigned)ti[u][2] | ((unsigned)ti[u][3] << 16)};
+          *reinterpret_cast<u2 *>(tt + ((size_t)u * BN + nl) * TP + ml) = vr;
+          *reinterpret_cast<u2 *>(tt + ((size_t)(NT + u) * BN + nl) * TP + ml) = vi;
+        }
+      }
+    __syncthreads();
+    constexpr int RC = BM / 8;                  // 16-byte chunks per row
+    constexpr int NCH = PL * BN * RC;
+    static_assert(NCH % kThreads == 0, "epilogue chunking");
+#pragma unroll
+    for (int s_ = 0; s_ < NCH / kThreads; ++s_) {
+      const int id = tid + kThreads * s_;
+      const int c = id % RC, nl = (id / RC) % BN, pl = id / (RC * BN);
+      const u4 v = *reinterpret_cast<const u4 *>(tt + ((size_t)pl * BN + nl) * TP + 8 * c);
+      *reinterpret_cast<u4 *>(a.pt + (size_t)pl * a.pt_plane +
+                              kblk_index(n0 + nl, m0 + 8 * c, a.N)) = v;   // 8 m, one k-block
+    }
+  }
+}
+
+template <bool BF, int NT, int EPI>
+hipError_t launch_d16(const GemmTile &tl, const SplitArgs &args, int grid, hipStream_t s) {
+  if constexpr (NT == 2 && (EPI == EPI_PROJECT || EPI == EPI_STORE)) {
+    if (tl.bm == 48 && tl.bn == 192) {
+      hipLaunchKernelGGL((cgemm_split_d16<48, 192, BF, NT, EPI>), dim3(grid), dim3(kThreads), 0,
+                         s, args);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
 hipError_t launch_t(const SplitArgs &args, int grid, hipStream_t s) {
   hipLaunchKernelGGL((cgemm_split_mfma<BM, BN, BK, BF, NT, EPI, KG, PIPE>), dim3(grid),
@@ -834,6 +1113,7 @@ hipError_t launch_tail_split(int precision, const GemmTile &tl, const SplitArgs 
 
 template <bool BF, int NT, int EPI>
 hipError_t launch_e(const GemmTile &tl, const SplitArgs &args, int grid, hipStream_t s) {
+  if (tl.pipe == 3) return launch_d16<BF, NT, EPI>(tl, args, grid, s);
   if (tl.bk == 32) {
     if (tl.bm == 64 && tl.bn == 64) {
       if (tl.pipe) return launch_fit<64, 64, 32, BF, NT, EPI, 1, 1>(args, grid, s);
@@ -924,6 +1204,8 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
   a.tiles_m = sc.tiles_m;
   a.t_dp = sc.t_dp;
   a.split = sc.split;
+  a.xgm = sc.xgm;
+  if (sc.tile.pipe == 3 && (sc.n_tail > 0 || epi == EPI_GATHER)) return hipErrorInvalidValue;
   for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
     if (!(phases & (1 << phase))) continue;
     a.phase = phase;

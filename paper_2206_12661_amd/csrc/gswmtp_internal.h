@@ -209,7 +209,9 @@ __device__ __forceinline__ void tile_slot_pos(int tid, int i, int j, int r, int 
 
 // complex tile M x N, K per stage; split products: kg k-groups of four waves,
 // pipe: 1 software-pipelined fragment reads (one k-group), 2 the same with
-// the B operand read straight into registers (1 x 4 waves, two terms)
+// the B operand read straight into registers (1 x 4 waves, two terms), 3 the
+// 16x16-block loop (B straight into registers, BM a multiple of 16, no K
+// split; adjoint epilogues only)
 struct GemmTile { int bm = 64, bn = 64, bk = 16, kg = 1, pipe = 0; };
 
 // Launch schedule of one complex product: t_dp whole tiles, then n_tail tiles
@@ -220,6 +222,7 @@ struct GemmSched {
   int t_dp = 0, n_tail = 0, split = 1;
   int grid = 0;
   size_t part_floats = 0;
+  int xgm = 1;                  // 16x16-block loop: XCD groups of M tiles
 };
 
 typedef float gsw_v16f __attribute__((ext_vector_type(16)));

@@ -993,6 +993,25 @@ void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
   p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp,
                             choose_tile(D.Rp, D.Cp, split_mode, terms, p->cus), p->cus,
                             split_enabled(), chunk_div);
+  // Two-term split adjoint on 48 x 192 tiles (the 16x16-block loop) when its
+  // default tiles would need a split-K second round and the 48 x 192 tiles
+  // make one round over at least 85% of the CUs (1152 x 1920: 240 tiles
+  // against 540 of 64 x 64).  GSWMTP_ADJ_LOOP=d16|default forces either
+  // (d16 where the shape allows); GSWMTP_XCD_GM=g sets its XCD groups along M.
+  if (split_mode && terms == 2 && D.Rp % 48 == 0 && D.Cp % 192 == 0) {
+    const long t16 = (long)(D.Rp / 48) * (D.Cp / 192);
+    bool d16 = p->sched_bwd.n_tail > 0 && t16 <= p->cus && 100 * t16 >= 85L * p->cus;
+    if (const char *al = std::getenv("GSWMTP_ADJ_LOOP")) {
+      if (std::strcmp(al, "d16") == 0) d16 = true;
+      if (std::strcmp(al, "default") == 0) d16 = false;
+    }
+    if (d16) {
+      p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp, GemmTile{48, 192, 32, 1, 3}, p->cus, false);
+      const char *gm = std::getenv("GSWMTP_XCD_GM");
+      p->sched_bwd.xgm = gm ? std::max(1, std::atoi(gm)) : 2;
+      if (p->sched_bwd.tiles_m % p->sched_bwd.xgm) p->sched_bwd.xgm = 1;
+    }
+  }
   // Grid form (float32): when the foci fill a quarter or more of the reduced
   // grid and are many enough to repay its extra launches (measured
   // crossover: the per-focus gather and scatter cost ~0.09 us per focus and

@@ -121,3 +121,44 @@ def test_scaled_form_many_passes_graph_and_early_stop(g, mode, monkeypatch):
             p.iterate(20, stop)
             assert p.iterations_done() == k, form
         monkeypatch.delenv("GSWMTP_ADJOINT", raising=False)
+
+
+@pytest.mark.parametrize("form", ["scaled", "scatter"])
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16x3"])
+def test_d16_adjoint_loop_forced(g, mode, form, monkeypatch):
+    """The 16x16-block adjoint loop (48 x 192 tiles, B straight into
+    registers) forced on a 384 x 576 pupil (8 x 3 tiles), both adjoint forms:
+    the adjoint operator and one pass from a well-conditioned state against
+    the oracle at the mode's bar, and against the 64 x 64 loop."""
+    h = synth_ofa.random_case(48, 384, 576, 150, amplitude="random")
+    announce(f"d16 adjoint forced {mode} {form}")
+    if form == "scatter":
+        monkeypatch.setenv("GSWMTP_ADJOINT", "scatter")
+    with g.Plan(h) as p:
+        p.iterate(6)
+        phi_k, w_k, _ = p.state()
+    rng = np.random.default_rng(9)
+    T = (rng.standard_normal(h.n_foci) + 1j * rng.standard_normal(h.n_foci)).astype(np.complex64)
+    out = {}
+    for loop in ("d16", "default"):
+        monkeypatch.setenv("GSWMTP_ADJ_LOOP", loop)
+        with g.Plan(h, precision=mode) as q:
+            assert (q.stage_kernel(3) == "cgemm_split_d16") == (loop == "d16")
+            adj = q.adjoint_field(T)
+            q.set_state(phi_k, w_k, 0)
+            q.iterate(1)
+            out[loop] = (adj, q.phase(), q.weights(), q.foci_field())
+    ref = oracle.adjoint(T.astype(np.complex128), h.ny, h.nx, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    hk = synth_ofa.Hologram(h.name, h.ny, h.nx, h.amplitude, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy,
+                            h.target, phi_k, 1)
+    r = oracle.gsw(hk, n_iter=1, w=w_k)
+    amp = np.asarray(h.amplitude, np.float64)
+    field = lambda phi: amp * np.exp(1j * phi.astype(np.float64))
+    for loop, (adj, phi1, w1, th1) in out.items():
+        ea, ew, et = rel_l2(adj, ref), rel_l2(w1, r["w"]), rel_l2(th1, r["theta"])
+        ee = rel_l2(field(phi1), field(r["phi"]))
+        print(f"  {loop}: adjoint {ea:.2e} w {ew:.2e} theta {et:.2e} E {ee:.2e}")
+        assert ea <= TOL[mode] and ew <= TOL[mode] and et <= TOL[mode] and ee <= 2 * TOL[mode]
+    a, b = out["d16"], out["default"]
+    assert rel_l2(a[0], b[0]) <= TOL[mode]
+    assert rel_l2(field(a[1]), field(b[1])) <= 2 * TOL[mode]
