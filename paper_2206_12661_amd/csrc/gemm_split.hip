@@ -855,7 +855,9 @@ __device__ __forceinline__ void mma16(const u4 (&fa)[MB][2 * NT], const u4 (&fb)
 template <int BM, int BN, int NT, int EPI>
 constexpr int d16_lds_bytes() {
   constexpr int ring = 4 * 2 * NT * BM * 4 * 16;              // four A stages
-  constexpr int tr = EPI == EPI_PROJECT ? 2 * NT * BN * (BM + 8) * 2 : 0;
+  constexpr int tr = EPI == EPI_PROJECT  ? 2 * NT * BN * (BM + 8) * 2
+                     : EPI == EPI_GATHER ? gather_lds_bytes<BM, BN>()
+                                         : 0;
   return ring > tr ? ring : tr;
 }
 
@@ -871,10 +873,10 @@ __device__ __forceinline__ int rank_tile(int r, int tiles_m, int tiles, int gm) 
 }
 
 // The main loop over all of K; false when the done flag stops the product.
-template <int BM, int BN, bool BF, int NT>
+template <int BM, int BN, bool BF, int NT, bool PRE>
 __device__ __forceinline__ bool d16_loop(const SplitArgs &a, int m0, int n0, int tid, u4 *lds,
                                          v4f (&accR)[BM / 16][BN / 64],
-                                         v4f (&accI)[BM / 16][BN / 64]) {
+                                         v4f (&accI)[BM / 16][BN / 64], GatherPre &gp) {
   constexpr int WTN = BN / 4, MB = BM / 16, NB = WTN / 16, PL = 2 * NT, CH = 4;
   constexpr int LA = PL * BM * CH, NA = LA / kThreads, SA = LA;
   static_assert(LA % kThreads == 0 && WTN % 16 == 0 && BM % 16 == 0, "d16 tile");
@@ -924,6 +926,7 @@ __device__ __forceinline__ bool d16_loop(const SplitArgs &a, int m0, int n0, int
   E_LOAD_B(bq1, 1 < last ? 1 : last);
   E_LOAD_B(bq2, 2 < last ? 2 : last);
   E_LOAD_B(bq3, 3 < last ? 3 : last);
+  if constexpr (PRE) gather_pre_foci(a.g, m0, tid, gp);   // behind the operand loads
   const int stop = a.done ? *a.done : 0;
   asm volatile("" ::: "memory");
   if (stop) return false;
@@ -1003,8 +1006,27 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_d16(SplitArgs a) {
           ampv[i][j][r] = a.amp[(size_t)(m0 + 16 * i + 4 * q + r) * a.ldc + n0 + wave * WTN +
                                 16 * j + l16];
   }
-  if (!d16_loop<BM, BN, BF, NT>(a, m0, n0, tid, lds, accR, accI)) return;
-  if constexpr (EPI == EPI_STORE) {
+  // the gather's focus indices: row range now, foci behind the operand loads
+  GatherPre gp;
+  if constexpr (EPI == EPI_GATHER) gather_pre_rows(a.g, m0, BM, gp);
+  if (!d16_loop<BM, BN, BF, NT, EPI == EPI_GATHER>(a, m0, n0, tid, lds, accR, accI, gp)) return;
+  if constexpr (EPI == EPI_GATHER) {
+    // stage the tile of L in LDS, then gather the tile's foci from it
+    constexpr int LD = BN + 1;
+    float *tr = reinterpret_cast<float *>(lds), *ti = tr + BM * LD;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = 16 * i + 4 * q + r, nl = wave * WTN + 16 * j + l16;
+          tr[ml * LD + nl] = accR[i][j][r];
+          ti[ml * LD + nl] = accI[i][j][r];
+        }
+    __syncthreads();
+    gather_tile_lds<BM, BN>(a.g, reinterpret_cast<float *>(lds), m0, n0, tid, gp);
+  } else if constexpr (EPI == EPI_STORE) {
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -1062,11 +1084,20 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_d16(SplitArgs a) {
 
 template <bool BF, int NT, int EPI>
 hipError_t launch_d16(const GemmTile &tl, const SplitArgs &args, int grid, hipStream_t s) {
-  if constexpr (NT == 2 && (EPI == EPI_PROJECT || EPI == EPI_STORE)) {
-    if (tl.bm == 48 && tl.bn == 192) {
-      hipLaunchKernelGGL((cgemm_split_d16<48, 192, BF, NT, EPI>), dim3(grid), dim3(kThreads), 0,
-                         s, args);
-      return hipGetLastError();
+  if constexpr (NT == 2) {
+    if constexpr (EPI == EPI_PROJECT || EPI == EPI_STORE) {
+      if (tl.bm == 48 && tl.bn == 192) {
+        hipLaunchKernelGGL((cgemm_split_d16<48, 192, BF, NT, EPI>), dim3(grid), dim3(kThreads),
+                           0, s, args);
+        return hipGetLastError();
+      }
+    }
+    if constexpr (EPI == EPI_GATHER) {
+      if (tl.bm == 64 && tl.bn == 128) {
+        hipLaunchKernelGGL((cgemm_split_d16<64, 128, BF, NT, EPI>), dim3(grid), dim3(kThreads),
+                           0, s, args);
+        return hipGetLastError();
+      }
     }
   }
   return hipErrorInvalidValue;
@@ -1205,7 +1236,7 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
   a.t_dp = sc.t_dp;
   a.split = sc.split;
   a.xgm = sc.xgm;
-  if (sc.tile.pipe == 3 && (sc.n_tail > 0 || epi == EPI_GATHER)) return hipErrorInvalidValue;
+  if (sc.tile.pipe == 3 && sc.n_tail > 0) return hipErrorInvalidValue;
   for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
     if (!(phases & (1 << phase))) continue;
     a.phase = phase;

@@ -264,47 +264,22 @@ __device__ __forceinline__ void gather_pre_foci(const GatherCtx &g, int m0, int 
   q.loaded = true;
 }
 
-// Focus gather fused into the forward product's epilogue (the second
-// product of Eq. 2, formed only at the foci).  The BM x BN complex tile of
-// L = Omega_r P held in the accumulators is staged in LDS; then the tile's
-// foci are taken 64 at a time, one per lane: wave w forms
+// The focus gather of one BM x BN tile of L staged in LDS (real part at
+// lds[m (BN + 1) + n], imaginary part BM (BN + 1) floats further on): the
+// tile's foci are taken 64 at a time, one per lane: wave w forms
 //   sum_{n in its BN/4 columns} L[ir][n] Wc[ic][n]
 // for the lane's focus (its Omega_c run read as 16-byte loads, all in
 // flight together), the four waves' sums are added in wave order and the
-// result written as partial number n0 / BN of that focus.  Accumulator item
-// r of lane (l32, h) of a 32x32 block holds row 8 (r/4) + 4 h + r % 4,
-// column l32.
-template <int BM, int BN, bool COLS = false>
-__device__ __forceinline__ void gather_epilogue(
-    const GatherCtx &g,
-    const gsw_v16f (&accR)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
-    const gsw_v16f (&accI)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
-    float *lds, int m0, int n0, int tid, GatherPre q) {
-  using L = WaveLayout<BM, BN, COLS>;
-  constexpr int MB = L::MB, NB = L::NB, WTM = L::WTM, WTN = L::WTN, LD = BN + 1;
+// result written as partial number n0 / BN of that focus.
+template <int BM, int BN>
+__device__ __forceinline__ void gather_tile_lds(const GatherCtx &g, float *lds, int m0, int n0,
+                                                int tid, const GatherPre &q) {
+  constexpr int LD = BN + 1;
   constexpr int CW = BN / 4;   // columns per wave
   typedef float f4 __attribute__((ext_vector_type(4)));
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = L::wm(wave), wn = L::wn(wave), l32 = lane & 31, h = lane >> 5;
   float *tr = lds, *ti = lds + BM * LD;
   float *red = lds + 2 * BM * LD;   // [4 waves][64 lanes][re, im]
-  if (!q.loaded) {
-    gather_pre_rows(g, m0, BM, q);
-    gather_pre_foci(g, m0, tid, q);
-  }
-  __syncthreads();   // operand stages are no longer read
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int ml = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        const int nl = wn * WTN + j * 32 + l32;
-        tr[ml * LD + nl] = accR[i][j][r];
-        ti[ml * LD + nl] = accI[i][j][r];
-      }
-  __syncthreads();
   const int p0 = q.p0, nfoc = q.p1 - q.p0;
   float *out = g.part + 2 * (size_t)(n0 / BN) * g.ldp;
   for (int u0 = 0; u0 < nfoc; u0 += 64) {
@@ -350,6 +325,42 @@ __device__ __forceinline__ void gather_epilogue(
     }
     __syncthreads();   // the sums are read before the next round writes them
   }
+}
+
+// Focus gather fused into the forward product's epilogue (the second
+// product of Eq. 2, formed only at the foci).  The BM x BN complex tile of
+// L = Omega_r P held in the accumulators is staged in LDS, then gathered by
+// gather_tile_lds.  Accumulator item r of lane (l32, h) of a 32x32 block
+// holds row 8 (r/4) + 4 h + r % 4, column l32.
+template <int BM, int BN, bool COLS = false>
+__device__ __forceinline__ void gather_epilogue(
+    const GatherCtx &g,
+    const gsw_v16f (&accR)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
+    const gsw_v16f (&accI)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
+    float *lds, int m0, int n0, int tid, GatherPre q) {
+  using L = WaveLayout<BM, BN, COLS>;
+  constexpr int MB = L::MB, NB = L::NB, WTM = L::WTM, WTN = L::WTN, LD = BN + 1;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = L::wm(wave), wn = L::wn(wave), l32 = lane & 31, h = lane >> 5;
+  float *tr = lds, *ti = lds + BM * LD;
+  if (!q.loaded) {
+    gather_pre_rows(g, m0, BM, q);
+    gather_pre_foci(g, m0, tid, q);
+  }
+  __syncthreads();   // operand stages are no longer read
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int ml = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        const int nl = wn * WTN + j * 32 + l32;
+        tr[ml * LD + nl] = accR[i][j][r];
+        ti[ml * LD + nl] = accI[i][j][r];
+      }
+  __syncthreads();
+  gather_tile_lds<BM, BN>(g, lds, m0, n0, tid, q);
 }
 
 // The same without indices read ahead (they are read at the epilogue).

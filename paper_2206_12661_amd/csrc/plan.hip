@@ -993,6 +993,25 @@ void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
   p->sched_bwd = make_sched(D.Rp, D.Cp, D.Urp,
                             choose_tile(D.Rp, D.Cp, split_mode, terms, p->cus), p->cus,
                             split_enabled(), chunk_div);
+  // The two-term split forward product with the fused focus gather on the
+  // 16x16-block loop (64 x 128 tiles) when those tiles make one round over
+  // at least half of the CUs (1152 x 1920, 1000 foci: 240 tiles; 2.7% faster
+  // per pass than the 32x32-block direct loop on the same tiles).
+  // GSWMTP_FWD_LOOP=d16|default forces either (d16 up to one round).
+  if (split_mode && terms == 2 && D.Urp % 64 == 0 && D.Cp % 128 == 0) {
+    const long t16 = (long)(D.Urp / 64) * (D.Cp / 128);
+    bool d16 = t16 <= p->cus && 2 * t16 >= p->cus;
+    if (const char *fl = std::getenv("GSWMTP_FWD_LOOP")) {
+      if (std::strcmp(fl, "d16") == 0) d16 = t16 <= p->cus;
+      if (std::strcmp(fl, "default") == 0) d16 = false;
+    }
+    if (d16) {
+      p->sched_fwd = make_sched(D.Urp, D.Cp, D.Rp, GemmTile{64, 128, 32, 1, 3}, p->cus, false);
+      const char *gm = std::getenv("GSWMTP_XCD_GM");
+      p->sched_fwd.xgm = gm ? std::max(1, std::atoi(gm)) : 2;
+      if (p->sched_fwd.tiles_m % p->sched_fwd.xgm) p->sched_fwd.xgm = 1;
+    }
+  }
   // Two-term split adjoint on 48 x 192 tiles (the 16x16-block loop) when its
   // default tiles would need a split-K second round and the 48 x 192 tiles
   // make one round over at least 85% of the CUs (1152 x 1920: 240 tiles

@@ -180,3 +180,23 @@ def test_batch_config4_subset_against_oracle(g, mode):
         assert kap < 1.01
         assert ew <= TOL[mode] and et <= TOL[mode] and ee <= TOL[mode]
         p.close()
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16x3"])
+def test_d16_forward_loop_config3(g, c3_state, mode, monkeypatch):
+    """The forward product with the fused focus gather on the 16x16-block loop
+    (64 x 128 tiles, the default at this size; GSWMTP_FWD_LOOP=d16 asserts it)
+    at the benchmark size: the field of phi0 at every focus, and one pass
+    from the identical state, against the oracle at the mode's bar."""
+    h, phi_k, w_k, r, thk = c3_state
+    monkeypatch.setenv("GSWMTP_FWD_LOOP", "d16")
+    announce(f"config3 {mode} forward on the 16x16-block loop")
+    with g.Plan(h, precision=mode) as p:
+        assert p.stage_kernel(0) == "cgemm_split_d16"
+        th0 = p.foci_field()
+    ref0 = oracle.forward(oracle.pupil_field(h), h.u, h.v, h.s_x, h.s_y, h.fx, h.fy)
+    phi1, w1, th1 = _one_pass(g, h, phi_k, w_k, mode)
+    e0, ew, et = rel_l2(th0, ref0), rel_l2(w1, r["w"]), rel_l2(th1, r["theta"])
+    ee = rel_l2(_field(h, phi1), _field(h, r["phi"]))
+    print(f"  phi0 field {e0:.2e}; pass: w {ew:.2e} theta {et:.2e} E {ee:.2e}")
+    assert e0 <= TOL[mode] and ew <= TOL[mode] and et <= TOL[mode] and ee <= TOL[mode]
