@@ -306,41 +306,82 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out);
 const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage);
 
 /* Batched form: several independent plans (one hologram each, any sizes)
- * iterated together.  Each stage of a pass of Algorithm 1 (forward product of
- * Eq. 2 with the focus gather, weight update of Algorithm 1, scatter, adjoint
- * product with the phase-only projection) is one grouped launch over the
- * tiles of all plans, replayed from a captured HIP graph.
+ * iterated together (an addition of this library; the paper computes one
+ * hologram at a time).  Each pass runs Algorithm 1 on every plan: forward
+ * product of Eq. 2 with the focus gather, weight update, scatter, adjoint
+ * product with the phase-only projection.
+ *
+ * Products: every plan's forward and adjoint product falls in a shape class,
+ * (product, padded M, N, K).  Each class has its own kernel configuration
+ * (tile, loop, K chunks of the forward), chosen by an autotuner at
+ * batch_create: every candidate valid for the shape is timed on the class's
+ * own tiles, repeated until they fill the device twice, with the adjoint's
+ * output sent to scratch (no plan state changes); the fastest wins.  Choices
+ * are kept per process and, when the environment variable GSWMTP_TUNE_CACHE
+ * names a file, in that JSON file (read at batch_create, rewritten when new
+ * classes were tuned), keyed by architecture, CU count, precision, product
+ * and (M, N, K).  GSWMTP_BATCH_TILE=BMxBN fixes the tile of every class it
+ * divides; GSWMTP_BATCH_TILE=plan or GSWMTP_BATCH_NO_TUNE=1 gives each class
+ * its plans' single-plan configuration (no K split).  A tuned class whose
+ * timing of its product's dominant configuration is within 10% of its best
+ * takes the dominant one.  The tiles of all plans go to one device work list
+ * per configuration, longest K first, one launch each: a stage with one
+ * configuration runs it persistently (the tiles dealt to the resident
+ * workgroups on the host, longest first, each to the least-loaded one;
+ * GSWMTP_BATCH_PERSIST=0: one workgroup per tile); a stage's several
+ * configurations (at most 5) run as parallel branches of the captured graph
+ * with one workgroup per tile.  Focus update and scatter are one grouped
+ * launch each.
  *
  * batch_create: plans[n_plans] (1..65536 distinct plans on one device, all
  *   of one precision, else GSWMTP_E_INVAL) must outlive the batch; the
- *   batch keeps pointers, copies nothing.  FP32: chooses the product tiles
- *   (among 64/128 x 64/128 tiles that divide every plan, by timing a few
- *   grouped launches when more than one is valid; GSWMTP_BATCH_TILE=BMxBN
- *   fixes it, GSWMTP_BATCH_NO_TUNE=1 takes the first valid) without changing
- *   any plan's state.  Split precisions: the single-plan form's product
- *   loops on 64 x 64 tiles (the forward 64 x 128 when
- *   GSWMTP_BATCH_TILE=64x128 and every plan allows it).  Allocates its own
- *   argument tables.  stream: hipStream_t or NULL.
+ *   batch keeps pointers, copies nothing.  Allocates its own work lists and
+ *   argument tables (and tuning scratch while it tunes).  stream:
+ *   hipStream_t or NULL.  GSWMTP_E_INVAL when the tuning cache cannot be
+ *   written; GSWMTP_E_UNSUPPORTED when a stage would need more than five
+ *   configurations.
  * batch_iterate: n_iter passes on every plan, each plan stopping on its own
  *   as gswmtp_iterate(p, n_iter, stop_accuracy) would; ordered after the
  *   caller's stream and each plan's queued work, and before later calls on
  *   the plans and the caller's stream.  Each plan's results equal those of
- *   gswmtp_iterate on that plan alone with no K split
- *   (GSWMTP_NO_SPLITK=1) bit for bit when the tiles are the same, and to
- *   float32 rounding otherwise.  Read results through the plans.
+ *   gswmtp_iterate on that plan alone with no K split (GSWMTP_NO_SPLITK=1)
+ *   bit for bit when its classes' configurations are the plan's own (as
+ *   under GSWMTP_BATCH_TILE=plan), and to float32 rounding otherwise.  Read
+ *   results through the plans.
  * batch_set_stream: the caller stream later batch_iterate calls are ordered with.
  * batch_sync: wait for the batch's queued passes.
- * batch_tiles: tiles[4] = forward BM, BN, adjoint BM, BN; tune_ms (nullable)
- *   [8] = mean grouped-launch milliseconds per candidate (64x64, 64x128,
- *   128x64, 128x128; forward then adjoint; 0 = not timed, always for split
- *   precisions).
+ * batch_tiles: tiles[4] = forward BM, BN, adjoint BM, BN of the class with
+ *   the most work of each product; tune_ms (nullable) [8] = that class's
+ *   timed ms for the plain 64x64, 64x128, 128x64, 128x128 candidates
+ *   (forward then adjoint; 0 = not timed).
+ * batch_n_classes / batch_class_info: the shape classes and their
+ *   configurations, with the tuning table of each (the candidates timed and
+ *   their ms per copy of the class's tiles).
+ * batch_tune_ms: host milliseconds batch_create spent timing candidates.
  * batch_last_error: message of the batch's last failed call, or of the last
  *   failed batch_create on this thread when b == NULL. */
+#define GSWMTP_BATCH_MAX_CANDIDATES 8
+typedef struct gswmtp_batch_class {
+    int product;                  /* 0 forward (with the focus gather), 1 adjoint */
+    int m, n, k;                  /* padded product sizes */
+    int n_plans;                  /* plans in the class */
+    int config[6];                /* BM, BN, BK, k-groups, loop (0 plain, 1 pipelined,
+                                     2 direct, 3 16x16 blocks), forward K chunks */
+    double ms;                    /* timed ms per copy of the class's tiles (0: not timed) */
+    int source;                   /* 0 the plans' own or the only candidate, 1 tuned now,
+                                     2 tuning cache, 3 GSWMTP_BATCH_TILE */
+    int n_tried;
+    int tried_config[GSWMTP_BATCH_MAX_CANDIDATES][6];
+    double tried_ms[GSWMTP_BATCH_MAX_CANDIDATES];
+} gswmtp_batch_class;
 int gswmtp_batch_create(gswmtp_batch **out, gswmtp_plan *const *plans, int n_plans, void *stream);
 int gswmtp_batch_iterate(gswmtp_batch *b, int n_iter, double stop_accuracy);
 int gswmtp_batch_set_stream(gswmtp_batch *b, void *stream);
 int gswmtp_batch_sync(gswmtp_batch *b);
 int gswmtp_batch_tiles(const gswmtp_batch *b, int *tiles, double *tune_ms);
+int gswmtp_batch_n_classes(const gswmtp_batch *b, int *n);
+int gswmtp_batch_class_info(const gswmtp_batch *b, int i, gswmtp_batch_class *out);
+int gswmtp_batch_tune_ms(const gswmtp_batch *b, double *ms);
 const char *gswmtp_batch_last_error(const gswmtp_batch *b);
 int gswmtp_batch_destroy(gswmtp_batch *b);
 

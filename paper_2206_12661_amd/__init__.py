@@ -60,6 +60,19 @@ class gswmtp_index_info(ctypes.Structure):
     ]
 
 
+_MAX_CAND = 8
+
+
+class gswmtp_batch_class(ctypes.Structure):
+    _fields_ = [
+        ("product", ctypes.c_int), ("m", ctypes.c_int), ("n", ctypes.c_int), ("k", ctypes.c_int),
+        ("n_plans", ctypes.c_int), ("config", ctypes.c_int * 6), ("ms", ctypes.c_double),
+        ("source", ctypes.c_int), ("n_tried", ctypes.c_int),
+        ("tried_config", (ctypes.c_int * 6) * _MAX_CAND),
+        ("tried_ms", ctypes.c_double * _MAX_CAND),
+    ]
+
+
 _P = ctypes.c_void_p
 _SIGNATURES = {
     "gswmtp_version": ([], ctypes.c_int),
@@ -103,6 +116,10 @@ _SIGNATURES = {
     "gswmtp_batch_set_stream": ([_P, _P], ctypes.c_int),
     "gswmtp_batch_sync": ([_P], ctypes.c_int),
     "gswmtp_batch_tiles": ([_P, _P, _P], ctypes.c_int),
+    "gswmtp_batch_n_classes": ([_P, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+    "gswmtp_batch_class_info": ([_P, ctypes.c_int, ctypes.POINTER(gswmtp_batch_class)],
+                                ctypes.c_int),
+    "gswmtp_batch_tune_ms": ([_P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "gswmtp_batch_last_error": ([_P], ctypes.c_char_p),
     "gswmtp_batch_destroy": ([_P], ctypes.c_int),
 }
@@ -448,11 +465,23 @@ class Plan:
         return self._lib.gswmtp_stage_kernel(self._h, stage).decode()
 
 
+_LOOPS = {0: "plain", 1: "pipe", 2: "direct", 3: "b16"}
+_SOURCES = {0: "plan", 1: "tuned", 2: "cache", 3: "env"}
+
+
+def _config_text(c) -> str:
+    bm, bn, bk, kg, loop, split = list(c)
+    return f"{bm}x{bn}/{'kg2' if kg == 2 else _LOOPS.get(loop, loop)}/k{split}"
+
+
 class Batch:
-    """Several plans iterated together (one grouped launch per stage of a pass
-    for all of them, replayed from a captured HIP graph).  The plans stay
-    usable: their state is read and set through each ``Plan``; keep them open
-    while the batch lives."""
+    """Several plans iterated together: the tiles of every plan's products
+    on per-configuration device work lists (persistent launches, one per
+    kernel configuration and stage), focus update and scatter grouped, a pass
+    replayed from a captured HIP graph.  Each shape class of a product gets
+    its own tuned configuration (``classes()``).  The plans stay usable:
+    their state is read and set through each ``Plan``; keep them open while
+    the batch lives."""
 
     def __init__(self, plans):
         lib = load_library()
@@ -485,6 +514,31 @@ class Batch:
                 "tune_ms": {"forward": {c: ms[i] for i, c in enumerate(cands) if ms[i] > 0},
                             "adjoint": {c: ms[4 + i] for i, c in enumerate(cands)
                                         if ms[4 + i] > 0}}}
+
+    def classes(self) -> list:
+        """Shape classes (product, padded M x N x K) with their configuration,
+        where it came from and the tuning table (candidate -> ms per copy of
+        the class's tiles)."""
+        n = ctypes.c_int(0)
+        self._check(self._lib.gswmtp_batch_n_classes(self._h, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            c = gswmtp_batch_class()
+            self._check(self._lib.gswmtp_batch_class_info(self._h, i, ctypes.byref(c)))
+            out.append({
+                "product": "forward" if c.product == 0 else "adjoint",
+                "mnk": [c.m, c.n, c.k], "plans": c.n_plans,
+                "config": _config_text(c.config), "ms": c.ms,
+                "source": _SOURCES.get(c.source, c.source),
+                "tried": {_config_text(c.tried_config[k]): c.tried_ms[k]
+                          for k in range(c.n_tried)},
+            })
+        return out
+
+    def tune_ms(self) -> float:
+        v = ctypes.c_double(0.0)
+        self._check(self._lib.gswmtp_batch_tune_ms(self._h, ctypes.byref(v)))
+        return v.value
 
     def close(self):
         if getattr(self, "_h", None):

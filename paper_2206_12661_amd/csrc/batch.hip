@@ -1,43 +1,83 @@
 // Batched form: several independent plans iterated together.
 //
-// Every stage of a pass (forward product with the fused focus gather, focus
-// update, scatter, adjoint product with the projection) is ONE grouped launch
-// over all plans of the batch: the launch's workgroups are the concatenated
-// tile lists of the plans' products, each workgroup finding its plan by a
-// binary search over the item start offsets.  A pass of the whole batch is
-// thus four launches whatever the number of plans, and it is replayed from a
-// captured HIP graph.  The plans share one precision: float32 products with
-// autotuned tiles, or the split-precision products with the single-plan
-// form's loops.  Items are ordered by descending K (the longest tiles
-// are dispatched first) so that the short products of small holograms fill
-// the tail of the launch.
+// Products.  Every plan's forward and adjoint product belongs to a shape
+// class: (product, padded M, N, K).  Each class has its own kernel
+// configuration (tile, loop, K chunks of the forward), chosen by the
+// autotuner below; the tiles of every plan of a product, as work units
+// (plan, tile, K range), go to a device work list per configuration.  Each
+// work list is ONE launch.  A stage with one configuration runs it
+// persistently: the units, longest first, are dealt to the resident
+// workgroups on the host (each to the least-loaded workgroup so far), and
+// every workgroup runs its range of units.  A stage's several configurations
+// run as parallel branches of the captured graph with one workgroup per unit
+// (longest first), which the hardware dispatcher balances across them.
+
+// Autotuner.  For a class whose configuration is not yet known, every
+// candidate valid for its shape is timed on the class's own units, repeated
+// until the list fills the chip twice (so each candidate is judged on its
+// throughput, not on one short launch), with the adjoint's output sent to
+// scratch and the done flags ignored, so no plan state changes; the fastest
+// wins.  Choices are kept per process and, when GSWMTP_TUNE_CACHE names a
+// file, in that JSON file, keyed by architecture, CU count, precision,
+// product and (M, N, K).  GSWMTP_BATCH_TILE=BMxBN fixes the tile of every
+// class it divides (no tuning); GSWMTP_BATCH_TILE=plan, or
+// GSWMTP_BATCH_NO_TUNE=1, gives each class its plans' single-plan
+// configuration (no K split).  GSWMTP_BATCH_PERSIST=0 launches one
+// workgroup per unit instead of the persistent grid.
 //
-// Each plan's own arithmetic is exactly that of its single-plan pass with no
-// K split: tiles, k order, reductions and epilogues are the same code, so a
-// batched result equals the single-plan result bit for bit whenever the tiles
-// are the same.
+// The other stages (focus update, scatter) are one grouped launch each over
+// all plans.  A pass of the batch is replayed from a captured HIP graph.
+//
+// Each plan's own arithmetic is exactly that of its single-plan pass with the
+// same tile and loop and no K split: a batched result then equals the
+// single-plan result bit for bit.  Forward K chunks add their focus-gather
+// partials in the focus update like column tiles (fixed order).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <numeric>
+#include <queue>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "gswmtp_internal.h"
 
 using namespace gswmtp;
 
+// One shape class of a product and its configuration.
+struct BatchClass {
+  int product = 0;                  // 0 forward (with the focus gather), 1 adjoint
+  int M = 0, N = 0, K = 0;          // padded product sizes
+  std::vector<int> plans;           // indices into the batch's plans
+  WorkConfig cfg;
+  double ms = 0.0;                  // timed ms of one copy of its units (0: not timed)
+  int source = 0;                   // gswmtp_batch_class::source
+  std::vector<std::pair<WorkConfig, double>> tried;   // the tuning table
+};
+
+constexpr int kBatchBranches = 4;   // parallel branches per stage beyond the main stream
+
 struct gswmtp_batch {
   int device = 0;
+  int cus = 256;
   hipStream_t user_stream = nullptr;
   hipStream_t stream = nullptr;
-  hipEvent_t ev_user = nullptr, ev_done = nullptr;
+  hipStream_t side[kBatchBranches] = {};
+  hipEvent_t ev_user = nullptr, ev_done = nullptr, ev_fork = nullptr;
+  hipEvent_t ev_join[kBatchBranches] = {};
   std::vector<gswmtp_plan *> plans;
   std::vector<hipEvent_t> ev_plan;
-  GroupedLaunch fwd, bwd;
+  std::vector<BatchClass> classes;
+  std::vector<WorkLaunch> work[2];  // per product: one launch per configuration
   GroupedUpdate upd;
   void *d_sc = nullptr;
   int *d_sc_starts = nullptr;
@@ -47,8 +87,9 @@ struct gswmtp_batch {
   void *pool = nullptr;
   hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
   bool use_graph = true;
-  double tune_ms[2][4] = {};   // [forward/adjoint][candidate] mean launch ms (0: not timed)
-  int precision = GSWMTP_FP32; // common precision of the plans
+  bool persistent = true;
+  double tune_total_ms = 0.0;       // host time spent timing candidates
+  int precision = GSWMTP_FP32;      // common precision of the plans
   std::string err;
 };
 
@@ -94,26 +135,428 @@ __global__ void k_batch_control(int *const *ctrl, double *const *stats, int n, d
   stats[i][ST_STOP] = stop;
 }
 
-constexpr int kCand[4][2] = {{64, 64}, {64, 128}, {128, 64}, {128, 128}};
-
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+bool is_split_prec(int precision) { return split_terms_of(precision) > 0; }
+
+// ---------------------------------------------------------------------------
+// Configurations
+// ---------------------------------------------------------------------------
+
+// K stages of a configuration's tile for a product of depth K.
+int stages_of(const WorkConfig &c, int K) { return K / c.tile.bk; }
+
+// Candidates valid for a class: float32 tiles 64/128 x 64/128 (K stages of
+// 16); two-term split tiles 64 x 64 and 64 x 128 on the software-pipelined
+// loop and the 16x16-block loop (forward 64 x 128, adjoint 48 x 192);
+// three-term split 64 x 64 with two k-groups.  The forward also tries two K
+// chunks per 128-wide tile (their gather partials fit the plan's partial
+// rows: at most one per 64 columns).
+std::vector<WorkConfig> candidates(int precision, int product, int M, int N) {
+  std::vector<WorkConfig> out;
+  const int nt = split_terms_of(precision);
+  auto add = [&](GemmTile t, int split) {
+    if (M % t.bm || N % t.bn) return;
+    if (split > 1 && (product != 0 || t.bn / 64 < split || t.pipe == 3)) return;
+    WorkConfig c;
+    c.tile = t;
+    c.split = split;
+    out.push_back(c);
+  };
+  if (nt == 0) {
+    const int tiles[4][2] = {{64, 64}, {64, 128}, {128, 64}, {128, 128}};
+    for (auto &t : tiles) {
+      add(GemmTile{t[0], t[1], 16, 1, 0}, 1);
+      add(GemmTile{t[0], t[1], 16, 1, 0}, 2);
+    }
+  } else if (nt == 2) {
+    add(GemmTile{64, 64, 32, 1, 1}, 1);
+    add(GemmTile{64, 128, 32, 1, 1}, 1);
+    add(GemmTile{64, 128, 32, 1, 1}, 2);
+    if (product == 0) add(GemmTile{64, 128, 32, 1, 3}, 1);
+    else add(GemmTile{48, 192, 32, 1, 3}, 1);
+  } else {
+    add(GemmTile{64, 64, 32, 2, 0}, 1);
+  }
+  return out;
+}
+
+// The plan's own single-plan configuration of a product, without K split.
+WorkConfig plan_config(const gswmtp_plan *p, int product) {
+  WorkConfig c;
+  c.tile = product == 0 ? p->sched_fwd.tile : p->sched_bwd.tile;
+  c.split = 1;
+  return c;
+}
+
+// GSWMTP_BATCH_TILE=BMxBN as a configuration for this precision and product.
+bool env_tile(int precision, int product, int M, int N, WorkConfig &c) {
+  const char *env = std::getenv("GSWMTP_BATCH_TILE");
+  int bm = 0, bn = 0;
+  if (!env || std::sscanf(env, "%dx%d", &bm, &bn) != 2) return false;
+  const int nt = split_terms_of(precision);
+  if (M % bm || N % bn) return false;
+  if (nt == 0) {
+    if ((bm != 64 && bm != 128) || (bn != 64 && bn != 128)) return false;
+    c.tile = GemmTile{bm, bn, 16, 1, 0};
+  } else if (nt == 2) {
+    if (bm != 64 || (bn != 64 && bn != 128)) return false;
+    c.tile = GemmTile{64, bn, 32, 1, 1};
+  } else {
+    if (bm != 64 || bn != 64) return false;
+    c.tile = GemmTile{64, 64, 32, 2, 0};
+  }
+  c.split = 1;
+  (void)product;
+  return true;
+}
+
+std::string config_text(const WorkConfig &c) {
+  char buf[64];
+  snprintf(buf, sizeof buf, "%dx%d/%s/k%d", c.tile.bm, c.tile.bn,
+           c.tile.pipe == 3 ? "b16" : c.tile.kg == 2 ? "kg2" : c.tile.pipe == 2 ? "direct"
+                              : c.tile.pipe == 1 ? "pipe" : "plain",
+           c.split);
+  return buf;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning cache: per process, and in the JSON file GSWMTP_TUNE_CACHE names.
+// The file is one object of entries, one per line,
+//   "arch:cus:precision:product:MxNxK": [[bm, bn, bk, kgroups, loop, split, ms], ...]
+// holding the timed candidates of the class (its tuning table).
+// ---------------------------------------------------------------------------
+
+typedef std::vector<std::pair<WorkConfig, double>> TuneTable;
+std::mutex g_cache_mu;
+std::map<std::string, TuneTable> g_cache;
+
+const char *prec_name(int precision) {
+  switch (precision) {
+    case GSWMTP_BF16X3: return "bf16x3";
+    case GSWMTP_FP16X3: return "fp16x3";
+    case GSWMTP_BF16X6: return "bf16x6";
+  }
+  return "fp32";
+}
+
+std::string cache_key(const std::string &arch, int cus, int precision, const BatchClass &c) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s:%d:%s:%s:%dx%dx%d", arch.c_str(), cus, prec_name(precision),
+           c.product == 0 ? "forward" : "adjoint", c.M, c.N, c.K);
+  return buf;
+}
+
+void cache_load(const char *path) {
+  std::ifstream in(path);
+  if (!in) return;
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t q0 = line.find('"'), q1 = line.find('"', q0 + 1);
+    if (q0 == std::string::npos || q1 == std::string::npos) continue;
+    TuneTable t;
+    size_t at = line.find('[', q1);
+    if (at == std::string::npos) continue;
+    for (at = line.find('[', at + 1); at != std::string::npos; at = line.find('[', at + 1)) {
+      WorkConfig c;
+      double ms = 0.0;
+      if (std::sscanf(line.c_str() + at, "[%d, %d, %d, %d, %d, %d, %lf]", &c.tile.bm, &c.tile.bn,
+                      &c.tile.bk, &c.tile.kg, &c.tile.pipe, &c.split, &ms) != 7)
+        break;
+      t.push_back({c, ms});
+    }
+    if (!t.empty()) g_cache[line.substr(q0 + 1, q1 - q0 - 1)] = t;
+  }
+}
+
+bool cache_save(const char *path) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp);
+    if (!out) return false;
+    out << "{\n";
+    size_t k = 0;
+    for (const auto &e : g_cache) {
+      out << "  \"" << e.first << "\": [";
+      for (size_t i = 0; i < e.second.size(); ++i) {
+        const WorkConfig &c = e.second[i].first;
+        char buf[96];
+        snprintf(buf, sizeof buf, "[%d, %d, %d, %d, %d, %d, %.6f]", c.tile.bm, c.tile.bn,
+                 c.tile.bk, c.tile.kg, c.tile.pipe, c.split, e.second[i].second);
+        out << (i ? ", " : "") << buf;
+      }
+      out << "]" << (++k < g_cache.size() ? ",\n" : "\n");
+    }
+    out << "}\n";
+    if (!out) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+// The fastest entry of a tuning table (the first of equal times).
+void take_best(BatchClass &cl) {
+  for (size_t i = 0; i < cl.tried.size(); ++i)
+    if (i == 0 || cl.tried[i].second < cl.ms) {
+      cl.cfg = cl.tried[i].first;
+      cl.ms = cl.tried[i].second;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Work lists
+// ---------------------------------------------------------------------------
+
+// Units of one plan's product under configuration c (item k of the launch).
+void add_units(std::vector<WorkUnit> &u, int item, int tiles, int tiles_m, int K,
+               const WorkConfig &c) {
+  const int KT = stages_of(c, K), tiles_n = tiles / tiles_m;
+  for (int t = 0; t < tiles; ++t)
+    for (int ch = 0; ch < c.split; ++ch) {
+      WorkUnit w{};
+      w.item = item;
+      w.tile = t;
+      w.kb = ch * KT / c.split;
+      w.ke = (ch + 1) * KT / c.split;
+      w.prow = ch * tiles_n + t / tiles_m;
+      u.push_back(w);
+    }
+}
+
+// Longest units first (K stages, then plan and tile order).
+void sort_units(std::vector<WorkUnit> &u) {
+  std::stable_sort(u.begin(), u.end(),
+                   [](const WorkUnit &x, const WorkUnit &y) { return x.ke - x.kb > y.ke - y.kb; });
+}
+
+// Estimated cost of a unit in K stages, with a fixed per-unit share for its
+// prologue and epilogue.
+double unit_cost(const WorkUnit &u) { return (double)(u.ke - u.kb) + 4.0; }
+
+// Persistent grid: the units (longest first) dealt to `grid` workgroups, each
+// to the least-loaded one so far (longest-processing-time list scheduling);
+// u is reordered by workgroup and off[b] .. off[b + 1] - 1 are workgroup b's.
+void assign_units(std::vector<WorkUnit> &u, int grid, std::vector<int> &off) {
+  typedef std::pair<double, int> Load;   // (cost so far, workgroup)
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int b = 0; b < grid; ++b) heap.push({0.0, b});
+  std::vector<std::vector<WorkUnit>> per(grid);
+  for (const auto &w : u) {
+    Load l = heap.top();
+    heap.pop();
+    per[l.second].push_back(w);
+    l.first += unit_cost(w);
+    heap.push(l);
+  }
+  off.assign(grid + 1, 0);
+  u.clear();
+  for (int b = 0; b < grid; ++b) {
+    off[b] = (int)u.size();
+    u.insert(u.end(), per[b].begin(), per[b].end());
+  }
+  off[grid] = (int)u.size();
+}
+
+
+int occupancy(const gswmtp_batch *b, const WorkConfig &c, int epi) {
+  const int n = is_split_prec(b->precision) ? cgemm_split_work_occupancy(c, epi, b->precision)
+                                             : cgemm_work_occupancy(c, epi);
+  return n > 0 ? n : 1;
+}
+
+hipError_t launch_work(const gswmtp_batch *b, const WorkLaunch &w, hipStream_t s) {
+  return is_split_prec(b->precision) ? launch_cgemm_split_work(w, s) : launch_cgemm_work(w, s);
+}
+
+// Product arguments of plan p under configuration c.  out_cr / out_ci /
+// out_pt (tuning): the adjoint's output redirected.
+int fill_item(const gswmtp_batch *b, const gswmtp_plan *p, int product, const WorkConfig &c,
+              bool honour_done, float *out_cr, float *out_ci, unsigned short *out_pt,
+              void *out) {
+  if (is_split_prec(b->precision))
+    return fill_split_args(p, product == 0, c.tile, honour_done, out_pt, out);
+  return fill_cgemm_args(p, product == 0, c.tile.bm, c.tile.bn, honour_done, out_cr, out_ci,
+                         out);
+}
+
+size_t item_bytes(const gswmtp_batch *b) {
+  return is_split_prec(b->precision) ? split_args_bytes() : cgemm_args_bytes();
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of one class
+// ---------------------------------------------------------------------------
+
+struct TuneScratch {
+  void *buf = nullptr;
+  size_t bytes = 0;
+  ~TuneScratch() {
+    if (buf) (void)hipFree(buf);
+  }
+  hipError_t need(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    if (buf) (void)hipFree(buf);
+    buf = nullptr;
+    bytes = 0;
+    const hipError_t e = hipMalloc(&buf, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+};
+
+int tune_class(gswmtp_batch *b, BatchClass &cl, TuneScratch &ts) {
+  const std::vector<WorkConfig> cands = candidates(b->precision, cl.product, cl.M, cl.N);
+  const int epi = cl.product == 0 ? EPI_GATHER : EPI_PROJECT;
+  const size_t isz = item_bytes(b);
+  const int np = (int)cl.plans.size();
+  const bool split = is_split_prec(b->precision);
+  // adjoint output redirected to scratch: per plan [Rp][Cp] float planes, or
+  // the split planes of P^T
+  std::vector<size_t> out_off(np, 0);
+  size_t out_bytes = 0;
+  for (int k = 0; k < np; ++k) {
+    const gswmtp_plan *p = b->plans[cl.plans[k]];
+    const size_t plane = (size_t)p->d.Rp * p->d.Cp;
+    out_off[k] = out_bytes;
+    if (cl.product == 1)
+      out_bytes += align256(split ? 2 * (size_t)split_terms_of(b->precision) * plane * 2
+                                  : 2 * plane * sizeof(float));
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BHIP_TRY(b, hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, GSWMTP_E_HIP, "tuning events", he);
+  }
+  int rc = GSWMTP_OK;
+  for (size_t ci = 0; ci < cands.size() && rc == GSWMTP_OK; ++ci) {
+    const WorkConfig &c = cands[ci];
+    // the class's units, repeated until they fill the chip twice
+    std::vector<WorkUnit> units;
+    for (int k = 0; k < np; ++k) {
+      const gswmtp_plan *p = b->plans[cl.plans[k]];
+      const int tiles_m = (cl.product == 0 ? p->d.Urp : p->d.Rp) / c.tile.bm;
+      add_units(units, k, tiles_m * (p->d.Cp / c.tile.bn), tiles_m, cl.K, c);
+    }
+    const int slots = b->cus * occupancy(b, c, epi);
+    const int one = (int)units.size();
+    const int reps = std::max(1, (2 * slots + one - 1) / one);
+    std::vector<WorkUnit> all;
+    all.reserve((size_t)one * reps);
+    for (int r = 0; r < reps; ++r) all.insert(all.end(), units.begin(), units.end());
+    const int grid = b->persistent ? std::min((int)all.size(), slots) : (int)all.size();
+    std::vector<int> off;
+    if (b->persistent) assign_units(all, grid, off);
+    // scratch: [adjoint outputs][items][units][unit ranges]
+    const size_t need = align256(out_bytes) + align256(isz * np) +
+                        align256(all.size() * sizeof(WorkUnit)) +
+                        align256(off.size() * sizeof(int));
+    if ((he = ts.need(need)) != hipSuccess) {
+      rc = bfail(b, GSWMTP_E_NOMEM, "batch tuning scratch", he);
+      break;
+    }
+    char *base = static_cast<char *>(ts.buf);
+    std::vector<unsigned char> items(isz * np);
+    for (int k = 0; k < np; ++k) {
+      const gswmtp_plan *p = b->plans[cl.plans[k]];
+      const size_t plane = (size_t)p->d.Rp * p->d.Cp;
+      char *o = base + out_off[k];
+      float *cr = nullptr, *cim = nullptr;
+      unsigned short *pt = nullptr;
+      if (cl.product == 1) {
+        if (split) {
+          pt = reinterpret_cast<unsigned short *>(o);
+        } else {
+          cr = reinterpret_cast<float *>(o);
+          cim = cr + plane;
+        }
+      }
+      fill_item(b, p, cl.product, c, false, cr, cim, pt, items.data() + k * isz);
+    }
+    char *d_items = base + align256(out_bytes);
+    WorkUnit *d_work = reinterpret_cast<WorkUnit *>(d_items + align256(items.size()));
+    int *d_off = reinterpret_cast<int *>(reinterpret_cast<char *>(d_work) +
+                                         align256(all.size() * sizeof(WorkUnit)));
+    if ((he = hipMemcpy(d_items, items.data(), items.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (he = hipMemcpy(d_work, all.data(), all.size() * sizeof(WorkUnit),
+                        hipMemcpyHostToDevice)) != hipSuccess ||
+        (!off.empty() && (he = hipMemcpy(d_off, off.data(), off.size() * sizeof(int),
+                                         hipMemcpyHostToDevice)) != hipSuccess)) {
+      rc = bfail(b, GSWMTP_E_HIP, "batch tuning upload", he);
+      break;
+    }
+    WorkLaunch w;
+    w.cfg = c;
+    w.epi = epi;
+    w.precision = b->precision;
+    w.d_items = d_items;
+    w.d_work = d_work;
+    w.d_off = off.empty() ? nullptr : d_off;
+    w.n_work = (int)all.size();
+    w.grid = grid;
+    constexpr int kReps = 3;
+    if ((he = launch_work(b, w, b->stream)) != hipSuccess ||   // warm-up
+        (he = hipEventRecord(e0, b->stream)) != hipSuccess) {
+      rc = bfail(b, GSWMTP_E_HIP, "batch tuning launch", he);
+      break;
+    }
+    for (int r = 0; r < kReps && he == hipSuccess; ++r) he = launch_work(b, w, b->stream);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventRecord(e1, b->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      rc = bfail(b, GSWMTP_E_HIP, "batch tuning launch", he);
+      break;
+    }
+    cl.tried.push_back({c, (double)ms / kReps / reps});   // one copy of the class's units
+  }
+  (void)hipStreamSynchronize(b->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Stages of a batched pass
+// ---------------------------------------------------------------------------
+
+// One product: its configurations' launches, the first on `s`, the others
+// as parallel branches forked from `s` and joined back to it.
+hipError_t enqueue_product(gswmtp_batch *b, int product, hipStream_t s) {
+  const std::vector<WorkLaunch> &ws = b->work[product];
+  if (ws.empty()) return hipSuccess;
+  hipError_t e;
+  const int side = (int)ws.size() - 1;
+  if (side > 0) {
+    if ((e = hipEventRecord(b->ev_fork, s)) != hipSuccess) return e;
+    for (int k = 0; k < side; ++k)
+      if ((e = hipStreamWaitEvent(b->side[k], b->ev_fork, 0)) != hipSuccess) return e;
+  }
+  if ((e = launch_work(b, ws[0], s)) != hipSuccess) return e;
+  for (int k = 0; k < side; ++k) {
+    if ((e = launch_work(b, ws[k + 1], b->side[k])) != hipSuccess) return e;
+    if ((e = hipEventRecord(b->ev_join[k], b->side[k])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, b->ev_join[k], 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t enqueue_batch_pass(gswmtp_batch *b, hipStream_t s) {
   hipError_t e;
   const int n = (int)b->plans.size();
-  if (b->precision != GSWMTP_FP32) {
-    if ((e = launch_cgemm_split_grouped(b->fwd, s)) != hipSuccess) return e;
-    if ((e = launch_update_grouped(b->upd, s)) != hipSuccess) return e;
+  if ((e = enqueue_product(b, 0, s)) != hipSuccess) return e;
+  if ((e = launch_update_grouped(b->upd, s)) != hipSuccess) return e;
+  if (is_split_prec(b->precision)) {
     if ((e = launch_scatter_split_grouped(b->d_sc, b->d_sc_starts, n, b->sc_blocks, b->precision,
                                           s)) != hipSuccess)
       return e;
-    return launch_cgemm_split_grouped(b->bwd, s);
+  } else {
+    if ((e = launch_scatter_grouped(b->d_sc, b->d_sc_starts, n, b->sc_blocks, s)) != hipSuccess)
+      return e;
   }
-  if ((e = launch_cgemm_grouped(b->fwd, s)) != hipSuccess) return e;
-  if ((e = launch_update_grouped(b->upd, s)) != hipSuccess) return e;
-  if ((e = launch_scatter_grouped(b->d_sc, b->d_sc_starts, n, b->sc_blocks, s)) != hipSuccess)
-    return e;
-  return launch_cgemm_grouped(b->bwd, s);
+  return enqueue_product(b, 1, s);
 }
 
 hipError_t capture_batch(gswmtp_batch *b, int passes, hipGraphExec_t *out) {
@@ -136,228 +579,217 @@ hipError_t capture_batch(gswmtp_batch *b, int passes, hipGraphExec_t *out) {
 void free_batch(gswmtp_batch *b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto st : b->side)
+    if (st) (void)hipStreamSynchronize(st);
   if (b->graph1) (void)hipGraphExecDestroy(b->graph1);
   if (b->graph8) (void)hipGraphExecDestroy(b->graph8);
   if (b->pool) (void)hipFree(b->pool);
   for (auto e : b->ev_plan)
     if (e) (void)hipEventDestroy(e);
+  for (auto e : b->ev_join)
+    if (e) (void)hipEventDestroy(e);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   if (b->ev_user) (void)hipEventDestroy(b->ev_user);
   if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+  for (auto st : b->side)
+    if (st) (void)hipStreamDestroy(st);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
 
-// Host image of one grouped product: items in dispatch order and their
-// first-block offsets.
-struct GroupedHost {
-  std::vector<unsigned char> items;
-  std::vector<int> starts;
-  int blocks = 0;
-};
-
-// tuning: a timing run (no done flag; the adjoint's projected field goes to
-// `scratch`, which holds 2 Rp Cp floats per plan, so no plan state changes).
-GroupedHost build_grouped(const std::vector<gswmtp_plan *> &plans, const std::vector<int> &order,
-                          bool forward, int bm, int bn, bool tuning, float *scratch) {
-  const size_t sz = cgemm_args_bytes();
-  GroupedHost g;
-  g.items.resize(sz * order.size());
-  g.starts.resize(order.size() + 1);
-  size_t off = 0;
-  for (size_t k = 0; k < order.size(); ++k) {
-    const gswmtp_plan *p = plans[order[k]];
-    float *cr = nullptr, *ci = nullptr;
-    if (tuning && !forward) {
-      const size_t n = (size_t)p->d.Rp * p->d.Cp;
-      cr = scratch + off;
-      ci = scratch + off + n;
-      off += 2 * n;
+// Shape classes of both products, in first-appearance order.
+void make_classes(gswmtp_batch *b) {
+  std::map<std::tuple<int, int, int, int>, int> index;
+  for (int i = 0; i < (int)b->plans.size(); ++i) {
+    const Dims &d = b->plans[i]->d;
+    for (int product = 0; product < 2; ++product) {
+      const int M = product == 0 ? d.Urp : d.Rp, N = d.Cp, K = product == 0 ? d.Rp : d.Urp;
+      const auto key = std::make_tuple(product, M, N, K);
+      auto it = index.find(key);
+      if (it == index.end()) {
+        BatchClass c;
+        c.product = product;
+        c.M = M;
+        c.N = N;
+        c.K = K;
+        it = index.emplace(key, (int)b->classes.size()).first;
+        b->classes.push_back(c);
+      }
+      b->classes[it->second].plans.push_back(i);
     }
-    g.starts[k] = g.blocks;
-    g.blocks += fill_cgemm_args(p, forward, bm, bn, !tuning, cr, ci, g.items.data() + k * sz);
   }
-  g.starts[order.size()] = g.blocks;
-  return g;
 }
 
-bool tile_valid(const std::vector<gswmtp_plan *> &plans, bool forward, int bm, int bn) {
-  for (const auto *p : plans) {
-    const int M = forward ? p->d.Urp : p->d.Rp;
-    if (M % bm || p->d.Cp % bn) return false;
-  }
-  return true;
-}
-
-// Device copies of a grouped product (items + starts) carved from `base`.
-int upload_grouped(gswmtp_batch *b, const GroupedHost &h, char *&base, GroupedLaunch &g) {
-  const size_t isz = align256(h.items.size()), ssz = align256(h.starts.size() * sizeof(int));
-  g.d_items = base;
-  g.d_starts = reinterpret_cast<int *>(base + isz);
-  base += isz + ssz;
-  g.n_items = (int)h.starts.size() - 1;
-  g.blocks = h.blocks;
-  BHIP_TRY(b, hipMemcpy(g.d_items, h.items.data(), h.items.size(), hipMemcpyHostToDevice));
-  BHIP_TRY(b, hipMemcpy(g.d_starts, h.starts.data(), h.starts.size() * sizeof(int),
-                        hipMemcpyHostToDevice));
-  return GSWMTP_OK;
-}
-
-size_t grouped_bytes(size_t n, size_t item = cgemm_args_bytes()) {
-  return align256(item * n) + align256((n + 1) * sizeof(int));
-}
-
-// Split-precision products: one plan's whole-tile schedule per item.
-GroupedHost build_grouped_split(const std::vector<gswmtp_plan *> &plans,
-                                const std::vector<int> &order, bool forward, const GemmTile &tl) {
-  const size_t sz = split_args_bytes();
-  GroupedHost g;
-  g.items.resize(sz * order.size());
-  g.starts.resize(order.size() + 1);
-  for (size_t k = 0; k < order.size(); ++k) {
-    g.starts[k] = g.blocks;
-    g.blocks += fill_split_args(plans[order[k]], forward, tl, true, g.items.data() + k * sz);
-  }
-  g.starts[order.size()] = g.blocks;
-  return g;
-}
-
-// Split-precision tiles: the product loops of the single-plan form (the
-// software-pipelined loop for two terms, two k-groups for three), 64 x 64,
-// or a 64 x 128 forward tile (two terms) when GSWMTP_BATCH_TILE=64x128 asks
-// and it divides every plan.
-int choose_split_tile(gswmtp_batch *b, bool forward, GemmTile &t) {
-  const int nt = split_terms_of(b->precision);
-  t = GemmTile{64, 64, 32, nt > 2 ? 2 : 1, nt > 2 ? 0 : 1};
-  if (nt > 2) {
-    if (tile_valid(b->plans, forward, 64, 64)) return GSWMTP_OK;
-    return bfail(b, GSWMTP_E_INVAL, "no split tile divides every plan");
-  }
-  const bool v64 = tile_valid(b->plans, forward, 64, 64);
-  const bool v128 = tile_valid(b->plans, forward, 64, 128);
-  const char *env = std::getenv("GSWMTP_BATCH_TILE");
-  if (env && std::strcmp(env, "64x128") == 0 && v128) {
-    t.bn = 128;
-    return GSWMTP_OK;
-  }
-  if (v64) return GSWMTP_OK;
-  if (v128) {
-    t.bn = 128;
-    return GSWMTP_OK;
-  }
-  return bfail(b, GSWMTP_E_INVAL, "no split tile divides every plan");
-}
-
-// Autotuning: among the tiles valid for every plan, the one with the lowest
-// mean duration of the grouped product (a few timed launches each).  Only
-// run when more than one tile is valid; GSWMTP_BATCH_TILE=BMxBN fixes it.
-int choose_batch_tile(gswmtp_batch *b, bool forward, const std::vector<int> &order, int &bm,
-                      int &bn) {
-  const int dir = forward ? 0 : 1;
-  std::vector<int> valid;
-  for (int c = 0; c < 4; ++c)
-    if (tile_valid(b->plans, forward, kCand[c][0], kCand[c][1])) valid.push_back(c);
-  if (valid.empty()) return bfail(b, GSWMTP_E_INVAL, "no tile divides every plan");
-  const char *env = std::getenv("GSWMTP_BATCH_TILE");
-  if (env) {
-    int ebm = 0, ebn = 0;
-    if (std::sscanf(env, "%dx%d", &ebm, &ebn) == 2)
-      for (int c : valid)
-        if (kCand[c][0] == ebm && kCand[c][1] == ebn) {
-          bm = ebm;
-          bn = ebn;
-          return GSWMTP_OK;
-        }
-  }
-  bm = kCand[valid[0]][0];
-  bn = kCand[valid[0]][1];
+// Configuration of every class: forced, the plans' own, cached or tuned.
+int configure_classes(gswmtp_batch *b) {
+  const char *tenv = std::getenv("GSWMTP_BATCH_TILE");
   const char *nt = std::getenv("GSWMTP_BATCH_NO_TUNE");
-  if (valid.size() == 1 || (nt && std::atoi(nt) != 0)) return GSWMTP_OK;
-
-  const size_t need = grouped_bytes(b->plans.size());
-  size_t sbytes = 0;
-  if (!forward)
-    for (const auto *p : b->plans) sbytes += 2 * (size_t)p->d.Rp * p->d.Cp * sizeof(float);
-  void *tmp = nullptr;
-  BHIP_TRY(b, hipMalloc(&tmp, need + sbytes));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  int rc = GSWMTP_OK;
-  float best = 0.f;
-  hipError_t he = hipEventCreate(&e0);
-  if (he == hipSuccess) he = hipEventCreate(&e1);
-  for (size_t vi = 0; vi < valid.size() && he == hipSuccess; ++vi) {
-    const int c = valid[vi];
-    const GroupedHost h = build_grouped(b->plans, order, forward, kCand[c][0], kCand[c][1], true,
-                                        reinterpret_cast<float *>(static_cast<char *>(tmp) + need));
-    char *base = static_cast<char *>(tmp);
-    GroupedLaunch g;
-    g.bm = kCand[c][0];
-    g.bn = kCand[c][1];
-    g.epi = forward ? EPI_GATHER : EPI_PROJECT;
-    if ((rc = upload_grouped(b, h, base, g)) != GSWMTP_OK) break;
-    constexpr int kReps = 4;
-    if ((he = launch_cgemm_grouped(g, b->stream)) != hipSuccess) break;   // warm-up
-    if ((he = hipEventRecord(e0, b->stream)) != hipSuccess) break;
-    for (int r = 0; r < kReps && he == hipSuccess; ++r) he = launch_cgemm_grouped(g, b->stream);
-    if (he != hipSuccess) break;
-    if ((he = hipEventRecord(e1, b->stream)) != hipSuccess) break;
-    if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
-    float ms = 0.f;
-    if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-    ms /= kReps;
-    b->tune_ms[dir][c] = ms;
-    if (vi == 0 || ms < best) {
-      best = ms;
-      bm = g.bm;
-      bn = g.bn;
+  const bool plan_cfg = (tenv && std::strcmp(tenv, "plan") == 0) || (nt && std::atoi(nt) != 0);
+  const char *cpath = std::getenv("GSWMTP_TUNE_CACHE");
+  hipDeviceProp_t prop;
+  BHIP_TRY(b, hipGetDeviceProperties(&prop, b->device));
+  std::string arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  if (cpath && *cpath) cache_load(cpath);
+  TuneScratch ts;
+  bool tuned = false;
+  for (auto &cl : b->classes) {
+    const gswmtp_plan *p0 = b->plans[cl.plans[0]];
+    WorkConfig forced;
+    if (env_tile(b->precision, cl.product, cl.M, cl.N, forced)) {
+      cl.cfg = forced;
+      cl.source = 3;
+      continue;
+    }
+    const std::vector<WorkConfig> cands = candidates(b->precision, cl.product, cl.M, cl.N);
+    if (plan_cfg || cands.size() <= 1) {
+      cl.cfg = cands.size() == 1 && !plan_cfg ? cands[0] : plan_config(p0, cl.product);
+      cl.source = 0;
+      continue;
+    }
+    const std::string key = cache_key(arch, b->cus, b->precision, cl);
+    auto it = g_cache.find(key);
+    bool hit = it != g_cache.end();
+    if (hit)   // every cached candidate must still be one of this build's
+      for (const auto &t : it->second)
+        hit = hit && std::find(cands.begin(), cands.end(), t.first) != cands.end();
+    if (hit) {
+      cl.tried = it->second;
+      take_best(cl);
+      cl.source = 2;
+      continue;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = tune_class(b, cl, ts);
+    b->tune_total_ms +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rc != GSWMTP_OK) return rc;
+    take_best(cl);
+    cl.source = 1;
+    g_cache[key] = cl.tried;
+    tuned = true;
+  }
+  if (tuned && cpath && *cpath && !cache_save(cpath))
+    return bfail(b, GSWMTP_E_INVAL, "cannot write the tuning cache (GSWMTP_TUNE_CACHE)");
+  // Every extra configuration of a stage is another concurrent launch, which
+  // the stage pays for in balance (one workgroup per unit instead of a
+  // persistent grid): a tuned class whose timing of the product's dominant
+  // configuration (the one with the most padded work) is within 10% of its
+  // own best takes the dominant one.
+  for (int product = 0; product < 2; ++product) {
+    std::vector<std::pair<WorkConfig, double>> work;
+    for (const auto &cl : b->classes) {
+      if (cl.product != product) continue;
+      const double w = (double)cl.M * cl.N * cl.K * cl.plans.size();
+      size_t k = 0;
+      while (k < work.size() && !(work[k].first == cl.cfg)) ++k;
+      if (k == work.size()) work.push_back({cl.cfg, 0.0});
+      work[k].second += w;
+    }
+    if (work.size() < 2) continue;
+    const WorkConfig dom = std::max_element(work.begin(), work.end(), [](const auto &x,
+                                                                         const auto &y) {
+                             return x.second < y.second;
+                           })->first;
+    for (auto &cl : b->classes) {
+      if (cl.product != product || cl.cfg == dom || cl.tried.empty()) continue;
+      for (const auto &t : cl.tried)
+        if (t.first == dom && t.second <= 1.10 * cl.ms) {
+          cl.cfg = dom;
+          cl.ms = t.second;
+        }
     }
   }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  (void)hipStreamSynchronize(b->stream);
-  (void)hipFree(tmp);
-  if (rc != GSWMTP_OK) return rc;
-  if (he != hipSuccess) return bfail(b, GSWMTP_E_HIP, "batch tile tuning", he);
+  // GSWMTP_BATCH_FWD_SPLIT=k: k K chunks on every forward class whose tile
+  // takes them (k <= BN / 64, not the 16x16-block loop)
+  if (const char *fs = std::getenv("GSWMTP_BATCH_FWD_SPLIT")) {
+    const int k = std::atoi(fs);
+    for (auto &cl : b->classes)
+      if (cl.product == 0 && k >= 1 && cl.cfg.tile.pipe != 3 && k <= cl.cfg.tile.bn / 64 &&
+          k <= stages_of(cl.cfg, cl.K))
+        cl.cfg.split = k;
+  }
   return GSWMTP_OK;
 }
 
 int batch_build(gswmtp_batch *b) {
   const int n = (int)b->plans.size();
   BHIP_TRY(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  for (auto &st : b->side) BHIP_TRY(b, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   BHIP_TRY(b, hipEventCreateWithFlags(&b->ev_user, hipEventDisableTiming));
   BHIP_TRY(b, hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+  BHIP_TRY(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+  for (auto &e : b->ev_join) BHIP_TRY(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   b->ev_plan.assign(n, nullptr);
   for (auto &e : b->ev_plan) BHIP_TRY(b, hipEventCreateWithFlags(&e, hipEventDisableTiming));
   // plan-time work of every plan precedes anything the batch launches
   for (auto *p : b->plans) BHIP_TRY(b, hipStreamSynchronize(p->stream));
+  int cus = 0;
+  BHIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+  b->cus = cus > 0 ? cus : 256;
+  const char *pe = std::getenv("GSWMTP_BATCH_PERSIST");
+  b->persistent = !(pe && std::strcmp(pe, "0") == 0);
 
-  // dispatch order: longest tiles (largest K) first
-  std::vector<int> ofwd(n), obwd(n);
-  std::iota(ofwd.begin(), ofwd.end(), 0);
-  std::iota(obwd.begin(), obwd.end(), 0);
-  std::stable_sort(ofwd.begin(), ofwd.end(),
-                   [&](int x, int y) { return b->plans[x]->d.Rp > b->plans[y]->d.Rp; });
-  std::stable_sort(obwd.begin(), obwd.end(),
-                   [&](int x, int y) { return b->plans[x]->d.Urp > b->plans[y]->d.Urp; });
-
+  make_classes(b);
   int rc;
-  const bool split = b->precision != GSWMTP_FP32;
-  if (split) {
-    if ((rc = choose_split_tile(b, true, b->fwd.tile)) != GSWMTP_OK) return rc;
-    if ((rc = choose_split_tile(b, false, b->bwd.tile)) != GSWMTP_OK) return rc;
-    b->fwd.bm = b->fwd.tile.bm;
-    b->fwd.bn = b->fwd.tile.bn;
-    b->bwd.bm = b->bwd.tile.bm;
-    b->bwd.bn = b->bwd.tile.bn;
-    b->fwd.precision = b->bwd.precision = b->precision;
-  } else {
-    if ((rc = choose_batch_tile(b, true, ofwd, b->fwd.bm, b->fwd.bn)) != GSWMTP_OK) return rc;
-    if ((rc = choose_batch_tile(b, false, obwd, b->bwd.bm, b->bwd.bn)) != GSWMTP_OK) return rc;
-  }
-  b->fwd.epi = EPI_GATHER;
-  b->bwd.epi = EPI_PROJECT;
+  if ((rc = configure_classes(b)) != GSWMTP_OK) return rc;
 
-  // update / scatter items in plan order; the many-focus plans' update
-  // items also go to a second table for the update's phases 2 and 3
+  // per plan: its class configuration of each product
+  std::vector<WorkConfig> pcfg[2];
+  pcfg[0].resize(n);
+  pcfg[1].resize(n);
+  for (const auto &cl : b->classes)
+    for (int i : cl.plans) pcfg[cl.product][i] = cl.cfg;
+
+  // product items (one per plan and product) and the work lists per configuration
+  const size_t isz = item_bytes(b);
+  std::vector<unsigned char> items[2];
+  std::vector<WorkConfig> cfgs[2];
+  std::vector<std::vector<WorkUnit>> units[2];
+  for (int product = 0; product < 2; ++product) {
+    items[product].resize(isz * n);
+    for (int i = 0; i < n; ++i) {
+      const gswmtp_plan *p = b->plans[i];
+      const WorkConfig &c = pcfg[product][i];
+      const int tiles = fill_item(b, p, product, c, true, nullptr, nullptr, nullptr,
+                                  items[product].data() + i * isz);
+      size_t k = 0;
+      while (k < cfgs[product].size() && !(cfgs[product][k] == c)) ++k;
+      if (k == cfgs[product].size()) {
+        cfgs[product].push_back(c);
+        units[product].emplace_back();
+      }
+      add_units(units[product][k], i, tiles, (product == 0 ? p->d.Urp : p->d.Rp) / c.tile.bm,
+                product == 0 ? p->d.Rp : p->d.Urp, c);
+    }
+    if ((int)cfgs[product].size() > kBatchBranches + 1)
+      return bfail(b, GSWMTP_E_UNSUPPORTED, "more kernel configurations than parallel branches");
+    // the configuration with most work first (it runs on the main stream)
+    std::vector<size_t> ord(cfgs[product].size());
+    std::iota(ord.begin(), ord.end(), 0);
+    auto work_of = [&](size_t k) {
+      double wsum = 0.0;
+      for (const auto &u : units[product][k])
+        wsum += (double)(u.ke - u.kb) * cfgs[product][k].tile.bm * cfgs[product][k].tile.bn *
+                cfgs[product][k].tile.bk;
+      return wsum;
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return work_of(x) > work_of(y); });
+    std::vector<WorkConfig> c2;
+    std::vector<std::vector<WorkUnit>> u2;
+    for (size_t k : ord) {
+      c2.push_back(cfgs[product][k]);
+      u2.push_back(std::move(units[product][k]));
+      sort_units(u2.back());
+    }
+    cfgs[product] = c2;
+    units[product] = std::move(u2);
+  }
+
+  // focus update and scatter items in plan order; the many-focus plans'
+  // update items also go to a second table for the update's phases 2 and 3
+  const bool split = is_split_prec(b->precision);
   const size_t usz = update_args_bytes();
   const size_t ssz = split ? scatter_split_args_bytes() : scatter_args_bytes();
   std::vector<unsigned char> upd(usz * n), sc(ssz * n), big;
@@ -367,7 +799,9 @@ int batch_build(gswmtp_batch *b) {
   int blocks = 0, ublocks = 0;
   for (int i = 0; i < n; ++i) {
     gswmtp_plan *p = b->plans[i];
-    const int nwg = fill_update_args(p, UPD_ITERATE, b->fwd.bn, upd.data() + i * usz);
+    const WorkConfig &cf = pcfg[0][i];
+    const int nwg = fill_update_args(p, UPD_ITERATE, (p->d.Cp / cf.tile.bn) * cf.split,
+                                     upd.data() + i * usz);
     upd_starts[i] = ublocks;
     ublocks += nwg > 0 ? nwg : 1;
     if (nwg > 0) {
@@ -385,20 +819,66 @@ int batch_build(gswmtp_batch *b) {
   b->sc_blocks = blocks;
   const int nb = (int)big_starts.size() - 1;
 
-  const size_t isz = split ? split_args_bytes() : cgemm_args_bytes();
-  const size_t bytes = 2 * grouped_bytes(n, isz) + align256(usz * n) + align256(ssz * n) +
-                       2 * align256((n + 1) * sizeof(int)) + 2 * align256(n * sizeof(void *)) +
-                       align256(usz * (nb > 0 ? nb : 1)) + align256((nb + 1) * sizeof(int));
+  // Grids and the persistent launches' unit ranges.
+  std::vector<int> grids[2];
+  std::vector<std::vector<int>> offs[2];
+  for (int product = 0; product < 2; ++product) {
+    const int epi = product == 0 ? EPI_GATHER : EPI_PROJECT;
+    for (size_t k = 0; k < cfgs[product].size(); ++k) {
+      auto &u = units[product][k];
+      const int slots = b->cus * occupancy(b, cfgs[product][k], epi);
+      int grid = std::max(1, std::min(slots, (int)u.size()));
+      std::vector<int> off;
+      // persistent when the stage has this configuration alone; several
+      // concurrent configurations run one workgroup per unit, which the
+      // hardware balances across them (a static split between kernels that
+      // share the CUs leaves one waiting on the other)
+      if (b->persistent && cfgs[product].size() == 1 && cfgs[product][k].tile.kg == 1) {
+        assign_units(u, grid, off);
+      } else {
+        grid = (int)u.size();   // one unit per workgroup, longest first
+      }
+      grids[product].push_back(grid);
+      offs[product].push_back(off);
+    }
+  }
+
+  size_t bytes = 2 * align256(isz * n) + align256(usz * n) + align256(ssz * n) +
+                 2 * align256((n + 1) * sizeof(int)) + 2 * align256(n * sizeof(void *)) +
+                 align256(usz * (nb > 0 ? nb : 1)) + align256((nb + 1) * sizeof(int));
+  for (int product = 0; product < 2; ++product)
+    for (size_t k = 0; k < units[product].size(); ++k)
+      bytes += align256(units[product][k].size() * sizeof(WorkUnit)) +
+               align256(offs[product][k].size() * sizeof(int));
   BHIP_TRY(b, hipMalloc(&b->pool, bytes));
   char *base = static_cast<char *>(b->pool);
-  const GroupedHost hf =
-      split ? build_grouped_split(b->plans, ofwd, true, b->fwd.tile)
-            : build_grouped(b->plans, ofwd, true, b->fwd.bm, b->fwd.bn, false, nullptr);
-  const GroupedHost hb =
-      split ? build_grouped_split(b->plans, obwd, false, b->bwd.tile)
-            : build_grouped(b->plans, obwd, false, b->bwd.bm, b->bwd.bn, false, nullptr);
-  if ((rc = upload_grouped(b, hf, base, b->fwd)) != GSWMTP_OK) return rc;
-  if ((rc = upload_grouped(b, hb, base, b->bwd)) != GSWMTP_OK) return rc;
+  for (int product = 0; product < 2; ++product) {
+    char *d_items = base;
+    base += align256(isz * n);
+    BHIP_TRY(b, hipMemcpy(d_items, items[product].data(), items[product].size(),
+                          hipMemcpyHostToDevice));
+    const int epi = product == 0 ? EPI_GATHER : EPI_PROJECT;
+    for (size_t k = 0; k < cfgs[product].size(); ++k) {
+      const auto &u = units[product][k];
+      WorkLaunch w;
+      w.cfg = cfgs[product][k];
+      w.epi = epi;
+      w.precision = b->precision;
+      w.d_items = d_items;
+      w.d_work = reinterpret_cast<const WorkUnit *>(base);
+      w.n_work = (int)u.size();
+      w.grid = grids[product][k];
+      BHIP_TRY(b, hipMemcpy(base, u.data(), u.size() * sizeof(WorkUnit), hipMemcpyHostToDevice));
+      base += align256(u.size() * sizeof(WorkUnit));
+      const auto &off = offs[product][k];
+      if (!off.empty()) {
+        w.d_off = reinterpret_cast<const int *>(base);
+        BHIP_TRY(b, hipMemcpy(base, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+        base += align256(off.size() * sizeof(int));
+      }
+      b->work[product].push_back(w);
+    }
+  }
   b->upd.d_items = base;
   base += align256(usz * n);
   b->upd.d_starts = reinterpret_cast<int *>(base);
@@ -432,6 +912,21 @@ int batch_build(gswmtp_batch *b) {
   BHIP_TRY(b, hipMemcpy(b->d_ctrl, ctrl.data(), n * sizeof(void *), hipMemcpyHostToDevice));
   BHIP_TRY(b, hipMemcpy(b->d_stats, stats.data(), n * sizeof(void *), hipMemcpyHostToDevice));
   return GSWMTP_OK;
+}
+
+// The class with the most padded work of a product.
+const BatchClass *largest_class(const gswmtp_batch *b, int product) {
+  const BatchClass *best = nullptr;
+  double bw = -1.0;
+  for (const auto &c : b->classes) {
+    if (c.product != product) continue;
+    const double w = (double)c.M * c.N * c.K * c.plans.size();
+    if (w > bw) {
+      bw = w;
+      best = &c;
+    }
+  }
+  return best;
 }
 
 }  // namespace
@@ -542,13 +1037,65 @@ int gswmtp_batch_sync(gswmtp_batch *b) {
 
 int gswmtp_batch_tiles(const gswmtp_batch *b, int *tiles, double *tune_ms) {
   if (!b || !tiles) return GSWMTP_E_INVAL;
-  tiles[0] = b->fwd.bm;
-  tiles[1] = b->fwd.bn;
-  tiles[2] = b->bwd.bm;
-  tiles[3] = b->bwd.bn;
-  if (tune_ms)
-    for (int d = 0; d < 2; ++d)
-      for (int c = 0; c < 4; ++c) tune_ms[4 * d + c] = b->tune_ms[d][c];
+  for (int product = 0; product < 2; ++product) {
+    const BatchClass *c = largest_class(b, product);
+    tiles[2 * product] = c ? c->cfg.tile.bm : 0;
+    tiles[2 * product + 1] = c ? c->cfg.tile.bn : 0;
+  }
+  if (tune_ms) {
+    static const int cand[4][2] = {{64, 64}, {64, 128}, {128, 64}, {128, 128}};
+    for (int product = 0; product < 2; ++product) {
+      const BatchClass *c = largest_class(b, product);
+      for (int k = 0; k < 4; ++k) {
+        tune_ms[4 * product + k] = 0.0;
+        if (!c) continue;
+        for (const auto &t : c->tried)
+          if (t.first.tile.bm == cand[k][0] && t.first.tile.bn == cand[k][1] &&
+              t.first.split == 1 && t.first.tile.pipe != 3)
+            tune_ms[4 * product + k] = t.second;
+      }
+    }
+  }
+  return GSWMTP_OK;
+}
+
+int gswmtp_batch_n_classes(const gswmtp_batch *b, int *n) {
+  if (!b || !n) return GSWMTP_E_INVAL;
+  *n = (int)b->classes.size();
+  return GSWMTP_OK;
+}
+
+int gswmtp_batch_class_info(const gswmtp_batch *b, int i, gswmtp_batch_class *out) {
+  if (!b || !out || i < 0 || i >= (int)b->classes.size()) return GSWMTP_E_INVAL;
+  const BatchClass &c = b->classes[i];
+  std::memset(out, 0, sizeof *out);
+  out->product = c.product;
+  out->m = c.M;
+  out->n = c.N;
+  out->k = c.K;
+  out->n_plans = (int)c.plans.size();
+  auto put = [](const WorkConfig &w, int *cfg) {
+    cfg[0] = w.tile.bm;
+    cfg[1] = w.tile.bn;
+    cfg[2] = w.tile.bk;
+    cfg[3] = w.tile.kg;
+    cfg[4] = w.tile.pipe;
+    cfg[5] = w.split;
+  };
+  put(c.cfg, out->config);
+  out->ms = c.ms;
+  out->source = c.source;
+  out->n_tried = (int)std::min<size_t>(c.tried.size(), GSWMTP_BATCH_MAX_CANDIDATES);
+  for (int k = 0; k < out->n_tried; ++k) {
+    put(c.tried[k].first, out->tried_config[k]);
+    out->tried_ms[k] = c.tried[k].second;
+  }
+  return GSWMTP_OK;
+}
+
+int gswmtp_batch_tune_ms(const gswmtp_batch *b, double *ms) {
+  if (!b || !ms) return GSWMTP_E_INVAL;
+  *ms = b->tune_total_ms;
   return GSWMTP_OK;
 }
 

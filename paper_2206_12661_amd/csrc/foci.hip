@@ -986,9 +986,9 @@ hipError_t launch_update(const gswmtp_plan *p, int mode, hipStream_t s) {
 }
 
 size_t update_args_bytes() { return sizeof(UpdateArgs); }
-int fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out) {
+int fill_update_args(const gswmtp_plan *p, int mode, int partials, void *out) {
   UpdateArgs a = update_args(p, mode);
-  a.T = p->d.Cp / gather_bn;   // partials per focus of the batch's forward tile
+  a.T = partials;   // partials per focus of the batch's forward product
   std::memcpy(out, &a, sizeof a);
   return a.nwg;
 }

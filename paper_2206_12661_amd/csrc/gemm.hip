@@ -108,10 +108,15 @@ constexpr int f32_lds_floats() {
   return A_F + B_F > G_F ? A_F + B_F : G_F;
 }
 
-// One workgroup's share of a product: whole tile, K chunk (phase 0) or tail
-// reduction (phase 1) number `bid` of the schedule in `a`.
+// One unit of a product: tile t over K stages [kb, ke).  tail < 0: the
+// epilogue runs on the sums (a forward tile's gather writes partial row prow,
+// -1: n0 / BN); tail >= 0 in phase 0: chunk `chunk` of tail tile `tail`
+// stores its partial tile; phase 1 (kb = ke): tail tile `tail` adds its
+// chunks' partials in order and runs the epilogue.
 template <int BM, int BN, int EPI>
-__device__ __forceinline__ void cgemm_f32_body(const CgemmArgs &a, const int bid, float *lds) {
+__device__ __forceinline__ void cgemm_f32_unit(const CgemmArgs &a, const int t, const int kb,
+                                               const int ke, const int tail, const int chunk,
+                                               const int prow, float *lds) {
   constexpr int WTM = BM / 2, WTN = BN / 2;    // wave tile (complex)
   constexpr int MB = WTM / 32, NB = WTN / 32;  // 32x32 blocks per wave
   constexpr int SA = BM + 32, SB = BN + 32;    // padded LDS row pitch (floats)
@@ -127,24 +132,6 @@ __device__ __forceinline__ void cgemm_f32_body(const CgemmArgs &a, const int bid
   constexpr int BUF_A = 2 * kBK * SA, BUF_B = 2 * kBK * SB;
 
   const int tid = threadIdx.x;
-  const int KT = a.K / kBK;
-  int t, kb, ke, tail = -1, chunk = 0;
-  if (a.phase == 1) {
-    tail = bid;
-    t = a.t_dp + tail;
-    kb = ke = 0;
-  } else if (bid < a.t_dp) {
-    t = xcd_tile(bid, a.t_dp);
-    kb = 0;
-    ke = KT;
-  } else {
-    const int u = bid - a.t_dp;
-    tail = u / a.split;
-    chunk = u % a.split;
-    t = a.t_dp + tail;
-    kb = chunk * KT / a.split;
-    ke = (chunk + 1) * KT / a.split;
-  }
   const int m0 = (t % a.tiles_m) * BM;
   const int n0 = (t / a.tiles_m) * BN;
 
@@ -304,31 +291,50 @@ __device__ __forceinline__ void cgemm_f32_body(const CgemmArgs &a, const int bid
     }
   }
   if constexpr (EPI == EPI_GATHER)
-    gather_epilogue<BM, BN>(a.g, accR, accI, lds, m0, n0, tid);
+    gather_epilogue<BM, BN>(a.g, accR, accI, lds, m0, n0, tid, prow);
   else
     epilogue<MB, NB, EPI>(a, accR, accI, m0 + wm * WTM, n0 + wn * WTN, l32, h);
+}
+
+// One workgroup's share of a product: whole tile, K chunk (phase 0) or tail
+// reduction (phase 1) number `bid` of the schedule in `a`.
+template <int BM, int BN, int EPI>
+__device__ __forceinline__ void cgemm_f32_body(const CgemmArgs &a, const int bid, float *lds) {
+  const int KT = a.K / kBK;
+  if (a.phase == 1) {
+    cgemm_f32_unit<BM, BN, EPI>(a, a.t_dp + bid, 0, 0, bid, 0, -1, lds);
+  } else if (bid < a.t_dp) {
+    cgemm_f32_unit<BM, BN, EPI>(a, xcd_tile(bid, a.t_dp), 0, KT, -1, 0, -1, lds);
+  } else {
+    const int u = bid - a.t_dp, tail = u / a.split, chunk = u % a.split;
+    cgemm_f32_unit<BM, BN, EPI>(a, a.t_dp + tail, chunk * KT / a.split,
+                                (chunk + 1) * KT / a.split, tail, chunk, -1, lds);
+  }
+}
+
+// Work-list launch (batched form): workgroup b runs the units off[b] ..
+// off[b + 1] - 1 of the list (a persistent grid, the ranges balanced on the
+// host), or unit b alone when off is null; each unit is a tile (or the K
+// chunk of a forward tile) of one plan's product; the LDS is reused from unit
+// to unit behind a barrier.
+template <int BM, int BN, int EPI>
+__global__ __launch_bounds__(kThreads) void cgemm_f32_work(const CgemmArgs *items,
+                                                           const WorkUnit *work, const int *off, int n) {
+  __shared__ __attribute__((aligned(16))) float lds[f32_lds_floats<BM, BN, EPI>()];
+  // units off[b] .. off[b + 1] - 1 (persistent), or unit b (off null)
+  const int w0 = off ? off[blockIdx.x] : (int)blockIdx.x;
+  const int w1 = off ? off[blockIdx.x + 1] : w0 + 1;
+  for (int w = w0; w < w1 && w < n; ++w) {
+    if (w != w0) __syncthreads();   // the previous unit's LDS reads are done
+    const WorkUnit u = work[w];
+    cgemm_f32_unit<BM, BN, EPI>(items[u.item], u.tile, u.kb, u.ke, -1, 0, u.prow, lds);
+  }
 }
 
 template <int BM, int BN, int EPI>
 __global__ __launch_bounds__(kThreads) void cgemm_f32_mfma(CgemmArgs a) {
   __shared__ __attribute__((aligned(16))) float lds[f32_lds_floats<BM, BN, EPI>()];
   cgemm_f32_body<BM, BN, EPI>(a, blockIdx.x, lds);
-}
-
-// Grouped launch: the concatenated schedules of several products (one per
-// plan of a batch); workgroup b runs item h's block b - starts[h].
-template <int BM, int BN, int EPI>
-__global__ __launch_bounds__(kThreads) void cgemm_f32_grouped(const CgemmArgs *items,
-                                                              const int *starts, int n) {
-  __shared__ __attribute__((aligned(16))) float lds[f32_lds_floats<BM, BN, EPI>()];
-  const int b = blockIdx.x;
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (starts[mid] <= b) lo = mid; else hi = mid;
-  }
-  const CgemmArgs a = items[lo];
-  cgemm_f32_body<BM, BN, EPI>(a, b - starts[lo], lds);
 }
 
 // Split-K tail with the projection epilogue: adds the K-chunk partials of
@@ -528,8 +534,8 @@ hipError_t launch_cgemm_ex(const gswmtp_plan *p, const GemmSched &sc, const floa
 
 size_t cgemm_args_bytes() { return sizeof(CgemmArgs); }
 
-// Arguments of plan p's product for a grouped (batched) launch with tile
-// (bm, bn): every tile whole (no K split).  honour_done: return at once when
+// Arguments of plan p's product for a batched work-list launch with tile
+// (bm, bn); the work units pick the tiles and K ranges.  honour_done: return at once when
 // the plan's done flag is set.  cr / ci (adjoint only, nullable): write the
 // projected field there instead of the plan's pupil field.  Returns the
 // block count (tiles).
@@ -563,25 +569,47 @@ int fill_cgemm_args(const gswmtp_plan *p, bool forward, int bm, int bn, bool hon
   return a.t_dp;
 }
 
-hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s) {
-  const auto *items = static_cast<const CgemmArgs *>(g.d_items);
-#define GROUPED(BM, BN, EPI)                                                                   \
-  hipLaunchKernelGGL((cgemm_f32_grouped<BM, BN, EPI>), dim3(g.blocks), dim3(kThreads), 0, s, \
-                     items, g.d_starts, g.n_items)
-#define GROUPED_EPI(BM, BN)                                  \
-  do {                                                       \
-    if (g.epi == EPI_GATHER) GROUPED(BM, BN, EPI_GATHER);    \
-    else if (g.epi == EPI_PROJECT) GROUPED(BM, BN, EPI_PROJECT); \
-    else return hipErrorInvalidValue;                        \
+hipError_t launch_cgemm_work(const WorkLaunch &w, hipStream_t s) {
+  if (w.n_work == 0) return hipSuccess;
+  const auto *items = static_cast<const CgemmArgs *>(w.d_items);
+  const GemmTile &t = w.cfg.tile;
+#define WORK(BM, BN, EPI)                                                                   \
+  hipLaunchKernelGGL((cgemm_f32_work<BM, BN, EPI>), dim3(w.grid), dim3(kThreads), 0, s, items, \
+                     w.d_work, w.d_off, w.n_work)
+#define WORK_EPI(BM, BN)                                        \
+  do {                                                          \
+    if (w.epi == EPI_GATHER) WORK(BM, BN, EPI_GATHER);          \
+    else if (w.epi == EPI_PROJECT) WORK(BM, BN, EPI_PROJECT);   \
+    else return hipErrorInvalidValue;                           \
   } while (0)
-  if (g.bm == 64 && g.bn == 64) GROUPED_EPI(64, 64);
-  else if (g.bm == 64 && g.bn == 128) GROUPED_EPI(64, 128);
-  else if (g.bm == 128 && g.bn == 64) GROUPED_EPI(128, 64);
-  else if (g.bm == 128 && g.bn == 128) GROUPED_EPI(128, 128);
+  if (t.bm == 64 && t.bn == 64) WORK_EPI(64, 64);
+  else if (t.bm == 64 && t.bn == 128) WORK_EPI(64, 128);
+  else if (t.bm == 128 && t.bn == 64) WORK_EPI(128, 64);
+  else if (t.bm == 128 && t.bn == 128) WORK_EPI(128, 128);
   else return hipErrorInvalidValue;
-#undef GROUPED_EPI
-#undef GROUPED
+#undef WORK_EPI
+#undef WORK
   return hipGetLastError();
+}
+
+int cgemm_work_occupancy(const WorkConfig &c, int epi) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define OCC(BM, BN, EPI) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cgemm_f32_work<BM, BN, EPI>, kThreads, 0)
+#define OCC_EPI(BM, BN)                                        \
+  do {                                                         \
+    if (epi == EPI_GATHER) OCC(BM, BN, EPI_GATHER);            \
+    else if (epi == EPI_PROJECT) OCC(BM, BN, EPI_PROJECT);     \
+  } while (0)
+  const GemmTile &t = c.tile;
+  if (t.bm == 64 && t.bn == 64) OCC_EPI(64, 64);
+  else if (t.bm == 64 && t.bn == 128) OCC_EPI(64, 128);
+  else if (t.bm == 128 && t.bn == 64) OCC_EPI(128, 64);
+  else if (t.bm == 128 && t.bn == 128) OCC_EPI(128, 128);
+#undef OCC_EPI
+#undef OCC
+  return e == hipSuccess ? n : 0;
 }
 
 const char *cgemm_kernel_name(const gswmtp_plan *p, bool forward, int) {

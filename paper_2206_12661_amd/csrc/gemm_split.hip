@@ -372,10 +372,16 @@ __device__ __forceinline__ bool direct_loop(const SplitArgs &a, int m0, int n0, 
   return true;
 }
 
-// The product for block `bid` of one schedule (whole tile, K chunk or tail
-// reduction), LDS `lds` of split_lds_u4 entries.
+// One unit of a product: tile t over K stages [kb, ke) (LDS `lds` of
+// split_lds_u4 entries).  tail < 0: the epilogue runs on the sums (a forward
+// tile's gather writes partial row prow, -1: n0 / BN); tail >= 0 in phase 0:
+// chunk `chunk` of tail tile `tail` stores its partial tile; phase 1 (kb =
+// ke): tail tile `tail` adds its chunks' partials in order and runs the
+// epilogue.
 template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
-__device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int bid, u4 *lds) {
+__device__ __forceinline__ void cgemm_split_unit(const SplitArgs &a, const int t, const int kb,
+                                                 const int ke, const int tail, const int chunk,
+                                                 const int prow, u4 *lds) {
   constexpr int NTH = kThreads * KG;
   using L = WaveLayout<BM, BN, PIPE == 2>;
   constexpr int WTM = L::WTM, WTN = L::WTN;
@@ -393,24 +399,6 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
   u4 *sB = lds + 2 * SA_SZ;             // [2][SB_SZ]
 
   const int tid = threadIdx.x;
-  const int KT = a.K / BK;
-  int t, kb, ke, tail = -1, chunk = 0;
-  if (a.phase == 1) {
-    tail = bid;
-    t = a.t_dp + tail;
-    kb = ke = 0;
-  } else if (bid < a.t_dp) {
-    t = xcd_tile(bid, a.t_dp);
-    kb = 0;
-    ke = KT;
-  } else {
-    const int u = bid - a.t_dp;
-    tail = u / a.split;
-    chunk = u % a.split;
-    t = a.t_dp + tail;
-    kb = chunk * KT / a.split;
-    ke = (chunk + 1) * KT / a.split;
-  }
   const int m0 = (t % a.tiles_m) * BM;
   const int n0 = (t / a.tiles_m) * BN;
   const int lane = tid & 63, wave = (tid >> 6) & 3, kg = tid >> 8;
@@ -651,7 +639,7 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
   // epilogue; accumulator item r of lane (l32, h): row 8 (r/4) + 4 h + r % 4, column l32
   if constexpr (EPI == EPI_GATHER) {
     gather_epilogue<BM, BN, PIPE == 2>(a.g, accR, accI, reinterpret_cast<float *>(lds), m0, n0,
-                                       tid, gp);
+                                       tid, gp, prow);
   } else if constexpr (EPI == EPI_STORE) {
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -716,27 +704,48 @@ __device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int b
   }
 }
 
+// The product for block `bid` of one schedule (whole tile, K chunk or tail
+// reduction).
+template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
+__device__ __forceinline__ void cgemm_split_body(const SplitArgs &a, const int bid, u4 *lds) {
+  const int KT = a.K / BK;
+  if (a.phase == 1) {
+    cgemm_split_unit<BM, BN, BK, BF, NT, EPI, KG, PIPE>(a, a.t_dp + bid, 0, 0, bid, 0, -1, lds);
+  } else if (bid < a.t_dp) {
+    cgemm_split_unit<BM, BN, BK, BF, NT, EPI, KG, PIPE>(a, xcd_tile(bid, a.t_dp), 0, KT, -1, 0,
+                                                        -1, lds);
+  } else {
+    const int u = bid - a.t_dp, tail = u / a.split, chunk = u % a.split;
+    cgemm_split_unit<BM, BN, BK, BF, NT, EPI, KG, PIPE>(a, a.t_dp + tail, chunk * KT / a.split,
+                                                        (chunk + 1) * KT / a.split, tail, chunk,
+                                                        -1, lds);
+  }
+}
+
 template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
 __global__ __launch_bounds__(kThreads * KG) void cgemm_split_mfma(SplitArgs a) {
   __shared__ u4 lds[split_lds_u4<BM, BN, BK, BF, NT, EPI, KG, PIPE>()];
   cgemm_split_body<BM, BN, BK, BF, NT, EPI, KG, PIPE>(a, blockIdx.x, lds);
 }
 
-// Grouped launch (batched form): the concatenated whole-tile schedules of
-// several plans' products; block b belongs to the item whose start offset is
-// the largest one <= b (binary search) and runs its local block b - start.
+// Work-list launch (batched form): workgroup b runs the units off[b] ..
+// off[b + 1] - 1 of the list (a persistent grid, the ranges balanced on the
+// host), or unit b alone when off is null; each unit is a tile (or the K
+// chunk of a forward tile) of one plan's product; the LDS is reused from unit
+// to unit behind a barrier.
 template <int BM, int BN, int BK, bool BF, int NT, int EPI, int KG, int PIPE>
-__global__ __launch_bounds__(kThreads * KG) void cgemm_split_grouped(const SplitArgs *items,
-                                                                     const int *starts, int n) {
+__global__ __launch_bounds__(kThreads * KG) void cgemm_split_work(const SplitArgs *items,
+                                                                  const WorkUnit *work, const int *off, int n) {
   __shared__ u4 lds[split_lds_u4<BM, BN, BK, BF, NT, EPI, KG, PIPE>()];
-  const int b = blockIdx.x;
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (starts[mid] <= b) lo = mid;
-    else hi = mid - 1;
+  // units off[b] .. off[b + 1] - 1 (persistent), or unit b (off null)
+  const int w0 = off ? off[blockIdx.x] : (int)blockIdx.x;
+  const int w1 = off ? off[blockIdx.x + 1] : w0 + 1;
+  for (int w = w0; w < w1 && w < n; ++w) {
+    if (w != w0) __syncthreads();   // the previous unit's LDS reads are done
+    const WorkUnit u = work[w];
+    cgemm_split_unit<BM, BN, BK, BF, NT, EPI, KG, PIPE>(items[u.item], u.tile, u.kb, u.ke, -1, 0,
+                                                        u.prow, lds);
   }
-  cgemm_split_body<BM, BN, BK, BF, NT, EPI, KG, PIPE>(items[lo], b - starts[lo], lds);
 }
 
 // Split-K tail with the projection epilogue: adds the K-chunk partials of
@@ -979,12 +988,11 @@ __device__ __forceinline__ bool d16_loop(const SplitArgs &a, int m0, int n0, int
 // One whole tile per workgroup (no K split); epilogues: store float32 C, or
 // project onto the amplitude constraint and write the split planes of P^T.
 template <int BM, int BN, bool BF, int NT, int EPI>
-__global__ __launch_bounds__(kThreads) void cgemm_split_d16(SplitArgs a) {
+__device__ __forceinline__ void cgemm_split_d16_unit(const SplitArgs &a, const int t,
+                                                     const int prow, u4 *lds) {
   constexpr int WTN = BN / 4, MB = BM / 16, NB = WTN / 16, PL = 2 * NT, TP = BM + 8;
-  __shared__ u4 lds[(d16_lds_bytes<BM, BN, NT, EPI>() + 15) / 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, q = lane >> 4;
-  const int t = rank_tile(xcd_tile(blockIdx.x, a.t_dp), a.tiles_m, a.t_dp, a.xgm);
   const int m0 = (t % a.tiles_m) * BM, n0 = (t / a.tiles_m) * BN;
   v4f accR[MB][NB], accI[MB][NB];
 #pragma unroll
@@ -1025,7 +1033,8 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_d16(SplitArgs a) {
           ti[ml * LD + nl] = accI[i][j][r];
         }
     __syncthreads();
-    gather_tile_lds<BM, BN>(a.g, reinterpret_cast<float *>(lds), m0, n0, tid, gp);
+    gather_tile_lds<BM, BN>(a.g, reinterpret_cast<float *>(lds), m0, n0, tid, gp,
+                            prow >= 0 ? prow : n0 / BN);
   } else if constexpr (EPI == EPI_STORE) {
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -1079,6 +1088,29 @@ __global__ __launch_bounds__(kThreads) void cgemm_split_d16(SplitArgs a) {
       *reinterpret_cast<u4 *>(a.pt + (size_t)pl * a.pt_plane +
                               kblk_index(n0 + nl, m0 + 8 * c, a.N)) = v;   // 8 m, one k-block
     }
+  }
+}
+
+template <int BM, int BN, bool BF, int NT, int EPI>
+__global__ __launch_bounds__(kThreads) void cgemm_split_d16(SplitArgs a) {
+  __shared__ u4 lds[(d16_lds_bytes<BM, BN, NT, EPI>() + 15) / 16];
+  const int t = rank_tile(xcd_tile(blockIdx.x, a.t_dp), a.tiles_m, a.t_dp, a.xgm);
+  cgemm_split_d16_unit<BM, BN, BF, NT, EPI>(a, t, -1, lds);
+}
+
+// Work-list launch of the 16x16-block loop (whole K per unit).
+template <int BM, int BN, bool BF, int NT, int EPI>
+__global__ __launch_bounds__(kThreads) void cgemm_split_d16_work(const SplitArgs *items,
+                                                                 const WorkUnit *work,
+                                                                 const int *off, int n) {
+  __shared__ u4 lds[(d16_lds_bytes<BM, BN, NT, EPI>() + 15) / 16];
+  // units off[b] .. off[b + 1] - 1 (persistent), or unit b (off null)
+  const int w0 = off ? off[blockIdx.x] : (int)blockIdx.x;
+  const int w1 = off ? off[blockIdx.x + 1] : w0 + 1;
+  for (int w = w0; w < w1 && w < n; ++w) {
+    if (w != w0) __syncthreads();   // the previous unit's LDS reads are done
+    const WorkUnit u = work[w];
+    cgemm_split_d16_unit<BM, BN, BF, NT, EPI>(items[u.item], u.tile, u.prow, lds);
   }
 }
 
@@ -1255,15 +1287,15 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
 }
 
 
-// ---- batched form -----------------------------------------------------------
+// ---- batched form: work-list launches ----------------------------------------
 
 size_t split_args_bytes() { return sizeof(SplitArgs); }
 
 int fill_split_args(const gswmtp_plan *p, bool forward, const GemmTile &tl, bool honour_done,
-                    void *out) {
+                    unsigned short *pt_out, void *out) {
   SplitArgs a = forward ? split_args(p, true, p->b.ps, nullptr, nullptr, nullptr, honour_done)
                         : split_args(p, false, p->scaled_adj ? p->b.bs : p->b.ss, nullptr,
-                                     nullptr, p->b.ps, honour_done);
+                                     nullptr, pt_out ? pt_out : p->b.ps, honour_done);
   if (!forward && p->scaled_adj) a.a = p->b.as_s;   // the re-associated adjoint
   a.tiles_m = a.M / tl.bm;
   a.t_dp = a.tiles_m * (a.N / tl.bn);
@@ -1276,49 +1308,85 @@ int fill_split_args(const gswmtp_plan *p, bool forward, const GemmTile &tl, bool
 namespace {
 
 template <int BM, int BN, bool BF, int NT, int EPI, int KG, int PIPE>
-hipError_t grouped_t(const GroupedLaunch &g, hipStream_t s) {
+hipError_t work_t(const WorkLaunch &w, hipStream_t s, int *occ) {
   if constexpr (split_lds_bytes<BM, BN, 32, NT, EPI, PIPE>() <= 160 * 1024) {
-    hipLaunchKernelGGL((cgemm_split_grouped<BM, BN, 32, BF, NT, EPI, KG, PIPE>), dim3(g.blocks),
-                       dim3(kThreads * KG), 0, s, static_cast<const SplitArgs *>(g.d_items),
-                       g.d_starts, g.n_items);
+    if (occ)
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          occ, cgemm_split_work<BM, BN, 32, BF, NT, EPI, KG, PIPE>, kThreads * KG, 0);
+    // k-group loops end group 1 early in each unit, so a unit per workgroup
+    // (the loop in the kernel runs once): no barrier after a unit
+    const int grid = KG > 1 ? w.n_work : w.grid;
+    hipLaunchKernelGGL((cgemm_split_work<BM, BN, 32, BF, NT, EPI, KG, PIPE>), dim3(grid),
+                       dim3(kThreads * KG), 0, s, static_cast<const SplitArgs *>(w.d_items),
+                       w.d_work, KG > 1 ? nullptr : w.d_off, w.n_work);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
 }
 
+template <int BM, int BN, bool BF, int NT, int EPI>
+hipError_t work_d16_t(const WorkLaunch &w, hipStream_t s, int *occ) {
+  if (occ)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        occ, cgemm_split_d16_work<BM, BN, BF, NT, EPI>, kThreads, 0);
+  hipLaunchKernelGGL((cgemm_split_d16_work<BM, BN, BF, NT, EPI>), dim3(w.grid), dim3(kThreads), 0,
+                     s, static_cast<const SplitArgs *>(w.d_items), w.d_work, w.d_off, w.n_work);
+  return hipGetLastError();
+}
+
+// occ != null: only report the kernel's resident workgroups per CU
 template <bool BF, int NT, int EPI>
-hipError_t grouped_e(const GroupedLaunch &g, hipStream_t s) {
-  const GemmTile &t = g.tile;
-  if (t.bk != 32 || t.bm != 64) return hipErrorInvalidValue;
+hipError_t work_e(const WorkLaunch &w, hipStream_t s, int *occ) {
+  const GemmTile &t = w.cfg.tile;
   if constexpr (NT == 2) {
-    if (!t.pipe) return hipErrorInvalidValue;
-    if (t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 1, 1>(g, s);
-    if (t.bn == 128)
-      return t.pipe == 2 ? grouped_t<64, 128, BF, NT, EPI, 1, 2>(g, s)
-                         : grouped_t<64, 128, BF, NT, EPI, 1, 1>(g, s);
+    if (t.pipe == 3) {
+      if constexpr (EPI == EPI_PROJECT)
+        if (t.bm == 48 && t.bn == 192) return work_d16_t<48, 192, BF, NT, EPI>(w, s, occ);
+      if constexpr (EPI == EPI_GATHER)
+        if (t.bm == 64 && t.bn == 128) return work_d16_t<64, 128, BF, NT, EPI>(w, s, occ);
+      return hipErrorInvalidValue;
+    }
+    if (t.bk != 32 || t.bm != 64) return hipErrorInvalidValue;
+    if (t.pipe == 1 && t.bn == 64) return work_t<64, 64, BF, NT, EPI, 1, 1>(w, s, occ);
+    if (t.pipe == 1 && t.bn == 128) return work_t<64, 128, BF, NT, EPI, 1, 1>(w, s, occ);
+    if (t.pipe == 2 && t.bn == 128) return work_t<64, 128, BF, NT, EPI, 1, 2>(w, s, occ);
   } else {
-    if (t.kg == 2 && t.bn == 64) return grouped_t<64, 64, BF, NT, EPI, 2, 0>(g, s);
+    if (t.bk == 32 && t.bm == 64 && t.bn == 64 && t.kg == 2)
+      return work_t<64, 64, BF, NT, EPI, 2, 0>(w, s, occ);
   }
   return hipErrorInvalidValue;
 }
 
 template <int EPI>
-hipError_t grouped_p(const GroupedLaunch &g, hipStream_t s) {
-  switch (g.precision) {
-    case GSWMTP_BF16X3: return grouped_e<true, 2, EPI>(g, s);
-    case GSWMTP_FP16X3: return grouped_e<false, 2, EPI>(g, s);
-    case GSWMTP_BF16X6: return grouped_e<true, 3, EPI>(g, s);
+hipError_t work_p(int precision, const WorkLaunch &w, hipStream_t s, int *occ) {
+  switch (precision) {
+    case GSWMTP_BF16X3: return work_e<true, 2, EPI>(w, s, occ);
+    case GSWMTP_FP16X3: return work_e<false, 2, EPI>(w, s, occ);
+    case GSWMTP_BF16X6: return work_e<true, 3, EPI>(w, s, occ);
   }
+  return hipErrorInvalidValue;
+}
+
+hipError_t work_dispatch(const WorkLaunch &w, hipStream_t s, int *occ) {
+  if (w.epi == EPI_GATHER) return work_p<EPI_GATHER>(w.precision, w, s, occ);
+  if (w.epi == EPI_PROJECT) return work_p<EPI_PROJECT>(w.precision, w, s, occ);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_cgemm_split_grouped(const GroupedLaunch &g, hipStream_t s) {
-  if (g.blocks == 0) return hipSuccess;
-  if (g.epi == EPI_GATHER) return grouped_p<EPI_GATHER>(g, s);
-  if (g.epi == EPI_PROJECT) return grouped_p<EPI_PROJECT>(g, s);
-  return hipErrorInvalidValue;
+hipError_t launch_cgemm_split_work(const WorkLaunch &w, hipStream_t s) {
+  if (w.n_work == 0) return hipSuccess;
+  return work_dispatch(w, s, nullptr);
+}
+
+int cgemm_split_work_occupancy(const WorkConfig &c, int epi, int precision) {
+  WorkLaunch w;
+  w.cfg = c;
+  w.epi = epi;
+  w.precision = precision;
+  int n = 0;
+  return work_dispatch(w, nullptr, &n) == hipSuccess ? n : 0;
 }
 
 }  // namespace gswmtp

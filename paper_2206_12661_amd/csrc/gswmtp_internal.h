@@ -270,10 +270,12 @@ __device__ __forceinline__ void gather_pre_foci(const GatherCtx &g, int m0, int 
 //   sum_{n in its BN/4 columns} L[ir][n] Wc[ic][n]
 // for the lane's focus (its Omega_c run read as 16-byte loads, all in
 // flight together), the four waves' sums are added in wave order and the
-// result written as partial number n0 / BN of that focus.
+// result written as partial number prow of that focus (n0 / BN for a whole-K
+// tile; the batched form's K chunks of a forward tile write partial rows of
+// their own, which the focus update adds like the column tiles').
 template <int BM, int BN>
 __device__ __forceinline__ void gather_tile_lds(const GatherCtx &g, float *lds, int m0, int n0,
-                                                int tid, const GatherPre &q) {
+                                                int tid, const GatherPre &q, int prow) {
   constexpr int LD = BN + 1;
   constexpr int CW = BN / 4;   // columns per wave
   typedef float f4 __attribute__((ext_vector_type(4)));
@@ -281,7 +283,7 @@ __device__ __forceinline__ void gather_tile_lds(const GatherCtx &g, float *lds, 
   float *tr = lds, *ti = lds + BM * LD;
   float *red = lds + 2 * BM * LD;   // [4 waves][64 lanes][re, im]
   const int p0 = q.p0, nfoc = q.p1 - q.p0;
-  float *out = g.part + 2 * (size_t)(n0 / BN) * g.ldp;
+  float *out = g.part + 2 * (size_t)prow * g.ldp;
   for (int u0 = 0; u0 < nfoc; u0 += 64) {
     const bool on = u0 + lane < nfoc;
     int f = q.f, a = q.a, c = q.c;
@@ -337,7 +339,7 @@ __device__ __forceinline__ void gather_epilogue(
     const GatherCtx &g,
     const gsw_v16f (&accR)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
     const gsw_v16f (&accI)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
-    float *lds, int m0, int n0, int tid, GatherPre q) {
+    float *lds, int m0, int n0, int tid, GatherPre q, int prow = -1) {
   using L = WaveLayout<BM, BN, COLS>;
   constexpr int MB = L::MB, NB = L::NB, WTM = L::WTM, WTN = L::WTN, LD = BN + 1;
   const int lane = tid & 63, wave = tid >> 6;
@@ -360,7 +362,7 @@ __device__ __forceinline__ void gather_epilogue(
         ti[ml * LD + nl] = accI[i][j][r];
       }
   __syncthreads();
-  gather_tile_lds<BM, BN>(g, lds, m0, n0, tid, q);
+  gather_tile_lds<BM, BN>(g, lds, m0, n0, tid, q, prow >= 0 ? prow : n0 / BN);
 }
 
 // The same without indices read ahead (they are read at the epilogue).
@@ -369,8 +371,8 @@ __device__ __forceinline__ void gather_epilogue(
     const GatherCtx &g,
     const gsw_v16f (&accR)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
     const gsw_v16f (&accI)[WaveLayout<BM, BN, COLS>::MB][WaveLayout<BM, BN, COLS>::NB],
-    float *lds, int m0, int n0, int tid) {
-  gather_epilogue<BM, BN, COLS>(g, accR, accI, lds, m0, n0, tid, GatherPre{});
+    float *lds, int m0, int n0, int tid, int prow = -1) {
+  gather_epilogue<BM, BN, COLS>(g, accR, accI, lds, m0, n0, tid, GatherPre{}, prow);
 }
 
 template <int BM, int BN>
@@ -453,25 +455,52 @@ int gather_ld(const gswmtp_plan *p);   // gather partial row stride: nf rounded 
 GemmSched make_sched(int M, int N, int K, GemmTile tile, int cus, bool allow_split,
                      int min_chunk_div = 0);
 
-// Grouped launches over the plans of a batch (float32 products).
-struct GroupedLaunch {
-  int bm = 64, bn = 64, epi = 0;
-  GemmTile tile;             // split products: the full tile (BK, k-groups, loop)
-  int precision = 0;         // split products: the plans' common precision
-  int n_items = 0, blocks = 0;
-  void *d_items = nullptr;   // per-plan kernel arguments
-  int *d_starts = nullptr;   // [n_items + 1] first block of each item
+// One unit of a batched product's device work list: tile `tile` of item
+// `item` (a plan's product arguments), K stages [kb, ke), its focus-gather
+// partials (forward) written to partial row `prow`.
+struct WorkUnit {
+  int item, tile, kb, ke, prow, pad0, pad1, pad2;
 };
+// Kernel configuration of a batched product: tile, loop (GemmTile::pipe;
+// k-groups for the three-term split) and the forward's K chunks per tile.
+struct WorkConfig {
+  GemmTile tile;
+  int split = 1;
+  bool operator==(const WorkConfig &o) const {
+    return tile.bm == o.tile.bm && tile.bn == o.tile.bn && tile.bk == o.tile.bk &&
+           tile.kg == o.tile.kg && tile.pipe == o.tile.pipe && split == o.split;
+  }
+};
+// Persistent (or one-unit-per-workgroup) launch over a work list of one
+// configuration: workgroup b runs units d_off[b] .. d_off[b + 1] - 1, or
+// unit b when d_off is null (grid = n_work).  Configurations with two
+// k-groups always run one unit per workgroup.
+struct WorkLaunch {
+  WorkConfig cfg;
+  int epi = 0, precision = 0;
+  const void *d_items = nullptr;   // per-plan product arguments (CgemmArgs / SplitArgs)
+  const WorkUnit *d_work = nullptr;
+  const int *d_off = nullptr;      // [grid + 1] unit ranges per workgroup, or null
+  int n_work = 0, grid = 0;
+};
+hipError_t launch_cgemm_work(const WorkLaunch &w, hipStream_t s);
+hipError_t launch_cgemm_split_work(const WorkLaunch &w, hipStream_t s);
+// Resident workgroups per CU of a configuration's work-list kernel (0: the
+// configuration has no such kernel).
+int cgemm_work_occupancy(const WorkConfig &c, int epi);
+int cgemm_split_work_occupancy(const WorkConfig &c, int epi, int precision);
+
+// Per-plan product arguments of the batched form for a work-list launch with
+// tile (bm, bn) / `tl`: size of one item, and the tile count it fills in.
+// honour_done: return at once when the plan's done flag is set.  cr / ci
+// (float32 adjoint) and pt_out (split adjoint), nullable: write the
+// projected field there instead of the plan's pupil field (tuning runs).
 size_t cgemm_args_bytes();
 int fill_cgemm_args(const gswmtp_plan *p, bool forward, int bm, int bn, bool honour_done,
                     float *cr, float *ci, void *out);
-hipError_t launch_cgemm_grouped(const GroupedLaunch &g, hipStream_t s);
-// Split-precision products of the batched form: one plan's whole-tile
-// schedule of tile `tl` (no K split) as an item; the grouped launch.
 size_t split_args_bytes();
 int fill_split_args(const gswmtp_plan *p, bool forward, const GemmTile &tl, bool honour_done,
-                    void *out);
-hipError_t launch_cgemm_split_grouped(const GroupedLaunch &g, hipStream_t s);
+                    unsigned short *pt_out, void *out);
 // Split-precision scatter of the batched form.
 size_t scatter_split_args_bytes();
 int fill_scatter_split_args(const gswmtp_plan *p, void *out);
@@ -495,7 +524,8 @@ struct GroupedUpdate {
 };
 size_t update_args_bytes();
 // Returns the plan's many-focus workgroup count (0: register form, one block).
-int fill_update_args(const gswmtp_plan *p, int mode, int gather_bn, void *out);
+// partials: gather partials per focus of the batch's forward product
+int fill_update_args(const gswmtp_plan *p, int mode, int partials, void *out);
 hipError_t launch_update_grouped(const GroupedUpdate &g, hipStream_t s);
 size_t scatter_args_bytes();
 int fill_scatter_args(const gswmtp_plan *p, void *out);

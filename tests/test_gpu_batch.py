@@ -224,13 +224,15 @@ def test_batch_rejects(g):
 @pytest.mark.parametrize("form", ["own", "scatter"])
 @pytest.mark.parametrize("mode", ["bf16x3", "fp16x3", "bf16x6"])
 def test_split_batch_bit_exact_vs_single(g, monkeypatch, mode, form):
-    """Split-precision plans batched: the single-plan product loops on the
-    same tiles with no K split (GSWMTP_NO_SPLITK=1), and every plan keeps its
+    """Split-precision plans batched with each plan's own configuration
+    (GSWMTP_BATCH_TILE=plan): the single-plan product loops on the same tiles
+    with no K split (GSWMTP_NO_SPLITK=1), and every plan keeps its
     adjoint form in the batch (re-associated where each reduced row holds one
     focus, the random cases here; scatter for the grid cases; scatter for
     all under GSWMTP_ADJOINT=scatter), so every plan's result equals its
     single-plan result bit for bit."""
     monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
+    monkeypatch.setenv("GSWMTP_BATCH_TILE", "plan")
     if form == "scatter":
         monkeypatch.setenv("GSWMTP_ADJOINT", "scatter")
     hs = _ragged_set()
@@ -281,3 +283,133 @@ def test_split_batch_graph_equals_eager_and_full_size(g, monkeypatch):
     err = rel_l2(states[0][0][3], ref)
     print(f"  full-size plan, batch vs single: {err:.2e}")
     assert err <= 5e-5
+
+
+def _identical_start(g, hs, passes=3):
+    """float32 states after a few passes (a well-conditioned common start)."""
+    out = []
+    for h in hs:
+        with g.Plan(h) as p:
+            p.iterate(passes)
+            out.append(p.state()[:2])
+    return out
+
+
+@pytest.mark.parametrize("mode", ["bf16x3", "fp16x3"])
+def test_batch_plan_configs_bit_exact_with_16x16_loops(g, monkeypatch, mode):
+    """A batch holding a 1152 x 1920 plan (forward on the 16x16-block loop,
+    adjoint forced onto it) beside small plans (pipelined 64 x 64 loop), each
+    class on its plans' own configuration: two configurations per product run
+    as parallel branches of the graph, and every plan equals its single-plan
+    run bit for bit."""
+    monkeypatch.setenv("GSWMTP_NO_SPLITK", "1")
+    monkeypatch.setenv("GSWMTP_BATCH_TILE", "plan")
+    monkeypatch.setenv("GSWMTP_ADJ_LOOP", "d16")
+    hs = [synth_ofa.config3()] + _ragged_set()[:3]
+    announce(f"{mode} batch with 16x16-block loops, plan configurations")
+    single = []
+    for h in hs:
+        with g.Plan(h, precision=mode) as p:
+            p.iterate(4)
+            single.append(_state(p))
+    plans = [g.Plan(h, precision=mode) for h in hs]
+    assert plans[0].stage_kernel(0) == "cgemm_split_d16"
+    assert plans[0].stage_kernel(3) == "cgemm_split_d16"
+    with g.Batch(plans) as b:
+        cls = b.classes()
+        configs = {(c["product"], c["config"]) for c in cls}
+        print("  configurations:", sorted(configs))
+        assert ("forward", "64x128/b16/k1") in configs and ("adjoint", "48x192/b16/k1") in configs
+        assert all(c["source"] == "plan" for c in cls)
+        b.iterate(4)
+        b.sync()
+    for k, p in enumerate(plans):
+        _assert_same(_state(p), single[k])
+        p.close()
+
+
+def test_batch_persistent_equals_one_unit_per_workgroup(g, monkeypatch):
+    """The persistent work-list launch and one workgroup per unit run the same
+    units: bit-identical results (float32 and BF16x3)."""
+    hs = _ragged_set()[:5]
+    for mode in ("fp32", "bf16x3"):
+        outs = []
+        for pe in ("1", "0"):
+            monkeypatch.setenv("GSWMTP_BATCH_PERSIST", pe)
+            monkeypatch.setenv("GSWMTP_BATCH_NO_TUNE", "1")
+            announce(f"batch {mode} persistent={pe}")
+            plans = [g.Plan(h, precision=mode) for h in hs]
+            with g.Batch(plans) as b:
+                b.iterate(5)
+                b.sync()
+            outs.append([_state(p) for p in plans])
+            for p in plans:
+                p.close()
+        for a, c in zip(outs[0], outs[1]):
+            _assert_same(a, c)
+
+
+@pytest.mark.parametrize("mode,bar", [("fp32", 1e-5), ("bf16x3", 5e-5)])
+def test_batch_forward_k_chunks_against_oracle(g, monkeypatch, mode, bar):
+    """Forward tiles split in two K chunks (GSWMTP_BATCH_FWD_SPLIT=2 on
+    64 x 128 tiles): each chunk gathers its partial product into partial rows
+    of its own, which the focus update adds with the column tiles'.  One pass
+    from a well-conditioned state against the oracle at the mode's bar."""
+    monkeypatch.setenv("GSWMTP_BATCH_TILE", "64x128")
+    monkeypatch.setenv("GSWMTP_BATCH_FWD_SPLIT", "2")
+    hs = _ragged_set()[:6]
+    starts = _identical_start(g, hs)
+    announce(f"batch forward K chunks {mode}")
+    plans = []
+    for h, (phi, w) in zip(hs, starts):
+        p = g.Plan(h, precision=mode)
+        p.set_state(phi, w, 0)
+        plans.append(p)
+    with g.Batch(plans) as b:
+        split_cls = [c for c in b.classes() if c["product"] == "forward"
+                     and c["config"].endswith("/k2")]
+        print("  forward classes with K chunks:", [c["mnk"] for c in split_cls])
+        assert split_cls
+        b.iterate(1)
+    for h, p, (phi, w) in zip(hs, plans, starts):
+        hk = synth_ofa.Hologram(h.name, h.ny, h.nx, h.amplitude, h.u, h.v, h.s_x, h.s_y,
+                                h.fx, h.fy, h.target, phi, 1)
+        r = oracle.gsw(hk, n_iter=1, w=w)
+        ew, et = rel_l2(p.weights(), r["w"]), rel_l2(p.foci_field(), r["theta"])
+        print(f"  {h.name}: w {ew:.2e} theta {et:.2e}")
+        assert ew <= bar and et <= bar
+        p.close()
+
+
+def test_batch_tuning_cache(g, monkeypatch, tmp_path):
+    """Per-class tuning writes the JSON cache GSWMTP_TUNE_CACHE names; a
+    second batch of the same shapes takes every choice from it, and both
+    batches give the same results bit for bit."""
+    import json
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("GSWMTP_TUNE_CACHE", str(cache))
+    hs = _ragged_set()[:4]
+    runs = []
+    for k in range(2):
+        announce(f"batch tuning cache run {k}")
+        plans = [g.Plan(h, precision="bf16x3") for h in hs]
+        with g.Batch(plans) as b:
+            cls = b.classes()
+            b.iterate(3)
+            b.sync()
+        runs.append((cls, [_state(p) for p in plans]))
+        for p in plans:
+            p.close()
+    entries = json.loads(cache.read_text())
+    tuned = [c for c in runs[0][0] if c["source"] == "tuned"]
+    print(f"  {len(entries)} cache entries; first run tuned {len(tuned)} of {len(runs[0][0])} "
+          f"classes")
+    assert tuned and len(entries) >= len(tuned)
+    for c in tuned:
+        assert len(c["tried"]) >= 2 and c["ms"] > 0
+    for c0, c1 in zip(runs[0][0], runs[1][0]):
+        assert c1["config"] == c0["config"]
+        if c0["source"] == "tuned":
+            assert c1["source"] == "cache"
+    for a, c in zip(runs[0][1], runs[1][1]):
+        _assert_same(a, c)
