@@ -43,6 +43,8 @@ def _load():
         _b.build()
     lib = ctypes.CDLL(LIB_PATH)
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = None
     lib.oracle_forward.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, _D, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]
     lib.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double,
@@ -91,6 +93,11 @@ def _fz(holo):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (results do not depend on it)."""
+    _load().oracle_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------

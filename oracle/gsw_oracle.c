@@ -142,6 +142,16 @@ static void adjoint_t(const tables *t, const double *theta, double *E)
     }
 }
 
+/* Threads of the OpenMP loops (n >= 1); results do not depend on it. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_num_threads(void)
 {
 #ifdef _OPENMP
