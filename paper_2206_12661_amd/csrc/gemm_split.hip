@@ -1287,6 +1287,83 @@ hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
 }
 
 
+// A split product with explicit operands, both stored as 16-bit term planes
+// of [rows][K] matrices, k-blocked: C[M][N] = sum_k A[m][k] B[n][k] into
+// float32 planes cr / ci [M][ldc], on schedule sc (the grid form's first
+// product, L^T = P^T Omega_r^T).
+hipError_t launch_cgemm_split_ex(const gswmtp_plan *p, const GemmSched &sc,
+                                 const unsigned short *a, int M, const unsigned short *b, int N,
+                                 int K, float *cr, float *ci, int ldc, bool honour_done,
+                                 hipStream_t s) {
+  const int nt = split_terms_of(p->precision);
+  if (nt < 2 || sc.tile.pipe == 3 || M % sc.tile.bm || N % sc.tile.bn || K % sc.tile.bk ||
+      sc.tiles_m * sc.tile.bm != M || sc.tiles * sc.tile.bm * sc.tile.bn != M * N)
+    return hipErrorInvalidValue;
+  SplitArgs x{};
+  x.a = a;
+  x.M = M;
+  x.K = K;
+  x.a_plane = (size_t)M * K;
+  x.b = b;
+  x.N = N;
+  x.b_plane = (size_t)N * K;
+  x.cr = cr;
+  x.ci = ci;
+  x.ldc = ldc;
+  x.done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+  x.part = p->b.part;
+  x.tiles_m = sc.tiles_m;
+  x.t_dp = sc.t_dp;
+  x.split = sc.split;
+  x.xgm = sc.xgm;
+  for (int phase = 0; phase < (sc.n_tail > 0 ? 2 : 1); ++phase) {
+    x.phase = phase;
+    const hipError_t e =
+        launch_p<EPI_STORE>(p->precision, sc.tile, x, phase == 0 ? sc.grid : sc.n_tail, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+namespace {
+
+// Float32 planes S [Urp][ldc] as the split planes of S^T ([2][NT] x [Cp][Urp],
+// k-blocked), times an exact power-of-two scale: one (c, u) per thread, u
+// fastest so every store run is contiguous.
+template <bool BF, int NT>
+__global__ void k_split_transpose(const float *__restrict__ sr, const float *__restrict__ si,
+                                  int Urp, int Cp, int ldc, float scale,
+                                  unsigned short *__restrict__ st, const int *done) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)Urp * Cp) return;
+  const int u = (int)(id % Urp), c = (int)(id / Urp);
+  const float re = sr[(size_t)u * ldc + c] * scale, im = si[(size_t)u * ldc + c] * scale;
+  if (done && *done) return;
+  const size_t plane = (size_t)Cp * Urp, at = kblk_index(c, u, Cp);
+  split_terms<BF, NT>(re, st + at, (int)plane);
+  split_terms<BF, NT>(im, st + (size_t)NT * plane + at, (int)plane);
+}
+
+}  // namespace
+
+hipError_t launch_split_transpose(const gswmtp_plan *p, const float *sr, const float *si,
+                                  float scale, bool honour_done, hipStream_t s) {
+  const Dims &d = p->d;
+  const dim3 grid((unsigned)(((size_t)d.Urp * d.Cp + 255) / 256));
+  const int *done = honour_done ? p->b.ctrl + CTRL_DONE : nullptr;
+#define SPLIT_T(BF, NT)                                                                       \
+  hipLaunchKernelGGL((k_split_transpose<BF, NT>), grid, dim3(256), 0, s, sr, si, d.Urp, d.Cp, \
+                     d.Cp, scale, p->b.ss, done)
+  switch (p->precision) {
+    case GSWMTP_BF16X3: SPLIT_T(true, 2); break;
+    case GSWMTP_FP16X3: SPLIT_T(false, 2); break;
+    case GSWMTP_BF16X6: SPLIT_T(true, 3); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SPLIT_T
+  return hipGetLastError();
+}
+
 // ---- batched form: work-list launches ----------------------------------------
 
 size_t split_args_bytes() { return sizeof(SplitArgs); }

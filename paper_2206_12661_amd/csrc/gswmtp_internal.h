@@ -442,6 +442,17 @@ hipError_t launch_cgemm_ex(const gswmtp_plan *p, const GemmSched &sc, const floa
                            const float *ati, int lda, const float *br, const float *bi, int ldb,
                            float *cr, float *ci, int ldc, int M, int N, int K, int epi,
                            bool honour_done, hipStream_t s);
+// A split product with explicit operands (16-bit term planes of [rows][K]
+// matrices, k-blocked): C[M][N] = sum_k A[m][k] B[n][k] into float32 planes
+// [M][ldc] on schedule sc.
+hipError_t launch_cgemm_split_ex(const gswmtp_plan *p, const GemmSched &sc,
+                                 const unsigned short *a, int M, const unsigned short *b, int N,
+                                 int K, float *cr, float *ci, int ldc, bool honour_done,
+                                 hipStream_t s);
+// Split grid form: float32 S [Urp][Cp] (times scale) as the split planes of
+// S^T in the plan's scatter buffer.
+hipError_t launch_split_transpose(const gswmtp_plan *p, const float *sr, const float *si,
+                                  float scale, bool honour_done, hipStream_t s);
 // Grid form: Theta_n = G[ir_n][ic_n] into the gather partials (one per focus);
 // Theta'_n onto the transposed grid at (ic_n, ir_n).
 hipError_t launch_grid_gather(const gswmtp_plan *p, hipStream_t s);

@@ -811,6 +811,21 @@ bool is_split(const gswmtp_plan *p) { return split_terms_of(p->precision) > 0; }
 // foci, in the first product's epilogue) or the grid form (L^T = P^T
 // Omega_r^T, then G = L Omega_c^T on the matrix cores, then Theta_n = G at
 // the focus).
+// Split grid form, forward: L^T = P^T Omega_r^T on the 16-bit matrix cores
+// (pt: the split planes of P^T), then the float32 grid product and gather.
+hipError_t split_grid_forward(gswmtp_plan *p, const unsigned short *pt, bool done,
+                              hipStream_t s) {
+  const Dims &D = p->d;
+  Bufs &b = p->b;
+  hipError_t e = launch_cgemm_split_ex(p, p->sched_f1, pt, D.Cp, b.as_f, D.Urp, D.Rp, b.lt_r,
+                                       b.lt_i, D.Urp, done, s);
+  if (e != hipSuccess) return e;
+  e = launch_cgemm_ex(p, p->sched_f2, b.lt_r, b.lt_i, D.Urp, b.wt_r, b.wt_i, D.Ucp, b.g_r, b.g_i,
+                      D.Ucp, D.Urp, D.Ucp, D.Cp, EPI_STORE, done, s);
+  if (e != hipSuccess) return e;
+  return launch_grid_gather(p, s);
+}
+
 hipError_t forward_products(gswmtp_plan *p, const float *er, const float *ei, bool done,
                             hipStream_t s) {
   if (!p->grid_form)
@@ -829,23 +844,35 @@ hipError_t forward_products(gswmtp_plan *p, const float *er, const float *ei, bo
 // Float32 scatter of focal values theta (device, interleaved) into S: per
 // row of foci (gather form) or as the product Theta'_grid conj(Omega_c)
 // (grid form).
-hipError_t scatter_products(gswmtp_plan *p, const float *theta, bool done, hipStream_t s) {
+hipError_t scatter_products(gswmtp_plan *p, const float *theta, bool done, hipStream_t s,
+                            float scale = 1.f) {
   if (!p->grid_form) return launch_scatter(p, theta, done, s);
   const Dims &D = p->d;
   Bufs &b = p->b;
-  hipError_t e = launch_grid_scatter(p, theta, 1.f, s);
+  hipError_t e = launch_grid_scatter(p, theta, scale, s);
   if (e != hipSuccess) return e;
   return launch_cgemm_ex(p, p->sched_a1, b.tg_r, b.tg_i, D.Urp, b.wc_r, b.wn_i, D.Cp, b.s_r,
                          b.s_i, D.Cp, D.Urp, D.Cp, D.Ucp, EPI_STORE, done, s);
 }
 
+// Split grid form, scatter: the float32 grid scatter product into S, then S
+// as the split planes of S^T for the adjoint product.
+hipError_t split_grid_scatter(gswmtp_plan *p, const float *theta, float scale, bool done,
+                              hipStream_t s) {
+  hipError_t e = scatter_products(p, theta, done, s, scale);
+  if (e != hipSuccess) return e;
+  return launch_split_transpose(p, p->b.s_r, p->b.s_i, 1.f, done, s);
+}
+
 hipError_t stage_forward(gswmtp_plan *p, bool done, hipStream_t s) {
+  if (is_split(p) && p->grid_form) return split_grid_forward(p, p->b.ps, done, s);
   if (is_split(p))
     return launch_cgemm_split(p, true, EPI_GATHER, p->b.ps, nullptr, nullptr, nullptr, done, s);
   return forward_products(p, p->b.p_r, p->b.p_i, done, s);
 }
 hipError_t stage_scatter(gswmtp_plan *p, bool done, hipStream_t s) {
   if (p->scaled_adj) return launch_scale_adjoint_split(p, done, s);
+  if (is_split(p) && p->grid_form) return split_grid_scatter(p, p->b.theta_new, 1.f, done, s);
   if (is_split(p)) return launch_scatter_split(p, p->b.theta_new, 1.f, done, s);
   return scatter_products(p, p->b.theta_new, done, s);
 }
@@ -1038,10 +1065,10 @@ void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
   // foci), the second product of Eq. 2 is formed densely on the matrix cores
   // (as the paper does) instead of per focus.  GSWMTP_SECOND=gather|grid
   // forces either form.
-  p->grid_form = !split_mode && (double)D.Ur * D.Uc <= 4.0 * D.nf && D.nf >= 384;
+  p->grid_form = (double)D.Ur * D.Uc <= 4.0 * D.nf && D.nf >= 384;
   if (const char *sf = std::getenv("GSWMTP_SECOND")) {
     if (std::strcmp(sf, "gather") == 0) p->grid_form = false;
-    if (std::strcmp(sf, "grid") == 0 && !split_mode) p->grid_form = true;
+    if (std::strcmp(sf, "grid") == 0) p->grid_form = true;
   }
   D.Ucp = (int)round_up(D.Uc, kPadCols);
   // Split modes with one focus in every reduced row (N = U_r, e.g. random
@@ -1053,8 +1080,12 @@ void derive_layout(gswmtp_plan *p, const gswmtp_desc *d) {
   if (const char *sa = std::getenv("GSWMTP_ADJOINT"))
     if (std::strcmp(sa, "scatter") == 0) p->scaled_adj = false;
   if (p->grid_form) {
-    p->sched_f1 = make_sched(D.Cp, D.Urp, D.Rp, choose_tile(D.Cp, D.Urp, false), p->cus,
-                             split_enabled());
+    // the first product L^T = P^T Omega_r^T in the plan's precision; the grid
+    // product and the grid scatter's product in float32 (small: U_r x U_c)
+    p->sched_f1 = make_sched(D.Cp, D.Urp, D.Rp,
+                             choose_tile(D.Cp, D.Urp, split_mode, terms, p->cus), p->cus,
+                             split_enabled(), chunk_div);
+    if (p->sched_f1.tile.pipe == 2) p->sched_f1.tile.pipe = 1;   // the pipelined loop
     p->sched_f2 = make_sched(D.Urp, D.Ucp, D.Cp, choose_tile(D.Urp, D.Ucp, false), p->cus,
                              split_enabled());
     p->sched_a1 = make_sched(D.Urp, D.Cp, D.Ucp, choose_tile(D.Urp, D.Cp, false), p->cus,
@@ -1089,7 +1120,8 @@ void carve_pool1(Carver &c, Bufs &b, const gswmtp_plan *p) {
   // gather partials: one per forward column tile and focus, sized for the
   // narrowest tile (64 columns) so that a batch may run any tile width
   b.gpart = c.take<float>(2 * (size_t)(Cp / 64) * ((nf + 1) & ~(size_t)1));
-  b.s_r = c.take<float>(f32 * Urp * Cp); b.s_i = c.take<float>(f32 * Urp * Cp);
+  const size_t fs = f32 || p->grid_form ? 1 : 0;   // float32 S (split grid form too)
+  b.s_r = c.take<float>(fs * Urp * Cp); b.s_i = c.take<float>(fs * Urp * Cp);
   b.x_r = c.take<float>(Rp * Cp); b.x_i = c.take<float>(Rp * Cp);
   b.part = c.take<float>(part_floats);
   b.as_f = c.take<unsigned short>(2 * nt * Urp * Rp);
@@ -1825,8 +1857,11 @@ static int forward_field_impl(gswmtp_plan *p, const float *E, float *theta) {
     DISPATCH_SPLIT(p->precision, COMPACT)
 #undef COMPACT
     HIP_TRY(p, hipGetLastError());
-    HIP_TRY(p, launch_cgemm_split(p, true, EPI_GATHER, p->b.xs, nullptr, nullptr, nullptr, false,
-                                  s));
+    if (p->grid_form)
+      HIP_TRY(p, split_grid_forward(p, p->b.xs, false, s));
+    else
+      HIP_TRY(p, launch_cgemm_split(p, true, EPI_GATHER, p->b.xs, nullptr, nullptr, nullptr,
+                                    false, s));
   } else {
     hipLaunchKernelGGL(k_compact_complex, gr, dim3(256), 0, s, o, p->b.iobuf, D.nx, D.Rp, D.Cp,
                        p->b.x_r, p->b.x_i);
@@ -1855,7 +1890,10 @@ int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E) {
       amax = std::max(amax, (double)std::fabs(theta[i]));
     const int e = p->precision == GSWMTP_FP16X3 ? scale_exponent(amax) : 0;
     unscale = std::ldexp(1.f, -e);
-    HIP_TRY(p, launch_scatter_split(p, p->b.theta_new, std::ldexp(1.f, e), false, s));
+    if (p->grid_form)
+      HIP_TRY(p, split_grid_scatter(p, p->b.theta_new, std::ldexp(1.f, e), false, s));
+    else
+      HIP_TRY(p, launch_scatter_split(p, p->b.theta_new, std::ldexp(1.f, e), false, s));
     HIP_TRY(p, launch_cgemm_split(p, false, EPI_STORE, p->b.ss, p->b.x_r, p->b.x_i, nullptr,
                                   false, s));
   } else {
