@@ -67,6 +67,9 @@ def parse():
                     help="timed repeats of --steps passes (the median is reported)")
     ap.add_argument("--sweep-cases", default="9,51,227",
                     help="k of the k x k foci arrays of the sweep leg ('' skips it)")
+    ap.add_argument("--legs", default="headline,small,batch,adam,sweep",
+                    help="legs to run; without 'headline' the line carries only the "
+                         "named legs' results (for profiling one leg alone)")
     return ap.parse_args()
 
 
@@ -377,25 +380,38 @@ def run_sweep(g, torch, args):
 def run_adam(g, torch, args):
     """The differentiable form: phase design of a 50 x 50 grid on the
     1152 x 1920 pupil by Adam (lr 0.05) through the forward product and the
-    adjoint-gradient epilogue; steps per second over the whole run."""
+    adjoint-gradient epilogue; steps per second over the whole run, with each
+    step replayed from one captured graph (the eager loop, which launches every
+    step from the host, is timed beside it over a quarter of the steps)."""
     import synth_ofa
     h = synth_ofa.config5()
+    n = args.adam_steps
     with g.Plan(h) as p:
         g.adam_design(p, 5, phi0=h.phi0, target=h.target)      # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        phi, hist = g.adam_design(p, args.adam_steps, phi0=h.phi0, target=h.target)
+        phi, hist = g.adam_design(p, n, phi0=h.phi0, target=h.target)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        n_e = max(1, n // 4)
+        g.adam_design(p, 2, phi0=h.phi0, target=h.target, graph=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.adam_design(p, n_e, phi0=h.phi0, target=h.target, graph=False)
+        torch.cuda.synchronize()
+        dt_e = time.perf_counter() - t0
         p.set_phase(phi)
         st = p.stats()
         idx = p.index()
     hist = hist.cpu().numpy()
     fl = algorithmic_flops(idx, len(h.fx))
     step_flops = fl["forward_product"] + fl["adjoint_product_project"] + fl["scatter"]
-    return {"workload": "gsw-adam-1152x1920-50x50grid", "steps": args.adam_steps,
-            "steps_s": round(args.adam_steps / dt, 2),
-            "ms_per_step": round(1e3 * dt / args.adam_steps, 4),
+    return {"workload": "gsw-adam-1152x1920-50x50grid", "steps": n,
+            "steps_s": round(n / dt, 2),
+            "ms_per_step": round(1e3 * dt / n, 4),
+            "form": "one captured graph per step, replayed",
+            "eager_steps": n_e, "eager_steps_s": round(n_e / dt_e, 2),
+            "eager_ms_per_step": round(1e3 * dt_e / n_e, 4),
             "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
             "uniformity": round(st["uniformity"], 5), "efficiency": round(st["eta"], 5),
             "flops_per_step": step_flops}
@@ -422,6 +438,19 @@ def main():
 
     h = synth_ofa.config3()
     torch.cuda.init()
+    legs = {x.strip() for x in args.legs.split(",") if x.strip()}
+    if "headline" not in legs:
+        part = {}
+        if "small" in legs and args.small_steps > 0:
+            part["small_configs"] = run_small(g, torch, args, ("fp32", "bf16x3"))
+        if "batch" in legs and args.batch_steps > 0:
+            part["batch"] = run_batch(g, torch, args)
+        if "adam" in legs and args.adam_steps > 0:
+            part["differentiable"] = run_adam(g, torch, args)
+        if "sweep" in legs and args.sweep_cases.strip():
+            part["sweep"] = run_sweep(g, torch, args)
+        print(json.dumps({"legs": sorted(legs), **part}), flush=True)
+        return
     modes = [m.strip() for m in args.modes.split(",") if m.strip()]
     res = {m: run_mode(g, torch, h, m, args) for m in modes}
 
@@ -460,10 +489,12 @@ def main():
             head = max(ok, key=lambda m: res[m]["value"])
     hr = res[head]
     libref = library_reference(torch, hr["index"]) if not args.no_library_reference else None
-    small = run_small(g, torch, args, ("fp32", head)) if args.small_steps > 0 else None
-    batch = run_batch(g, torch, args) if args.batch_steps > 0 else None
-    adam = run_adam(g, torch, args) if args.adam_steps > 0 else None
-    sweep = run_sweep(g, torch, args) if (args.sweep or args.sweep_cases.strip()) else None
+    small = (run_small(g, torch, args, ("fp32", head))
+             if args.small_steps > 0 and "small" in legs else None)
+    batch = run_batch(g, torch, args) if args.batch_steps > 0 and "batch" in legs else None
+    adam = run_adam(g, torch, args) if args.adam_steps > 0 and "adam" in legs else None
+    sweep = (run_sweep(g, torch, args)
+             if (args.sweep or args.sweep_cases.strip()) and "sweep" in legs else None)
     out = {
         "metric": METRIC,
         "value": round(hr["value"], 3), "unit": "iter/s", "n_gpus": 1, "steps": args.steps,

@@ -129,7 +129,8 @@ int gswmtp_version(void);
 /* Human-readable name of a status code (static string, never NULL). */
 const char *gswmtp_status_string(int status);
 
-/* Message of the last failed call on plan p (static "" if none or p == NULL). */
+/* Message of the last failed call on plan p (static "" if none); with
+ * p == NULL, the message of the calling thread's last failed plan creation. */
 const char *gswmtp_last_error(const gswmtp_plan *p);
 
 /* Fill d with defaults: all pointers NULL, s_x = s_y = 0 (must be set),
@@ -144,7 +145,16 @@ int gswmtp_desc_init(gswmtp_desc *d);
  * -0.0 and +0.0 are one coordinate), axis choice (fewer unique coordinates,
  * ties to y), kernel matrices (phase reduced in float64), E0 = A exp(i phi0).
  * Synchronises once to size the product buffers.  stream: hipStream_t or NULL.
- * On failure *out is NULL and nothing is leaked. */
+ * On failure *out is NULL and nothing is leaked; gswmtp_last_error(NULL)
+ * holds the message.
+ * Testing the failure paths: with the environment variable
+ * GSWMTP_FAULT_INJECT=alloc (read at each call) every device allocation of
+ * the call fails - it returns GSWMTP_E_NOMEM after validating d, before any
+ * device work; with GSWMTP_FAULT_INJECT=alloc:K only the K-th allocation
+ * fails (the plan makes two: index pool, product pool), and what was built
+ * is released.  The same applies to gswmtp_batch_create (its allocations:
+ * the tuner's scratch, then its pool); gswmtp_plan_create_with_workspace
+ * allocates nothing and ignores it. */
 int gswmtp_plan_create(gswmtp_plan **out, const gswmtp_desc *d, void *stream);
 
 /* Device memory a plan for d needs (both of its pools), in bytes, computed on
@@ -205,33 +215,56 @@ int gswmtp_iterate_measured(gswmtp_plan *p, const double *measured);
  * (synchronises). */
 int gswmtp_iterations_done(gswmtp_plan *p, int *n);
 
-/* Current phase phi, (-pi, pi], 0 outside the aperture: host [ny*nx]. */
+/* Current phase phi - the hologram Algorithm 1 outputs, the argument of the
+ * pupil field after the phase-only projection of its last pass - in
+ * (-pi, pi], 0 outside the aperture: host [ny*nx], row-major.  Synchronises. */
 int gswmtp_get_phase(gswmtp_plan *p, float *out);
 /* Same into device memory [ny*nx] (stream-ordered, no host sync). */
 int gswmtp_get_phase_device(gswmtp_plan *p, float *dev_out);
 
-/* Replace the current phase (host / device [ny*nx], finite): E = A exp(i phi).
- * Weights and the iteration count are kept. */
+/* Replace the current phase (host / device [ny*nx], finite, row-major): the
+ * pupil field becomes E = A exp(i phi), the input of Algorithm 1's forward
+ * step.  Weights and the iteration count are kept.  GSWMTP_E_INVAL for a
+ * non-finite host phase (the device form is not scanned). */
 int gswmtp_set_phase(gswmtp_plan *p, const float *phi);
 int gswmtp_set_phase_device(gswmtp_plan *p, const float *dev_phi);
 
-/* Focal field Theta of the CURRENT phase at every focus (caller order),
- * interleaved complex [2*n_foci] on the host.  Runs a forward pass when the
- * phase changed since the last one. */
+/* Focal field Theta of the CURRENT phase at every focus (caller order): the
+ * forward matrix triple product of Eq. 2 evaluated at the foci, as in the
+ * first step of each pass of Algorithm 1.  Interleaved complex [2*n_foci]
+ * (re, im) on the host.  Runs the forward product when the phase changed
+ * since the last one.  Synchronises. */
 int gswmtp_get_foci_field(gswmtp_plan *p, float *out);
-/* Same into device memory; dev_intensity (nullable) receives |Theta|^2 [n_foci]. */
+/* Same into device memory, stream-ordered, no host sync: dev_field [2*n_foci]
+ * receives Theta, dev_intensity [n_foci] the intensities I = |Theta|^2 of
+ * Algorithm 1; either may be NULL, not both (GSWMTP_E_INVAL). */
 int gswmtp_get_foci_field_device(gswmtp_plan *p, float *dev_field, float *dev_intensity);
 
-/* Accuracy xi, efficiency eta and uniformity of the CURRENT phase's field
- * (any output pointer may be NULL). */
+/* Statistics of the CURRENT phase's focal field (any output pointer may be
+ * NULL):
+ *   xi  - the intensity accuracy of Algorithm 1, 1 - ||t - i|| / ||i|| with
+ *         i = I / sum I and t = Itilde / sum Itilde (normalised, so the scale
+ *         of the targets does not matter);
+ *   eta - the diffraction efficiency of the Fig. 2 caption, energy at the
+ *         foci over the incident energy: sum I / (N_ap sum A^2), N_ap the
+ *         pupil samples with A > 0.  The foci's samples of the focal plane
+ *         are not orthogonal (foci closer than the diffraction limit share
+ *         energy), so eta can exceed 1 for such patterns;
+ *   uniformity - 1 - (max r - min r) / (max r + min r), r = i / t over the
+ *         foci with t > 0 (1 when every focus meets its target).
+ * Runs the forward product when the phase changed.  Synchronises. */
 int gswmtp_get_stats(gswmtp_plan *p, double *xi, double *eta, double *uniformity);
 
-/* Weights w [n_foci] (float64, host). */
+/* The weighting factors w of Algorithm 1 (the generalised weighting of
+ * Sec. 2; all ones at plan creation), [n_foci] float64 on the host, caller
+ * order.  set_weights replaces them (finite, else GSWMTP_E_INVAL); both
+ * synchronise. */
 int gswmtp_get_weights(gswmtp_plan *p, double *out);
 int gswmtp_set_weights(gswmtp_plan *p, const double *w);
 
-/* Per-pass history of (xi, eta, uniformity) of the field each pass started
- * from, oldest first.  Copies min(cap, stored) entries (3 doubles each) of the
+/* Per-pass history of (xi, eta, uniformity) - as gswmtp_get_stats defines
+ * them - of the field each pass of Algorithm 1 started from (the accuracy
+ * the pass tested for termination), oldest first.  Copies min(cap, stored) entries (3 doubles each) of the
  * most recent passes; *n receives the number copied.  The ring keeps the last
  * 4096 passes. */
 int gswmtp_get_history(gswmtp_plan *p, double *buf, int cap, int *n);
@@ -257,11 +290,17 @@ int gswmtp_get_index(gswmtp_plan *p, gswmtp_index_info *info, int32_t *ix, int32
                      double *xu, double *yu, int32_t *rows, int32_t *cols);
 
 /* Operator-level calls (do not touch the plan's phase, weights or history).
- * forward_field: Theta = P(E) at the foci for an arbitrary complex pupil field
- *   E (host, interleaved [2*ny*nx]); samples outside the kept rows/columns are
- *   ignored.  Output host [2*n_foci].
- * adjoint_field: E' = P^H(Theta) (no projection) for focal values Theta (host
- *   [2*n_foci]); output host [2*ny*nx], zero outside the kept rows/columns. */
+ * forward_field: Theta = P(E), the forward matrix triple product of Eq. 2,
+ *   at the foci for an arbitrary complex pupil field E (host, interleaved
+ *   [2*ny*nx], row-major); samples outside the kept rows/columns are ignored.
+ *   Output host [2*n_foci], caller order.
+ * adjoint_field: E' = P^H(Theta), the operator Algorithm 1 uses as its
+ *   inverse, taken as the adjoint of Eq. 2 (the conjugate kernels, opposite
+ *   exponent sign, no 1/N scale - the phase-only projection that follows in
+ *   a pass discards any positive scale), for focal values Theta (host
+ *   [2*n_foci]) with every other sample of the reduced focal grid zero;
+ *   no projection.  Output host [2*ny*nx], zero outside the kept
+ *   rows/columns.  Both synchronise; GSWMTP_E_INVAL for non-finite input. */
 int gswmtp_forward_field(gswmtp_plan *p, const float *E, float *theta);
 int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E);
 

@@ -19,7 +19,9 @@ import numpy as np
 import torch  # loads the HIP runtime the library binds to; must precede the CDLL
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgswmtp.so")
+# GSWMTP_LIBRARY names another build of the same library (the sanitized
+# host-only build the CPU tests use); it must exist like the default one.
+LIB_PATH = os.environ.get("GSWMTP_LIBRARY") or os.path.join(HERE, "libgswmtp.so")
 
 FP32, BF16X3, FP16X3, BF16X6 = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3, "bf16x6": BF16X6}
@@ -357,12 +359,15 @@ class Plan:
         self._check(self._lib.gswmtp_get_foci_field(self._h, out.ctypes.data))
         return out[0::2] + 1j * out[1::2]
 
-    def foci_field_device(self, intensity: bool = True):
-        field = torch.empty(2 * self.n_foci, dtype=torch.float32, device="cuda")
+    def foci_field_device(self, intensity: bool = True, field: bool = True):
+        """(Theta as interleaved float32 [2N] or None, I = |Theta|^2 [N] or None)
+        as device tensors on the current stream."""
+        if not (intensity or field):
+            raise ValueError("ask for the field, the intensities or both")
+        field = torch.empty(2 * self.n_foci, dtype=torch.float32, device="cuda") if field else None
         inten = torch.empty(self.n_foci, dtype=torch.float32, device="cuda") if intensity else None
         self._sync_stream()
-        self._check(self._lib.gswmtp_get_foci_field_device(self._h, field.data_ptr(),
-                                                            _ptr(inten)))
+        self._check(self._lib.gswmtp_get_foci_field_device(self._h, _ptr(field), _ptr(inten)))
         return field, inten
 
     def stats(self) -> dict:

@@ -27,7 +27,7 @@ class MTPIntensity(torch.autograd.Function):
         plan.set_phase(phi)
         token = next(_tokens)
         plan._phase_token = token
-        _, inten = plan.foci_field_device(intensity=True)
+        _, inten = plan.foci_field_device(intensity=True, field=False)
         ctx.plan = plan
         ctx.token = token
         ctx.save_for_backward(phi)
@@ -61,24 +61,69 @@ def design_loss(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
 
 
 def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
-                eta_weight: float = 0.1, phi0=None, target=None):
+                eta_weight: float = 0.1, phi0=None, target=None, graph: bool = True):
     """Phase design by gradient descent: Adam on ``design_loss`` of the plan's
     foci intensities, differentiated through ``MTPIntensity``.  Returns
-    (phi [ny, nx] float32 CUDA tensor, loss before each step [steps] tensor)."""
+    (phi [ny, nx] float32 CUDA tensor, loss before each step [steps] tensor).
+
+    graph=True captures one whole step - the phase encode, the forward product
+    with the focus gather, the loss and its backward, the adjoint product with
+    the gradient epilogue, and Adam with its step count on the device - in one
+    graph and replays it ``steps`` times, so no step waits on the host.  The
+    library's calls only record and wait on events against the caller's
+    stream, so its internal stream joins the capture.  The captured step is
+    the eager one: a warm-up step (which sets up Adam's state and autograd's
+    buffers) is undone before capture, and both forms give the same
+    trajectory.  graph=False runs the same step eagerly."""
     idx = plan.index()
     n_ap, sum_a2 = idx["n_aperture"], idx["sum_a2"]
     if target is None:
         raise ValueError("target intensities are required")
+    if steps < 0:
+        raise ValueError("steps must be >= 0")
     t = torch.as_tensor(target, dtype=torch.float32, device="cuda")
     if phi0 is None:
         phi0 = torch.zeros(plan.ny, plan.nx)
-    phi = torch.nn.Parameter(torch.as_tensor(phi0, dtype=torch.float32, device="cuda").clone())
-    opt = torch.optim.Adam([phi], lr=lr, betas=betas, eps=eps)
-    hist = torch.empty(steps, dtype=torch.float32, device="cuda")
-    for k in range(steps):
-        opt.zero_grad(set_to_none=False)
+    start = torch.as_tensor(phi0, dtype=torch.float32, device="cuda").clone()
+    phi = torch.nn.Parameter(start.clone())
+    # one fused update kernel; the step count lives on the device in both
+    # forms (capture needs it there)
+    opt = torch.optim.Adam([phi], lr=lr, betas=betas, eps=eps, fused=True, capturable=True)
+    hist = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
+    k = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def step():
         loss = design_loss(foci_intensity(phi, plan), t, n_ap, sum_a2, eta_weight)
         loss.backward()
-        hist[k] = loss.detach()
+        hist.index_put_((k,), loss.detach().reshape(1))
         opt.step()
-    return phi.detach(), hist
+        k.add_(1)
+
+    if not graph or steps == 0:
+        for _ in range(steps):
+            opt.zero_grad(set_to_none=False)
+            step()
+        return phi.detach(), hist[:steps]
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        opt.zero_grad(set_to_none=True)
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    # undo the warm-up: start phase, zero moments and step count
+    with torch.no_grad():
+        phi.copy_(start)
+        for st in opt.state[phi].values():
+            if torch.is_tensor(st):
+                st.zero_()
+        k.zero_()
+    opt.zero_grad(set_to_none=True)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(steps):
+        g.replay()
+    out = phi.detach().clone(), hist[:steps].clone()
+    del g
+    return out

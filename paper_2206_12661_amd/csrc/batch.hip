@@ -90,6 +90,8 @@ struct gswmtp_batch {
   bool persistent = true;
   double tune_total_ms = 0.0;       // host time spent timing candidates
   int precision = GSWMTP_FP32;      // common precision of the plans
+  int fault_alloc = -1;             // allocation fault injection (fault_alloc_setting)
+  int n_alloc = 0;                  // device allocations made by the create call
   std::string err;
 };
 
@@ -451,6 +453,10 @@ int tune_class(gswmtp_batch *b, BatchClass &cl, TuneScratch &ts) {
     const size_t need = align256(out_bytes) + align256(isz * np) +
                         align256(all.size() * sizeof(WorkUnit)) +
                         align256(off.size() * sizeof(int));
+    if (need > ts.bytes && fault_alloc_hit(b->fault_alloc, &b->n_alloc)) {
+      rc = bfail(b, GSWMTP_E_NOMEM, "batch tuning scratch: injected failure");
+      break;
+    }
     if ((he = ts.need(need)) != hipSuccess) {
       rc = bfail(b, GSWMTP_E_NOMEM, "batch tuning scratch", he);
       break;
@@ -850,6 +856,8 @@ int batch_build(gswmtp_batch *b) {
     for (size_t k = 0; k < units[product].size(); ++k)
       bytes += align256(units[product][k].size() * sizeof(WorkUnit)) +
                align256(offs[product][k].size() * sizeof(int));
+  if (fault_alloc_hit(b->fault_alloc, &b->n_alloc))
+    return bfail(b, GSWMTP_E_NOMEM, "batch device pool: injected failure");
   BHIP_TRY(b, hipMalloc(&b->pool, bytes));
   char *base = static_cast<char *>(b->pool);
   for (int product = 0; product < 2; ++product) {
@@ -969,8 +977,14 @@ int gswmtp_batch_create(gswmtp_batch **out, gswmtp_plan *const *plans, int n_pla
       return GSWMTP_E_INVAL;
     }
   }
+  const int fault = fault_alloc_setting();
+  if (fault == 0) {
+    g_batch_create_error = "device allocation: injected failure (GSWMTP_FAULT_INJECT=alloc)";
+    return GSWMTP_E_NOMEM;
+  }
   gswmtp_batch *b = new (std::nothrow) gswmtp_batch();
   if (!b) return GSWMTP_E_NOMEM;
+  b->fault_alloc = fault;
   b->device = ps[0]->device;
   b->precision = ps[0]->precision;
   b->user_stream = static_cast<hipStream_t>(stream);

@@ -408,10 +408,22 @@ struct gswmtp_plan {
   bool fwd_valid = false;                 // theta/stats match the current phase
   const double *meas_active = nullptr;    // b.meas while a measured pass is queued, else null
   bool use_graph = true;
+  int fault_alloc = -1;                   // allocation fault injection (fault_alloc_setting)
+  int n_alloc = 0;                        // device allocations made by the create call
   std::string err;
 };
 
 namespace gswmtp {
+
+// Allocation fault injection for testing the failure paths, read from the
+// environment at each create call: GSWMTP_FAULT_INJECT=alloc makes every
+// device allocation of the call fail (the call returns GSWMTP_E_NOMEM before
+// any device work), =alloc:K only its K-th one (K >= 1; the earlier ones
+// succeed and are released by the failure path).  -1: off.
+int fault_alloc_setting();
+// Whether the device allocation about to be made - the (*count + 1)-th of
+// the call - is the injected failure; advances *count.
+bool fault_alloc_hit(int setting, int *count);
 
 // Kernel launchers (stream-ordered, no synchronisation).
 // honour_done: the kernel returns at once when the plan's done flag is set

@@ -1181,6 +1181,8 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     if (p->pool0_bytes > p->ws_bytes)
       return fail(p, GSWMTP_E_NOMEM, "workspace smaller than the index pool");
     p->pool0 = p->ws;
+  } else if (fault_alloc_hit(p->fault_alloc, &p->n_alloc)) {
+    return fail(p, GSWMTP_E_NOMEM, "device allocation (index pool): injected failure");
   } else if (hipMalloc(&p->pool0, p->pool0_bytes) != hipSuccess) {
     return fail(p, GSWMTP_E_NOMEM, "device allocation (index pool)");
   }
@@ -1277,6 +1279,8 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
       return fail(p, GSWMTP_E_NOMEM, msg);
     }
     p->pool1 = static_cast<char *>(p->ws) + off;
+  } else if (fault_alloc_hit(p->fault_alloc, &p->n_alloc)) {
+    return fail(p, GSWMTP_E_NOMEM, "device allocation (product pool): injected failure");
   } else if (hipMalloc(&p->pool1, p->pool1_bytes) != hipSuccess) {
     return fail(p, GSWMTP_E_NOMEM, "device allocation (product pool)");
   }
@@ -1499,6 +1503,12 @@ static int create_impl(gswmtp_plan **out, const gswmtp_desc *d, void *ws, size_t
   p->ws = ws;
   p->ws_bytes = ws_bytes;
   p->user_stream = static_cast<hipStream_t>(stream);
+  p->fault_alloc = ws ? -1 : fault_alloc_setting();   // a caller's workspace: no allocation
+  if (p->fault_alloc == 0) {
+    g_last_create_error = "device allocation: injected failure (GSWMTP_FAULT_INJECT=alloc)";
+    delete p;
+    return GSWMTP_E_NOMEM;
+  }
   int rc = check_device(p);
   if (rc == GSWMTP_OK) {
     try {
@@ -1649,12 +1659,13 @@ int gswmtp_set_phase_device(gswmtp_plan *p, const float *dev_phi) {
 }
 
 int gswmtp_get_foci_field_device(gswmtp_plan *p, float *dev_field, float *dev_intensity) {
-  if (!p || !dev_field) return GSWMTP_E_INVAL;
+  if (!p || (!dev_field && !dev_intensity)) return GSWMTP_E_INVAL;
   DeviceGuard g(p->device);
   HIP_TRY(p, enter(p));
   HIP_TRY(p, ensure_forward(p));
   const size_t nf = p->d.nf;
-  HIP_TRY(p, hipMemcpyAsync(dev_field, p->b.theta, 8 * nf, hipMemcpyDeviceToDevice, p->stream));
+  if (dev_field)
+    HIP_TRY(p, hipMemcpyAsync(dev_field, p->b.theta, 8 * nf, hipMemcpyDeviceToDevice, p->stream));
   if (dev_intensity)
     HIP_TRY(p, hipMemcpyAsync(dev_intensity, p->b.intensity, 4 * nf, hipMemcpyDeviceToDevice,
                               p->stream));
@@ -1992,3 +2003,18 @@ const char *gswmtp_stage_kernel(gswmtp_plan *p, int stage) {
 }
 
 }  // extern "C"
+
+int gswmtp::fault_alloc_setting() {
+  const char *v = std::getenv("GSWMTP_FAULT_INJECT");
+  if (!v || std::strncmp(v, "alloc", 5) != 0) return -1;
+  if (v[5] == '\0') return 0;
+  if (v[5] != ':') return -1;
+  char *end = nullptr;
+  const long k = std::strtol(v + 6, &end, 10);
+  return (end && *end == '\0' && k >= 1 && k <= 1000) ? (int)k : -1;
+}
+
+bool gswmtp::fault_alloc_hit(int setting, int *count) {
+  const int n = ++*count;
+  return setting == 0 || (setting > 0 && n == setting);
+}

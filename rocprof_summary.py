@@ -1,10 +1,11 @@
 """Summarise rocprofv3 CSV output for the library's kernels.
 
-    python -m paper_2206_12661_amd.rocprof_summary stats DIR [--top N]
+    python rocprof_summary.py stats DIR [--top N] [--per STEPS]
         per-kernel calls and mean / min / max duration from the
         ``*_kernel_stats.csv`` that ``rocprofv3 --kernel-trace --stats
-        --output-format csv -d DIR`` writes;
-    python -m paper_2206_12661_amd.rocprof_summary pmc DIR [--match S]
+        --output-format csv -d DIR`` writes, and the total kernel time (per
+        step, with --per: the run's step count);
+    python rocprof_summary.py pmc DIR [--match S]
         per-kernel mean counter value per dispatch from the
         ``*_counter_collection.csv`` of a ``rocprofv3 --pmc ...`` run (counters
         summed over their instances within a dispatch).
@@ -36,7 +37,7 @@ def _key(row: dict, *names):
     raise KeyError(names)
 
 
-def stats(d: str, top: int):
+def stats(d: str, top: int, per: int = 0):
     rows = []
     for f in _files(d, "_kernel_stats.csv"):
         with open(f, newline="") as fh:
@@ -48,6 +49,11 @@ def stats(d: str, top: int):
         print(f"| `{_key(r, 'Name')[:110]}` | {_key(r, 'Calls')} | "
               f"{float(_key(r, 'AverageNs')) / 1e3:.2f} | {float(_key(r, 'MinNs')) / 1e3:.2f} | "
               f"{float(_key(r, 'MaxNs')) / 1e3:.2f} | {float(_key(r, 'Percentage')):.2f} |")
+    tot = sum(float(_key(r, "TotalDurationNs")) for r in rows) / 1e3
+    calls = sum(int(_key(r, "Calls")) for r in rows)
+    print(f"\nall kernels: {calls} launches, {tot:.1f} us in total")
+    if per > 0:
+        print(f"per step ({per} steps): {calls / per:.1f} launches, {tot / per:.2f} us")
 
 
 def pmc(d: str, match: str):
@@ -76,12 +82,13 @@ def main(argv=None):
     a = sub.add_parser("stats")
     a.add_argument("dir")
     a.add_argument("--top", type=int, default=12)
+    a.add_argument("--per", type=int, default=0)
     b = sub.add_parser("pmc")
     b.add_argument("dir")
     b.add_argument("--match", default="")
     args = ap.parse_args(argv)
     if args.cmd == "stats":
-        stats(args.dir, args.top)
+        stats(args.dir, args.top, args.per)
     else:
         pmc(args.dir, args.match)
 

@@ -199,3 +199,34 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+@pytest.mark.parametrize("setting", ["alloc", "alloc:1", "alloc:2", "alloc:0", "allocate", ""])
+def test_fault_inject_alloc(monkeypatch, setting):
+    """GSWMTP_FAULT_INJECT=alloc fails plan creation with GSWMTP_E_NOMEM on the
+    host, after validation and before any device work (so also here, without a
+    GPU); alloc:K fails only the K-th device allocation (reached on a GPU only:
+    here creation stops at the device check, GSWMTP_E_NODEV); malformed
+    settings are off.  A bad descriptor still reports GSWMTP_E_INVAL first."""
+    import paper_2206_12661_amd as g
+    from gpu_util import cuda_ok
+    lib = g.load_library()
+    monkeypatch.setenv("GSWMTP_FAULT_INJECT", setting)
+    d, keep = _desc(g)
+    h = ctypes.c_void_p()
+    rc = lib.gswmtp_plan_create(ctypes.byref(h), ctypes.byref(d), None)
+    msg = lib.gswmtp_last_error(None).decode()
+    created = bool(h.value)
+    if created:
+        lib.gswmtp_plan_destroy(h)
+    if setting == "alloc":
+        assert rc == -4 and "injected" in msg and not created
+        bad, keep2 = _desc(g, s_x=0.0)
+        h2 = ctypes.c_void_p()
+        assert lib.gswmtp_plan_create(ctypes.byref(h2), ctypes.byref(bad), None) == -1
+    elif not cuda_ok():
+        assert rc == -7 and "injected" not in msg and not created
+    elif setting in ("alloc:1", "alloc:2"):
+        assert rc == -4 and "injected" in msg and not created
+    else:
+        assert rc == 0 and created

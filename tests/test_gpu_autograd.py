@@ -91,6 +91,50 @@ def test_adam_trajectory(g):
     assert e_l <= max(10 * sens_l, 1e-5 * np.max(np.abs(hist_o)))
 
 
+def test_c5_step0_gradient_full_size(g):
+    """The design-loss gradient of the full 1152 x 1920 / 50 x 50 design at
+    its start phase, every pixel, against the oracle's chain rule (dL/dI from
+    the loss, then dL/dphi = 2 Im(conj(E) P^H(dL/dI * Theta)), Sec. 2 forward
+    model and its adjoint)."""
+    import torch
+    h = synth_ofa.config5()
+    announce("C-5 step-0 gradient, 1152x1920 / 50x50 grid")
+    with g.Plan(h) as p:
+        idx = p.index()
+        phi = torch.tensor(h.phi0, device="cuda", requires_grad=True)
+        t = torch.tensor(h.target, device="cuda", dtype=torch.float32)
+        loss = g.design_loss(g.foci_intensity(phi, p), t, idx["n_aperture"], idx["sum_a2"])
+        loss.backward()
+        gphi = phi.grad.cpu().numpy().astype(np.float64)
+        L_gpu = float(loss)
+    L, ref, _ = _oracle_grad(h, np.asarray(h.phi0, np.float64))
+    err = rel_l2(gphi, ref)
+    worst = float(np.max(np.abs(gphi - ref)) / np.max(np.abs(ref)))
+    print(f"  loss {L_gpu:.6e} vs {L:.6e}; gradient rel L2 {err:.2e}, max {worst:.2e}")
+    assert L_gpu == pytest.approx(L, rel=1e-5, abs=1e-7)
+    assert err <= 1e-4
+    assert worst <= 1e-3
+
+
+@pytest.mark.parametrize("case", ["gradcheck-64x64-4x4", "disc-200x300-8x8"])
+def test_adam_graph_replay_equals_eager(g, case):
+    """The captured-and-replayed design step is the eager one: same phases and
+    losses, bit for bit, over 20 steps (both run Adam's device-side step
+    count; the library's kernels are deterministic)."""
+    h = synth_ofa.config5_gradcheck() if case.startswith("gradcheck") else _medium()
+    announce(f"Adam graph vs eager, {case}")
+    with g.Plan(h) as p:
+        phi_g, hist_g = g.adam_design(p, 20, phi0=h.phi0, target=h.target, graph=True)
+        phi_e, hist_e = g.adam_design(p, 20, phi0=h.phi0, target=h.target, graph=False)
+        phi_g, phi_e = phi_g.cpu().numpy(), phi_e.cpu().numpy()
+        hist_g, hist_e = hist_g.cpu().numpy(), hist_e.cpu().numpy()
+    print(f"  max |dphi| {np.max(np.abs(phi_g - phi_e)):.3e}, "
+          f"max |dloss| {np.max(np.abs(hist_g - hist_e)):.3e}")
+    assert hist_g.shape == (20,) and np.all(np.isfinite(hist_g))
+    assert np.array_equal(phi_g, phi_e)
+    assert np.array_equal(hist_g, hist_e)
+
+
 def test_c5_adam_200_steps(g):
     """The full 1152 x 1920 / 50 x 50 design: 200 Adam steps (lr 0.05).  The
     loss before the first step and the foci intensities of the final phase

@@ -59,3 +59,73 @@ def test_max_foci_count(g, mode):
     assert ea <= TOL[mode]
     assert np.all(np.isfinite(phi)) and np.all(np.isfinite(hist))
     assert hist.shape == (3, 3)
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_nonfinite_intensities_status(g, mode):
+    """A valid descriptor whose amplitude (3e38 inside the aperture, finite in
+    float32) overflows the float32 accumulation of the forward product, so the
+    focal field and its intensity sum (kept in float64, which would hold any
+    finite float32 field's) become non-finite: the pass runs to its end (no
+    fault), and the next call that reads the control block reports
+    GSWMTP_E_NONFINITE as an ordinary status, with its message."""
+    h = synth_ofa.config1()
+    h.amplitude = (np.asarray(h.amplitude, np.float64) * 3e38).astype(np.float32)
+    assert np.all(np.isfinite(h.amplitude)) and h.amplitude.max() == np.float32(3e38)
+    announce(f"non-finite intensities, amplitude 3e38, {mode}")
+    with g.Plan(h, precision=mode) as p:
+        p.iterate(2)
+        with pytest.raises(g.GswmtpError) as ei:
+            p.iterations_done()
+        assert ei.value.status == -6
+        assert "non-finite" in str(ei.value)
+
+
+def _free_bytes():
+    import torch
+    torch.cuda.synchronize()
+    return torch.cuda.mem_get_info()[0]
+
+
+@pytest.mark.parametrize("setting", ["alloc", "alloc:1", "alloc:2"])
+def test_fault_inject_alloc_releases_everything(g, monkeypatch, setting):
+    """Injected device-allocation failures (the plan's index pool, then its
+    product pool) return GSWMTP_E_NOMEM naming the injection, leave no device
+    memory behind, and a plan created afterwards works."""
+    h = synth_ofa.config3()
+    announce(f"fault injection {setting}, 1152x1920 / 1000 foci")
+    free0 = _free_bytes()
+    monkeypatch.setenv("GSWMTP_FAULT_INJECT", setting)
+    with pytest.raises(g.GswmtpError) as ei:
+        g.Plan(h)
+    assert ei.value.status == -4 and "injected" in str(ei.value)
+    monkeypatch.delenv("GSWMTP_FAULT_INJECT")
+    assert abs(_free_bytes() - free0) <= (4 << 20)
+    with g.Plan(h) as p:
+        p.iterate(1)
+        assert p.iterations_done() == 1
+
+
+@pytest.mark.parametrize("setting", ["alloc", "alloc:1"])
+def test_fault_inject_alloc_batch(g, monkeypatch, setting):
+    """The batch's allocations (tuner scratch, pool) under injection: the
+    create fails with GSWMTP_E_NOMEM and releases what it made; the plans stay
+    usable and a batch created afterwards runs."""
+    hs = [synth_ofa.random_case(60 + i, 96 + 32 * i, 128, 40 + 10 * i) for i in range(3)]
+    announce(f"batch fault injection {setting}")
+    plans = [g.Plan(h) for h in hs]
+    try:
+        free0 = _free_bytes()
+        monkeypatch.setenv("GSWMTP_FAULT_INJECT", setting)
+        with pytest.raises(g.GswmtpError) as ei:
+            g.Batch(plans)
+        assert ei.value.status == -4 and "injected" in str(ei.value)
+        monkeypatch.delenv("GSWMTP_FAULT_INJECT")
+        assert abs(_free_bytes() - free0) <= (4 << 20)
+        with g.Batch(plans) as b:
+            b.iterate(2)
+            b.sync()
+        assert all(p.iterations_done() == 2 for p in plans)
+    finally:
+        for p in plans:
+            p.close()
