@@ -176,10 +176,9 @@ def cpu_baseline(h, passes: int):
 
 
 def run_mode(g, torch, h, mode, args):
-    t0 = time.perf_counter()
+    plan_ms = plan_time_ms(g, torch, h, mode)
     plan = g.Plan(h, precision=mode)
     plan.sync()
-    plan_ms = (time.perf_counter() - t0) * 1e3
     idx = plan.index()
     fl = algorithmic_flops(idx, plan.n_foci)
     theta0 = plan.foci_field()                      # field of phi0 (operator error)
@@ -345,10 +344,27 @@ def run_batch(g, torch, args):
     return out
 
 
+def plan_time_ms(g, torch, h, mode, reps: int = 3) -> float:
+    """Median wall time of creating a plan (host validation, copies, index
+    and kernel-matrix kernels, one synchronisation), after one creation that
+    warms the code paths."""
+    ts = []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = g.Plan(h, precision=mode)
+        p.sync()
+        ts.append((time.perf_counter() - t0) * 1e3)
+        p.close()
+    return round(float(np.median(ts[1:])), 3)
+
+
 def run_sweep(g, torch, args):
     """Foci-count sweep (Sec. 2, Fig. 2(e)): time of 100 passes for uniform
     k x k arrays on the 1000 x 1000 pupil, FP32 and FP16x3, and the
-    continuous double-heart pattern; accuracy / efficiency after the run."""
+    continuous double-heart pattern; accuracy / efficiency after the run.
+    Plan-creation time per case, and at the largest focus count a plan takes
+    (262144 foci, a 512 x 512 grid on a 1024 x 1024 pupil)."""
     import synth_ofa
     ks = (9, 25, 51, 101, 151, 227) if args.sweep else \
         tuple(int(k) for k in args.sweep_cases.split(",") if k.strip())
@@ -371,9 +387,17 @@ def run_sweep(g, torch, args):
                 st = p.stats()
             row["reduced_grid"] = [idx["uy"], idx["ux"]]
             row[mode] = {"ms_per_100_passes": round(dt * 1e3, 3), "xi": round(st["xi"], 5),
-                         "eta": round(st["eta"], 4)}
+                         "eta": round(st["eta"], 4),
+                         "plan_ms": plan_time_ms(g, torch, h, mode)}
         out.append(row)
         print(f"[sweep] {row}", file=sys.stderr, flush=True)
+    big = synth_ofa.random_case(50, 1024, 1024, 0, grid=(512, 512))
+    big.fx, big.fy = synth_ofa.grid_foci(512, 512, 0.45)
+    big.target = np.random.default_rng(51).uniform(0.5, 1.0, big.fx.shape[0])
+    out.append({"case": "plan-only-1024x1024-512x512grid", "n_foci": int(big.n_foci),
+                "fp32": {"plan_ms": plan_time_ms(g, torch, big, "fp32")},
+                "fp16x3": {"plan_ms": plan_time_ms(g, torch, big, "fp16x3")}})
+    print(f"[sweep] {out[-1]}", file=sys.stderr, flush=True)
     return out
 
 

@@ -41,6 +41,7 @@ __host__ __device__ __forceinline__ size_t kblk_index(size_t row, size_t k, size
 constexpr int kPadCols = 64;       // padding granule of the N dimension
 constexpr int kMaxFoci = 262144;
 constexpr int kMaxSide = 16384;
+constexpr int kApBlocks = 256;          // workgroups of the aperture statistics
 
 // Control block (device ints): done flag, passes done, history count,
 // non-finite flag, phase-fixing pass (0: off), phase-fixing phasors recorded.
@@ -71,7 +72,10 @@ struct Bufs {
   double *meas = nullptr;                // [nf] measured intensities, then at unit sum
   double *xzu = nullptr, *yzu = nullptr;  // z of each unique (x, z) / (y, z) key
   double *xu = nullptr, *yu = nullptr;
-  int *ix = nullptr, *iy = nullptr, *firstx = nullptr, *firsty = nullptr;
+  int *ix = nullptr, *iy = nullptr;
+  // plan-time sort scratch (index.hip): keys and focus numbers, ping-pong
+  uint64_t *skey0 = nullptr, *skey1 = nullptr;
+  int *sval0 = nullptr, *sval1 = nullptr, *shist = nullptr, *shead = nullptr, *srank = nullptr;
   int *rows = nullptr, *cols = nullptr, *row_pos = nullptr, *col_pos = nullptr;
   int *keep_row = nullptr, *keep_col = nullptr;
   float *aeff = nullptr;                 // [ny][nx] effective amplitude (user orientation)
@@ -81,6 +85,8 @@ struct Bufs {
   int *csr_ir = nullptr;                 // reduced-grid row of the focus at each CSR position
   int *scalars = nullptr;                // plan-time integer results
   double *dscalars = nullptr;            // plan-time float64 results
+  double *ap_part = nullptr;             // aperture statistics, per workgroup
+  int *ap_cnt = nullptr;
   int *dup = nullptr;
   // products and state (sized after the index work)
   float *omt_r = nullptr, *omt_i = nullptr, *omc_r = nullptr, *omc_i = nullptr;
@@ -424,6 +430,27 @@ int fault_alloc_setting();
 // Whether the device allocation about to be made - the (*count + 1)-th of
 // the call - is the injected failure; advances *count.
 bool fault_alloc_hit(int setting, int *count);
+
+// Plan-time index work by sorting (index.hip).  IndexScratch holds two
+// (key, focus number) buffers of n entries, the digit counts
+// (index_hist_ints(n)) and the group heads and ranks (n each).
+struct IndexScratch {
+  uint64_t *key[2];
+  int *val[2];
+  int *hist, *head, *rank;
+};
+size_t index_hist_ints(int n);
+// Distinct (coordinate, z) pairs of n foci in increasing order (coordinate,
+// then z; -0.0 is +0.0): uniq / uniq_z receive them, idx[i] the position of
+// focus i's pair among them, *count (device) their number.  has_z = false
+// when every z is zero (one sort of the coordinates suffices).
+hipError_t unique_pairs(const double *c, const double *z, bool has_z, int n, IndexScratch sc,
+                        int *idx, double *uniq, double *uniq_z, int *count, hipStream_t s);
+// Foci ordered by the index pair (hi, lo) (each < 2^18), ties in focus
+// order: order[pos] = focus number (nullable); *dup (device, nullable) is
+// or-ed with 1 when two foci share a pair.
+hipError_t pair_order(const int *hi, const int *lo, int n, IndexScratch sc, int *order,
+                      int *dup, hipStream_t s);
 
 // Kernel launchers (stream-ordered, no synchronisation).
 // honour_done: the kernel returns at once when the plan's done flag is set

@@ -87,22 +87,46 @@ struct Carver {
   }
 };
 
-bool finite_all(const double *a, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(a[i])) return false;
+// Finite test by the exponent field (all ones: inf or NaN), branch-free over
+// blocks of 4096 so that the loop vectorises; stops at the first bad block.
+template <typename T, typename U, U kExp>
+bool finite_bits(const T *a, size_t n) {
+  for (size_t i0 = 0; i0 < n; i0 += 4096) {
+    const size_t i1 = n - i0 < 4096 ? n : i0 + 4096;
+    U bad = 0;
+    for (size_t i = i0; i < i1; ++i) {
+      U u;
+      std::memcpy(&u, a + i, sizeof u);
+      bad |= (U)((u & kExp) == kExp);
+    }
+    if (bad) return false;
+  }
   return true;
 }
-bool finite_all(const float *a, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(a[i])) return false;
+bool finite_all(const double *a, size_t n) {
+  return finite_bits<double, uint64_t, 0x7ff0000000000000ull>(a, n);
+}
+bool finite_all(const float *a, size_t n) { return finite_bits<float, uint32_t, 0x7f800000u>(a, n); }
+
+// Valid amplitudes are finite and >= 0: bit patterns up to the largest
+// finite float, and -0.0.
+bool amplitude_ok(const float *a, size_t n) {
+  for (size_t i0 = 0; i0 < n; i0 += 4096) {
+    const size_t i1 = n - i0 < 4096 ? n : i0 + 4096;
+    uint32_t bad = 0;
+    for (size_t i = i0; i < i1; ++i) {
+      uint32_t u;
+      std::memcpy(&u, a + i, sizeof u);
+      bad |= (uint32_t)(u > 0x7f7fffffu && u != 0x80000000u);
+    }
+    if (bad) return false;
+  }
   return true;
 }
 
 // ---------------------------------------------------------------------------
 // Plan-time kernels
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double canon(double x) { return x == 0.0 ? 0.0 : x; }
 
 // Effective amplitude: mask ? amplitude : 0 (in place).
 __global__ void k_aeff(float *aeff, const unsigned char *mask, size_t n) {
@@ -168,16 +192,20 @@ __global__ __launch_bounds__(1024) void k_compact(const int *keep, int n, int *l
   }
 }
 
-// Aperture statistics: number of samples with A > 0 and sum of A^2 (float64,
-// fixed order).
-__global__ __launch_bounds__(1024) void k_aperture(const float *a, size_t n, int *n_ap,
-                                                   double *sum_a2) {
-  __shared__ double sd[1024];
-  __shared__ int si[1024];
+// Aperture statistics: number of samples with A > 0 and sum of A^2 (float64).
+// Workgroup b reduces the contiguous range [b chunk, (b + 1) chunk) with a
+// fixed tree; one workgroup then sums the kApBlocks partials with a fixed
+// tree, so the result depends on n alone, not on scheduling.
+__global__ __launch_bounds__(256) void k_aperture_part(const float *a, size_t n, double *part,
+                                                       int *cnt) {
+  __shared__ double sd[256];
+  __shared__ int si[256];
   const int t = threadIdx.x;
+  const size_t chunk = (n + kApBlocks - 1) / kApBlocks;
+  const size_t lo = (size_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
   double s = 0.0;
   int c = 0;
-  for (size_t i = t; i < n; i += 1024) {
+  for (size_t i = lo + t; i < hi; i += 256) {
     const double v = a[i];
     s += v * v;
     c += v > 0.0 ? 1 : 0;
@@ -185,7 +213,28 @@ __global__ __launch_bounds__(1024) void k_aperture(const float *a, size_t n, int
   sd[t] = s;
   si[t] = c;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      sd[t] += sd[t + w];
+      si[t] += si[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[blockIdx.x] = sd[0];
+    cnt[blockIdx.x] = si[0];
+  }
+}
+
+__global__ __launch_bounds__(kApBlocks) void k_aperture_sum(const double *part, const int *cnt,
+                                                            int *n_ap, double *sum_a2) {
+  __shared__ double sd[kApBlocks];
+  __shared__ int si[kApBlocks];
+  const int t = threadIdx.x;
+  sd[t] = part[t];
+  si[t] = cnt[t];
+  __syncthreads();
+  for (int w = kApBlocks / 2; w > 0; w >>= 1) {
     if (t < w) {
       sd[t] += sd[t + w];
       si[t] += si[t + w];
@@ -198,79 +247,6 @@ __global__ __launch_bounds__(1024) void k_aperture(const float *a, size_t n, int
   }
 }
 
-// Reduced-grid keys are (coordinate, z) pairs: the focal coordinate and the
-// axial position of the focus (all z = 0 for foci on the focal plane), both
-// canonical, ordered by coordinate, then z.
-__device__ __forceinline__ bool pair_less(double c0, double z0, double c1, double z1) {
-  return c0 < c1 || (c0 == c1 && z0 < z1);
-}
-
-// first[i] = 1 when no focus m < i has the same canonical (coordinate, z).
-__global__ __launch_bounds__(256) void k_first(const double *c, const double *z, int n,
-                                               int *first) {
-  __shared__ double tile[256], tz[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const double key = i < n ? canon(c[i]) : 0.0;
-  const double kz = i < n ? canon(z[i]) : 0.0;
-  int seen = 0;
-  const int last = (blockIdx.x + 1) * 256;  // only m < i matter
-  for (int base = 0; base < n && base < last; base += 256) {
-    const int j = base + threadIdx.x;
-    tile[threadIdx.x] = j < n ? canon(c[j]) : 0.0;
-    tz[threadIdx.x] = j < n ? canon(z[j]) : 0.0;
-    __syncthreads();
-    const int lim = n - base < 256 ? n - base : 256;
-    for (int q = 0; q < lim; ++q)
-      if (base + q < i && tile[q] == key && tz[q] == kz) seen = 1;
-    __syncthreads();
-  }
-  if (i < n) first[i] = !seen;
-}
-
-// idx[i] = number of distinct keys below key i (its position in the sorted
-// unique list); the first occurrence writes uniq[idx[i]] and uniq_z[idx[i]].
-__global__ __launch_bounds__(256) void k_rank(const double *c, const double *z, const int *first,
-                                              int n, int *idx, double *uniq, double *uniq_z) {
-  __shared__ double tile[256], tz[256];
-  __shared__ int tf[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const double key = i < n ? canon(c[i]) : 0.0;
-  const double kz = i < n ? canon(z[i]) : 0.0;
-  int cnt = 0;
-  for (int base = 0; base < n; base += 256) {
-    const int j = base + threadIdx.x;
-    tile[threadIdx.x] = j < n ? canon(c[j]) : 0.0;
-    tz[threadIdx.x] = j < n ? canon(z[j]) : 0.0;
-    tf[threadIdx.x] = j < n ? first[j] : 0;
-    __syncthreads();
-    const int lim = n - base < 256 ? n - base : 256;
-    for (int q = 0; q < lim; ++q) cnt += (tf[q] && pair_less(tile[q], tz[q], key, kz)) ? 1 : 0;
-    __syncthreads();
-  }
-  if (i < n) {
-    idx[i] = cnt;
-    if (first[i]) {
-      uniq[cnt] = key;
-      uniq_z[cnt] = kz;
-    }
-  }
-}
-
-__global__ __launch_bounds__(1024) void k_count(const int *flags, int n, int *out) {
-  __shared__ int s[1024];
-  const int t = threadIdx.x;
-  int c = 0;
-  for (int i = t; i < n; i += 1024) c += flags[i];
-  s[t] = c;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (t < w) s[t] += s[t + w];
-    __syncthreads();
-  }
-  if (t == 0) *out = s[0];
-}
-
-// Any two foci with the same (ix, iy) pair.
 // Measured focus intensities (camera in the loop) divided by their sum, as
 // the weight update normalises computed intensities: one workgroup, the sum
 // in float64 in a fixed order.  The host has checked that the sum is > 0.
@@ -288,47 +264,11 @@ __global__ __launch_bounds__(1024) void k_meas_norm(double *m, int n) {
   for (int i = threadIdx.x; i < n; i += 1024) m[i] = m[i] / sum;
 }
 
-__global__ __launch_bounds__(256) void k_dup(const int *ix, const int *iy, int n, int *dup) {
-  __shared__ int tx[256], ty[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int kx = i < n ? ix[i] : -1, ky = i < n ? iy[i] : -1;
-  int d = 0;
-  for (int base = 0; base < n; base += 256) {
-    const int j = base + threadIdx.x;
-    tx[threadIdx.x] = j < n ? ix[j] : -2;
-    ty[threadIdx.x] = j < n ? iy[j] : -2;
-    __syncthreads();
-    const int lim = n - base < 256 ? n - base : 256;
-    for (int q = 0; q < lim; ++q)
-      if (base + q != i && tx[q] == kx && ty[q] == ky) d = 1;
-    __syncthreads();
-  }
-  if (i < n && d) atomicOr(dup, 1);
-}
-
-// Foci sorted by (ir, ic): foci[pos] = n with pos = #{m : key_m < key_n}.
 // Column index of the focus at each CSR position (the scatter reads it
 // beside the focus number instead of through it).
 __global__ void k_csr_gather(const int *ic, const int *foci, int n, int *out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) out[p] = ic[foci[p]];
-}
-
-__global__ __launch_bounds__(256) void k_csr_order(const int *ir, const int *ic, int n,
-                                                   int *foci) {
-  __shared__ long long tk[256];
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const long long key = i < n ? ((long long)ir[i] << 32) | (long long)ic[i] : 0;
-  int pos = 0;
-  for (int base = 0; base < n; base += 256) {
-    const int j = base + threadIdx.x;
-    tk[threadIdx.x] = j < n ? (((long long)ir[j] << 32) | (long long)ic[j]) : 0;
-    __syncthreads();
-    const int lim = n - base < 256 ? n - base : 256;
-    for (int q = 0; q < lim; ++q) pos += tk[q] < key ? 1 : 0;
-    __syncthreads();
-  }
-  if (i < n) foci[pos] = i;
 }
 
 // Row pointers from the sorted order: ptr[a] = first sorted position whose
@@ -716,10 +656,7 @@ int validate(const gswmtp_desc *d) {
   if (!(tsum > 0.0) || !std::isfinite(tsum)) return GSWMTP_E_INVAL;
   if (d->u && !finite_all(d->u, d->nx)) return GSWMTP_E_INVAL;
   if (d->v && !finite_all(d->v, d->ny)) return GSWMTP_E_INVAL;
-  if (d->amplitude) {
-    for (size_t i = 0; i < np; ++i)
-      if (!(d->amplitude[i] >= 0.f) || !std::isfinite(d->amplitude[i])) return GSWMTP_E_INVAL;
-  }
+  if (d->amplitude && !amplitude_ok(d->amplitude, np)) return GSWMTP_E_INVAL;
   if (d->phi0 && !finite_all(d->phi0, np)) return GSWMTP_E_INVAL;
   return GSWMTP_OK;
 }
@@ -973,7 +910,10 @@ void carve_pool0(Carver &c, Bufs &b, size_t nf, size_t ny, size_t nx) {
   b.tinv = c.take<double>(nf); b.tsqrt = c.take<double>(nf);
   b.xu = c.take<double>(nf); b.yu = c.take<double>(nf);
   b.ix = c.take<int>(nf); b.iy = c.take<int>(nf);
-  b.firstx = c.take<int>(nf); b.firsty = c.take<int>(nf);
+  b.skey0 = c.take<uint64_t>(nf); b.skey1 = c.take<uint64_t>(nf);
+  b.sval0 = c.take<int>(nf); b.sval1 = c.take<int>(nf);
+  b.shist = c.take<int>(index_hist_ints((int)nf));
+  b.shead = c.take<int>(nf); b.srank = c.take<int>(nf);
   b.rows = c.take<int>(ny); b.row_pos = c.take<int>(ny); b.keep_row = c.take<int>(ny);
   b.cols = c.take<int>(nx); b.col_pos = c.take<int>(nx); b.keep_col = c.take<int>(nx);
   b.aeff = c.take<float>(np);
@@ -981,6 +921,7 @@ void carve_pool0(Carver &c, Bufs &b, size_t nf, size_t ny, size_t nx) {
   b.csr_foci = c.take<int>(nf); b.csr_ptr = c.take<int>(nf + 1); b.csr_ic = c.take<int>(nf);
   b.csr_ir = c.take<int>(nf);
   b.scalars = c.take<int>(16); b.dscalars = c.take<double>(8); b.dup = c.take<int>(1);
+  b.ap_part = c.take<double>(kApBlocks); b.ap_cnt = c.take<int>(kApBlocks);
   b.theta = c.take<float>(2 * nf); b.theta_new = c.take<float>(2 * nf);
   b.intensity = c.take<float>(nf);
   b.w = c.take<double>(nf); b.stats = c.take<double>(ST_N); b.fixph = c.take<double>(2 * nf);
@@ -1227,17 +1168,18 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
                      b.row_pos, sc + 2);
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, b.keep_col, (int)nx, b.cols,
                      b.col_pos, sc + 3);
-  hipLaunchKernelGGL(k_aperture, dim3(1), dim3(1024), 0, s, b.aeff, np, sc + 4, b.dscalars);
+  hipLaunchKernelGGL(k_aperture_part, dim3(kApBlocks), dim3(256), 0, s, b.aeff, np, b.ap_part,
+                     b.ap_cnt);
+  hipLaunchKernelGGL(k_aperture_sum, dim3(1), dim3(kApBlocks), 0, s, b.ap_part, b.ap_cnt, sc + 4,
+                     b.dscalars);
   const dim3 gf = grid1(nf);
-  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fx, b.fz, (int)nf, b.firstx);
-  hipLaunchKernelGGL(k_first, gf, dim3(256), 0, s, b.fy, b.fz, (int)nf, b.firsty);
-  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fx, b.fz, b.firstx, (int)nf, b.ix, b.xu,
-                     b.xzu);
-  hipLaunchKernelGGL(k_rank, gf, dim3(256), 0, s, b.fy, b.fz, b.firsty, (int)nf, b.iy, b.yu,
-                     b.yzu);
-  hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firstx, (int)nf, sc + 0);
-  hipLaunchKernelGGL(k_count, dim3(1), dim3(1024), 0, s, b.firsty, (int)nf, sc + 1);
-  hipLaunchKernelGGL(k_dup, gf, dim3(256), 0, s, b.ix, b.iy, (int)nf, b.dup);
+  IndexScratch isc{{b.skey0, b.skey1}, {b.sval0, b.sval1}, b.shist, b.shead, b.srank};
+  const bool has_z = d->fz != nullptr;
+  HIP_TRY(p, unique_pairs(b.fx, b.fz, has_z, (int)nf, isc, b.ix, b.xu, b.xzu, sc + 0, s));
+  HIP_TRY(p, unique_pairs(b.fy, b.fz, has_z, (int)nf, isc, b.iy, b.yu, b.yzu, sc + 1, s));
+  // duplicates, and the focus order of the compressed rows when y is the
+  // row axis (the x-row order is sorted again once the axis is known)
+  HIP_TRY(p, pair_order(b.iy, b.ix, (int)nf, isc, b.csr_foci, b.dup, s));
   hipLaunchKernelGGL(k_tnorm, dim3(1), dim3(1024), 0, s, b.target, (int)nf, b.tnorm, b.tinv,
                      b.tsqrt);
   HIP_TRY(p, hipGetLastError());
@@ -1292,7 +1234,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
 
   const int *ir = D.axis == 0 ? b.iy : b.ix;
   const int *ic = D.axis == 0 ? b.ix : b.iy;
-  hipLaunchKernelGGL(k_csr_order, gf, dim3(256), 0, s, ir, ic, (int)nf, b.csr_foci);
+  if (D.axis != 0) HIP_TRY(p, pair_order(ir, ic, (int)nf, isc, b.csr_foci, nullptr, s));
   hipLaunchKernelGGL(k_row_ptr, grid1(nf + 1), dim3(256), 0, s, ir, b.csr_foci, (int)nf, D.Ur,
                      b.csr_ptr);
   hipLaunchKernelGGL(k_csr_gather, grid1(nf), dim3(256), 0, s, ic, b.csr_foci, (int)nf, b.csr_ic);

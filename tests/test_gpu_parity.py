@@ -71,6 +71,54 @@ def test_index_bit_exact(g, name):
     assert got["n_aperture"] == int(np.count_nonzero(h.amplitude > 0))
 
 
+def _lattice_foci(n, seed):
+    """n distinct foci drawn from a coarse lattice (so most x and y values are
+    shared by many foci), in random order, with both signs of zero."""
+    rng = np.random.default_rng(seed)
+    xs = np.arange(-180, 181) * 0.75
+    ys = np.arange(-200, 201) * (2.0 / 3.0)
+    pick = rng.choice(xs.size * ys.size, n, replace=False)
+    fx, fy = xs[pick % xs.size].copy(), ys[pick // xs.size].copy()
+    fx[(fx == 0.0) & (rng.random(n) < 0.5)] = -0.0
+    fy[(fy == 0.0) & (rng.random(n) < 0.5)] = -0.0
+    return fx, fy
+
+
+@pytest.mark.parametrize("n", [2047, 2049, 30000, 144000])
+def test_index_bit_exact_many_foci(g, n):
+    """Index work across several sort chunks (2048 keys each), ragged tail
+    included: the distinct coordinates, gather indices and axis equal the
+    oracle's bit for bit."""
+    h = synth_ofa.random_case(7, 256, 384, 1)
+    h.fx, h.fy = _lattice_foci(n, n)
+    h.target = np.random.default_rng(n + 1).uniform(0.5, 1.0, n)
+    announce(f"index, {n} lattice foci")
+    with g.Plan(h) as p:
+        got = p.index()
+    ref = oracle.index_plan(h.fx, h.fy, h.amplitude)
+    for k in ["xu", "yu"]:
+        assert np.array_equal(got[k].view(np.uint64), ref[k].view(np.uint64)), k
+    for k in ["ix", "iy"]:
+        assert np.array_equal(got[k], ref[k]), k
+    assert got["axis"] == ref["axis"]
+
+
+def test_duplicate_focus_across_chunks_is_rejected(g):
+    """A repeated focus far from its twin in the input order (different sort
+    chunks), one of the pair written as -0.0."""
+    h = synth_ofa.random_case(8, 128, 128, 1)
+    fx, fy = _lattice_foci(20000, 9)
+    k = int(np.flatnonzero(fx == 0.0)[0])
+    fx[-1], fy[-1] = (-0.0 if not np.signbit(fx[k]) else 0.0), fy[k]
+    h.fx, h.fy = fx, fy
+    h.target = np.ones(fx.size)
+    assert oracle.index_plan(h.fx, h.fy, h.amplitude)["duplicate"]
+    announce("duplicate focus across sort chunks, 20000 foci")
+    with pytest.raises(g.GswmtpError) as e:
+        g.Plan(h)
+    assert e.value.status == -2
+
+
 def test_disc_aperture_compaction(g):
     h = synth_ofa.random_case(3, 64, 64, 30, radius=20.0)
     announce("compaction disc r=20")

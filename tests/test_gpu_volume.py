@@ -48,8 +48,31 @@ def _shared_planes():
     return h
 
 
+def _lattice_planes(n, seed):
+    """n distinct (x, y, z) foci from a coarse lateral lattice on 7 planes
+    (z both signs, -0.0 among them), random order: many foci share a lateral
+    coordinate on several planes, so the (coordinate, z) keys span several
+    sort chunks."""
+    rng = np.random.default_rng(seed)
+    h = synth_ofa.volume_case(4, 96, 128, 4)
+    xs = np.arange(-40, 41) * 0.9
+    ys = np.arange(-30, 31) * 1.1
+    zs = np.array([-30.0, -12.5, -0.0, 0.0, 12.5, 30.0, 47.0])
+    pick = rng.choice(xs.size * ys.size * zs.size, n, replace=False)
+    fx = xs[pick % xs.size]
+    fy = ys[(pick // xs.size) % ys.size]
+    fz = zs[pick // (xs.size * ys.size)]
+    key = np.stack([oracle.canonical(fx), oracle.canonical(fy), oracle.canonical(fz)], 1)
+    _, first = np.unique(key, axis=0, return_index=True)   # -0.0 and 0.0 planes merge
+    first = np.sort(first)
+    h.fx, h.fy, h.fz = fx[first].copy(), fy[first].copy(), fz[first].copy()
+    h.target = rng.uniform(0.3, 1.0, h.fx.shape[0])
+    return h
+
+
 def _cases():
     return {
+        "lattice-7planes-9000": _lattice_planes(9000, 31),
         "random-3planes-96x128": synth_ofa.volume_case(1, 96, 128, 30),
         "grid-3planes-64x64-disc": synth_ofa.volume_case(2, 64, 64, 0, grid=(5, 4),
                                                          radius=28.0, planes=(-20.0, 0.0, 20.0)),
