@@ -929,20 +929,28 @@ __device__ __forceinline__ bool d16_loop(const SplitArgs &a, int m0, int n0, int
         _Pragma("unroll") for (int p_ = 0; p_ < PL; ++p_) F[i_][p_] =                     \
             lds[(BUF) * SA + (p_ * BM + 16 * i_ + l16) * CH + q];                         \
   } while (0)
+  // Prologue.  The loads still in flight when the loop starts are issued in
+  // the order a loop step issues them (A of stage 2, its B, A of stage 3,
+  // its B), so that the wait counts the compiler sets at the top of the loop,
+  // which must hold for the first iteration as for every later one, are the
+  // steady-state ones and do not drain the prefetch on each iteration.
   E_LOAD_A(ra0, 0);
   E_LOAD_A(ra1, 1 < last ? 1 : last);
   E_LOAD_B(bq0, 0);
   E_LOAD_B(bq1, 1 < last ? 1 : last);
-  E_LOAD_B(bq2, 2 < last ? 2 : last);
-  E_LOAD_B(bq3, 3 < last ? 3 : last);
   if constexpr (PRE) gather_pre_foci(a.g, m0, tid, gp);   // behind the operand loads
   const int stop = a.done ? *a.done : 0;
   asm volatile("" ::: "memory");
   if (stop) return false;
   E_STORE_A(ra0, 0);
-  E_LOAD_A(ra0, 2 < last ? 2 : last);
   E_STORE_A(ra1, 1);
+  __builtin_amdgcn_sched_barrier(0);
+  E_LOAD_A(ra0, 2 < last ? 2 : last);
+  E_LOAD_B(bq2, 2 < last ? 2 : last);
+  __builtin_amdgcn_sched_barrier(0);
   E_LOAD_A(ra1, 3 < last ? 3 : last);
+  E_LOAD_B(bq3, 3 < last ? 3 : last);
+  __builtin_amdgcn_sched_barrier(0);
   __syncthreads();
   u4 f0[MB][PL], f1[MB][PL];
   E_READ_A(f0, 0);
@@ -1002,18 +1010,6 @@ __device__ __forceinline__ void cgemm_split_d16_unit(const SplitArgs &a, const i
       accR[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
       accI[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     }
-  // the projection's amplitudes, read now and used after the main loop
-  float ampv[EPI == EPI_PROJECT ? MB : 1][EPI == EPI_PROJECT ? NB : 1][4];
-  if constexpr (EPI == EPI_PROJECT) {
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          ampv[i][j][r] = a.amp[(size_t)(m0 + 16 * i + 4 * q + r) * a.ldc + n0 + wave * WTN +
-                                16 * j + l16];
-  }
   // the gather's focus indices: row range now, foci behind the operand loads
   GatherPre gp;
   if constexpr (EPI == EPI_GATHER) gather_pre_rows(a.g, m0, BM, gp);
@@ -1049,6 +1045,17 @@ __device__ __forceinline__ void cgemm_split_d16_unit(const SplitArgs &a, const i
         }
       }
   } else if constexpr (EPI == EPI_PROJECT) {
+    // the projection's amplitudes, read after the main loop (held through it
+    // they would add to its register pressure)
+    float ampv[MB][NB][4];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          ampv[i][j][r] = a.amp[(size_t)(m0 + 16 * i + 4 * q + r) * a.ldc + n0 + wave * WTN +
+                                16 * j + l16];
     // project, split into terms, transpose the tile through LDS, then write
     // rows of P^T [plane][n][m0 .. m0 + BM) in 16-byte runs
     unsigned short *tt = reinterpret_cast<unsigned short *>(lds);

@@ -137,9 +137,8 @@ __host__ __device__ inline bool split_is_bf16(int precision) {
 
 // Round-to-nearest-even float32 -> bfloat16 / float16 bit patterns and back.
 __device__ __forceinline__ unsigned short f32_to_bf16_rn(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  // one v_cvt_pk_bf16_f32 (round to nearest even) on gfx950
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
   return __uint_as_float((unsigned)h << 16);
