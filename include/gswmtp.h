@@ -327,6 +327,21 @@ int gswmtp_forward_field_noalloc(gswmtp_plan *p, const float *E, float *theta);
  * dev_grad: device float [ny*nx] (0 outside the aperture).  Stream-ordered. */
 int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad);
 
+/* One Adam step (Kingma and Ba's update with bias-corrected moments, the
+ * optimiser of the differentiable form's design loop; not from the paper) on
+ * n float32 values, all device memory, stream-ordered on `stream`
+ * (hipStream_t, NULL = default), no host synchronisation and no allocation,
+ * so a design step can be captured in a graph:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   phi -= (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps),
+ * with t read from dev_step (device float, the number of this step, >= 1;
+ * the caller advances it before each call).  phi, m, v [n] are updated in
+ * place; dev_grad [n] is read.  GSWMTP_E_INVAL for a null pointer (n > 0),
+ * betas outside [0, 1), non-finite lr or eps < 0; n = 0 does nothing. */
+int gswmtp_adam_step_device(float *phi, const float *dev_grad, float *m, float *v,
+                            const float *dev_step, size_t n, double lr, double beta1,
+                            double beta2, double eps, void *stream);
+
 /* Profiling: run n_iter passes eagerly with HIP events around each stage on
  * the plan's stream and return the mean milliseconds per launch of each stage
  * in ms_out[GSWMTP_N_STAGES] (order: forward product with the fused focus

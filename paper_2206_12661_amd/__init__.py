@@ -111,6 +111,9 @@ _SIGNATURES = {
     "gswmtp_forward_field_noalloc": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_adjoint_field": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_phase_gradient_device": ([_P, _P, _P], ctypes.c_int),
+    "gswmtp_adam_step_device": ([_P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _P],
+                                ctypes.c_int),
     "gswmtp_time_stages": ([_P, ctypes.c_int, _P], ctypes.c_int),
     "gswmtp_stage_kernel": ([_P, ctypes.c_int], ctypes.c_char_p),
     "gswmtp_batch_create": ([ctypes.POINTER(_P), _P, ctypes.c_int, _P], ctypes.c_int),
@@ -474,6 +477,24 @@ _LOOPS = {0: "plain", 1: "pipe", 2: "direct", 3: "b16"}
 _SOURCES = {0: "plan", 1: "tuned", 2: "cache", 3: "env"}
 
 
+def adam_step_device(phi: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                     step: torch.Tensor, lr: float, betas=(0.9, 0.999), eps: float = 1e-8):
+    """One Adam step in the library (gswmtp_adam_step_device) on contiguous
+    float32 CUDA tensors, in place on phi, m and v; ``step`` is a one-element
+    float32 CUDA tensor holding this step's number (advanced by the caller)."""
+    for t in (phi, grad, m, v, step):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("Adam operands must be contiguous float32 CUDA tensors")
+    n = phi.numel()
+    if not (grad.numel() == m.numel() == v.numel() == n and step.numel() == 1):
+        raise ValueError("Adam operands differ in size")
+    rc = load_library().gswmtp_adam_step_device(
+        phi.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), step.data_ptr(), n,
+        float(lr), float(betas[0]), float(betas[1]), float(eps), _stream_handle())
+    if rc != 0:
+        raise GswmtpError(rc, "gswmtp_adam_step_device")
+
+
 def _config_text(c) -> str:
     bm, bn, bk, kg, loop, split = list(c)
     return f"{bm}x{bn}/{'kg2' if kg == 2 else _LOOPS.get(loop, loop)}/k{split}"
@@ -566,4 +587,4 @@ class Batch:
 from .autograd import MTPIntensity, adam_design, design_loss, foci_intensity  # noqa: E402
 
 __all__ = ["Plan", "Batch", "GswmtpError", "load_library", "status_string", "MTPIntensity",
-           "foci_intensity", "design_loss", "adam_design", "FP32", "BF16X3", "FP16X3", "BF16X6", "STAGES"]
+           "foci_intensity", "design_loss", "adam_design", "FP32", "BF16X3", "FP16X3", "BF16X6", "STAGES", "adam_step_device"]

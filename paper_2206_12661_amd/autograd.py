@@ -63,18 +63,20 @@ def design_loss(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
 def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
                 eta_weight: float = 0.1, phi0=None, target=None, graph: bool = True):
     """Phase design by gradient descent: Adam on ``design_loss`` of the plan's
-    foci intensities, differentiated through ``MTPIntensity``.  Returns
-    (phi [ny, nx] float32 CUDA tensor, loss before each step [steps] tensor).
+    foci intensities, differentiated through ``MTPIntensity``, the update in
+    the library's kernel (``adam_step_device``).  Returns (phi [ny, nx]
+    float32 CUDA tensor, loss before each step [steps] tensor).
 
     graph=True captures one whole step - the phase encode, the forward product
     with the focus gather, the loss and its backward, the adjoint product with
-    the gradient epilogue, and Adam with its step count on the device - in one
-    graph and replays it ``steps`` times, so no step waits on the host.  The
-    library's calls only record and wait on events against the caller's
-    stream, so its internal stream joins the capture.  The captured step is
-    the eager one: a warm-up step (which sets up Adam's state and autograd's
-    buffers) is undone before capture, and both forms give the same
-    trajectory.  graph=False runs the same step eagerly."""
+    the gradient epilogue, and the Adam update with its step count on the
+    device - in one graph and replays it ``steps`` times, so no step waits on
+    the host.  The library's calls only record and wait on events against the
+    caller's stream, so its internal stream joins the capture.  The captured
+    step is the eager one: a warm-up step (which sets up autograd's buffers)
+    is undone before capture, and both forms give the same trajectory.
+    graph=False runs the same step eagerly."""
+    from . import adam_step_device
     idx = plan.index()
     n_ap, sum_a2 = idx["n_aperture"], idx["sum_a2"]
     if target is None:
@@ -85,40 +87,39 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     if phi0 is None:
         phi0 = torch.zeros(plan.ny, plan.nx)
     start = torch.as_tensor(phi0, dtype=torch.float32, device="cuda").clone()
-    phi = torch.nn.Parameter(start.clone())
-    # one fused update kernel; the step count lives on the device in both
-    # forms (capture needs it there)
-    opt = torch.optim.Adam([phi], lr=lr, betas=betas, eps=eps, fused=True, capturable=True)
+    phi = start.clone().requires_grad_(True)
+    m = torch.zeros_like(start)
+    v = torch.zeros_like(start)
+    count = torch.zeros(1, dtype=torch.float32, device="cuda")   # Adam's step number
     hist = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
     k = torch.zeros(1, dtype=torch.int64, device="cuda")
 
     def step():
         loss = design_loss(foci_intensity(phi, plan), t, n_ap, sum_a2, eta_weight)
-        loss.backward()
+        (gphi,) = torch.autograd.grad(loss, phi)
         hist.index_put_((k,), loss.detach().reshape(1))
-        opt.step()
+        count.add_(1.0)
+        with torch.no_grad():
+            adam_step_device(phi, gphi.contiguous(), m, v, count, lr, betas, eps)
         k.add_(1)
 
     if not graph or steps == 0:
         for _ in range(steps):
-            opt.zero_grad(set_to_none=False)
             step()
         return phi.detach(), hist[:steps]
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        opt.zero_grad(set_to_none=True)
         step()
     torch.cuda.current_stream().wait_stream(side)
-    # undo the warm-up: start phase, zero moments and step count
+    # undo the warm-up: start phase, zero moments and step counts
     with torch.no_grad():
         phi.copy_(start)
-        for st in opt.state[phi].values():
-            if torch.is_tensor(st):
-                st.zero_()
+        m.zero_()
+        v.zero_()
+        count.zero_()
         k.zero_()
-    opt.zero_grad(set_to_none=True)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         step()

@@ -230,3 +230,19 @@ def test_fault_inject_alloc(monkeypatch, setting):
         assert rc == -4 and "injected" in msg and not created
     else:
         assert rc == 0 and created
+
+
+def test_adam_step_validation(lib):
+    """The Adam entry point checks its arguments on the host (no GPU needed):
+    n = 0 is a no-op, null pointers and out-of-range betas are rejected."""
+    P = ctypes.c_void_p
+    buf = (ctypes.c_float * 4)()
+    p = ctypes.cast(buf, P)
+    call = lambda *a: lib.gswmtp_adam_step_device(*a)  # noqa: E731
+    assert call(None, None, None, None, None, 0, 0.05, 0.9, 0.999, 1e-8, None) == 0
+    assert call(None, p, p, p, p, 4, 0.05, 0.9, 0.999, 1e-8, None) == -1
+    assert call(p, p, p, p, None, 4, 0.05, 0.9, 0.999, 1e-8, None) == -1
+    assert call(p, p, p, p, p, 4, 0.05, 1.0, 0.999, 1e-8, None) == -1
+    assert call(p, p, p, p, p, 4, 0.05, 0.9, -0.1, 1e-8, None) == -1
+    assert call(p, p, p, p, p, 4, math.nan, 0.9, 0.999, 1e-8, None) == -1
+    assert call(p, p, p, p, p, 4, 0.05, 0.9, 0.999, -1.0, None) == -1

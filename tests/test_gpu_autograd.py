@@ -135,6 +135,35 @@ def test_adam_graph_replay_equals_eager(g, case):
     assert np.array_equal(hist_g, hist_e)
 
 
+def test_adam_kernel_matches_torch_adam(g):
+    """The library's Adam step against torch.optim.Adam (float32, the same
+    published update) on random data over five steps, both from zero moments:
+    phases within a few float32 roundings of each other."""
+    import torch
+    announce("Adam kernel vs torch.optim.Adam")
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    n = 300001                                  # a ragged tail past the 256-wide blocks
+    phi0 = torch.randn(n, generator=gen)
+    grads = [torch.randn(n, generator=gen) * 10.0 ** -k for k in range(5)]
+    p_ref = torch.nn.Parameter(phi0.clone().cuda())
+    opt = torch.optim.Adam([p_ref], lr=0.05, betas=(0.9, 0.999), eps=1e-8, foreach=False)
+    phi = phi0.clone().cuda()
+    m = torch.zeros_like(phi)
+    v = torch.zeros_like(phi)
+    step = torch.zeros(1, device="cuda")
+    for gr in grads:
+        gr = gr.cuda()
+        p_ref.grad = gr.clone()
+        opt.step()
+        step += 1.0
+        g.adam_step_device(phi, gr, m, v, step, 0.05)
+    torch.cuda.synchronize()
+    d = (phi - p_ref.detach()).abs().max().item()
+    print(f"  max |phi - torch| {d:.3e}")
+    assert d <= 1e-5
+    assert torch.equal(step.cpu(), torch.tensor([5.0]))
+
+
 def test_c5_adam_200_steps(g):
     """The full 1152 x 1920 / 50 x 50 design: 200 Adam steps (lr 0.05).  The
     loss before the first step and the foci intensities of the final phase
