@@ -135,14 +135,16 @@ def test_adam_graph_replay_equals_eager(g, case):
     assert np.array_equal(hist_g, hist_e)
 
 
-def test_adam_kernel_matches_torch_adam(g):
+@pytest.mark.parametrize("n", [300001, 300000])
+def test_adam_kernel_matches_torch_adam(g, n):
     """The library's Adam step against torch.optim.Adam (float32, the same
     published update) on random data over five steps, both from zero moments:
-    phases within a few float32 roundings of each other."""
+    phases within a few float32 roundings of each other.  n = 300001 runs the
+    one-value-per-thread kernel (a ragged tail past the 256-wide blocks),
+    n = 300000 the 16-byte one."""
     import torch
-    announce("Adam kernel vs torch.optim.Adam")
+    announce(f"Adam kernel vs torch.optim.Adam, n = {n}")
     gen = torch.Generator(device="cpu").manual_seed(5)
-    n = 300001                                  # a ragged tail past the 256-wide blocks
     phi0 = torch.randn(n, generator=gen)
     grads = [torch.randn(n, generator=gen) * 10.0 ** -k for k in range(5)]
     p_ref = torch.nn.Parameter(phi0.clone().cuda())
