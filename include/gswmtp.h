@@ -327,6 +327,23 @@ int gswmtp_forward_field_noalloc(gswmtp_plan *p, const float *E, float *theta);
  * dev_grad: device float [ny*nx] (0 outside the aperture).  Stream-ordered. */
 int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad);
 
+/* The design loss of the differentiable form and its gradient in the
+ * intensities, for the n foci intensities dev_I and targets dev_target (device
+ * float [n], targets >= 0 with a positive sum):
+ *   L = sum_n (i_n - t_n)^2 - eta_weight * eta,  i = I / sum I,
+ *   t = T / sum T,  eta = sum I / (n_ap sum_a2)
+ * (normalised intensities against normalised targets as in the weight update
+ * of Algorithm 1; eta the diffraction efficiency of the Fig. 2 caption with the
+ * incident energy of the discrete sums n_ap sum A^2), and
+ *   dL/dI_k = 2 r_k / S - 2 sum_m r_m i_m / S - eta_weight / (n_ap sum_a2),
+ * r = i - t, S = sum I.  dev_loss [1] and dev_dI [n] (device float) receive
+ * them.  One workgroup, sums in float64 over a fixed order; stream-ordered on
+ * `stream`, no host synchronisation.  GSWMTP_E_INVAL for n < 1, a null
+ * pointer, or n_ap, sum_a2 not positive and finite. */
+int gswmtp_design_loss_device(const float *dev_I, const float *dev_target, int n, double n_ap,
+                              double sum_a2, double eta_weight, float *dev_loss, float *dev_dI,
+                              void *stream);
+
 /* One Adam step (Kingma and Ba's update with bias-corrected moments, the
  * optimiser of the differentiable form's design loop; not from the paper) on
  * n float32 values, all device memory, stream-ordered on `stream`

@@ -111,6 +111,8 @@ _SIGNATURES = {
     "gswmtp_forward_field_noalloc": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_adjoint_field": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_phase_gradient_device": ([_P, _P, _P], ctypes.c_int),
+    "gswmtp_design_loss_device": ([_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, _P, _P, _P], ctypes.c_int),
     "gswmtp_adam_step_device": ([_P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, _P],
                                 ctypes.c_int),
@@ -584,7 +586,8 @@ class Batch:
         self.close()
 
 
-from .autograd import MTPIntensity, adam_design, design_loss, foci_intensity  # noqa: E402
+from .autograd import (MTPIntensity, adam_design, design_loss, design_loss_fused,  # noqa: E402
+                       foci_intensity)
 
 __all__ = ["Plan", "Batch", "GswmtpError", "load_library", "status_string", "MTPIntensity",
-           "foci_intensity", "design_loss", "adam_design", "FP32", "BF16X3", "FP16X3", "BF16X6", "STAGES", "adam_step_device"]
+           "foci_intensity", "design_loss", "adam_design", "design_loss_fused", "FP32", "BF16X3", "FP16X3", "BF16X6", "STAGES", "adam_step_device"]

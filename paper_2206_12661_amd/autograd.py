@@ -60,11 +60,49 @@ def design_loss(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
     return (r * r).sum() - eta_weight * S / (float(n_ap) * float(sum_a2))
 
 
+class DesignLoss(torch.autograd.Function):
+    """``design_loss`` as one library kernel (gswmtp_design_loss_device), which
+    forms the loss and dL/dI together (float64 sums in a fixed order); the
+    backward scales the saved dL/dI by the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
+                eta_weight: float):
+        from . import GswmtpError, _stream_handle, load_library
+        if not (I.is_cuda and I.dtype == torch.float32 and target.is_cuda and
+                target.dtype == torch.float32 and I.numel() == target.numel()):
+            raise TypeError("I and target must be float32 CUDA tensors of one size")
+        I = I.contiguous()
+        target = target.contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device=I.device)
+        dI = torch.empty_like(I)
+        rc = load_library().gswmtp_design_loss_device(
+            I.data_ptr(), target.data_ptr(), I.numel(), float(n_ap), float(sum_a2),
+            float(eta_weight), loss.data_ptr(), dI.data_ptr(), _stream_handle())
+        if rc != 0:
+            raise GswmtpError(rc, "gswmtp_design_loss_device")
+        ctx.save_for_backward(dI)
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, g: torch.Tensor):
+        (dI,) = ctx.saved_tensors
+        return g * dI, None, None, None, None
+
+
+def design_loss_fused(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
+                      eta_weight: float = 0.1) -> torch.Tensor:
+    """``design_loss`` in the library: the same value and gradient, with sums in
+    float64, in one kernel instead of a dozen small tensor operations."""
+    return DesignLoss.apply(I, target, n_ap, sum_a2, eta_weight)
+
+
 def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
                 eta_weight: float = 0.1, phi0=None, target=None, graph: bool = True):
     """Phase design by gradient descent: Adam on ``design_loss`` of the plan's
-    foci intensities, differentiated through ``MTPIntensity``, the update in
-    the library's kernel (``adam_step_device``).  Returns (phi [ny, nx]
+    foci intensities (the library's fused form, ``design_loss_fused``),
+    differentiated through ``MTPIntensity``, the update in the library's kernel
+    (``adam_step_device``).  Returns (phi [ny, nx]
     float32 CUDA tensor, loss before each step [steps] tensor).
 
     graph=True captures one whole step - the phase encode, the forward product
@@ -95,7 +133,7 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     k = torch.zeros(1, dtype=torch.int64, device="cuda")
 
     def step():
-        loss = design_loss(foci_intensity(phi, plan), t, n_ap, sum_a2, eta_weight)
+        loss = design_loss_fused(foci_intensity(phi, plan), t, n_ap, sum_a2, eta_weight)
         (gphi,) = torch.autograd.grad(loss, phi)
         hist.index_put_((k,), loss.detach().reshape(1))
         count.add_(1.0)

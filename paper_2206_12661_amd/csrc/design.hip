@@ -1,7 +1,7 @@
-// Adam update of the design phases (the optimiser of the differentiable
-// form's design loop): one elementwise pass over phi, its gradient and the two
-// moment estimates, stream-ordered, with the step number read from device
-// memory so that the whole design step can be captured in a graph.
+// The differentiable form's design loop on the device: the design loss of
+// the foci intensities with its gradient, and the Adam update of the phases.
+// Both are stream-ordered and read everything they need from device memory,
+// so that a whole design step can be captured in a graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,7 +60,64 @@ __global__ __launch_bounds__(256) void k_adam4(float4 *phi, const float4 *grad, 
   }
 }
 
+// Design loss L = sum_n (i_n - t_n)^2 - w eta and dL/dI, one workgroup:
+// i = I / sum I, t = T / sum T, eta = sum I / (n_ap sum A^2).  Sums in
+// float64 over a fixed tree (strided per thread, then a shared-memory tree),
+// so the result is the same on every run.
+constexpr int kLossThreads = 1024;
+
+__device__ __forceinline__ double block_sum(double x, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = x;
+  __syncthreads();
+  for (int w = kLossThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kLossThreads) void k_design_loss(const float *I, const float *T,
+                                                              int n, double c, double w,
+                                                              float *loss, float *dI) {
+  __shared__ double sh[kLossThreads];
+  double sI = 0.0, sT = 0.0;
+  for (int k = threadIdx.x; k < n; k += kLossThreads) {
+    sI += (double)I[k];
+    sT += (double)T[k];
+  }
+  const double SI = block_sum(sI, sh), ST = block_sum(sT, sh);
+  double rr = 0.0, ri = 0.0;
+  for (int k = threadIdx.x; k < n; k += kLossThreads) {
+    const double i = (double)I[k] / SI, r = i - (double)T[k] / ST;
+    rr += r * r;
+    ri += r * i;
+  }
+  const double RR = block_sum(rr, sh), RI = block_sum(ri, sh);
+  if (threadIdx.x == 0) *loss = (float)(RR - w * SI * c);
+  // d i_m / d I_k = (delta_mk - i_m) / S
+  for (int k = threadIdx.x; k < n; k += kLossThreads) {
+    const double r = (double)I[k] / SI - (double)T[k] / ST;
+    dI[k] = (float)(2.0 * r / SI - 2.0 * RI / SI - w * c);
+  }
+}
+
 }  // namespace
+
+extern "C" int gswmtp_design_loss_device(const float *dev_I, const float *dev_target, int n,
+                                         double n_ap, double sum_a2, double eta_weight,
+                                         float *dev_loss, float *dev_dI, void *stream) {
+  if (n < 1 || !dev_I || !dev_target || !dev_loss || !dev_dI) return GSWMTP_E_INVAL;
+  if (!(n_ap > 0.0) || !(sum_a2 > 0.0) || !std::isfinite(n_ap) || !std::isfinite(sum_a2) ||
+      !std::isfinite(eta_weight))
+    return GSWMTP_E_INVAL;
+  hipLaunchKernelGGL(k_design_loss, dim3(1), dim3(kLossThreads), 0,
+                     static_cast<hipStream_t>(stream), dev_I, dev_target, n,
+                     1.0 / (n_ap * sum_a2), eta_weight, dev_loss, dev_dI);
+  return hipGetLastError() == hipSuccess ? GSWMTP_OK : GSWMTP_E_HIP;
+}
 
 extern "C" int gswmtp_adam_step_device(float *phi, const float *grad, float *m, float *v,
                                        const float *step, size_t n, double lr, double beta1,

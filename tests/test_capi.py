@@ -246,3 +246,18 @@ def test_adam_step_validation(lib):
     assert call(p, p, p, p, p, 4, 0.05, 0.9, -0.1, 1e-8, None) == -1
     assert call(p, p, p, p, p, 4, math.nan, 0.9, 0.999, 1e-8, None) == -1
     assert call(p, p, p, p, p, 4, 0.05, 0.9, 0.999, -1.0, None) == -1
+
+
+def test_design_loss_validation(lib):
+    """The fused design-loss entry point rejects bad sizes and pointers on the
+    host (no GPU needed)."""
+    P = ctypes.c_void_p
+    buf = (ctypes.c_float * 4)()
+    p = ctypes.cast(buf, P)
+    call = lambda *a: lib.gswmtp_design_loss_device(*a)  # noqa: E731
+    assert call(p, p, 0, 10.0, 10.0, 0.1, p, p, None) == -1
+    assert call(None, p, 4, 10.0, 10.0, 0.1, p, p, None) == -1
+    assert call(p, p, 4, 10.0, 10.0, 0.1, p, None, None) == -1
+    assert call(p, p, 4, 0.0, 10.0, 0.1, p, p, None) == -1
+    assert call(p, p, 4, 10.0, -1.0, 0.1, p, p, None) == -1
+    assert call(p, p, 4, 10.0, 10.0, math.inf, p, p, None) == -1

@@ -135,6 +135,33 @@ def test_adam_graph_replay_equals_eager(g, case):
     assert np.array_equal(hist_g, hist_e)
 
 
+@pytest.mark.parametrize("n", [2500, 70001])
+def test_design_loss_fused_against_oracle(g, n):
+    """The library's design loss and dL/dI (one workgroup, float64 sums)
+    against the oracle's (float64) on seeded intensities and targets, and
+    against the torch form of the same loss."""
+    import torch
+    announce(f"fused design loss, {n} foci")
+    rng = np.random.default_rng(n)
+    I = rng.uniform(0.0, 2.0, n).astype(np.float32)
+    T = rng.uniform(0.5, 1.0, n).astype(np.float32)
+    n_ap, sum_a2 = 2211840, 2211840.0
+    It = torch.tensor(I, device="cuda", requires_grad=True)
+    Tt = torch.tensor(T, device="cuda")
+    L = g.design_loss_fused(It, Tt, n_ap, sum_a2)
+    L.backward()
+    L_o, dI_o = oracle.design_loss(I.astype(np.float64), T.astype(np.float64), n_ap, sum_a2)
+    dI = It.grad.cpu().numpy().astype(np.float64)
+    It2 = torch.tensor(I, device="cuda", requires_grad=True)
+    L2 = g.design_loss(It2, Tt, n_ap, sum_a2)
+    L2.backward()
+    print(f"  L {float(L):.9e} oracle {L_o:.9e} torch {float(L2):.9e}; "
+          f"dL/dI rel {rel_l2(dI, dI_o):.2e}")
+    assert float(L) == pytest.approx(L_o, rel=1e-6, abs=1e-9)
+    assert rel_l2(dI, dI_o) <= 1e-6
+    assert rel_l2(It2.grad.cpu().numpy(), dI_o) <= 1e-3   # the float32 torch form
+
+
 @pytest.mark.parametrize("n", [300001, 300000])
 def test_adam_kernel_matches_torch_adam(g, n):
     """The library's Adam step against torch.optim.Adam (float32, the same
