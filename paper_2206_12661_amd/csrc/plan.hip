@@ -393,10 +393,13 @@ __global__ void k_encode_amp(Orient o, const float *aeff, float scale, int nx, i
                                                             : 0.f;
 }
 
-// Pupil field E = A exp(i phi) from a user-layout phase (nullable = zeros).
+// Pupil field E = A exp(i phi) from a user-layout phase (nullable = zeros);
+// ctrl (nullable): the recorded focal phases of phase fixing are dropped
+// (its flag cleared by the first thread), as a new phase requires.
 __global__ void k_encode_phase(Orient o, const float *phi, const float *amp, int nx, int Rp,
-                               int Cp, float *pr, float *pi) {
+                               int Cp, float *pr, float *pi, int *ctrl) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ctrl && id == 0) ctrl[CTRL_FIXED] = 0;
   if (id >= (size_t)Rp * Cp) return;
   int y, x;
   float re = 0.f, im = 0.f;
@@ -530,8 +533,9 @@ __global__ void k_fill_unit(float *t, int nf) {
 // (amp already carries the power-of-two scale).
 template <bool BF, int NT>
 __global__ void k_encode_phase_split(Orient o, const float *phi, const float *amp, int nx,
-                                     int Rp, int Cp, unsigned short *pt) {
+                                     int Rp, int Cp, unsigned short *pt, int *ctrl) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ctrl && id == 0) ctrl[CTRL_FIXED] = 0;
   if (id >= (size_t)Rp * Cp) return;
   const int i = (int)(id / Rp), j = (int)(id % Rp);
   int y, x;
@@ -615,8 +619,6 @@ __global__ void k_set_fix(int *ctrl, int from) {
   ctrl[CTRL_FIX] = from;
   ctrl[CTRL_FIXED] = 0;
 }
-
-__global__ void k_clear_fixed(int *ctrl) { ctrl[CTRL_FIXED] = 0; }
 
 inline dim3 grid1(size_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
@@ -844,20 +846,22 @@ hipError_t ensure_forward(gswmtp_plan *p) {
   return hipSuccess;
 }
 
-// Encode a user-layout phase (device, nullable = zeros) into the pupil field.
-hipError_t encode_phase(gswmtp_plan *p, const float *dev_phi, hipStream_t s) {
+// Encode a user-layout phase (device, nullable = zeros) into the pupil field;
+// clear_fixed: also drop the recorded focal phases of phase fixing.
+hipError_t encode_phase(gswmtp_plan *p, const float *dev_phi, hipStream_t s, bool clear_fixed) {
+  int *ctrl = clear_fixed ? p->b.ctrl : nullptr;
   const Dims &D = p->d;
   const Orient o = orient_of(p);
   const dim3 g = grid1((size_t)D.Rp * D.Cp);
   if (is_split(p)) {
 #define ENC(BF, NT)                                                                              \
   hipLaunchKernelGGL((k_encode_phase_split<BF, NT>), g, dim3(256), 0, s, o, dev_phi, p->b.amp, \
-                     D.nx, D.Rp, D.Cp, p->b.ps)
+                     D.nx, D.Rp, D.Cp, p->b.ps, ctrl)
     DISPATCH_SPLIT(p->precision, ENC)
 #undef ENC
   } else {
     hipLaunchKernelGGL(k_encode_phase, g, dim3(256), 0, s, o, dev_phi, p->b.amp, D.nx, D.Rp,
-                       D.Cp, p->b.p_r, p->b.p_i);
+                       D.Cp, p->b.p_r, p->b.p_i, ctrl);
   }
   return hipGetLastError();
 }
@@ -1277,7 +1281,7 @@ int plan_build(gswmtp_plan *p, const gswmtp_desc *d) {
     HIP_TRY(p, hipMemcpyAsync(b.iobuf, d->phi0, np * 4, hipMemcpyHostToDevice, s));
     phi_dev = b.iobuf;
   }
-  HIP_TRY(p, encode_phase(p, phi_dev, s));
+  HIP_TRY(p, encode_phase(p, phi_dev, s, false));
   hipLaunchKernelGGL(k_fill_d, grid1(nf), dim3(256), 0, s, b.w, 1.0, nf);
   HIP_TRY(p, hipGetLastError());
   HIP_TRY(p, hipStreamSynchronize(s));
@@ -1570,9 +1574,7 @@ int gswmtp_get_phase(gswmtp_plan *p, float *out) {
 }
 
 static int set_phase_impl(gswmtp_plan *p, const float *dev_phi) {
-  HIP_TRY(p, encode_phase(p, dev_phi, p->stream));
-  hipLaunchKernelGGL(k_clear_fixed, dim3(1), dim3(1), 0, p->stream, p->b.ctrl);
-  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, encode_phase(p, dev_phi, p->stream, true));
   p->fwd_valid = false;
   return GSWMTP_OK;
 }
