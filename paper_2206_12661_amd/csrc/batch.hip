@@ -177,6 +177,7 @@ std::vector<WorkConfig> candidates(int precision, int product, int M, int N) {
     add(GemmTile{64, 128, 32, 1, 1}, 2);
     if (product == 0) add(GemmTile{64, 128, 32, 1, 3}, 1);
     else add(GemmTile{48, 192, 32, 1, 3}, 1);
+    add(GemmTile{64, 64, 32, 1, 3}, 1);    // 16x16-block loop on the small tiles
   } else {
     add(GemmTile{64, 64, 32, 2, 0}, 1);
   }

@@ -1428,6 +1428,7 @@ hipError_t work_e(const WorkLaunch &w, hipStream_t s, int *occ) {
         if (t.bm == 48 && t.bn == 192) return work_d16_t<48, 192, BF, NT, EPI>(w, s, occ);
       if constexpr (EPI == EPI_GATHER)
         if (t.bm == 64 && t.bn == 128) return work_d16_t<64, 128, BF, NT, EPI>(w, s, occ);
+      if (t.bm == 64 && t.bn == 64) return work_d16_t<64, 64, BF, NT, EPI>(w, s, occ);
       return hipErrorInvalidValue;
     }
     if (t.bk != 32 || t.bm != 64) return hipErrorInvalidValue;
