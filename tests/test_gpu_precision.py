@@ -124,12 +124,12 @@ def test_full_size_pass_split(g, mode, case):
     """One split-precision pass at a large size from an identical state after
     5 float32 passes, where the weight update's gain kappa is 1 (asserted):
     weights and the new foci field at the mode's plain bar.  The benchmark
-    size (1152 x 1920, 1000 foci) runs the 64 x 128 forward tiles on the
-    direct loop and the re-associated 64 x 64 adjoint with its split-K tail;
-    512 x 2048 with 1060 foci runs 544 forward tiles of 64 x 64 with 32
-    split-K tail tiles (gather epilogue in the tail launch) and the adjoint's
-    128 tiles of 64 x 128 on the direct loop, every one split in two K chunks
-    (the tail kernel of the column-wave layout)."""
+    size (1152 x 1920, 1000 foci) runs the two-term modes on the 16x16-block
+    loop (64 x 128 forward tiles, the re-associated adjoint on 48 x 192
+    tiles, one round and no split-K tail) and BF16x6 on 64 x 64 tiles with
+    the split-K tail; 512 x 2048 with 1060 foci has tile counts that leave a
+    short last round, so its products take the split-K tail launches (the
+    kernels each stage ran are printed)."""
     h = _large_case(case)
     announce(f"large pass {case} {mode}")
     with g.Plan(h) as p:
@@ -140,6 +140,7 @@ def test_full_size_pass_split(g, mode, case):
         q.iterate(1)
         w1 = q.weights()
         th1 = q.foci_field()
+        print("  stages:", [q.stage_kernel(i) for i in range(5)])
     hk = synth_ofa.Hologram(h.name, h.ny, h.nx, h.amplitude, h.u, h.v, h.s_x, h.s_y, h.fx, h.fy,
                             h.target, phi_k, 1)
     r = oracle.gsw(hk, n_iter=1, w=w_k)

@@ -3,7 +3,8 @@ one focus (N = U_r), Omega_r^H S is formed as (Omega_r^H diag Theta') times
 the conjugated Omega_c rows of the foci, with no scatter into S.  It must
 agree with the scatter form (GSWMTP_ADJOINT=scatter) and with the FP64 oracle
 to each mode's bar, with ragged row counts (U_r below the 32-row k-block and
-the 64-row padding) and under graph replay."""
+the 64-row padding), at the benchmark size (1152 x 1920, 1000 foci: the
+48 x 192 adjoint tiles of the 16x16-block loop) and under graph replay."""
 import numpy as np
 import pytest
 
@@ -28,6 +29,7 @@ def g():
 def _cases():
     return {
         "config2": synth_ofa.config2(),
+        "config3-1152x1920-1000": synth_ofa.config3(),
         "ragged-100x150-N70": synth_ofa.random_case(10, 100, 150, 70, amplitude="random"),
         "ragged-130x200-N45-disc": synth_ofa.random_case(11, 130, 200, 45, radius=60.0),
     }
