@@ -60,6 +60,26 @@ def design_loss(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
     return (r * r).sum() - eta_weight * S / (float(n_ap) * float(sum_a2))
 
 
+def _loss_and_gradient(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
+                       eta_weight: float):
+    """(loss [1], dL/dI [N]) of ``design_loss`` from the library kernel
+    (gswmtp_design_loss_device), on the current stream."""
+    from . import GswmtpError, _stream_handle, load_library
+    if not (I.is_cuda and I.dtype == torch.float32 and target.is_cuda and
+            target.dtype == torch.float32 and I.numel() == target.numel()):
+        raise TypeError("I and target must be float32 CUDA tensors of one size")
+    I = I.detach().contiguous()
+    target = target.contiguous()
+    loss = torch.empty(1, dtype=torch.float32, device=I.device)
+    dI = torch.empty_like(I)
+    rc = load_library().gswmtp_design_loss_device(
+        I.data_ptr(), target.data_ptr(), I.numel(), float(n_ap), float(sum_a2),
+        float(eta_weight), loss.data_ptr(), dI.data_ptr(), _stream_handle())
+    if rc != 0:
+        raise GswmtpError(rc, "gswmtp_design_loss_device")
+    return loss, dI
+
+
 class DesignLoss(torch.autograd.Function):
     """``design_loss`` as one library kernel (gswmtp_design_loss_device), which
     forms the loss and dL/dI together (float64 sums in a fixed order); the
@@ -68,19 +88,7 @@ class DesignLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
                 eta_weight: float):
-        from . import GswmtpError, _stream_handle, load_library
-        if not (I.is_cuda and I.dtype == torch.float32 and target.is_cuda and
-                target.dtype == torch.float32 and I.numel() == target.numel()):
-            raise TypeError("I and target must be float32 CUDA tensors of one size")
-        I = I.contiguous()
-        target = target.contiguous()
-        loss = torch.empty(1, dtype=torch.float32, device=I.device)
-        dI = torch.empty_like(I)
-        rc = load_library().gswmtp_design_loss_device(
-            I.data_ptr(), target.data_ptr(), I.numel(), float(n_ap), float(sum_a2),
-            float(eta_weight), loss.data_ptr(), dI.data_ptr(), _stream_handle())
-        if rc != 0:
-            raise GswmtpError(rc, "gswmtp_design_loss_device")
+        loss, dI = _loss_and_gradient(I, target, n_ap, sum_a2, eta_weight)
         ctx.save_for_backward(dI)
         return loss.reshape(())
 
@@ -100,19 +108,25 @@ def design_loss_fused(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: 
 def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
                 eta_weight: float = 0.1, phi0=None, target=None, graph: bool = True):
     """Phase design by gradient descent: Adam on ``design_loss`` of the plan's
-    foci intensities (the library's fused form, ``design_loss_fused``),
-    differentiated through ``MTPIntensity``, the update in the library's kernel
-    (``adam_step_device``).  Returns (phi [ny, nx]
-    float32 CUDA tensor, loss before each step [steps] tensor).
+    foci intensities, the update in the library's kernel
+    (``adam_step_device``).  Returns (phi [ny, nx] float32 CUDA tensor, loss
+    before each step [steps] tensor).
+
+    A step is the chain rule that ``foci_intensity`` and ``design_loss_fused``
+    run under autograd, called directly: the forward to I, the loss kernel
+    with dL/dI, the phase gradient of that dL/dI (``MTPIntensity``'s
+    backward), so no seed gradient or scaling by it (autograd's seed is 1.0:
+    the same gradient bit for bit).
 
     graph=True captures one whole step - the phase encode, the forward product
-    with the focus gather, the loss and its backward, the adjoint product with
+    with the focus gather, the loss and its gradient, the adjoint product with
     the gradient epilogue, and the Adam update with its step count on the
     device - in one graph and replays it ``steps`` times, so no step waits on
     the host.  The library's calls only record and wait on events against the
     caller's stream, so its internal stream joins the capture.  The captured
-    step is the eager one: a warm-up step (which sets up autograd's buffers)
-    is undone before capture, and both forms give the same trajectory.
+    step is the eager one: a warm-up step (which sets up the plan's lazy
+    buffers) is undone before capture, and both forms give the same
+    trajectory.
     graph=False runs the same step eagerly."""
     from . import adam_step_device
     idx = plan.index()
@@ -125,7 +139,7 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     if phi0 is None:
         phi0 = torch.zeros(plan.ny, plan.nx)
     start = torch.as_tensor(phi0, dtype=torch.float32, device="cuda").clone()
-    phi = start.clone().requires_grad_(True)
+    phi = start.clone()
     m = torch.zeros_like(start)
     v = torch.zeros_like(start)
     count = torch.zeros(1, dtype=torch.float32, device="cuda")   # Adam's step number
@@ -133,12 +147,14 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     k = torch.zeros(1, dtype=torch.int64, device="cuda")
 
     def step():
-        loss = design_loss_fused(foci_intensity(phi, plan), t, n_ap, sum_a2, eta_weight)
-        (gphi,) = torch.autograd.grad(loss, phi)
-        hist.index_put_((k,), loss.detach().reshape(1))
+        plan.set_phase(phi)
+        plan._phase_token = next(_tokens)   # a pending MTPIntensity backward re-sets its phase
+        _, inten = plan.foci_field_device(intensity=True, field=False)
+        loss, dI = _loss_and_gradient(inten, t, n_ap, sum_a2, eta_weight)
+        gphi = plan.phase_gradient_device(dI)
+        hist.index_put_((k,), loss)
         count.add_(1.0)
-        with torch.no_grad():
-            adam_step_device(phi, gphi.contiguous(), m, v, count, lr, betas, eps)
+        adam_step_device(phi, gphi, m, v, count, lr, betas, eps)
         k.add_(1)
 
     if not graph or steps == 0:
@@ -152,12 +168,11 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
         step()
     torch.cuda.current_stream().wait_stream(side)
     # undo the warm-up: start phase, zero moments and step counts
-    with torch.no_grad():
-        phi.copy_(start)
-        m.zero_()
-        v.zero_()
-        count.zero_()
-        k.zero_()
+    phi.copy_(start)
+    m.zero_()
+    v.zero_()
+    count.zero_()
+    k.zero_()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         step()

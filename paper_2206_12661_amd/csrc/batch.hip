@@ -1031,7 +1031,7 @@ int gswmtp_batch_iterate(gswmtp_batch *b, int n_iter, double stop_accuracy) {
   BHIP_TRY(b, hipEventRecord(b->ev_done, b->stream));
   for (auto *p : b->plans) {
     BHIP_TRY(b, hipStreamWaitEvent(p->stream, b->ev_done, 0));
-    p->fwd_valid = false;
+    p->fwd_valid = p->stats_valid = false;
   }
   BHIP_TRY(b, hipStreamWaitEvent(b->user_stream, b->ev_done, 0));
   return GSWMTP_OK;

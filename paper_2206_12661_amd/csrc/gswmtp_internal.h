@@ -410,7 +410,8 @@ struct gswmtp_plan {
   void *ws = nullptr;                     // caller's workspace holding both pools, or null
   size_t ws_bytes = 0;
   hipGraphExec_t graph1 = nullptr, graph8 = nullptr;
-  bool fwd_valid = false;                 // theta/stats match the current phase
+  bool fwd_valid = false;                 // theta and intensity match the current phase
+  bool stats_valid = false;               // so do the focus statistics (implies fwd_valid)
   const double *meas_active = nullptr;    // b.meas while a measured pass is queued, else null
   bool use_graph = true;
   int fault_alloc = -1;                   // allocation fault injection (fault_alloc_setting)
@@ -459,6 +460,9 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
                         const float *bi, float *cr, float *ci, const float *er,
                         const float *ei, bool honour_done, hipStream_t s, int phases = 3);
 hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s);
+// Theta and |Theta|^2 of the current forward's gather partials into the
+// plan's theta and intensity (no statistics, one launch).
+hipError_t launch_field(const gswmtp_plan *p, hipStream_t s);
 GatherCtx gather_ctx(const gswmtp_plan *p);
 hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
                               const unsigned short *bt, float *cr, float *ci,

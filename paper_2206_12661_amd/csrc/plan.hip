@@ -837,11 +837,20 @@ hipError_t enqueue_pass(gswmtp_plan *p, hipStream_t s) {
 }
 
 // Forward field and statistics of the current phase (no weight update).
-hipError_t ensure_forward(gswmtp_plan *p) {
-  if (p->fwd_valid) return hipSuccess;
+// Forward of the current phase (lazy): theta and intensity, and with stats
+// the focus statistics too.  The statistics are recomputed from a forward of
+// their own when asked for after a field-only call (the gather partials may
+// have been reused by an operator call since).
+hipError_t ensure_forward(gswmtp_plan *p, bool stats) {
+  if (stats ? p->stats_valid : p->fwd_valid) return hipSuccess;
   hipError_t e;
   if ((e = stage_forward(p, false, p->stream)) != hipSuccess) return e;
-  if ((e = launch_update(p, UPD_STATS, p->stream)) != hipSuccess) return e;
+  if (stats) {
+    if ((e = launch_update(p, UPD_STATS, p->stream)) != hipSuccess) return e;
+    p->stats_valid = true;
+  } else if ((e = launch_field(p, p->stream)) != hipSuccess) {
+    return e;
+  }
   p->fwd_valid = true;
   return hipSuccess;
 }
@@ -1509,7 +1518,7 @@ int gswmtp_iterate(gswmtp_plan *p, int n_iter, double stop_accuracy) {
   } else {
     for (int i = 0; i < n_iter; ++i) HIP_TRY(p, enqueue_pass(p, p->stream));
   }
-  p->fwd_valid = false;
+  p->fwd_valid = p->stats_valid = false;
   HIP_TRY(p, leave(p));
   return GSWMTP_OK;
 }
@@ -1535,7 +1544,7 @@ int gswmtp_iterate_measured(gswmtp_plan *p, const double *measured) {
   const hipError_t e = enqueue_pass(p, p->stream);   // eager: graphs hold no measured pass
   p->meas_active = nullptr;
   HIP_TRY(p, e);
-  p->fwd_valid = false;
+  p->fwd_valid = p->stats_valid = false;
   HIP_TRY(p, leave(p));
   HIP_TRY(p, hipStreamSynchronize(p->stream));        // the caller may reuse `measured`
   return GSWMTP_OK;
@@ -1575,7 +1584,7 @@ int gswmtp_get_phase(gswmtp_plan *p, float *out) {
 
 static int set_phase_impl(gswmtp_plan *p, const float *dev_phi) {
   HIP_TRY(p, encode_phase(p, dev_phi, p->stream, true));
-  p->fwd_valid = false;
+  p->fwd_valid = p->stats_valid = false;
   return GSWMTP_OK;
 }
 
@@ -1606,7 +1615,7 @@ int gswmtp_get_foci_field_device(gswmtp_plan *p, float *dev_field, float *dev_in
   if (!p || (!dev_field && !dev_intensity)) return GSWMTP_E_INVAL;
   DeviceGuard g(p->device);
   HIP_TRY(p, enter(p));
-  HIP_TRY(p, ensure_forward(p));
+  HIP_TRY(p, ensure_forward(p, false));
   const size_t nf = p->d.nf;
   if (dev_field)
     HIP_TRY(p, hipMemcpyAsync(dev_field, p->b.theta, 8 * nf, hipMemcpyDeviceToDevice, p->stream));
@@ -1621,7 +1630,7 @@ int gswmtp_get_foci_field(gswmtp_plan *p, float *out) {
   if (!p || !out) return GSWMTP_E_INVAL;
   DeviceGuard g(p->device);
   HIP_TRY(p, enter(p));
-  HIP_TRY(p, ensure_forward(p));
+  HIP_TRY(p, ensure_forward(p, false));
   HIP_TRY(p, hipMemcpyAsync(out, p->b.theta, 8 * (size_t)p->d.nf, hipMemcpyDeviceToHost,
                             p->stream));
   HIP_TRY(p, hipStreamSynchronize(p->stream));
@@ -1632,7 +1641,7 @@ int gswmtp_get_stats(gswmtp_plan *p, double *xi, double *eta, double *uniformity
   if (!p) return GSWMTP_E_INVAL;
   DeviceGuard g(p->device);
   HIP_TRY(p, enter(p));
-  HIP_TRY(p, ensure_forward(p));
+  HIP_TRY(p, ensure_forward(p, true));
   double st[ST_N];
   HIP_TRY(p, hipMemcpyAsync(st, p->b.stats, sizeof st, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(p, hipStreamSynchronize(p->stream));
@@ -1872,7 +1881,7 @@ int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_
   const Dims &D = p->d;
   HIP_TRY(p, enter(p));
   hipStream_t s = p->stream;
-  HIP_TRY(p, ensure_forward(p));
+  HIP_TRY(p, ensure_forward(p, false));
   HIP_TRY(p, launch_grad_field(p, dev_g, s));
   HIP_TRY(p, scatter_products(p, p->b.theta_new, false, s));
   HIP_TRY(p, launch_cgemm(p, false, EPI_GRAD, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i, p->b.p_r,
@@ -1921,7 +1930,7 @@ int gswmtp_time_stages(gswmtp_plan *p, int n_iter, double *ms_out) {
         ms_out[k] += ms / n_iter;
       }
     }
-    p->fwd_valid = false;
+    p->fwd_valid = p->stats_valid = false;
     if (leave(p) != hipSuccess) rc = fail(p, GSWMTP_E_HIP, "leave");
   } while (false);
   for (auto &e : ev)
