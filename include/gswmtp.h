@@ -344,6 +344,19 @@ int gswmtp_design_loss_device(const float *dev_I, const float *dev_target, int n
                               double sum_a2, double eta_weight, float *dev_loss, float *dev_dI,
                               void *stream);
 
+/* gswmtp_design_loss_device plus the design loop's bookkeeping on the device,
+ * so that a loop step needs no kernels besides the library's: after forming L,
+ * with s = *dev_step (device float, the number of steps recorded so far),
+ * dev_hist[s] = L when s < hist_cap, then *dev_step = s + 1 - the step number
+ * t of the gswmtp_adam_step_device call that follows on the same stream.
+ * dev_hist (device float [hist_cap]) may be NULL when hist_cap is 0.  Same
+ * errors as gswmtp_design_loss_device, and GSWMTP_E_INVAL for a null dev_step
+ * or hist_cap < 0. */
+int gswmtp_design_loss_record_device(const float *dev_I, const float *dev_target, int n,
+                                     double n_ap, double sum_a2, double eta_weight,
+                                     float *dev_loss, float *dev_dI, float *dev_hist,
+                                     int hist_cap, float *dev_step, void *stream);
+
 /* One Adam step (Kingma and Ba's update with bias-corrected moments, the
  * optimiser of the differentiable form's design loop; not from the paper) on
  * n float32 values, all device memory, stream-ordered on `stream`

@@ -113,6 +113,9 @@ _SIGNATURES = {
     "gswmtp_phase_gradient_device": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_design_loss_device": ([_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, _P, _P, _P], ctypes.c_int),
+    "gswmtp_design_loss_record_device": ([_P, _P, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, _P, _P, _P,
+                                          ctypes.c_int, _P, _P], ctypes.c_int),
     "gswmtp_adam_step_device": ([_P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, _P],
                                 ctypes.c_int),

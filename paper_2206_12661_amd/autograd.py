@@ -61,9 +61,11 @@ def design_loss(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
 
 
 def _loss_and_gradient(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: float,
-                       eta_weight: float):
-    """(loss [1], dL/dI [N]) of ``design_loss`` from the library kernel
-    (gswmtp_design_loss_device), on the current stream."""
+                       eta_weight: float, hist: torch.Tensor = None, step: torch.Tensor = None):
+    """(loss [1], dL/dI [N]) of ``design_loss`` from the library kernel, on the
+    current stream; with ``step`` (float32 CUDA [1]) the kernel also records
+    the loss in ``hist[step]`` and advances ``step`` by one
+    (gswmtp_design_loss_record_device)."""
     from . import GswmtpError, _stream_handle, load_library
     if not (I.is_cuda and I.dtype == torch.float32 and target.is_cuda and
             target.dtype == torch.float32 and I.numel() == target.numel()):
@@ -72,9 +74,16 @@ def _loss_and_gradient(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2:
     target = target.contiguous()
     loss = torch.empty(1, dtype=torch.float32, device=I.device)
     dI = torch.empty_like(I)
-    rc = load_library().gswmtp_design_loss_device(
-        I.data_ptr(), target.data_ptr(), I.numel(), float(n_ap), float(sum_a2),
-        float(eta_weight), loss.data_ptr(), dI.data_ptr(), _stream_handle())
+    args = (I.data_ptr(), target.data_ptr(), I.numel(), float(n_ap), float(sum_a2),
+            float(eta_weight), loss.data_ptr(), dI.data_ptr())
+    if step is None:
+        rc = load_library().gswmtp_design_loss_device(*args, _stream_handle())
+    else:
+        if not (step.is_cuda and step.dtype == torch.float32 and hist.is_cuda and
+                hist.dtype == torch.float32 and hist.is_contiguous()):
+            raise TypeError("hist and step must be float32 CUDA tensors")
+        rc = load_library().gswmtp_design_loss_record_device(
+            *args, hist.data_ptr(), hist.numel(), step.data_ptr(), _stream_handle())
     if rc != 0:
         raise GswmtpError(rc, "gswmtp_design_loss_device")
     return loss, dI
@@ -122,7 +131,8 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     with the focus gather, the loss and its gradient, the adjoint product with
     the gradient epilogue, and the Adam update with its step count on the
     device - in one graph and replays it ``steps`` times, so no step waits on
-    the host.  The library's calls only record and wait on events against the
+    the host; every kernel of the step is the library's.  The library's
+    calls only record and wait on events against the
     caller's stream, so its internal stream joins the capture.  The captured
     step is the eager one: a warm-up step (which sets up the plan's lazy
     buffers) is undone before capture, and both forms give the same
@@ -142,20 +152,18 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     phi = start.clone()
     m = torch.zeros_like(start)
     v = torch.zeros_like(start)
-    count = torch.zeros(1, dtype=torch.float32, device="cuda")   # Adam's step number
+    count = torch.zeros(1, dtype=torch.float32, device="cuda")   # steps recorded so far
     hist = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
-    k = torch.zeros(1, dtype=torch.int64, device="cuda")
 
     def step():
         plan.set_phase(phi)
         plan._phase_token = next(_tokens)   # a pending MTPIntensity backward re-sets its phase
         _, inten = plan.foci_field_device(intensity=True, field=False)
-        loss, dI = _loss_and_gradient(inten, t, n_ap, sum_a2, eta_weight)
+        # the loss kernel records L in hist[count] and advances count, which is
+        # then this step's number t for Adam
+        _, dI = _loss_and_gradient(inten, t, n_ap, sum_a2, eta_weight, hist, count)
         gphi = plan.phase_gradient_device(dI)
-        hist.index_put_((k,), loss)
-        count.add_(1.0)
         adam_step_device(phi, gphi, m, v, count, lr, betas, eps)
-        k.add_(1)
 
     if not graph or steps == 0:
         for _ in range(steps):
@@ -172,7 +180,6 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     m.zero_()
     v.zero_()
     count.zero_()
-    k.zero_()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         step()

@@ -79,9 +79,14 @@ __device__ __forceinline__ double block_sum(double x, double *sh) {
   return r;
 }
 
+// With `step` (the design loop's bookkeeping, optional): thread 0 also
+// writes L to hist[*step] (while *step < hist_cap) and advances *step by one,
+// the step number that the Adam update launched after it reads.
 __global__ __launch_bounds__(kLossThreads) void k_design_loss(const float *I, const float *T,
                                                               int n, double c, double w,
-                                                              float *loss, float *dI) {
+                                                              float *loss, float *dI,
+                                                              float *hist, int hist_cap,
+                                                              float *step) {
   __shared__ double sh[kLossThreads];
   double sI = 0.0, sT = 0.0;
   for (int k = threadIdx.x; k < n; k += kLossThreads) {
@@ -96,7 +101,15 @@ __global__ __launch_bounds__(kLossThreads) void k_design_loss(const float *I, co
     ri += r * i;
   }
   const double RR = block_sum(rr, sh), RI = block_sum(ri, sh);
-  if (threadIdx.x == 0) *loss = (float)(RR - w * SI * c);
+  if (threadIdx.x == 0) {
+    const float L = (float)(RR - w * SI * c);
+    *loss = L;
+    if (step) {
+      const float s = *step;
+      if (hist && s >= 0.f && s < (float)hist_cap) hist[(int)s] = L;
+      *step = s + 1.f;
+    }
+  }
   // d i_m / d I_k = (delta_mk - i_m) / S
   for (int k = threadIdx.x; k < n; k += kLossThreads) {
     const double r = (double)I[k] / SI - (double)T[k] / ST;
@@ -106,17 +119,39 @@ __global__ __launch_bounds__(kLossThreads) void k_design_loss(const float *I, co
 
 }  // namespace
 
-extern "C" int gswmtp_design_loss_device(const float *dev_I, const float *dev_target, int n,
-                                         double n_ap, double sum_a2, double eta_weight,
-                                         float *dev_loss, float *dev_dI, void *stream) {
+namespace {
+
+int design_loss(const float *dev_I, const float *dev_target, int n, double n_ap, double sum_a2,
+                double eta_weight, float *dev_loss, float *dev_dI, float *dev_hist,
+                int hist_cap, float *dev_step, void *stream) {
   if (n < 1 || !dev_I || !dev_target || !dev_loss || !dev_dI) return GSWMTP_E_INVAL;
   if (!(n_ap > 0.0) || !(sum_a2 > 0.0) || !std::isfinite(n_ap) || !std::isfinite(sum_a2) ||
       !std::isfinite(eta_weight))
     return GSWMTP_E_INVAL;
   hipLaunchKernelGGL(k_design_loss, dim3(1), dim3(kLossThreads), 0,
                      static_cast<hipStream_t>(stream), dev_I, dev_target, n,
-                     1.0 / (n_ap * sum_a2), eta_weight, dev_loss, dev_dI);
+                     1.0 / (n_ap * sum_a2), eta_weight, dev_loss, dev_dI, dev_hist, hist_cap,
+                     dev_step);
   return hipGetLastError() == hipSuccess ? GSWMTP_OK : GSWMTP_E_HIP;
+}
+
+}  // namespace
+
+extern "C" int gswmtp_design_loss_device(const float *dev_I, const float *dev_target, int n,
+                                         double n_ap, double sum_a2, double eta_weight,
+                                         float *dev_loss, float *dev_dI, void *stream) {
+  return design_loss(dev_I, dev_target, n, n_ap, sum_a2, eta_weight, dev_loss, dev_dI, nullptr,
+                     0, nullptr, stream);
+}
+
+extern "C" int gswmtp_design_loss_record_device(const float *dev_I, const float *dev_target,
+                                                int n, double n_ap, double sum_a2,
+                                                double eta_weight, float *dev_loss,
+                                                float *dev_dI, float *dev_hist, int hist_cap,
+                                                float *dev_step, void *stream) {
+  if (!dev_step || hist_cap < 0 || (hist_cap > 0 && !dev_hist)) return GSWMTP_E_INVAL;
+  return design_loss(dev_I, dev_target, n, n_ap, sum_a2, eta_weight, dev_loss, dev_dI, dev_hist,
+                     hist_cap, dev_step, stream);
 }
 
 extern "C" int gswmtp_adam_step_device(float *phi, const float *grad, float *m, float *v,

@@ -555,11 +555,13 @@ __global__ void grid_scatter(const float *__restrict__ tn, float scale, const in
 
 // Theta_n from the gather partials alone (operator-level forward calls, and
 // the field of the current phase when no statistics are asked for), and
-// optionally I_n = |Theta_n|^2.  The partials are added in ascending order
-// and scaled as the focus update does, so both give the same values.
+// optionally I_n = |Theta_n|^2; theta2 / intensity2 (optional) take second
+// copies.  The partials are added in ascending order and scaled as the focus
+// update does, so both give the same values.
 __global__ void gather_reduce(const float *__restrict__ gpart, int T, int nf, int ldp,
                               float scale, float *__restrict__ theta,
-                              float *__restrict__ intensity) {
+                              float *__restrict__ intensity, float *__restrict__ theta2,
+                              float *__restrict__ intensity2) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nf) return;
   float sr = 0.f, si = 0.f;
@@ -572,7 +574,15 @@ __global__ void gather_reduce(const float *__restrict__ gpart, int T, int nf, in
   si *= scale;
   theta[2 * n] = sr;
   theta[2 * n + 1] = si;
-  if (intensity) intensity[n] = (float)((double)sr * sr + (double)si * si);
+  if (theta2) {
+    theta2[2 * n] = sr;
+    theta2[2 * n + 1] = si;
+  }
+  if (intensity || intensity2) {
+    const float I = (float)((double)sr * sr + (double)si * si);
+    if (intensity) intensity[n] = I;
+    if (intensity2) intensity2[n] = I;
+  }
 }
 
 // Focal values for the phase gradient: g_n Theta_n.
@@ -922,15 +932,16 @@ hipError_t launch_scatter_split_grouped(const void *items, const int *starts, in
 hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s) {
   const int nf = p->d.nf;
   hipLaunchKernelGGL(gather_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.gpart,
-                     gather_partials(p), nf, gather_ld(p), scale, theta, nullptr);
+                     gather_partials(p), nf, gather_ld(p), scale, theta, nullptr, nullptr,
+                     nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_field(const gswmtp_plan *p, hipStream_t s) {
+hipError_t launch_field(const gswmtp_plan *p, hipStream_t s, float *field, float *intensity) {
   const int nf = p->d.nf;
   hipLaunchKernelGGL(gather_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.gpart,
                      gather_partials(p), nf, gather_ld(p), std::ldexp(1.f, -p->amp_exp),
-                     p->b.theta, p->b.intensity);
+                     p->b.theta, p->b.intensity, field, intensity);
   return hipGetLastError();
 }
 

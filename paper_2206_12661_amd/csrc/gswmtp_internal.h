@@ -461,8 +461,10 @@ hipError_t launch_cgemm(const gswmtp_plan *p, bool forward, int epi, const float
                         const float *ei, bool honour_done, hipStream_t s, int phases = 3);
 hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale, hipStream_t s);
 // Theta and |Theta|^2 of the current forward's gather partials into the
-// plan's theta and intensity (no statistics, one launch).
-hipError_t launch_field(const gswmtp_plan *p, hipStream_t s);
+// plan's theta and intensity, and into field / intensity when not null (no
+// statistics, one launch).
+hipError_t launch_field(const gswmtp_plan *p, hipStream_t s, float *field = nullptr,
+                        float *intensity = nullptr);
 GatherCtx gather_ctx(const gswmtp_plan *p);
 hipError_t launch_cgemm_split(const gswmtp_plan *p, bool forward, int epi,
                               const unsigned short *bt, float *cr, float *ci,

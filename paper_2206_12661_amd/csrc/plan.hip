@@ -1615,13 +1615,19 @@ int gswmtp_get_foci_field_device(gswmtp_plan *p, float *dev_field, float *dev_in
   if (!p || (!dev_field && !dev_intensity)) return GSWMTP_E_INVAL;
   DeviceGuard g(p->device);
   HIP_TRY(p, enter(p));
-  HIP_TRY(p, ensure_forward(p, false));
-  const size_t nf = p->d.nf;
-  if (dev_field)
-    HIP_TRY(p, hipMemcpyAsync(dev_field, p->b.theta, 8 * nf, hipMemcpyDeviceToDevice, p->stream));
-  if (dev_intensity)
-    HIP_TRY(p, hipMemcpyAsync(dev_intensity, p->b.intensity, 4 * nf, hipMemcpyDeviceToDevice,
-                              p->stream));
+  if (!p->fwd_valid) {   // the forward's field kernel writes the caller's buffers too
+    HIP_TRY(p, stage_forward(p, false, p->stream));
+    HIP_TRY(p, launch_field(p, p->stream, dev_field, dev_intensity));
+    p->fwd_valid = true;
+  } else {
+    const size_t nf = p->d.nf;
+    if (dev_field)
+      HIP_TRY(p, hipMemcpyAsync(dev_field, p->b.theta, 8 * nf, hipMemcpyDeviceToDevice,
+                                p->stream));
+    if (dev_intensity)
+      HIP_TRY(p, hipMemcpyAsync(dev_intensity, p->b.intensity, 4 * nf, hipMemcpyDeviceToDevice,
+                                p->stream));
+  }
   HIP_TRY(p, leave(p));
   return GSWMTP_OK;
 }

@@ -261,3 +261,8 @@ def test_design_loss_validation(lib):
     assert call(p, p, 4, 0.0, 10.0, 0.1, p, p, None) == -1
     assert call(p, p, 4, 10.0, -1.0, 0.1, p, p, None) == -1
     assert call(p, p, 4, 10.0, 10.0, math.inf, p, p, None) == -1
+    rec = lambda *a: lib.gswmtp_design_loss_record_device(*a)  # noqa: E731
+    assert rec(p, p, 4, 10.0, 10.0, 0.1, p, p, p, 4, None, None) == -1   # no step counter
+    assert rec(p, p, 4, 10.0, 10.0, 0.1, p, p, p, -1, p, None) == -1    # negative capacity
+    assert rec(p, p, 4, 10.0, 10.0, 0.1, p, p, None, 4, p, None) == -1  # no history buffer
+    assert rec(p, p, 0, 10.0, 10.0, 0.1, p, p, p, 4, p, None) == -1     # the loss's own checks
