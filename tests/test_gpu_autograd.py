@@ -162,6 +162,32 @@ def test_design_loss_fused_against_oracle(g, n):
     assert rel_l2(It2.grad.cpu().numpy(), dI_o) <= 1e-3   # the float32 torch form
 
 
+def test_design_loss_record_keeps_the_books(g):
+    """gswmtp_design_loss_record_device: the same loss and dL/dI as the plain
+    entry point, the loss written to hist[step] while step < capacity, and
+    the step counter advanced by one on every call (capacity 2, three calls:
+    the third loss is not recorded)."""
+    import torch
+    from paper_2206_12661_amd.autograd import _loss_and_gradient
+    announce("design loss with the loop's books")
+    rng = np.random.default_rng(7)
+    n_ap, sum_a2 = 4096, 4096.0
+    hist = torch.full((2,), -7.0, dtype=torch.float32, device="cuda")
+    step = torch.zeros(1, dtype=torch.float32, device="cuda")
+    Tt = torch.tensor(rng.uniform(0.5, 1.0, 300).astype(np.float32), device="cuda")
+    losses = []
+    for k in range(3):
+        It = torch.tensor(rng.uniform(0.0, 2.0, 300).astype(np.float32), device="cuda")
+        L0, d0 = _loss_and_gradient(It, Tt, n_ap, sum_a2, 0.1)
+        L1, d1 = _loss_and_gradient(It, Tt, n_ap, sum_a2, 0.1, hist, step)
+        assert torch.equal(L0, L1) and torch.equal(d0, d1)
+        assert float(step) == k + 1
+        losses.append(float(L1))
+    h = hist.cpu().numpy()
+    assert h[0] == np.float32(losses[0]) and h[1] == np.float32(losses[1])
+    assert losses[2] not in h.tolist()
+
+
 @pytest.mark.parametrize("n", [300001, 300000])
 def test_adam_kernel_matches_torch_adam(g, n):
     """The library's Adam step against torch.optim.Adam (float32, the same
