@@ -542,15 +542,47 @@ __global__ void grid_gather(const float *__restrict__ gr, const float *__restric
 }
 
 // Grid form of the scatter: Theta'_n onto the transposed grid at (ic_n, ir_n);
-// every other entry of the grid stays zero from plan creation.
+// every other entry of the grid stays zero from plan creation.  With g (the
+// phase gradient's focal weights) the value placed is g_n Theta_n, the same
+// product grad_field forms.
 __global__ void grid_scatter(const float *__restrict__ tn, float scale, const int *__restrict__ ir,
                              const int *__restrict__ ic, int nf, float *__restrict__ tr,
-                             float *__restrict__ ti, int ldt) {
+                             float *__restrict__ ti, int ldt, const float *__restrict__ g) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nf) return;
   const size_t o = (size_t)ic[n] * ldt + ir[n];
-  tr[o] = tn[2 * n] * scale;
-  ti[o] = tn[2 * n + 1] * scale;
+  float a = tn[2 * n], b = tn[2 * n + 1];
+  if (g) {
+    a = g[n] * a;
+    b = g[n] * b;
+  }
+  tr[o] = a * scale;
+  ti[o] = b * scale;
+}
+
+// Grid form of the focus field: Theta_n = G[ir_n][ic_n] (scaled) and I_n,
+// the values grid_gather and gather_reduce give (one partial from zero).
+__global__ void grid_field(const float *__restrict__ gr, const float *__restrict__ gi, int ldg,
+                           const int *__restrict__ ir, const int *__restrict__ ic, int nf,
+                           float scale, float *__restrict__ theta, float *__restrict__ intensity,
+                           float *__restrict__ theta2, float *__restrict__ intensity2) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nf) return;
+  const size_t o = (size_t)ir[n] * ldg + ic[n];
+  float sr = 0.f, si = 0.f;
+  sr += gr[o];
+  si += gi[o];
+  sr *= scale;
+  si *= scale;
+  theta[2 * n] = sr;
+  theta[2 * n + 1] = si;
+  if (theta2) {
+    theta2[2 * n] = sr;
+    theta2[2 * n + 1] = si;
+  }
+  const float I = (float)((double)sr * sr + (double)si * si);
+  intensity[n] = I;
+  if (intensity2) intensity2[n] = I;
 }
 
 // Theta_n from the gather partials alone (operator-level forward calls, and
@@ -938,10 +970,17 @@ hipError_t launch_gather_reduce(const gswmtp_plan *p, float *theta, float scale,
 }
 
 hipError_t launch_field(const gswmtp_plan *p, hipStream_t s, float *field, float *intensity) {
-  const int nf = p->d.nf;
-  hipLaunchKernelGGL(gather_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.gpart,
-                     gather_partials(p), nf, gather_ld(p), std::ldexp(1.f, -p->amp_exp),
-                     p->b.theta, p->b.intensity, field, intensity);
+  const Dims &d = p->d;
+  const int nf = d.nf;
+  const float scale = std::ldexp(1.f, -p->amp_exp);
+  if (p->grid_form)   // straight from the dense grid (the forward skipped its gather)
+    hipLaunchKernelGGL(grid_field, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.g_r, p->b.g_i,
+                       d.Ucp, d.axis == 0 ? p->b.iy : p->b.ix, d.axis == 0 ? p->b.ix : p->b.iy,
+                       nf, scale, p->b.theta, p->b.intensity, field, intensity);
+  else
+    hipLaunchKernelGGL(gather_reduce, dim3((nf + 255) / 256), dim3(256), 0, s, p->b.gpart,
+                       gather_partials(p), nf, gather_ld(p), scale, p->b.theta, p->b.intensity,
+                       field, intensity);
   return hipGetLastError();
 }
 
@@ -960,11 +999,11 @@ hipError_t launch_grid_gather(const gswmtp_plan *p, hipStream_t s) {
 }
 
 hipError_t launch_grid_scatter(const gswmtp_plan *p, const float *theta_new, float scale,
-                               hipStream_t s) {
+                               hipStream_t s, const float *g) {
   const Dims &d = p->d;
   hipLaunchKernelGGL(grid_scatter, dim3((d.nf + 255) / 256), dim3(256), 0, s, theta_new, scale,
                      d.axis == 0 ? p->b.iy : p->b.ix, d.axis == 0 ? p->b.ix : p->b.iy, d.nf,
-                     p->b.tg_r, p->b.tg_i, d.Urp);
+                     p->b.tg_r, p->b.tg_i, d.Urp, g);
   return hipGetLastError();
 }
 

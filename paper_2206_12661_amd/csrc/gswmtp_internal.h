@@ -498,10 +498,11 @@ hipError_t launch_cgemm_split_ex(const gswmtp_plan *p, const GemmSched &sc,
 hipError_t launch_split_transpose(const gswmtp_plan *p, const float *sr, const float *si,
                                   float scale, bool honour_done, hipStream_t s);
 // Grid form: Theta_n = G[ir_n][ic_n] into the gather partials (one per focus);
-// Theta'_n onto the transposed grid at (ic_n, ir_n).
+// Theta'_n (times g_n when g is not null) onto the transposed grid at
+// (ic_n, ir_n).
 hipError_t launch_grid_gather(const gswmtp_plan *p, hipStream_t s);
 hipError_t launch_grid_scatter(const gswmtp_plan *p, const float *theta_new, float scale,
-                               hipStream_t s);
+                               hipStream_t s, const float *g = nullptr);
 // Gather partials per focus of the plan's forward form.
 int gather_partials(const gswmtp_plan *p);
 int gather_ld(const gswmtp_plan *p);   // gather partial row stride: nf rounded up to even

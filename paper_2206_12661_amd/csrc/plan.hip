@@ -753,7 +753,7 @@ bool is_split(const gswmtp_plan *p) { return split_terms_of(p->precision) > 0; }
 // Split grid form, forward: L^T = P^T Omega_r^T on the 16-bit matrix cores
 // (pt: the split planes of P^T), then the float32 grid product and gather.
 hipError_t split_grid_forward(gswmtp_plan *p, const unsigned short *pt, bool done,
-                              hipStream_t s) {
+                              hipStream_t s, bool gather = true) {
   const Dims &D = p->d;
   Bufs &b = p->b;
   hipError_t e = launch_cgemm_split_ex(p, p->sched_f1, pt, D.Cp, b.as_f, D.Urp, D.Rp, b.lt_r,
@@ -761,12 +761,14 @@ hipError_t split_grid_forward(gswmtp_plan *p, const unsigned short *pt, bool don
   if (e != hipSuccess) return e;
   e = launch_cgemm_ex(p, p->sched_f2, b.lt_r, b.lt_i, D.Urp, b.wt_r, b.wt_i, D.Ucp, b.g_r, b.g_i,
                       D.Ucp, D.Urp, D.Ucp, D.Cp, EPI_STORE, done, s);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !gather) return e;
   return launch_grid_gather(p, s);
 }
 
+// gather = false (grid form only): leave the dense grid G without gathering
+// the foci from it (launch_field reads them from G).
 hipError_t forward_products(gswmtp_plan *p, const float *er, const float *ei, bool done,
-                            hipStream_t s) {
+                            hipStream_t s, bool gather = true) {
   if (!p->grid_form)
     return launch_cgemm(p, true, EPI_GATHER, er, ei, nullptr, nullptr, nullptr, nullptr, done, s);
   const Dims &D = p->d;
@@ -776,7 +778,7 @@ hipError_t forward_products(gswmtp_plan *p, const float *er, const float *ei, bo
   if (e != hipSuccess) return e;
   e = launch_cgemm_ex(p, p->sched_f2, b.lt_r, b.lt_i, D.Urp, b.wt_r, b.wt_i, D.Ucp, b.g_r, b.g_i,
                       D.Ucp, D.Urp, D.Ucp, D.Cp, EPI_STORE, done, s);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !gather) return e;
   return launch_grid_gather(p, s);
 }
 
@@ -784,11 +786,11 @@ hipError_t forward_products(gswmtp_plan *p, const float *er, const float *ei, bo
 // row of foci (gather form) or as the product Theta'_grid conj(Omega_c)
 // (grid form).
 hipError_t scatter_products(gswmtp_plan *p, const float *theta, bool done, hipStream_t s,
-                            float scale = 1.f) {
+                            float scale = 1.f, const float *g = nullptr) {
   if (!p->grid_form) return launch_scatter(p, theta, done, s);
   const Dims &D = p->d;
   Bufs &b = p->b;
-  hipError_t e = launch_grid_scatter(p, theta, scale, s);
+  hipError_t e = launch_grid_scatter(p, theta, scale, s, g);
   if (e != hipSuccess) return e;
   return launch_cgemm_ex(p, p->sched_a1, b.tg_r, b.tg_i, D.Urp, b.wc_r, b.wn_i, D.Cp, b.s_r,
                          b.s_i, D.Cp, D.Urp, D.Cp, D.Ucp, EPI_STORE, done, s);
@@ -803,11 +805,12 @@ hipError_t split_grid_scatter(gswmtp_plan *p, const float *theta, float scale, b
   return launch_split_transpose(p, p->b.s_r, p->b.s_i, 1.f, done, s);
 }
 
-hipError_t stage_forward(gswmtp_plan *p, bool done, hipStream_t s) {
-  if (is_split(p) && p->grid_form) return split_grid_forward(p, p->b.ps, done, s);
+// gather = false: the grid form leaves the focus gather to launch_field.
+hipError_t stage_forward(gswmtp_plan *p, bool done, hipStream_t s, bool gather = true) {
+  if (is_split(p) && p->grid_form) return split_grid_forward(p, p->b.ps, done, s, gather);
   if (is_split(p))
     return launch_cgemm_split(p, true, EPI_GATHER, p->b.ps, nullptr, nullptr, nullptr, done, s);
-  return forward_products(p, p->b.p_r, p->b.p_i, done, s);
+  return forward_products(p, p->b.p_r, p->b.p_i, done, s, gather);
 }
 hipError_t stage_scatter(gswmtp_plan *p, bool done, hipStream_t s) {
   if (p->scaled_adj) return launch_scale_adjoint_split(p, done, s);
@@ -844,7 +847,7 @@ hipError_t enqueue_pass(gswmtp_plan *p, hipStream_t s) {
 hipError_t ensure_forward(gswmtp_plan *p, bool stats) {
   if (stats ? p->stats_valid : p->fwd_valid) return hipSuccess;
   hipError_t e;
-  if ((e = stage_forward(p, false, p->stream)) != hipSuccess) return e;
+  if ((e = stage_forward(p, false, p->stream, stats)) != hipSuccess) return e;
   if (stats) {
     if ((e = launch_update(p, UPD_STATS, p->stream)) != hipSuccess) return e;
     p->stats_valid = true;
@@ -1616,7 +1619,7 @@ int gswmtp_get_foci_field_device(gswmtp_plan *p, float *dev_field, float *dev_in
   DeviceGuard g(p->device);
   HIP_TRY(p, enter(p));
   if (!p->fwd_valid) {   // the forward's field kernel writes the caller's buffers too
-    HIP_TRY(p, stage_forward(p, false, p->stream));
+    HIP_TRY(p, stage_forward(p, false, p->stream, false));
     HIP_TRY(p, launch_field(p, p->stream, dev_field, dev_intensity));
     p->fwd_valid = true;
   } else {
@@ -1888,8 +1891,12 @@ int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_
   HIP_TRY(p, enter(p));
   hipStream_t s = p->stream;
   HIP_TRY(p, ensure_forward(p, false));
-  HIP_TRY(p, launch_grad_field(p, dev_g, s));
-  HIP_TRY(p, scatter_products(p, p->b.theta_new, false, s));
+  if (p->grid_form) {   // g Theta formed by the grid scatter itself
+    HIP_TRY(p, scatter_products(p, p->b.theta, false, s, 1.f, dev_g));
+  } else {
+    HIP_TRY(p, launch_grad_field(p, dev_g, s));
+    HIP_TRY(p, scatter_products(p, p->b.theta_new, false, s));
+  }
   HIP_TRY(p, launch_cgemm(p, false, EPI_GRAD, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i, p->b.p_r,
                           p->b.p_i, false, s));
   hipLaunchKernelGGL(k_expand_real, grid1((size_t)D.ny * D.nx), dim3(256), 0, s, p->b.x_r,
