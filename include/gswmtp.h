@@ -326,6 +326,15 @@ int gswmtp_forward_field_noalloc(gswmtp_plan *p, const float *E, float *theta);
  * with Theta the field of the current phase.  dev_g: device float [n_foci];
  * dev_grad: device float [ny*nx] (0 outside the aperture).  Stream-ordered. */
 int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad);
+/* That gradient applied at once by one Adam step (the update of
+ * gswmtp_adam_step_device, same arguments and errors) to the user-layout
+ * phases phi and moments m, v (device float [ny*nx], in place), with the step
+ * number t read from dev_step: the Adam kernel reads the gradient where the
+ * adjoint product left it, so no gradient array is written or read.  The
+ * same values as the two calls in a row, bit for bit.  Stream-ordered. */
+int gswmtp_phase_gradient_adam_device(gswmtp_plan *p, const float *dev_g, float *phi, float *m,
+                                      float *v, const float *dev_step, double lr, double beta1,
+                                      double beta2, double eps);
 
 /* The design loss of the differentiable form and its gradient in the
  * intensities, for the n foci intensities dev_I and targets dev_target (device

@@ -111,6 +111,9 @@ _SIGNATURES = {
     "gswmtp_forward_field_noalloc": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_adjoint_field": ([_P, _P, _P], ctypes.c_int),
     "gswmtp_phase_gradient_device": ([_P, _P, _P], ctypes.c_int),
+    "gswmtp_phase_gradient_adam_device": ([_P, _P, _P, _P, _P, _P, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double],
+                                          ctypes.c_int),
     "gswmtp_design_loss_device": ([_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, _P, _P, _P], ctypes.c_int),
     "gswmtp_design_loss_record_device": ([_P, _P, ctypes.c_int, ctypes.c_double,
@@ -466,6 +469,26 @@ class Plan:
         self._check(self._lib.gswmtp_phase_gradient_device(self._h, g.data_ptr(),
                                                             out.data_ptr()))
         return out
+
+    def phase_gradient_adam_device(self, g: torch.Tensor, phi: torch.Tensor, m: torch.Tensor,
+                                   v: torch.Tensor, step: torch.Tensor, lr: float,
+                                   betas=(0.9, 0.999), eps: float = 1e-8):
+        """The phase gradient of L = sum g_n |Theta_n|^2 at the current phase
+        applied at once by one Adam step to phi, m, v (contiguous float32 CUDA
+        tensors of ny * nx values, in place); ``step`` holds the step number
+        (one float32 CUDA value)."""
+        g = g.detach().to(torch.float32).contiguous()
+        assert g.is_cuda and g.numel() == self.n_foci
+        for t in (phi, m, v):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and
+                    t.numel() == self.ny * self.nx):
+                raise TypeError("phi, m, v must be contiguous float32 CUDA tensors of ny*nx")
+        if not (step.is_cuda and step.dtype == torch.float32 and step.numel() == 1):
+            raise TypeError("step must be one float32 CUDA value")
+        self._sync_stream()
+        self._check(self._lib.gswmtp_phase_gradient_adam_device(
+            self._h, g.data_ptr(), phi.data_ptr(), m.data_ptr(), v.data_ptr(), step.data_ptr(),
+            float(lr), float(betas[0]), float(betas[1]), float(eps)))
 
     # -- profiling ---------------------------------------------------------
     def time_stages(self, n_iter: int) -> dict:

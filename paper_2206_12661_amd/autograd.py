@@ -117,15 +117,18 @@ def design_loss_fused(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2: 
 def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: float = 1e-8,
                 eta_weight: float = 0.1, phi0=None, target=None, graph: bool = True):
     """Phase design by gradient descent: Adam on ``design_loss`` of the plan's
-    foci intensities, the update in the library's kernel
-    (``adam_step_device``).  Returns (phi [ny, nx] float32 CUDA tensor, loss
+    foci intensities, the update in the library's Adam kernel (the update
+    of ``adam_step_device``).  Returns (phi [ny, nx] float32 CUDA tensor, loss
     before each step [steps] tensor).
 
     A step is the chain rule that ``foci_intensity`` and ``design_loss_fused``
     run under autograd, called directly: the forward to I, the loss kernel
     with dL/dI, the phase gradient of that dL/dI (``MTPIntensity``'s
-    backward), so no seed gradient or scaling by it (autograd's seed is 1.0:
-    the same gradient bit for bit).
+    backward) applied by Adam in the same library call
+    (``Plan.phase_gradient_adam_device``: the update reads the gradient where
+    the adjoint product leaves it), so no seed gradient or scaling by it
+    (autograd's seed is 1.0: the same gradient bit for bit) and no gradient
+    array.
 
     graph=True captures one whole step - the phase encode, the forward product
     with the focus gather, the loss and its gradient, the adjoint product with
@@ -138,7 +141,6 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
     buffers) is undone before capture, and both forms give the same
     trajectory.
     graph=False runs the same step eagerly."""
-    from . import adam_step_device
     idx = plan.index()
     n_ap, sum_a2 = idx["n_aperture"], idx["sum_a2"]
     if target is None:
@@ -162,8 +164,7 @@ def adam_design(plan, steps: int, lr: float = 0.05, betas=(0.9, 0.999), eps: flo
         # the loss kernel records L in hist[count] and advances count, which is
         # then this step's number t for Adam
         _, dI = _loss_and_gradient(inten, t, n_ap, sum_a2, eta_weight, hist, count)
-        gphi = plan.phase_gradient_device(dI)
-        adam_step_device(phi, gphi, m, v, count, lr, betas, eps)
+        plan.phase_gradient_adam_device(dI, phi, m, v, count, lr, betas, eps)
 
     if not graph or steps == 0:
         for _ in range(steps):

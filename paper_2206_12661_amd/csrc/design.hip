@@ -9,27 +9,28 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "adam_update.h"
 #include "gswmtp_internal.h"
 
 namespace {
 
-// Kingma and Ba's update with bias-corrected moments, in float32:
-//   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
-//   phi -= (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+using gswmtp::adam_apply;
+using gswmtp::adam_scalars;
+
+// Kingma and Ba's update with bias-corrected moments (adam_update.h), one
+// value per thread.
 __global__ __launch_bounds__(256) void k_adam(float *phi, const float *grad, float *m, float *v,
                                               const float *step, size_t n, float lr, float b1,
                                               float b2, float eps) {
-  const float t = *step;
-  const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
-  const float step_size = lr / bc1, rbc2 = 1.f / sqrtf(bc2);
+  float step_size, rbc2;
+  adam_scalars(*step, lr, b1, b2, step_size, rbc2);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
-    const float g = grad[i];
-    const float mi = b1 * m[i] + (1.f - b1) * g;
-    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    float mi = m[i], vi = v[i], p = phi[i];
+    adam_apply(p, mi, vi, grad[i], b1, b2, step_size, rbc2, eps);
     m[i] = mi;
     v[i] = vi;
-    phi[i] -= step_size * mi / (sqrtf(vi) * rbc2 + eps);
+    phi[i] = p;
   }
 }
 
@@ -38,22 +39,16 @@ __global__ __launch_bounds__(256) void k_adam(float *phi, const float *grad, flo
 __global__ __launch_bounds__(256) void k_adam4(float4 *phi, const float4 *grad, float4 *m,
                                                float4 *v, const float *step, size_t n4,
                                                float lr, float b1, float b2, float eps) {
-  const float t = *step;
-  const float bc1 = 1.f - powf(b1, t), bc2 = 1.f - powf(b2, t);
-  const float step_size = lr / bc1, rbc2 = 1.f / sqrtf(bc2);
+  float step_size, rbc2;
+  adam_scalars(*step, lr, b1, b2, step_size, rbc2);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
        i += (size_t)gridDim.x * blockDim.x) {
     const float4 g = grad[i];
     float4 mi = m[i], vi = v[i], p = phi[i];
-#define ADAM_LANE(c)                                                                        \
-  mi.c = b1 * mi.c + (1.f - b1) * g.c;                                                      \
-  vi.c = b2 * vi.c + (1.f - b2) * g.c * g.c;                                                \
-  p.c -= step_size * mi.c / (sqrtf(vi.c) * rbc2 + eps);
-    ADAM_LANE(x)
-    ADAM_LANE(y)
-    ADAM_LANE(z)
-    ADAM_LANE(w)
-#undef ADAM_LANE
+    adam_apply(p.x, mi.x, vi.x, g.x, b1, b2, step_size, rbc2, eps);
+    adam_apply(p.y, mi.y, vi.y, g.y, b1, b2, step_size, rbc2, eps);
+    adam_apply(p.z, mi.z, vi.z, g.z, b1, b2, step_size, rbc2, eps);
+    adam_apply(p.w, mi.w, vi.w, g.w, b1, b2, step_size, rbc2, eps);
     m[i] = mi;
     v[i] = vi;
     phi[i] = p;

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <algorithm>
@@ -18,6 +19,7 @@
 #include <new>
 #include <vector>
 
+#include "adam_update.h"
 #include "gswmtp_internal.h"
 
 using namespace gswmtp;
@@ -474,6 +476,57 @@ __global__ void k_expand_complex(const float *xr, const float *xi, const int *ro
   }
   out[2 * id] = re;
   out[2 * id + 1] = im;
+}
+
+// Adam on user-layout phases (adam_update.h) with the gradient read from the
+// internal real plane in place (0 where compacted): the expansion of
+// k_expand_real and the update of the library's Adam kernel in one pass.
+// Grid-stride over groups of VEC values (VEC = 4: 16-byte accesses of phi, m
+// and v, which the caller has checked are aligned and a multiple of 4 long).
+__device__ __forceinline__ float internal_value(const float *xr, const int *row_pos,
+                                                const int *col_pos, int axis, int nx, int Cp,
+                                                size_t id) {
+  int r, c;
+  if (internal_of(row_pos, col_pos, axis, (int)(id / nx), (int)(id % nx), &r, &c))
+    return xr[(size_t)r * Cp + c];
+  return 0.f;
+}
+
+template <int VEC>
+__global__ __launch_bounds__(256) void k_adam_internal(const float *xr, const int *row_pos,
+                                                       const int *col_pos, int axis, int ny,
+                                                       int nx, int Cp, float *phi, float *m,
+                                                       float *v, const float *step, float lr,
+                                                       float b1, float b2, float eps) {
+  float step_size, rbc2;
+  adam_scalars(*step, lr, b1, b2, step_size, rbc2);
+  const size_t n = (size_t)ny * nx / VEC;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    if constexpr (VEC == 4) {
+      float4 p = reinterpret_cast<float4 *>(phi)[i], mi = reinterpret_cast<float4 *>(m)[i],
+             vi = reinterpret_cast<float4 *>(v)[i];
+      const size_t id = 4 * i;
+      adam_apply(p.x, mi.x, vi.x, internal_value(xr, row_pos, col_pos, axis, nx, Cp, id), b1,
+                 b2, step_size, rbc2, eps);
+      adam_apply(p.y, mi.y, vi.y, internal_value(xr, row_pos, col_pos, axis, nx, Cp, id + 1),
+                 b1, b2, step_size, rbc2, eps);
+      adam_apply(p.z, mi.z, vi.z, internal_value(xr, row_pos, col_pos, axis, nx, Cp, id + 2),
+                 b1, b2, step_size, rbc2, eps);
+      adam_apply(p.w, mi.w, vi.w, internal_value(xr, row_pos, col_pos, axis, nx, Cp, id + 3),
+                 b1, b2, step_size, rbc2, eps);
+      reinterpret_cast<float4 *>(phi)[i] = p;
+      reinterpret_cast<float4 *>(m)[i] = mi;
+      reinterpret_cast<float4 *>(v)[i] = vi;
+    } else {
+      float p = phi[i], mi = m[i], vi = v[i];
+      adam_apply(p, mi, vi, internal_value(xr, row_pos, col_pos, axis, nx, Cp, i), b1, b2,
+                 step_size, rbc2, eps);
+      phi[i] = p;
+      m[i] = mi;
+      v[i] = vi;
+    }
+  }
 }
 
 // Internal real plane -> user layout (zero where compacted).
@@ -1882,13 +1935,9 @@ int gswmtp_adjoint_field(gswmtp_plan *p, const float *theta, float *E) {
   return GSWMTP_OK;
 }
 
-int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad) {
-  if (!p || !dev_g || !dev_grad) return GSWMTP_E_INVAL;
-  if (is_split(p))
-    return fail(p, GSWMTP_E_UNSUPPORTED, "phase gradient is built for FP32 plans only");
-  DeviceGuard g(p->device);
-  const Dims &D = p->d;
-  HIP_TRY(p, enter(p));
+// The phase gradient into the internal real plane x_r (both gradient entry
+// points; the caller has entered the plan's stream).
+static int phase_gradient_internal(gswmtp_plan *p, const float *dev_g) {
   hipStream_t s = p->stream;
   HIP_TRY(p, ensure_forward(p, false));
   if (p->grid_form) {   // g Theta formed by the grid scatter itself
@@ -1899,8 +1948,52 @@ int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_
   }
   HIP_TRY(p, launch_cgemm(p, false, EPI_GRAD, p->b.s_r, p->b.s_i, p->b.x_r, p->b.x_i, p->b.p_r,
                           p->b.p_i, false, s));
-  hipLaunchKernelGGL(k_expand_real, grid1((size_t)D.ny * D.nx), dim3(256), 0, s, p->b.x_r,
+  return GSWMTP_OK;
+}
+
+int gswmtp_phase_gradient_device(gswmtp_plan *p, const float *dev_g, float *dev_grad) {
+  if (!p || !dev_g || !dev_grad) return GSWMTP_E_INVAL;
+  if (is_split(p))
+    return fail(p, GSWMTP_E_UNSUPPORTED, "phase gradient is built for FP32 plans only");
+  DeviceGuard g(p->device);
+  const Dims &D = p->d;
+  HIP_TRY(p, enter(p));
+  const int rc = phase_gradient_internal(p, dev_g);
+  if (rc != GSWMTP_OK) return rc;
+  hipLaunchKernelGGL(k_expand_real, grid1((size_t)D.ny * D.nx), dim3(256), 0, p->stream, p->b.x_r,
                      p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, dev_grad);
+  HIP_TRY(p, hipGetLastError());
+  HIP_TRY(p, leave(p));
+  return GSWMTP_OK;
+}
+
+int gswmtp_phase_gradient_adam_device(gswmtp_plan *p, const float *dev_g, float *phi, float *m,
+                                      float *v, const float *dev_step, double lr, double beta1,
+                                      double beta2, double eps) {
+  if (!p || !dev_g || !phi || !m || !v || !dev_step) return GSWMTP_E_INVAL;
+  if (!std::isfinite(lr) || !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) ||
+      !(eps >= 0.0) || !std::isfinite(eps))
+    return GSWMTP_E_INVAL;
+  if (is_split(p))
+    return fail(p, GSWMTP_E_UNSUPPORTED, "phase gradient is built for FP32 plans only");
+  DeviceGuard g(p->device);
+  const Dims &D = p->d;
+  HIP_TRY(p, enter(p));
+  const int rc = phase_gradient_internal(p, dev_g);
+  if (rc != GSWMTP_OK) return rc;
+  const size_t np = (size_t)D.ny * D.nx;
+  const auto aligned = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  const bool vec = np % 4 == 0 && aligned(phi) && aligned(m) && aligned(v);
+  const size_t groups = vec ? np / 4 : np;
+  const dim3 grid((unsigned)std::min<size_t>((groups + 255) / 256, 8192));
+  if (vec)
+    hipLaunchKernelGGL(k_adam_internal<4>, grid, dim3(256), 0, p->stream, p->b.x_r,
+                       p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, phi, m, v,
+                       dev_step, (float)lr, (float)beta1, (float)beta2, (float)eps);
+  else
+    hipLaunchKernelGGL(k_adam_internal<1>, grid, dim3(256), 0, p->stream, p->b.x_r,
+                       p->b.row_pos, p->b.col_pos, D.axis, D.ny, D.nx, D.Cp, phi, m, v,
+                       dev_step, (float)lr, (float)beta1, (float)beta2, (float)eps);
   HIP_TRY(p, hipGetLastError());
   HIP_TRY(p, leave(p));
   return GSWMTP_OK;

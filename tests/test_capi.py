@@ -248,6 +248,22 @@ def test_adam_step_validation(lib):
     assert call(p, p, p, p, p, 4, 0.05, 0.9, 0.999, -1.0, None) == -1
 
 
+def test_phase_gradient_adam_validation(lib):
+    """The fused gradient + Adam entry point rejects a null plan or pointer
+    and bad hyper-parameters on the host (no GPU needed)."""
+    P = ctypes.c_void_p
+    buf = (ctypes.c_float * 4)()
+    p = ctypes.cast(buf, P)
+    call = lambda *a: lib.gswmtp_phase_gradient_adam_device(*a)  # noqa: E731
+    assert call(None, p, p, p, p, p, 0.05, 0.9, 0.999, 1e-8) == -1
+    fake = p   # never dereferenced: every case below fails before the plan is used
+    assert call(fake, None, p, p, p, p, 0.05, 0.9, 0.999, 1e-8) == -1
+    assert call(fake, p, p, p, p, None, 0.05, 0.9, 0.999, 1e-8) == -1
+    assert call(fake, p, p, p, p, p, math.nan, 0.9, 0.999, 1e-8) == -1
+    assert call(fake, p, p, p, p, p, 0.05, 1.0, 0.999, 1e-8) == -1
+    assert call(fake, p, p, p, p, p, 0.05, 0.9, 0.999, -1.0) == -1
+
+
 def test_design_loss_validation(lib):
     """The fused design-loss entry point rejects bad sizes and pointers on the
     host (no GPU needed)."""

@@ -162,6 +162,40 @@ def test_design_loss_fused_against_oracle(g, n):
     assert rel_l2(It2.grad.cpu().numpy(), dI_o) <= 1e-3   # the float32 torch form
 
 
+@pytest.mark.parametrize("shape", [(130, 200), (131, 199)])
+def test_phase_gradient_adam_equals_the_two_calls(g, shape):
+    """gswmtp_phase_gradient_adam_device against gswmtp_phase_gradient_device
+    followed by gswmtp_adam_step_device (its 16-byte kernel for 130 x 200, the
+    one-value kernel for 131 x 199): phases and moments bit for bit over
+    three steps, on a disc whose compacted-away border rows and columns take
+    a zero gradient."""
+    import torch
+    ny, nx = shape
+    h = synth_ofa.random_case(11, ny, nx, 45, radius=60.0)
+    announce(f"phase gradient + Adam in one call {ny}x{nx}")
+    rng = np.random.default_rng(5)
+    bits = lambda t: t.view(torch.int32).cpu().numpy()  # noqa: E731
+    with g.Plan(h) as p:
+        assert len(p.index()["rows"]) < ny and len(p.index()["cols"]) < nx
+        phi_a = torch.tensor(np.asarray(h.phi0, np.float32).reshape(-1), device="cuda")
+        phi_b = phi_a.clone()
+        m_a, v_a = torch.zeros_like(phi_a), torch.zeros_like(phi_a)
+        m_b, v_b = m_a.clone(), v_a.clone()
+        step = torch.zeros(1, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            step += 1.0
+            gv = torch.tensor(rng.standard_normal(h.n_foci).astype(np.float32), device="cuda")
+            p.set_phase(phi_a.view(ny, nx))
+            grad = p.phase_gradient_device(gv)
+            g.adam_step_device(phi_a, grad.reshape(-1), m_a, v_a, step, 0.05)
+            p.set_phase(phi_b.view(ny, nx))
+            p.phase_gradient_adam_device(gv, phi_b, m_b, v_b, step, 0.05)
+            for a, b in ((phi_a, phi_b), (m_a, m_b), (v_a, v_b)):
+                assert np.array_equal(bits(a), bits(b))
+        assert float((phi_a - torch.tensor(np.asarray(h.phi0, np.float32).reshape(-1),
+                                           device="cuda")).abs().max()) > 0
+
+
 def test_design_loss_record_keeps_the_books(g):
     """gswmtp_design_loss_record_device: the same loss and dL/dI as the plain
     entry point, the loss written to hist[step] while step < capacity, and

@@ -613,6 +613,29 @@ def test_second_product_forms_operators(g, monkeypatch, form, name, mode):
     assert np.all(got_a[~kept] == 0)
 
 
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("form", ["gather", "grid"])
+def test_field_only_forward_equals_statistics_forward(g, mode, form):
+    """The lazy forward of the current phase in its two forms - field and
+    intensities only (one kernel over the gather partials, or read straight
+    off the dense grid in the grid form) and with the focus statistics (the
+    focus update's kernels) - give the same Theta and I bit for bit."""
+    import torch
+    h = (synth_ofa.random_case(81, 160, 200, 0, grid=(24, 20), radius=75.0) if form == "grid"
+         else synth_ofa.random_case(10, 100, 150, 70, amplitude="random"))
+    announce(f"field-only forward vs statistics forward {form} {mode}")
+    with g.Plan(h, precision=mode) as p:
+        p.iterate(3)
+        f1, i1 = p.foci_field_device()   # field-only form
+        f1, i1 = f1.clone(), i1.clone()
+        st = p.stats()                   # a forward of its own, with the statistics
+        f2, i2 = p.foci_field_device()   # served from that forward
+        assert np.isfinite(st["xi"])
+    bits = lambda t: t.view(torch.int32).cpu().numpy()  # noqa: E731
+    assert np.array_equal(bits(f1), bits(f2))
+    assert np.array_equal(bits(i1), bits(i2))
+
+
 @pytest.mark.parametrize("mode", list(MODE_TOL))
 def test_grid_form_passes_against_oracle(g, monkeypatch, mode):
     """Passes in the grid form (chosen automatically for a full grid of at
