@@ -283,8 +283,11 @@ bool cache_save(const char *path) {
       out << "  \"" << e.first << "\": [";
       for (size_t i = 0; i < e.second.size(); ++i) {
         const WorkConfig &c = e.second[i].first;
-        char buf[96];
-        snprintf(buf, sizeof buf, "[%d, %d, %d, %d, %d, %d, %.6f]", c.tile.bm, c.tile.bn,
+        // times with every digit a double holds: the choice made from the
+        // table read back (the fastest, then the 10% rule below) must be the
+        // tuning run's, also for near-equal candidates
+        char buf[128];
+        snprintf(buf, sizeof buf, "[%d, %d, %d, %d, %d, %d, %.17g]", c.tile.bm, c.tile.bn,
                  c.tile.bk, c.tile.kg, c.tile.pipe, c.split, e.second[i].second);
         out << (i ? ", " : "") << buf;
       }
