@@ -77,15 +77,17 @@ def _loss_and_gradient(I: torch.Tensor, target: torch.Tensor, n_ap: int, sum_a2:
     args = (I.data_ptr(), target.data_ptr(), I.numel(), float(n_ap), float(sum_a2),
             float(eta_weight), loss.data_ptr(), dI.data_ptr())
     if step is None:
+        name = "gswmtp_design_loss_device"
         rc = load_library().gswmtp_design_loss_device(*args, _stream_handle())
     else:
-        if not (step.is_cuda and step.dtype == torch.float32 and hist.is_cuda and
-                hist.dtype == torch.float32 and hist.is_contiguous()):
-            raise TypeError("hist and step must be float32 CUDA tensors")
+        if not (step.is_cuda and step.dtype == torch.float32 and step.numel() == 1 and
+                hist.is_cuda and hist.dtype == torch.float32 and hist.is_contiguous()):
+            raise TypeError("hist and step must be float32 CUDA tensors (step of one value)")
+        name = "gswmtp_design_loss_record_device"
         rc = load_library().gswmtp_design_loss_record_device(
             *args, hist.data_ptr(), hist.numel(), step.data_ptr(), _stream_handle())
     if rc != 0:
-        raise GswmtpError(rc, "gswmtp_design_loss_device")
+        raise GswmtpError(rc, name)
     return loss, dI
 
 
